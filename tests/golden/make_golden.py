@@ -1,0 +1,48 @@
+"""Writes the stored expected values under tests/golden/ using only ``oracle``.
+
+Run from the repository root:  python tests/golden/make_golden.py
+Each value is a full-chain exact diagonalization (LAPACK) of a Hamiltonian
+built straight from the paper's Eq. 1-8 by ``oracle.models``; none comes from
+the HIP library.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+from oracle import models  # noqa: E402
+
+
+def sector_min(H, labels, want):
+    idx = np.flatnonzero(labels == want)
+    return float(np.linalg.eigvalsh(H[np.ix_(idx, idx)])[0])
+
+
+def main():
+    out = {}
+    # Eq. 1-3, open chain, Delta = 1, S^z_total = 0 sector (label 2 S^z = 0)
+    for n in (2, 4, 6, 8, 10):
+        H = models.heisenberg_chain(n, delta=1.0)
+        out[f"heisenberg_open_N{n}_Sz0"] = sector_min(H, models.spin_labels(n), 0)
+    # Delta = 0 (XX chain)
+    for n in (8, 10):
+        H = models.heisenberg_chain(n, delta=0.0)
+        out[f"xx_open_N{n}_Sz0"] = sector_min(H, models.spin_labels(n), 0)
+    # Eq. 4-8, spin-1/2 Hubbard, t = 1, U = 4, half filling
+    for n in (2, 4):
+        H, Nup, Ndn = models.hubbard_chain(n, t=1.0, U=4.0)
+        lab = np.rint(np.diag(Nup)).astype(int) * 100 + np.rint(np.diag(Ndn)).astype(int)
+        out[f"hubbard_open_N{n}_t1_U4_half"] = sector_min(H, lab, (n // 2) * 100 + n // 2)
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "exact_energies.json")
+    with open(path, "w") as f:
+        json.dump({"source": "oracle.models + numpy.linalg.eigvalsh (LAPACK), FP64",
+                   "energies": out}, f, indent=1, sort_keys=True)
+    print(json.dumps(out, indent=1))
+
+
+if __name__ == "__main__":
+    main()
