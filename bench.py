@@ -1,0 +1,200 @@
+#!/usr/bin/env python3
+"""Benchmark of the superblock projection + Davidson hot path on one MI355X.
+
+Workload: the two-site Hubbard superblock with m = 2048 states per block
+(t = 1, U = 4, U(1)xU(1) sectors, 241 sectors, target-sector dimension
+n = 37 668, 12 terms), seeded synthetic operators.
+
+One step = one pass of the whole hot path on that input, inputs resident in
+HBM: a ground-state solve by the device Davidson iteration with the
+projection in reduced precision (FP32 by default) and FP64 refinement to a
+residual of 1e-10 (energy within 1e-8 of the FP64 result), replayed from
+captured hipGraphs, followed by the energy gradient dE/dc_k through the
+adjoint kernel.  `value` = Davidson iterations per second over the timed
+steps.  The projection alone is also timed (HIP events, FP64/FP32/BF16) and
+reported in TFLOP/s, and the FP64-only solve is timed for comparison.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"hbm_GBs": 8000.0, "f64_TFs": 78.6, "f32_TFs": 157.3, "bf16_TFs": 2500.0}
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--prec", default="f32", choices=["f32", "bf16"], help="reduced precision of phase 1")
+    ap.add_argument("--proj-reps", type=int, default=200)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--quick", action="store_true", help="skip the projection and FP64 comparison timings")
+    return ap.parse_args()
+
+
+def timed_projection(plan, psi, y, prec, reps, torch):
+    """Average duration of one projection call, HIP events on the launch stream."""
+    s = torch.cuda.current_stream()
+    for _ in range(5):
+        plan.project_raw(psi, prec=prec, out=y)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        plan.project_raw(psi, prec=prec, out=y)
+    e1.record(s)
+    e1.synchronize()
+    return e0.elapsed_time(e1) * 1e-3 / reps
+
+
+def cpu_baseline(p, x0):
+    """The FP64 oracle (NumPy + OpenBLAS) on the host: one full Davidson solve
+    of the same workload from the same start vector, plus projection timing."""
+    import numpy as np
+
+    from oracle import davidson as odav
+    from oracle import projection
+
+    threads = int(os.environ.get("OPENBLAS_NUM_THREADS", os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
+    t0 = time.perf_counter()
+    r = odav.ground_state_davidson(p, x0, tol=1e-10)
+    t_dav = time.perf_counter() - t0
+    flop = projection.flop_count(p)
+    reps = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < 3.0:
+        projection.project_sectors(p, x0)
+        reps += 1
+    t_proj = (time.perf_counter() - t0) / reps
+    return {
+        "value": r.iterations / t_dav,
+        "unit": "iter/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"one FP64 oracle Davidson solve of the m=2048 Hubbard superblock to ||r|| <= 1e-10 "
+                  f"({r.iterations} iterations, {t_dav:.2f} s) and {reps} oracle projections",
+        "projection_ms": t_proj * 1e3,
+        "projection_gflops": flop / t_proj * 1e-9,
+        "energy": r.energy,
+    }, r.energy
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_1309_5571_amd as dm
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    p = gen.config(3)
+    plan = dm.Plan(p, prec=args.prec)
+    x0_np = gen.start_vector(plan.n, 7)
+    x0 = torch.from_numpy(x0_np).to(dev)
+    coef = plan.coef.clone()
+
+    def step(prec):
+        psi, E, info, st = plan.davidson(x0, coef, tol=1e-10, prec=prec)
+        if st != 0:
+            raise RuntimeError(f"Davidson status {st}: {info}")
+        _, gcoef = plan.backward_raw(psi, psi, coef, want_psi=False, want_coef=True)
+        return E, info, gcoef
+
+    for _ in range(args.warmup):
+        step(args.prec)
+    torch.cuda.synchronize()
+    iters = 0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        E, info, gcoef = step(args.prec)
+        iters += info[0]["iterations"]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    E_mixed = float(E[0])
+    info_mixed = info[0]
+
+    extra = {}
+    if not args.quick:
+        # FP64-only solve of the same problem
+        for _ in range(2):
+            step("f64")
+        torch.cuda.synchronize()
+        it64 = 0
+        t1 = time.perf_counter()
+        n64 = max(3, args.steps // 2)
+        for _ in range(n64):
+            E64, info64, _ = step("f64")
+            it64 += info64[0]["iterations"]
+        torch.cuda.synchronize()
+        dt64 = time.perf_counter() - t1
+        extra["fp64_solve"] = {"iters_per_s": it64 / dt64, "ms_per_solve": dt64 / n64 * 1e3,
+                               "iterations": info64[0]["iterations"], "energy": float(E64[0])}
+        # projection alone, per precision (events on the launch stream)
+        psi = torch.from_numpy(x0_np / np.linalg.norm(x0_np)).to(dev)
+        y = torch.empty_like(psi)
+        planb = dm.Plan(p, prec="bf16") if args.prec != "bf16" else plan
+        proj = {}
+        for prec, pl in (("f64", plan), (args.prec, plan), ("bf16", planb)):
+            t = timed_projection(pl, psi, y, prec, args.proj_reps, torch)
+            proj[prec] = {"us": t * 1e6, "tflops": plan.flop / t * 1e-12}
+        extra["projection"] = proj
+        extra["mixed_vs_fp64_time_ratio"] = (dt / args.steps * 1e3) / extra["fp64_solve"]["ms_per_solve"]
+
+    # roofline of the dominant kernel: the FP64 projection, bound by HBM bytes at
+    # this workload's arithmetic intensity (algorithmic FLOP / algorithmic bytes = 5)
+    t_proj = extra["projection"]["f64"]["us"] * 1e-6 if "projection" in extra else None
+    roof = None
+    if t_proj:
+        achieved = plan.bytes / t_proj * 1e-9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK["hbm_GBs"], "unit": "GB/s",
+                "frac": achieved / PEAK["hbm_GBs"], "traffic": None, "kernel": "projection (f64, 2 launches)",
+                "algorithmic_bytes": plan.bytes, "algorithmic_flop": plan.flop}
+
+    cpu = None
+    E_ref = None
+    if not args.no_cpu_baseline:
+        cpu, E_ref = cpu_baseline(p, x0_np)
+
+    out = {
+        "metric": "H·ψ projection TFLOP/s + Davidson iters/s at m=2048 Hubbard; mixed vs FP64 @1e-8 dE",
+        "value": iters / dt,
+        "unit": "iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": f"{args.prec}+f64",
+        "data": "synthetic",
+        "config": {"workload": "hubbard_m2048_two_site", "m": 2048, "n": plan.n, "sectors": int(p.left.nsec),
+                   "terms": int(len(p.coef)), "t": 1.0, "U": 4.0, "tol": 1e-10,
+                   "phase1": args.prec, "refine": "f64", "graph": True},
+        "iterations_per_step": info_mixed["iterations"],
+        "iterations_lowprec": info_mixed["iterations_low"],
+        "energy": E_mixed,
+        "dE_vs_fp64_oracle": (E_mixed - E_ref) if E_ref is not None else None,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    out.update(extra)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

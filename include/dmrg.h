@@ -1,0 +1,239 @@
+/*
+ * dmrg.h — C ABI of the MI355X superblock-projection and Davidson library.
+ *
+ * The library evaluates the DMRG superblock projection of the LR strategy
+ * (Nemes et al., "The density matrix renormalization group algorithm on
+ * kilo-processor architectures", Sec. "LR strategy", Eq. 9-11)
+ *
+ *     y = H_SB psi = sum_k c_k (A_k (x) B_k) psi ,
+ *
+ * restricted to one target symmetry sector Q and evaluated block by block as
+ *     Y_{jl} += c_k A_{k, i->j} X_{ik} B_{k, k->l}^T                 (Eq. 11)
+ * on the GPU, and runs the Davidson iteration (Alg. 3) for the lowest
+ * eigenpair of H_SB in that sector entirely on the device.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Pointers marked "host" are read during the call only.  Pointers marked
+ *    "device" must be GPU memory of the device that was current when the plan
+ *    was created.
+ *  - "stream" is a hipStream_t passed as void* (NULL = the legacy default
+ *    stream).  All device work is enqueued on it.
+ *  - Every function returns a dmrg_status; no exception or abort crosses the
+ *    ABI.  On failure dmrg_last_error() returns a message (thread-local).
+ *  - A plan is not thread-safe; distinct plans are independent.
+ *  - Symmetry labels are int32 tuples of length `rank` (1 for S^z, 2 for
+ *    (N_up, N_dn)); sector labels of a space must be strictly ascending in
+ *    lexicographic order.
+ *
+ * Layout of the target-sector vector psi (the paper leaves it open; this is
+ * the library's reading of Eq. 10-11): for every left sector s_L in ascending
+ * order whose complement Q - label(s_L) is a right sector s_R, and whose two
+ * dimensions are both non-zero, one row-major block X[d_L(s_L)][d_R(s_R)];
+ * psi is the concatenation of those blocks.  For a batched plan, psi is the
+ * concatenation of the members' vectors in member order.
+ */
+#ifndef DMRG_H
+#define DMRG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t dmrg_status; /* 0 ok, > 0 warning, < 0 error */
+
+enum {
+    DMRG_OK = 0,
+    DMRG_W_NOT_CONVERGED = 1, /* Davidson stopped at max_iter; outputs are the last iterate */
+    DMRG_E_INVALID_ARG = -1,  /* null pointer, negative size, bad enum, bad index */
+    DMRG_E_SECTOR = -2,       /* a term maps the target sector outside itself, or block
+                                 dims do not match the sector dims */
+    DMRG_E_LAYOUT = -3,       /* labels not strictly ascending, duplicate blocks */
+    DMRG_E_NOMEM = -4,        /* device allocation failed */
+    DMRG_E_HIP = -5,          /* a HIP runtime call failed (message has the HIP error) */
+    DMRG_E_NONFINITE = -6,    /* NaN/Inf in the start vector or the result */
+    DMRG_E_BREAKDOWN = -7,    /* Davidson correction vanished after orthogonalization */
+    DMRG_E_UNSUPPORTED = -8   /* valid request the library does not implement */
+};
+
+/* Compute precision of the projection GEMMs.  Vectors and all Davidson
+ * arithmetic other than the projection are always FP64. */
+enum { DMRG_F64 = 0, DMRG_F32 = 1, DMRG_BF16 = 2 };
+
+/* Operator kinds (Sec. "Symmetries to be exploited": a symmetric operator is
+ * a set of dense blocks A_{q_i -> q_j}). */
+enum { DMRG_OP_IDENTITY = 0, DMRG_OP_DIAG = 1, DMRG_OP_DENSE = 2 };
+
+/* A block basis grouped by symmetry sectors.  host arrays. */
+typedef struct {
+    int32_t nsec;         /* number of sectors, >= 1 */
+    int32_t rank;         /* labels per sector, 1 or 2 */
+    const int32_t *label; /* host [nsec * rank], strictly ascending (lexicographic) */
+    const int64_t *dim;   /* host [nsec], >= 0 */
+} dmrg_space;
+
+/* One block operator.
+ *  IDENTITY: all other fields ignored.
+ *  DIAG:     data = device FP64 [m] (m = sum of dims), the diagonal in sector order.
+ *  DENSE:    nblk blocks; block b maps sector src[b] to sector dst[b] and is a
+ *            row-major FP64 matrix [dim(dst[b])][dim(src[b])] stored at
+ *            data + off[b].  A (src, dst) pair may appear at most once.
+ * The plan keeps the data pointer (not a copy): the FP64 data must stay
+ * valid and unchanged for the plan's lifetime. */
+typedef struct {
+    int32_t kind;
+    int32_t nblk;
+    const int32_t *src;  /* host [nblk] */
+    const int32_t *dst;  /* host [nblk] */
+    const int64_t *off;  /* host [nblk], element offsets into data */
+    const double *data;  /* device */
+} dmrg_op;
+
+/* Term k of H_SB: coef[k] * ops_left[a] (x) ops_right[b]   (Eq. 9). */
+typedef struct {
+    int32_t a, b;
+} dmrg_term;
+
+/* One superblock (Alg. 1, steps 1-2: left block, right block, superblock). */
+typedef struct {
+    dmrg_space left, right;
+    const int32_t *target; /* host [rank]: the conserved label Q of the sector */
+    int32_t nop_left, nop_right;
+    const dmrg_op *ops_left, *ops_right; /* host arrays of descriptors */
+    int32_t nterm;
+    const dmrg_term *terms; /* host [nterm] */
+} dmrg_problem;
+
+typedef struct dmrg_plan dmrg_plan; /* opaque */
+
+/* Validate one problem on the host only (no GPU needed).  Checks labels,
+ * dims, block indices and sizes, and that every term keeps the target
+ * sector closed.  Returns DMRG_OK or the first error found. */
+dmrg_status dmrg_problem_check(const dmrg_problem *prob);
+
+/* Build a plan for nprob independent problems (nprob = 1 for a single
+ * superblock): enumerate the target-sector pairs, build the operation records
+ * once (A and B do not change during Davidson, Sec. "Accelerating projection
+ * operation"), choose tiles, upload the task lists, and, for prec != F64,
+ * convert the dense operator blocks once (FP64 -> FP32 [-> BF16], round to
+ * nearest even) with the diagonals of square blocks kept in FP64.
+ * A plan of precision F32/BF16 can also project in F64.  Synchronizes stream.
+ * out: receives the plan (NULL on failure). */
+dmrg_status dmrg_plan_create(dmrg_plan **out, int32_t nprob, const dmrg_problem *probs,
+                             int32_t prec, void *stream);
+
+/* Sizes of a plan.  Any output pointer may be NULL.
+ *  n:       total length of psi (sum over members)
+ *  npair:   total number of target-sector pairs
+ *  nrec:    total number of operation records
+ *  flop:    algorithmic FLOP of one projection (2 min(...) per two-sided
+ *           record, 2 d_j d_i d_k per one-sided record, 2 per element of a
+ *           purely diagonal record)
+ *  bytes:   algorithmic bytes of one F64 projection (operator blocks and
+ *           diagonals read once, psi read once, y written once) */
+dmrg_status dmrg_plan_sizes(const dmrg_plan *plan, int64_t *n, int32_t *npair, int32_t *nrec,
+                            int64_t *flop, int64_t *bytes);
+
+/* psi layout, host outputs sized by dmrg_plan_sizes:
+ *  member [npair], pair_left [npair], pair_right [npair] (sector indices),
+ *  pair_off [npair + 1] (element offsets into psi), member_off [nprob + 1]. */
+dmrg_status dmrg_plan_layout(const dmrg_plan *plan, int32_t *member, int32_t *pair_left,
+                             int32_t *pair_right, int64_t *pair_off, int64_t *member_off);
+
+/* Operation records (Alg. 5, step 1), host outputs [nrec] each:
+ *  term index (within the member), input pair, output pair (global pair
+ *  indices), and the product order chosen (0: (A X) B^T, 1: A (X B^T),
+ *  2: one-sided or diagonal). */
+dmrg_status dmrg_plan_records(const dmrg_plan *plan, int32_t *term, int32_t *pair_in,
+                              int32_t *pair_out, int32_t *order);
+
+/* y = H_SB psi for every member.
+ *  prec: DMRG_F64, or the plan's own precision.
+ *  coef: device FP64 [total terms] (members' coefficients concatenated).
+ *  psi, y: device FP64 [n]; must not overlap.  Asynchronous on stream. */
+dmrg_status dmrg_project(dmrg_plan *plan, int32_t prec, const double *coef, const double *psi,
+                         double *y, void *stream);
+
+/* Adjoint of dmrg_project with respect to psi and coef, in FP64:
+ *  gpsi  = sum_k c_k (A_k^T (x) B_k^T) gbar     (device [n]; may be NULL)
+ *  gcoef[k] = <gbar, (A_k (x) B_k) psi>          (device [total terms]; may be NULL)
+ * psi, gbar: device [n].  Asynchronous on stream.  With gbar = psi = the
+ * normalized ground state, gcoef is dE/dc_k (Hellmann-Feynman). */
+dmrg_status dmrg_project_backward(dmrg_plan *plan, const double *coef, const double *psi,
+                                  const double *gbar, double *gpsi, double *gcoef, void *stream);
+
+/* Davidson options (Alg. 3 with the readings documented in the design notes). */
+typedef struct {
+    double tol;            /* stop when ||r||_2 <= tol (||x|| = 1).  default 1e-10 */
+    int32_t kmax;          /* subspace limit (thick restart when reached), 2..64, default 32 */
+    int32_t kmin;          /* vectors kept at a restart, 1..kmax-1, default 8 */
+    int32_t max_iter;      /* iterations (Ritz evaluations) per phase, default 500 */
+    double precond_floor;  /* |D - sigma| floor of the diagonal preconditioner, default 1e-3 */
+    int32_t prec;          /* projection precision of phase 1: F64 (one phase) or the plan's */
+    double tol_lowprec;    /* phase-1 tolerance for F32/BF16 (0: 1e-5 for F32, 1e-3 for BF16) */
+    int32_t refine;        /* F32/BF16: 1 = continue in F64 to tol (default), 0 = stop after phase 1 */
+    int32_t use_graph;     /* 1 = replay captured hipGraphs of graph_chunk iterations (default) */
+    int32_t graph_chunk;   /* iterations per graph launch, default 8 */
+} dmrg_davidson_opts;
+
+/* Per-member results, host. */
+typedef struct {
+    double energy;          /* lowest Ritz value */
+    double residual;        /* final ||r||_2 */
+    int32_t iterations;     /* Ritz evaluations, both phases */
+    int32_t iterations_low; /* of which in the reduced-precision phase */
+    int32_t projections;    /* H.v products */
+    int32_t restarts;
+    int32_t converged;      /* 1 if ||r|| <= tol */
+    int32_t breakdown;      /* 1 if the correction vanished */
+} dmrg_davidson_info;
+
+void dmrg_davidson_default_opts(dmrg_davidson_opts *opts);
+
+/* Lowest eigenpair of every member (Alg. 3 on the device).
+ *  coef: device FP64 [total terms].
+ *  psi:  device FP64 [n]; in: start vectors (any norm, non-zero per member),
+ *        out: normalized ground states.
+ *  energy: host [nprob] (may be NULL); info: host [nprob] (may be NULL).
+ * Synchronizes stream.  Returns DMRG_W_NOT_CONVERGED if any member did not
+ * converge, DMRG_E_BREAKDOWN if any broke down, DMRG_E_NONFINITE for a
+ * zero or non-finite start vector. */
+dmrg_status dmrg_davidson(dmrg_plan *plan, const double *coef, const dmrg_davidson_opts *opts,
+                          double *psi, double *energy, dmrg_davidson_info *info, void *stream);
+
+/* Diagonal of H_SB in the target sector (the Davidson preconditioner),
+ * device FP64 [n].  Asynchronous. */
+dmrg_status dmrg_diagonal(dmrg_plan *plan, const double *coef, double *diag, void *stream);
+
+/* Tall-skinny products of the Davidson orthogonalization (Alg. 3, lines 3,
+ * 5, 12, 13) on column-major V (device FP64, column j at V + j * ldv):
+ *  dmrg_gemv_t: s[j] = sum_e V[e, j] x[e], j < k          (s: device [k])
+ *  dmrg_gemv_n: y[e] = beta * y[e] + sum_j V[e, j] s[j]    (y: device [n])
+ * n <= ldv, 1 <= k <= 64.  Asynchronous.  These are the kernels the
+ * Davidson driver uses, exposed for measurement. */
+dmrg_status dmrg_gemv_t(int64_t n, int32_t k, const double *V, int64_t ldv, const double *x,
+                        double *s, void *stream);
+dmrg_status dmrg_gemv_n(int64_t n, int32_t k, const double *V, int64_t ldv, const double *s,
+                        double beta, double *y, void *stream);
+
+/* Set the tile table used by later dmrg_plan_create calls: for output
+ * blocks with max(rows, cols) <= bound[c] (ascending, ncls <= 8), tiles of
+ * tile[c] rows and columns (16 or 32).  ncls = 0 restores the built-in table.
+ * Process-wide; not thread-safe against concurrent plan creation. */
+dmrg_status dmrg_set_tile_table(int32_t ncls, const int32_t *bound, const int32_t *tile);
+
+void dmrg_plan_destroy(dmrg_plan *plan);
+
+const char *dmrg_last_error(void);
+
+/* Library version string. */
+const char *dmrg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DMRG_H */

@@ -1,0 +1,340 @@
+"""MI355X superblock projection and Davidson solver (Python binding).
+
+A thin layer over the C ABI of ``include/dmrg.h``: it marshals problem
+descriptions into the ABI structs, lets PyTorch own device memory and
+streams, and wraps two entry points as ``torch.autograd.Function``s.  Every
+step of the projection and of the Davidson iteration runs in the HIP
+library; nothing here computes.
+
+Problem descriptions are duck-typed: any object with the attributes
+``left``/``right`` (``labels`` int [nsec, rank], ``dims`` int [nsec]),
+``target``, ``ops_left``/``ops_right`` (each with ``kind`` in
+{"identity", "diag", "dense"}, and ``src``/``dst``/``blocks`` or ``diag``),
+``terms`` ([nterm, 2]) and ``coef`` ([nterm]).
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+from . import _native as N
+from ._native import DmrgError  # noqa: F401
+
+__all__ = ["Plan", "project", "ground_energy", "problem_check", "DmrgError", "gemv_t", "gemv_n",
+           "set_tile_table", "version"]
+
+
+def version() -> str:
+    return N.lib().dmrg_version().decode()
+
+
+def _i32(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+
+
+def _i64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.int64))
+
+
+def _ptr(a: np.ndarray, ct):
+    return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+class _Marshal:
+    """Builds the ABI structs for a list of problems and keeps every buffer alive.
+
+    ``device`` None: operator data pointers are host addresses (only valid for
+    dmrg_problem_check, which never dereferences them).  Otherwise the data
+    is uploaded as float64 tensors on that device.
+    """
+
+    def __init__(self, problems: Sequence, device=None):
+        self.keep: list = []
+        self.dev_tensors: list = []
+        self.structs = (N.Problem * len(problems))()
+        for i, p in enumerate(problems):
+            self.structs[i] = self._problem(p, device)
+
+    def _space(self, sp) -> N.Space:
+        lab = _i32(sp.labels)
+        if lab.ndim == 1:
+            lab = lab[:, None].copy()
+        dims = _i64(sp.dims)
+        self.keep += [lab, dims]
+        return N.Space(int(dims.shape[0]), int(lab.shape[1]), _ptr(lab, ctypes.c_int32), _ptr(dims, ctypes.c_int64))
+
+    def _data(self, arr: np.ndarray, device):
+        arr = np.ascontiguousarray(arr, dtype=np.float64)
+        if device is None:
+            if arr.size == 0:
+                arr = np.zeros(1)
+            self.keep.append(arr)
+            return arr.ctypes.data
+        import torch
+
+        t = torch.from_numpy(arr if arr.size else np.zeros(1)).to(device)
+        self.dev_tensors.append(t)
+        return t.data_ptr()
+
+    def _op(self, op, device) -> N.Op:
+        kind = N.OP_KIND[op.kind]
+        if kind == N.OP_IDENTITY:
+            return N.Op(kind, 0, None, None, None, None)
+        if kind == N.OP_DIAG:
+            return N.Op(kind, 0, None, None, None, self._data(op.diag, device))
+        blocks = [np.ascontiguousarray(b, dtype=np.float64) for b in op.blocks]
+        sizes = np.array([b.size for b in blocks], dtype=np.int64)
+        off = np.zeros(len(blocks), dtype=np.int64)
+        if len(blocks) > 1:
+            off[1:] = np.cumsum(sizes)[:-1]
+        flat = np.concatenate([b.reshape(-1) for b in blocks]) if blocks else np.zeros(0)
+        src, dst = _i32(op.src), _i32(op.dst)
+        self.keep += [src, dst, off]
+        return N.Op(kind, len(blocks), _ptr(src, ctypes.c_int32), _ptr(dst, ctypes.c_int32),
+                    _ptr(off, ctypes.c_int64), self._data(flat, device))
+
+    def _problem(self, p, device) -> N.Problem:
+        L, R = self._space(p.left), self._space(p.right)
+        tgt = _i32(np.asarray(p.target).reshape(-1))
+        opsL = (N.Op * max(1, len(p.ops_left)))(*[self._op(o, device) for o in p.ops_left])
+        opsR = (N.Op * max(1, len(p.ops_right)))(*[self._op(o, device) for o in p.ops_right])
+        terms_np = _i32(np.asarray(p.terms).reshape(-1, 2))
+        terms = (N.Term * max(1, terms_np.shape[0]))(*[N.Term(int(a), int(b)) for a, b in terms_np])
+        self.keep += [tgt, opsL, opsR, terms]
+        return N.Problem(L, R, _ptr(tgt, ctypes.c_int32), len(p.ops_left), len(p.ops_right), opsL, opsR,
+                         int(terms_np.shape[0]), terms)
+
+
+def problem_check(problem) -> int:
+    """Host-only validation (no GPU needed); returns the dmrg status code."""
+    m = _Marshal([problem], device=None)
+    return int(N.lib().dmrg_problem_check(ctypes.byref(m.structs[0])))
+
+
+def set_tile_table(bounds: Sequence[int] = (), tiles: Sequence[int] = ()) -> None:
+    b, t = _i32(bounds), _i32(tiles)
+    N.check(N.lib().dmrg_set_tile_table(len(b), _ptr(b, ctypes.c_int32) if len(b) else None,
+                                        _ptr(t, ctypes.c_int32) if len(t) else None))
+
+
+def _stream(device):
+    import torch
+
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Plan:
+    """A device plan for one or many superblocks (dmrg_plan_create).
+
+    ``prec``: "f64", "f32" or "bf16" -- the reduced precision the plan
+    prepares in addition to FP64.
+    """
+
+    def __init__(self, problems, prec: str = "f64", device=None):
+        import torch
+
+        if not isinstance(problems, (list, tuple)):
+            problems = [problems]
+        self.problems = list(problems)
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else
+                                   torch.device(device).index or 0)
+        self.prec = N.PREC[prec]
+        self._lib = N.lib()
+        with torch.cuda.device(self.device):
+            self._m = _Marshal(self.problems, device=self.device)
+            h = ctypes.c_void_p()
+            N.check(self._lib.dmrg_plan_create(ctypes.byref(h), len(self.problems), self._m.structs, self.prec,
+                                               _stream(self.device)))
+        self._h = h
+        n, npair, nrec, flop, nbytes = (ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64(),
+                                        ctypes.c_int64())
+        N.check(self._lib.dmrg_plan_sizes(h, ctypes.byref(n), ctypes.byref(npair), ctypes.byref(nrec),
+                                          ctypes.byref(flop), ctypes.byref(nbytes)))
+        self.n, self.npair, self.nrec, self.flop, self.bytes = n.value, npair.value, nrec.value, flop.value, \
+            nbytes.value
+        self.nterm = [int(np.asarray(p.terms).reshape(-1, 2).shape[0]) for p in self.problems]
+        coef = np.concatenate([np.asarray(p.coef, dtype=np.float64).reshape(-1) for p in self.problems]) \
+            if sum(self.nterm) else np.zeros(1)
+        self.coef = torch.from_numpy(coef).to(self.device)
+        lay = self.layout()
+        self.member_off = lay["member_off"]
+
+    # ------------------------------------------------------------ plumbing
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self._lib.dmrg_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _vec(self, x, name):
+        import torch
+
+        if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float64 and x.is_contiguous()):
+            raise TypeError(f"{name} must be a contiguous float64 CUDA tensor")
+        if x.device != self.device:
+            raise ValueError(f"{name} is on {x.device}, plan on {self.device}")
+        return ctypes.c_void_p(x.data_ptr())
+
+    def _coef(self, coef):
+        c = self.coef if coef is None else coef
+        if c.numel() != max(1, sum(self.nterm)):
+            raise ValueError("coef has the wrong length")
+        return c
+
+    # ------------------------------------------------------------ metadata
+    def layout(self) -> dict:
+        np_ = self.npair
+        member = np.zeros(max(np_, 1), dtype=np.int32)
+        pl = np.zeros(max(np_, 1), dtype=np.int32)
+        pr = np.zeros(max(np_, 1), dtype=np.int32)
+        po = np.zeros(np_ + 1, dtype=np.int64)
+        mo = np.zeros(len(self.problems) + 1, dtype=np.int64)
+        N.check(self._lib.dmrg_plan_layout(self._h, _ptr(member, ctypes.c_int32), _ptr(pl, ctypes.c_int32),
+                                           _ptr(pr, ctypes.c_int32), _ptr(po, ctypes.c_int64),
+                                           _ptr(mo, ctypes.c_int64)))
+        return {"member": member[:np_], "pair_left": pl[:np_], "pair_right": pr[:np_], "pair_off": po,
+                "member_off": mo}
+
+    def records(self) -> dict:
+        k = max(self.nrec, 1)
+        term, pin, pout, order = (np.zeros(k, dtype=np.int32) for _ in range(4))
+        N.check(self._lib.dmrg_plan_records(self._h, _ptr(term, ctypes.c_int32), _ptr(pin, ctypes.c_int32),
+                                            _ptr(pout, ctypes.c_int32), _ptr(order, ctypes.c_int32)))
+        r = self.nrec
+        return {"term": term[:r], "pair_in": pin[:r], "pair_out": pout[:r], "order": order[:r]}
+
+    # ------------------------------------------------------------ raw entry points
+    def project_raw(self, psi, coef=None, prec: str = "f64", out=None):
+        import torch
+
+        c = self._coef(coef)
+        y = torch.empty_like(psi) if out is None else out
+        N.check(self._lib.dmrg_project(self._h, N.PREC[prec], self._vec(c, "coef"), self._vec(psi, "psi"),
+                                       self._vec(y, "y"), _stream(self.device)))
+        return y
+
+    def backward_raw(self, psi, gbar, coef=None, want_psi: bool = True, want_coef: bool = True):
+        import torch
+
+        c = self._coef(coef)
+        gpsi = torch.empty_like(gbar) if want_psi else None
+        gcoef = torch.empty(max(1, sum(self.nterm)), dtype=torch.float64, device=self.device) if want_coef else None
+        N.check(self._lib.dmrg_project_backward(
+            self._h, self._vec(c, "coef"), self._vec(psi, "psi") if want_coef else None, self._vec(gbar, "gbar"),
+            self._vec(gpsi, "gpsi") if want_psi else None, self._vec(gcoef, "gcoef") if want_coef else None,
+            _stream(self.device)))
+        return gpsi, gcoef
+
+    def diagonal(self, coef=None):
+        import torch
+
+        c = self._coef(coef)
+        d = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        N.check(self._lib.dmrg_diagonal(self._h, self._vec(c, "coef"), self._vec(d, "diag"), _stream(self.device)))
+        return d
+
+    def davidson(self, psi0, coef=None, tol: float = 1e-10, kmax: int = 32, kmin: int = 8, max_iter: int = 500,
+                 precond_floor: float = 1e-3, prec: str = "f64", tol_lowprec: float = 0.0, refine: bool = True,
+                 use_graph: bool = True, graph_chunk: int = 8, raise_on_warning: bool = False):
+        """Ground states of every member; returns (psi, energies [host], infos, status)."""
+        c = self._coef(coef)
+        psi = psi0.clone()
+        o = N.DavidsonOpts(tol, kmax, kmin, max_iter, precond_floor, N.PREC[prec], tol_lowprec, int(refine),
+                           int(use_graph), graph_chunk)
+        nprob = len(self.problems)
+        E = (ctypes.c_double * nprob)()
+        infos = (N.DavidsonInfo * nprob)()
+        st = self._lib.dmrg_davidson(self._h, self._vec(c, "coef"), ctypes.byref(o), self._vec(psi, "psi"), E,
+                                     infos, _stream(self.device))
+        if st < 0 and st != N.E_BREAKDOWN:
+            N.check(st)
+        if raise_on_warning and st != 0:
+            N.check(st)
+        return psi, np.array(E[:]), [infos[i].as_dict() for i in range(nprob)], int(st)
+
+
+# ---------------------------------------------------------------- autograd
+
+
+def _torch_functions():
+    import torch
+
+    class _Project(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, plan, psi, coef, prec):
+            ctx.plan = plan
+            ctx.save_for_backward(psi, coef)
+            return plan.project_raw(psi.contiguous(), coef.contiguous(), prec)
+
+        @staticmethod
+        def backward(ctx, gy):
+            psi, coef = ctx.saved_tensors
+            gpsi, gcoef = ctx.plan.backward_raw(psi, gy.contiguous(), coef, want_psi=ctx.needs_input_grad[1],
+                                                want_coef=ctx.needs_input_grad[2])
+            return None, gpsi, gcoef, None
+
+    class _GroundEnergy(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, plan, coef, psi0, opts):
+            psi, E, infos, st = plan.davidson(psi0, coef.detach().contiguous(), **opts)
+            ctx.plan = plan
+            ctx.save_for_backward(psi, coef)
+            ctx.infos = infos
+            return torch.as_tensor(E, dtype=torch.float64, device=coef.device)
+
+        @staticmethod
+        def backward(ctx, gE):
+            psi, coef = ctx.saved_tensors
+            # Hellmann-Feynman: dE_m / dc_k = <psi_m, T_k psi_m> for the member m owning term k
+            _, gcoef = ctx.plan.backward_raw(psi, psi, coef, want_psi=False, want_coef=True)
+            owner = torch.repeat_interleave(torch.arange(len(ctx.plan.nterm), device=coef.device),
+                                            torch.as_tensor(ctx.plan.nterm, device=coef.device))
+            return None, gcoef[: owner.numel()] * gE[owner], None, None
+
+    return _Project, _GroundEnergy
+
+
+_FN = None
+
+
+def project(plan: Plan, psi, coef=None, prec: str = "f64"):
+    """y = H psi, differentiable in psi and coef (backward: dmrg_project_backward)."""
+    global _FN
+    if _FN is None:
+        _FN = _torch_functions()
+    return _FN[0].apply(plan, psi, plan.coef if coef is None else coef, prec)
+
+
+def ground_energy(plan: Plan, coef, psi0, **opts):
+    """Lowest eigenvalue of every member, differentiable in coef (Hellmann-Feynman)."""
+    global _FN
+    if _FN is None:
+        _FN = _torch_functions()
+    return _FN[1].apply(plan, coef, psi0, opts)
+
+
+def gemv_t(V, x, k: Optional[int] = None):
+    """s = V[:, :k]^T x for column-major V given as a [k, n] row-per-column tensor."""
+    import torch
+
+    k = V.shape[0] if k is None else k
+    s = torch.empty(k, dtype=torch.float64, device=V.device)
+    N.check(N.lib().dmrg_gemv_t(V.shape[1], k, ctypes.c_void_p(V.data_ptr()), V.stride(0),
+                                ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(s.data_ptr()), _stream(V.device)))
+    return s
+
+
+def gemv_n(V, s, y, beta: float = 0.0, k: Optional[int] = None):
+    """y = beta y + V[:, :k] s for column-major V given as a [k, n] tensor."""
+    k = V.shape[0] if k is None else k
+    N.check(N.lib().dmrg_gemv_n(V.shape[1], k, ctypes.c_void_p(V.data_ptr()), V.stride(0),
+                                ctypes.c_void_p(s.data_ptr()), beta, ctypes.c_void_p(y.data_ptr()),
+                                _stream(V.device)))
+    return y

@@ -1,0 +1,178 @@
+// Internal structures of the projection/Davidson library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "dmrg.h"
+
+namespace dmrg {
+
+// ---------------------------------------------------------------- status helpers
+dmrg_status set_error(dmrg_status st, const char *fmt, ...);
+void clear_error();
+
+#define DMRG_HIP(call)                                                                    \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return ::dmrg::set_error(e_ == hipErrorOutOfMemory ? DMRG_E_NOMEM : DMRG_E_HIP, \
+                                     "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), \
+                                     __FILE__, __LINE__);                                 \
+    } while (0)
+
+#define DMRG_TRY(expr)                 \
+    do {                               \
+        dmrg_status s_ = (expr);       \
+        if (s_ < 0) return s_;         \
+    } while (0)
+
+// ---------------------------------------------------------------- device descriptors
+// Where a GEMM operand lives.
+enum : int16_t {
+    OPD_ABS = 0,  // absolute device address (operator blocks, plan-owned copies)
+    OPD_IN = 1,   // element offset into the call's input vector (psi, or gbar in the adjoint)
+    OPD_TMP = 2   // element offset into the plan's intermediate buffer
+};
+
+// One GEMM contribution to an output matrix:  C += coef * op(P) op(Q)
+//   P element (r, k): ptrans ? P[k * ldp + r] : P[r * ldp + k]   (r = output row)
+//   Q element (k, c): qtrans ? Q[c * ldq + k] : Q[k * ldq + c]   (c = output column)
+// with optional FP64 row scale pscale[r] and column scale qscale[c] applied to
+// the operands on load (a diagonal factor of the term).
+struct Seg {
+    uint64_t p, q;            // address (OPD_ABS) or element offset
+    uint64_t pscale, qscale;  // absolute FP64 addresses, 0 = none
+    int32_t ldp, ldq;
+    int32_t K;
+    int16_t pkind, qkind;
+    int16_t ptrans, qtrans;
+    int32_t coef;  // global coefficient index, -1 = 1.0
+    int32_t term;  // global term index (for coefficient gradients), -1 = none
+    int32_t pad;
+};
+
+// A purely diagonal contribution at an output pair:
+//   C(r, c) += coef * vl[r] * vr[c] * X(r, c),  X = the call's input at the same pair.
+//   vl / vr are read with strides sl / sr (1 for a diagonal operator; d + 1 to
+//   walk the diagonal of a dense square block, used for the preconditioner).
+struct DiagTerm {
+    uint64_t vl, vr;  // absolute FP64 addresses of the pair's slices, 0 = ones
+    int32_t coef;
+    int32_t term;
+    int32_t sl, sr;
+};
+
+// One output tile.
+struct Task {
+    int32_t seg_begin, seg_end;
+    int32_t diag_begin, diag_end;
+    int64_t c_off;     // element offset of the output matrix (in y, gpsi or the intermediate buffer)
+    int64_t x_off;     // element offset of the matching input block (diagonal terms)
+    int32_t ldc;       // row length of the output matrix
+    int32_t row0, col0;
+    int32_t m, n;      // rows / columns of this tile (<= tile size)
+    int32_t member;
+    int32_t part0;     // first coefficient-gradient partial slot of this task
+    int32_t pad;
+};
+
+// ---------------------------------------------------------------- host metadata
+struct Pair {
+    int32_t sl, sr;
+    int64_t dl, dr;
+    int64_t off;  // global offset in psi
+};
+
+struct OpBlock {  // resolved block of one operator (identity/diag/dense)
+    int32_t src, dst;
+    int32_t kind;       // DMRG_OP_*
+    int64_t rows, cols; // dims of dst, src
+    const double *data; // FP64 device address of the block (dense) or the diag slice (diag); null for identity
+    int32_t op;         // global operator id
+    int32_t blk;        // block index within the operator (dense), -1 otherwise
+};
+
+struct Record {
+    int32_t term;   // term index within the member
+    int32_t gterm;  // global term index
+    int32_t pin, pout;  // global pair indices
+    OpBlock a, b;
+    int32_t order;  // 0: (A X) B^T, 1: A (X B^T), 2: one-sided / diagonal
+};
+
+struct Lists {  // device task lists of one pass
+    Task *tasks = nullptr;
+    int32_t ntask = 0;
+};
+
+struct PassSet {  // everything one projection direction needs in one precision
+    Lists stageA, stageB;
+    Seg *segs = nullptr;
+    DiagTerm *diags = nullptr;
+    int32_t nseg = 0, ndiag = 0;
+    int64_t tmp_elems = 0;  // intermediate buffer length (elements)
+    int32_t npart = 0;      // coefficient-gradient partials (forward only)
+};
+
+struct DavidsonWork;
+
+}  // namespace dmrg
+
+struct dmrg_plan {
+    int32_t nprob = 0;
+    int32_t prec = DMRG_F64;
+    int device = 0;
+    int64_t n = 0;
+    int64_t flop = 0;
+    int64_t bytes = 0;
+    int32_t nterm_total = 0;
+    std::vector<int64_t> member_off;     // [nprob + 1]
+    std::vector<int32_t> term_off;       // [nprob + 1]
+    std::vector<dmrg::Pair> pairs;
+    std::vector<int32_t> pair_member;
+    std::vector<dmrg::Record> records;
+    // diagonal-of-H data for the preconditioner: per member, per term, per pair
+    std::vector<dmrg::DiagTerm> hdiag_terms;      // host copy
+    std::vector<int32_t> hdiag_task_pair;         // unused placeholder
+    // device pass sets: [prec slot][direction]  slot 0 = F64, slot 1 = plan precision
+    dmrg::PassSet fwd[2], adj[2];
+    // coefficient-gradient reduction (forward F64 pass): CSR over global terms
+    int32_t *d_term_ptr = nullptr;
+    int32_t *d_term_ent = nullptr;
+    double *d_partials = nullptr;
+    // plan-owned device memory
+    std::vector<void *> owned;
+    void *d_tmp = nullptr;  // intermediate buffer (max over passes, 8-byte elements)
+    int64_t tmp_bytes = 0;
+    // preconditioner diagonal tasks (elementwise): one DiagTerm list per pair
+    dmrg::Task *d_diag_tasks = nullptr;
+    dmrg::DiagTerm *d_diag_terms = nullptr;
+    int32_t n_diag_tasks = 0;
+    dmrg::DavidsonWork *dav = nullptr;
+};
+
+namespace dmrg {
+// plan.cpp
+dmrg_status build_plan(dmrg_plan *plan, int32_t nprob, const dmrg_problem *probs, int32_t prec,
+                       hipStream_t stream);
+dmrg_status plan_free(dmrg_plan *plan);
+int tile_for(int64_t rows, int64_t cols);
+// project.hip
+// mask: optional device [nprob]; tasks of members with mask[m] == 0 are skipped
+dmrg_status launch_project(dmrg_plan *plan, int slot, const double *coef, const double *in,
+                           double *out, hipStream_t s, const int32_t *mask = nullptr);
+dmrg_status launch_adjoint(dmrg_plan *plan, const double *coef, const double *in, double *out,
+                           hipStream_t s);
+dmrg_status launch_gcoef(dmrg_plan *plan, const double *psi, const double *gbar, double *gcoef,
+                         hipStream_t s);
+dmrg_status launch_convert(const double *src, void *dst, int64_t rows, int64_t cols, int prec,
+                           int offdiag, hipStream_t s);
+dmrg_status launch_extract_diag(const double *src, double *dst, int64_t d, hipStream_t s);
+dmrg_status launch_diagonal(dmrg_plan *plan, const double *coef, double *diag, hipStream_t s);
+// davidson.hip
+dmrg_status davidson_free(dmrg_plan *plan);
+}  // namespace dmrg

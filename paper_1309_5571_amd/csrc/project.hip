@@ -1,0 +1,527 @@
+// Superblock projection kernels for gfx950 (CDNA4, wave64).
+//
+// The projection of the LR strategy is a sum over operation records
+//     Y_{jl} += c_k A_{k,i->j} X_{ik} B_{k,k->l}^T          (Eq. 10-11)
+// evaluated in two launches over task lists built once per plan:
+//   stage A: the intermediates T = A X (or X B^T) of two-sided records;
+//   stage B: every output tile of y, summing all of its records' second
+//            products, the one-sided records, and the diagonal terms, and
+//            writing the tile exactly once (no atomics, fixed order).
+// Both launches run the same grouped-GEMM kernel: one wavefront owns one
+// output tile of up to 32 x 32 (2 x 2 MFMA sub-tiles of 16 x 16) and walks
+// its list of GEMM segments.  The paper issues two cuBLAS dgemm calls per
+// record on four CUDA streams (Alg. 6-7) to overlap many small GEMMs; here
+// every tile of every record is one entry of a single launch instead.
+//
+// Operand lane layouts (checked on the device): lane l supplies A[l % 16][k]
+// and B[k][l % 16] for the k of its group l / 16 (KPL consecutive k per group
+// for BF16).  The accumulator layout differs: FP32/BF16 hold D[4 (l/16) + v]
+// [l % 16] in value v, FP64 holds D[4 v + l/16][l % 16].
+//
+// Precisions: F64 uses v_mfma_f64_16x16x4; F32 uses v_mfma_f32_16x16x4 with
+// FP32 accumulation inside a segment; BF16 uses v_mfma_f32_16x16x32_bf16.
+// Across segments, and in the diagonal epilogue, sums are FP64.
+#include <cstdio>
+
+#include "internal.h"
+
+namespace dmrg {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+// ------------------------------------------------------------------ precision traits
+
+__device__ __forceinline__ uint16_t f32_to_bf16_bits(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest, ties to even
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_bits_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+template <int PREC>
+struct Tr;
+
+template <>
+struct Tr<DMRG_F64> {
+    typedef double store_t;  // operator copies / intermediates
+    typedef double val_t;    // operand value in registers
+    typedef v4d acc_t;
+    static constexpr int KPL = 4;  // consecutive k per lane per k-block
+    // accumulator value v of lane (g = lane / 16, c = lane % 16) holds D[4 v + g][c]
+    __device__ static int row(int g, int v) { return 4 * v + g; }
+    __device__ static val_t from_in(double x) { return x; }
+    __device__ static val_t from_store(store_t x) { return x; }
+    __device__ static store_t to_store(double x) { return x; }
+    __device__ static void mma(acc_t &c, const val_t (&a)[KPL], const val_t (&b)[KPL]) {
+#pragma unroll
+        for (int j = 0; j < KPL; ++j) c = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j], b[j], c, 0, 0, 0);
+    }
+};
+
+template <>
+struct Tr<DMRG_F32> {
+    typedef float store_t;
+    typedef float val_t;
+    typedef v4f acc_t;
+    static constexpr int KPL = 4;
+    // accumulator value v of lane (g, c) holds D[4 g + v][c]
+    __device__ static int row(int g, int v) { return 4 * g + v; }
+    __device__ static val_t from_in(double x) { return (float)x; }
+    __device__ static val_t from_store(store_t x) { return x; }
+    __device__ static store_t to_store(double x) { return (float)x; }
+    __device__ static void mma(acc_t &c, const val_t (&a)[KPL], const val_t (&b)[KPL]) {
+#pragma unroll
+        for (int j = 0; j < KPL; ++j) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], b[j], c, 0, 0, 0);
+    }
+};
+
+template <>
+struct Tr<DMRG_BF16> {
+    typedef uint16_t store_t;  // bf16 bit pattern
+    typedef uint16_t val_t;
+    typedef v4f acc_t;
+    static constexpr int KPL = 8;
+    // accumulator value v of lane (g, c) holds D[4 g + v][c]
+    __device__ static int row(int g, int v) { return 4 * g + v; }
+    __device__ static val_t from_in(double x) { return f32_to_bf16_bits((float)x); }
+    __device__ static val_t from_store(store_t x) { return x; }
+    __device__ static store_t to_store(double x) { return f32_to_bf16_bits((float)x); }
+    __device__ static void mma(acc_t &c, const val_t (&a)[KPL], const val_t (&b)[KPL]) {
+        v8bf va, vb;
+#pragma unroll
+        for (int j = 0; j < KPL; ++j) {
+            va[j] = __builtin_bit_cast(__bf16, a[j]);
+            vb[j] = __builtin_bit_cast(__bf16, b[j]);
+        }
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(va, vb, c, 0, 0, 0);
+    }
+};
+
+// ------------------------------------------------------------------ operand fetch
+
+// P fragment: rows row (tile-local r), k = kb + KPL*g + j
+template <int PREC, bool PIN, bool PT>
+__device__ __forceinline__ void load_p(typename Tr<PREC>::val_t (&v)[Tr<PREC>::KPL], const Seg &s,
+                                       const double *__restrict__ in, const void *__restrict__ tmp, int row,
+                                       bool row_ok, int k0, int K, double scale) {
+    typedef Tr<PREC> T;
+    if (PIN) {
+        const double *P = in + s.p;
+#pragma unroll
+        for (int j = 0; j < T::KPL; ++j) {
+            int k = k0 + j;
+            double x = 0.0;
+            if (row_ok && k < K) x = PT ? P[(int64_t)k * s.ldp + row] : P[(int64_t)row * s.ldp + k];
+            v[j] = T::from_in(x * scale);
+        }
+    } else {
+        const typename T::store_t *P = (s.pkind == OPD_ABS)
+                                           ? (const typename T::store_t *)(uintptr_t)s.p
+                                           : (const typename T::store_t *)tmp + s.p;
+#pragma unroll
+        for (int j = 0; j < T::KPL; ++j) {
+            int k = k0 + j;
+            typename T::store_t x = 0;
+            if (row_ok && k < K) x = PT ? P[(int64_t)k * s.ldp + row] : P[(int64_t)row * s.ldp + k];
+            v[j] = T::from_store(x);
+        }
+    }
+}
+
+// Q fragment: column col, k = kb + KPL*g + j
+template <int PREC, bool QIN, bool QT>
+__device__ __forceinline__ void load_q(typename Tr<PREC>::val_t (&v)[Tr<PREC>::KPL], const Seg &s,
+                                       const double *__restrict__ in, const void *__restrict__ tmp, int col,
+                                       bool col_ok, int k0, int K, double scale) {
+    typedef Tr<PREC> T;
+    if (QIN) {
+        const double *Q = in + s.q;
+#pragma unroll
+        for (int j = 0; j < T::KPL; ++j) {
+            int k = k0 + j;
+            double x = 0.0;
+            if (col_ok && k < K) x = QT ? Q[(int64_t)col * s.ldq + k] : Q[(int64_t)k * s.ldq + col];
+            v[j] = T::from_in(x * scale);
+        }
+    } else {
+        const typename T::store_t *Q = (s.qkind == OPD_ABS)
+                                           ? (const typename T::store_t *)(uintptr_t)s.q
+                                           : (const typename T::store_t *)tmp + s.q;
+#pragma unroll
+        for (int j = 0; j < T::KPL; ++j) {
+            int k = k0 + j;
+            typename T::store_t x = 0;
+            if (col_ok && k < K) x = QT ? Q[(int64_t)col * s.ldq + k] : Q[(int64_t)k * s.ldq + col];
+            v[j] = T::from_store(x);
+        }
+    }
+}
+
+// One segment: acc[sr][sc] = op(P)[tile rows, :] op(Q)[:, tile cols]
+template <int PREC, bool PIN, bool PT, bool QIN, bool QT>
+__device__ __forceinline__ void seg_gemm(typename Tr<PREC>::acc_t (&acc)[2][2], const Seg &s, const Task &tk,
+                                         const double *__restrict__ in, const void *__restrict__ tmp, int nsr,
+                                         int nsc) {
+    typedef Tr<PREC> T;
+    constexpr int KB = 4 * T::KPL;
+    const int lane = threadIdx.x & 63;
+    const int r16 = lane & 15, g = lane >> 4;
+    int prow[2], qcol[2];
+    bool pok[2], qok[2];
+    double ps[2] = {1.0, 1.0}, qs[2] = {1.0, 1.0};
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        int r = t * 16 + r16;
+        pok[t] = r < tk.m;
+        prow[t] = tk.row0 + (pok[t] ? r : 0);
+        int c = t * 16 + r16;
+        qok[t] = c < tk.n;
+        qcol[t] = tk.col0 + (qok[t] ? c : 0);
+        if (PIN && s.pscale && pok[t]) ps[t] = ((const double *)(uintptr_t)s.pscale)[prow[t]];
+        if (QIN && s.qscale && qok[t]) qs[t] = ((const double *)(uintptr_t)s.qscale)[qcol[t]];
+    }
+    for (int kb = 0; kb < s.K; kb += KB) {
+        typename T::val_t pv[2][T::KPL], qv[2][T::KPL];
+        const int k0 = kb + T::KPL * g;
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            if (t < nsr) load_p<PREC, PIN, PT>(pv[t], s, in, tmp, prow[t], pok[t], k0, s.K, ps[t]);
+            if (t < nsc) load_q<PREC, QIN, QT>(qv[t], s, in, tmp, qcol[t], qok[t], k0, s.K, qs[t]);
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+                if (a < nsr && b < nsc) T::mma(acc[a][b], pv[a], qv[b]);
+    }
+}
+
+template <int PREC>
+__device__ __forceinline__ void seg_dispatch(typename Tr<PREC>::acc_t (&acc)[2][2], const Seg &s, const Task &tk,
+                                             const double *__restrict__ in, const void *__restrict__ tmp, int nsr,
+                                             int nsc) {
+    const bool pin = s.pkind == OPD_IN, qin = s.qkind == OPD_IN;
+    const int code = (pin ? 8 : 0) | (s.ptrans ? 4 : 0) | (qin ? 2 : 0) | (s.qtrans ? 1 : 0);
+    switch (code) {
+        case 0: seg_gemm<PREC, false, false, false, false>(acc, s, tk, in, tmp, nsr, nsc); break;
+        case 1: seg_gemm<PREC, false, false, false, true>(acc, s, tk, in, tmp, nsr, nsc); break;
+        case 2: seg_gemm<PREC, false, false, true, false>(acc, s, tk, in, tmp, nsr, nsc); break;
+        case 3: seg_gemm<PREC, false, false, true, true>(acc, s, tk, in, tmp, nsr, nsc); break;
+        case 4: seg_gemm<PREC, false, true, false, false>(acc, s, tk, in, tmp, nsr, nsc); break;
+        case 5: seg_gemm<PREC, false, true, false, true>(acc, s, tk, in, tmp, nsr, nsc); break;
+        case 6: seg_gemm<PREC, false, true, true, false>(acc, s, tk, in, tmp, nsr, nsc); break;
+        case 7: seg_gemm<PREC, false, true, true, true>(acc, s, tk, in, tmp, nsr, nsc); break;
+        case 8: seg_gemm<PREC, true, false, false, false>(acc, s, tk, in, tmp, nsr, nsc); break;
+        case 9: seg_gemm<PREC, true, false, false, true>(acc, s, tk, in, tmp, nsr, nsc); break;
+        case 10: seg_gemm<PREC, true, false, true, false>(acc, s, tk, in, tmp, nsr, nsc); break;
+        case 11: seg_gemm<PREC, true, false, true, true>(acc, s, tk, in, tmp, nsr, nsc); break;
+        case 12: seg_gemm<PREC, true, true, false, false>(acc, s, tk, in, tmp, nsr, nsc); break;
+        case 13: seg_gemm<PREC, true, true, false, true>(acc, s, tk, in, tmp, nsr, nsc); break;
+        case 14: seg_gemm<PREC, true, true, true, false>(acc, s, tk, in, tmp, nsr, nsc); break;
+        default: seg_gemm<PREC, true, true, true, true>(acc, s, tk, in, tmp, nsr, nsc); break;
+    }
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// MODE 0: write the intermediate (store_t) of stage A.
+// MODE 1: write FP64 output tiles with the diagonal epilogue (stage B).
+// MODE 2: coefficient-gradient partials <gbar, segment product> per segment
+//         and per diagonal term (stage B task list of the FP64 pass).
+template <int PREC, int MODE>
+__global__ __launch_bounds__(64) void k_tasks(const Task *__restrict__ tasks, int ntask,
+                                             const Seg *__restrict__ segs, const DiagTerm *__restrict__ diags,
+                                             const double *__restrict__ in, const void *__restrict__ tmp,
+                                             void *__restrict__ out, const double *__restrict__ coef,
+                                             const double *__restrict__ gbar, double *__restrict__ partials,
+                                             const int32_t *__restrict__ mask) {
+    typedef Tr<PREC> T;
+    const int t = blockIdx.x;
+    if (t >= ntask) return;
+    const Task tk = tasks[t];
+    if (mask && !mask[tk.member]) return;
+    const int lane = threadIdx.x & 63;
+    const int r16 = lane & 15, g = lane >> 4;
+    const int nsr = (tk.m + 15) >> 4, nsc = (tk.n + 15) >> 4;
+    double tot[2][2][4];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) tot[a][b][v] = 0.0;
+
+    for (int si = tk.seg_begin; si < tk.seg_end; ++si) {
+        const Seg s = segs[si];
+        typename T::acc_t acc[2][2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) acc[a][b] = typename T::acc_t{0, 0, 0, 0};
+        seg_dispatch<PREC>(acc, s, tk, in, tmp, nsr, nsc);
+        if (MODE == 2) {
+            double part = 0.0;
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        int r = a * 16 + T::row(g, v), c = b * 16 + r16;
+                        if (a < nsr && b < nsc && r < tk.m && c < tk.n)
+                            part += (double)acc[a][b][v] *
+                                    gbar[tk.c_off + (int64_t)(tk.row0 + r) * tk.ldc + tk.col0 + c];
+                    }
+            part = wave_sum(part);
+            if (lane == 0) partials[tk.part0 + (si - tk.seg_begin)] = part;
+        } else {
+            const double c = s.coef >= 0 ? coef[s.coef] : 1.0;
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) tot[a][b][v] += c * (double)acc[a][b][v];
+        }
+    }
+
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            if (a >= nsr || b >= nsc) continue;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = a * 16 + T::row(g, v), c = b * 16 + r16;
+                const bool ok = r < tk.m && c < tk.n;
+                const int64_t rr = tk.row0 + r, cc = tk.col0 + c;
+                const int64_t o = tk.c_off + rr * tk.ldc + cc;
+                if (MODE == 0) {
+                    if (ok) ((typename T::store_t *)out)[o] = T::to_store(tot[a][b][v]);
+                } else if (MODE == 1) {
+                    double val = tot[a][b][v];
+                    if (ok) {
+                        const double x = in[tk.x_off + rr * tk.ldc + cc];
+                        for (int d = tk.diag_begin; d < tk.diag_end; ++d) {
+                            const DiagTerm dt = diags[d];
+                            double w = coef[dt.coef] * x;
+                            if (dt.vl) w *= ((const double *)(uintptr_t)dt.vl)[rr * dt.sl];
+                            if (dt.vr) w *= ((const double *)(uintptr_t)dt.vr)[cc * dt.sr];
+                            val += w;
+                        }
+                        ((double *)out)[o] = val;
+                    }
+                }
+            }
+        }
+    }
+    if (MODE == 2) {
+        const int nseg = tk.seg_end - tk.seg_begin;
+        for (int d = tk.diag_begin; d < tk.diag_end; ++d) {
+            const DiagTerm dt = diags[d];
+            double part = 0.0;
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int r = a * 16 + T::row(g, v), c = b * 16 + r16;
+                        if (a < nsr && b < nsc && r < tk.m && c < tk.n) {
+                            const int64_t rr = tk.row0 + r, cc = tk.col0 + c;
+                            double w = in[tk.x_off + rr * tk.ldc + cc] * gbar[tk.c_off + rr * tk.ldc + cc];
+                            if (dt.vl) w *= ((const double *)(uintptr_t)dt.vl)[rr * dt.sl];
+                            if (dt.vr) w *= ((const double *)(uintptr_t)dt.vr)[cc * dt.sr];
+                            part += w;
+                        }
+                    }
+            part = wave_sum(part);
+            if (lane == 0) partials[tk.part0 + nseg + (d - tk.diag_begin)] = part;
+        }
+    }
+}
+
+// gcoef[k] = sum of the partial slots listed for term k, in list order.
+__global__ __launch_bounds__(64) void k_reduce_terms(const int32_t *__restrict__ ptr, const int32_t *__restrict__ ent,
+                                                     const double *__restrict__ partials, double *__restrict__ gcoef,
+                                                     int nterm) {
+    const int k = blockIdx.x;
+    if (k >= nterm) return;
+    double s = 0.0;
+    for (int i = ptr[k] + (int)threadIdx.x; i < ptr[k + 1]; i += 64) s += partials[ent[i]];
+    s = wave_sum(s);
+    if (threadIdx.x == 0) gcoef[k] = s;
+}
+
+// Elementwise diagonal of H (preconditioner): out = sum_d c_d vl[r sl] vr[c sr].
+__global__ __launch_bounds__(256) void k_hdiag(const Task *__restrict__ tasks, int ntask,
+                                               const DiagTerm *__restrict__ diags, const double *__restrict__ coef,
+                                               double *__restrict__ out) {
+    const int t = blockIdx.x;
+    if (t >= ntask) return;
+    const Task tk = tasks[t];
+    const int64_t cnt = (int64_t)tk.m * tk.n;
+    for (int64_t e = threadIdx.x; e < cnt; e += 256) {
+        const int64_t r = tk.row0 + e / tk.n, c = e % tk.n;
+        double v = 0.0;
+        for (int d = tk.diag_begin; d < tk.diag_end; ++d) {
+            const DiagTerm dt = diags[d];
+            double w = coef[dt.coef];
+            if (dt.vl) w *= ((const double *)(uintptr_t)dt.vl)[r * dt.sl];
+            if (dt.vr) w *= ((const double *)(uintptr_t)dt.vr)[c * dt.sr];
+            v += w;
+        }
+        out[tk.c_off + r * tk.ldc + c] = v;
+    }
+}
+
+// FP64 block -> FP32 / BF16 copy (round to nearest even), optionally with a zero diagonal.
+__global__ __launch_bounds__(256) void k_convert(const double *__restrict__ src, void *__restrict__ dst,
+                                                 int64_t rows, int64_t cols, int prec, int offdiag) {
+    const int64_t cnt = rows * cols;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < cnt; e += (int64_t)gridDim.x * 256) {
+        double x = src[e];
+        if (offdiag && (e / cols) == (e % cols)) x = 0.0;
+        float f = (float)x;
+        if (prec == DMRG_F32)
+            ((float *)dst)[e] = f;
+        else
+            ((uint16_t *)dst)[e] = f32_to_bf16_bits(f);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_extract_diag(const double *__restrict__ src, double *__restrict__ dst,
+                                                      int64_t d) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < d; i += (int64_t)gridDim.x * 256)
+        dst[i] = src[i * (d + 1)];
+}
+
+// ------------------------------------------------------------------ launchers
+
+template <int PREC>
+static dmrg_status run_pass(const PassSet &ps, const double *coef, const double *in, void *tmp, double *out,
+                            hipStream_t s, const int32_t *mask) {
+    if (ps.stageA.ntask)
+        hipLaunchKernelGGL((k_tasks<PREC, 0>), dim3(ps.stageA.ntask), dim3(64), 0, s, ps.stageA.tasks,
+                           ps.stageA.ntask, ps.segs, ps.diags, in, (const void *)tmp, tmp, coef, nullptr, nullptr,
+                           mask);
+    if (ps.stageB.ntask)
+        hipLaunchKernelGGL((k_tasks<PREC, 1>), dim3(ps.stageB.ntask), dim3(64), 0, s, ps.stageB.tasks,
+                           ps.stageB.ntask, ps.segs, ps.diags, in, (const void *)tmp, (void *)out, coef, nullptr,
+                           nullptr, mask);
+    DMRG_HIP(hipGetLastError());
+    return DMRG_OK;
+}
+
+dmrg_status launch_project(dmrg_plan *plan, int slot, const double *coef, const double *in, double *out,
+                           hipStream_t s, const int32_t *mask) {
+    if (slot == 0) return run_pass<DMRG_F64>(plan->fwd[0], coef, in, plan->d_tmp, out, s, mask);
+    if (plan->prec == DMRG_F32) return run_pass<DMRG_F32>(plan->fwd[1], coef, in, plan->d_tmp, out, s, mask);
+    return run_pass<DMRG_BF16>(plan->fwd[1], coef, in, plan->d_tmp, out, s, mask);
+}
+
+dmrg_status launch_adjoint(dmrg_plan *plan, const double *coef, const double *in, double *out, hipStream_t s) {
+    return run_pass<DMRG_F64>(plan->adj[0], coef, in, plan->d_tmp, out, s, nullptr);
+}
+
+dmrg_status launch_gcoef(dmrg_plan *plan, const double *psi, const double *gbar, double *gcoef, hipStream_t s) {
+    const PassSet &ps = plan->fwd[0];
+    if (ps.stageA.ntask)
+        hipLaunchKernelGGL((k_tasks<DMRG_F64, 0>), dim3(ps.stageA.ntask), dim3(64), 0, s, ps.stageA.tasks,
+                           ps.stageA.ntask, ps.segs, ps.diags, psi, (const void *)plan->d_tmp, plan->d_tmp,
+                           (const double *)nullptr, nullptr, nullptr, nullptr);
+    if (ps.stageB.ntask)
+        hipLaunchKernelGGL((k_tasks<DMRG_F64, 2>), dim3(ps.stageB.ntask), dim3(64), 0, s, ps.stageB.tasks,
+                           ps.stageB.ntask, ps.segs, ps.diags, psi, (const void *)plan->d_tmp, nullptr,
+                           (const double *)nullptr, gbar, plan->d_partials, nullptr);
+    if (plan->nterm_total)
+        hipLaunchKernelGGL(k_reduce_terms, dim3(plan->nterm_total), dim3(64), 0, s, plan->d_term_ptr,
+                           plan->d_term_ent, (const double *)plan->d_partials, gcoef, plan->nterm_total);
+    DMRG_HIP(hipGetLastError());
+    return DMRG_OK;
+}
+
+dmrg_status launch_convert(const double *src, void *dst, int64_t rows, int64_t cols, int prec, int offdiag,
+                           hipStream_t s) {
+    int64_t cnt = rows * cols;
+    if (cnt <= 0) return DMRG_OK;
+    int grid = (int)std::min<int64_t>((cnt + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_convert, dim3(grid), dim3(256), 0, s, src, dst, rows, cols, prec, offdiag);
+    DMRG_HIP(hipGetLastError());
+    return DMRG_OK;
+}
+
+dmrg_status launch_extract_diag(const double *src, double *dst, int64_t d, hipStream_t s) {
+    if (d <= 0) return DMRG_OK;
+    int grid = (int)std::min<int64_t>((d + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_extract_diag, dim3(grid), dim3(256), 0, s, src, dst, d);
+    DMRG_HIP(hipGetLastError());
+    return DMRG_OK;
+}
+
+dmrg_status launch_diagonal(dmrg_plan *plan, const double *coef, double *diag, hipStream_t s) {
+    if (plan->n_diag_tasks)
+        hipLaunchKernelGGL(k_hdiag, dim3(plan->n_diag_tasks), dim3(256), 0, s, plan->d_diag_tasks,
+                           plan->n_diag_tasks, plan->d_diag_terms, coef, diag);
+    DMRG_HIP(hipGetLastError());
+    return DMRG_OK;
+}
+
+}  // namespace dmrg
+
+// ================================================================== ABI
+
+using namespace dmrg;
+
+static dmrg_status check_device(const dmrg_plan *plan) {
+    int cur = -1;
+    DMRG_HIP(hipGetDevice(&cur));
+    if (cur != plan->device)
+        return set_error(DMRG_E_INVALID_ARG, "plan was created on device %d but device %d is current", plan->device,
+                         cur);
+    return DMRG_OK;
+}
+
+extern "C" {
+
+dmrg_status dmrg_project(dmrg_plan *plan, int32_t prec, const double *coef, const double *psi, double *y,
+                         void *stream) {
+    clear_error();
+    if (!plan || !psi || !y || (!coef && plan->nterm_total))
+        return set_error(DMRG_E_INVALID_ARG, "null plan, coef, psi or y");
+    if (prec != DMRG_F64 && prec != plan->prec)
+        return set_error(DMRG_E_INVALID_ARG, "precision %d not available in this plan (built for %d)", prec,
+                         plan->prec);
+    if (psi == y) return set_error(DMRG_E_INVALID_ARG, "psi and y must not overlap");
+    DMRG_TRY(check_device(plan));
+    return launch_project(plan, prec == DMRG_F64 ? 0 : 1, coef, psi, y, (hipStream_t)stream);
+}
+
+dmrg_status dmrg_project_backward(dmrg_plan *plan, const double *coef, const double *psi, const double *gbar,
+                                  double *gpsi, double *gcoef, void *stream) {
+    clear_error();
+    if (!plan || !gbar) return set_error(DMRG_E_INVALID_ARG, "null plan or gbar");
+    if (gpsi && !coef && plan->nterm_total) return set_error(DMRG_E_INVALID_ARG, "gpsi needs coef");
+    if (gcoef && !psi) return set_error(DMRG_E_INVALID_ARG, "gcoef needs psi");
+    if (gpsi && gpsi == gbar) return set_error(DMRG_E_INVALID_ARG, "gpsi and gbar must not overlap");
+    DMRG_TRY(check_device(plan));
+    hipStream_t s = (hipStream_t)stream;
+    if (gcoef) DMRG_TRY(launch_gcoef(plan, psi, gbar, gcoef, s));
+    if (gpsi) DMRG_TRY(launch_adjoint(plan, coef, gbar, gpsi, s));
+    return DMRG_OK;
+}
+
+dmrg_status dmrg_diagonal(dmrg_plan *plan, const double *coef, double *diag, void *stream) {
+    clear_error();
+    if (!plan || !diag || (!coef && plan->nterm_total)) return set_error(DMRG_E_INVALID_ARG, "null argument");
+    DMRG_TRY(check_device(plan));
+    return launch_diagonal(plan, coef, diag, (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,127 @@
+"""Host-only checks of the C ABI: the library loads, exports every declared
+entry point, and its host-side validation returns the documented status
+codes without touching a GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import gen
+from paper_1309_5571_amd import _native as N
+from paper_1309_5571_amd import problem_check
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "dmrg.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dmrg_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    lib = N.lib()
+    names = declared_functions()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(N.SIGNATURES), "binding and header disagree"
+
+
+def test_version_and_default_opts():
+    assert b"gfx950" in N.lib().dmrg_version()
+    o = N.DavidsonOpts()
+    N.lib().dmrg_davidson_default_opts(ctypes.byref(o))
+    assert (o.tol, o.kmax, o.kmin, o.max_iter, o.precond_floor, o.refine, o.use_graph) == (1e-10, 32, 8, 500, 1e-3, 1, 1)
+
+
+def test_struct_sizes_match_c_layout():
+    assert ctypes.sizeof(N.Space) == 24
+    assert ctypes.sizeof(N.Op) == 40
+    assert ctypes.sizeof(N.DavidsonOpts) == 64
+    assert ctypes.sizeof(N.DavidsonInfo) == 40
+
+
+@pytest.mark.parametrize("cfg", [1, 2, 3, 5])
+def test_valid_problems_pass(cfg):
+    assert problem_check(gen.config(cfg)) == N.OK
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_random_problems_pass(seed):
+    assert problem_check(gen.random_problem(seed, rank=1 + seed % 2)) == N.OK
+
+
+def test_unsorted_labels():
+    p = gen.heisenberg_synthetic(64, seed=1)
+    p.left.labels = p.left.labels[::-1].copy()
+    assert problem_check(p) == N.E_LAYOUT
+
+
+def test_duplicate_labels():
+    p = gen.heisenberg_synthetic(64, seed=1)
+    p.right.labels = p.right.labels.copy()
+    p.right.labels[1] = p.right.labels[0]
+    assert problem_check(p) == N.E_LAYOUT
+
+
+def test_non_conserving_term():
+    p = gen.heisenberg_synthetic(64, seed=1)
+    p.terms = np.array([[3, 3]], dtype=np.int32)  # S+ (x) S+
+    p.coef = np.array([1.0])
+    assert problem_check(p) == N.E_SECTOR
+
+
+def test_duplicate_block():
+    p = gen.heisenberg_synthetic(64, seed=1)
+    op = p.ops_left[3]
+    op.src = np.concatenate([op.src, op.src[:1]])
+    op.dst = np.concatenate([op.dst, op.dst[:1]])
+    op.blocks = op.blocks + [op.blocks[0]]
+    assert problem_check(p) == N.E_LAYOUT
+
+
+def test_bad_indices():
+    p = gen.heisenberg_synthetic(64, seed=1)
+    p.terms = np.array([[0, 99]], dtype=np.int32)
+    p.coef = np.array([1.0])
+    assert problem_check(p) == N.E_INVALID_ARG
+    q = gen.heisenberg_synthetic(64, seed=1)
+    q.ops_left[3].src = q.ops_left[3].src.copy()
+    q.ops_left[3].src[0] = 1000
+    assert problem_check(q) == N.E_INVALID_ARG
+
+
+def test_negative_dim_and_rank_mismatch():
+    p = gen.heisenberg_synthetic(64, seed=1)
+    p.left.dims = p.left.dims.copy()
+    p.left.dims[0] = -1
+    assert problem_check(p) == N.E_INVALID_ARG
+    q = gen.hubbard_synthetic(64, seed=1)
+    q.right.labels = q.right.labels[:, :1].copy()
+    assert problem_check(q) in (N.E_INVALID_ARG, N.E_LAYOUT)
+
+
+def test_plan_create_rejects_invalid_input_without_gpu():
+    """Validation happens before any device call, so it works on a CPU host."""
+    from paper_1309_5571_amd import _Marshal
+
+    p = gen.heisenberg_synthetic(64, seed=1)
+    p.terms = np.array([[3, 3]], dtype=np.int32)
+    p.coef = np.array([1.0])
+    m = _Marshal([p], device=None)
+    h = ctypes.c_void_p()
+    st = N.lib().dmrg_plan_create(ctypes.byref(h), 1, m.structs, N.F64, None)
+    assert st == N.E_SECTOR and not h.value
+    assert "target sector" in N.last_error()
+    st = N.lib().dmrg_plan_create(ctypes.byref(h), 1, m.structs, 7, None)
+    assert st == N.E_INVALID_ARG
+
+
+def test_gemv_argument_errors():
+    lib = N.lib()
+    assert lib.dmrg_gemv_t(0, 1, None, 1, None, None, None) == N.E_INVALID_ARG
+    assert lib.dmrg_gemv_n(10, 65, None, 10, None, 0.0, None, None) == N.E_INVALID_ARG
+    assert lib.dmrg_set_tile_table(1, (ctypes.c_int32 * 1)(8), (ctypes.c_int32 * 1)(24)) == N.E_INVALID_ARG
