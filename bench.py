@@ -86,6 +86,10 @@ def cpu_baseline(p, x0):
     }, r.energy
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -114,9 +118,11 @@ def main():
         _, gcoef = plan.backward_raw(psi, psi, coef, want_psi=False, want_coef=True)
         return E, info, gcoef
 
+    log(f"plan ready: n={plan.n}, records={plan.nrec}, flop/projection={plan.flop}")
     for _ in range(args.warmup):
         step(args.prec)
     torch.cuda.synchronize()
+    log("warmup done")
     iters = 0
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -124,6 +130,7 @@ def main():
         iters += info[0]["iterations"]
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    log(f"timed {args.steps} steps: {dt / args.steps * 1e3:.3f} ms/step, {iters / dt:.1f} iter/s")
     E_mixed = float(E[0])
     info_mixed = info[0]
 
@@ -152,6 +159,7 @@ def main():
             t = timed_projection(pl, psi, y, prec, args.proj_reps, torch)
             proj[prec] = {"us": t * 1e6, "tflops": plan.flop / t * 1e-12}
         extra["projection"] = proj
+        log(f"projection: {proj}")
         extra["mixed_vs_fp64_time_ratio"] = (dt / args.steps * 1e3) / extra["fp64_solve"]["ms_per_solve"]
 
     # roofline of the dominant kernel: the FP64 projection, bound by HBM bytes at
@@ -167,6 +175,7 @@ def main():
     cpu = None
     E_ref = None
     if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
         cpu, E_ref = cpu_baseline(p, x0_np)
 
     out = {

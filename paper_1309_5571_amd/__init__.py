@@ -130,9 +130,13 @@ class Plan:
 
     ``prec``: "f64", "f32" or "bf16" -- the reduced precision the plan
     prepares in addition to FP64.
+    ``tiles``: "auto" applies the autotuned tile table stored for this
+    workload class and precision (built-in table if none is stored), None
+    keeps the process-wide table as set by :func:`set_tile_table`, or a pair
+    ``(bounds, tiles)`` is used for this plan only.
     """
 
-    def __init__(self, problems, prec: str = "f64", device=None):
+    def __init__(self, problems, prec: str = "f64", device=None, tiles="auto"):
         import torch
 
         if not isinstance(problems, (list, tuple)):
@@ -142,11 +146,26 @@ class Plan:
                                    torch.device(device).index or 0)
         self.prec = N.PREC[prec]
         self._lib = N.lib()
+        table = None
+        if tiles == "auto":
+            from . import autotune
+
+            table = autotune.load_table(autotune.key_of(self.problems, prec))
+        elif tiles is not None:
+            table = tiles
+        self.tiles = table
         with torch.cuda.device(self.device):
             self._m = _Marshal(self.problems, device=self.device)
             h = ctypes.c_void_p()
-            N.check(self._lib.dmrg_plan_create(ctypes.byref(h), len(self.problems), self._m.structs, self.prec,
-                                               _stream(self.device)))
+            if table is not None:
+                set_tile_table(*table)
+            try:
+                st = self._lib.dmrg_plan_create(ctypes.byref(h), len(self.problems), self._m.structs, self.prec,
+                                                _stream(self.device))
+            finally:
+                if table is not None:
+                    set_tile_table((), ())
+            N.check(st)
         self._h = h
         n, npair, nrec, flop, nbytes = (ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64(),
                                         ctypes.c_int64())

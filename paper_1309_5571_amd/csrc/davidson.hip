@@ -49,6 +49,7 @@ struct DavArgs {
     int nprob = 0;
     int nchunk = 0;
     double *V = nullptr, *W = nullptr, *T = nullptr, *D = nullptr, *coef = nullptr;
+    double *dfold = nullptr;         // [n] folded diagonal terms of the current phase's pass
     double *part = nullptr;          // [nchunk][KM + 2]
     int32_t *chunk_member = nullptr;
     int64_t *chunk_begin = nullptr;  // [nchunk + 1] element ranges
@@ -90,6 +91,29 @@ __device__ double member_sum(const double *part, int c0, int c1, int j, double *
     double r[1] = {v};
     block_reduce<1>(r, 1, lds);
     return r[0];
+}
+
+// Sums columns [0, ncols) of the member's chunk partials at once: thread t owns
+// column t % ncols and every (TPB / ncols)-th chunk from t / ncols, then the
+// per-thread sums of each column are added in slot order.  out: shared [ncols].
+__device__ void member_sums(const double *__restrict__ part, int c0, int c1, int ncols, double *scratch,
+                            double *out) {
+    const int t = threadIdx.x;
+    const int per = TPB / ncols;
+    const int j = t % ncols, slot = t / ncols;
+    double v = 0.0;
+    if (slot < per) {
+#pragma unroll 4
+        for (int c = c0 + slot; c < c1; c += per) v += part[(size_t)c * (KM + 2) + j];
+    }
+    scratch[t] = v;
+    __syncthreads();
+    if (t < ncols) {
+        double acc = 0.0;
+        for (int q = 0; q < per; ++q) acc += scratch[t + q * ncols];
+        out[t] = acc;
+    }
+    __syncthreads();
 }
 
 // ------------------------------------------------------------------ init kernels
@@ -140,11 +164,15 @@ __global__ __launch_bounds__(TPB) void k_init_vec(const double *__restrict__ psi
     if (threadIdx.x == 0) w.part[(size_t)c * (KM + 2)] = red[0];
     const int c0 = w.member_chunk[member], c1 = w.member_chunk[member + 1];
     if (!last_block_of_member(w.counter, member, c1 - c0)) return;
-    if (threadIdx.x == 0) {
-        double m = INFINITY;
-        for (int q = c0; q < c1; ++q) m = fmin(m, w.part[(size_t)q * (KM + 2)]);
-        w.st[member].dmin = m;
+    mn = INFINITY;
+    for (int q = c0 + (int)threadIdx.x; q < c1; q += TPB) mn = fmin(mn, w.part[(size_t)q * (KM + 2)]);
+    red[threadIdx.x] = mn;
+    __syncthreads();
+    for (int off = TPB / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + off]);
+        __syncthreads();
     }
+    if (threadIdx.x == 0) w.st[member].dmin = red[0];
     (void)lds;
 }
 
@@ -296,9 +324,11 @@ __global__ __launch_bounds__(TPB) void k_rayleigh(DavArgs w, int i) {
     const double *wc = w.W + (int64_t)(i - 1) * n;
     for (int64_t e = w.chunk_begin[c] + threadIdx.x; e < w.chunk_begin[c + 1]; e += TPB) {
         const double x = wc[e];
+        double v[KB];
 #pragma unroll
-        for (int j = 0; j < KB; ++j)
-            if (j < i) acc[j] += w.V[(int64_t)j * n + e] * x;
+        for (int j = 0; j < KB; ++j) v[j] = w.V[(int64_t)min(j, i - 1) * n + e];  // clamped: no branch
+#pragma unroll
+        for (int j = 0; j < KB; ++j) acc[j] += (j < i ? v[j] : 0.0) * x;
     }
     block_reduce<KB>(acc, i, &L.Tm[0][0]);  // Tm is free until the eigensolve
     if (threadIdx.x == 0)
@@ -306,12 +336,12 @@ __global__ __launch_bounds__(TPB) void k_rayleigh(DavArgs w, int i) {
     const int c0 = w.member_chunk[member], c1 = w.member_chunk[member + 1];
     if (!last_block_of_member(w.counter, member, c1 - c0)) return;
     DavState &S = w.st[member];
-    for (int j = 0; j < i; ++j) {
-        double b = member_sum(w.part, c0, c1, j, L.red);
-        if (threadIdx.x == 0) {
-            S.Bm[j * KM + (i - 1)] = b;
-            S.Bm[(i - 1) * KM + j] = b;
-        }
+    member_sums(w.part, c0, c1, i, &L.Tm[0][0], &L.A[0][0]);
+    if ((int)threadIdx.x < i) {
+        const int j = threadIdx.x;
+        const double b = L.A[0][j];
+        S.Bm[j * KM + (i - 1)] = b;
+        S.Bm[(i - 1) * KM + j] = b;
     }
     __syncthreads();
     jacobi_eig(S, i, L);
@@ -327,6 +357,8 @@ __global__ __launch_bounds__(TPB) void k_rayleigh(DavArgs w, int i) {
 template <int KB>
 __global__ __launch_bounds__(TPB) void k_ritz(DavArgs w, int i, int restart) {
     __shared__ double lds[4 * (KB + 2)];
+    __shared__ double scratch[TPB];
+    __shared__ double sums[KB + 2];
     const int c = blockIdx.x;
     const int member = w.chunk_member[c];
     const DavState &S = w.st[member];
@@ -340,17 +372,18 @@ __global__ __launch_bounds__(TPB) void k_ritz(DavArgs w, int i, int restart) {
 #pragma unroll
     for (int j = 0; j < KB + 2; ++j) acc[j] = 0.0;
     for (int64_t e = w.chunk_begin[c] + threadIdx.x; e < w.chunk_begin[c + 1]; e += TPB) {
-        double v[KB];
+        double v[KB], wv[KB];
         double x = 0.0, wy = 0.0;
 #pragma unroll
         for (int j = 0; j < KB; ++j) {
-            if (j < i) {
-                v[j] = w.V[(int64_t)j * n + e];
-                x += v[j] * y[j];
-                wy += w.W[(int64_t)j * n + e] * y[j];
-            } else {
-                v[j] = 0.0;
-            }
+            v[j] = w.V[(int64_t)min(j, i - 1) * n + e];
+            wv[j] = w.W[(int64_t)min(j, i - 1) * n + e];
+        }
+#pragma unroll
+        for (int j = 0; j < KB; ++j) {
+            v[j] = (j < i) ? v[j] : 0.0;
+            x += v[j] * y[j];
+            wy += wv[j] * y[j];
         }
         const double r = wy - lam * x;
         double den = w.D[e] - sig;
@@ -361,8 +394,7 @@ __global__ __launch_bounds__(TPB) void k_ritz(DavArgs w, int i, int restart) {
         acc[KB + 1] += t * t;
         if (!restart) {
 #pragma unroll
-            for (int j = 0; j < KB; ++j)
-                if (j < i) acc[j] += v[j] * t;
+            for (int j = 0; j < KB; ++j) acc[j] += v[j] * t;
         }
     }
     block_reduce<KB + 2>(acc, KB + 2, lds);
@@ -372,15 +404,13 @@ __global__ __launch_bounds__(TPB) void k_ritz(DavArgs w, int i, int restart) {
     const int c0 = w.member_chunk[member], c1 = w.member_chunk[member + 1];
     if (!last_block_of_member(w.counter, member, c1 - c0)) return;
     DavState &Sm = w.st[member];
-    const double rr = member_sum(w.part, c0, c1, KB, lds);
-    const double tt = member_sum(w.part, c0, c1, KB + 1, lds);
+    member_sums(w.part, c0, c1, KB + 2, scratch, sums);
+    const double rr = sums[KB];
+    const double tt = sums[KB + 1];
     double ss = 0.0;
     if (!restart) {
-        for (int j = 0; j < i; ++j) {
-            double sj = member_sum(w.part, c0, c1, j, lds);
-            if (threadIdx.x == 0) Sm.s[j] = sj;
-            ss += sj * sj;
-        }
+        if ((int)threadIdx.x < i) Sm.s[threadIdx.x] = sums[threadIdx.x];
+        for (int j = 0; j < i; ++j) ss += sums[j] * sums[j];
     }
     if (threadIdx.x == 0) {
         Sm.rnorm = sqrt(rr);
@@ -407,13 +437,15 @@ template <int KB>
 __global__ __launch_bounds__(TPB) void k_restart(DavArgs w, int i, int kmin) {
     __shared__ double lds[4 * (KB + 1)];
     __shared__ double Ys[KB * KB];
+    __shared__ double scratch[TPB];
+    __shared__ double sums[KB + 1];
     const int c = blockIdx.x;
     const int member = w.chunk_member[c];
     const DavState &S = w.st[member];
     if (!w.active[member]) return;
-    for (int e = threadIdx.x; e < i * kmin; e += TPB) {
-        int r = e / kmin, q = e % kmin;
-        Ys[r * KB + q] = S.Y[r * KM + q];
+    for (int e = threadIdx.x; e < KB * KB; e += TPB) {
+        int r = e / KB, q = e % KB;
+        Ys[r * KB + q] = (r < i && q < kmin) ? S.Y[r * KM + q] : 0.0;
     }
     __syncthreads();
     const int64_t n = w.n;
@@ -424,18 +456,22 @@ __global__ __launch_bounds__(TPB) void k_restart(DavArgs w, int i, int kmin) {
         double v[KB], wv[KB];
 #pragma unroll
         for (int j = 0; j < KB; ++j) {
-            v[j] = (j < i) ? w.V[(int64_t)j * n + e] : 0.0;
-            wv[j] = (j < i) ? w.W[(int64_t)j * n + e] : 0.0;
+            v[j] = w.V[(int64_t)min(j, i - 1) * n + e];
+            wv[j] = w.W[(int64_t)min(j, i - 1) * n + e];
+        }
+#pragma unroll
+        for (int j = 0; j < KB; ++j) {
+            v[j] = (j < i) ? v[j] : 0.0;
+            wv[j] = (j < i) ? wv[j] : 0.0;
         }
         const double t = w.T[e];
         for (int q = 0; q < kmin; ++q) {
             double a = 0.0, b = 0.0;
 #pragma unroll
-            for (int j = 0; j < KB; ++j)
-                if (j < i) {
-                    a += v[j] * Ys[j * KB + q];
-                    b += wv[j] * Ys[j * KB + q];
-                }
+            for (int j = 0; j < KB; ++j) {
+                a += v[j] * Ys[j * KB + q];
+                b += wv[j] * Ys[j * KB + q];
+            }
             w.V[(int64_t)q * n + e] = a;
             w.W[(int64_t)q * n + e] = b;
             acc[q] += a * t;
@@ -448,13 +484,11 @@ __global__ __launch_bounds__(TPB) void k_restart(DavArgs w, int i, int kmin) {
     const int c0 = w.member_chunk[member], c1 = w.member_chunk[member + 1];
     if (!last_block_of_member(w.counter, member, c1 - c0)) return;
     DavState &Sm = w.st[member];
-    const double tt = member_sum(w.part, c0, c1, KB, lds);
+    member_sums(w.part, c0, c1, KB + 1, scratch, sums);
+    const double tt = sums[KB];
     double ss = 0.0;
-    for (int j = 0; j < kmin; ++j) {
-        double sj = member_sum(w.part, c0, c1, j, lds);
-        if (threadIdx.x == 0) Sm.s[j] = sj;
-        ss += sj * sj;
-    }
+    if ((int)threadIdx.x < kmin) Sm.s[threadIdx.x] = sums[threadIdx.x];
+    for (int j = 0; j < kmin; ++j) ss += sums[j] * sums[j];
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int r = 0; r < kmin; ++r)
@@ -472,6 +506,8 @@ __global__ __launch_bounds__(TPB) void k_restart(DavArgs w, int i, int kmin) {
 template <int KB>
 __global__ __launch_bounds__(TPB) void k_orth(DavArgs w, int i) {
     __shared__ double lds[4 * (KB + 1)];
+    __shared__ double scratch[TPB];
+    __shared__ double sums[KB + 1];
     const int c = blockIdx.x;
     const int member = w.chunk_member[c];
     const DavState &S = w.st[member];
@@ -487,14 +523,15 @@ __global__ __launch_bounds__(TPB) void k_orth(DavArgs w, int i) {
         double v[KB];
         double t = w.T[e];
 #pragma unroll
+        for (int j = 0; j < KB; ++j) v[j] = w.V[(int64_t)min(j, i - 1) * n + e];
+#pragma unroll
         for (int j = 0; j < KB; ++j) {
-            v[j] = (j < i) ? w.V[(int64_t)j * n + e] : 0.0;
+            v[j] = (j < i) ? v[j] : 0.0;
             t -= v[j] * s[j];
         }
         w.T[e] = t;
 #pragma unroll
-        for (int j = 0; j < KB; ++j)
-            if (j < i) acc[j] += v[j] * t;
+        for (int j = 0; j < KB; ++j) acc[j] += v[j] * t;
         acc[KB] += t * t;
     }
     block_reduce<KB + 1>(acc, KB + 1, lds);
@@ -503,13 +540,11 @@ __global__ __launch_bounds__(TPB) void k_orth(DavArgs w, int i) {
     const int c0 = w.member_chunk[member], c1 = w.member_chunk[member + 1];
     if (!last_block_of_member(w.counter, member, c1 - c0)) return;
     DavState &Sm = w.st[member];
-    const double tt = member_sum(w.part, c0, c1, KB, lds);
+    member_sums(w.part, c0, c1, KB + 1, scratch, sums);
+    const double tt = sums[KB];
     double ss = 0.0;
-    for (int j = 0; j < i; ++j) {
-        double sj = member_sum(w.part, c0, c1, j, lds);
-        if (threadIdx.x == 0) Sm.s2[j] = Sm.dgks ? sj : 0.0;
-        ss += sj * sj;
-    }
+    if ((int)threadIdx.x < i) Sm.s2[threadIdx.x] = Sm.dgks ? sums[threadIdx.x] : 0.0;
+    for (int j = 0; j < i; ++j) ss += sums[j] * sums[j];
     if (threadIdx.x == 0) {
         double nn = Sm.dgks ? (tt - ss) : tt;
         double nrm = sqrt(fmax(nn, 0.0));
@@ -539,9 +574,11 @@ __global__ __launch_bounds__(TPB) void k_append(DavArgs w, int i) {
     for (int64_t e = w.chunk_begin[c] + threadIdx.x; e < w.chunk_begin[c + 1]; e += TPB) {
         double t = w.T[e];
         if (dg) {
+            double v[KB];
 #pragma unroll
-            for (int j = 0; j < KB; ++j)
-                if (j < i) t -= w.V[(int64_t)j * n + e] * s2[j];
+            for (int j = 0; j < KB; ++j) v[j] = w.V[(int64_t)min(j, i - 1) * n + e];
+#pragma unroll
+            for (int j = 0; j < KB; ++j) t -= v[j] * s2[j];
         }
         w.V[(int64_t)i * n + e] = t * sc;
     }
@@ -561,10 +598,12 @@ __global__ __launch_bounds__(TPB) void k_finalize(DavArgs w, double *__restrict_
     for (int j = 0; j < KB; ++j) y[j] = (j < nv) ? S.Y[j * KM] : 0.0;
     const int64_t n = w.n;
     for (int64_t e = w.chunk_begin[c] + threadIdx.x; e < w.chunk_begin[c + 1]; e += TPB) {
+        double v[KB];
+#pragma unroll
+        for (int j = 0; j < KB; ++j) v[j] = w.V[(int64_t)min(j, nv - 1) * n + e];
         double x = 0.0;
 #pragma unroll
-        for (int j = 0; j < KB; ++j)
-            if (j < nv) x += w.V[(int64_t)j * n + e] * y[j];
+        for (int j = 0; j < KB; ++j) x += v[j] * y[j];
         psi[e] = x;
     }
 }
@@ -592,11 +631,15 @@ __global__ void k_set_state(DavArgs w, double tol, double floor_, int max_iter) 
 
 // ------------------------------------------------------------------ host driver
 
+// Register bucket for kernels that keep one row of V (and W) per thread: the
+// smallest of 8 / 16 / 32 / 48 columns that holds the current subspace.
 template <class K>
-static void set_kb(int kmax, K &&f) {
-    if (kmax <= 16)
+static void set_kb(int ncols, K &&f) {
+    if (ncols <= 8)
+        f(std::integral_constant<int, 8>{});
+    else if (ncols <= 16)
         f(std::integral_constant<int, 16>{});
-    else if (kmax <= 32)
+    else if (ncols <= 32)
         f(std::integral_constant<int, 32>{});
     else
         f(std::integral_constant<int, KM>{});
@@ -617,7 +660,7 @@ static dmrg_status work_alloc(dmrg_plan *plan, int kmax, int kmin, hipStream_t s
     std::vector<int32_t> cm;
     std::vector<int64_t> cb;
     std::vector<int32_t> mc(1, 0);
-    const int64_t CH = 1024;
+    const int64_t CH = TPB;  // one element per thread: many blocks, every column load in flight
     for (int p = 0; p < plan->nprob; ++p) {
         int64_t b = plan->member_off[p], e = plan->member_off[p + 1];
         if (e == b) {  // empty member: one empty chunk keeps the bookkeeping uniform
@@ -642,6 +685,7 @@ static dmrg_status work_alloc(dmrg_plan *plan, int kmax, int kmin, hipStream_t s
     DMRG_TRY(alloc((void **)&A.W, (kmax + 1) * n * 8));
     DMRG_TRY(alloc((void **)&A.T, n * 8));
     DMRG_TRY(alloc((void **)&A.D, n * 8));
+    DMRG_TRY(alloc((void **)&A.dfold, n * 8));
     DMRG_TRY(alloc((void **)&A.coef, std::max(plan->nterm_total, 1) * 8));
     DMRG_TRY(alloc((void **)&A.part, (size_t)A.nchunk * (KM + 2) * 8));
     DMRG_TRY(alloc((void **)&A.chunk_member, cm.size() * 4));
@@ -680,26 +724,27 @@ static dmrg_status enqueue_iters(dmrg_plan *plan, int slot, int i, int count, in
     const dim3 grid(A.nchunk), block(TPB);
     for (int it = 0; it < count; ++it) {
         const bool restart = (i == kmax);
-        set_kb(kmax, [&](auto kb) {
+        set_kb(i, [&](auto kb) {
             constexpr int KB = decltype(kb)::value;
             hipLaunchKernelGGL(k_rayleigh<KB>, grid, block, sizeof(JacobiLds), s, A, i);
             hipLaunchKernelGGL(k_ritz<KB>, grid, block, 0, s, A, i, restart ? 1 : 0);
         });
         int ie = i;
         if (restart) {
-            set_kb(kmax, [&](auto kb) {
+            set_kb(i, [&](auto kb) {
                 constexpr int KB = decltype(kb)::value;
                 hipLaunchKernelGGL(k_restart<KB>, grid, block, 0, s, A, i, kmin);
             });
             ie = kmin;
         }
-        set_kb(kmax, [&](auto kb) {
+        set_kb(ie, [&](auto kb) {
             constexpr int KB = decltype(kb)::value;
             hipLaunchKernelGGL(k_orth<KB>, grid, block, 0, s, A, ie);
             hipLaunchKernelGGL(k_append<KB>, grid, block, 0, s, A, ie);
         });
         DMRG_HIP(hipGetLastError());
-        DMRG_TRY(launch_project(plan, slot, A.coef, A.V + (int64_t)ie * A.n, A.W + (int64_t)ie * A.n, s, A.active));
+        DMRG_TRY(launch_project(plan, slot, A.coef, A.V + (int64_t)ie * A.n, A.W + (int64_t)ie * A.n, s, A.active,
+                                A.dfold));
         i = ie + 1;
     }
     *i_next = i;
@@ -715,7 +760,8 @@ static dmrg_status run_phase(dmrg_plan *plan, int slot, const double *psi_in, do
     hipLaunchKernelGGL(k_init_norm, grid, block, 0, s, psi_in, A);
     hipLaunchKernelGGL(k_init_vec, grid, block, 0, s, psi_in, A);
     DMRG_HIP(hipGetLastError());
-    DMRG_TRY(launch_project(plan, slot, A.coef, A.V, A.W, s, A.active));
+    DMRG_TRY(launch_diag_fold(plan, slot, A.coef, A.dfold, s));  // coefficients are fixed for the phase
+    DMRG_TRY(launch_project(plan, slot, A.coef, A.V, A.W, s, A.active, A.dfold));
     int i = 1;
     int done = 0;
     while (done < max_iter) {
@@ -869,7 +915,7 @@ dmrg_status dmrg_davidson(dmrg_plan *plan, const double *coef, const dmrg_davids
         tl = std::max(tl, o.tol);
         DMRG_TRY(run_phase(plan, 1, psi, tl, o.precond_floor, o.max_iter, o.use_graph != 0, o.graph_chunk, s,
                            &done));
-        set_kb(kmax, [&](auto kb) {
+        set_kb(kmax, [&](auto kb) {  // nvec <= kmax
             constexpr int KB = decltype(kb)::value;
             hipLaunchKernelGGL(k_finalize<KB>, dim3(A.nchunk), dim3(TPB), 0, s, A, psi);
         });
@@ -885,7 +931,7 @@ dmrg_status dmrg_davidson(dmrg_plan *plan, const double *coef, const dmrg_davids
     if (!two_phase || o.refine) {
         DMRG_TRY(run_phase(plan, 0, psi, o.tol, o.precond_floor, o.max_iter, o.use_graph != 0, o.graph_chunk, s,
                            &done));
-        set_kb(kmax, [&](auto kb) {
+        set_kb(kmax, [&](auto kb) {  // nvec <= kmax
             constexpr int KB = decltype(kb)::value;
             hipLaunchKernelGGL(k_finalize<KB>, dim3(A.nchunk), dim3(TPB), 0, s, A, psi);
         });

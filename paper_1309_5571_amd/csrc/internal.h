@@ -163,8 +163,12 @@ dmrg_status plan_free(dmrg_plan *plan);
 int tile_for(int64_t rows, int64_t cols);
 // project.hip
 // mask: optional device [nprob]; tasks of members with mask[m] == 0 are skipped
+// dfold: optional device [n]; the diagonal terms folded by launch_diag_fold for
+// the same coefficients (replaces the per-term diagonal epilogue)
 dmrg_status launch_project(dmrg_plan *plan, int slot, const double *coef, const double *in,
-                           double *out, hipStream_t s, const int32_t *mask = nullptr);
+                           double *out, hipStream_t s, const int32_t *mask = nullptr,
+                           const double *dfold = nullptr);
+dmrg_status launch_diag_fold(dmrg_plan *plan, int slot, const double *coef, double *out, hipStream_t s);
 dmrg_status launch_adjoint(dmrg_plan *plan, const double *coef, const double *in, double *out,
                            hipStream_t s);
 dmrg_status launch_gcoef(dmrg_plan *plan, const double *psi, const double *gbar, double *gcoef,

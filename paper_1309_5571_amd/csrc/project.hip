@@ -21,6 +21,7 @@
 // Precisions: F64 uses v_mfma_f64_16x16x4; F32 uses v_mfma_f32_16x16x4 with
 // FP32 accumulation inside a segment; BF16 uses v_mfma_f32_16x16x32_bf16.
 // Across segments, and in the diagonal epilogue, sums are FP64.
+#include <algorithm>
 #include <cstdio>
 
 #include "internal.h"
@@ -159,13 +160,19 @@ __device__ __forceinline__ void load_q(typename Tr<PREC>::val_t (&v)[Tr<PREC>::K
     }
 }
 
-// One segment: acc[sr][sc] = op(P)[tile rows, :] op(Q)[:, tile cols]
+constexpr int PW = 4;            // wavefronts per workgroup
+constexpr int KC = 32;           // contraction length of one work item
+constexpr int TASK_GRID_MAX = 4096;  // persistent grid cap (blocks loop over tasks)
+
+// One work item: acc[sr][sc] += op(P)[tile rows, k0:k0+KC] op(Q)[k0:k0+KC, tile cols].
+// All operand loads of the item are issued before its MFMAs.
 template <int PREC, bool PIN, bool PT, bool QIN, bool QT>
-__device__ __forceinline__ void seg_gemm(typename Tr<PREC>::acc_t (&acc)[2][2], const Seg &s, const Task &tk,
-                                         const double *__restrict__ in, const void *__restrict__ tmp, int nsr,
-                                         int nsc) {
+__device__ __forceinline__ void item_gemm(typename Tr<PREC>::acc_t (&acc)[2][2], const Seg &s, const Task &tk,
+                                          const double *__restrict__ in, const void *__restrict__ tmp, int nsr,
+                                          int nsc, int k0) {
     typedef Tr<PREC> T;
-    constexpr int KB = 4 * T::KPL;
+    constexpr int KB = 4 * T::KPL;  // k per MFMA block
+    constexpr int NKB = KC / KB;    // blocks per item
     const int lane = threadIdx.x & 63;
     const int r16 = lane & 15, g = lane >> 4;
     int prow[2], qcol[2];
@@ -182,45 +189,57 @@ __device__ __forceinline__ void seg_gemm(typename Tr<PREC>::acc_t (&acc)[2][2], 
         if (PIN && s.pscale && pok[t]) ps[t] = ((const double *)(uintptr_t)s.pscale)[prow[t]];
         if (QIN && s.qscale && qok[t]) qs[t] = ((const double *)(uintptr_t)s.qscale)[qcol[t]];
     }
-    for (int kb = 0; kb < s.K; kb += KB) {
-        typename T::val_t pv[2][T::KPL], qv[2][T::KPL];
-        const int k0 = kb + T::KPL * g;
+    typename T::val_t pv[2][NKB][T::KPL], qv[2][NKB][T::KPL];
+#pragma unroll
+    for (int b = 0; b < NKB; ++b) {
+        const int kk = k0 + b * KB + T::KPL * g;
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
-            if (t < nsr) load_p<PREC, PIN, PT>(pv[t], s, in, tmp, prow[t], pok[t], k0, s.K, ps[t]);
-            if (t < nsc) load_q<PREC, QIN, QT>(qv[t], s, in, tmp, qcol[t], qok[t], k0, s.K, qs[t]);
+            if (t < nsr) load_p<PREC, PIN, PT>(pv[t][b], s, in, tmp, prow[t], pok[t], kk, s.K, ps[t]);
+            if (t < nsc) load_q<PREC, QIN, QT>(qv[t][b], s, in, tmp, qcol[t], qok[t], kk, s.K, qs[t]);
         }
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int b = 0; b < 2; ++b)
-                if (a < nsr && b < nsc) T::mma(acc[a][b], pv[a], qv[b]);
     }
+#pragma unroll
+    for (int b = 0; b < NKB; ++b)
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+            for (int y = 0; y < 2; ++y)
+                if (x < nsr && y < nsc) T::mma(acc[x][y], pv[x][b], qv[y][b]);
 }
 
+// All work items [first, nit) step PW of one segment, for one operand layout.
+template <int PREC, bool PIN, bool PT, bool QIN, bool QT>
+__device__ __forceinline__ void seg_items(typename Tr<PREC>::acc_t (&acc)[2][2], const Seg &s, const Task &tk,
+                                       const double *__restrict__ in, const void *__restrict__ tmp, int nsr, int nsc,
+                                       int first, int nit) {
+    for (int it = first; it < nit; it += PW) item_gemm<PREC, PIN, PT, QIN, QT>(acc, s, tk, in, tmp, nsr, nsc, it * KC);
+}
+
+// One switch per segment on the operand layout (the task lists use 7 of the 16).
 template <int PREC>
 __device__ __forceinline__ void seg_dispatch(typename Tr<PREC>::acc_t (&acc)[2][2], const Seg &s, const Task &tk,
                                              const double *__restrict__ in, const void *__restrict__ tmp, int nsr,
-                                             int nsc) {
+                                             int nsc, int first, int nit) {
     const bool pin = s.pkind == OPD_IN, qin = s.qkind == OPD_IN;
     const int code = (pin ? 8 : 0) | (s.ptrans ? 4 : 0) | (qin ? 2 : 0) | (s.qtrans ? 1 : 0);
     switch (code) {
-        case 0: seg_gemm<PREC, false, false, false, false>(acc, s, tk, in, tmp, nsr, nsc); break;
-        case 1: seg_gemm<PREC, false, false, false, true>(acc, s, tk, in, tmp, nsr, nsc); break;
-        case 2: seg_gemm<PREC, false, false, true, false>(acc, s, tk, in, tmp, nsr, nsc); break;
-        case 3: seg_gemm<PREC, false, false, true, true>(acc, s, tk, in, tmp, nsr, nsc); break;
-        case 4: seg_gemm<PREC, false, true, false, false>(acc, s, tk, in, tmp, nsr, nsc); break;
-        case 5: seg_gemm<PREC, false, true, false, true>(acc, s, tk, in, tmp, nsr, nsc); break;
-        case 6: seg_gemm<PREC, false, true, true, false>(acc, s, tk, in, tmp, nsr, nsc); break;
-        case 7: seg_gemm<PREC, false, true, true, true>(acc, s, tk, in, tmp, nsr, nsc); break;
-        case 8: seg_gemm<PREC, true, false, false, false>(acc, s, tk, in, tmp, nsr, nsc); break;
-        case 9: seg_gemm<PREC, true, false, false, true>(acc, s, tk, in, tmp, nsr, nsc); break;
-        case 10: seg_gemm<PREC, true, false, true, false>(acc, s, tk, in, tmp, nsr, nsc); break;
-        case 11: seg_gemm<PREC, true, false, true, true>(acc, s, tk, in, tmp, nsr, nsc); break;
-        case 12: seg_gemm<PREC, true, true, false, false>(acc, s, tk, in, tmp, nsr, nsc); break;
-        case 13: seg_gemm<PREC, true, true, false, true>(acc, s, tk, in, tmp, nsr, nsc); break;
-        case 14: seg_gemm<PREC, true, true, true, false>(acc, s, tk, in, tmp, nsr, nsc); break;
-        default: seg_gemm<PREC, true, true, true, true>(acc, s, tk, in, tmp, nsr, nsc); break;
+        case 0: seg_items<PREC, false, false, false, false>(acc, s, tk, in, tmp, nsr, nsc, first, nit); break;
+        case 1: seg_items<PREC, false, false, false, true>(acc, s, tk, in, tmp, nsr, nsc, first, nit); break;
+        case 2: seg_items<PREC, false, false, true, false>(acc, s, tk, in, tmp, nsr, nsc, first, nit); break;
+        case 3: seg_items<PREC, false, false, true, true>(acc, s, tk, in, tmp, nsr, nsc, first, nit); break;
+        case 4: seg_items<PREC, false, true, false, false>(acc, s, tk, in, tmp, nsr, nsc, first, nit); break;
+        case 5: seg_items<PREC, false, true, false, true>(acc, s, tk, in, tmp, nsr, nsc, first, nit); break;
+        case 6: seg_items<PREC, false, true, true, false>(acc, s, tk, in, tmp, nsr, nsc, first, nit); break;
+        case 7: seg_items<PREC, false, true, true, true>(acc, s, tk, in, tmp, nsr, nsc, first, nit); break;
+        case 8: seg_items<PREC, true, false, false, false>(acc, s, tk, in, tmp, nsr, nsc, first, nit); break;
+        case 9: seg_items<PREC, true, false, false, true>(acc, s, tk, in, tmp, nsr, nsc, first, nit); break;
+        case 10: seg_items<PREC, true, false, true, false>(acc, s, tk, in, tmp, nsr, nsc, first, nit); break;
+        case 11: seg_items<PREC, true, false, true, true>(acc, s, tk, in, tmp, nsr, nsc, first, nit); break;
+        case 12: seg_items<PREC, true, true, false, false>(acc, s, tk, in, tmp, nsr, nsc, first, nit); break;
+        case 13: seg_items<PREC, true, true, false, true>(acc, s, tk, in, tmp, nsr, nsc, first, nit); break;
+        case 14: seg_items<PREC, true, true, true, false>(acc, s, tk, in, tmp, nsr, nsc, first, nit); break;
+        default: seg_items<PREC, true, true, true, true>(acc, s, tk, in, tmp, nsr, nsc, first, nit); break;
     }
 }
 
@@ -230,120 +249,144 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+template <int PREC>
+__device__ __forceinline__ void zero_acc(typename Tr<PREC>::acc_t (&acc)[2][2]) {
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = typename Tr<PREC>::acc_t{0, 0, 0, 0};
+}
+
+// diagonal-term contribution at output element (rr, cc) of a task's pair
+__device__ __forceinline__ double diag_sum(const DiagTerm *__restrict__ diags, int d0, int d1,
+                                           const double *__restrict__ coef, double x, int64_t rr, int64_t cc) {
+    double val = 0.0;
+    for (int d = d0; d < d1; ++d) {
+        const DiagTerm dt = diags[d];
+        double w = (coef ? coef[dt.coef] : 1.0) * x;
+        if (dt.vl) w *= ((const double *)(uintptr_t)dt.vl)[rr * dt.sl];
+        if (dt.vr) w *= ((const double *)(uintptr_t)dt.vr)[cc * dt.sr];
+        val += w;
+    }
+    return val;
+}
+
 // MODE 0: write the intermediate (store_t) of stage A.
 // MODE 1: write FP64 output tiles with the diagonal epilogue (stage B).
 // MODE 2: coefficient-gradient partials <gbar, segment product> per segment
 //         and per diagonal term (stage B task list of the FP64 pass).
+// A workgroup of PW wavefronts owns one output tile at a time (a persistent
+// grid walks the cost-sorted task list).  In modes 0/1 the work items of a
+// tile -- (segment, KC-long slice of its contraction) in list order -- are
+// dealt round-robin to the wavefronts; the PW partial tiles are summed in a
+// fixed order through LDS, so results do not depend on scheduling.
 template <int PREC, int MODE>
-__global__ __launch_bounds__(64) void k_tasks(const Task *__restrict__ tasks, int ntask,
-                                             const Seg *__restrict__ segs, const DiagTerm *__restrict__ diags,
-                                             const double *__restrict__ in, const void *__restrict__ tmp,
-                                             void *__restrict__ out, const double *__restrict__ coef,
-                                             const double *__restrict__ gbar, double *__restrict__ partials,
-                                             const int32_t *__restrict__ mask) {
+__global__ __launch_bounds__(64 * PW) void k_tasks(const Task *__restrict__ tasks, int ntask,
+                                                  const Seg *__restrict__ segs, const DiagTerm *__restrict__ diags,
+                                                  const double *__restrict__ in, const void *__restrict__ tmp,
+                                                  void *__restrict__ out, const double *__restrict__ coef,
+                                                  const double *__restrict__ gbar, double *__restrict__ partials,
+                                                  const int32_t *__restrict__ mask,
+                                                  const double *__restrict__ dfold) {
     typedef Tr<PREC> T;
-    const int t = blockIdx.x;
-    if (t >= ntask) return;
-    const Task tk = tasks[t];
-    if (mask && !mask[tk.member]) return;
+    __shared__ double red[PW][32][33];
+    const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const int r16 = lane & 15, g = lane >> 4;
-    const int nsr = (tk.m + 15) >> 4, nsc = (tk.n + 15) >> 4;
-    double tot[2][2][4];
+    for (int t = blockIdx.x; t < ntask; t += gridDim.x) {
+        const Task tk = tasks[t];
+        if (mask && !mask[tk.member]) continue;
+        const int nsr = (tk.m + 15) >> 4, nsc = (tk.n + 15) >> 4;
+        if (MODE == 2) {
+            // one wavefront per segment: each partial slot has exactly one writer
+            for (int si = tk.seg_begin + wave; si < tk.seg_end; si += PW) {
+                const Seg s = segs[si];
+                typename T::acc_t acc[2][2];
+                zero_acc<PREC>(acc);
+                // one wavefront runs every work item of the segment (PW-strided item loop, 4 passes)
+                for (int f = 0; f < PW; ++f) seg_dispatch<PREC>(acc, s, tk, in, tmp, nsr, nsc, f, (s.K + KC - 1) / KC);
+                double part = 0.0;
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+                for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+                    for (int b = 0; b < 2; ++b)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) tot[a][b][v] = 0.0;
-
-    for (int si = tk.seg_begin; si < tk.seg_end; ++si) {
-        const Seg s = segs[si];
-        typename T::acc_t acc[2][2];
+                        for (int v = 0; v < 4; ++v) {
+                            const int r = a * 16 + T::row(g, v), c = b * 16 + r16;
+                            if (a < nsr && b < nsc && r < tk.m && c < tk.n)
+                                part += (double)acc[a][b][v] *
+                                        gbar[tk.c_off + (int64_t)(tk.row0 + r) * tk.ldc + tk.col0 + c];
+                        }
+                part = wave_sum(part);
+                if (lane == 0) partials[tk.part0 + (si - tk.seg_begin)] = part;
+            }
+            const int nseg = tk.seg_end - tk.seg_begin;
+            for (int d = tk.diag_begin + wave; d < tk.diag_end; d += PW) {
+                double part = 0.0;
+                for (int e = lane; e < tk.m * tk.n; e += 64) {
+                    const int64_t rr = tk.row0 + e / tk.n, cc = tk.col0 + e % tk.n;
+                    const int64_t o = tk.c_off + rr * tk.ldc + cc;
+                    part += diag_sum(diags, d, d + 1, nullptr, in[tk.x_off + rr * tk.ldc + cc], rr, cc) * gbar[o];
+                }
+                part = wave_sum(part);
+                if (lane == 0) partials[tk.part0 + nseg + (d - tk.diag_begin)] = part;
+            }
+            continue;
+        }
+        double tot[2][2][4];
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
-            for (int b = 0; b < 2; ++b) acc[a][b] = typename T::acc_t{0, 0, 0, 0};
-        seg_dispatch<PREC>(acc, s, tk, in, tmp, nsr, nsc);
-        if (MODE == 2) {
-            double part = 0.0;
+            for (int b = 0; b < 2; ++b)
 #pragma unroll
-            for (int a = 0; a < 2; ++a)
+                for (int v = 0; v < 4; ++v) tot[a][b][v] = 0.0;
+        int q = 0;  // work-item counter, identical in every wavefront
+        for (int si = tk.seg_begin; si < tk.seg_end; ++si) {
+            const int K = segs[si].K;
+            const int nit = (K + KC - 1) / KC;
+            const int first = (wave - q % PW + PW) % PW;  // first item of this segment owned by this wave
+            if (first < nit) {
+                const Seg s = segs[si];
+                typename T::acc_t acc[2][2];
+                zero_acc<PREC>(acc);
+                seg_dispatch<PREC>(acc, s, tk, in, tmp, nsr, nsc, first, nit);
+                const double c = s.coef >= 0 ? coef[s.coef] : 1.0;
 #pragma unroll
-                for (int b = 0; b < 2; ++b)
+                for (int a = 0; a < 2; ++a)
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        int r = a * 16 + T::row(g, v), c = b * 16 + r16;
-                        if (a < nsr && b < nsc && r < tk.m && c < tk.n)
-                            part += (double)acc[a][b][v] *
-                                    gbar[tk.c_off + (int64_t)(tk.row0 + r) * tk.ldc + tk.col0 + c];
-                    }
-            part = wave_sum(part);
-            if (lane == 0) partials[tk.part0 + (si - tk.seg_begin)] = part;
-        } else {
-            const double c = s.coef >= 0 ? coef[s.coef] : 1.0;
+                    for (int b = 0; b < 2; ++b)
 #pragma unroll
-            for (int a = 0; a < 2; ++a)
-#pragma unroll
-                for (int b = 0; b < 2; ++b)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) tot[a][b][v] += c * (double)acc[a][b][v];
+                        for (int v = 0; v < 4; ++v) tot[a][b][v] += c * (double)acc[a][b][v];
+            }
+            q += nit;
         }
-    }
-
 #pragma unroll
-    for (int a = 0; a < 2; ++a) {
+        for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
-            if (a >= nsr || b >= nsc) continue;
+            for (int b = 0; b < 2; ++b)
+                if (a < nsr && b < nsc) {
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int r = a * 16 + T::row(g, v), c = b * 16 + r16;
-                const bool ok = r < tk.m && c < tk.n;
-                const int64_t rr = tk.row0 + r, cc = tk.col0 + c;
-                const int64_t o = tk.c_off + rr * tk.ldc + cc;
-                if (MODE == 0) {
-                    if (ok) ((typename T::store_t *)out)[o] = T::to_store(tot[a][b][v]);
-                } else if (MODE == 1) {
-                    double val = tot[a][b][v];
-                    if (ok) {
-                        const double x = in[tk.x_off + rr * tk.ldc + cc];
-                        for (int d = tk.diag_begin; d < tk.diag_end; ++d) {
-                            const DiagTerm dt = diags[d];
-                            double w = coef[dt.coef] * x;
-                            if (dt.vl) w *= ((const double *)(uintptr_t)dt.vl)[rr * dt.sl];
-                            if (dt.vr) w *= ((const double *)(uintptr_t)dt.vr)[cc * dt.sr];
-                            val += w;
-                        }
-                        ((double *)out)[o] = val;
-                    }
+                    for (int v = 0; v < 4; ++v) red[wave][a * 16 + T::row(g, v)][b * 16 + r16] = tot[a][b][v];
                 }
+        __syncthreads();
+        for (int e = threadIdx.x; e < tk.m * tk.n; e += 64 * PW) {
+            const int r = e / tk.n, c = e % tk.n;
+            double val = 0.0;
+#pragma unroll
+            for (int w = 0; w < PW; ++w) val += red[w][r][c];
+            const int64_t rr = tk.row0 + r, cc = tk.col0 + c;
+            const int64_t o = tk.c_off + rr * tk.ldc + cc;
+            if (MODE == 0) {
+                ((typename T::store_t *)out)[o] = T::to_store(val);
+            } else {
+                if (dfold)  // sum_d c_d vl vr, folded once for fixed coefficients
+                    val += dfold[o] * in[tk.x_off + rr * tk.ldc + cc];
+                else if (tk.diag_end > tk.diag_begin)
+                    val += diag_sum(diags, tk.diag_begin, tk.diag_end, coef, in[tk.x_off + rr * tk.ldc + cc], rr, cc);
+                ((double *)out)[o] = val;
             }
         }
-    }
-    if (MODE == 2) {
-        const int nseg = tk.seg_end - tk.seg_begin;
-        for (int d = tk.diag_begin; d < tk.diag_end; ++d) {
-            const DiagTerm dt = diags[d];
-            double part = 0.0;
-#pragma unroll
-            for (int a = 0; a < 2; ++a)
-#pragma unroll
-                for (int b = 0; b < 2; ++b)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int r = a * 16 + T::row(g, v), c = b * 16 + r16;
-                        if (a < nsr && b < nsc && r < tk.m && c < tk.n) {
-                            const int64_t rr = tk.row0 + r, cc = tk.col0 + c;
-                            double w = in[tk.x_off + rr * tk.ldc + cc] * gbar[tk.c_off + rr * tk.ldc + cc];
-                            if (dt.vl) w *= ((const double *)(uintptr_t)dt.vl)[rr * dt.sl];
-                            if (dt.vr) w *= ((const double *)(uintptr_t)dt.vr)[cc * dt.sr];
-                            part += w;
-                        }
-                    }
-            part = wave_sum(part);
-            if (lane == 0) partials[tk.part0 + nseg + (d - tk.diag_begin)] = part;
-        }
+        __syncthreads();  // red is reused by the next task
     }
 }
 
@@ -381,6 +424,20 @@ __global__ __launch_bounds__(256) void k_hdiag(const Task *__restrict__ tasks, i
     }
 }
 
+// Folded diagonal terms of a pass: out[o] = sum_d c_d vl[r] vr[c] over each
+// stage-B tile's diagonal terms (tiles partition the output, one writer each).
+__global__ __launch_bounds__(256) void k_diag_fold(const Task *__restrict__ tasks, int ntask,
+                                                   const DiagTerm *__restrict__ diags,
+                                                   const double *__restrict__ coef, double *__restrict__ out) {
+    for (int t = blockIdx.x; t < ntask; t += gridDim.x) {
+        const Task tk = tasks[t];
+        for (int e = threadIdx.x; e < tk.m * tk.n; e += 256) {
+            const int64_t rr = tk.row0 + e / tk.n, cc = tk.col0 + e % tk.n;
+            out[tk.c_off + rr * tk.ldc + cc] = diag_sum(diags, tk.diag_begin, tk.diag_end, coef, 1.0, rr, cc);
+        }
+    }
+}
+
 // FP64 block -> FP32 / BF16 copy (round to nearest even), optionally with a zero diagonal.
 __global__ __launch_bounds__(256) void k_convert(const double *__restrict__ src, void *__restrict__ dst,
                                                  int64_t rows, int64_t cols, int prec, int offdiag) {
@@ -404,42 +461,53 @@ __global__ __launch_bounds__(256) void k_extract_diag(const double *__restrict__
 
 // ------------------------------------------------------------------ launchers
 
+static dim3 task_grid(int ntask) { return dim3(std::min(ntask, TASK_GRID_MAX)); }
+
 template <int PREC>
 static dmrg_status run_pass(const PassSet &ps, const double *coef, const double *in, void *tmp, double *out,
-                            hipStream_t s, const int32_t *mask) {
+                            hipStream_t s, const int32_t *mask, const double *dfold) {
     if (ps.stageA.ntask)
-        hipLaunchKernelGGL((k_tasks<PREC, 0>), dim3(ps.stageA.ntask), dim3(64), 0, s, ps.stageA.tasks,
+        hipLaunchKernelGGL((k_tasks<PREC, 0>), task_grid(ps.stageA.ntask), dim3(64 * PW), 0, s, ps.stageA.tasks,
                            ps.stageA.ntask, ps.segs, ps.diags, in, (const void *)tmp, tmp, coef, nullptr, nullptr,
-                           mask);
+                           mask, (const double *)nullptr);
     if (ps.stageB.ntask)
-        hipLaunchKernelGGL((k_tasks<PREC, 1>), dim3(ps.stageB.ntask), dim3(64), 0, s, ps.stageB.tasks,
+        hipLaunchKernelGGL((k_tasks<PREC, 1>), task_grid(ps.stageB.ntask), dim3(64 * PW), 0, s, ps.stageB.tasks,
                            ps.stageB.ntask, ps.segs, ps.diags, in, (const void *)tmp, (void *)out, coef, nullptr,
-                           nullptr, mask);
+                           nullptr, mask, dfold);
     DMRG_HIP(hipGetLastError());
     return DMRG_OK;
 }
 
 dmrg_status launch_project(dmrg_plan *plan, int slot, const double *coef, const double *in, double *out,
-                           hipStream_t s, const int32_t *mask) {
-    if (slot == 0) return run_pass<DMRG_F64>(plan->fwd[0], coef, in, plan->d_tmp, out, s, mask);
-    if (plan->prec == DMRG_F32) return run_pass<DMRG_F32>(plan->fwd[1], coef, in, plan->d_tmp, out, s, mask);
-    return run_pass<DMRG_BF16>(plan->fwd[1], coef, in, plan->d_tmp, out, s, mask);
+                           hipStream_t s, const int32_t *mask, const double *dfold) {
+    if (slot == 0) return run_pass<DMRG_F64>(plan->fwd[0], coef, in, plan->d_tmp, out, s, mask, dfold);
+    if (plan->prec == DMRG_F32) return run_pass<DMRG_F32>(plan->fwd[1], coef, in, plan->d_tmp, out, s, mask, dfold);
+    return run_pass<DMRG_BF16>(plan->fwd[1], coef, in, plan->d_tmp, out, s, mask, dfold);
 }
 
 dmrg_status launch_adjoint(dmrg_plan *plan, const double *coef, const double *in, double *out, hipStream_t s) {
-    return run_pass<DMRG_F64>(plan->adj[0], coef, in, plan->d_tmp, out, s, nullptr);
+    return run_pass<DMRG_F64>(plan->adj[0], coef, in, plan->d_tmp, out, s, nullptr, nullptr);
+}
+
+dmrg_status launch_diag_fold(dmrg_plan *plan, int slot, const double *coef, double *out, hipStream_t s) {
+    const PassSet &ps = plan->fwd[slot];
+    if (ps.stageB.ntask)
+        hipLaunchKernelGGL(k_diag_fold, task_grid(ps.stageB.ntask), dim3(256), 0, s, ps.stageB.tasks,
+                           ps.stageB.ntask, ps.diags, coef, out);
+    DMRG_HIP(hipGetLastError());
+    return DMRG_OK;
 }
 
 dmrg_status launch_gcoef(dmrg_plan *plan, const double *psi, const double *gbar, double *gcoef, hipStream_t s) {
     const PassSet &ps = plan->fwd[0];
     if (ps.stageA.ntask)
-        hipLaunchKernelGGL((k_tasks<DMRG_F64, 0>), dim3(ps.stageA.ntask), dim3(64), 0, s, ps.stageA.tasks,
+        hipLaunchKernelGGL((k_tasks<DMRG_F64, 0>), task_grid(ps.stageA.ntask), dim3(64 * PW), 0, s, ps.stageA.tasks,
                            ps.stageA.ntask, ps.segs, ps.diags, psi, (const void *)plan->d_tmp, plan->d_tmp,
-                           (const double *)nullptr, nullptr, nullptr, nullptr);
+                           (const double *)nullptr, nullptr, nullptr, nullptr, (const double *)nullptr);
     if (ps.stageB.ntask)
-        hipLaunchKernelGGL((k_tasks<DMRG_F64, 2>), dim3(ps.stageB.ntask), dim3(64), 0, s, ps.stageB.tasks,
+        hipLaunchKernelGGL((k_tasks<DMRG_F64, 2>), task_grid(ps.stageB.ntask), dim3(64 * PW), 0, s, ps.stageB.tasks,
                            ps.stageB.ntask, ps.segs, ps.diags, psi, (const void *)plan->d_tmp, nullptr,
-                           (const double *)nullptr, gbar, plan->d_partials, nullptr);
+                           (const double *)nullptr, gbar, plan->d_partials, nullptr, (const double *)nullptr);
     if (plan->nterm_total)
         hipLaunchKernelGGL(k_reduce_terms, dim3(plan->nterm_total), dim3(64), 0, s, plan->d_term_ptr,
                            plan->d_term_ent, (const double *)plan->d_partials, gcoef, plan->nterm_total);
