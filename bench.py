@@ -37,6 +37,10 @@ def parse():
     ap.add_argument("--proj-reps", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true", help="skip the projection and FP64 comparison timings")
+    ap.add_argument("--workload", default="hubbard_m2048",
+                    choices=["hubbard_m2048", "heisenberg_m1024", "j1j2_m1024", "batched_64", "gemv"],
+                    help="hubbard_m2048 is the headline line; the others time the projection and the "
+                         "mixed-precision solve of the other synthetic workloads")
     return ap.parse_args()
 
 
@@ -90,6 +94,40 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def gemv_sweep(reps=100):
+    """The tall-skinny products of the orthogonalization (dmrg_gemv_t / _n) at the
+    heights the paper sweeps (1e5, 5e5, 1e6) plus 4e6, widths 1..32, FP64.
+    GB/s counts the algorithmic bytes: V (k columns) + x + s for V^T x, V + y for V s."""
+    import torch
+
+    import paper_1309_5571_amd as dm
+
+    rows = []
+    s = torch.cuda.current_stream()
+    for n in (100_000, 500_000, 1_000_000, 4_000_000):
+        V = torch.randn(32, n, dtype=torch.float64, device="cuda")
+        x = torch.randn(n, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for k in (1, 2, 4, 8, 16, 20, 32):
+            sv = dm.gemv_t(V, x, k)
+            for name, fn, nbytes in (("gemv_t", lambda: dm.gemv_t(V, x, k), 8 * n * (k + 1)),
+                                     ("gemv_n", lambda: dm.gemv_n(V, sv, y, 0.0, k), 8 * n * (k + 1))):
+                for _ in range(5):
+                    fn()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(s)
+                for _ in range(reps):
+                    fn()
+                e1.record(s)
+                e1.synchronize()
+                t = e0.elapsed_time(e1) * 1e-3 / reps
+                rows.append({"op": name, "n": n, "k": k, "us": t * 1e6, "GBs": nbytes / t * 1e-9,
+                             "frac_hbm": nbytes / t * 1e-9 / PEAK["hbm_GBs"]})
+        log(f"gemv n={n} done")
+        del V, x, y
+    return rows
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -105,11 +143,16 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    p = gen.config(3)
+    if args.workload == "gemv":
+        print(json.dumps({"workload": "gemv_sweep", "unit": "GB/s", "rows": gemv_sweep()}))
+        return
+    cfg = {"hubbard_m2048": 3, "heisenberg_m1024": 2, "j1j2_m1024": 5, "batched_64": 4}[args.workload]
+    p = gen.config(cfg)
     plan = dm.Plan(p, prec=args.prec)
     x0_np = gen.start_vector(plan.n, 7)
     x0 = torch.from_numpy(x0_np).to(dev)
     coef = plan.coef.clone()
+    nmem = len(plan.problems)
 
     def step(prec):
         psi, E, info, st = plan.davidson(x0, coef, tol=1e-10, prec=prec)
@@ -127,12 +170,11 @@ def main():
     t0 = time.perf_counter()
     for _ in range(args.steps):
         E, info, gcoef = step(args.prec)
-        iters += info[0]["iterations"]
+        iters += sum(i["iterations"] for i in info)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     log(f"timed {args.steps} steps: {dt / args.steps * 1e3:.3f} ms/step, {iters / dt:.1f} iter/s")
     E_mixed = float(E[0])
-    info_mixed = info[0]
 
     extra = {}
     if not args.quick:
@@ -145,11 +187,12 @@ def main():
         n64 = max(3, args.steps // 2)
         for _ in range(n64):
             E64, info64, _ = step("f64")
-            it64 += info64[0]["iterations"]
+            it64 += sum(i["iterations"] for i in info64)
         torch.cuda.synchronize()
         dt64 = time.perf_counter() - t1
         extra["fp64_solve"] = {"iters_per_s": it64 / dt64, "ms_per_solve": dt64 / n64 * 1e3,
-                               "iterations": info64[0]["iterations"], "energy": float(E64[0])}
+                               "iterations": sum(i["iterations"] for i in info64) / nmem,
+                               "energy": float(E64[0])}
         # projection alone, per precision (events on the launch stream)
         psi = torch.from_numpy(x0_np / np.linalg.norm(x0_np)).to(dev)
         y = torch.empty_like(psi)
@@ -174,12 +217,13 @@ def main():
 
     cpu = None
     E_ref = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and nmem == 1:
         log("cpu baseline (oracle)")
         cpu, E_ref = cpu_baseline(p, x0_np)
 
     out = {
-        "metric": "H·ψ projection TFLOP/s + Davidson iters/s at m=2048 Hubbard; mixed vs FP64 @1e-8 dE",
+        "metric": ("H·ψ projection TFLOP/s + Davidson iters/s at m=2048 Hubbard; mixed vs FP64 @1e-8 dE"
+                   if cfg == 3 else f"projection TFLOP/s + Davidson iters/s ({args.workload})"),
         "value": iters / dt,
         "unit": "iter/s",
         "n_gpus": 1,
@@ -191,11 +235,13 @@ def main():
         "vs_baseline": None,
         "dtype": f"{args.prec}+f64",
         "data": "synthetic",
-        "config": {"workload": "hubbard_m2048_two_site", "m": 2048, "n": plan.n, "sectors": int(p.left.nsec),
-                   "terms": int(len(p.coef)), "t": 1.0, "U": 4.0, "tol": 1e-10,
-                   "phase1": args.prec, "refine": "f64", "graph": True},
-        "iterations_per_step": info_mixed["iterations"],
-        "iterations_lowprec": info_mixed["iterations_low"],
+        "config": ({"workload": "hubbard_m2048_two_site", "m": 2048, "n": plan.n, "sectors": int(p.left.nsec),
+                    "terms": int(len(p.coef)), "t": 1.0, "U": 4.0, "tol": 1e-10,
+                    "phase1": args.prec, "refine": "f64", "graph": True} if cfg == 3 else
+                   {"workload": args.workload, "members": nmem, "n": plan.n, "tol": 1e-10,
+                    "phase1": args.prec, "refine": "f64", "graph": True}),
+        "iterations_per_step": sum(i["iterations"] for i in info) / nmem,
+        "iterations_lowprec": sum(i["iterations_low"] for i in info) / nmem,
         "energy": E_mixed,
         "dE_vs_fp64_oracle": (E_mixed - E_ref) if E_ref is not None else None,
         "roofline": roof,

@@ -119,6 +119,7 @@ def main():
     ap.add_argument("--prec", default="all", choices=["all", "f64", "f32", "bf16"])
     ap.add_argument("--reps", type=int, default=50)
     ap.add_argument("--save", action="store_true")
+    ap.add_argument("--table", default=TABLE_PATH, help="where --save writes the table")
     a = ap.parse_args()
     loads = {"heisenberg_m1024": lambda: [gen.config(2)], "hubbard_m2048": lambda: [gen.config(3)],
              "j1j2_m1024": lambda: [gen.config(5)], "batched_64": lambda: gen.config(4)}
@@ -130,7 +131,7 @@ def main():
             r = tune(probs, pr, reps=a.reps)
             print(json.dumps({"workload": nm, **r}), flush=True)
             if a.save:
-                save(r)
+                save(r, a.table)
 
 
 if __name__ == "__main__":

@@ -70,6 +70,26 @@ struct DavidsonWork {
 
 // ------------------------------------------------------------------ helpers
 
+// Element range and member of chunk c.  A single-member plan needs no lookup:
+// its chunks are the consecutive TPB-element ranges.
+struct Chunk {
+    int member;
+    int64_t e0, e1;
+};
+__device__ __forceinline__ Chunk chunk_of(const DavArgs &w, int c) {
+    Chunk k;
+    if (w.nprob == 1) {
+        k.member = 0;
+        k.e0 = (int64_t)c * TPB;
+        k.e1 = min(w.n, k.e0 + TPB);
+    } else {
+        k.member = w.chunk_member[c];
+        k.e0 = w.chunk_begin[c];
+        k.e1 = w.chunk_begin[c + 1];
+    }
+    return k;
+}
+
 __device__ __forceinline__ bool last_block_of_member(int32_t *counter, int member, int nch) {
     __shared__ int is_last;
     __syncthreads();
@@ -122,9 +142,10 @@ __device__ void member_sums(const double *__restrict__ part, int c0, int c1, int
 __global__ __launch_bounds__(TPB) void k_init_norm(const double *__restrict__ psi, DavArgs w) {
     __shared__ double lds[4 * 2];
     const int c = blockIdx.x;
-    const int member = w.chunk_member[c];
+    const Chunk ck = chunk_of(w, c);
+    const int member = ck.member;
     double v[1] = {0.0};
-    for (int64_t e = w.chunk_begin[c] + threadIdx.x; e < w.chunk_begin[c + 1]; e += TPB) v[0] += psi[e] * psi[e];
+    for (int64_t e = ck.e0 + threadIdx.x; e < ck.e1; e += TPB) v[0] += psi[e] * psi[e];
     block_reduce<1>(v, 1, lds);
     if (threadIdx.x == 0) w.part[(size_t)c * (KM + 2)] = v[0];
     const int c0 = w.member_chunk[member], c1 = w.member_chunk[member + 1];
@@ -148,10 +169,11 @@ __global__ __launch_bounds__(TPB) void k_init_vec(const double *__restrict__ psi
     __shared__ double lds[4 * 2];
     __shared__ double red[TPB];
     const int c = blockIdx.x;
-    const int member = w.chunk_member[c];
+    const Chunk ck = chunk_of(w, c);
+    const int member = ck.member;
     const double sc = w.st[member].scale;
     double mn = INFINITY;
-    for (int64_t e = w.chunk_begin[c] + threadIdx.x; e < w.chunk_begin[c + 1]; e += TPB) {
+    for (int64_t e = ck.e0 + threadIdx.x; e < ck.e1; e += TPB) {
         w.V[e] = psi[e] * sc;
         mn = fmin(mn, w.D[e]);
     }
@@ -189,6 +211,7 @@ struct JacobiLds {
     double c[KM / 2], s[KM / 2];
     double red[4 * 2];
     int order[KM];
+    int rotated;
 };
 
 __device__ void jacobi_eig(DavState &S, int n, JacobiLds &L) {
@@ -227,17 +250,18 @@ __device__ void jacobi_eig(DavState &S, int n, JacobiLds &L) {
     __syncthreads();
     const int n2 = (n + 1) & ~1;
     const int np = n2 / 2;
-    for (int sweep = 0; sweep < 40; ++sweep) {
-        double off = 0.0, tot = 0.0;
-        for (int e = tid; e < n * n; e += TPB) {
-            int r = e / n, c = e % n;
-            double a = L.A[r][c] * L.A[r][c];
-            tot += a;
-            if (r != c) off += a;
-        }
-        double v2[2] = {off, tot};
-        block_reduce<2>(v2, 2, L.red);
-        if (v2[0] <= 1e-30 * v2[1] || v2[0] < 1e-300) break;
+    // Frobenius norm for the absolute part of the rotation threshold
+    double fro = 0.0;
+    for (int e = tid; e < n * n; e += TPB) fro += L.A[e / n][e % n] * L.A[e / n][e % n];
+    double fv[1] = {fro};
+    block_reduce<1>(fv, 1, L.red);
+    const double abs_tol = 1e-18 * sqrt(fv[0]);
+    // Classical threshold Jacobi: a rotation is skipped when |a_pq| is below
+    // 1e-16 sqrt(|a_pp a_qq|) (or the absolute floor); stop after a sweep
+    // without rotations.
+    for (int sweep = 0; sweep < 30; ++sweep) {
+        if (tid == 0) L.rotated = 0;
+        __syncthreads();
         for (int step = 0; step < n2 - 1; ++step) {
             if (tid < np) {
                 int k = tid;
@@ -246,11 +270,13 @@ __device__ void jacobi_eig(DavState &S, int n, JacobiLds &L) {
                 double cc = 1.0, ss = 0.0;
                 if (p < n && q < n) {
                     double apq = L.A[p][q];
-                    if (fabs(apq) > 1e-300) {
-                        double th = (L.A[q][q] - L.A[p][p]) / (2.0 * apq);
+                    double app = L.A[p][p], aqq = L.A[q][q];
+                    if (fabs(apq) > fmax(1e-16 * sqrt(fabs(app * aqq)), abs_tol)) {
+                        double th = (aqq - app) / (2.0 * apq);
                         double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
                         cc = 1.0 / sqrt(t * t + 1.0);
                         ss = t * cc;
+                        L.rotated = 1;
                     }
                 }
                 L.c[k] = cc;
@@ -263,7 +289,7 @@ __device__ void jacobi_eig(DavState &S, int n, JacobiLds &L) {
             for (int e = tid; e < np * n; e += TPB) {
                 int k = e / n, j = e % n;
                 int p = L.order[2 * k], q = L.order[2 * k + 1];
-                if (p < n && q < n) {
+                if (p < n && q < n && L.s[k] != 0.0) {
                     double cc = L.c[k], ss = L.s[k];
                     double ap = L.A[p][j], aq = L.A[q][j];
                     L.A[p][j] = cc * ap - ss * aq;
@@ -275,7 +301,7 @@ __device__ void jacobi_eig(DavState &S, int n, JacobiLds &L) {
             for (int e = tid; e < np * n; e += TPB) {
                 int k = e / n, j = e % n;
                 int p = L.order[2 * k], q = L.order[2 * k + 1];
-                if (p < n && q < n) {
+                if (p < n && q < n && L.s[k] != 0.0) {
                     double cc = L.c[k], ss = L.s[k];
                     double ap = L.A[j][p], aq = L.A[j][q];
                     L.A[j][p] = cc * ap - ss * aq;
@@ -287,6 +313,8 @@ __device__ void jacobi_eig(DavState &S, int n, JacobiLds &L) {
             }
             __syncthreads();
         }
+        if (!L.rotated) break;  // read after the last barrier of the sweep: uniform
+        __syncthreads();
     }
     // sort eigenvalues ascending (stable selection by rank)
     for (int a = tid; a < n; a += TPB) {
@@ -315,14 +343,15 @@ __global__ __launch_bounds__(TPB) void k_rayleigh(DavArgs w, int i) {
     extern __shared__ __align__(16) unsigned char smem[];
     JacobiLds &L = *reinterpret_cast<JacobiLds *>(smem);
     const int c = blockIdx.x;
-    const int member = w.chunk_member[c];
-    if (!w.active[member]) return;
+    const Chunk ck = chunk_of(w, c);
+    const int member = ck.member;
+    const int act = w.active[member];  // checked after the loads are in flight
     const int64_t n = w.n;
     double acc[KB];
 #pragma unroll
     for (int j = 0; j < KB; ++j) acc[j] = 0.0;
     const double *wc = w.W + (int64_t)(i - 1) * n;
-    for (int64_t e = w.chunk_begin[c] + threadIdx.x; e < w.chunk_begin[c + 1]; e += TPB) {
+    for (int64_t e = ck.e0 + threadIdx.x; e < ck.e1; e += TPB) {
         const double x = wc[e];
         double v[KB];
 #pragma unroll
@@ -330,6 +359,7 @@ __global__ __launch_bounds__(TPB) void k_rayleigh(DavArgs w, int i) {
 #pragma unroll
         for (int j = 0; j < KB; ++j) acc[j] += (j < i ? v[j] : 0.0) * x;
     }
+    if (!act) return;
     block_reduce<KB>(acc, i, &L.Tm[0][0]);  // Tm is free until the eigensolve
     if (threadIdx.x == 0)
         for (int j = 0; j < i; ++j) w.part[(size_t)c * (KM + 2) + j] = acc[j];
@@ -360,9 +390,10 @@ __global__ __launch_bounds__(TPB) void k_ritz(DavArgs w, int i, int restart) {
     __shared__ double scratch[TPB];
     __shared__ double sums[KB + 2];
     const int c = blockIdx.x;
-    const int member = w.chunk_member[c];
+    const Chunk ck = chunk_of(w, c);
+    const int member = ck.member;
     const DavState &S = w.st[member];
-    if (!w.active[member]) return;
+    const int act = w.active[member];
     const int64_t n = w.n;
     double y[KB];
 #pragma unroll
@@ -371,7 +402,7 @@ __global__ __launch_bounds__(TPB) void k_ritz(DavArgs w, int i, int restart) {
     double acc[KB + 2];
 #pragma unroll
     for (int j = 0; j < KB + 2; ++j) acc[j] = 0.0;
-    for (int64_t e = w.chunk_begin[c] + threadIdx.x; e < w.chunk_begin[c + 1]; e += TPB) {
+    for (int64_t e = ck.e0 + threadIdx.x; e < ck.e1; e += TPB) {
         double v[KB], wv[KB];
         double x = 0.0, wy = 0.0;
 #pragma unroll
@@ -389,7 +420,7 @@ __global__ __launch_bounds__(TPB) void k_ritz(DavArgs w, int i, int restart) {
         double den = w.D[e] - sig;
         if (fabs(den) < fl) den = (den < 0.0) ? -fl : fl;
         const double t = r / den;
-        w.T[e] = t;
+        if (act) w.T[e] = t;
         acc[KB] += r * r;
         acc[KB + 1] += t * t;
         if (!restart) {
@@ -397,9 +428,10 @@ __global__ __launch_bounds__(TPB) void k_ritz(DavArgs w, int i, int restart) {
             for (int j = 0; j < KB; ++j) acc[j] += v[j] * t;
         }
     }
+    if (!act) return;
     block_reduce<KB + 2>(acc, KB + 2, lds);
     if (threadIdx.x == 0)
-        for (int j = 0; j < KB + 2; ++j) w.part[(size_t)c * (KM + 2) + j] = (j < KB) ? acc[j] : acc[j];
+        for (int j = 0; j < KB + 2; ++j) w.part[(size_t)c * (KM + 2) + j] = acc[j];
     // note: columns KB, KB+1 of the partial row hold ||r||^2 and ||t||^2
     const int c0 = w.member_chunk[member], c1 = w.member_chunk[member + 1];
     if (!last_block_of_member(w.counter, member, c1 - c0)) return;
@@ -440,7 +472,8 @@ __global__ __launch_bounds__(TPB) void k_restart(DavArgs w, int i, int kmin) {
     __shared__ double scratch[TPB];
     __shared__ double sums[KB + 1];
     const int c = blockIdx.x;
-    const int member = w.chunk_member[c];
+    const Chunk ck = chunk_of(w, c);
+    const int member = ck.member;
     const DavState &S = w.st[member];
     if (!w.active[member]) return;
     for (int e = threadIdx.x; e < KB * KB; e += TPB) {
@@ -452,7 +485,7 @@ __global__ __launch_bounds__(TPB) void k_restart(DavArgs w, int i, int kmin) {
     double acc[KB + 1];
 #pragma unroll
     for (int j = 0; j < KB + 1; ++j) acc[j] = 0.0;
-    for (int64_t e = w.chunk_begin[c] + threadIdx.x; e < w.chunk_begin[c + 1]; e += TPB) {
+    for (int64_t e = ck.e0 + threadIdx.x; e < ck.e1; e += TPB) {
         double v[KB], wv[KB];
 #pragma unroll
         for (int j = 0; j < KB; ++j) {
@@ -509,9 +542,10 @@ __global__ __launch_bounds__(TPB) void k_orth(DavArgs w, int i) {
     __shared__ double scratch[TPB];
     __shared__ double sums[KB + 1];
     const int c = blockIdx.x;
-    const int member = w.chunk_member[c];
+    const Chunk ck = chunk_of(w, c);
+    const int member = ck.member;
     const DavState &S = w.st[member];
-    if (!w.active[member]) return;
+    const int act = w.active[member];
     double s[KB];
 #pragma unroll
     for (int j = 0; j < KB; ++j) s[j] = (j < i) ? S.s[j] : 0.0;
@@ -519,7 +553,7 @@ __global__ __launch_bounds__(TPB) void k_orth(DavArgs w, int i) {
     double acc[KB + 1];
 #pragma unroll
     for (int j = 0; j < KB + 1; ++j) acc[j] = 0.0;
-    for (int64_t e = w.chunk_begin[c] + threadIdx.x; e < w.chunk_begin[c + 1]; e += TPB) {
+    for (int64_t e = ck.e0 + threadIdx.x; e < ck.e1; e += TPB) {
         double v[KB];
         double t = w.T[e];
 #pragma unroll
@@ -529,11 +563,12 @@ __global__ __launch_bounds__(TPB) void k_orth(DavArgs w, int i) {
             v[j] = (j < i) ? v[j] : 0.0;
             t -= v[j] * s[j];
         }
-        w.T[e] = t;
+        if (act) w.T[e] = t;
 #pragma unroll
         for (int j = 0; j < KB; ++j) acc[j] += v[j] * t;
         acc[KB] += t * t;
     }
+    if (!act) return;
     block_reduce<KB + 1>(acc, KB + 1, lds);
     if (threadIdx.x == 0)
         for (int j = 0; j < KB + 1; ++j) w.part[(size_t)c * (KM + 2) + j] = acc[j];
@@ -562,16 +597,17 @@ __global__ __launch_bounds__(TPB) void k_orth(DavArgs w, int i) {
 template <int KB>
 __global__ __launch_bounds__(TPB) void k_append(DavArgs w, int i) {
     const int c = blockIdx.x;
-    const int member = w.chunk_member[c];
+    const Chunk ck = chunk_of(w, c);
+    const int member = ck.member;
     const DavState &S = w.st[member];
-    if (!w.active[member]) return;
+    const int act = w.active[member];
     double s2[KB];
     const bool dg = S.dgks != 0;
 #pragma unroll
     for (int j = 0; j < KB; ++j) s2[j] = (dg && j < i) ? S.s2[j] : 0.0;
     const double sc = S.scale;
     const int64_t n = w.n;
-    for (int64_t e = w.chunk_begin[c] + threadIdx.x; e < w.chunk_begin[c + 1]; e += TPB) {
+    for (int64_t e = ck.e0 + threadIdx.x; e < ck.e1; e += TPB) {
         double t = w.T[e];
         if (dg) {
             double v[KB];
@@ -580,16 +616,17 @@ __global__ __launch_bounds__(TPB) void k_append(DavArgs w, int i) {
 #pragma unroll
             for (int j = 0; j < KB; ++j) t -= v[j] * s2[j];
         }
-        w.V[(int64_t)i * n + e] = t * sc;
+        if (act) w.V[(int64_t)i * n + e] = t * sc;
     }
-    if (threadIdx.x == 0 && blockIdx.x == w.member_chunk[member]) w.st[member].nproj += 1;
+    if (act && threadIdx.x == 0 && blockIdx.x == w.member_chunk[member]) w.st[member].nproj += 1;
 }
 
 // psi = V(:, :nvec) y (normalized Ritz vector of each member)
 template <int KB>
 __global__ __launch_bounds__(TPB) void k_finalize(DavArgs w, double *__restrict__ psi) {
     const int c = blockIdx.x;
-    const int member = w.chunk_member[c];
+    const Chunk ck = chunk_of(w, c);
+    const int member = ck.member;
     const DavState &S = w.st[member];
     if (S.bad_start == 1) return;
     const int nv = S.nvec;
@@ -597,7 +634,7 @@ __global__ __launch_bounds__(TPB) void k_finalize(DavArgs w, double *__restrict_
 #pragma unroll
     for (int j = 0; j < KB; ++j) y[j] = (j < nv) ? S.Y[j * KM] : 0.0;
     const int64_t n = w.n;
-    for (int64_t e = w.chunk_begin[c] + threadIdx.x; e < w.chunk_begin[c + 1]; e += TPB) {
+    for (int64_t e = ck.e0 + threadIdx.x; e < ck.e1; e += TPB) {
         double v[KB];
 #pragma unroll
         for (int j = 0; j < KB; ++j) v[j] = w.V[(int64_t)min(j, nv - 1) * n + e];
@@ -830,15 +867,24 @@ __global__ __launch_bounds__(TPB) void k_gemv_t_part(int64_t n, int k, const dou
         for (int j = 0; j < k; ++j) part[(size_t)blockIdx.x * KB + j] = acc[j];
 }
 
+// second stage: all k columns at once, thread t owns column t % k and every
+// (TPB / k)-th block from t / k; slots are then added in order (deterministic)
 template <int KB>
 __global__ __launch_bounds__(TPB) void k_gemv_t_final(int nblk, int k, const double *__restrict__ part,
                                                       double *__restrict__ s) {
-    __shared__ double lds[4];
-    for (int j = 0; j < k; ++j) {
-        double v[1] = {0.0};
-        for (int b = threadIdx.x; b < nblk; b += TPB) v[0] += part[(size_t)b * KB + j];
-        block_reduce<1>(v, 1, lds);
-        if (threadIdx.x == 0) s[j] = v[0];
+    __shared__ double scratch[TPB];
+    const int t = threadIdx.x, per = TPB / k, j = t % k, slot = t / k;
+    double v = 0.0;
+    if (slot < per) {
+#pragma unroll 4
+        for (int b = slot; b < nblk; b += per) v += part[(size_t)b * KB + j];
+    }
+    scratch[t] = v;
+    __syncthreads();
+    if (t < k) {
+        double acc = 0.0;
+        for (int q = 0; q < per; ++q) acc += scratch[t + q * k];
+        s[t] = acc;
     }
 }
 
@@ -857,8 +903,12 @@ __global__ __launch_bounds__(TPB) void k_gemv_n(int64_t n, int k, const double *
     }
 }
 
-static double *g_gemv_part = nullptr;
-static size_t g_gemv_part_bytes = 0;
+// per-device partials of dmrg_gemv_t (kept until the process ends)
+struct GemvScratch {
+    double *p = nullptr;
+    size_t bytes = 0;
+};
+static std::map<int, GemvScratch> g_gemv_scratch;
 
 extern "C" {
 
@@ -971,18 +1021,24 @@ dmrg_status dmrg_gemv_t(int64_t n, int32_t k, const double *V, int64_t ldv, cons
         return set_error(DMRG_E_INVALID_ARG, "need n >= 1, 1 <= k <= 64, ldv >= n and non-null pointers");
     int nblk = (int)std::min<int64_t>((n + TPB - 1) / TPB, 1024);
     size_t need = (size_t)nblk * 64 * 8;
-    if (need > g_gemv_part_bytes) {
-        if (g_gemv_part) (void)hipFree(g_gemv_part);
-        g_gemv_part = nullptr;
-        g_gemv_part_bytes = 0;
-        DMRG_HIP(hipMalloc((void **)&g_gemv_part, need));
-        g_gemv_part_bytes = need;
+    int dev = 0;
+    DMRG_HIP(hipGetDevice(&dev));
+    GemvScratch &gs = g_gemv_scratch[dev];
+    if (need > gs.bytes) {
+        // the stream may still use the old buffer: let it finish before freeing
+        DMRG_HIP(hipStreamSynchronize((hipStream_t)stream));
+        if (gs.p) (void)hipFree(gs.p);
+        gs.p = nullptr;
+        gs.bytes = 0;
+        DMRG_HIP(hipMalloc((void **)&gs.p, need));
+        gs.bytes = need;
     }
+    double *part = gs.p;
     hipStream_t st = (hipStream_t)stream;
     auto go = [&](auto kb) {
         constexpr int KB = decltype(kb)::value;
-        hipLaunchKernelGGL(k_gemv_t_part<KB>, dim3(nblk), dim3(TPB), 0, st, n, k, V, ldv, x, g_gemv_part);
-        hipLaunchKernelGGL(k_gemv_t_final<KB>, dim3(1), dim3(TPB), 0, st, nblk, k, (const double *)g_gemv_part, s);
+        hipLaunchKernelGGL(k_gemv_t_part<KB>, dim3(nblk), dim3(TPB), 0, st, n, k, V, ldv, x, part);
+        hipLaunchKernelGGL(k_gemv_t_final<KB>, dim3(1), dim3(TPB), 0, st, nblk, k, (const double *)part, s);
     };
     if (k <= 16)
         go(std::integral_constant<int, 16>{});

@@ -43,16 +43,24 @@ enum : int16_t {
 //   Q element (k, c): qtrans ? Q[c * ldq + k] : Q[k * ldq + c]   (c = output column)
 // with optional FP64 row scale pscale[r] and column scale qscale[c] applied to
 // the operands on load (a diagonal factor of the term).
+//
+// A fused two-sided segment (fused = 1) computes, for the tile's rows, the
+// intermediate slice T = P[rows, :K] Q[:K, :K2] (P = A block, Q = the input
+// block, both as above) in LDS and then C += coef * T R^T with R the
+// row-major B block read as R[c * ldr + k], k < K2.
 struct Seg {
     uint64_t p, q;            // address (OPD_ABS) or element offset
     uint64_t pscale, qscale;  // absolute FP64 addresses, 0 = none
+    uint64_t r;               // fused: absolute address of the B block
     int32_t ldp, ldq;
     int32_t K;
+    int32_t K2;   // fused: width of the intermediate
+    int32_t ldr;  // fused: row length of the B block
     int16_t pkind, qkind;
     int16_t ptrans, qtrans;
+    int16_t fused, pad16;
     int32_t coef;  // global coefficient index, -1 = 1.0
     int32_t term;  // global term index (for coefficient gradients), -1 = none
-    int32_t pad;
 };
 
 // A purely diagonal contribution at an output pair:
@@ -118,6 +126,15 @@ struct PassSet {  // everything one projection direction needs in one precision
     int32_t npart = 0;      // coefficient-gradient partials (forward only)
 };
 
+// One low-precision operator copy made at plan creation.
+struct ConvJob {
+    const double *src;
+    void *dst;
+    int64_t rows, cols;
+    int32_t mode;  // 0: full copy, 1: copy with a zero diagonal, 2: FP64 diagonal of a square block
+    int32_t pad;
+};
+
 struct DavidsonWork;
 
 }  // namespace dmrg
@@ -176,6 +193,7 @@ dmrg_status launch_gcoef(dmrg_plan *plan, const double *psi, const double *gbar,
 dmrg_status launch_convert(const double *src, void *dst, int64_t rows, int64_t cols, int prec,
                            int offdiag, hipStream_t s);
 dmrg_status launch_extract_diag(const double *src, double *dst, int64_t d, hipStream_t s);
+dmrg_status launch_convert_jobs(const ConvJob *jobs, int njob, int prec, hipStream_t s);
 dmrg_status launch_diagonal(dmrg_plan *plan, const double *coef, double *diag, hipStream_t s);
 // davidson.hip
 dmrg_status davidson_free(dmrg_plan *plan);

@@ -247,6 +247,9 @@ struct HostPass {
 
 static uint64_t U(const void *p) { return (uint64_t)(uintptr_t)p; }
 
+// Largest intermediate width a fused two-sided segment keeps in LDS (16 rows x 64).
+constexpr int64_t FUSE_MAX_K2 = 64;
+
 static void add_tiles(std::vector<Task> &out, int64_t rows, int64_t cols, int64_t c_off, int64_t x_off,
                       int32_t seg_b, int32_t seg_e, int32_t d_b, int32_t d_e, int member) {
     int ts = tile_for(rows, cols);
@@ -272,7 +275,13 @@ static void add_tiles(std::vector<Task> &out, int64_t rows, int64_t cols, int64_
 static double task_cost(const Task &t, const std::vector<Seg> &segs) {
     double sub = std::ceil(t.m / 16.0) * std::ceil(t.n / 16.0);
     double c = 8.0 * (t.diag_end - t.diag_begin) + 1.0;
-    for (int s = t.seg_begin; s < t.seg_end; ++s) c += sub * (segs[s].K + 16);
+    for (int s = t.seg_begin; s < t.seg_end; ++s) {
+        const Seg &g = segs[s];
+        if (g.fused)
+            c += (g.K + 16) * std::ceil(g.K2 / 16.0) + sub * (g.K2 + 16);
+        else
+            c += sub * (g.K + 16);
+    }
     return c;
 }
 
@@ -382,6 +391,20 @@ static void build_pass(const dmrg_plan *plan, bool adjoint, LowStore *low, uint6
                     hp.segs.push_back(s);
                     if (split)
                         hp.diags.push_back(DiagTerm{diag_addr(rc.a), blk_addr(rc.b, 2), gt, -1, 1, 1});
+                } else if (tile_for(po.dl, po.dr) == 16 && dk <= FUSE_MAX_K2) {
+                    // small intermediate: fused in the output tile (no stage-A task)
+                    s.fused = 1;
+                    s.p = blk_addr(rc.a, 0);
+                    s.pkind = OPD_ABS;
+                    s.ldp = (int32_t)di;
+                    s.q = (uint64_t)pin.off;
+                    s.qkind = OPD_IN;
+                    s.ldq = (int32_t)dk;
+                    s.K = (int32_t)di;
+                    s.r = blk_addr(rc.b, 0);
+                    s.ldr = (int32_t)dk;
+                    s.K2 = (int32_t)dk;
+                    hp.segs.push_back(s);
                 } else {
                     int64_t dj = po.dl, dl = po.dr;
                     Seg a{};
@@ -645,13 +668,13 @@ dmrg_status build_plan(dmrg_plan *plan, int32_t nprob, const dmrg_problem *probs
         // rebuild with the real base address (same order, so the same offsets)
         HostPass lo2;
         build_pass(plan, false, &ls, U(arena), lo2);
-        for (const auto &j : ls.jobs) {
-            char *dst = (char *)arena + j.off;
-            if (j.diag)
-                DMRG_TRY(launch_extract_diag(j.src, (double *)dst, j.rows, stream));
-            else
-                DMRG_TRY(launch_convert(j.src, dst, j.rows, j.cols, prec, j.offdiag, stream));
-        }
+        std::vector<ConvJob> jobs;
+        jobs.reserve(ls.jobs.size());
+        for (const auto &j : ls.jobs)
+            jobs.push_back(ConvJob{j.src, (char *)arena + j.off, j.rows, j.cols, j.diag ? 2 : (j.offdiag ? 1 : 0), 0});
+        ConvJob *d_jobs = nullptr;
+        DMRG_TRY(upload(plan, jobs, &d_jobs, stream));
+        DMRG_TRY(launch_convert_jobs(d_jobs, (int)jobs.size(), prec, stream));
         DMRG_TRY(upload_pass(plan, lo2, plan->fwd[1], stream));
         tmp = std::max(tmp, lo2.tmp);
     }

@@ -208,6 +208,83 @@ __device__ __forceinline__ void item_gemm(typename Tr<PREC>::acc_t (&acc)[2][2],
                 if (x < nsr && y < nsc) T::mma(acc[x][y], pv[x][b], qv[y][b]);
 }
 
+// Wave-local ordering of LDS accesses (lanes of one wavefront exchange data
+// through LDS; other wavefronts of the workgroup are not involved).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Fused two-sided segment on a tile of at most 16 rows:
+//   Tl[r][k] = sum_i A[row0 + r][i] X[i][k]      (k < K2, MFMA, then into LDS)
+//   acc[0][b] += Tl[r][:] R[col0 + c][:]^T        (second MFMA pass from LDS)
+// Tl is rounded to the operand format before the second product, like the
+// intermediate of the two-stage path.  tl: this wavefront's LDS slice
+// (16 x 64 doubles).
+template <int PREC>
+__device__ __forceinline__ void fused_item(typename Tr<PREC>::acc_t (&acc)[2][2], const Seg &s, const Task &tk,
+                                           const double *__restrict__ in, double *tl, int nsc) {
+    typedef Tr<PREC> T;
+    constexpr int KB = 4 * T::KPL;
+    const int lane = threadIdx.x & 63;
+    const int r16 = lane & 15, g = lane >> 4;
+    const int ncs = (s.K2 + 15) >> 4;  // column sub-tiles of the intermediate (<= 4)
+    const bool pok = r16 < tk.m;
+    const int prow = tk.row0 + (pok ? r16 : 0);
+    typename T::acc_t a1[4];
+#pragma unroll
+    for (int cs = 0; cs < 4; ++cs) a1[cs] = typename T::acc_t{0, 0, 0, 0};
+    for (int k0 = 0; k0 < s.K; k0 += KB) {
+        typename T::val_t pv[T::KPL], qv[4][T::KPL];
+        const int kk = k0 + T::KPL * g;
+        load_p<PREC, false, false>(pv, s, in, nullptr, prow, pok, kk, s.K, 1.0);
+#pragma unroll
+        for (int cs = 0; cs < 4; ++cs) {
+            const int col = cs * 16 + r16;
+            if (cs < ncs) load_q<PREC, true, false>(qv[cs], s, in, nullptr, col < s.K2 ? col : 0, col < s.K2, kk, s.K, 1.0);
+        }
+#pragma unroll
+        for (int cs = 0; cs < 4; ++cs)
+            if (cs < ncs) T::mma(a1[cs], pv, qv[cs]);
+    }
+#pragma unroll
+    for (int cs = 0; cs < 4; ++cs)
+        if (cs < ncs) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) tl[T::row(g, v) * 64 + cs * 16 + r16] = (double)a1[cs][v];
+        }
+    wave_lds_sync();
+    const typename T::store_t *R = (const typename T::store_t *)(uintptr_t)s.r;
+    for (int k0 = 0; k0 < s.K2; k0 += KB) {
+        typename T::val_t pv[T::KPL], qv[2][T::KPL];
+        const int kk = k0 + T::KPL * g;
+#pragma unroll
+        for (int j = 0; j < T::KPL; ++j) {
+            const int k = kk + j;
+            pv[j] = T::from_in((k < s.K2) ? tl[r16 * 64 + k] : 0.0);
+        }
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int c = b * 16 + r16;
+            const bool ok = c < tk.n;
+            const int col = tk.col0 + (ok ? c : 0);
+            if (b < nsc) {
+#pragma unroll
+                for (int j = 0; j < T::KPL; ++j) {
+                    const int k = kk + j;
+                    typename T::store_t x = 0;
+                    if (ok && k < s.K2) x = R[(int64_t)col * s.ldr + k];
+                    qv[b][j] = T::from_store(x);
+                }
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+            if (b < nsc) T::mma(acc[0][b], pv, qv[b]);
+    }
+    wave_lds_sync();  // the slice is rewritten by this wavefront's next fused item
+}
+
 // All work items [first, nit) step PW of one segment, for one operand layout.
 template <int PREC, bool PIN, bool PT, bool QIN, bool QT>
 __device__ __forceinline__ void seg_items(typename Tr<PREC>::acc_t (&acc)[2][2], const Seg &s, const Task &tk,
@@ -303,8 +380,13 @@ __global__ __launch_bounds__(64 * PW) void k_tasks(const Task *__restrict__ task
                 const Seg s = segs[si];
                 typename T::acc_t acc[2][2];
                 zero_acc<PREC>(acc);
-                // one wavefront runs every work item of the segment (PW-strided item loop, 4 passes)
-                for (int f = 0; f < PW; ++f) seg_dispatch<PREC>(acc, s, tk, in, tmp, nsr, nsc, f, (s.K + KC - 1) / KC);
+                if (s.fused) {
+                    fused_item<PREC>(acc, s, tk, in, &red[wave][0][0], nsc);
+                } else {
+                    // one wavefront runs every work item of the segment (PW-strided item loop, 4 passes)
+                    for (int f = 0; f < PW; ++f)
+                        seg_dispatch<PREC>(acc, s, tk, in, tmp, nsr, nsc, f, (s.K + KC - 1) / KC);
+                }
                 double part = 0.0;
 #pragma unroll
                 for (int a = 0; a < 2; ++a)
@@ -333,6 +415,21 @@ __global__ __launch_bounds__(64 * PW) void k_tasks(const Task *__restrict__ task
             }
             continue;
         }
+        // epilogue inputs (folded diagonal and the matching input entries) are
+        // fetched before the GEMM work so their latency overlaps it
+        double pre_x[4], pre_d[4];
+        if (MODE == 1 && dfold) {
+#pragma unroll
+            for (int qq = 0; qq < 4; ++qq) {
+                const int e = threadIdx.x + qq * 64 * PW;
+                pre_x[qq] = pre_d[qq] = 0.0;
+                if (e < tk.m * tk.n) {
+                    const int64_t rr = tk.row0 + e / tk.n, cc = tk.col0 + e % tk.n;
+                    pre_x[qq] = in[tk.x_off + rr * tk.ldc + cc];
+                    pre_d[qq] = dfold[tk.c_off + rr * tk.ldc + cc];
+                }
+            }
+        }
         double tot[2][2][4];
 #pragma unroll
         for (int a = 0; a < 2; ++a)
@@ -343,13 +440,17 @@ __global__ __launch_bounds__(64 * PW) void k_tasks(const Task *__restrict__ task
         int q = 0;  // work-item counter, identical in every wavefront
         for (int si = tk.seg_begin; si < tk.seg_end; ++si) {
             const int K = segs[si].K;
-            const int nit = (K + KC - 1) / KC;
+            const bool fused = segs[si].fused != 0;
+            const int nit = fused ? 1 : (K + KC - 1) / KC;  // a fused segment is one item
             const int first = (wave - q % PW + PW) % PW;  // first item of this segment owned by this wave
             if (first < nit) {
                 const Seg s = segs[si];
                 typename T::acc_t acc[2][2];
                 zero_acc<PREC>(acc);
-                seg_dispatch<PREC>(acc, s, tk, in, tmp, nsr, nsc, first, nit);
+                if (fused)
+                    fused_item<PREC>(acc, s, tk, in, &red[wave][0][0], nsc);
+                else
+                    seg_dispatch<PREC>(acc, s, tk, in, tmp, nsr, nsc, first, nit);
                 const double c = s.coef >= 0 ? coef[s.coef] : 1.0;
 #pragma unroll
                 for (int a = 0; a < 2; ++a)
@@ -369,7 +470,10 @@ __global__ __launch_bounds__(64 * PW) void k_tasks(const Task *__restrict__ task
                     for (int v = 0; v < 4; ++v) red[wave][a * 16 + T::row(g, v)][b * 16 + r16] = tot[a][b][v];
                 }
         __syncthreads();
-        for (int e = threadIdx.x; e < tk.m * tk.n; e += 64 * PW) {
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) {
+            const int e = threadIdx.x + qq * 64 * PW;
+            if (e >= tk.m * tk.n) break;
             const int r = e / tk.n, c = e % tk.n;
             double val = 0.0;
 #pragma unroll
@@ -380,7 +484,7 @@ __global__ __launch_bounds__(64 * PW) void k_tasks(const Task *__restrict__ task
                 ((typename T::store_t *)out)[o] = T::to_store(val);
             } else {
                 if (dfold)  // sum_d c_d vl vr, folded once for fixed coefficients
-                    val += dfold[o] * in[tk.x_off + rr * tk.ldc + cc];
+                    val += pre_d[qq] * pre_x[qq];
                 else if (tk.diag_end > tk.diag_begin)
                     val += diag_sum(diags, tk.diag_begin, tk.diag_end, coef, in[tk.x_off + rr * tk.ldc + cc], rr, cc);
                 ((double *)out)[o] = val;
@@ -457,6 +561,35 @@ __global__ __launch_bounds__(256) void k_extract_diag(const double *__restrict__
                                                       int64_t d) {
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < d; i += (int64_t)gridDim.x * 256)
         dst[i] = src[i * (d + 1)];
+}
+
+// All operator-copy jobs of a plan in one launch: a block per job (grid-strided).
+__global__ __launch_bounds__(256) void k_convert_jobs(const ConvJob *__restrict__ jobs, int njob, int prec) {
+    for (int j = blockIdx.x; j < njob; j += gridDim.x) {
+        const ConvJob jb = jobs[j];
+        if (jb.mode == 2) {
+            for (int64_t i = threadIdx.x; i < jb.rows; i += 256)
+                ((double *)jb.dst)[i] = jb.src[i * (jb.rows + 1)];
+            continue;
+        }
+        const int64_t cnt = jb.rows * jb.cols;
+        for (int64_t e = threadIdx.x; e < cnt; e += 256) {
+            double x = jb.src[e];
+            if (jb.mode == 1 && (e / jb.cols) == (e % jb.cols)) x = 0.0;
+            const float f = (float)x;
+            if (prec == DMRG_F32)
+                ((float *)jb.dst)[e] = f;
+            else
+                ((uint16_t *)jb.dst)[e] = f32_to_bf16_bits(f);
+        }
+    }
+}
+
+dmrg_status launch_convert_jobs(const ConvJob *jobs, int njob, int prec, hipStream_t s) {
+    if (njob <= 0) return DMRG_OK;
+    hipLaunchKernelGGL(k_convert_jobs, dim3(std::min(njob, 8192)), dim3(256), 0, s, jobs, njob, prec);
+    DMRG_HIP(hipGetLastError());
+    return DMRG_OK;
 }
 
 // ------------------------------------------------------------------ launchers

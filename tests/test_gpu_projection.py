@@ -78,11 +78,18 @@ def test_projection_fp64_configs(cfg):
     assert _relerr(y, ref) <= 1e-12, _relerr(y, ref)
 
 
+TILES = {"auto": "auto", "t16": ((1 << 30,), (16,)), "t32": ((1 << 30,), (32,))}
+
+
+@pytest.mark.parametrize("tiles", ["auto", "t16", "t32"])
 @pytest.mark.parametrize("seed,rank", RANDOM)
-def test_projection_fp64_random_structures(seed, rank):
-    """Ragged, empty and 1x1 sectors, missing blocks, diagonal factors on either side."""
+def test_projection_fp64_random_structures(seed, rank, tiles):
+    """Ragged, empty and 1x1 sectors, missing blocks, diagonal factors on either
+    side; 16-row tiles take the fused two-sided path, 32-row tiles the two-stage one."""
+    import paper_1309_5571_amd as dm
+
     p = gen.random_problem(seed, rank=rank, dmax=40 if seed % 3 == 0 else 12)
-    pl = _plan(p)
+    pl = dm.Plan(p, tiles=TILES[tiles])
     psi = np.random.default_rng(seed).standard_normal(pl.n)
     y = pl.project_raw(_dev(psi)).cpu().numpy()
     ref = projection.project_sectors(p, psi)
@@ -130,10 +137,13 @@ def test_batched_plan_equals_members():
 # ------------------------------------------------------------------ adjoint and coefficient gradient
 
 
+@pytest.mark.parametrize("tiles", ["t16", "t32"])
 @pytest.mark.parametrize("seed,rank", RANDOM[:10])
-def test_adjoint_random(seed, rank):
+def test_adjoint_random(seed, rank, tiles):
+    import paper_1309_5571_amd as dm
+
     p = gen.random_problem(seed, rank=rank, dmax=24)
-    pl = _plan(p)
+    pl = dm.Plan(p, tiles=TILES[tiles])
     rng = np.random.default_rng(seed + 7)
     psi, g = rng.standard_normal(pl.n), rng.standard_normal(pl.n)
     gpsi, gcoef = pl.backward_raw(_dev(psi), _dev(g))
@@ -203,11 +213,14 @@ def test_lowprec_projection_envelope(cfg, prec, u):
     assert _relerr(y64, exact) <= 1e-12
 
 
-def test_lowprec_random_structures():
+@pytest.mark.parametrize("tiles", ["t16", "t32"])
+def test_lowprec_random_structures(tiles):
+    import paper_1309_5571_amd as dm
+
     for seed in range(6):
         p = gen.random_problem(seed, rank=1 + seed % 2, dmax=30)
         for prec in ("f32", "bf16"):
-            pl = _plan(p, prec=prec)
+            pl = dm.Plan(p, prec=prec, tiles=TILES[tiles])
             psi = np.random.default_rng(seed).standard_normal(pl.n)
             y = pl.project_raw(_dev(psi), prec=prec).cpu().numpy()
             emul = precision.project_emulated(p, psi, "fp32" if prec == "f32" else "bf16")
