@@ -38,7 +38,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true", help="skip the projection and FP64 comparison timings")
     ap.add_argument("--workload", default="hubbard_m2048",
-                    choices=["hubbard_m2048", "heisenberg_m1024", "j1j2_m1024", "batched_64", "gemv"],
+                    choices=["hubbard_m2048", "heisenberg_m1024", "j1j2_m1024", "batched_64", "gemv", "pmc"],
                     help="hubbard_m2048 is the headline line; the others time the projection and the "
                          "mixed-precision solve of the other synthetic workloads")
     return ap.parse_args()
@@ -94,6 +94,54 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+COPY_BYTES = 256 << 20  # calibration copy: reads and writes this many bytes
+
+
+def pmc_workload():
+    """Dispatches for the HBM-traffic counters (run under rocprofv3 --pmc): a plain
+    device copy of COPY_BYTES (calibrates FETCH_SIZE / WRITE_SIZE), then 20 FP64
+    projections of the Hubbard m=2048 superblock."""
+    import torch
+
+    import gen
+    import paper_1309_5571_amd as dm
+
+    x = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    del x, y
+    p = gen.config(3)
+    plan = dm.Plan(p)
+    psi = torch.from_numpy(gen.start_vector(plan.n, 7)).cuda()
+    out = torch.empty_like(psi)
+    for _ in range(20):
+        plan.project_raw(psi, out=out)
+    torch.cuda.synchronize()
+    return {"workload": "pmc", "copy_bytes": COPY_BYTES, "projections": 20,
+            "projection_algorithmic_bytes": plan.bytes}
+
+
+def traffic_from_profile(plan_bytes):
+    """HBM bytes per projection from the committed counter summary, if it was
+    taken on the current kernel sources (else None)."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "traffic_projection_hubbard_m2048.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    h = hashlib.sha256()
+    for src in rec.get("sources", []):
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != rec.get("sources_sha256"):
+        return None
+    return rec.get("bytes_per_projection")
+
+
 def gemv_sweep(reps=100):
     """The tall-skinny products of the orthogonalization (dmrg_gemv_t / _n) at the
     heights the paper sweeps (1e5, 5e5, 1e6) plus 4e6, widths 1..32, FP64.
@@ -145,6 +193,9 @@ def main():
     torch.cuda.set_device(dev)
     if args.workload == "gemv":
         print(json.dumps({"workload": "gemv_sweep", "unit": "GB/s", "rows": gemv_sweep()}))
+        return
+    if args.workload == "pmc":
+        print(json.dumps(pmc_workload()))
         return
     cfg = {"hubbard_m2048": 3, "heisenberg_m1024": 2, "j1j2_m1024": 5, "batched_64": 4}[args.workload]
     p = gen.config(cfg)
@@ -212,8 +263,9 @@ def main():
     if t_proj:
         achieved = plan.bytes / t_proj * 1e-9
         roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK["hbm_GBs"], "unit": "GB/s",
-                "frac": achieved / PEAK["hbm_GBs"], "traffic": None, "kernel": "projection (f64, 2 launches)",
-                "algorithmic_bytes": plan.bytes, "algorithmic_flop": plan.flop}
+                "frac": achieved / PEAK["hbm_GBs"],
+                "traffic": traffic_from_profile(plan.bytes) if cfg == 3 else None,
+                "kernel": "projection (f64)", "algorithmic_bytes": plan.bytes, "algorithmic_flop": plan.flop}
 
     cpu = None
     E_ref = None

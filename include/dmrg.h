@@ -168,7 +168,7 @@ dmrg_status dmrg_project_backward(dmrg_plan *plan, const double *coef, const dou
 /* Davidson options (Alg. 3 with the readings documented in the design notes). */
 typedef struct {
     double tol;            /* stop when ||r||_2 <= tol (||x|| = 1).  default 1e-10 */
-    int32_t kmax;          /* subspace limit (thick restart when reached), 2..64, default 32 */
+    int32_t kmax;          /* subspace limit (thick restart when reached), 2..48, default 32 */
     int32_t kmin;          /* vectors kept at a restart, 1..kmax-1, default 8 */
     int32_t max_iter;      /* iterations (Ritz evaluations) per phase, default 500 */
     double precond_floor;  /* |D - sigma| floor of the diagonal preconditioner, default 1e-3 */

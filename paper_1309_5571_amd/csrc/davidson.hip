@@ -5,16 +5,16 @@
 // host knows the kernel sequence of each iteration in advance and can replay
 // captured hipGraphs of several iterations.  Per iteration:
 //
-//   k_rayleigh  B(:, i-1) = V^T W(:, i-1)            (Alg. 3 line 3)
-//               last block per member: smallest Ritz pair of B (line 4) by a
+//   projection  W(:, i-1) = H V(:, i-1)                  (line 2), whose output
+//               tiles also form B(:, i-1) = V^T W(:, i-1) (line 3); the last
+//               tile of a member solves the small eigenproblem (line 4) by a
 //               warm-started parallel Jacobi in one workgroup
 //   k_ritz      x = V y, r = W y - lambda x, ||r||   (lines 5-7)
 //               t = r / (D - sigma) (line 10, shifted diagonal preconditioner)
 //               s = V^T t (line 12, first pass) -- all in one sweep over V, W
 //   k_restart   (when i = kmax) V <- V Y(:, :kmin), W <- W Y(:, :kmin), s = V^T t
 //   k_orth      t <- t - V s (line 13), ||t||, and V^T t for the DGKS pass
-//   k_append    V(:, i) = (t - V s2) / ||.||        (line 14)
-//   projection  W(:, i) = H V(:, i)                  (line 2 of the next iteration)
+//   k_append    V(:, i) = (t - V s2) / ||.||  when a second pass is needed (line 14)
 //
 // Reductions over the vector length are split into fixed chunks; each block
 // writes its partial sums, and the last block of a member (atomic arrival
@@ -26,22 +26,11 @@
 #include <map>
 #include <tuple>
 
+#include "dav_common.h"
 #include "gemv.h"
 #include "internal.h"
 
 namespace dmrg {
-
-constexpr int KM = 48;  // largest supported kmax
-constexpr int TPB = GEMV_THREADS;
-
-struct DavState {
-    double Bm[KM * KM];  // Rayleigh matrix, row-major, leading dimension KM
-    double Y[KM * KM];   // eigenvectors of Bm (column c = Y[r * KM + c])
-    double theta[KM];
-    double s[KM], s2[KM];
-    double lambda, sigma, dmin, rnorm, tn0, scale, tol, floor_;
-    int32_t converged, breakdown, iters, nproj, restarts, dgks, nvec, max_iter, bad_start;
-};
 
 // Kernel-argument view of the Davidson workspace (plain pointers only).
 struct DavArgs {
@@ -90,52 +79,6 @@ __device__ __forceinline__ Chunk chunk_of(const DavArgs &w, int c) {
     return k;
 }
 
-__device__ __forceinline__ bool last_block_of_member(int32_t *counter, int member, int nch) {
-    __shared__ int is_last;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        int old = atomicAdd(&counter[member], 1);
-        is_last = (old == nch - 1);
-        if (is_last) counter[member] = 0;
-    }
-    __syncthreads();
-    if (is_last) __threadfence();
-    return is_last != 0;
-}
-
-// sum of partial column j over the member's chunks (fixed order), all threads get it
-__device__ double member_sum(const double *part, int c0, int c1, int j, double *lds) {
-    double v = 0.0;
-    for (int c = c0 + (int)threadIdx.x; c < c1; c += TPB) v += part[(size_t)c * (KM + 2) + j];
-    double r[1] = {v};
-    block_reduce<1>(r, 1, lds);
-    return r[0];
-}
-
-// Sums columns [0, ncols) of the member's chunk partials at once: thread t owns
-// column t % ncols and every (TPB / ncols)-th chunk from t / ncols, then the
-// per-thread sums of each column are added in slot order.  out: shared [ncols].
-__device__ void member_sums(const double *__restrict__ part, int c0, int c1, int ncols, double *scratch,
-                            double *out) {
-    const int t = threadIdx.x;
-    const int per = TPB / ncols;
-    const int j = t % ncols, slot = t / ncols;
-    double v = 0.0;
-    if (slot < per) {
-#pragma unroll 4
-        for (int c = c0 + slot; c < c1; c += per) v += part[(size_t)c * (KM + 2) + j];
-    }
-    scratch[t] = v;
-    __syncthreads();
-    if (t < ncols) {
-        double acc = 0.0;
-        for (int q = 0; q < per; ++q) acc += scratch[t + q * ncols];
-        out[t] = acc;
-    }
-    __syncthreads();
-}
-
 // ------------------------------------------------------------------ init kernels
 
 // ||psi||^2 per member; last block stores the scale, flags zero / non-finite starts.
@@ -148,8 +91,9 @@ __global__ __launch_bounds__(TPB) void k_init_norm(const double *__restrict__ ps
     for (int64_t e = ck.e0 + threadIdx.x; e < ck.e1; e += TPB) v[0] += psi[e] * psi[e];
     block_reduce<1>(v, 1, lds);
     if (threadIdx.x == 0) w.part[(size_t)c * (KM + 2)] = v[0];
-    const int c0 = w.member_chunk[member], c1 = w.member_chunk[member + 1];
-    if (!last_block_of_member(w.counter, member, c1 - c0)) return;
+    const int c0 = w.nprob == 1 ? 0 : w.member_chunk[member];
+    const int c1 = w.nprob == 1 ? w.nchunk : w.member_chunk[member + 1];
+    if (!last_arrival(w.counter, member, c - c0, c1 - c0)) return;
     double s = member_sum(w.part, c0, c1, 0, lds);
     if (threadIdx.x == 0) {
         DavState &S = w.st[member];
@@ -184,8 +128,9 @@ __global__ __launch_bounds__(TPB) void k_init_vec(const double *__restrict__ psi
         __syncthreads();
     }
     if (threadIdx.x == 0) w.part[(size_t)c * (KM + 2)] = red[0];
-    const int c0 = w.member_chunk[member], c1 = w.member_chunk[member + 1];
-    if (!last_block_of_member(w.counter, member, c1 - c0)) return;
+    const int c0 = w.nprob == 1 ? 0 : w.member_chunk[member];
+    const int c1 = w.nprob == 1 ? w.nchunk : w.member_chunk[member + 1];
+    if (!last_arrival(w.counter, member, c - c0, c1 - c0)) return;
     mn = INFINITY;
     for (int q = c0 + (int)threadIdx.x; q < c1; q += TPB) mn = fmin(mn, w.part[(size_t)q * (KM + 2)]);
     red[threadIdx.x] = mn;
@@ -200,188 +145,7 @@ __global__ __launch_bounds__(TPB) void k_init_vec(const double *__restrict__ psi
 
 // ------------------------------------------------------------------ small eigenproblem
 
-// Smallest-first eigen-decomposition of the member's Rayleigh matrix B[:n,:n]
-// by cyclic Jacobi in parallel (round-robin) order.  Warm start: the matrix is
-// first transformed by the previous eigenvectors extended with e_n, which
-// makes it nearly diagonal.  Runs in one workgroup; all threads must call.
-struct JacobiLds {
-    double A[KM][KM + 1];
-    double Vv[KM][KM + 1];
-    double Tm[KM][KM + 1];
-    double c[KM / 2], s[KM / 2];
-    double red[4 * 2];
-    int order[KM];
-    int rotated;
-};
-
-__device__ void jacobi_eig(DavState &S, int n, JacobiLds &L) {
-    const int tid = threadIdx.x;
-    // A = B, Vv = [Y_prev 0; 0 1]
-    for (int e = tid; e < n * n; e += TPB) {
-        int r = e / n, c = e % n;
-        L.Tm[r][c] = S.Bm[r * KM + c];
-        double y;
-        if (r < n - 1 && c < n - 1)
-            y = S.Y[r * KM + c];
-        else
-            y = (r == c) ? 1.0 : 0.0;
-        L.Vv[r][c] = y;
-    }
-    __syncthreads();
-    // A = Vv^T B Vv  (Tm holds B; A = B Vv first, then Vv^T A)
-    for (int e = tid; e < n * n; e += TPB) {
-        int r = e / n, c = e % n;
-        double acc = 0.0;
-        for (int k = 0; k < n; ++k) acc += L.Tm[r][k] * L.Vv[k][c];
-        L.A[r][c] = acc;
-    }
-    __syncthreads();
-    for (int e = tid; e < n * n; e += TPB) {
-        int r = e / n, c = e % n;
-        double acc = 0.0;
-        for (int k = 0; k < n; ++k) acc += L.Vv[k][r] * L.A[k][c];
-        L.Tm[r][c] = acc;
-    }
-    __syncthreads();
-    for (int e = tid; e < n * n; e += TPB) {
-        int r = e / n, c = e % n;
-        L.A[r][c] = 0.5 * (L.Tm[r][c] + L.Tm[c][r]);  // exact symmetry
-    }
-    __syncthreads();
-    const int n2 = (n + 1) & ~1;
-    const int np = n2 / 2;
-    // Frobenius norm for the absolute part of the rotation threshold
-    double fro = 0.0;
-    for (int e = tid; e < n * n; e += TPB) fro += L.A[e / n][e % n] * L.A[e / n][e % n];
-    double fv[1] = {fro};
-    block_reduce<1>(fv, 1, L.red);
-    const double abs_tol = 1e-18 * sqrt(fv[0]);
-    // Classical threshold Jacobi: a rotation is skipped when |a_pq| is below
-    // 1e-16 sqrt(|a_pp a_qq|) (or the absolute floor); stop after a sweep
-    // without rotations.
-    for (int sweep = 0; sweep < 30; ++sweep) {
-        if (tid == 0) L.rotated = 0;
-        __syncthreads();
-        for (int step = 0; step < n2 - 1; ++step) {
-            if (tid < np) {
-                int k = tid;
-                int p = (k == 0) ? 0 : ((k - 1 + step) % (n2 - 1)) + 1;
-                int q = ((n2 - 2 - k + step) % (n2 - 1)) + 1;
-                double cc = 1.0, ss = 0.0;
-                if (p < n && q < n) {
-                    double apq = L.A[p][q];
-                    double app = L.A[p][p], aqq = L.A[q][q];
-                    if (fabs(apq) > fmax(1e-16 * sqrt(fabs(app * aqq)), abs_tol)) {
-                        double th = (aqq - app) / (2.0 * apq);
-                        double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-                        cc = 1.0 / sqrt(t * t + 1.0);
-                        ss = t * cc;
-                        L.rotated = 1;
-                    }
-                }
-                L.c[k] = cc;
-                L.s[k] = ss;
-                L.order[2 * k] = p;
-                L.order[2 * k + 1] = q;
-            }
-            __syncthreads();
-            // rows: A <- J^T A
-            for (int e = tid; e < np * n; e += TPB) {
-                int k = e / n, j = e % n;
-                int p = L.order[2 * k], q = L.order[2 * k + 1];
-                if (p < n && q < n && L.s[k] != 0.0) {
-                    double cc = L.c[k], ss = L.s[k];
-                    double ap = L.A[p][j], aq = L.A[q][j];
-                    L.A[p][j] = cc * ap - ss * aq;
-                    L.A[q][j] = ss * ap + cc * aq;
-                }
-            }
-            __syncthreads();
-            // columns: A <- A J, Vv <- Vv J
-            for (int e = tid; e < np * n; e += TPB) {
-                int k = e / n, j = e % n;
-                int p = L.order[2 * k], q = L.order[2 * k + 1];
-                if (p < n && q < n && L.s[k] != 0.0) {
-                    double cc = L.c[k], ss = L.s[k];
-                    double ap = L.A[j][p], aq = L.A[j][q];
-                    L.A[j][p] = cc * ap - ss * aq;
-                    L.A[j][q] = ss * ap + cc * aq;
-                    double vp = L.Vv[j][p], vq = L.Vv[j][q];
-                    L.Vv[j][p] = cc * vp - ss * vq;
-                    L.Vv[j][q] = ss * vp + cc * vq;
-                }
-            }
-            __syncthreads();
-        }
-        if (!L.rotated) break;  // read after the last barrier of the sweep: uniform
-        __syncthreads();
-    }
-    // sort eigenvalues ascending (stable selection by rank)
-    for (int a = tid; a < n; a += TPB) {
-        double da = L.A[a][a];
-        int rank = 0;
-        for (int b = 0; b < n; ++b) {
-            double db = L.A[b][b];
-            rank += (db < da) || (db == da && b < a);
-        }
-        L.order[rank] = a;
-    }
-    __syncthreads();
-    for (int e = tid; e < n * n; e += TPB) {
-        int r = e / n, c = e % n;
-        S.Y[r * KM + c] = L.Vv[r][L.order[c]];
-    }
-    for (int c = tid; c < n; c += TPB) S.theta[c] = L.A[L.order[c]][L.order[c]];
-    __syncthreads();
-}
-
 // ------------------------------------------------------------------ iteration kernels
-
-// B(:, i-1) = V(:, :i)^T W(:, i-1); last block of a member: Ritz pair.
-template <int KB>
-__global__ __launch_bounds__(TPB) void k_rayleigh(DavArgs w, int i) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    JacobiLds &L = *reinterpret_cast<JacobiLds *>(smem);
-    const int c = blockIdx.x;
-    const Chunk ck = chunk_of(w, c);
-    const int member = ck.member;
-    const int act = w.active[member];  // checked after the loads are in flight
-    const int64_t n = w.n;
-    double acc[KB];
-#pragma unroll
-    for (int j = 0; j < KB; ++j) acc[j] = 0.0;
-    const double *wc = w.W + (int64_t)(i - 1) * n;
-    for (int64_t e = ck.e0 + threadIdx.x; e < ck.e1; e += TPB) {
-        const double x = wc[e];
-        double v[KB];
-#pragma unroll
-        for (int j = 0; j < KB; ++j) v[j] = w.V[(int64_t)min(j, i - 1) * n + e];  // clamped: no branch
-#pragma unroll
-        for (int j = 0; j < KB; ++j) acc[j] += (j < i ? v[j] : 0.0) * x;
-    }
-    if (!act) return;
-    block_reduce<KB>(acc, i, &L.Tm[0][0]);  // Tm is free until the eigensolve
-    if (threadIdx.x == 0)
-        for (int j = 0; j < i; ++j) w.part[(size_t)c * (KM + 2) + j] = acc[j];
-    const int c0 = w.member_chunk[member], c1 = w.member_chunk[member + 1];
-    if (!last_block_of_member(w.counter, member, c1 - c0)) return;
-    DavState &S = w.st[member];
-    member_sums(w.part, c0, c1, i, &L.Tm[0][0], &L.A[0][0]);
-    if ((int)threadIdx.x < i) {
-        const int j = threadIdx.x;
-        const double b = L.A[0][j];
-        S.Bm[j * KM + (i - 1)] = b;
-        S.Bm[(i - 1) * KM + j] = b;
-    }
-    __syncthreads();
-    jacobi_eig(S, i, L);
-    if (threadIdx.x == 0) {
-        S.lambda = S.theta[0];
-        S.sigma = fmin(S.lambda, S.dmin);
-        S.iters += 1;
-        S.nvec = i;
-    }
-}
 
 // x = V y, r = W y - lambda x, t = r / (D - sigma); partials: ||r||^2, ||t||^2, V^T t.
 template <int KB>
@@ -433,8 +197,9 @@ __global__ __launch_bounds__(TPB) void k_ritz(DavArgs w, int i, int restart) {
     if (threadIdx.x == 0)
         for (int j = 0; j < KB + 2; ++j) w.part[(size_t)c * (KM + 2) + j] = acc[j];
     // note: columns KB, KB+1 of the partial row hold ||r||^2 and ||t||^2
-    const int c0 = w.member_chunk[member], c1 = w.member_chunk[member + 1];
-    if (!last_block_of_member(w.counter, member, c1 - c0)) return;
+    const int c0 = w.nprob == 1 ? 0 : w.member_chunk[member];
+    const int c1 = w.nprob == 1 ? w.nchunk : w.member_chunk[member + 1];
+    if (!last_arrival(w.counter, member, c - c0, c1 - c0)) return;
     DavState &Sm = w.st[member];
     member_sums(w.part, c0, c1, KB + 2, scratch, sums);
     const double rr = sums[KB];
@@ -459,7 +224,15 @@ __global__ __launch_bounds__(TPB) void k_ritz(DavArgs w, int i, int restart) {
             w.active[member] = 0;
             atomicSub(w.nactive, 1);
         } else if (!restart) {
+            // ||t - V s||^2 = ||t||^2 - ||s||^2; reliable unless it cancels below half
             Sm.dgks = (tt - ss) < 0.5 * tt;
+            if (!(tt > 0.0)) {
+                Sm.breakdown = 1;
+                w.active[member] = 0;
+                atomicSub(w.nactive, 1);
+            } else if (!Sm.dgks) {
+                Sm.scale = 1.0 / sqrt(tt - ss);
+            }
         }
     }
 }
@@ -514,8 +287,9 @@ __global__ __launch_bounds__(TPB) void k_restart(DavArgs w, int i, int kmin) {
     block_reduce<KB + 1>(acc, KB + 1, lds);
     if (threadIdx.x == 0)
         for (int j = 0; j < KB + 1; ++j) w.part[(size_t)c * (KM + 2) + j] = acc[j];
-    const int c0 = w.member_chunk[member], c1 = w.member_chunk[member + 1];
-    if (!last_block_of_member(w.counter, member, c1 - c0)) return;
+    const int c0 = w.nprob == 1 ? 0 : w.member_chunk[member];
+    const int c1 = w.nprob == 1 ? w.nchunk : w.member_chunk[member + 1];
+    if (!last_arrival(w.counter, member, c - c0, c1 - c0)) return;
     DavState &Sm = w.st[member];
     member_sums(w.part, c0, c1, KB + 1, scratch, sums);
     const double tt = sums[KB];
@@ -531,6 +305,13 @@ __global__ __launch_bounds__(TPB) void k_restart(DavArgs w, int i, int kmin) {
             }
         Sm.tn0 = sqrt(tt);
         Sm.dgks = (tt - ss) < 0.5 * tt;
+        if (!(tt > 0.0)) {
+            Sm.breakdown = 1;
+            w.active[member] = 0;
+            atomicSub(w.nactive, 1);
+        } else if (!Sm.dgks) {
+            Sm.scale = 1.0 / sqrt(tt - ss);
+        }
         Sm.restarts += 1;
     }
 }
@@ -546,6 +327,8 @@ __global__ __launch_bounds__(TPB) void k_orth(DavArgs w, int i) {
     const int member = ck.member;
     const DavState &S = w.st[member];
     const int act = w.active[member];
+    const int dg = S.dgks;         // second Gram-Schmidt pass needed (decided by the previous tail)
+    const double sc = S.scale;     // 1/||t - V s|| by Pythagoras when no second pass is needed
     double s[KB];
 #pragma unroll
     for (int j = 0; j < KB; ++j) s[j] = (j < i) ? S.s[j] : 0.0;
@@ -563,26 +346,30 @@ __global__ __launch_bounds__(TPB) void k_orth(DavArgs w, int i) {
             v[j] = (j < i) ? v[j] : 0.0;
             t -= v[j] * s[j];
         }
+        if (!dg) {
+            if (act) w.V[(int64_t)i * n + e] = t * sc;  // line 14: normalize and append
+            continue;
+        }
         if (act) w.T[e] = t;
 #pragma unroll
         for (int j = 0; j < KB; ++j) acc[j] += v[j] * t;
         acc[KB] += t * t;
     }
-    if (!act) return;
+    if (!act || !dg) return;
     block_reduce<KB + 1>(acc, KB + 1, lds);
     if (threadIdx.x == 0)
         for (int j = 0; j < KB + 1; ++j) w.part[(size_t)c * (KM + 2) + j] = acc[j];
-    const int c0 = w.member_chunk[member], c1 = w.member_chunk[member + 1];
-    if (!last_block_of_member(w.counter, member, c1 - c0)) return;
+    const int c0 = w.nprob == 1 ? 0 : w.member_chunk[member];
+    const int c1 = w.nprob == 1 ? w.nchunk : w.member_chunk[member + 1];
+    if (!last_arrival(w.counter, member, c - c0, c1 - c0)) return;
     DavState &Sm = w.st[member];
     member_sums(w.part, c0, c1, KB + 1, scratch, sums);
     const double tt = sums[KB];
     double ss = 0.0;
-    if ((int)threadIdx.x < i) Sm.s2[threadIdx.x] = Sm.dgks ? sums[threadIdx.x] : 0.0;
+    if ((int)threadIdx.x < i) Sm.s2[threadIdx.x] = sums[threadIdx.x];
     for (int j = 0; j < i; ++j) ss += sums[j] * sums[j];
     if (threadIdx.x == 0) {
-        double nn = Sm.dgks ? (tt - ss) : tt;
-        double nrm = sqrt(fmax(nn, 0.0));
+        const double nrm = sqrt(fmax(tt - ss, 0.0));
         if (!(nrm > 1e-13 * Sm.tn0)) {
             Sm.breakdown = 1;
             w.active[member] = 0;
@@ -593,32 +380,28 @@ __global__ __launch_bounds__(TPB) void k_orth(DavArgs w, int i) {
     }
 }
 
-// V(:, i) = (t - V s2) * scale
+// Second Gram-Schmidt pass: V(:, i) = (t - V s2) * scale; no-op unless needed.
 template <int KB>
 __global__ __launch_bounds__(TPB) void k_append(DavArgs w, int i) {
     const int c = blockIdx.x;
     const Chunk ck = chunk_of(w, c);
     const int member = ck.member;
     const DavState &S = w.st[member];
-    const int act = w.active[member];
+    if (!S.dgks || !w.active[member]) return;
     double s2[KB];
-    const bool dg = S.dgks != 0;
 #pragma unroll
-    for (int j = 0; j < KB; ++j) s2[j] = (dg && j < i) ? S.s2[j] : 0.0;
+    for (int j = 0; j < KB; ++j) s2[j] = (j < i) ? S.s2[j] : 0.0;
     const double sc = S.scale;
     const int64_t n = w.n;
     for (int64_t e = ck.e0 + threadIdx.x; e < ck.e1; e += TPB) {
         double t = w.T[e];
-        if (dg) {
-            double v[KB];
+        double v[KB];
 #pragma unroll
-            for (int j = 0; j < KB; ++j) v[j] = w.V[(int64_t)min(j, i - 1) * n + e];
+        for (int j = 0; j < KB; ++j) v[j] = w.V[(int64_t)min(j, i - 1) * n + e];
 #pragma unroll
-            for (int j = 0; j < KB; ++j) t -= v[j] * s2[j];
-        }
-        if (act) w.V[(int64_t)i * n + e] = t * sc;
+        for (int j = 0; j < KB; ++j) t -= v[j] * s2[j];
+        w.V[(int64_t)i * n + e] = t * sc;
     }
-    if (act && threadIdx.x == 0 && blockIdx.x == w.member_chunk[member]) w.st[member].nproj += 1;
 }
 
 // psi = V(:, :nvec) y (normalized Ritz vector of each member)
@@ -661,8 +444,7 @@ __global__ void k_set_state(DavArgs w, double tol, double floor_, int max_iter) 
     S.iters = 0;  // counts are per phase; the host adds the phases
     S.nproj = 0;
     S.restarts = 0;
-    S.Y[0] = 1.0;
-    w.counter[m] = 0;
+    S.Y[0] = 1.0;  // (arrival counters are zeroed at allocation and by every completed reduction)
     if (m == 0) *w.nactive = w.nprob;
 }
 
@@ -712,6 +494,15 @@ static dmrg_status work_alloc(dmrg_plan *plan, int kmax, int kmin, hipStream_t s
     }
     cb.push_back(plan->n);
     A.nchunk = (int)cm.size();
+    // two-level arrival counters bound the chunks (and output tiles) of one member
+    const int64_t max_arrivals = (int64_t)ARRIVE_G * (CTR_STRIDE - 1);
+    for (int p = 0; p < plan->nprob; ++p)
+        if (mc[p + 1] - mc[p] > max_arrivals)
+            return set_error(DMRG_E_UNSUPPORTED, "member %d: target sector larger than %lld elements", p,
+                             (long long)(max_arrivals * CH));
+    for (int q = 0; q < 2; ++q)
+        if (plan->fwd[q].stageB.ntask > max_arrivals)
+            return set_error(DMRG_E_UNSUPPORTED, "more than %lld output tiles", (long long)max_arrivals);
     auto alloc = [&](void **p, size_t bytes) -> dmrg_status {
         DMRG_HIP(hipMalloc(p, std::max<size_t>(bytes, 8)));
         w->owned.push_back(*p);
@@ -724,11 +515,13 @@ static dmrg_status work_alloc(dmrg_plan *plan, int kmax, int kmin, hipStream_t s
     DMRG_TRY(alloc((void **)&A.D, n * 8));
     DMRG_TRY(alloc((void **)&A.dfold, n * 8));
     DMRG_TRY(alloc((void **)&A.coef, std::max(plan->nterm_total, 1) * 8));
-    DMRG_TRY(alloc((void **)&A.part, (size_t)A.nchunk * (KM + 2) * 8));
+    // partial rows: one per chunk, or one per output tile when the projection runs the Rayleigh step
+    const int rows = std::max({A.nchunk, plan->fwd[0].stageB.ntask, plan->fwd[1].stageB.ntask});
+    DMRG_TRY(alloc((void **)&A.part, (size_t)rows * (KM + 2) * 8));
     DMRG_TRY(alloc((void **)&A.chunk_member, cm.size() * 4));
     DMRG_TRY(alloc((void **)&A.chunk_begin, cb.size() * 8));
     DMRG_TRY(alloc((void **)&A.member_chunk, mc.size() * 4));
-    DMRG_TRY(alloc((void **)&A.counter, plan->nprob * 4));
+    DMRG_TRY(alloc((void **)&A.counter, (size_t)plan->nprob * CTR_STRIDE * 4));
     DMRG_TRY(alloc((void **)&A.nactive, 4));
     DMRG_TRY(alloc((void **)&A.st, plan->nprob * sizeof(DavState)));
     DMRG_TRY(alloc((void **)&A.active, plan->nprob * 4));
@@ -737,7 +530,7 @@ static dmrg_status work_alloc(dmrg_plan *plan, int kmax, int kmin, hipStream_t s
     DMRG_HIP(hipMemcpyAsync(A.chunk_begin, cb.data(), cb.size() * 8, hipMemcpyHostToDevice, s));
     DMRG_HIP(hipMemcpyAsync(A.member_chunk, mc.data(), mc.size() * 4, hipMemcpyHostToDevice, s));
     DMRG_HIP(hipMemsetAsync(A.st, 0, plan->nprob * sizeof(DavState), s));
-    DMRG_HIP(hipMemsetAsync(A.counter, 0, plan->nprob * 4, s));
+    DMRG_HIP(hipMemsetAsync(A.counter, 0, (size_t)plan->nprob * CTR_STRIDE * 4, s));
     DMRG_HIP(hipStreamSynchronize(s));
     return DMRG_OK;
 }
@@ -753,6 +546,18 @@ dmrg_status davidson_free(dmrg_plan *plan) {
     return DMRG_OK;
 }
 
+// Davidson context of a projection whose output is W(:, i-1).
+static RayArgs ray_args(const DavArgs &A, int i) {
+    RayArgs r;
+    r.V = A.V;
+    r.n = A.n;
+    r.i = i;
+    r.part = A.part;
+    r.counter = A.counter;
+    r.st = A.st;
+    return r;  // slot_begin is filled per pass by the launcher
+}
+
 // Enqueue `count` iterations starting at subspace size i; returns the next i.
 static dmrg_status enqueue_iters(dmrg_plan *plan, int slot, int i, int count, int *i_next, hipStream_t s) {
     DavidsonWork *w = plan->dav;
@@ -761,9 +566,9 @@ static dmrg_status enqueue_iters(dmrg_plan *plan, int slot, int i, int count, in
     const dim3 grid(A.nchunk), block(TPB);
     for (int it = 0; it < count; ++it) {
         const bool restart = (i == kmax);
+        // the Rayleigh step of this iteration ran in the tail of the previous projection
         set_kb(i, [&](auto kb) {
             constexpr int KB = decltype(kb)::value;
-            hipLaunchKernelGGL(k_rayleigh<KB>, grid, block, sizeof(JacobiLds), s, A, i);
             hipLaunchKernelGGL(k_ritz<KB>, grid, block, 0, s, A, i, restart ? 1 : 0);
         });
         int ie = i;
@@ -780,8 +585,9 @@ static dmrg_status enqueue_iters(dmrg_plan *plan, int slot, int i, int count, in
             hipLaunchKernelGGL(k_append<KB>, grid, block, 0, s, A, ie);
         });
         DMRG_HIP(hipGetLastError());
+        const RayArgs ray = ray_args(A, ie + 1);
         DMRG_TRY(launch_project(plan, slot, A.coef, A.V + (int64_t)ie * A.n, A.W + (int64_t)ie * A.n, s, A.active,
-                                A.dfold));
+                                A.dfold, &ray));
         i = ie + 1;
     }
     *i_next = i;
@@ -798,7 +604,8 @@ static dmrg_status run_phase(dmrg_plan *plan, int slot, const double *psi_in, do
     hipLaunchKernelGGL(k_init_vec, grid, block, 0, s, psi_in, A);
     DMRG_HIP(hipGetLastError());
     DMRG_TRY(launch_diag_fold(plan, slot, A.coef, A.dfold, s));  // coefficients are fixed for the phase
-    DMRG_TRY(launch_project(plan, slot, A.coef, A.V, A.W, s, A.active, A.dfold));
+    const RayArgs ray = ray_args(A, 1);  // W(:, 0) and the first Rayleigh step
+    DMRG_TRY(launch_project(plan, slot, A.coef, A.V, A.W, s, A.active, A.dfold, &ray));
     int i = 1;
     int done = 0;
     while (done < max_iter) {
@@ -1001,7 +808,7 @@ dmrg_status dmrg_davidson(dmrg_plan *plan, const double *coef, const dmrg_davids
             I.residual = S.rnorm;
             I.iterations = S.iters + (two_phase && o.refine ? low_iters[p] : 0);
             I.iterations_low = two_phase ? low_iters[p] : 0;
-            I.projections = S.nproj + 1 + (two_phase && o.refine ? low[p].nproj + 1 : 0);
+            I.projections = S.nproj + (two_phase && o.refine ? low[p].nproj : 0);
             I.restarts = S.restarts + (two_phase && o.refine ? low[p].restarts : 0);
             I.converged = S.converged;
             I.breakdown = S.breakdown;

@@ -85,7 +85,7 @@ struct Task {
     int32_t m, n;      // rows / columns of this tile (<= tile size)
     int32_t member;
     int32_t part0;     // first coefficient-gradient partial slot of this task
-    int32_t pad;
+    int32_t rslot;     // output-tile tasks: Rayleigh partial row (member-contiguous)
 };
 
 // ---------------------------------------------------------------- host metadata
@@ -119,6 +119,7 @@ struct Lists {  // device task lists of one pass
 
 struct PassSet {  // everything one projection direction needs in one precision
     Lists stageA, stageB;
+    int32_t *slot_begin = nullptr;  // [nprob + 1] Rayleigh partial rows of each member (stage B)
     Seg *segs = nullptr;
     DiagTerm *diags = nullptr;
     int32_t nseg = 0, ndiag = 0;
@@ -136,6 +137,20 @@ struct ConvJob {
 };
 
 struct DavidsonWork;
+struct DavState;
+
+// Davidson context for a projection that also runs the Rayleigh step of the
+// iteration it feeds: B(:, i-1) = V(:, :i)^T W(:, i-1) per member, then the
+// small eigenproblem, in the last output tile of each member.
+struct RayArgs {
+    const double *V = nullptr;  // column j at V + j * n; nullptr = plain projection
+    int64_t n = 0;
+    int i = 0;
+    double *part = nullptr;     // [rows][KM + 2] partial rows
+    const int32_t *slot_begin = nullptr;
+    int32_t *counter = nullptr; // [nprob] arrival counters
+    DavState *st = nullptr;
+};
 
 }  // namespace dmrg
 
@@ -152,9 +167,6 @@ struct dmrg_plan {
     std::vector<dmrg::Pair> pairs;
     std::vector<int32_t> pair_member;
     std::vector<dmrg::Record> records;
-    // diagonal-of-H data for the preconditioner: per member, per term, per pair
-    std::vector<dmrg::DiagTerm> hdiag_terms;      // host copy
-    std::vector<int32_t> hdiag_task_pair;         // unused placeholder
     // device pass sets: [prec slot][direction]  slot 0 = F64, slot 1 = plan precision
     dmrg::PassSet fwd[2], adj[2];
     // coefficient-gradient reduction (forward F64 pass): CSR over global terms
@@ -182,17 +194,15 @@ int tile_for(int64_t rows, int64_t cols);
 // mask: optional device [nprob]; tasks of members with mask[m] == 0 are skipped
 // dfold: optional device [n]; the diagonal terms folded by launch_diag_fold for
 // the same coefficients (replaces the per-term diagonal epilogue)
+// ray: optional Davidson context (see RayArgs), stage-B tiles only
 dmrg_status launch_project(dmrg_plan *plan, int slot, const double *coef, const double *in,
                            double *out, hipStream_t s, const int32_t *mask = nullptr,
-                           const double *dfold = nullptr);
+                           const double *dfold = nullptr, const RayArgs *ray = nullptr);
 dmrg_status launch_diag_fold(dmrg_plan *plan, int slot, const double *coef, double *out, hipStream_t s);
 dmrg_status launch_adjoint(dmrg_plan *plan, const double *coef, const double *in, double *out,
                            hipStream_t s);
 dmrg_status launch_gcoef(dmrg_plan *plan, const double *psi, const double *gbar, double *gcoef,
                          hipStream_t s);
-dmrg_status launch_convert(const double *src, void *dst, int64_t rows, int64_t cols, int prec,
-                           int offdiag, hipStream_t s);
-dmrg_status launch_extract_diag(const double *src, double *dst, int64_t d, hipStream_t s);
 dmrg_status launch_convert_jobs(const ConvJob *jobs, int njob, int prec, hipStream_t s);
 dmrg_status launch_diagonal(dmrg_plan *plan, const double *coef, double *diag, hipStream_t s);
 // davidson.hip

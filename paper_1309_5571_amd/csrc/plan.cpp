@@ -551,6 +551,13 @@ static dmrg_status upload(dmrg_plan *plan, const std::vector<T> &v, T **dst, hip
 }
 
 static dmrg_status upload_pass(dmrg_plan *plan, HostPass &hp, PassSet &ps, hipStream_t s) {
+    // member-contiguous rows for the per-tile Rayleigh partials of stage B
+    std::vector<int32_t> begin(plan->nprob + 1, 0), next;
+    for (const Task &t : hp.B) begin[t.member + 1] += 1;
+    for (int m = 0; m < plan->nprob; ++m) begin[m + 1] += begin[m];
+    next.assign(begin.begin(), begin.end() - 1);
+    for (Task &t : hp.B) t.rslot = next[t.member]++;
+    DMRG_TRY(upload(plan, begin, &ps.slot_begin, s));
     DMRG_TRY(upload(plan, hp.segs, &ps.segs, s));
     DMRG_TRY(upload(plan, hp.diags, &ps.diags, s));
     DMRG_TRY(upload(plan, hp.A, &ps.stageA.tasks, s));

@@ -24,6 +24,7 @@
 #include <algorithm>
 #include <cstdio>
 
+#include "dav_common.h"
 #include "internal.h"
 
 namespace dmrg {
@@ -161,6 +162,8 @@ __device__ __forceinline__ void load_q(typename Tr<PREC>::val_t (&v)[Tr<PREC>::K
 }
 
 constexpr int PW = 4;            // wavefronts per workgroup
+// dynamic LDS of the task kernel: PW partial tiles + one tile of output values
+constexpr size_t TASK_LDS = (size_t)(PW * 32 * 33 + 1024) * sizeof(double);
 constexpr int KC = 32;           // contraction length of one work item
 constexpr int TASK_GRID_MAX = 4096;  // persistent grid cap (blocks loop over tasks)
 
@@ -364,9 +367,11 @@ __global__ __launch_bounds__(64 * PW) void k_tasks(const Task *__restrict__ task
                                                   void *__restrict__ out, const double *__restrict__ coef,
                                                   const double *__restrict__ gbar, double *__restrict__ partials,
                                                   const int32_t *__restrict__ mask,
-                                                  const double *__restrict__ dfold) {
+                                                  const double *__restrict__ dfold, RayArgs ray) {
     typedef Tr<PREC> T;
-    __shared__ double red[PW][32][33];
+    extern __shared__ __align__(16) double smem_tasks[];
+    double(*red)[32][33] = reinterpret_cast<double(*)[32][33]>(smem_tasks);
+    double *wtile = smem_tasks + PW * 32 * 33;  // output values of the tile (Rayleigh step)
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const int r16 = lane & 15, g = lane >> 4;
@@ -488,9 +493,57 @@ __global__ __launch_bounds__(64 * PW) void k_tasks(const Task *__restrict__ task
                 else if (tk.diag_end > tk.diag_begin)
                     val += diag_sum(diags, tk.diag_begin, tk.diag_end, coef, in[tk.x_off + rr * tk.ldc + cc], rr, cc);
                 ((double *)out)[o] = val;
+                if (MODE == 1 && ray.V) wtile[e] = val;
             }
         }
-        __syncthreads();  // red is reused by the next task
+        if (MODE == 1 && ray.V) {
+            // Rayleigh step of the next Davidson iteration: this tile's share of
+            // V(:, :i)^T w, thread t on column t % i, elements strided by 64 PW / i
+            // (column jc owned by an aligned group of G lanes, combined by shuffles)
+            __syncthreads();
+            const int ii = ray.i;
+            const int G = lanes_per_column(ii);
+            const int jc = threadIdx.x / G, l = threadIdx.x % G;
+            double acc = 0.0;
+            const int cnt = tk.m * tk.n;
+            if (jc < ii) {
+                const double *Vj = ray.V + (int64_t)jc * ray.n;
+#pragma unroll 4
+                for (int e = l; e < cnt; e += G) {
+                    const int64_t o = tk.c_off + (int64_t)(tk.row0 + e / tk.n) * tk.ldc + tk.col0 + e % tk.n;
+                    acc += Vj[o] * wtile[e];
+                }
+            }
+            for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+            if (jc < ii && l == 0) {
+                ray.part[(size_t)tk.rslot * (KM + 2) + jc] = acc;
+                __threadfence();
+            }
+            const int s0 = ray.slot_begin[tk.member], s1 = ray.slot_begin[tk.member + 1];
+            if (last_arrival(ray.counter, tk.member, tk.rslot - s0, s1 - s0)) {
+                // every tile of this member is done: B(:, i-1), then its smallest Ritz pairs
+                DavState &S = ray.st[tk.member];
+                JacobiLds &L = *reinterpret_cast<JacobiLds *>(smem_tasks);
+                member_sums(ray.part, s0, s1, ii, &L.Tm[0][0], &L.A[0][0]);
+                if ((int)threadIdx.x < ii) {
+                    const int j = threadIdx.x;
+                    const double b = L.A[0][j];
+                    S.Bm[j * KM + (ii - 1)] = b;
+                    S.Bm[(ii - 1) * KM + j] = b;
+                }
+                __syncthreads();
+                if (threadIdx.x < 64) jacobi_eig_wave(S, ii, L);
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    S.lambda = S.theta[0];
+                    S.sigma = fmin(S.lambda, S.dmin);
+                    S.iters += 1;
+                    S.nproj += 1;
+                    S.nvec = ii;
+                }
+            }
+        }
+        __syncthreads();  // LDS is reused by the next task
     }
 }
 
@@ -542,27 +595,6 @@ __global__ __launch_bounds__(256) void k_diag_fold(const Task *__restrict__ task
     }
 }
 
-// FP64 block -> FP32 / BF16 copy (round to nearest even), optionally with a zero diagonal.
-__global__ __launch_bounds__(256) void k_convert(const double *__restrict__ src, void *__restrict__ dst,
-                                                 int64_t rows, int64_t cols, int prec, int offdiag) {
-    const int64_t cnt = rows * cols;
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < cnt; e += (int64_t)gridDim.x * 256) {
-        double x = src[e];
-        if (offdiag && (e / cols) == (e % cols)) x = 0.0;
-        float f = (float)x;
-        if (prec == DMRG_F32)
-            ((float *)dst)[e] = f;
-        else
-            ((uint16_t *)dst)[e] = f32_to_bf16_bits(f);
-    }
-}
-
-__global__ __launch_bounds__(256) void k_extract_diag(const double *__restrict__ src, double *__restrict__ dst,
-                                                      int64_t d) {
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < d; i += (int64_t)gridDim.x * 256)
-        dst[i] = src[i * (d + 1)];
-}
-
 // All operator-copy jobs of a plan in one launch: a block per job (grid-strided).
 __global__ __launch_bounds__(256) void k_convert_jobs(const ConvJob *__restrict__ jobs, int njob, int prec) {
     for (int j = blockIdx.x; j < njob; j += gridDim.x) {
@@ -598,28 +630,33 @@ static dim3 task_grid(int ntask) { return dim3(std::min(ntask, TASK_GRID_MAX)); 
 
 template <int PREC>
 static dmrg_status run_pass(const PassSet &ps, const double *coef, const double *in, void *tmp, double *out,
-                            hipStream_t s, const int32_t *mask, const double *dfold) {
+                            hipStream_t s, const int32_t *mask, const double *dfold, const RayArgs *ray) {
     if (ps.stageA.ntask)
-        hipLaunchKernelGGL((k_tasks<PREC, 0>), task_grid(ps.stageA.ntask), dim3(64 * PW), 0, s, ps.stageA.tasks,
-                           ps.stageA.ntask, ps.segs, ps.diags, in, (const void *)tmp, tmp, coef, nullptr, nullptr,
-                           mask, (const double *)nullptr);
-    if (ps.stageB.ntask)
-        hipLaunchKernelGGL((k_tasks<PREC, 1>), task_grid(ps.stageB.ntask), dim3(64 * PW), 0, s, ps.stageB.tasks,
+        hipLaunchKernelGGL((k_tasks<PREC, 0>), task_grid(ps.stageA.ntask), dim3(64 * PW), TASK_LDS, s,
+                           ps.stageA.tasks, ps.stageA.ntask, ps.segs, ps.diags, in, (const void *)tmp, tmp, coef,
+                           nullptr, nullptr, mask, (const double *)nullptr, RayArgs{});
+    if (ps.stageB.ntask) {
+        RayArgs ra = ray ? *ray : RayArgs{};
+        if (ray) ra.slot_begin = ps.slot_begin;
+        const size_t lds = ray ? std::max(TASK_LDS, sizeof(JacobiLds)) : TASK_LDS;
+        hipLaunchKernelGGL((k_tasks<PREC, 1>), task_grid(ps.stageB.ntask), dim3(64 * PW), lds, s, ps.stageB.tasks,
                            ps.stageB.ntask, ps.segs, ps.diags, in, (const void *)tmp, (void *)out, coef, nullptr,
-                           nullptr, mask, dfold);
+                           nullptr, mask, dfold, ra);
+    }
     DMRG_HIP(hipGetLastError());
     return DMRG_OK;
 }
 
 dmrg_status launch_project(dmrg_plan *plan, int slot, const double *coef, const double *in, double *out,
-                           hipStream_t s, const int32_t *mask, const double *dfold) {
-    if (slot == 0) return run_pass<DMRG_F64>(plan->fwd[0], coef, in, plan->d_tmp, out, s, mask, dfold);
-    if (plan->prec == DMRG_F32) return run_pass<DMRG_F32>(plan->fwd[1], coef, in, plan->d_tmp, out, s, mask, dfold);
-    return run_pass<DMRG_BF16>(plan->fwd[1], coef, in, plan->d_tmp, out, s, mask, dfold);
+                           hipStream_t s, const int32_t *mask, const double *dfold, const RayArgs *ray) {
+    if (slot == 0) return run_pass<DMRG_F64>(plan->fwd[0], coef, in, plan->d_tmp, out, s, mask, dfold, ray);
+    if (plan->prec == DMRG_F32)
+        return run_pass<DMRG_F32>(plan->fwd[1], coef, in, plan->d_tmp, out, s, mask, dfold, ray);
+    return run_pass<DMRG_BF16>(plan->fwd[1], coef, in, plan->d_tmp, out, s, mask, dfold, ray);
 }
 
 dmrg_status launch_adjoint(dmrg_plan *plan, const double *coef, const double *in, double *out, hipStream_t s) {
-    return run_pass<DMRG_F64>(plan->adj[0], coef, in, plan->d_tmp, out, s, nullptr, nullptr);
+    return run_pass<DMRG_F64>(plan->adj[0], coef, in, plan->d_tmp, out, s, nullptr, nullptr, nullptr);
 }
 
 dmrg_status launch_diag_fold(dmrg_plan *plan, int slot, const double *coef, double *out, hipStream_t s) {
@@ -634,34 +671,18 @@ dmrg_status launch_diag_fold(dmrg_plan *plan, int slot, const double *coef, doub
 dmrg_status launch_gcoef(dmrg_plan *plan, const double *psi, const double *gbar, double *gcoef, hipStream_t s) {
     const PassSet &ps = plan->fwd[0];
     if (ps.stageA.ntask)
-        hipLaunchKernelGGL((k_tasks<DMRG_F64, 0>), task_grid(ps.stageA.ntask), dim3(64 * PW), 0, s, ps.stageA.tasks,
-                           ps.stageA.ntask, ps.segs, ps.diags, psi, (const void *)plan->d_tmp, plan->d_tmp,
-                           (const double *)nullptr, nullptr, nullptr, nullptr, (const double *)nullptr);
+        hipLaunchKernelGGL((k_tasks<DMRG_F64, 0>), task_grid(ps.stageA.ntask), dim3(64 * PW), TASK_LDS, s,
+                           ps.stageA.tasks, ps.stageA.ntask, ps.segs, ps.diags, psi, (const void *)plan->d_tmp,
+                           plan->d_tmp, (const double *)nullptr, nullptr, nullptr, nullptr, (const double *)nullptr,
+                           RayArgs{});
     if (ps.stageB.ntask)
-        hipLaunchKernelGGL((k_tasks<DMRG_F64, 2>), task_grid(ps.stageB.ntask), dim3(64 * PW), 0, s, ps.stageB.tasks,
-                           ps.stageB.ntask, ps.segs, ps.diags, psi, (const void *)plan->d_tmp, nullptr,
-                           (const double *)nullptr, gbar, plan->d_partials, nullptr, (const double *)nullptr);
+        hipLaunchKernelGGL((k_tasks<DMRG_F64, 2>), task_grid(ps.stageB.ntask), dim3(64 * PW), TASK_LDS, s,
+                           ps.stageB.tasks, ps.stageB.ntask, ps.segs, ps.diags, psi, (const void *)plan->d_tmp,
+                           nullptr, (const double *)nullptr, gbar, plan->d_partials, nullptr,
+                           (const double *)nullptr, RayArgs{});
     if (plan->nterm_total)
         hipLaunchKernelGGL(k_reduce_terms, dim3(plan->nterm_total), dim3(64), 0, s, plan->d_term_ptr,
                            plan->d_term_ent, (const double *)plan->d_partials, gcoef, plan->nterm_total);
-    DMRG_HIP(hipGetLastError());
-    return DMRG_OK;
-}
-
-dmrg_status launch_convert(const double *src, void *dst, int64_t rows, int64_t cols, int prec, int offdiag,
-                           hipStream_t s) {
-    int64_t cnt = rows * cols;
-    if (cnt <= 0) return DMRG_OK;
-    int grid = (int)std::min<int64_t>((cnt + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_convert, dim3(grid), dim3(256), 0, s, src, dst, rows, cols, prec, offdiag);
-    DMRG_HIP(hipGetLastError());
-    return DMRG_OK;
-}
-
-dmrg_status launch_extract_diag(const double *src, double *dst, int64_t d, hipStream_t s) {
-    if (d <= 0) return DMRG_OK;
-    int grid = (int)std::min<int64_t>((d + 255) / 256, 1024);
-    hipLaunchKernelGGL(k_extract_diag, dim3(grid), dim3(256), 0, s, src, dst, d);
     DMRG_HIP(hipGetLastError());
     return DMRG_OK;
 }
