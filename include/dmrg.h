@@ -177,6 +177,9 @@ typedef struct {
     int32_t refine;        /* F32/BF16: 1 = continue in F64 to tol (default), 0 = stop after phase 1 */
     int32_t use_graph;     /* 1 = replay captured hipGraphs of graph_chunk iterations (default) */
     int32_t graph_chunk;   /* iterations per graph launch, default 8 */
+    int32_t eig_solver;    /* small eigenproblem of the Rayleigh step: 0 = direct solve of the
+                              arrowhead (secular equation, Jacobi only where poles nearly
+                              coincide), default; 1 = Jacobi always */
 } dmrg_davidson_opts;
 
 /* Per-member results, host. */

@@ -261,12 +261,14 @@ class Plan:
 
     def davidson(self, psi0, coef=None, tol: float = 1e-10, kmax: int = 32, kmin: int = 8, max_iter: int = 500,
                  precond_floor: float = 1e-3, prec: str = "f64", tol_lowprec: float = 0.0, refine: bool = True,
-                 use_graph: bool = True, graph_chunk: int = 8, raise_on_warning: bool = False):
-        """Ground states of every member; returns (psi, energies [host], infos, status)."""
+                 use_graph: bool = True, graph_chunk: int = 8, eig_solver: str = "arrowhead",
+                 raise_on_warning: bool = False):
+        """Ground states of every member; returns (psi, energies [host], infos, status).
+        eig_solver: "arrowhead" (direct solve of the Rayleigh step, default) or "jacobi"."""
         c = self._coef(coef)
         psi = psi0.clone()
         o = N.DavidsonOpts(tol, kmax, kmin, max_iter, precond_floor, N.PREC[prec], tol_lowprec, int(refine),
-                           int(use_graph), graph_chunk)
+                           int(use_graph), graph_chunk, {"arrowhead": 0, "jacobi": 1}[eig_solver])
         nprob = len(self.problems)
         E = (ctypes.c_double * nprob)()
         infos = (N.DavidsonInfo * nprob)()

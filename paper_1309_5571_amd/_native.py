@@ -51,7 +51,8 @@ class Problem(ctypes.Structure):
 class DavidsonOpts(ctypes.Structure):
     _fields_ = [("tol", c_double), ("kmax", c_int32), ("kmin", c_int32), ("max_iter", c_int32),
                 ("precond_floor", c_double), ("prec", c_int32), ("tol_lowprec", c_double),
-                ("refine", c_int32), ("use_graph", c_int32), ("graph_chunk", c_int32)]
+                ("refine", c_int32), ("use_graph", c_int32), ("graph_chunk", c_int32),
+                ("eig_solver", c_int32)]
 
 
 class DavidsonInfo(ctypes.Structure):

@@ -1,36 +1,56 @@
 // Device-resident Davidson iteration (Alg. 3) for one or many superblocks.
 //
 // Every member of a plan runs in lock step: all members share the subspace
-// size i of an iteration, a member that has converged is masked out, so the
+// size i of an iteration, a member that has stopped is masked out, so the
 // host knows the kernel sequence of each iteration in advance and can replay
 // captured hipGraphs of several iterations.  Per iteration:
 //
-//   projection  W(:, i-1) = H V(:, i-1)                  (line 2), whose output
-//               tiles also form B(:, i-1) = V^T W(:, i-1) (line 3); the last
-//               tile of a member solves the small eigenproblem (line 4) by a
-//               warm-started parallel Jacobi in one workgroup
-//   k_ritz      x = V y, r = W y - lambda x, ||r||   (lines 5-7)
-//               t = r / (D - sigma) (line 10, shifted diagonal preconditioner)
-//               s = V^T t (line 12, first pass) -- all in one sweep over V, W
+//   projection  W(:, i-1) = H V(:, i-1) (line 2); every output tile also
+//               writes its partial row of V(:, :i)^T W(:, i-1)
+//   k_rayleigh  one workgroup per member: B(:, i-1) from the tile rows
+//               (line 3), then the small eigenproblem (line 4) by a
+//               warm-started parallel Jacobi in one wavefront
+//   k_ritz      x = V y, r = W y - lambda x, ||r|| (lines 5-7),
+//               t = r / (D - sigma) (line 10, shifted diagonal preconditioner),
+//               s = V^T t (line 12, first pass): one sweep over V and W
 //   k_restart   (when i = kmax) V <- V Y(:, :kmin), W <- W Y(:, :kmin), s = V^T t
-//   k_orth      t <- t - V s (line 13), ||t||, and V^T t for the DGKS pass
-//   k_append    V(:, i) = (t - V s2) / ||.||  when a second pass is needed (line 14)
+//   k_orth      stop test on ||r||, t <- t - V s (line 13); V(:, i) = t / ||t||
+//               (line 14) unless the norms call for a second pass, then V^T t
+//   k_append    second Gram-Schmidt pass: V(:, i) = (t - V s2) / ||.||
 //
-// Reductions over the vector length are split into fixed chunks; each block
-// writes its partial sums, and the last block of a member (atomic arrival
-// counter, reset by that block) sums the partials in chunk order, so results
-// are independent of scheduling and identical between eager and graph runs.
+// Reductions over the vector length never wait inside a kernel: each block
+// writes one partial row, and EVERY block of the next kernel sums the rows of
+// its member itself, in row order.  Results are therefore independent of
+// scheduling, identical in all blocks (so every block takes the same stop and
+// orthogonalization decisions), and identical between eager and graph runs.
+// One block per member (the first chunk's) records the decisions in the
+// member's state for the kernels that follow.  No kernel needs a device-scope
+// fence: on gfx950 such a fence writes back and invalidates the L2 of the
+// XCD, which would stall every other workgroup reading operator blocks.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <map>
 #include <tuple>
 
-#include "dav_common.h"
 #include "gemv.h"
 #include "internal.h"
 
 namespace dmrg {
+
+constexpr int TPB = GEMV_THREADS;
+constexpr int PR_R = KM;      // partial-row column of ||r||^2
+constexpr int PR_T = KM + 1;  // partial-row column of ||t||^2
+
+// The Rayleigh matrix B = V^T H V itself is not stored: after every Rayleigh
+// step Y^T B Y = diag(theta) up to the Jacobi threshold, which is all the next
+// step needs (it only adds a row and column to B).
+struct DavState {
+    double Y[KM * KM];   // eigenvectors of B (column c = Y[r * KM + c]), ascending
+    double theta[KM];    // Ritz values, ascending
+    double lambda, sigma, dmin, rnorm, tn0, scale, tol, floor_;
+    int32_t converged, breakdown, iters, nproj, restarts, dgks, nvec, max_iter, bad_start;
+};
 
 // Kernel-argument view of the Davidson workspace (plain pointers only).
 struct DavArgs {
@@ -38,32 +58,39 @@ struct DavArgs {
     int nprob = 0;
     int nchunk = 0;
     double *V = nullptr, *W = nullptr, *T = nullptr, *D = nullptr, *coef = nullptr;
-    double *dfold = nullptr;         // [n] folded diagonal terms of the current phase's pass
-    double *part = nullptr;          // [nchunk][KM + 2]
+    double *dfold = nullptr;          // [n] folded diagonal terms of the current phase's pass
+    // partial rows, stored column-major ([KM + 2][rows]) so that sums over rows
+    // read contiguous memory
+    double *pa = nullptr;             // rows of k_init_norm and k_ritz, one per chunk
+    double *pb = nullptr;             // rows of k_restart
+    double *pc = nullptr;             // rows of k_orth (second pass)
+    double *ptile = nullptr;          // Rayleigh rows of the projection, one per output tile
+    int64_t tile_ld = 0;              // rows of ptile
     int32_t *chunk_member = nullptr;
-    int64_t *chunk_begin = nullptr;  // [nchunk + 1] element ranges
-    int32_t *member_chunk = nullptr; // [nprob + 1] chunk ranges
-    int32_t *counter = nullptr;      // [nprob] arrival counters
-    int32_t *nactive = nullptr;      // [1] members still iterating
-    int32_t *active = nullptr;       // [nprob] 1 while the member iterates
-    DavState *st = nullptr;          // [nprob]
+    int64_t *chunk_begin = nullptr;   // [nchunk + 1] element ranges
+    int32_t *member_chunk = nullptr;  // [nprob + 1] chunk ranges
+    int32_t *nactive = nullptr;       // [1] members still iterating
+    int32_t *active = nullptr;        // [nprob] 1 while the member iterates
+    DavState *st = nullptr;           // [nprob]
 };
 
 struct DavidsonWork {
     DavArgs a;
     int kmax = 0, kmin = 0;
+    int eig_solver = 0;
     int32_t *h_nactive = nullptr;  // pinned
-    std::map<std::tuple<int, int, int, int>, hipGraphExec_t> graphs;
+    std::map<std::tuple<int, int, int, int, int>, hipGraphExec_t> graphs;
     std::vector<void *> owned;
 };
 
 // ------------------------------------------------------------------ helpers
 
-// Element range and member of chunk c.  A single-member plan needs no lookup:
-// its chunks are the consecutive TPB-element ranges.
+// Element range and member of chunk c, and the chunk range of that member.  A
+// single-member plan needs no lookup: its chunks are consecutive TPB-element ranges.
 struct Chunk {
     int member;
     int64_t e0, e1;
+    int c0, c1;
 };
 __device__ __forceinline__ Chunk chunk_of(const DavArgs &w, int c) {
     Chunk k;
@@ -71,93 +98,543 @@ __device__ __forceinline__ Chunk chunk_of(const DavArgs &w, int c) {
         k.member = 0;
         k.e0 = (int64_t)c * TPB;
         k.e1 = min(w.n, k.e0 + TPB);
+        k.c0 = 0;
+        k.c1 = w.nchunk;
     } else {
         k.member = w.chunk_member[c];
         k.e0 = w.chunk_begin[c];
         k.e1 = w.chunk_begin[c + 1];
+        k.c0 = w.member_chunk[k.member];
+        k.c1 = w.member_chunk[k.member + 1];
     }
     return k;
 }
 
+// Lanes per column for all-column reductions: the largest power of two G <= 64
+// with G * ncols <= TPB, so each column is owned by an aligned group of G lanes
+// inside one wavefront and combined with shuffles.
+static __device__ __forceinline__ int lanes_per_column(int ncols) {
+    int G = 64;
+    while (G > 1 && G * ncols > TPB) G >>= 1;
+    return G;
+}
+
+// out[q] = sum of partial rows [r0, r1) in column col(q), q < nq, where
+// col(q) = q for q < i and KM + (q - i) beyond (the norm columns); element
+// (r, col) at part[col * ld + r].  Each lane keeps 4 running sums (rows
+// interleaved), combined in a fixed order; all threads must call; out is shared.
+static __device__ void sum_rows(const double *__restrict__ part, int64_t ld, int r0, int r1, int i, int nq,
+                                double *out) {
+    const int G = lanes_per_column(nq);
+    const int q = threadIdx.x / G, l = threadIdx.x % G;
+    double v = 0.0;
+    if (q < nq) {
+        const double *col = part + (int64_t)(q < i ? q : KM + (q - i)) * ld;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int r = r0 + l;
+        for (; r + 7 * G < r1; r += 8 * G) {
+            const double x0 = col[r], x1 = col[r + G], x2 = col[r + 2 * G], x3 = col[r + 3 * G];
+            const double x4 = col[r + 4 * G], x5 = col[r + 5 * G], x6 = col[r + 6 * G], x7 = col[r + 7 * G];
+            a0 += x0 + x4;
+            a1 += x1 + x5;
+            a2 += x2 + x6;
+            a3 += x3 + x7;
+        }
+        for (int k = 0; r < r1; r += G, ++k) {
+            const double x = col[r];
+            if (k == 0) a0 += x;
+            else if (k == 1) a1 += x;
+            else if (k == 2) a2 += x;
+            else a3 += x;
+        }
+        v = (a0 + a1) + (a2 + a3);
+    }
+    for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (q < nq && l == 0) out[q] = v;
+    __syncthreads();
+}
+
+static __device__ double block_min(double v, double *lds) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double m = lds[0];
+#pragma unroll
+    for (int q = 1; q < TPB / 64; ++q) m = fmin(m, lds[q]);
+    __syncthreads();
+    return m;
+}
+
+static __device__ __forceinline__ void deactivate(const DavArgs &w, int member) {
+    w.active[member] = 0;
+    atomicSub(w.nactive, 1);
+}
+
+// Stop test on the residual norm: 0 go on, 1 converged, 2 iteration limit, 3 non-finite.
+static __device__ __forceinline__ int stop_code(const DavState &S, double rr) {
+    const double rn = sqrt(rr);
+    if (!(rn == rn) || isinf(rn)) return 3;
+    if (rn <= S.tol) return 1;
+    if (S.iters >= S.max_iter) return 2;
+    return 0;
+}
+
 // ------------------------------------------------------------------ init kernels
 
-// ||psi||^2 per member; last block stores the scale, flags zero / non-finite starts.
+// partial rows: ||psi||^2 (column 0) and min D (column 1) of each chunk
 __global__ __launch_bounds__(TPB) void k_init_norm(const double *__restrict__ psi, DavArgs w) {
-    __shared__ double lds[4 * 2];
-    const int c = blockIdx.x;
-    const Chunk ck = chunk_of(w, c);
-    const int member = ck.member;
-    double v[1] = {0.0};
-    for (int64_t e = ck.e0 + threadIdx.x; e < ck.e1; e += TPB) v[0] += psi[e] * psi[e];
+    __shared__ double lds[4];
+    const Chunk ck = chunk_of(w, blockIdx.x);
+    double ss = 0.0, mn = INFINITY;
+    for (int64_t e = ck.e0 + threadIdx.x; e < ck.e1; e += TPB) {
+        ss += psi[e] * psi[e];
+        mn = fmin(mn, w.D[e]);
+    }
+    double v[1] = {ss};
     block_reduce<1>(v, 1, lds);
-    if (threadIdx.x == 0) w.part[(size_t)c * (KM + 2)] = v[0];
-    const int c0 = w.nprob == 1 ? 0 : w.member_chunk[member];
-    const int c1 = w.nprob == 1 ? w.nchunk : w.member_chunk[member + 1];
-    if (!last_arrival(w.counter, member, c - c0, c1 - c0)) return;
-    double s = member_sum(w.part, c0, c1, 0, lds);
+    mn = block_min(mn, lds);
     if (threadIdx.x == 0) {
-        DavState &S = w.st[member];
-        if (!(s > 0.0) || !isfinite(s)) {
-            S.bad_start = 1;
-            w.active[member] = 0;
-            S.scale = 0.0;
-            atomicSub(w.nactive, 1);
-        } else {
-            S.scale = 1.0 / sqrt(s);
-        }
+        w.pa[blockIdx.x] = v[0];
+        w.pa[(int64_t)w.nchunk + blockIdx.x] = mn;
     }
 }
 
-// V(:,0) = psi * scale; also the diagonal's minimum per member.
+// V(:, 0) = psi / ||psi|| per member; flags zero or non-finite starts.
 __global__ __launch_bounds__(TPB) void k_init_vec(const double *__restrict__ psi, DavArgs w) {
-    __shared__ double lds[4 * 2];
-    __shared__ double red[TPB];
+    __shared__ double lds[4];
+    __shared__ double sums[1];
     const int c = blockIdx.x;
     const Chunk ck = chunk_of(w, c);
-    const int member = ck.member;
-    const double sc = w.st[member].scale;
+    sum_rows(w.pa, w.nchunk, ck.c0, ck.c1, 1, 1, sums);
     double mn = INFINITY;
-    for (int64_t e = ck.e0 + threadIdx.x; e < ck.e1; e += TPB) {
-        w.V[e] = psi[e] * sc;
-        mn = fmin(mn, w.D[e]);
+    for (int r = ck.c0 + (int)threadIdx.x; r < ck.c1; r += TPB) mn = fmin(mn, w.pa[(int64_t)w.nchunk + r]);
+    mn = block_min(mn, lds);
+    const double s = sums[0];
+    const bool bad = !(s > 0.0) || !isfinite(s);
+    if (c == ck.c0 && threadIdx.x == 0) {
+        DavState &S = w.st[ck.member];
+        S.dmin = mn;
+        S.scale = bad ? 0.0 : 1.0 / sqrt(s);
+        if (bad) {
+            S.bad_start = 1;
+            deactivate(w, ck.member);
+        }
     }
-    red[threadIdx.x] = mn;
-    __syncthreads();
-    for (int off = TPB / 2; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + off]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) w.part[(size_t)c * (KM + 2)] = red[0];
-    const int c0 = w.nprob == 1 ? 0 : w.member_chunk[member];
-    const int c1 = w.nprob == 1 ? w.nchunk : w.member_chunk[member + 1];
-    if (!last_arrival(w.counter, member, c - c0, c1 - c0)) return;
-    mn = INFINITY;
-    for (int q = c0 + (int)threadIdx.x; q < c1; q += TPB) mn = fmin(mn, w.part[(size_t)q * (KM + 2)]);
-    red[threadIdx.x] = mn;
-    __syncthreads();
-    for (int off = TPB / 2; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + off]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) w.st[member].dmin = red[0];
-    (void)lds;
+    if (bad) return;
+    const double sc = 1.0 / sqrt(s);
+    for (int64_t e = ck.e0 + threadIdx.x; e < ck.e1; e += TPB) w.V[e] = psi[e] * sc;
 }
 
 // ------------------------------------------------------------------ small eigenproblem
 
+// Smallest-first eigen-decomposition of the member's Rayleigh matrix B[:n, :n].
+// Warm start: in the basis of the previous Ritz vectors (extended by e_n) the
+// matrix is the arrowhead A = [[diag(d), z], [z^T, beta]] with d the previous
+// Ritz values (ascending), z = Y^T b and b, beta the new column of B; its
+// leading block is diagonal up to the previous step's threshold
+// tol = 1e-15 ||A||_F, which is dropped.
+//
+// Main path (one wavefront): the arrowhead is solved directly.  Border entries
+// |z_j| <= tol are dropped as well, which makes (d_j, e_j) an eigenpair
+// (deflation).  The other eigenvalues are the roots of the secular equation
+//     f(x) = beta - x - sum_j z_j^2 / (d_j - x) = 0,
+// exactly one in each gap of the remaining poles and one beyond each end; lane
+// i finds root i as pole + offset (so that differences from the poles keep
+// full relative accuracy) by Newton steps on x f(x) relative to the nearer
+// pole (smooth there), kept inside a shrinking bracket with geometric
+// bisection.  Eigenvectors are (z'_j / (d_j - x))_j extended by -1, normalized,
+// with the border z' recomputed from the roots and poles (Loewner's formula
+// for an arrowhead matrix: z'_j^2 = -prod_i (d_j - x_i) / prod_{l != j} (d_j - d_l)),
+// which keeps them orthogonal to working precision (Gu and Eisenstat).
+//
+// Fallback (two remaining poles closer than 1e3 tol, or a root not found in
+// 100 steps): cyclic Jacobi in parallel (round-robin) order on the arrowhead,
+// rotations with |a_pq| <= tol skipped, until a sweep without rotations.  A
+// step applies all of its disjoint rotations at once, block by block:
+// A[{p_k,q_k}, {p_l,q_l}] <- R_k A[..] R_l^T, and Vv[:, {p_k,q_k}] <- Vv[..] R_k^T.
+struct EigLds {
+    double A[KM][KM + 1];   // the arrowhead; on the main path then the eigenvector matrix U
+    double Vv[KM][KM + 1];  // previous eigenvectors extended by e_n
+    double c[KM / 2], s[KM / 2];
+    double d[KM], z[KM];               // poles and border
+    double dk[KM], zk[KM], zh[KM];     // remaining poles, their border, recomputed border
+    double org[KM + 1], tau[KM + 1];   // root i = org[i] + tau[i]
+    double val[KM + 1];                // eigenvalue of each entry (roots, then deflated poles)
+    int kidx[KM], didx[KM];            // original index of each remaining / deflated pole
+    int col[KM + 1], inv[KM + 1];      // ascending position of each entry, and its inverse
+    double tol;
+    int k, path;
+};
+
+static __device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// round-robin pairing: pair k of a step (indices < n2; index n is a dummy for odd n)
+static __device__ __forceinline__ void rr_pair(int k, int step, int n2, int &p, int &q) {
+    const int h = n2 - 1;
+    int a = k - 1 + step;  // in [-1, 2h)
+    a = (a >= h) ? a - h : a;
+    p = (k == 0) ? 0 : a + 1;
+    int b = h - 1 - k + step;  // in [0, 2h)
+    b = (b >= h) ? b - h : b;
+    q = b + 1;
+}
+
+// One wavefront: the arrowhead's diagonal block and the extended eigenvectors.
+// Independent of the new column, so it overlaps the sums that produce it.
+static __device__ void eig_load(const DavState &S, int n, EigLds &L) {
+    const int lane = threadIdx.x & 63;
+    const int m = n - 1;
+    for (int e = lane; e < n * n; e += 64) {
+        const int r = e / n, c = e - r * n;
+        L.A[r][c] = (r == c && r < m) ? S.theta[r] : 0.0;
+        L.Vv[r][c] = (r < m && c < m) ? S.Y[r * KM + c] : (r == c ? 1.0 : 0.0);
+    }
+    for (int j = lane; j < m; j += 64) L.d[j] = S.theta[j];
+}
+
+// One wavefront: border z = Y^T b and the corner, and the threshold.
+static __device__ void eig_border(int n, const double *bcol, EigLds &L) {
+    const int lane = threadIdx.x & 63;
+    const int m = n - 1;
+    wave_sync();
+    for (int r = lane; r < m; r += 64) {
+        double g = 0.0;
+        for (int k = 0; k < m; ++k) g += L.Vv[k][r] * bcol[k];
+        L.A[r][m] = g;
+        L.A[m][r] = g;
+        L.z[r] = g;
+    }
+    if (lane == 0) L.A[m][m] = bcol[m];
+    wave_sync();
+    double fro = 0.0;
+    for (int r = 0; r < n; ++r)
+        for (int c = lane; c < n; c += 64) fro += L.A[r][c] * L.A[r][c];
+    fro = wave_reduce(fro);
+    if (lane == 0) L.tol = 1e-15 * sqrt(fro);
+    wave_sync();
+}
+
+// f(o + t) and its derivative, with the pole differences taken relative to o
+static __device__ __forceinline__ double secular_f(const EigLds &L, int k, double beta, double o, double t,
+                                                   double &fp) {
+    double fv = (beta - o) - t;
+    fp = -1.0;
+    for (int j = 0; j < k; ++j) {
+        const double dl = (L.dk[j] - o) - t;
+        const double q = L.zk[j] / dl;
+        fv -= L.zk[j] * q;
+        fp -= q * q;
+    }
+    return fv;
+}
+
+// One wavefront.  Returns 1 when the fallback is needed (then L.A, L.Vv are
+// untouched); else leaves U in L.A and the entries' values and order in L.val,
+// L.col, L.inv.
+static __device__ int eig_secular(int n, EigLds &L) {
+    const int lane = threadIdx.x & 63;
+    const int m = n - 1;
+    const double tol = L.tol, beta = L.A[m][m];
+    constexpr double EPS = 1.1102230246251565e-16;  // 2^-53
+    // deflation: poles with |z_j| <= tol leave the secular equation
+    const bool live = lane < m && fabs(L.z[lane]) > tol;
+    const bool dead = lane < m && !live;
+    const uint64_t lm = __ballot(live), dm = __ballot(dead);
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int k = __popcll(lm);
+    if (live) {
+        const int r = __popcll(lm & below);
+        L.dk[r] = L.d[lane];
+        L.zk[r] = L.z[lane];
+        L.kidx[r] = lane;
+    }
+    if (dead) L.didx[__popcll(dm & below)] = lane;
+    wave_sync();
+    bool close = false;
+    if (lane + 1 < k) close = L.dk[lane + 1] - L.dk[lane] <= 1e3 * tol;
+    if (__any(close)) return 1;
+    // roots: lane i <= k
+    double zn = (lane < k) ? L.zk[lane] * L.zk[lane] : 0.0;
+    zn = sqrt(wave_reduce(zn));
+    bool fail = false;
+    if (lane <= k) {
+        const int i = lane;
+        double o = beta, t = 0.0;
+        if (k > 0) {
+            double a, b;
+            if (i == 0) {
+                o = L.dk[0];
+                a = (fmin(L.dk[0], beta) - zn - tol) - o;
+                b = 0.0;
+            } else if (i == k) {
+                o = L.dk[k - 1];
+                a = 0.0;
+                b = (fmax(L.dk[k - 1], beta) + zn + tol) - o;
+            } else {
+                const double mid = 0.5 * (L.dk[i - 1] + L.dk[i]);
+                double fp;
+                if (secular_f(L, k, beta, 0.0, mid, fp) >= 0.0) {  // root between mid and the upper pole
+                    o = L.dk[i];
+                    a = mid - o;
+                    b = 0.0;
+                } else {
+                    o = L.dk[i - 1];
+                    a = 0.0;
+                    b = mid - o;
+                }
+            }
+            t = 0.5 * (a + b);
+            bool done = false;
+            for (int it = 0; it < 100 && !done; ++it) {
+                double fp;
+                const double fv = secular_f(L, k, beta, o, t, fp);
+                if (fv == 0.0) {
+                    done = true;
+                    break;
+                }
+                if (fv > 0.0)
+                    a = t;
+                else
+                    b = t;
+                const double den = fv + t * fp;  // Newton on t f(t), smooth at the pole o
+                double tn = (den != 0.0) ? t - t * fv / den : 0.5 * (a + b);
+                if (fabs(tn - t) <= 2.0 * EPS * fabs(t)) {
+                    t = tn;
+                    done = true;
+                    break;
+                }
+                if (!(tn > a && tn < b)) {
+                    if (a >= 0.0 && b > 0.0 && b > 4.0 * fmax(a, 1e-300 * b))
+                        tn = sqrt(fmax(a, 1e-300 * b) * b);
+                    else if (b <= 0.0 && a < 0.0 && -a > 4.0 * fmax(-b, -1e-300 * a))
+                        tn = -sqrt(fmax(-b, -1e-300 * a) * -a);
+                    else
+                        tn = 0.5 * (a + b);
+                }
+                if (b - a <= 2.0 * EPS * fmax(fabs(a), fabs(b))) {
+                    t = tn;
+                    done = true;
+                    break;
+                }
+                t = tn;
+            }
+            fail = !done || !isfinite(t);
+        }
+        L.org[i] = o;
+        L.tau[i] = t;
+    }
+    if (__any(fail)) return 1;
+    wave_sync();
+    // recomputed border (pairs each pole difference with a root difference)
+    if (lane < k) {
+        const int j = lane;
+        const double dj = L.dk[j];
+        double prod = -((dj - L.org[j]) - L.tau[j]) * ((dj - L.org[j + 1]) - L.tau[j + 1]);
+        for (int l = 0; l < j; ++l) prod *= ((dj - L.org[l]) - L.tau[l]) / (dj - L.dk[l]);
+        for (int l = j + 1; l < k; ++l) prod *= ((dj - L.org[l + 1]) - L.tau[l + 1]) / (dj - L.dk[l]);
+        L.zh[j] = copysign(sqrt(fmax(prod, 0.0)), L.zk[j]);
+    }
+    // entries: roots 0..k, then the deflated poles; ascending order, ties by entry
+    for (int e = lane; e < n; e += 64) L.val[e] = (e <= k) ? L.org[e] + L.tau[e] : L.d[L.didx[e - k - 1]];
+    wave_sync();
+    for (int e = lane; e < n; e += 64) {
+        const double v = L.val[e];
+        int rank = 0;
+        for (int f = 0; f < n; ++f) {
+            const double w = L.val[f];
+            rank += (w < v) || (w == v && f < e);
+        }
+        L.col[e] = rank;
+        L.inv[rank] = e;
+    }
+    for (int e = lane; e < n * n; e += 64) L.A[e / n][e % n] = 0.0;
+    wave_sync();
+    // eigenvector columns of the arrowhead
+    for (int e = lane; e < n; e += 64) {
+        const int c = L.col[e];
+        if (e <= k) {
+            const double o = L.org[e], t = L.tau[e];
+            double nrm = 1.0;
+            for (int j = 0; j < k; ++j) {
+                const double u = L.zh[j] / ((L.dk[j] - o) - t);
+                nrm += u * u;
+            }
+            const double sc = 1.0 / sqrt(nrm);
+            for (int j = 0; j < k; ++j) L.A[L.kidx[j]][c] = sc * (L.zh[j] / ((L.dk[j] - o) - t));
+            L.A[m][c] = -sc;
+        } else {
+            L.A[L.didx[e - k - 1]][c] = 1.0;
+        }
+    }
+    if (lane == 0) L.k = k;
+    return 0;
+}
+
+// All threads: Y = Vv U and the sorted Ritz values (main path).
+static __device__ void eig_assemble(DavState &S, int n, EigLds &L) {
+    for (int e = threadIdx.x; e < n * n; e += TPB) {
+        const int r = e / n, c = e - r * n;
+        double acc = 0.0;
+        for (int q = 0; q < n; ++q) acc += L.Vv[r][q] * L.A[q][c];
+        S.Y[r * KM + c] = acc;
+    }
+    for (int c = threadIdx.x; c < n; c += TPB) S.theta[c] = L.val[L.inv[c]];
+    if (threadIdx.x == 0) {
+        S.lambda = L.val[L.inv[0]];
+        S.sigma = fmin(S.lambda, S.dmin);
+        S.iters += 1;
+        S.nproj += 1;
+        S.nvec = n;
+    }
+}
+
+// One wavefront: the Jacobi fallback on the arrowhead in L.A, L.Vv; writes the state.
+static __device__ void eig_jacobi(DavState &S, int n, EigLds &L) {
+    const int lane = threadIdx.x & 63;
+    const double tol = L.tol;
+    const int n2 = (n + 1) & ~1;
+    const int np = n2 / 2;
+    // lanes as an 8 x 8 grid: lane (ga, gb) updates the blocks (k, l) with
+    // k = ga mod 8, l = gb mod 8, and the rows j = gb mod 8 of Vv's column pair k
+    const int ga = lane >> 3, gb = lane & 7;
+    for (int sweep = 0; sweep < 30; ++sweep) {
+        int rotated = 0;
+        for (int step = 0; step < n2 - 1; ++step) {
+            bool any_rot = false;
+            if (lane < np) {
+                int p, q;
+                rr_pair(lane, step, n2, p, q);
+                // all three loads in flight together (indices < n2 <= KM stay inside the arrays)
+                const double apq = L.A[p][q], app = L.A[p][p], aqq = L.A[q][q];
+                double cc = 1.0, ss = 0.0;
+                if (p < n && q < n && fabs(apq) > tol) {
+                    // tan of the annihilating angle: t = sgn(d) e / (|d| + sqrt(d^2 + e^2)),
+                    // d = a_qq - a_pp, e = 2 a_pq; then c = u / sqrt(u^2 + e^2), s = t c
+                    const double d = aqq - app, e2 = 2.0 * apq;
+                    const double u = fabs(d) + sqrt(d * d + e2 * e2);
+                    const double wr = rsqrt(u * u + e2 * e2);
+                    cc = u * wr;
+                    ss = (d >= 0.0 ? e2 : -e2) * wr;
+                    rotated = 1;
+                    any_rot = true;
+                }
+                L.c[lane] = cc;
+                L.s[lane] = ss;
+            }
+            if (!__any(any_rot)) continue;  // nothing to apply in this step
+            wave_sync();
+            for (int k = ga; k < np; k += 8) {
+                int pk, qk;
+                rr_pair(k, step, n2, pk, qk);
+                const bool vk = pk < n && qk < n;
+                for (int l = gb; l < np; l += 8) {
+                    int pl, ql;
+                    rr_pair(l, step, n2, pl, ql);
+                    const bool vl = pl < n && ql < n;
+                    // one batch of loads: both rotations and the 2 x 2 block
+                    const double ck = L.c[k], sk = L.s[k], cl = L.c[l], sl = L.s[l];
+                    const double a = L.A[pk][pl], b = L.A[pk][ql], c = L.A[qk][pl], d = L.A[qk][ql];
+                    if (sk == 0.0 && sl == 0.0) continue;
+                    // rows (R_k), then columns (R_l^T); with a dummy index one side is the identity
+                    const double ra = ck * a - sk * c, rb = ck * b - sk * d;
+                    const double rc = sk * a + ck * c, rd = sk * b + ck * d;
+                    if (vk && vl) {
+                        L.A[pk][pl] = cl * ra - sl * rb;
+                        L.A[pk][ql] = sl * ra + cl * rb;
+                        L.A[qk][pl] = cl * rc - sl * rd;
+                        L.A[qk][ql] = sl * rc + cl * rd;
+                    } else if (vk) {  // column pair holds the dummy index: one valid column
+                        if (pl < n) {
+                            L.A[pk][pl] = ra;
+                            L.A[qk][pl] = rc;
+                        } else {
+                            L.A[pk][ql] = rb;
+                            L.A[qk][ql] = rd;
+                        }
+                    } else if (vl) {  // row pair holds the dummy index: one valid row
+                        if (pk < n) {
+                            L.A[pk][pl] = cl * a - sl * b;
+                            L.A[pk][ql] = sl * a + cl * b;
+                        } else {
+                            L.A[qk][pl] = cl * c - sl * d;
+                            L.A[qk][ql] = sl * c + cl * d;
+                        }
+                    }
+                }
+                const double ck = L.c[k], sk = L.s[k];
+                if (sk != 0.0) {
+                    for (int j = gb; j < n; j += 8) {
+                        const double vp = L.Vv[j][pk], vq = L.Vv[j][qk];
+                        L.Vv[j][pk] = ck * vp - sk * vq;
+                        L.Vv[j][qk] = sk * vp + ck * vq;
+                    }
+                }
+            }
+            wave_sync();
+        }
+        if (!__any(rotated)) break;
+    }
+    // ascending order (stable rank); c[] and s[] are free now: reuse as scratch
+    int *order = reinterpret_cast<int *>(&L.c[0]);
+    for (int a = lane; a < n; a += 64) {
+        const double da = L.A[a][a];
+        int rank = 0;
+        for (int b = 0; b < n; ++b) {
+            const double db = L.A[b][b];
+            rank += (db < da) || (db == da && b < a);
+        }
+        order[rank] = a;
+    }
+    wave_sync();
+    for (int e = lane; e < n * n; e += 64) {
+        const int r = e / n, c = e - r * n;
+        S.Y[r * KM + c] = L.Vv[r][order[c]];
+    }
+    for (int c = lane; c < n; c += 64) S.theta[c] = L.A[order[c]][order[c]];
+    if (lane == 0) {
+        S.lambda = L.A[order[0]][order[0]];
+        S.sigma = fmin(S.lambda, S.dmin);
+        S.iters += 1;
+        S.nproj += 1;
+        S.nvec = n;
+    }
+}
+
 // ------------------------------------------------------------------ iteration kernels
 
-// x = V y, r = W y - lambda x, t = r / (D - sigma); partials: ||r||^2, ||t||^2, V^T t.
+// Rayleigh step, one workgroup per member: B(:, i-1) = sum of the member's
+// tile rows, then the Ritz pairs of B[:i, :i].
+__global__ __launch_bounds__(TPB) void k_rayleigh(DavArgs w, const int32_t *__restrict__ slot_begin, int i,
+                                                  int jacobi_only) {
+    __shared__ EigLds L;
+    __shared__ double bcol[KM];
+    const int member = blockIdx.x;
+    if (!w.active[member]) return;
+    DavState &S = w.st[member];
+    if (threadIdx.x < 64) eig_load(S, i, L);  // independent of the sums: overlaps them
+    sum_rows(w.ptile, w.tile_ld, slot_begin[member], slot_begin[member + 1], i, i, bcol);
+    if (threadIdx.x < 64) {
+        eig_border(i, bcol, L);
+        const int fb = jacobi_only ? 1 : eig_secular(i, L);
+        if (fb) eig_jacobi(S, i, L);
+        if (threadIdx.x == 0) L.path = fb;
+    }
+    __syncthreads();
+    if (!L.path) eig_assemble(S, i, L);
+}
+
+// x = V y, r = W y - lambda x, t = r / (D - sigma); partial row: V^T t, ||r||^2, ||t||^2.
 template <int KB>
 __global__ __launch_bounds__(TPB) void k_ritz(DavArgs w, int i, int restart) {
     __shared__ double lds[4 * (KB + 2)];
-    __shared__ double scratch[TPB];
-    __shared__ double sums[KB + 2];
     const int c = blockIdx.x;
     const Chunk ck = chunk_of(w, c);
-    const int member = ck.member;
-    const DavState &S = w.st[member];
-    const int act = w.active[member];
+    if (!w.active[ck.member]) return;
+    const DavState &S = w.st[ck.member];
     const int64_t n = w.n;
     double y[KB];
 #pragma unroll
@@ -184,7 +661,7 @@ __global__ __launch_bounds__(TPB) void k_ritz(DavArgs w, int i, int restart) {
         double den = w.D[e] - sig;
         if (fabs(den) < fl) den = (den < 0.0) ? -fl : fl;
         const double t = r / den;
-        if (act) w.T[e] = t;
+        w.T[e] = t;
         acc[KB] += r * r;
         acc[KB + 1] += t * t;
         if (!restart) {
@@ -192,72 +669,43 @@ __global__ __launch_bounds__(TPB) void k_ritz(DavArgs w, int i, int restart) {
             for (int j = 0; j < KB; ++j) acc[j] += v[j] * t;
         }
     }
-    if (!act) return;
     block_reduce<KB + 2>(acc, KB + 2, lds);
-    if (threadIdx.x == 0)
-        for (int j = 0; j < KB + 2; ++j) w.part[(size_t)c * (KM + 2) + j] = acc[j];
-    // note: columns KB, KB+1 of the partial row hold ||r||^2 and ||t||^2
-    const int c0 = w.nprob == 1 ? 0 : w.member_chunk[member];
-    const int c1 = w.nprob == 1 ? w.nchunk : w.member_chunk[member + 1];
-    if (!last_arrival(w.counter, member, c - c0, c1 - c0)) return;
-    DavState &Sm = w.st[member];
-    member_sums(w.part, c0, c1, KB + 2, scratch, sums);
-    const double rr = sums[KB];
-    const double tt = sums[KB + 1];
-    double ss = 0.0;
-    if (!restart) {
-        if ((int)threadIdx.x < i) Sm.s[threadIdx.x] = sums[threadIdx.x];
-        for (int j = 0; j < i; ++j) ss += sums[j] * sums[j];
-    }
     if (threadIdx.x == 0) {
-        Sm.rnorm = sqrt(rr);
-        Sm.tn0 = sqrt(tt);
-        if (!(Sm.rnorm == Sm.rnorm) || isinf(Sm.rnorm)) {
-            w.active[member] = 0;
-            Sm.bad_start = 2;  // non-finite iterate
-            atomicSub(w.nactive, 1);
-        } else if (Sm.rnorm <= Sm.tol) {
-            Sm.converged = 1;
-            w.active[member] = 0;
-            atomicSub(w.nactive, 1);
-        } else if (Sm.iters >= Sm.max_iter) {
-            w.active[member] = 0;
-            atomicSub(w.nactive, 1);
-        } else if (!restart) {
-            // ||t - V s||^2 = ||t||^2 - ||s||^2; reliable unless it cancels below half
-            Sm.dgks = (tt - ss) < 0.5 * tt;
-            if (!(tt > 0.0)) {
-                Sm.breakdown = 1;
-                w.active[member] = 0;
-                atomicSub(w.nactive, 1);
-            } else if (!Sm.dgks) {
-                Sm.scale = 1.0 / sqrt(tt - ss);
-            }
+        const int64_t ld = w.nchunk;
+        if (!restart) {
+#pragma unroll
+            for (int j = 0; j < KB; ++j)
+                if (j < i) w.pa[j * ld + c] = acc[j];
         }
+        w.pa[PR_R * ld + c] = acc[KB];
+        w.pa[PR_T * ld + c] = acc[KB + 1];
     }
 }
 
-// Thick restart: V(:, :kmin) = V(:, :i) Y(:, :kmin), same for W; then s = V^T t, ||t||^2.
+// Thick restart: V(:, :kmin) = V(:, :i) Y(:, :kmin), same for W; partial row:
+// V^T t of the new basis (as Y(:, :kmin)^T of the old basis' V^T t), and the
+// norms of k_ritz's row.  Skipped when the stop
+// test (made again by k_orth from the same sums) ends the member.
 template <int KB>
 __global__ __launch_bounds__(TPB) void k_restart(DavArgs w, int i, int kmin) {
-    __shared__ double lds[4 * (KB + 1)];
+    __shared__ double lds[4 * KB];
     __shared__ double Ys[KB * KB];
-    __shared__ double scratch[TPB];
-    __shared__ double sums[KB + 1];
+    __shared__ double sums[2];
     const int c = blockIdx.x;
     const Chunk ck = chunk_of(w, c);
-    const int member = ck.member;
-    const DavState &S = w.st[member];
-    if (!w.active[member]) return;
+    if (!w.active[ck.member]) return;
+    const DavState &S = w.st[ck.member];
+    sum_rows(w.pa, w.nchunk, ck.c0, ck.c1, 0, 2, sums);
+    if (stop_code(S, sums[0])) return;
     for (int e = threadIdx.x; e < KB * KB; e += TPB) {
         int r = e / KB, q = e % KB;
         Ys[r * KB + q] = (r < i && q < kmin) ? S.Y[r * KM + q] : 0.0;
     }
     __syncthreads();
     const int64_t n = w.n;
-    double acc[KB + 1];
+    double acc[KB];
 #pragma unroll
-    for (int j = 0; j < KB + 1; ++j) acc[j] = 0.0;
+    for (int j = 0; j < KB; ++j) acc[j] = 0.0;
     for (int64_t e = ck.e0 + threadIdx.x; e < ck.e1; e += TPB) {
         double v[KB], wv[KB];
 #pragma unroll
@@ -280,58 +728,66 @@ __global__ __launch_bounds__(TPB) void k_restart(DavArgs w, int i, int kmin) {
             }
             w.V[(int64_t)q * n + e] = a;
             w.W[(int64_t)q * n + e] = b;
-            acc[q] += a * t;
         }
-        acc[KB] += t * t;
+#pragma unroll
+        for (int j = 0; j < KB; ++j) acc[j] += v[j] * t;  // old V^T t; the new one is Y^T of it
     }
-    block_reduce<KB + 1>(acc, KB + 1, lds);
-    if (threadIdx.x == 0)
-        for (int j = 0; j < KB + 1; ++j) w.part[(size_t)c * (KM + 2) + j] = acc[j];
-    const int c0 = w.nprob == 1 ? 0 : w.member_chunk[member];
-    const int c1 = w.nprob == 1 ? w.nchunk : w.member_chunk[member + 1];
-    if (!last_arrival(w.counter, member, c - c0, c1 - c0)) return;
-    DavState &Sm = w.st[member];
-    member_sums(w.part, c0, c1, KB + 1, scratch, sums);
-    const double tt = sums[KB];
-    double ss = 0.0;
-    if ((int)threadIdx.x < kmin) Sm.s[threadIdx.x] = sums[threadIdx.x];
-    for (int j = 0; j < kmin; ++j) ss += sums[j] * sums[j];
-    __syncthreads();
+    block_reduce<KB>(acc, i, lds);
     if (threadIdx.x == 0) {
-        for (int r = 0; r < kmin; ++r)
-            for (int q = 0; q < kmin; ++q) {
-                Sm.Bm[r * KM + q] = (r == q) ? Sm.theta[r] : 0.0;
-                Sm.Y[r * KM + q] = (r == q) ? 1.0 : 0.0;
-            }
-        Sm.tn0 = sqrt(tt);
-        Sm.dgks = (tt - ss) < 0.5 * tt;
-        if (!(tt > 0.0)) {
-            Sm.breakdown = 1;
-            w.active[member] = 0;
-            atomicSub(w.nactive, 1);
-        } else if (!Sm.dgks) {
-            Sm.scale = 1.0 / sqrt(tt - ss);
+        const int64_t ld = w.nchunk;
+        for (int q = 0; q < kmin; ++q) {
+            double sq = 0.0;
+#pragma unroll
+            for (int j = 0; j < KB; ++j) sq += Ys[j * KB + q] * acc[j];
+            w.pb[q * ld + c] = sq;
         }
-        Sm.restarts += 1;
+        w.pb[PR_R * ld + c] = w.pa[PR_R * ld + c];
+        w.pb[PR_T * ld + c] = w.pa[PR_T * ld + c];
     }
 }
 
-// t <- t - V s; partials: ||t||^2 and V^T t (for the DGKS pass).
+// Stop test, then t <- t - V s.  When ||t - V s||^2 = ||t||^2 - ||s||^2 does not
+// cancel below half of ||t||^2, V(:, i) = (t - V s) / sqrt(||t||^2 - ||s||^2)
+// directly; otherwise t is kept and its partial row (V^T t, ||t||^2) feeds the
+// second pass.  pin: the rows of k_ritz, or of k_restart after a restart.
 template <int KB>
-__global__ __launch_bounds__(TPB) void k_orth(DavArgs w, int i) {
+__global__ __launch_bounds__(TPB) void k_orth(DavArgs w, int i, const double *__restrict__ pin, int after_restart) {
     __shared__ double lds[4 * (KB + 1)];
-    __shared__ double scratch[TPB];
-    __shared__ double sums[KB + 1];
+    __shared__ double sums[KM + 2];
     const int c = blockIdx.x;
     const Chunk ck = chunk_of(w, c);
     const int member = ck.member;
-    const DavState &S = w.st[member];
-    const int act = w.active[member];
-    const int dg = S.dgks;         // second Gram-Schmidt pass needed (decided by the previous tail)
-    const double sc = S.scale;     // 1/||t - V s|| by Pythagoras when no second pass is needed
+    if (!w.active[member]) return;
+    DavState &S = w.st[member];
+    sum_rows(pin, w.nchunk, ck.c0, ck.c1, i, i + 2, sums);
+    const double rr = sums[i], tt = sums[i + 1];
+    double ss = 0.0;
+    for (int j = 0; j < i; ++j) ss += sums[j] * sums[j];
+    const int code = stop_code(S, rr);
+    const bool brk = !code && !(tt > 0.0);
+    const bool dg = (tt - ss) < 0.5 * tt;
+    if (c == ck.c0 && threadIdx.x == 0) {
+        S.rnorm = sqrt(rr);
+        S.tn0 = sqrt(tt);
+        if (code == 1) S.converged = 1;
+        if (code == 3) S.bad_start = 2;  // non-finite iterate
+        if (brk) S.breakdown = 1;
+        if (code || brk) {
+            deactivate(w, member);
+        } else {
+            S.dgks = dg;
+            if (after_restart) {  // the kept Ritz vectors are the new basis: B = diag(theta), Y = I
+                S.restarts += 1;
+                for (int r = 0; r < i; ++r)
+                    for (int q = 0; q < i; ++q) S.Y[r * KM + q] = (r == q) ? 1.0 : 0.0;
+            }
+        }
+    }
+    if (code || brk) return;
     double s[KB];
 #pragma unroll
-    for (int j = 0; j < KB; ++j) s[j] = (j < i) ? S.s[j] : 0.0;
+    for (int j = 0; j < KB; ++j) s[j] = (j < i) ? sums[j] : 0.0;
+    const double sc = dg ? 0.0 : 1.0 / sqrt(tt - ss);
     const int64_t n = w.n;
     double acc[KB + 1];
 #pragma unroll
@@ -347,51 +803,52 @@ __global__ __launch_bounds__(TPB) void k_orth(DavArgs w, int i) {
             t -= v[j] * s[j];
         }
         if (!dg) {
-            if (act) w.V[(int64_t)i * n + e] = t * sc;  // line 14: normalize and append
+            w.V[(int64_t)i * n + e] = t * sc;
             continue;
         }
-        if (act) w.T[e] = t;
+        w.T[e] = t;
 #pragma unroll
         for (int j = 0; j < KB; ++j) acc[j] += v[j] * t;
         acc[KB] += t * t;
     }
-    if (!act || !dg) return;
+    if (!dg) return;
     block_reduce<KB + 1>(acc, KB + 1, lds);
-    if (threadIdx.x == 0)
-        for (int j = 0; j < KB + 1; ++j) w.part[(size_t)c * (KM + 2) + j] = acc[j];
-    const int c0 = w.nprob == 1 ? 0 : w.member_chunk[member];
-    const int c1 = w.nprob == 1 ? w.nchunk : w.member_chunk[member + 1];
-    if (!last_arrival(w.counter, member, c - c0, c1 - c0)) return;
-    DavState &Sm = w.st[member];
-    member_sums(w.part, c0, c1, KB + 1, scratch, sums);
-    const double tt = sums[KB];
-    double ss = 0.0;
-    if ((int)threadIdx.x < i) Sm.s2[threadIdx.x] = sums[threadIdx.x];
-    for (int j = 0; j < i; ++j) ss += sums[j] * sums[j];
     if (threadIdx.x == 0) {
-        const double nrm = sqrt(fmax(tt - ss, 0.0));
-        if (!(nrm > 1e-13 * Sm.tn0)) {
-            Sm.breakdown = 1;
-            w.active[member] = 0;
-            atomicSub(w.nactive, 1);
-        } else {
-            Sm.scale = 1.0 / nrm;
-        }
+        const int64_t ld = w.nchunk;
+#pragma unroll
+        for (int j = 0; j < KB; ++j)
+            if (j < i) w.pc[j * ld + c] = acc[j];
+        w.pc[PR_R * ld + c] = 0.0;
+        w.pc[PR_T * ld + c] = acc[KB];
     }
 }
 
-// Second Gram-Schmidt pass: V(:, i) = (t - V s2) * scale; no-op unless needed.
+// Second Gram-Schmidt pass: V(:, i) = (t - V s2) / ||t - V s2||; no-op unless
+// k_orth asked for it.
 template <int KB>
 __global__ __launch_bounds__(TPB) void k_append(DavArgs w, int i) {
+    __shared__ double sums[KM + 2];
     const int c = blockIdx.x;
     const Chunk ck = chunk_of(w, c);
     const int member = ck.member;
-    const DavState &S = w.st[member];
-    if (!S.dgks || !w.active[member]) return;
+    if (!w.active[member]) return;
+    DavState &S = w.st[member];
+    if (!S.dgks) return;
+    sum_rows(w.pc, w.nchunk, ck.c0, ck.c1, i, i + 2, sums);
+    double ss = 0.0;
+    for (int j = 0; j < i; ++j) ss += sums[j] * sums[j];
+    const double nrm = sqrt(fmax(sums[i + 1] - ss, 0.0));
+    if (!(nrm > 1e-13 * S.tn0)) {
+        if (c == ck.c0 && threadIdx.x == 0) {
+            S.breakdown = 1;
+            deactivate(w, member);
+        }
+        return;
+    }
     double s2[KB];
 #pragma unroll
-    for (int j = 0; j < KB; ++j) s2[j] = (j < i) ? S.s2[j] : 0.0;
-    const double sc = S.scale;
+    for (int j = 0; j < KB; ++j) s2[j] = (j < i) ? sums[j] : 0.0;
+    const double sc = 1.0 / nrm;
     const int64_t n = w.n;
     for (int64_t e = ck.e0 + threadIdx.x; e < ck.e1; e += TPB) {
         double t = w.T[e];
@@ -444,7 +901,7 @@ __global__ void k_set_state(DavArgs w, double tol, double floor_, int max_iter) 
     S.iters = 0;  // counts are per phase; the host adds the phases
     S.nproj = 0;
     S.restarts = 0;
-    S.Y[0] = 1.0;  // (arrival counters are zeroed at allocation and by every completed reduction)
+    S.Y[0] = 1.0;
     if (m == 0) *w.nactive = w.nprob;
 }
 
@@ -494,15 +951,6 @@ static dmrg_status work_alloc(dmrg_plan *plan, int kmax, int kmin, hipStream_t s
     }
     cb.push_back(plan->n);
     A.nchunk = (int)cm.size();
-    // two-level arrival counters bound the chunks (and output tiles) of one member
-    const int64_t max_arrivals = (int64_t)ARRIVE_G * (CTR_STRIDE - 1);
-    for (int p = 0; p < plan->nprob; ++p)
-        if (mc[p + 1] - mc[p] > max_arrivals)
-            return set_error(DMRG_E_UNSUPPORTED, "member %d: target sector larger than %lld elements", p,
-                             (long long)(max_arrivals * CH));
-    for (int q = 0; q < 2; ++q)
-        if (plan->fwd[q].stageB.ntask > max_arrivals)
-            return set_error(DMRG_E_UNSUPPORTED, "more than %lld output tiles", (long long)max_arrivals);
     auto alloc = [&](void **p, size_t bytes) -> dmrg_status {
         DMRG_HIP(hipMalloc(p, std::max<size_t>(bytes, 8)));
         w->owned.push_back(*p);
@@ -515,13 +963,17 @@ static dmrg_status work_alloc(dmrg_plan *plan, int kmax, int kmin, hipStream_t s
     DMRG_TRY(alloc((void **)&A.D, n * 8));
     DMRG_TRY(alloc((void **)&A.dfold, n * 8));
     DMRG_TRY(alloc((void **)&A.coef, std::max(plan->nterm_total, 1) * 8));
-    // partial rows: one per chunk, or one per output tile when the projection runs the Rayleigh step
-    const int rows = std::max({A.nchunk, plan->fwd[0].stageB.ntask, plan->fwd[1].stageB.ntask});
-    DMRG_TRY(alloc((void **)&A.part, (size_t)rows * (KM + 2) * 8));
+    // partial rows: one per chunk (three sets), one per output tile (Rayleigh rows)
+    const size_t rowb = (KM + 2) * 8;
+    const int tiles = std::max({1, plan->fwd[0].stageB.ntask, plan->fwd[1].stageB.ntask});
+    A.tile_ld = tiles;
+    DMRG_TRY(alloc((void **)&A.pa, (size_t)A.nchunk * rowb));
+    DMRG_TRY(alloc((void **)&A.pb, (size_t)A.nchunk * rowb));
+    DMRG_TRY(alloc((void **)&A.pc, (size_t)A.nchunk * rowb));
+    DMRG_TRY(alloc((void **)&A.ptile, (size_t)tiles * rowb));
     DMRG_TRY(alloc((void **)&A.chunk_member, cm.size() * 4));
     DMRG_TRY(alloc((void **)&A.chunk_begin, cb.size() * 8));
     DMRG_TRY(alloc((void **)&A.member_chunk, mc.size() * 4));
-    DMRG_TRY(alloc((void **)&A.counter, (size_t)plan->nprob * CTR_STRIDE * 4));
     DMRG_TRY(alloc((void **)&A.nactive, 4));
     DMRG_TRY(alloc((void **)&A.st, plan->nprob * sizeof(DavState)));
     DMRG_TRY(alloc((void **)&A.active, plan->nprob * 4));
@@ -530,7 +982,6 @@ static dmrg_status work_alloc(dmrg_plan *plan, int kmax, int kmin, hipStream_t s
     DMRG_HIP(hipMemcpyAsync(A.chunk_begin, cb.data(), cb.size() * 8, hipMemcpyHostToDevice, s));
     DMRG_HIP(hipMemcpyAsync(A.member_chunk, mc.data(), mc.size() * 4, hipMemcpyHostToDevice, s));
     DMRG_HIP(hipMemsetAsync(A.st, 0, plan->nprob * sizeof(DavState), s));
-    DMRG_HIP(hipMemsetAsync(A.counter, 0, (size_t)plan->nprob * CTR_STRIDE * 4, s));
     DMRG_HIP(hipStreamSynchronize(s));
     return DMRG_OK;
 }
@@ -552,10 +1003,9 @@ static RayArgs ray_args(const DavArgs &A, int i) {
     r.V = A.V;
     r.n = A.n;
     r.i = i;
-    r.part = A.part;
-    r.counter = A.counter;
-    r.st = A.st;
-    return r;  // slot_begin is filled per pass by the launcher
+    r.part = A.ptile;
+    r.ld = A.tile_ld;
+    return r;
 }
 
 // Enqueue `count` iterations starting at subspace size i; returns the next i.
@@ -564,24 +1014,28 @@ static dmrg_status enqueue_iters(dmrg_plan *plan, int slot, int i, int count, in
     const DavArgs &A = w->a;
     const int kmax = w->kmax, kmin = w->kmin;
     const dim3 grid(A.nchunk), block(TPB);
+    const int32_t *slot_begin = plan->fwd[slot].slot_begin;
     for (int it = 0; it < count; ++it) {
         const bool restart = (i == kmax);
-        // the Rayleigh step of this iteration ran in the tail of the previous projection
+        // W(:, i-1) and its Rayleigh rows came from the previous projection
+        hipLaunchKernelGGL(k_rayleigh, dim3(A.nprob), block, 0, s, A, slot_begin, i, w->eig_solver);
         set_kb(i, [&](auto kb) {
             constexpr int KB = decltype(kb)::value;
             hipLaunchKernelGGL(k_ritz<KB>, grid, block, 0, s, A, i, restart ? 1 : 0);
         });
         int ie = i;
+        const double *pin = A.pa;
         if (restart) {
             set_kb(i, [&](auto kb) {
                 constexpr int KB = decltype(kb)::value;
                 hipLaunchKernelGGL(k_restart<KB>, grid, block, 0, s, A, i, kmin);
             });
             ie = kmin;
+            pin = A.pb;
         }
         set_kb(ie, [&](auto kb) {
             constexpr int KB = decltype(kb)::value;
-            hipLaunchKernelGGL(k_orth<KB>, grid, block, 0, s, A, ie);
+            hipLaunchKernelGGL(k_orth<KB>, grid, block, 0, s, A, ie, pin, restart ? 1 : 0);
             hipLaunchKernelGGL(k_append<KB>, grid, block, 0, s, A, ie);
         });
         DMRG_HIP(hipGetLastError());
@@ -604,7 +1058,7 @@ static dmrg_status run_phase(dmrg_plan *plan, int slot, const double *psi_in, do
     hipLaunchKernelGGL(k_init_vec, grid, block, 0, s, psi_in, A);
     DMRG_HIP(hipGetLastError());
     DMRG_TRY(launch_diag_fold(plan, slot, A.coef, A.dfold, s));  // coefficients are fixed for the phase
-    const RayArgs ray = ray_args(A, 1);  // W(:, 0) and the first Rayleigh step
+    const RayArgs ray = ray_args(A, 1);  // W(:, 0) and the rows of B(0, 0)
     DMRG_TRY(launch_project(plan, slot, A.coef, A.V, A.W, s, A.active, A.dfold, &ray));
     int i = 1;
     int done = 0;
@@ -612,7 +1066,7 @@ static dmrg_status run_phase(dmrg_plan *plan, int slot, const double *psi_in, do
         int cnt = std::min(chunk, max_iter - done);
         int inext = i;
         if (use_graph) {
-            auto key = std::make_tuple(slot, i, cnt, w->kmax);
+            auto key = std::make_tuple(slot, i, cnt, w->kmax, w->eig_solver);
             auto it = w->graphs.find(key);
             if (it == w->graphs.end()) {
                 hipStream_t cs;
@@ -670,8 +1124,11 @@ __global__ __launch_bounds__(TPB) void k_gemv_t_part(int64_t n, int k, const dou
             if (j < k) acc[j] += V[(int64_t)j * ldv + e] * xv;
     }
     block_reduce<KB>(acc, k, lds);
-    if (threadIdx.x == 0)
-        for (int j = 0; j < k; ++j) part[(size_t)blockIdx.x * KB + j] = acc[j];
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int j = 0; j < KB; ++j)
+            if (j < k) part[(size_t)blockIdx.x * KB + j] = acc[j];
+    }
 }
 
 // second stage: all k columns at once, thread t owns column t % k and every
@@ -731,6 +1188,7 @@ void dmrg_davidson_default_opts(dmrg_davidson_opts *o) {
     o->refine = 1;
     o->use_graph = 1;
     o->graph_chunk = 8;
+    o->eig_solver = 0;
 }
 
 dmrg_status dmrg_davidson(dmrg_plan *plan, const double *coef, const dmrg_davidson_opts *opts, double *psi,
@@ -744,6 +1202,7 @@ dmrg_status dmrg_davidson(dmrg_plan *plan, const double *coef, const dmrg_davids
         return set_error(DMRG_E_INVALID_ARG, "need 2 <= kmax <= %d and 1 <= kmin < kmax", KM);
     if (!(o.tol > 0.0) || o.max_iter < 1 || !(o.precond_floor > 0.0) || o.graph_chunk < 1)
         return set_error(DMRG_E_INVALID_ARG, "need tol > 0, max_iter >= 1, precond_floor > 0, graph_chunk >= 1");
+    if (o.eig_solver != 0 && o.eig_solver != 1) return set_error(DMRG_E_INVALID_ARG, "eig_solver must be 0 or 1");
     if (o.prec != DMRG_F64 && o.prec != plan->prec)
         return set_error(DMRG_E_INVALID_ARG, "precision %d not available in this plan", o.prec);
     int cur = -1;
@@ -758,6 +1217,7 @@ dmrg_status dmrg_davidson(dmrg_plan *plan, const double *coef, const dmrg_davids
     int kmin = std::min(o.kmin, kmax - 1);
     DMRG_TRY(work_alloc(plan, kmax, kmin, s));
     DavidsonWork *w = plan->dav;
+    w->eig_solver = o.eig_solver;
     const DavArgs &A = w->a;
     if (plan->nterm_total)
         DMRG_HIP(hipMemcpyAsync(A.coef, coef, plan->nterm_total * 8, hipMemcpyDeviceToDevice, s));

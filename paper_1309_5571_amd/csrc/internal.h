@@ -137,19 +137,20 @@ struct ConvJob {
 };
 
 struct DavidsonWork;
-struct DavState;
 
-// Davidson context for a projection that also runs the Rayleigh step of the
-// iteration it feeds: B(:, i-1) = V(:, :i)^T W(:, i-1) per member, then the
-// small eigenproblem, in the last output tile of each member.
+constexpr int KM = 48;  // largest Davidson subspace (kmax)
+
+// Davidson context for a projection that feeds an iteration: besides
+// W(:, i-1), every output tile writes its share of B(:, i-1) = V(:, :i)^T
+// W(:, i-1) as one partial row (columns 0..i-1, row = the tile's rslot).  The
+// rows are summed by the next kernel in the stream, so no tile waits on
+// another and no device-scope fence is needed.
 struct RayArgs {
     const double *V = nullptr;  // column j at V + j * n; nullptr = plain projection
     int64_t n = 0;
     int i = 0;
-    double *part = nullptr;     // [rows][KM + 2] partial rows
-    const int32_t *slot_begin = nullptr;
-    int32_t *counter = nullptr; // [nprob] arrival counters
-    DavState *st = nullptr;
+    double *part = nullptr;     // partial rows, column-major: (row r, column j) at part[j * ld + r]
+    int64_t ld = 0;
 };
 
 }  // namespace dmrg

@@ -24,7 +24,6 @@
 #include <algorithm>
 #include <cstdio>
 
-#include "dav_common.h"
 #include "internal.h"
 
 namespace dmrg {
@@ -497,49 +496,49 @@ __global__ __launch_bounds__(64 * PW) void k_tasks(const Task *__restrict__ task
             }
         }
         if (MODE == 1 && ray.V) {
-            // Rayleigh step of the next Davidson iteration: this tile's share of
-            // V(:, :i)^T w, thread t on column t % i, elements strided by 64 PW / i
-            // (column jc owned by an aligned group of G lanes, combined by shuffles)
-            __syncthreads();
-            const int ii = ray.i;
-            const int G = lanes_per_column(ii);
-            const int jc = threadIdx.x / G, l = threadIdx.x % G;
-            double acc = 0.0;
-            const int cnt = tk.m * tk.n;
-            if (jc < ii) {
-                const double *Vj = ray.V + (int64_t)jc * ray.n;
-#pragma unroll 4
-                for (int e = l; e < cnt; e += G) {
-                    const int64_t o = tk.c_off + (int64_t)(tk.row0 + e / tk.n) * tk.ldc + tk.col0 + e % tk.n;
-                    acc += Vj[o] * wtile[e];
+            // Rayleigh partials of the iteration this projection feeds: the
+            // tile's share of V(:, :i)^T w.  Wave w takes columns w, w + PW, ...;
+            // its lanes run over the tile's elements (coalesced along tile rows)
+            // and combine by shuffles in a fixed order.
+            __syncthreads();  // wtile complete
+            constexpr int JW = KM / PW;  // columns per wave
+            const int ii = ray.i, cnt = tk.m * tk.n;
+            double acc[JW];
+#pragma unroll
+            for (int jj = 0; jj < JW; ++jj) acc[jj] = 0.0;
+            for (int e0 = 0; e0 < cnt; e0 += 4 * 64) {
+                int64_t off[4];
+                double wv[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int e = e0 + lane + 64 * k;
+                    off[k] = 0;  // element 0 of the column: in bounds, weight 0
+                    wv[k] = 0.0;
+                    if (e < cnt) {
+                        off[k] = tk.c_off + (int64_t)(tk.row0 + e / tk.n) * tk.ldc + tk.col0 + e % tk.n;
+                        wv[k] = wtile[e];
+                    }
+                }
+                // groups of 4 columns: one branch per group, loads of a group in flight together
+#pragma unroll
+                for (int jg = 0; jg < JW; jg += 4) {
+                    if (wave + PW * jg < ii) {
+#pragma unroll
+                        for (int jj = jg; jj < jg + 4; ++jj) {
+                            const int j = min(wave + PW * jj, ii - 1);
+                            const double *Vj = ray.V + (int64_t)j * ray.n;
+#pragma unroll
+                            for (int k = 0; k < 4; ++k) acc[jj] += Vj[off[k]] * wv[k];
+                        }
+                    }
                 }
             }
-            for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-            if (jc < ii && l == 0) {
-                ray.part[(size_t)tk.rslot * (KM + 2) + jc] = acc;
-                __threadfence();
-            }
-            const int s0 = ray.slot_begin[tk.member], s1 = ray.slot_begin[tk.member + 1];
-            if (last_arrival(ray.counter, tk.member, tk.rslot - s0, s1 - s0)) {
-                // every tile of this member is done: B(:, i-1), then its smallest Ritz pairs
-                DavState &S = ray.st[tk.member];
-                JacobiLds &L = *reinterpret_cast<JacobiLds *>(smem_tasks);
-                member_sums(ray.part, s0, s1, ii, &L.Tm[0][0], &L.A[0][0]);
-                if ((int)threadIdx.x < ii) {
-                    const int j = threadIdx.x;
-                    const double b = L.A[0][j];
-                    S.Bm[j * KM + (ii - 1)] = b;
-                    S.Bm[(ii - 1) * KM + j] = b;
-                }
-                __syncthreads();
-                if (threadIdx.x < 64) jacobi_eig_wave(S, ii, L);
-                __syncthreads();
-                if (threadIdx.x == 0) {
-                    S.lambda = S.theta[0];
-                    S.sigma = fmin(S.lambda, S.dmin);
-                    S.iters += 1;
-                    S.nproj += 1;
-                    S.nvec = ii;
+#pragma unroll
+            for (int jj = 0; jj < JW; ++jj) {
+                const int j = wave + PW * jj;
+                if (j < ii) {
+                    const double v = wave_sum(acc[jj]);
+                    if (lane == 0) ray.part[j * ray.ld + tk.rslot] = v;
                 }
             }
         }
@@ -636,10 +635,8 @@ static dmrg_status run_pass(const PassSet &ps, const double *coef, const double 
                            ps.stageA.tasks, ps.stageA.ntask, ps.segs, ps.diags, in, (const void *)tmp, tmp, coef,
                            nullptr, nullptr, mask, (const double *)nullptr, RayArgs{});
     if (ps.stageB.ntask) {
-        RayArgs ra = ray ? *ray : RayArgs{};
-        if (ray) ra.slot_begin = ps.slot_begin;
-        const size_t lds = ray ? std::max(TASK_LDS, sizeof(JacobiLds)) : TASK_LDS;
-        hipLaunchKernelGGL((k_tasks<PREC, 1>), task_grid(ps.stageB.ntask), dim3(64 * PW), lds, s, ps.stageB.tasks,
+        const RayArgs ra = ray ? *ray : RayArgs{};
+        hipLaunchKernelGGL((k_tasks<PREC, 1>), task_grid(ps.stageB.ntask), dim3(64 * PW), TASK_LDS, s, ps.stageB.tasks,
                            ps.stageB.ntask, ps.segs, ps.diags, in, (const void *)tmp, (void *)out, coef, nullptr,
                            nullptr, mask, dfold, ra);
     }

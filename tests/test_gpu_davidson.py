@@ -70,12 +70,29 @@ def test_synthetic_configs_match_oracle(cfg):
     assert np.linalg.norm(r) <= 2e-10
 
 
-def test_restart_path_matches():
+@pytest.mark.parametrize("solver", ["arrowhead", "jacobi"])
+def test_restart_path_matches(solver):
     p = gen.config(1)
     pl = _plan(p)
-    psi, E, info, st = pl.davidson(_dev(gen.start_vector(pl.n, 3)), tol=1e-11, kmax=5, kmin=2, max_iter=3000)
+    psi, E, info, st = pl.davidson(_dev(gen.start_vector(pl.n, 3)), tol=1e-11, kmax=5, kmin=2, max_iter=3000,
+                                   eig_solver=solver)
     assert st == 0 and info[0]["restarts"] > 0
     assert abs(E[0] - GOLDEN["heisenberg_open_N10_Sz0"]) <= 1e-10
+
+
+@pytest.mark.parametrize("cfg", [1, 2, 3, 5])
+def test_small_eigensolvers_agree(cfg):
+    """The arrowhead solve of the Rayleigh step and the Jacobi sweeps give the
+    same Davidson run up to rounding (same iterations, energy, vector)."""
+    p = gen.config(cfg)
+    pl = _plan(p)
+    x0 = _dev(gen.start_vector(pl.n, 7))
+    a, Ea, ia, sa = pl.davidson(x0, tol=1e-10, kmax=12, kmin=4, eig_solver="arrowhead")
+    b, Eb, ib, sb = pl.davidson(x0, tol=1e-10, kmax=12, kmin=4, eig_solver="jacobi")
+    assert sa == 0 and sb == 0
+    assert abs(Ea[0] - Eb[0]) <= 1e-11 * max(1.0, abs(Eb[0]))
+    assert abs(ia[0]["iterations"] - ib[0]["iterations"]) <= 1
+    assert abs(abs(float(a @ b)) - 1.0) <= 1e-10
 
 
 def test_graph_replay_bit_identical_to_eager():
