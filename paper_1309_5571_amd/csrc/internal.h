@@ -115,6 +115,7 @@ struct Record {
 struct Lists {  // device task lists of one pass
     Task *tasks = nullptr;
     int32_t ntask = 0;
+    int32_t ns = 1;  // 16 x 16 sub-tiles per tile side: 1 when every tile fits 16 x 16, else 2
 };
 
 struct PassSet {  // everything one projection direction needs in one precision

@@ -564,6 +564,10 @@ static dmrg_status upload_pass(dmrg_plan *plan, HostPass &hp, PassSet &ps, hipSt
     DMRG_TRY(upload(plan, hp.B, &ps.stageB.tasks, s));
     ps.stageA.ntask = (int32_t)hp.A.size();
     ps.stageB.ntask = (int32_t)hp.B.size();
+    for (const Task &t : hp.A)
+        if (t.m > 16 || t.n > 16) ps.stageA.ns = 2;
+    for (const Task &t : hp.B)
+        if (t.m > 16 || t.n > 16) ps.stageB.ns = 2;
     ps.nseg = (int32_t)hp.segs.size();
     ps.ndiag = (int32_t)hp.diags.size();
     ps.tmp_elems = hp.tmp;

@@ -168,7 +168,7 @@ constexpr int TASK_GRID_MAX = 4096;  // persistent grid cap (blocks loop over ta
 
 // One work item: acc[sr][sc] += op(P)[tile rows, k0:k0+KC] op(Q)[k0:k0+KC, tile cols].
 // All operand loads of the item are issued before its MFMAs.
-template <int PREC, bool PIN, bool PT, bool QIN, bool QT>
+template <int PREC, int NS, bool PIN, bool PT, bool QIN, bool QT>
 __device__ __forceinline__ void item_gemm(typename Tr<PREC>::acc_t (&acc)[2][2], const Seg &s, const Task &tk,
                                           const double *__restrict__ in, const void *__restrict__ tmp, int nsr,
                                           int nsc, int k0) {
@@ -177,11 +177,12 @@ __device__ __forceinline__ void item_gemm(typename Tr<PREC>::acc_t (&acc)[2][2],
     constexpr int NKB = KC / KB;    // blocks per item
     const int lane = threadIdx.x & 63;
     const int r16 = lane & 15, g = lane >> 4;
-    int prow[2], qcol[2];
-    bool pok[2], qok[2];
-    double ps[2] = {1.0, 1.0}, qs[2] = {1.0, 1.0};
+    int prow[NS], qcol[NS];
+    bool pok[NS], qok[NS];
+    double ps[NS], qs[NS];
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
+    for (int t = 0; t < NS; ++t) {
+        ps[t] = qs[t] = 1.0;
         int r = t * 16 + r16;
         pok[t] = r < tk.m;
         prow[t] = tk.row0 + (pok[t] ? r : 0);
@@ -191,12 +192,12 @@ __device__ __forceinline__ void item_gemm(typename Tr<PREC>::acc_t (&acc)[2][2],
         if (PIN && s.pscale && pok[t]) ps[t] = ((const double *)(uintptr_t)s.pscale)[prow[t]];
         if (QIN && s.qscale && qok[t]) qs[t] = ((const double *)(uintptr_t)s.qscale)[qcol[t]];
     }
-    typename T::val_t pv[2][NKB][T::KPL], qv[2][NKB][T::KPL];
+    typename T::val_t pv[NS][NKB][T::KPL], qv[NS][NKB][T::KPL];
 #pragma unroll
     for (int b = 0; b < NKB; ++b) {
         const int kk = k0 + b * KB + T::KPL * g;
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
+        for (int t = 0; t < NS; ++t) {
             if (t < nsr) load_p<PREC, PIN, PT>(pv[t][b], s, in, tmp, prow[t], pok[t], kk, s.K, ps[t]);
             if (t < nsc) load_q<PREC, QIN, QT>(qv[t][b], s, in, tmp, qcol[t], qok[t], kk, s.K, qs[t]);
         }
@@ -204,9 +205,9 @@ __device__ __forceinline__ void item_gemm(typename Tr<PREC>::acc_t (&acc)[2][2],
 #pragma unroll
     for (int b = 0; b < NKB; ++b)
 #pragma unroll
-        for (int x = 0; x < 2; ++x)
+        for (int x = 0; x < NS; ++x)
 #pragma unroll
-            for (int y = 0; y < 2; ++y)
+            for (int y = 0; y < NS; ++y)
                 if (x < nsr && y < nsc) T::mma(acc[x][y], pv[x][b], qv[y][b]);
 }
 
@@ -223,7 +224,7 @@ __device__ __forceinline__ void wave_lds_sync() {
 // Tl is rounded to the operand format before the second product, like the
 // intermediate of the two-stage path.  tl: this wavefront's LDS slice
 // (16 x 64 doubles).
-template <int PREC>
+template <int PREC, int NS>
 __device__ __forceinline__ void fused_item(typename Tr<PREC>::acc_t (&acc)[2][2], const Seg &s, const Task &tk,
                                            const double *__restrict__ in, double *tl, int nsc) {
     typedef Tr<PREC> T;
@@ -258,7 +259,7 @@ __device__ __forceinline__ void fused_item(typename Tr<PREC>::acc_t (&acc)[2][2]
     wave_lds_sync();
     const typename T::store_t *R = (const typename T::store_t *)(uintptr_t)s.r;
     for (int k0 = 0; k0 < s.K2; k0 += KB) {
-        typename T::val_t pv[T::KPL], qv[2][T::KPL];
+        typename T::val_t pv[T::KPL], qv[NS][T::KPL];
         const int kk = k0 + T::KPL * g;
 #pragma unroll
         for (int j = 0; j < T::KPL; ++j) {
@@ -266,7 +267,7 @@ __device__ __forceinline__ void fused_item(typename Tr<PREC>::acc_t (&acc)[2][2]
             pv[j] = T::from_in((k < s.K2) ? tl[r16 * 64 + k] : 0.0);
         }
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
+        for (int b = 0; b < NS; ++b) {
             const int c = b * 16 + r16;
             const bool ok = c < tk.n;
             const int col = tk.col0 + (ok ? c : 0);
@@ -281,44 +282,45 @@ __device__ __forceinline__ void fused_item(typename Tr<PREC>::acc_t (&acc)[2][2]
             }
         }
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int b = 0; b < NS; ++b)
             if (b < nsc) T::mma(acc[0][b], pv, qv[b]);
     }
     wave_lds_sync();  // the slice is rewritten by this wavefront's next fused item
 }
 
 // All work items [first, nit) step PW of one segment, for one operand layout.
-template <int PREC, bool PIN, bool PT, bool QIN, bool QT>
+template <int PREC, int NS, bool PIN, bool PT, bool QIN, bool QT>
 __device__ __forceinline__ void seg_items(typename Tr<PREC>::acc_t (&acc)[2][2], const Seg &s, const Task &tk,
                                        const double *__restrict__ in, const void *__restrict__ tmp, int nsr, int nsc,
                                        int first, int nit) {
-    for (int it = first; it < nit; it += PW) item_gemm<PREC, PIN, PT, QIN, QT>(acc, s, tk, in, tmp, nsr, nsc, it * KC);
+    for (int it = first; it < nit; it += PW)
+        item_gemm<PREC, NS, PIN, PT, QIN, QT>(acc, s, tk, in, tmp, nsr, nsc, it * KC);
 }
 
 // One switch per segment on the operand layout (the task lists use 7 of the 16).
-template <int PREC>
+template <int PREC, int NS>
 __device__ __forceinline__ void seg_dispatch(typename Tr<PREC>::acc_t (&acc)[2][2], const Seg &s, const Task &tk,
                                              const double *__restrict__ in, const void *__restrict__ tmp, int nsr,
                                              int nsc, int first, int nit) {
     const bool pin = s.pkind == OPD_IN, qin = s.qkind == OPD_IN;
     const int code = (pin ? 8 : 0) | (s.ptrans ? 4 : 0) | (qin ? 2 : 0) | (s.qtrans ? 1 : 0);
     switch (code) {
-        case 0: seg_items<PREC, false, false, false, false>(acc, s, tk, in, tmp, nsr, nsc, first, nit); break;
-        case 1: seg_items<PREC, false, false, false, true>(acc, s, tk, in, tmp, nsr, nsc, first, nit); break;
-        case 2: seg_items<PREC, false, false, true, false>(acc, s, tk, in, tmp, nsr, nsc, first, nit); break;
-        case 3: seg_items<PREC, false, false, true, true>(acc, s, tk, in, tmp, nsr, nsc, first, nit); break;
-        case 4: seg_items<PREC, false, true, false, false>(acc, s, tk, in, tmp, nsr, nsc, first, nit); break;
-        case 5: seg_items<PREC, false, true, false, true>(acc, s, tk, in, tmp, nsr, nsc, first, nit); break;
-        case 6: seg_items<PREC, false, true, true, false>(acc, s, tk, in, tmp, nsr, nsc, first, nit); break;
-        case 7: seg_items<PREC, false, true, true, true>(acc, s, tk, in, tmp, nsr, nsc, first, nit); break;
-        case 8: seg_items<PREC, true, false, false, false>(acc, s, tk, in, tmp, nsr, nsc, first, nit); break;
-        case 9: seg_items<PREC, true, false, false, true>(acc, s, tk, in, tmp, nsr, nsc, first, nit); break;
-        case 10: seg_items<PREC, true, false, true, false>(acc, s, tk, in, tmp, nsr, nsc, first, nit); break;
-        case 11: seg_items<PREC, true, false, true, true>(acc, s, tk, in, tmp, nsr, nsc, first, nit); break;
-        case 12: seg_items<PREC, true, true, false, false>(acc, s, tk, in, tmp, nsr, nsc, first, nit); break;
-        case 13: seg_items<PREC, true, true, false, true>(acc, s, tk, in, tmp, nsr, nsc, first, nit); break;
-        case 14: seg_items<PREC, true, true, true, false>(acc, s, tk, in, tmp, nsr, nsc, first, nit); break;
-        default: seg_items<PREC, true, true, true, true>(acc, s, tk, in, tmp, nsr, nsc, first, nit); break;
+        case 0: seg_items<PREC, NS, false, false, false, false>(acc, s, tk, in, tmp, nsr, nsc, first, nit); break;
+        case 1: seg_items<PREC, NS, false, false, false, true>(acc, s, tk, in, tmp, nsr, nsc, first, nit); break;
+        case 2: seg_items<PREC, NS, false, false, true, false>(acc, s, tk, in, tmp, nsr, nsc, first, nit); break;
+        case 3: seg_items<PREC, NS, false, false, true, true>(acc, s, tk, in, tmp, nsr, nsc, first, nit); break;
+        case 4: seg_items<PREC, NS, false, true, false, false>(acc, s, tk, in, tmp, nsr, nsc, first, nit); break;
+        case 5: seg_items<PREC, NS, false, true, false, true>(acc, s, tk, in, tmp, nsr, nsc, first, nit); break;
+        case 6: seg_items<PREC, NS, false, true, true, false>(acc, s, tk, in, tmp, nsr, nsc, first, nit); break;
+        case 7: seg_items<PREC, NS, false, true, true, true>(acc, s, tk, in, tmp, nsr, nsc, first, nit); break;
+        case 8: seg_items<PREC, NS, true, false, false, false>(acc, s, tk, in, tmp, nsr, nsc, first, nit); break;
+        case 9: seg_items<PREC, NS, true, false, false, true>(acc, s, tk, in, tmp, nsr, nsc, first, nit); break;
+        case 10: seg_items<PREC, NS, true, false, true, false>(acc, s, tk, in, tmp, nsr, nsc, first, nit); break;
+        case 11: seg_items<PREC, NS, true, false, true, true>(acc, s, tk, in, tmp, nsr, nsc, first, nit); break;
+        case 12: seg_items<PREC, NS, true, true, false, false>(acc, s, tk, in, tmp, nsr, nsc, first, nit); break;
+        case 13: seg_items<PREC, NS, true, true, false, true>(acc, s, tk, in, tmp, nsr, nsc, first, nit); break;
+        case 14: seg_items<PREC, NS, true, true, true, false>(acc, s, tk, in, tmp, nsr, nsc, first, nit); break;
+        default: seg_items<PREC, NS, true, true, true, true>(acc, s, tk, in, tmp, nsr, nsc, first, nit); break;
     }
 }
 
@@ -359,7 +361,7 @@ __device__ __forceinline__ double diag_sum(const DiagTerm *__restrict__ diags, i
 // tile -- (segment, KC-long slice of its contraction) in list order -- are
 // dealt round-robin to the wavefronts; the PW partial tiles are summed in a
 // fixed order through LDS, so results do not depend on scheduling.
-template <int PREC, int MODE>
+template <int PREC, int MODE, int NS>
 __global__ __launch_bounds__(64 * PW) void k_tasks(const Task *__restrict__ tasks, int ntask,
                                                   const Seg *__restrict__ segs, const DiagTerm *__restrict__ diags,
                                                   const double *__restrict__ in, const void *__restrict__ tmp,
@@ -385,17 +387,17 @@ __global__ __launch_bounds__(64 * PW) void k_tasks(const Task *__restrict__ task
                 typename T::acc_t acc[2][2];
                 zero_acc<PREC>(acc);
                 if (s.fused) {
-                    fused_item<PREC>(acc, s, tk, in, &red[wave][0][0], nsc);
+                    fused_item<PREC, NS>(acc, s, tk, in, &red[wave][0][0], nsc);
                 } else {
                     // one wavefront runs every work item of the segment (PW-strided item loop, 4 passes)
                     for (int f = 0; f < PW; ++f)
-                        seg_dispatch<PREC>(acc, s, tk, in, tmp, nsr, nsc, f, (s.K + KC - 1) / KC);
+                        seg_dispatch<PREC, NS>(acc, s, tk, in, tmp, nsr, nsc, f, (s.K + KC - 1) / KC);
                 }
                 double part = 0.0;
 #pragma unroll
-                for (int a = 0; a < 2; ++a)
+                for (int a = 0; a < NS; ++a)
 #pragma unroll
-                    for (int b = 0; b < 2; ++b)
+                    for (int b = 0; b < NS; ++b)
 #pragma unroll
                         for (int v = 0; v < 4; ++v) {
                             const int r = a * 16 + T::row(g, v), c = b * 16 + r16;
@@ -421,10 +423,11 @@ __global__ __launch_bounds__(64 * PW) void k_tasks(const Task *__restrict__ task
         }
         // epilogue inputs (folded diagonal and the matching input entries) are
         // fetched before the GEMM work so their latency overlaps it
-        double pre_x[4], pre_d[4];
+        constexpr int NQ = NS * NS;  // tile elements per thread: (16 NS)^2 / (64 PW)
+        double pre_x[NQ], pre_d[NQ];
         if (MODE == 1 && dfold) {
 #pragma unroll
-            for (int qq = 0; qq < 4; ++qq) {
+            for (int qq = 0; qq < NQ; ++qq) {
                 const int e = threadIdx.x + qq * 64 * PW;
                 pre_x[qq] = pre_d[qq] = 0.0;
                 if (e < tk.m * tk.n) {
@@ -434,11 +437,11 @@ __global__ __launch_bounds__(64 * PW) void k_tasks(const Task *__restrict__ task
                 }
             }
         }
-        double tot[2][2][4];
+        double tot[NS][NS][4];
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < NS; ++a)
 #pragma unroll
-            for (int b = 0; b < 2; ++b)
+            for (int b = 0; b < NS; ++b)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) tot[a][b][v] = 0.0;
         int q = 0;  // work-item counter, identical in every wavefront
@@ -452,30 +455,30 @@ __global__ __launch_bounds__(64 * PW) void k_tasks(const Task *__restrict__ task
                 typename T::acc_t acc[2][2];
                 zero_acc<PREC>(acc);
                 if (fused)
-                    fused_item<PREC>(acc, s, tk, in, &red[wave][0][0], nsc);
+                    fused_item<PREC, NS>(acc, s, tk, in, &red[wave][0][0], nsc);
                 else
-                    seg_dispatch<PREC>(acc, s, tk, in, tmp, nsr, nsc, first, nit);
+                    seg_dispatch<PREC, NS>(acc, s, tk, in, tmp, nsr, nsc, first, nit);
                 const double c = s.coef >= 0 ? coef[s.coef] : 1.0;
 #pragma unroll
-                for (int a = 0; a < 2; ++a)
+                for (int a = 0; a < NS; ++a)
 #pragma unroll
-                    for (int b = 0; b < 2; ++b)
+                    for (int b = 0; b < NS; ++b)
 #pragma unroll
                         for (int v = 0; v < 4; ++v) tot[a][b][v] += c * (double)acc[a][b][v];
             }
             q += nit;
         }
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < NS; ++a)
 #pragma unroll
-            for (int b = 0; b < 2; ++b)
+            for (int b = 0; b < NS; ++b)
                 if (a < nsr && b < nsc) {
 #pragma unroll
                     for (int v = 0; v < 4; ++v) red[wave][a * 16 + T::row(g, v)][b * 16 + r16] = tot[a][b][v];
                 }
         __syncthreads();
 #pragma unroll
-        for (int qq = 0; qq < 4; ++qq) {
+        for (int qq = 0; qq < NQ; ++qq) {
             const int e = threadIdx.x + qq * 64 * PW;
             if (e >= tk.m * tk.n) break;
             const int r = e / tk.n, c = e % tk.n;
@@ -627,18 +630,29 @@ dmrg_status launch_convert_jobs(const ConvJob *jobs, int njob, int prec, hipStre
 
 static dim3 task_grid(int ntask) { return dim3(std::min(ntask, TASK_GRID_MAX)); }
 
+// k_tasks<PREC, MODE, NS> launch with the pass list's sub-tile count
+template <int PREC, int MODE, class... Args>
+static void launch_tasks(const Lists &l, size_t lds, hipStream_t s, Args... args) {
+    if (l.ns == 1)
+        hipLaunchKernelGGL((k_tasks<PREC, MODE, 1>), task_grid(l.ntask), dim3(64 * PW), lds, s, l.tasks, l.ntask,
+                           args...);
+    else
+        hipLaunchKernelGGL((k_tasks<PREC, MODE, 2>), task_grid(l.ntask), dim3(64 * PW), lds, s, l.tasks, l.ntask,
+                           args...);
+}
+
 template <int PREC>
 static dmrg_status run_pass(const PassSet &ps, const double *coef, const double *in, void *tmp, double *out,
                             hipStream_t s, const int32_t *mask, const double *dfold, const RayArgs *ray) {
     if (ps.stageA.ntask)
-        hipLaunchKernelGGL((k_tasks<PREC, 0>), task_grid(ps.stageA.ntask), dim3(64 * PW), TASK_LDS, s,
-                           ps.stageA.tasks, ps.stageA.ntask, ps.segs, ps.diags, in, (const void *)tmp, tmp, coef,
-                           nullptr, nullptr, mask, (const double *)nullptr, RayArgs{});
+        launch_tasks<PREC, 0>(ps.stageA, TASK_LDS, s, (const Seg *)ps.segs, (const DiagTerm *)ps.diags, in,
+                              (const void *)tmp, tmp, coef, (const double *)nullptr, (double *)nullptr, mask,
+                              (const double *)nullptr, RayArgs{});
     if (ps.stageB.ntask) {
         const RayArgs ra = ray ? *ray : RayArgs{};
-        hipLaunchKernelGGL((k_tasks<PREC, 1>), task_grid(ps.stageB.ntask), dim3(64 * PW), TASK_LDS, s, ps.stageB.tasks,
-                           ps.stageB.ntask, ps.segs, ps.diags, in, (const void *)tmp, (void *)out, coef, nullptr,
-                           nullptr, mask, dfold, ra);
+        launch_tasks<PREC, 1>(ps.stageB, TASK_LDS, s, (const Seg *)ps.segs, (const DiagTerm *)ps.diags, in,
+                              (const void *)tmp, (void *)out, coef, (const double *)nullptr, (double *)nullptr, mask,
+                              dfold, ra);
     }
     DMRG_HIP(hipGetLastError());
     return DMRG_OK;
@@ -668,15 +682,14 @@ dmrg_status launch_diag_fold(dmrg_plan *plan, int slot, const double *coef, doub
 dmrg_status launch_gcoef(dmrg_plan *plan, const double *psi, const double *gbar, double *gcoef, hipStream_t s) {
     const PassSet &ps = plan->fwd[0];
     if (ps.stageA.ntask)
-        hipLaunchKernelGGL((k_tasks<DMRG_F64, 0>), task_grid(ps.stageA.ntask), dim3(64 * PW), TASK_LDS, s,
-                           ps.stageA.tasks, ps.stageA.ntask, ps.segs, ps.diags, psi, (const void *)plan->d_tmp,
-                           plan->d_tmp, (const double *)nullptr, nullptr, nullptr, nullptr, (const double *)nullptr,
-                           RayArgs{});
+        launch_tasks<DMRG_F64, 0>(ps.stageA, TASK_LDS, s, (const Seg *)ps.segs, (const DiagTerm *)ps.diags, psi,
+                                  (const void *)plan->d_tmp, (void *)plan->d_tmp, (const double *)nullptr,
+                                  (const double *)nullptr, (double *)nullptr, (const int32_t *)nullptr,
+                                  (const double *)nullptr, RayArgs{});
     if (ps.stageB.ntask)
-        hipLaunchKernelGGL((k_tasks<DMRG_F64, 2>), task_grid(ps.stageB.ntask), dim3(64 * PW), TASK_LDS, s,
-                           ps.stageB.tasks, ps.stageB.ntask, ps.segs, ps.diags, psi, (const void *)plan->d_tmp,
-                           nullptr, (const double *)nullptr, gbar, plan->d_partials, nullptr,
-                           (const double *)nullptr, RayArgs{});
+        launch_tasks<DMRG_F64, 2>(ps.stageB, TASK_LDS, s, (const Seg *)ps.segs, (const DiagTerm *)ps.diags, psi,
+                                  (const void *)plan->d_tmp, (void *)nullptr, (const double *)nullptr, gbar,
+                                  plan->d_partials, (const int32_t *)nullptr, (const double *)nullptr, RayArgs{});
     if (plan->nterm_total)
         hipLaunchKernelGGL(k_reduce_terms, dim3(plan->nterm_total), dim3(64), 0, s, plan->d_term_ptr,
                            plan->d_term_ent, (const double *)plan->d_partials, gcoef, plan->nterm_total);
