@@ -176,7 +176,7 @@ typedef struct {
     double tol_lowprec;    /* phase-1 tolerance for F32/BF16 (0: 1e-5 for F32, 1e-3 for BF16) */
     int32_t refine;        /* F32/BF16: 1 = continue in F64 to tol (default), 0 = stop after phase 1 */
     int32_t use_graph;     /* 1 = replay captured hipGraphs of graph_chunk iterations (default) */
-    int32_t graph_chunk;   /* iterations per graph launch, default 8 */
+    int32_t graph_chunk;   /* most iterations per launch (graph replay or eager), default 8 */
     int32_t eig_solver;    /* small eigenproblem of the Rayleigh step: 0 = direct solve of the
                               arrowhead (secular equation, Jacobi only where poles nearly
                               coincide), default; 1 = Jacobi always */
@@ -201,7 +201,11 @@ void dmrg_davidson_default_opts(dmrg_davidson_opts *opts);
  *  psi:  device FP64 [n]; in: start vectors (any norm, non-zero per member),
  *        out: normalized ground states.
  *  energy: host [nprob] (may be NULL); info: host [nprob] (may be NULL).
- * Synchronizes stream.  Returns DMRG_W_NOT_CONVERGED if any member did not
+ * Iterations run in launches of at most graph_chunk (4 first, then as many as
+ * the residual decay predicts); the host waits for each launch's summary.
+ * energy and info are final on return; psi is completed in stream order
+ * (work enqueued on stream afterwards sees it; synchronize stream before
+ * reading it from the host).  Returns DMRG_W_NOT_CONVERGED if any member did not
  * converge, DMRG_E_BREAKDOWN if any broke down, DMRG_E_NONFINITE for a
  * zero or non-finite start vector. */
 dmrg_status dmrg_davidson(dmrg_plan *plan, const double *coef, const dmrg_davidson_opts *opts,

@@ -48,8 +48,14 @@ constexpr int PR_T = KM + 1;  // partial-row column of ||t||^2
 struct DavState {
     double Y[KM * KM];   // eigenvectors of B (column c = Y[r * KM + c]), ascending
     double theta[KM];    // Ritz values, ascending
-    double lambda, sigma, dmin, rnorm, tn0, scale, tol, floor_;
+    double lambda, sigma, dmin, rnorm, rnorm1, tn0, scale, tol, floor_;
     int32_t converged, breakdown, iters, nproj, restarts, dgks, nvec, max_iter, bad_start;
+};
+
+// Per-member results copied to the host after every launch of iterations.
+struct DavSummary {
+    double energy, rnorm, rnorm1;  // rnorm1: residual of the phase's first iteration
+    int32_t active, iters, nproj, restarts, converged, breakdown, bad_start, pad;
 };
 
 // Kernel-argument view of the Davidson workspace (plain pointers only).
@@ -69,17 +75,22 @@ struct DavArgs {
     int32_t *chunk_member = nullptr;
     int64_t *chunk_begin = nullptr;   // [nchunk + 1] element ranges
     int32_t *member_chunk = nullptr;  // [nprob + 1] chunk ranges
-    int32_t *nactive = nullptr;       // [1] members still iterating
     int32_t *active = nullptr;        // [nprob] 1 while the member iterates
     DavState *st = nullptr;           // [nprob]
+    const double *X0 = nullptr;       // [n] start vectors of the phase (private copy)
+    DavSummary *sum = nullptr;        // [nprob] device view of pinned host memory
 };
 
 struct DavidsonWork {
     DavArgs a;
     int kmax = 0, kmin = 0;
     int eig_solver = 0;
-    int32_t *h_nactive = nullptr;  // pinned
-    std::map<std::tuple<int, int, int, int, int>, hipGraphExec_t> graphs;
+    DavSummary *h_sum = nullptr;  // pinned, mapped [nprob]
+    hipStream_t side = nullptr;   // second branch of the phase set-up
+    hipEvent_t fork = nullptr, join = nullptr;
+    // graphs by (slot, 2 * first i (0: with the phase set-up) + finalize-into-X0, iterations, kmax, eig_solver,
+    // max_iter, tol bits, floor bits)
+    std::map<std::tuple<int, int, int, int, int, int, uint64_t, uint64_t>, hipGraphExec_t> graphs;
     std::vector<void *> owned;
 };
 
@@ -166,10 +177,7 @@ static __device__ double block_min(double v, double *lds) {
     return m;
 }
 
-static __device__ __forceinline__ void deactivate(const DavArgs &w, int member) {
-    w.active[member] = 0;
-    atomicSub(w.nactive, 1);
-}
+static __device__ __forceinline__ void deactivate(const DavArgs &w, int member) { w.active[member] = 0; }
 
 // Stop test on the residual norm: 0 go on, 1 converged, 2 iteration limit, 3 non-finite.
 static __device__ __forceinline__ int stop_code(const DavState &S, double rr) {
@@ -182,10 +190,33 @@ static __device__ __forceinline__ int stop_code(const DavState &S, double rr) {
 
 // ------------------------------------------------------------------ init kernels
 
-// partial rows: ||psi||^2 (column 0) and min D (column 1) of each chunk
-__global__ __launch_bounds__(TPB) void k_init_norm(const double *__restrict__ psi, DavArgs w) {
+// Phase start of member m: options, flags and counters.
+static __device__ void set_state(const DavArgs &w, int m, double tol, double floor_, int max_iter) {
+    DavState &S = w.st[m];
+    S.tol = tol;
+    S.floor_ = floor_;
+    S.max_iter = max_iter;
+    w.active[m] = 1;
+    S.converged = 0;
+    S.breakdown = 0;
+    S.bad_start = 0;
+    S.dgks = 0;
+    S.nvec = 1;
+    S.iters = 0;  // counts are per phase; the host adds the phases
+    S.nproj = 0;
+    S.restarts = 0;
+    S.rnorm = 0.0;
+    S.rnorm1 = 0.0;
+    S.Y[0] = 1.0;
+}
+
+// Phase start (the first block of each member resets its state); partial
+// rows: ||psi||^2 (column 0) and min D (column 1) of each chunk.
+__global__ __launch_bounds__(TPB) void k_init_norm(const double *__restrict__ psi, DavArgs w, double tol,
+                                                   double floor_, int max_iter) {
     __shared__ double lds[4];
     const Chunk ck = chunk_of(w, blockIdx.x);
+    if ((int)blockIdx.x == ck.c0 && threadIdx.x == 0) set_state(w, ck.member, tol, floor_, max_iter);
     double ss = 0.0, mn = INFINITY;
     for (int64_t e = ck.e0 + threadIdx.x; e < ck.e1; e += TPB) {
         ss += psi[e] * psi[e];
@@ -768,6 +799,7 @@ __global__ __launch_bounds__(TPB) void k_orth(DavArgs w, int i, const double *__
     const bool dg = (tt - ss) < 0.5 * tt;
     if (c == ck.c0 && threadIdx.x == 0) {
         S.rnorm = sqrt(rr);
+        if (S.iters == 1) S.rnorm1 = S.rnorm;
         S.tn0 = sqrt(tt);
         if (code == 1) S.converged = 1;
         if (code == 3) S.bad_start = 2;  // non-finite iterate
@@ -885,24 +917,23 @@ __global__ __launch_bounds__(TPB) void k_finalize(DavArgs w, double *__restrict_
     }
 }
 
-__global__ void k_set_state(DavArgs w, double tol, double floor_, int max_iter) {
+__global__ void k_summary(DavArgs w) {
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= w.nprob) return;
-    DavState &S = w.st[m];
-    S.tol = tol;
-    S.floor_ = floor_;
-    S.max_iter = max_iter;
-    w.active[m] = 1;
-    S.converged = 0;
-    S.breakdown = 0;
-    S.bad_start = 0;
-    S.dgks = 0;
-    S.nvec = 1;
-    S.iters = 0;  // counts are per phase; the host adds the phases
-    S.nproj = 0;
-    S.restarts = 0;
-    S.Y[0] = 1.0;
-    if (m == 0) *w.nactive = w.nprob;
+    const DavState &S = w.st[m];
+    DavSummary r;
+    r.energy = S.lambda;
+    r.rnorm = S.rnorm;
+    r.rnorm1 = S.rnorm1;
+    r.active = w.active[m];
+    r.iters = S.iters;
+    r.nproj = S.nproj;
+    r.restarts = S.restarts;
+    r.converged = S.converged;
+    r.breakdown = S.breakdown;
+    r.bad_start = S.bad_start;
+    r.pad = 0;
+    w.sum[m] = r;
 }
 
 // ------------------------------------------------------------------ host driver
@@ -974,10 +1005,16 @@ static dmrg_status work_alloc(dmrg_plan *plan, int kmax, int kmin, hipStream_t s
     DMRG_TRY(alloc((void **)&A.chunk_member, cm.size() * 4));
     DMRG_TRY(alloc((void **)&A.chunk_begin, cb.size() * 8));
     DMRG_TRY(alloc((void **)&A.member_chunk, mc.size() * 4));
-    DMRG_TRY(alloc((void **)&A.nactive, 4));
     DMRG_TRY(alloc((void **)&A.st, plan->nprob * sizeof(DavState)));
     DMRG_TRY(alloc((void **)&A.active, plan->nprob * 4));
-    DMRG_HIP(hipHostMalloc((void **)&w->h_nactive, 4, hipHostMallocDefault));
+    DMRG_TRY(alloc((void **)&A.X0, n * 8));
+    // the summary goes straight to pinned, mapped, coherent host memory (no copy step)
+    DMRG_HIP(hipHostMalloc((void **)&w->h_sum, plan->nprob * sizeof(DavSummary),
+                           hipHostMallocMapped | hipHostMallocCoherent));
+    DMRG_HIP(hipHostGetDevicePointer((void **)&A.sum, w->h_sum, 0));
+    DMRG_HIP(hipStreamCreateWithFlags(&w->side, hipStreamNonBlocking));
+    DMRG_HIP(hipEventCreateWithFlags(&w->fork, hipEventDisableTiming));
+    DMRG_HIP(hipEventCreateWithFlags(&w->join, hipEventDisableTiming));
     DMRG_HIP(hipMemcpyAsync(A.chunk_member, cm.data(), cm.size() * 4, hipMemcpyHostToDevice, s));
     DMRG_HIP(hipMemcpyAsync(A.chunk_begin, cb.data(), cb.size() * 8, hipMemcpyHostToDevice, s));
     DMRG_HIP(hipMemcpyAsync(A.member_chunk, mc.data(), mc.size() * 4, hipMemcpyHostToDevice, s));
@@ -991,7 +1028,10 @@ dmrg_status davidson_free(dmrg_plan *plan) {
     if (!w) return DMRG_OK;
     for (auto &kv : w->graphs) (void)hipGraphExecDestroy(kv.second);
     for (void *p : w->owned) (void)hipFree(p);
-    if (w->h_nactive) (void)hipHostFree(w->h_nactive);
+    if (w->h_sum) (void)hipHostFree(w->h_sum);
+    if (w->fork) (void)hipEventDestroy(w->fork);
+    if (w->join) (void)hipEventDestroy(w->join);
+    if (w->side) (void)hipStreamDestroy(w->side);
     delete w;
     plan->dav = nullptr;
     return DMRG_OK;
@@ -1048,32 +1088,90 @@ static dmrg_status enqueue_iters(dmrg_plan *plan, int slot, int i, int count, in
     return DMRG_OK;
 }
 
-static dmrg_status run_phase(dmrg_plan *plan, int slot, const double *psi_in, double tol, double floor_,
-                             int max_iter, bool use_graph, int chunk, hipStream_t s, int *iters_out) {
+// Phase set-up: state, start vector, diagonal folding (on a parallel branch),
+// and W(:, 0) with the rows of B(0, 0).  Reads the private copy X0 of the
+// start vectors.
+static dmrg_status enqueue_setup(dmrg_plan *plan, int slot, double tol, double floor_, int max_iter, hipStream_t s) {
     DavidsonWork *w = plan->dav;
     const DavArgs &A = w->a;
     const dim3 grid(A.nchunk), block(TPB);
-    hipLaunchKernelGGL(k_set_state, dim3((A.nprob + 63) / 64), dim3(64), 0, s, A, tol, floor_, max_iter);
-    hipLaunchKernelGGL(k_init_norm, grid, block, 0, s, psi_in, A);
-    hipLaunchKernelGGL(k_init_vec, grid, block, 0, s, psi_in, A);
+    DMRG_HIP(hipEventRecord(w->fork, s));
+    DMRG_HIP(hipStreamWaitEvent(w->side, w->fork, 0));
+    DMRG_TRY(launch_diag_fold(plan, slot, A.coef, A.dfold, w->side));  // coefficients are fixed for the phase
+    DMRG_HIP(hipEventRecord(w->join, w->side));
+    hipLaunchKernelGGL(k_init_norm, grid, block, 0, s, A.X0, A, tol, floor_, max_iter);
+    hipLaunchKernelGGL(k_init_vec, grid, block, 0, s, A.X0, A);
     DMRG_HIP(hipGetLastError());
-    DMRG_TRY(launch_diag_fold(plan, slot, A.coef, A.dfold, s));  // coefficients are fixed for the phase
-    const RayArgs ray = ray_args(A, 1);  // W(:, 0) and the rows of B(0, 0)
-    DMRG_TRY(launch_project(plan, slot, A.coef, A.V, A.W, s, A.active, A.dfold, &ray));
-    int i = 1;
+    DMRG_HIP(hipStreamWaitEvent(s, w->join, 0));
+    const RayArgs ray = ray_args(A, 1);
+    return launch_project(plan, slot, A.coef, A.V, A.W, s, A.active, A.dfold, &ray);
+}
+
+static uint64_t bits_of(double x) {
+    uint64_t u;
+    std::memcpy(&u, &x, 8);
+    return u;
+}
+
+constexpr int FIRST_CHUNK = 4;  // iterations of the first launch of a phase
+
+// Iterations still needed by the slowest active member, from its residual
+// decay over the phase so far (geometric model); cap when unknown.
+static int predict_iters(const std::vector<DavSummary> &sm, double tol, int cap) {
+    int need = 1;
+    for (const DavSummary &r : sm) {
+        if (!r.active) continue;
+        int k = cap;
+        if (r.iters > 1 && r.rnorm1 > 0.0 && r.rnorm > 0.0 && r.rnorm < r.rnorm1 && r.rnorm > tol) {
+            const double rate = std::log(r.rnorm / r.rnorm1) / (r.iters - 1);  // < 0
+            const double est = std::ceil(std::log(tol / r.rnorm) / rate);
+            k = (int)std::min<double>(cap, std::max(1.0, est));
+        }
+        need = std::max(need, k);
+    }
+    return std::min(need, cap);
+}
+
+// One phase (fixed projection precision) to tolerance tol, in launches of
+// iterations (captured hipGraphs when use_graph); after each launch the
+// per-member summary comes back to the host and decides about the next one.
+// psi_in: start vectors (nullptr: X0 already holds them).  fin_x0: every
+// launch ends with X0 = the current Ritz vectors (start of a following phase).
+static dmrg_status run_phase(dmrg_plan *plan, int slot, const double *psi_in, double tol, double floor_,
+                             int max_iter, bool use_graph, int chunk_max, bool fin_x0, hipStream_t s,
+                             int *iters_out, std::vector<DavSummary> &out) {
+    DavidsonWork *w = plan->dav;
+    const DavArgs &A = w->a;
+    if (psi_in) DMRG_HIP(hipMemcpyAsync((void *)A.X0, psi_in, (size_t)A.n * 8, hipMemcpyDeviceToDevice, s));
+    int i = 0;  // 0: the launch starts with the phase set-up
     int done = 0;
-    while (done < max_iter) {
-        int cnt = std::min(chunk, max_iter - done);
-        int inext = i;
+    int cnt = std::min({chunk_max, max_iter, FIRST_CHUNK});
+    std::vector<DavSummary> sm(A.nprob);
+    for (;;) {
+        const int i0 = (i == 0) ? 1 : i;
+        int inext = i0;
+        auto enqueue = [&](hipStream_t q) -> dmrg_status {
+            if (i == 0) DMRG_TRY(enqueue_setup(plan, slot, tol, floor_, max_iter, q));
+            DMRG_TRY(enqueue_iters(plan, slot, i0, cnt, &inext, q));
+            hipLaunchKernelGGL(k_summary, dim3((A.nprob + 63) / 64), dim3(64), 0, q, A);
+            if (fin_x0)
+                set_kb(w->kmax, [&](auto kb) {  // nvec <= kmax
+                    constexpr int KB = decltype(kb)::value;
+                    hipLaunchKernelGGL(k_finalize<KB>, dim3(A.nchunk), dim3(TPB), 0, q, A, (double *)A.X0);
+                });
+            DMRG_HIP(hipGetLastError());
+            return DMRG_OK;
+        };
         if (use_graph) {
-            auto key = std::make_tuple(slot, i, cnt, w->kmax, w->eig_solver);
+            auto key = std::make_tuple(slot, i * 2 + (fin_x0 ? 1 : 0), cnt, w->kmax, w->eig_solver, max_iter,
+                                       bits_of(tol), bits_of(floor_));
             auto it = w->graphs.find(key);
             if (it == w->graphs.end()) {
                 hipStream_t cs;
                 DMRG_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
                 hipGraph_t g;
                 DMRG_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-                dmrg_status st = enqueue_iters(plan, slot, i, cnt, &inext, cs);
+                dmrg_status st = enqueue(cs);
                 hipError_t ce = hipStreamEndCapture(cs, &g);
                 (void)hipStreamDestroy(cs);
                 if (st < 0) return st;
@@ -1086,20 +1184,24 @@ static dmrg_status run_phase(dmrg_plan *plan, int slot, const double *psi_in, do
                 it = w->graphs.emplace(key, ge).first;
             } else {
                 // the subspace sequence is deterministic: recompute the next i
-                int ii = i;
+                int ii = i0;
                 for (int q = 0; q < cnt; ++q) ii = (ii == w->kmax ? w->kmin : ii) + 1;
                 inext = ii;
             }
             DMRG_HIP(hipGraphLaunch(it->second, s));
         } else {
-            DMRG_TRY(enqueue_iters(plan, slot, i, cnt, &inext, s));
+            DMRG_TRY(enqueue(s));
         }
         i = inext;
         done += cnt;
-        DMRG_HIP(hipMemcpyAsync(w->h_nactive, A.nactive, 4, hipMemcpyDeviceToHost, s));
-        DMRG_HIP(hipStreamSynchronize(s));
-        if (*w->h_nactive <= 0) break;
+        DMRG_HIP(hipStreamSynchronize(s));  // k_summary wrote h_sum
+        sm.assign(w->h_sum, w->h_sum + A.nprob);
+        bool any = false;
+        for (const DavSummary &r : sm) any = any || r.active;
+        if (!any || done >= max_iter) break;
+        cnt = std::min(predict_iters(sm, tol, chunk_max), max_iter - done);
     }
+    out = sm;
     *iters_out = done;
     return DMRG_OK;
 }
@@ -1223,53 +1325,48 @@ dmrg_status dmrg_davidson(dmrg_plan *plan, const double *coef, const dmrg_davids
         DMRG_HIP(hipMemcpyAsync(A.coef, coef, plan->nterm_total * 8, hipMemcpyDeviceToDevice, s));
     DMRG_TRY(launch_diagonal(plan, A.coef, A.D, s));
 
-    std::vector<DavState> hs(plan->nprob);
-    std::vector<int> low_iters(plan->nprob, 0);
+    auto finalize = [&]() -> dmrg_status {  // psi = V y, ordered on the stream
+        set_kb(kmax, [&](auto kb) {  // nvec <= kmax
+            constexpr int KB = decltype(kb)::value;
+            hipLaunchKernelGGL(k_finalize<KB>, dim3(A.nchunk), dim3(TPB), 0, s, A, psi);
+        });
+        DMRG_HIP(hipGetLastError());
+        return DMRG_OK;
+    };
+    std::vector<DavSummary> hs, low;
     int done = 0;
     const bool two_phase = o.prec != DMRG_F64;
     if (two_phase) {
         double tl = o.tol_lowprec > 0 ? o.tol_lowprec : (o.prec == DMRG_F32 ? 1e-5 : 1e-3);
         tl = std::max(tl, o.tol);
-        DMRG_TRY(run_phase(plan, 1, psi, tl, o.precond_floor, o.max_iter, o.use_graph != 0, o.graph_chunk, s,
-                           &done));
-        set_kb(kmax, [&](auto kb) {  // nvec <= kmax
-            constexpr int KB = decltype(kb)::value;
-            hipLaunchKernelGGL(k_finalize<KB>, dim3(A.nchunk), dim3(TPB), 0, s, A, psi);
-        });
-        DMRG_HIP(hipGetLastError());
-        DMRG_HIP(hipMemcpyAsync(hs.data(), A.st, plan->nprob * sizeof(DavState), hipMemcpyDeviceToHost, s));
-        DMRG_HIP(hipStreamSynchronize(s));
-        for (int p = 0; p < plan->nprob; ++p) {
-            if (hs[p].bad_start == 1) return set_error(DMRG_E_NONFINITE, "member %d: zero or non-finite start", p);
-            low_iters[p] = hs[p].iters;
-        }
+        // with refinement the phase-1 Ritz vectors stay in X0 as the start of phase 2
+        DMRG_TRY(run_phase(plan, 1, psi, tl, o.precond_floor, o.max_iter, o.use_graph != 0, o.graph_chunk,
+                           o.refine != 0, s, &done, low));
+        if (!o.refine) DMRG_TRY(finalize());
+        for (int p = 0; p < plan->nprob; ++p)
+            if (low[p].bad_start == 1) return set_error(DMRG_E_NONFINITE, "member %d: zero or non-finite start", p);
+        hs = low;
     }
-    std::vector<DavState> low = hs;
     if (!two_phase || o.refine) {
-        DMRG_TRY(run_phase(plan, 0, psi, o.tol, o.precond_floor, o.max_iter, o.use_graph != 0, o.graph_chunk, s,
-                           &done));
-        set_kb(kmax, [&](auto kb) {  // nvec <= kmax
-            constexpr int KB = decltype(kb)::value;
-            hipLaunchKernelGGL(k_finalize<KB>, dim3(A.nchunk), dim3(TPB), 0, s, A, psi);
-        });
-        DMRG_HIP(hipGetLastError());
-        DMRG_HIP(hipMemcpyAsync(hs.data(), A.st, plan->nprob * sizeof(DavState), hipMemcpyDeviceToHost, s));
-        DMRG_HIP(hipStreamSynchronize(s));
+        DMRG_TRY(run_phase(plan, 0, two_phase ? nullptr : psi, o.tol, o.precond_floor, o.max_iter,
+                           o.use_graph != 0, o.graph_chunk, false, s, &done, hs));
+        DMRG_TRY(finalize());
     }
+    const bool both = two_phase && o.refine;
     dmrg_status ret = DMRG_OK;
     for (int p = 0; p < plan->nprob; ++p) {
-        const DavState &S = hs[p];
+        const DavSummary &S = hs[p];
         if (S.bad_start == 1) return set_error(DMRG_E_NONFINITE, "member %d: zero or non-finite start vector", p);
         if (S.bad_start == 2) ret = set_error(DMRG_E_NONFINITE, "member %d: non-finite iterate", p);
-        if (energy) energy[p] = S.lambda;
+        if (energy) energy[p] = S.energy;
         if (info) {
             dmrg_davidson_info &I = info[p];
-            I.energy = S.lambda;
+            I.energy = S.energy;
             I.residual = S.rnorm;
-            I.iterations = S.iters + (two_phase && o.refine ? low_iters[p] : 0);
-            I.iterations_low = two_phase ? low_iters[p] : 0;
-            I.projections = S.nproj + (two_phase && o.refine ? low[p].nproj : 0);
-            I.restarts = S.restarts + (two_phase && o.refine ? low[p].restarts : 0);
+            I.iterations = S.iters + (both ? low[p].iters : 0);
+            I.iterations_low = two_phase ? low[p].iters : 0;
+            I.projections = S.nproj + (both ? low[p].nproj : 0);
+            I.restarts = S.restarts + (both ? low[p].restarts : 0);
             I.converged = S.converged;
             I.breakdown = S.breakdown;
         }
