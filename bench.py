@@ -58,6 +58,29 @@ def timed_projection(plan, psi, y, prec, reps, torch):
     return e0.elapsed_time(e1) * 1e-3 / reps
 
 
+def projection_stats(plan, psi, y, prec, torch, reps=200, flush=None):
+    """Per-call durations of the projection (a HIP event pair around each call on the
+    launch stream): median, p10, p90 in microseconds.  With `flush` (a device buffer),
+    each call is preceded by a write of that buffer, which evicts L2 and the
+    Infinity Cache (cold-cache variant)."""
+    import numpy as np
+
+    s = torch.cuda.current_stream()
+    for _ in range(20):
+        plan.project_raw(psi, prec=prec, out=y)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in ev:
+        if flush is not None:
+            flush.fill_(1.0)
+        a.record(s)
+        plan.project_raw(psi, prec=prec, out=y)
+        b.record(s)
+    torch.cuda.synchronize()
+    d = np.array([a.elapsed_time(b) * 1e3 for a, b in ev])
+    return {"median_us": float(np.median(d)), "p10_us": float(np.percentile(d, 10)),
+            "p90_us": float(np.percentile(d, 90))}
+
+
 def cpu_baseline(p, x0):
     """The FP64 oracle (NumPy + OpenBLAS) on the host: one full Davidson solve
     of the same workload from the same start vector, plus projection timing."""
@@ -254,6 +277,14 @@ def main():
             proj[prec] = {"us": t * 1e6, "tflops": plan.flop / t * 1e-12}
         extra["projection"] = proj
         log(f"projection: {proj}")
+        flush = torch.empty(64 << 20, dtype=torch.float64, device=dev)  # 512 MiB
+        stats = {}
+        for prec, pl in (("f64", plan), (args.prec, plan), ("bf16", planb)):
+            stats[prec] = {"warm": projection_stats(pl, psi, y, prec, torch),
+                           "cold": projection_stats(pl, psi, y, prec, torch, reps=50, flush=flush)}
+        del flush
+        extra["projection_percall"] = stats
+        log(f"projection per call: {stats}")
         extra["mixed_vs_fp64_time_ratio"] = (dt / args.steps * 1e3) / extra["fp64_solve"]["ms_per_solve"]
 
     # roofline of the dominant kernel: the FP64 projection, bound by HBM bytes at

@@ -39,6 +39,7 @@
 namespace dmrg {
 
 constexpr int TPB = GEMV_THREADS;
+constexpr int RT = 1024;  // threads of the Rayleigh-step workgroup (the sums of the tile rows)
 constexpr int PR_R = KM;      // partial-row column of ||r||^2
 constexpr int PR_T = KM + 1;  // partial-row column of ||t||^2
 
@@ -49,7 +50,9 @@ struct DavState {
     double Y[KM * KM];   // eigenvectors of B (column c = Y[r * KM + c]), ascending
     double theta[KM];    // Ritz values, ascending
     double lambda, sigma, dmin, rnorm, rnorm1, tn0, scale, tol, floor_;
+    double rbest;  // smallest residual of the phase that halved the one before it
     int32_t converged, breakdown, iters, nproj, restarts, dgks, nvec, max_iter, bad_start;
+    int32_t stag_window, rbest_it, stagnated;  // stagnation exit of a reduced-precision phase
 };
 
 // Per-member results copied to the host after every launch of iterations.
@@ -124,9 +127,10 @@ __device__ __forceinline__ Chunk chunk_of(const DavArgs &w, int c) {
 // Lanes per column for all-column reductions: the largest power of two G <= 64
 // with G * ncols <= TPB, so each column is owned by an aligned group of G lanes
 // inside one wavefront and combined with shuffles.
+template <int NT = TPB>
 static __device__ __forceinline__ int lanes_per_column(int ncols) {
     int G = 64;
-    while (G > 1 && G * ncols > TPB) G >>= 1;
+    while (G > 1 && G * ncols > NT) G >>= 1;
     return G;
 }
 
@@ -134,9 +138,10 @@ static __device__ __forceinline__ int lanes_per_column(int ncols) {
 // col(q) = q for q < i and KM + (q - i) beyond (the norm columns); element
 // (r, col) at part[col * ld + r].  Each lane keeps 4 running sums (rows
 // interleaved), combined in a fixed order; all threads must call; out is shared.
+template <int NT = TPB>
 static __device__ void sum_rows(const double *__restrict__ part, int64_t ld, int r0, int r1, int i, int nq,
                                 double *out) {
-    const int G = lanes_per_column(nq);
+    const int G = lanes_per_column<NT>(nq);
     const int q = threadIdx.x / G, l = threadIdx.x % G;
     double v = 0.0;
     if (q < nq) {
@@ -179,20 +184,40 @@ static __device__ double block_min(double v, double *lds) {
 
 static __device__ __forceinline__ void deactivate(const DavArgs &w, int member) { w.active[member] = 0; }
 
-// Stop test on the residual norm: 0 go on, 1 converged, 2 iteration limit, 3 non-finite.
+// Stop test on the residual norm: 0 go on, 1 converged, 2 iteration limit,
+// 3 non-finite, 4 stagnated (reduced-precision phase only).  Reads only state
+// written by earlier kernels, so every block of a kernel decides alike.
 static __device__ __forceinline__ int stop_code(const DavState &S, double rr) {
     const double rn = sqrt(rr);
     if (!(rn == rn) || isinf(rn)) return 3;
     if (rn <= S.tol) return 1;
     if (S.iters >= S.max_iter) return 2;
+    if (S.stagnated) return 4;
     return 0;
+}
+
+// Stagnation bookkeeping at the start of a Rayleigh step (one thread per
+// member): the residual of the previous iteration either halves the best one
+// so far or counts toward the window.
+static __device__ __forceinline__ void track_stagnation(DavState &S) {
+    if (S.stag_window <= 0 || S.iters < 1) return;
+    if (S.rnorm < 0.5 * S.rbest) {
+        S.rbest = S.rnorm;
+        S.rbest_it = S.iters;
+    } else if (S.iters - S.rbest_it >= S.stag_window) {
+        S.stagnated = 1;
+    }
 }
 
 // ------------------------------------------------------------------ init kernels
 
 // Phase start of member m: options, flags and counters.
-static __device__ void set_state(const DavArgs &w, int m, double tol, double floor_, int max_iter) {
+static __device__ void set_state(const DavArgs &w, int m, double tol, double floor_, int max_iter, int stag) {
     DavState &S = w.st[m];
+    S.stag_window = stag;
+    S.rbest = INFINITY;
+    S.rbest_it = 0;
+    S.stagnated = 0;
     S.tol = tol;
     S.floor_ = floor_;
     S.max_iter = max_iter;
@@ -213,10 +238,10 @@ static __device__ void set_state(const DavArgs &w, int m, double tol, double flo
 // Phase start (the first block of each member resets its state); partial
 // rows: ||psi||^2 (column 0) and min D (column 1) of each chunk.
 __global__ __launch_bounds__(TPB) void k_init_norm(const double *__restrict__ psi, DavArgs w, double tol,
-                                                   double floor_, int max_iter) {
+                                                   double floor_, int max_iter, int stag) {
     __shared__ double lds[4];
     const Chunk ck = chunk_of(w, blockIdx.x);
-    if ((int)blockIdx.x == ck.c0 && threadIdx.x == 0) set_state(w, ck.member, tol, floor_, max_iter);
+    if ((int)blockIdx.x == ck.c0 && threadIdx.x == 0) set_state(w, ck.member, tol, floor_, max_iter, stag);
     double ss = 0.0, mn = INFINITY;
     for (int64_t e = ck.e0 + threadIdx.x; e < ck.e1; e += TPB) {
         ss += psi[e] * psi[e];
@@ -349,6 +374,15 @@ static __device__ void eig_border(int n, const double *bcol, EigLds &L) {
     wave_sync();
 }
 
+// 1/x from the hardware estimate and two Newton steps (a few ulps)
+static __device__ __forceinline__ double rcp_nr(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
 // f(o + t) and its derivative, with the pole differences taken relative to o
 static __device__ __forceinline__ double secular_f(const EigLds &L, int k, double beta, double o, double t,
                                                    double &fp) {
@@ -356,7 +390,7 @@ static __device__ __forceinline__ double secular_f(const EigLds &L, int k, doubl
     fp = -1.0;
     for (int j = 0; j < k; ++j) {
         const double dl = (L.dk[j] - o) - t;
-        const double q = L.zk[j] / dl;
+        const double q = L.zk[j] * rcp_nr(dl);
         fv -= L.zk[j] * q;
         fp -= q * q;
     }
@@ -465,8 +499,8 @@ static __device__ int eig_secular(int n, EigLds &L) {
         const int j = lane;
         const double dj = L.dk[j];
         double prod = -((dj - L.org[j]) - L.tau[j]) * ((dj - L.org[j + 1]) - L.tau[j + 1]);
-        for (int l = 0; l < j; ++l) prod *= ((dj - L.org[l]) - L.tau[l]) / (dj - L.dk[l]);
-        for (int l = j + 1; l < k; ++l) prod *= ((dj - L.org[l + 1]) - L.tau[l + 1]) / (dj - L.dk[l]);
+        for (int l = 0; l < j; ++l) prod *= ((dj - L.org[l]) - L.tau[l]) * rcp_nr(dj - L.dk[l]);
+        for (int l = j + 1; l < k; ++l) prod *= ((dj - L.org[l + 1]) - L.tau[l + 1]) * rcp_nr(dj - L.dk[l]);
         L.zh[j] = copysign(sqrt(fmax(prod, 0.0)), L.zk[j]);
     }
     // entries: roots 0..k, then the deflated poles; ascending order, ties by entry
@@ -491,11 +525,12 @@ static __device__ int eig_secular(int n, EigLds &L) {
             const double o = L.org[e], t = L.tau[e];
             double nrm = 1.0;
             for (int j = 0; j < k; ++j) {
-                const double u = L.zh[j] / ((L.dk[j] - o) - t);
+                const double u = L.zh[j] * rcp_nr((L.dk[j] - o) - t);
+                L.A[L.kidx[j]][c] = u;
                 nrm += u * u;
             }
             const double sc = 1.0 / sqrt(nrm);
-            for (int j = 0; j < k; ++j) L.A[L.kidx[j]][c] = sc * (L.zh[j] / ((L.dk[j] - o) - t));
+            for (int j = 0; j < k; ++j) L.A[L.kidx[j]][c] *= sc;
             L.A[m][c] = -sc;
         } else {
             L.A[L.didx[e - k - 1]][c] = 1.0;
@@ -507,13 +542,13 @@ static __device__ int eig_secular(int n, EigLds &L) {
 
 // All threads: Y = Vv U and the sorted Ritz values (main path).
 static __device__ void eig_assemble(DavState &S, int n, EigLds &L) {
-    for (int e = threadIdx.x; e < n * n; e += TPB) {
+    for (int e = threadIdx.x; e < n * n; e += RT) {
         const int r = e / n, c = e - r * n;
         double acc = 0.0;
         for (int q = 0; q < n; ++q) acc += L.Vv[r][q] * L.A[q][c];
         S.Y[r * KM + c] = acc;
     }
-    for (int c = threadIdx.x; c < n; c += TPB) S.theta[c] = L.val[L.inv[c]];
+    for (int c = threadIdx.x; c < n; c += RT) S.theta[c] = L.val[L.inv[c]];
     if (threadIdx.x == 0) {
         S.lambda = L.val[L.inv[0]];
         S.sigma = fmin(S.lambda, S.dmin);
@@ -639,15 +674,16 @@ static __device__ void eig_jacobi(DavState &S, int n, EigLds &L) {
 
 // Rayleigh step, one workgroup per member: B(:, i-1) = sum of the member's
 // tile rows, then the Ritz pairs of B[:i, :i].
-__global__ __launch_bounds__(TPB) void k_rayleigh(DavArgs w, const int32_t *__restrict__ slot_begin, int i,
+__global__ __launch_bounds__(RT) void k_rayleigh(DavArgs w, const int32_t *__restrict__ slot_begin, int i,
                                                   int jacobi_only) {
     __shared__ EigLds L;
     __shared__ double bcol[KM];
     const int member = blockIdx.x;
     if (!w.active[member]) return;
     DavState &S = w.st[member];
+    if (threadIdx.x == 0) track_stagnation(S);  // before this step counts itself
     if (threadIdx.x < 64) eig_load(S, i, L);  // independent of the sums: overlaps them
-    sum_rows(w.ptile, w.tile_ld, slot_begin[member], slot_begin[member + 1], i, i, bcol);
+    sum_rows<RT>(w.ptile, w.tile_ld, slot_begin[member], slot_begin[member + 1], i, i, bcol);
     if (threadIdx.x < 64) {
         eig_border(i, bcol, L);
         const int fb = jacobi_only ? 1 : eig_secular(i, L);
@@ -790,6 +826,17 @@ __global__ __launch_bounds__(TPB) void k_orth(DavArgs w, int i, const double *__
     const int member = ck.member;
     if (!w.active[member]) return;
     DavState &S = w.st[member];
+    // this thread's element (a chunk holds at most TPB): its loads overlap the sums
+    const int64_t n = w.n, e = ck.e0 + threadIdx.x;
+    const bool has = e < ck.e1;
+    double t = 0.0, v[KB];
+#pragma unroll
+    for (int j = 0; j < KB; ++j) v[j] = 0.0;
+    if (has) {
+        t = w.T[e];
+#pragma unroll
+        for (int j = 0; j < KB; ++j) v[j] = w.V[(int64_t)min(j, i - 1) * n + e];
+    }
     sum_rows(pin, w.nchunk, ck.c0, ck.c1, i, i + 2, sums);
     const double rr = sums[i], tt = sums[i + 1];
     double ss = 0.0;
@@ -816,34 +863,23 @@ __global__ __launch_bounds__(TPB) void k_orth(DavArgs w, int i, const double *__
         }
     }
     if (code || brk) return;
-    double s[KB];
-#pragma unroll
-    for (int j = 0; j < KB; ++j) s[j] = (j < i) ? sums[j] : 0.0;
     const double sc = dg ? 0.0 : 1.0 / sqrt(tt - ss);
-    const int64_t n = w.n;
     double acc[KB + 1];
 #pragma unroll
     for (int j = 0; j < KB + 1; ++j) acc[j] = 0.0;
-    for (int64_t e = ck.e0 + threadIdx.x; e < ck.e1; e += TPB) {
-        double v[KB];
-        double t = w.T[e];
 #pragma unroll
-        for (int j = 0; j < KB; ++j) v[j] = w.V[(int64_t)min(j, i - 1) * n + e];
-#pragma unroll
-        for (int j = 0; j < KB; ++j) {
-            v[j] = (j < i) ? v[j] : 0.0;
-            t -= v[j] * s[j];
-        }
-        if (!dg) {
-            w.V[(int64_t)i * n + e] = t * sc;
-            continue;
-        }
-        w.T[e] = t;
-#pragma unroll
-        for (int j = 0; j < KB; ++j) acc[j] += v[j] * t;
-        acc[KB] += t * t;
+    for (int j = 0; j < KB; ++j) {
+        v[j] = (j < i) ? v[j] : 0.0;
+        t -= v[j] * ((j < i) ? sums[j] : 0.0);
     }
-    if (!dg) return;
+    if (!dg) {
+        if (has) w.V[(int64_t)i * n + e] = t * sc;
+        return;
+    }
+    if (has) w.T[e] = t;
+#pragma unroll
+    for (int j = 0; j < KB; ++j) acc[j] = v[j] * t;
+    acc[KB] = t * t;
     block_reduce<KB + 1>(acc, KB + 1, lds);
     if (threadIdx.x == 0) {
         const int64_t ld = w.nchunk;
@@ -866,6 +902,16 @@ __global__ __launch_bounds__(TPB) void k_append(DavArgs w, int i) {
     if (!w.active[member]) return;
     DavState &S = w.st[member];
     if (!S.dgks) return;
+    const int64_t n = w.n, e = ck.e0 + threadIdx.x;
+    const bool has = e < ck.e1;
+    double t = 0.0, v[KB];
+#pragma unroll
+    for (int j = 0; j < KB; ++j) v[j] = 0.0;
+    if (has) {  // overlaps the sums
+        t = w.T[e];
+#pragma unroll
+        for (int j = 0; j < KB; ++j) v[j] = w.V[(int64_t)min(j, i - 1) * n + e];
+    }
     sum_rows(w.pc, w.nchunk, ck.c0, ck.c1, i, i + 2, sums);
     double ss = 0.0;
     for (int j = 0; j < i; ++j) ss += sums[j] * sums[j];
@@ -877,20 +923,9 @@ __global__ __launch_bounds__(TPB) void k_append(DavArgs w, int i) {
         }
         return;
     }
-    double s2[KB];
 #pragma unroll
-    for (int j = 0; j < KB; ++j) s2[j] = (j < i) ? sums[j] : 0.0;
-    const double sc = 1.0 / nrm;
-    const int64_t n = w.n;
-    for (int64_t e = ck.e0 + threadIdx.x; e < ck.e1; e += TPB) {
-        double t = w.T[e];
-        double v[KB];
-#pragma unroll
-        for (int j = 0; j < KB; ++j) v[j] = w.V[(int64_t)min(j, i - 1) * n + e];
-#pragma unroll
-        for (int j = 0; j < KB; ++j) t -= v[j] * s2[j];
-        w.V[(int64_t)i * n + e] = t * sc;
-    }
+    for (int j = 0; j < KB; ++j) t -= v[j] * ((j < i) ? sums[j] : 0.0);
+    if (has) w.V[(int64_t)i * n + e] = t * (1.0 / nrm);
 }
 
 // psi = V(:, :nvec) y (normalized Ritz vector of each member)
@@ -1058,7 +1093,7 @@ static dmrg_status enqueue_iters(dmrg_plan *plan, int slot, int i, int count, in
     for (int it = 0; it < count; ++it) {
         const bool restart = (i == kmax);
         // W(:, i-1) and its Rayleigh rows came from the previous projection
-        hipLaunchKernelGGL(k_rayleigh, dim3(A.nprob), block, 0, s, A, slot_begin, i, w->eig_solver);
+        hipLaunchKernelGGL(k_rayleigh, dim3(A.nprob), dim3(RT), 0, s, A, slot_begin, i, w->eig_solver);
         set_kb(i, [&](auto kb) {
             constexpr int KB = decltype(kb)::value;
             hipLaunchKernelGGL(k_ritz<KB>, grid, block, 0, s, A, i, restart ? 1 : 0);
@@ -1099,7 +1134,8 @@ static dmrg_status enqueue_setup(dmrg_plan *plan, int slot, double tol, double f
     DMRG_HIP(hipStreamWaitEvent(w->side, w->fork, 0));
     DMRG_TRY(launch_diag_fold(plan, slot, A.coef, A.dfold, w->side));  // coefficients are fixed for the phase
     DMRG_HIP(hipEventRecord(w->join, w->side));
-    hipLaunchKernelGGL(k_init_norm, grid, block, 0, s, A.X0, A, tol, floor_, max_iter);
+    // a reduced-precision phase ends early when its residual stops halving (5 iterations)
+    hipLaunchKernelGGL(k_init_norm, grid, block, 0, s, A.X0, A, tol, floor_, max_iter, slot == 0 ? 0 : 5);
     hipLaunchKernelGGL(k_init_vec, grid, block, 0, s, A.X0, A);
     DMRG_HIP(hipGetLastError());
     DMRG_HIP(hipStreamWaitEvent(s, w->join, 0));
