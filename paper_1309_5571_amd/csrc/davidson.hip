@@ -7,10 +7,9 @@
 //
 //   projection  W(:, i-1) = H V(:, i-1) (line 2); every output tile also
 //               writes its partial row of V(:, :i)^T W(:, i-1)
-//   k_rayleigh  one workgroup per member: B(:, i-1) from the tile rows
-//               (line 3), then the small eigenproblem (line 4) by a
-//               warm-started parallel Jacobi in one wavefront
-//   k_ritz      x = V y, r = W y - lambda x, ||r|| (lines 5-7),
+//   k_ritz      B(:, i-1) from the tile rows (line 3) and the small
+//               eigenproblem (line 4), solved redundantly in every block;
+//               x = V y, r = W y - lambda x, ||r|| (lines 5-7),
 //               t = r / (D - sigma) (line 10, shifted diagonal preconditioner),
 //               s = V^T t (line 12, first pass): one sweep over V and W
 //   k_restart   (when i = kmax) V <- V Y(:, :kmin), W <- W Y(:, :kmin), s = V^T t
@@ -39,16 +38,18 @@
 namespace dmrg {
 
 constexpr int TPB = GEMV_THREADS;
-constexpr int RT = 1024;  // threads of the Rayleigh-step workgroup (the sums of the tile rows)
+constexpr int FUSED_RAYLEIGH_MAX_CHUNKS = 1024;  // see enqueue_iters
 constexpr int PR_R = KM;      // partial-row column of ||r||^2
 constexpr int PR_T = KM + 1;  // partial-row column of ||t||^2
 
 // The Rayleigh matrix B = V^T H V itself is not stored: after every Rayleigh
 // step Y^T B Y = diag(theta) up to the Jacobi threshold, which is all the next
 // step needs (it only adds a row and column to B).
+// Y and theta are double-buffered by the parity of the iteration that wrote them
+// (the blocks of an iteration read the previous buffer while one of them writes).
 struct DavState {
-    double Y[KM * KM];   // eigenvectors of B (column c = Y[r * KM + c]), ascending
-    double theta[KM];    // Ritz values, ascending
+    double Y[2][KM * KM];  // eigenvectors of B (column c = Y[b][r * KM + c]), ascending
+    double theta[2][KM];   // Ritz values, ascending
     double lambda, sigma, dmin, rnorm, rnorm1, tn0, scale, tol, floor_;
     double rbest;  // smallest residual of the phase that halved the one before it
     int32_t converged, breakdown, iters, nproj, restarts, dgks, nvec, max_iter, bad_start;
@@ -91,7 +92,8 @@ struct DavidsonWork {
     DavSummary *h_sum = nullptr;  // pinned, mapped [nprob]
     hipStream_t side = nullptr;   // second branch of the phase set-up
     hipEvent_t fork = nullptr, join = nullptr;
-    // graphs by (slot, 2 * first i (0: with the phase set-up) + finalize-into-X0, iterations, kmax, eig_solver,
+    // graphs by (slot, 4 * first i (0: with the phase set-up) + 2 * finalize-into-X0 + parity of the
+    // first iteration, iterations, kmax, eig_solver,
     // max_iter, tol bits, floor bits)
     std::map<std::tuple<int, int, int, int, int, int, uint64_t, uint64_t>, hipGraphExec_t> graphs;
     std::vector<void *> owned;
@@ -232,7 +234,7 @@ static __device__ void set_state(const DavArgs &w, int m, double tol, double flo
     S.restarts = 0;
     S.rnorm = 0.0;
     S.rnorm1 = 0.0;
-    S.Y[0] = 1.0;
+    S.Y[0][0] = S.Y[1][0] = 1.0;
 }
 
 // Phase start (the first block of each member resets its state); partial
@@ -341,15 +343,16 @@ static __device__ __forceinline__ void rr_pair(int k, int step, int n2, int &p, 
 
 // One wavefront: the arrowhead's diagonal block and the extended eigenvectors.
 // Independent of the new column, so it overlaps the sums that produce it.
-static __device__ void eig_load(const DavState &S, int n, EigLds &L) {
+static __device__ void eig_load(const DavState &S, int n, int ob, EigLds &L) {
     const int lane = threadIdx.x & 63;
     const int m = n - 1;
+    const double *Yo = S.Y[ob], *to = S.theta[ob];
     for (int e = lane; e < n * n; e += 64) {
         const int r = e / n, c = e - r * n;
-        L.A[r][c] = (r == c && r < m) ? S.theta[r] : 0.0;
-        L.Vv[r][c] = (r < m && c < m) ? S.Y[r * KM + c] : (r == c ? 1.0 : 0.0);
+        L.A[r][c] = (r == c && r < m) ? to[r] : 0.0;
+        L.Vv[r][c] = (r < m && c < m) ? Yo[r * KM + c] : (r == c ? 1.0 : 0.0);
     }
-    for (int j = lane; j < m; j += 64) L.d[j] = S.theta[j];
+    for (int j = lane; j < m; j += 64) L.d[j] = to[j];
 }
 
 // One wavefront: border z = Y^T b and the corner, and the threshold.
@@ -540,15 +543,23 @@ static __device__ int eig_secular(int n, EigLds &L) {
     return 0;
 }
 
-// All threads: Y = Vv U and the sorted Ritz values (main path).
-static __device__ void eig_assemble(DavState &S, int n, EigLds &L) {
-    for (int e = threadIdx.x; e < n * n; e += RT) {
+// Column c of the new eigenvectors: Vv U(:, c) on the main path, the rotated
+// Vv's column inv[c] after Jacobi.
+static __device__ __forceinline__ double eig_y(const EigLds &L, int n, int r, int c) {
+    if (L.path) return L.Vv[r][L.inv[c]];
+    double acc = 0.0;
+    for (int q = 0; q < n; ++q) acc += L.Vv[r][q] * L.A[q][c];
+    return acc;
+}
+
+// All threads of the member's first block: Y and theta into buffer nb, and the
+// scalars of the iteration.
+static __device__ void eig_store(DavState &S, int n, int nb, const EigLds &L) {
+    for (int e = threadIdx.x; e < n * n; e += TPB) {
         const int r = e / n, c = e - r * n;
-        double acc = 0.0;
-        for (int q = 0; q < n; ++q) acc += L.Vv[r][q] * L.A[q][c];
-        S.Y[r * KM + c] = acc;
+        S.Y[nb][r * KM + c] = eig_y(L, n, r, c);
     }
-    for (int c = threadIdx.x; c < n; c += RT) S.theta[c] = L.val[L.inv[c]];
+    for (int c = threadIdx.x; c < n; c += TPB) S.theta[nb][c] = L.val[L.inv[c]];
     if (threadIdx.x == 0) {
         S.lambda = L.val[L.inv[0]];
         S.sigma = fmin(S.lambda, S.dmin);
@@ -558,8 +569,9 @@ static __device__ void eig_assemble(DavState &S, int n, EigLds &L) {
     }
 }
 
-// One wavefront: the Jacobi fallback on the arrowhead in L.A, L.Vv; writes the state.
-static __device__ void eig_jacobi(DavState &S, int n, EigLds &L) {
+// One wavefront: the Jacobi fallback on the arrowhead in L.A, L.Vv; leaves the
+// rotated Vv, the eigenvalues in L.val and their ascending order in L.inv.
+static __device__ void eig_jacobi(int n, EigLds &L) {
     const int lane = threadIdx.x & 63;
     const double tol = L.tol;
     const int n2 = (n + 1) & ~1;
@@ -644,8 +656,7 @@ static __device__ void eig_jacobi(DavState &S, int n, EigLds &L) {
         }
         if (!__any(rotated)) break;
     }
-    // ascending order (stable rank); c[] and s[] are free now: reuse as scratch
-    int *order = reinterpret_cast<int *>(&L.c[0]);
+    // ascending order (stable rank)
     for (int a = lane; a < n; a += 64) {
         const double da = L.A[a][a];
         int rank = 0;
@@ -653,28 +664,33 @@ static __device__ void eig_jacobi(DavState &S, int n, EigLds &L) {
             const double db = L.A[b][b];
             rank += (db < da) || (db == da && b < a);
         }
-        order[rank] = a;
+        L.val[a] = da;
+        L.inv[rank] = a;
     }
     wave_sync();
-    for (int e = lane; e < n * n; e += 64) {
-        const int r = e / n, c = e - r * n;
-        S.Y[r * KM + c] = L.Vv[r][order[c]];
-    }
-    for (int c = lane; c < n; c += 64) S.theta[c] = L.A[order[c]][order[c]];
-    if (lane == 0) {
-        S.lambda = L.A[order[0]][order[0]];
-        S.sigma = fmin(S.lambda, S.dmin);
-        S.iters += 1;
-        S.nproj += 1;
-        S.nvec = n;
-    }
 }
 
 // ------------------------------------------------------------------ iteration kernels
 
-// Rayleigh step, one workgroup per member: B(:, i-1) = sum of the member's
-// tile rows, then the Ritz pairs of B[:i, :i].
-__global__ __launch_bounds__(RT) void k_rayleigh(DavArgs w, const int32_t *__restrict__ slot_begin, int i,
+// Small eigenproblem of the Rayleigh step for one member in one block (all
+// threads call): B(:, i-1) from the member's tile rows, then the arrowhead
+// solve (Jacobi fallback) by wavefront 0.  Results stay in L.
+static __device__ void rayleigh_solve(DavState &S, const DavArgs &w, const int32_t *__restrict__ slot_begin,
+                                      int member, int i, int par, int jacobi_only, EigLds &L, double *bcol) {
+    if (threadIdx.x < 64) eig_load(S, i, par ^ 1, L);
+    sum_rows(w.ptile, w.tile_ld, slot_begin[member], slot_begin[member + 1], i, i, bcol);
+    if (threadIdx.x < 64) {
+        eig_border(i, bcol, L);
+        const int fb = jacobi_only ? 1 : eig_secular(i, L);
+        if (fb) eig_jacobi(i, L);
+        if (threadIdx.x == 0) L.path = fb;
+    }
+    __syncthreads();
+}
+
+// Rayleigh step as its own kernel, one block per member (plans with many
+// chunks per member): stores Y, theta (buffer par) and the scalars.
+__global__ __launch_bounds__(TPB) void k_rayleigh(DavArgs w, const int32_t *__restrict__ slot_begin, int i, int par,
                                                   int jacobi_only) {
     __shared__ EigLds L;
     __shared__ double bcol[KM];
@@ -682,60 +698,80 @@ __global__ __launch_bounds__(RT) void k_rayleigh(DavArgs w, const int32_t *__res
     if (!w.active[member]) return;
     DavState &S = w.st[member];
     if (threadIdx.x == 0) track_stagnation(S);  // before this step counts itself
-    if (threadIdx.x < 64) eig_load(S, i, L);  // independent of the sums: overlaps them
-    sum_rows<RT>(w.ptile, w.tile_ld, slot_begin[member], slot_begin[member + 1], i, i, bcol);
-    if (threadIdx.x < 64) {
-        eig_border(i, bcol, L);
-        const int fb = jacobi_only ? 1 : eig_secular(i, L);
-        if (fb) eig_jacobi(S, i, L);
-        if (threadIdx.x == 0) L.path = fb;
-    }
-    __syncthreads();
-    if (!L.path) eig_assemble(S, i, L);
+    rayleigh_solve(S, w, slot_begin, member, i, par, jacobi_only, L, bcol);
+    eig_store(S, i, par, L);
 }
 
-// x = V y, r = W y - lambda x, t = r / (D - sigma); partial row: V^T t, ||r||^2, ||t||^2.
-template <int KB>
-__global__ __launch_bounds__(TPB) void k_ritz(DavArgs w, int i, int restart) {
+// Ritz vector, residual and correction: x = V y, r = W y - lambda x,
+// t = r / (D - sigma); partial row: V^T t, ||r||^2, ||t||^2.  With SOLVE the
+// Rayleigh step runs here too: every block of a member sums the member's tile
+// rows and solves the small eigenproblem itself (identical inputs and order,
+// hence identical results in every block) while its own rows of V and W are
+// loaded, and the member's first block stores Y and theta (buffer par; the
+// previous iteration's are read from par ^ 1).  Without SOLVE, y, lambda and
+// sigma come from k_rayleigh.
+template <int KB, bool SOLVE>
+__global__ __launch_bounds__(TPB) void k_ritz(DavArgs w, const int32_t *__restrict__ slot_begin, int i, int restart,
+                                              int par, int jacobi_only) {
+    __shared__ EigLds L;
+    __shared__ double bcol[KM];
+    __shared__ double y0[KM];
     __shared__ double lds[4 * (KB + 2)];
+    constexpr bool PRE = SOLVE && KB <= 16;  // keep the rows in registers across the solve
     const int c = blockIdx.x;
     const Chunk ck = chunk_of(w, c);
-    if (!w.active[ck.member]) return;
-    const DavState &S = w.st[ck.member];
-    const int64_t n = w.n;
-    double y[KB];
+    const int member = ck.member;
+    if (!w.active[member]) return;
+    DavState &S = w.st[member];
+    const bool writer = c == ck.c0;
+    const int64_t n = w.n, e = ck.e0 + threadIdx.x;
+    const bool has = e < ck.e1;
+    double v[KB], wv[KB], dv = 0.0;
 #pragma unroll
-    for (int j = 0; j < KB; ++j) y[j] = (j < i) ? S.Y[j * KM] : 0.0;
-    const double lam = S.lambda, sig = S.sigma, fl = S.floor_;
+    for (int j = 0; j < KB; ++j) v[j] = wv[j] = 0.0;
+    auto load_rows = [&]() {
+        if (has) {
+            dv = w.D[e];
+#pragma unroll
+            for (int j = 0; j < KB; ++j) {
+                v[j] = w.V[(int64_t)min(j, i - 1) * n + e];
+                wv[j] = w.W[(int64_t)min(j, i - 1) * n + e];
+            }
+        }
+    };
+    if (PRE) load_rows();
+    double lam;
+    if (SOLVE) {
+        if (writer && threadIdx.x == 0) track_stagnation(S);  // before this step counts itself
+        rayleigh_solve(S, w, slot_begin, member, i, par, jacobi_only, L, bcol);
+        for (int r = threadIdx.x; r < i; r += TPB) y0[r] = eig_y(L, i, r, 0);
+        if (writer) eig_store(S, i, par, L);
+        lam = L.val[L.inv[0]];
+    } else {
+        for (int r = threadIdx.x; r < i; r += TPB) y0[r] = S.Y[par][r * KM];
+        lam = S.lambda;
+    }
+    if (!PRE) load_rows();
+    __syncthreads();
+    const double sig = fmin(lam, S.dmin), fl = S.floor_;
+    double x = 0.0, wy = 0.0;
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+        const double yj = (j < i) ? y0[j] : 0.0;
+        v[j] = (j < i) ? v[j] : 0.0;
+        x += v[j] * yj;
+        wy += wv[j] * yj;
+    }
+    const double r = wy - lam * x;
+    double den = dv - sig;
+    if (fabs(den) < fl) den = (den < 0.0) ? -fl : fl;
+    const double t = has ? r / den : 0.0;
+    if (has) w.T[e] = t;
     double acc[KB + 2];
 #pragma unroll
-    for (int j = 0; j < KB + 2; ++j) acc[j] = 0.0;
-    for (int64_t e = ck.e0 + threadIdx.x; e < ck.e1; e += TPB) {
-        double v[KB], wv[KB];
-        double x = 0.0, wy = 0.0;
-#pragma unroll
-        for (int j = 0; j < KB; ++j) {
-            v[j] = w.V[(int64_t)min(j, i - 1) * n + e];
-            wv[j] = w.W[(int64_t)min(j, i - 1) * n + e];
-        }
-#pragma unroll
-        for (int j = 0; j < KB; ++j) {
-            v[j] = (j < i) ? v[j] : 0.0;
-            x += v[j] * y[j];
-            wy += wv[j] * y[j];
-        }
-        const double r = wy - lam * x;
-        double den = w.D[e] - sig;
-        if (fabs(den) < fl) den = (den < 0.0) ? -fl : fl;
-        const double t = r / den;
-        w.T[e] = t;
-        acc[KB] += r * r;
-        acc[KB + 1] += t * t;
-        if (!restart) {
-#pragma unroll
-            for (int j = 0; j < KB; ++j) acc[j] += v[j] * t;
-        }
-    }
+    for (int j = 0; j < KB; ++j) acc[j] = restart ? 0.0 : v[j] * t;
+    acc[KB] = has ? r * r : 0.0;
+    acc[KB + 1] = t * t;
     block_reduce<KB + 2>(acc, KB + 2, lds);
     if (threadIdx.x == 0) {
         const int64_t ld = w.nchunk;
@@ -754,7 +790,7 @@ __global__ __launch_bounds__(TPB) void k_ritz(DavArgs w, int i, int restart) {
 // norms of k_ritz's row.  Skipped when the stop
 // test (made again by k_orth from the same sums) ends the member.
 template <int KB>
-__global__ __launch_bounds__(TPB) void k_restart(DavArgs w, int i, int kmin) {
+__global__ __launch_bounds__(TPB) void k_restart(DavArgs w, int i, int kmin, int par) {
     __shared__ double lds[4 * KB];
     __shared__ double Ys[KB * KB];
     __shared__ double sums[2];
@@ -766,7 +802,7 @@ __global__ __launch_bounds__(TPB) void k_restart(DavArgs w, int i, int kmin) {
     if (stop_code(S, sums[0])) return;
     for (int e = threadIdx.x; e < KB * KB; e += TPB) {
         int r = e / KB, q = e % KB;
-        Ys[r * KB + q] = (r < i && q < kmin) ? S.Y[r * KM + q] : 0.0;
+        Ys[r * KB + q] = (r < i && q < kmin) ? S.Y[par][r * KM + q] : 0.0;
     }
     __syncthreads();
     const int64_t n = w.n;
@@ -818,7 +854,8 @@ __global__ __launch_bounds__(TPB) void k_restart(DavArgs w, int i, int kmin) {
 // directly; otherwise t is kept and its partial row (V^T t, ||t||^2) feeds the
 // second pass.  pin: the rows of k_ritz, or of k_restart after a restart.
 template <int KB>
-__global__ __launch_bounds__(TPB) void k_orth(DavArgs w, int i, const double *__restrict__ pin, int after_restart) {
+__global__ __launch_bounds__(TPB) void k_orth(DavArgs w, int i, const double *__restrict__ pin, int after_restart,
+                                              int par) {
     __shared__ double lds[4 * (KB + 1)];
     __shared__ double sums[KM + 2];
     const int c = blockIdx.x;
@@ -858,7 +895,7 @@ __global__ __launch_bounds__(TPB) void k_orth(DavArgs w, int i, const double *__
             if (after_restart) {  // the kept Ritz vectors are the new basis: B = diag(theta), Y = I
                 S.restarts += 1;
                 for (int r = 0; r < i; ++r)
-                    for (int q = 0; q < i; ++q) S.Y[r * KM + q] = (r == q) ? 1.0 : 0.0;
+                    for (int q = 0; q < i; ++q) S.Y[par][r * KM + q] = (r == q) ? 1.0 : 0.0;
             }
         }
     }
@@ -939,7 +976,7 @@ __global__ __launch_bounds__(TPB) void k_finalize(DavArgs w, double *__restrict_
     const int nv = S.nvec;
     double y[KB];
 #pragma unroll
-    for (int j = 0; j < KB; ++j) y[j] = (j < nv) ? S.Y[j * KM] : 0.0;
+    for (int j = 0; j < KB; ++j) y[j] = (j < nv) ? S.Y[S.iters & 1][j * KM] : 0.0;
     const int64_t n = w.n;
     for (int64_t e = ck.e0 + threadIdx.x; e < ck.e1; e += TPB) {
         double v[KB];
@@ -1083,34 +1120,45 @@ static RayArgs ray_args(const DavArgs &A, int i) {
     return r;
 }
 
-// Enqueue `count` iterations starting at subspace size i; returns the next i.
-static dmrg_status enqueue_iters(dmrg_plan *plan, int slot, int i, int count, int *i_next, hipStream_t s) {
+// Enqueue `count` iterations starting at subspace size i and iteration number
+// t (1 = the phase's first; its parity selects the Y/theta buffer); returns the next i.
+static dmrg_status enqueue_iters(dmrg_plan *plan, int slot, int i, int t, int count, int *i_next, hipStream_t s) {
     DavidsonWork *w = plan->dav;
     const DavArgs &A = w->a;
     const int kmax = w->kmax, kmin = w->kmin;
     const dim3 grid(A.nchunk), block(TPB);
     const int32_t *slot_begin = plan->fwd[slot].slot_begin;
-    for (int it = 0; it < count; ++it) {
+    for (int it = 0; it < count; ++it, ++t) {
         const bool restart = (i == kmax);
-        // W(:, i-1) and its Rayleigh rows came from the previous projection
-        hipLaunchKernelGGL(k_rayleigh, dim3(A.nprob), dim3(RT), 0, s, A, slot_begin, i, w->eig_solver);
+        const int par = t & 1;
+        // W(:, i-1) and its Rayleigh rows came from the previous projection.  The
+        // Rayleigh step runs redundantly inside k_ritz while all chunk blocks fit on
+        // the device at once; beyond that a block per member solves it first.
+        const bool fused = A.nchunk <= FUSED_RAYLEIGH_MAX_CHUNKS;
+        if (!fused)
+            hipLaunchKernelGGL(k_rayleigh, dim3(A.nprob), block, 0, s, A, slot_begin, i, par, w->eig_solver);
         set_kb(i, [&](auto kb) {
             constexpr int KB = decltype(kb)::value;
-            hipLaunchKernelGGL(k_ritz<KB>, grid, block, 0, s, A, i, restart ? 1 : 0);
+            if (fused)
+                hipLaunchKernelGGL((k_ritz<KB, true>), grid, block, 0, s, A, slot_begin, i, restart ? 1 : 0, par,
+                                   w->eig_solver);
+            else
+                hipLaunchKernelGGL((k_ritz<KB, false>), grid, block, 0, s, A, slot_begin, i, restart ? 1 : 0, par,
+                                   w->eig_solver);
         });
         int ie = i;
         const double *pin = A.pa;
         if (restart) {
             set_kb(i, [&](auto kb) {
                 constexpr int KB = decltype(kb)::value;
-                hipLaunchKernelGGL(k_restart<KB>, grid, block, 0, s, A, i, kmin);
+                hipLaunchKernelGGL(k_restart<KB>, grid, block, 0, s, A, i, kmin, par);
             });
             ie = kmin;
             pin = A.pb;
         }
         set_kb(ie, [&](auto kb) {
             constexpr int KB = decltype(kb)::value;
-            hipLaunchKernelGGL(k_orth<KB>, grid, block, 0, s, A, ie, pin, restart ? 1 : 0);
+            hipLaunchKernelGGL(k_orth<KB>, grid, block, 0, s, A, ie, pin, restart ? 1 : 0, par);
             hipLaunchKernelGGL(k_append<KB>, grid, block, 0, s, A, ie);
         });
         DMRG_HIP(hipGetLastError());
@@ -1188,7 +1236,7 @@ static dmrg_status run_phase(dmrg_plan *plan, int slot, const double *psi_in, do
         int inext = i0;
         auto enqueue = [&](hipStream_t q) -> dmrg_status {
             if (i == 0) DMRG_TRY(enqueue_setup(plan, slot, tol, floor_, max_iter, q));
-            DMRG_TRY(enqueue_iters(plan, slot, i0, cnt, &inext, q));
+            DMRG_TRY(enqueue_iters(plan, slot, i0, done + 1, cnt, &inext, q));
             hipLaunchKernelGGL(k_summary, dim3((A.nprob + 63) / 64), dim3(64), 0, q, A);
             if (fin_x0)
                 set_kb(w->kmax, [&](auto kb) {  // nvec <= kmax
@@ -1199,8 +1247,8 @@ static dmrg_status run_phase(dmrg_plan *plan, int slot, const double *psi_in, do
             return DMRG_OK;
         };
         if (use_graph) {
-            auto key = std::make_tuple(slot, i * 2 + (fin_x0 ? 1 : 0), cnt, w->kmax, w->eig_solver, max_iter,
-                                       bits_of(tol), bits_of(floor_));
+            auto key = std::make_tuple(slot, i * 4 + (fin_x0 ? 2 : 0) + ((done + 1) & 1), cnt, w->kmax,
+                                       w->eig_solver, max_iter, bits_of(tol), bits_of(floor_));
             auto it = w->graphs.find(key);
             if (it == w->graphs.end()) {
                 hipStream_t cs;
