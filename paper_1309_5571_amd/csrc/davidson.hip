@@ -13,9 +13,11 @@
 //               t = r / (D - sigma) (line 10, shifted diagonal preconditioner),
 //               s = V^T t (line 12, first pass): one sweep over V and W
 //   k_restart   (when i = kmax) V <- V Y(:, :kmin), W <- W Y(:, :kmin), s = V^T t
-//   k_orth      stop test on ||r||, t <- t - V s (line 13); V(:, i) = t / ||t||
-//               (line 14) unless the norms call for a second pass, then V^T t
-//   k_append    second Gram-Schmidt pass: V(:, i) = (t - V s2) / ||.||
+//   k_orth      stop test (line 7), first Gram-Schmidt pass t' = t - V s
+//               (line 13) and the rows of the second pass s2 = V^T t', ||t'||;
+//               the next projection takes t' itself, and the next k_ritz
+//               finishes V(:, i) = (t' - V s2) / nu (line 14) and W(:, i) by
+//               linearity
 //
 // Reductions over the vector length never wait inside a kernel: each block
 // writes one partial row, and EVERY block of the next kernel sums the rows of
@@ -52,7 +54,7 @@ struct DavState {
     double theta[2][KM];   // Ritz values, ascending
     double lambda, sigma, dmin, rnorm, rnorm1, tn0, scale, tol, floor_;
     double rbest;  // smallest residual of the phase that halved the one before it
-    int32_t converged, breakdown, iters, nproj, restarts, dgks, nvec, max_iter, bad_start;
+    int32_t converged, breakdown, iters, nproj, restarts, nvec, max_iter, bad_start;
     int32_t stag_window, rbest_it, stagnated;  // stagnation exit of a reduced-precision phase
 };
 
@@ -172,6 +174,49 @@ static __device__ void sum_rows(const double *__restrict__ part, int64_t ld, int
     __syncthreads();
 }
 
+// Two sums_rows at once (one barrier): columns [0, nqa) of set a, then [0, nqb)
+// of set b, each mapped as in sum_rows; every lane group owns one column.
+static __device__ void sum_rows2(const double *__restrict__ pa, int64_t lda, int a0, int a1, int ia, int nqa,
+                                 double *outa, const double *__restrict__ pb, int64_t ldb, int b0, int b1, int ib,
+                                 int nqb, double *outb) {
+    const int nq = nqa + nqb;
+    const int G = lanes_per_column(nq);
+    const int q = threadIdx.x / G, l = threadIdx.x % G;
+    double v = 0.0;
+    if (q < nq) {
+        const bool A = q < nqa;
+        const int qq = A ? q : q - nqa, ii = A ? ia : ib;
+        const double *col = (A ? pa : pb) + (int64_t)(qq < ii ? qq : KM + (qq - ii)) * (A ? lda : ldb);
+        const int r0 = A ? a0 : b0, r1 = A ? a1 : b1;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        int r = r0 + l;
+        for (; r + 7 * G < r1; r += 8 * G) {
+            const double x0 = col[r], x1 = col[r + G], x2 = col[r + 2 * G], x3 = col[r + 3 * G];
+            const double x4 = col[r + 4 * G], x5 = col[r + 5 * G], x6 = col[r + 6 * G], x7 = col[r + 7 * G];
+            s0 += x0 + x4;
+            s1 += x1 + x5;
+            s2 += x2 + x6;
+            s3 += x3 + x7;
+        }
+        for (int k = 0; r < r1; r += G, ++k) {
+            const double x = col[r];
+            if (k == 0) s0 += x;
+            else if (k == 1) s1 += x;
+            else if (k == 2) s2 += x;
+            else s3 += x;
+        }
+        v = (s0 + s1) + (s2 + s3);
+    }
+    for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (q < nq && l == 0) {
+        if (q < nqa)
+            outa[q] = v;
+        else
+            outb[q - nqa] = v;
+    }
+    __syncthreads();
+}
+
 static __device__ double block_min(double v, double *lds) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
@@ -227,7 +272,6 @@ static __device__ void set_state(const DavArgs &w, int m, double tol, double flo
     S.converged = 0;
     S.breakdown = 0;
     S.bad_start = 0;
-    S.dgks = 0;
     S.nvec = 1;
     S.iters = 0;  // counts are per phase; the host adds the phases
     S.nproj = 0;
@@ -274,14 +318,28 @@ __global__ __launch_bounds__(TPB) void k_init_vec(const double *__restrict__ psi
         DavState &S = w.st[ck.member];
         S.dmin = mn;
         S.scale = bad ? 0.0 : 1.0 / sqrt(s);
+        S.tn0 = 1.0;
         if (bad) {
             S.bad_start = 1;
             deactivate(w, ck.member);
         }
     }
     if (bad) return;
+    // the first basis vector goes through the same path as every later one:
+    // projected as T, finalized (here: normalized once more) by the next k_ritz
     const double sc = 1.0 / sqrt(s);
-    for (int64_t e = ck.e0 + threadIdx.x; e < ck.e1; e += TPB) w.V[e] = psi[e] * sc;
+    const int64_t e = ck.e0 + threadIdx.x;
+    double q[1] = {0.0};
+    if (e < ck.e1) {
+        const double x = psi[e] * sc;
+        w.T[e] = x;
+        q[0] = x * x;
+    }
+    block_reduce<1>(q, 1, lds);
+    if (threadIdx.x == 0) {
+        w.pc[PR_R * (int64_t)w.nchunk + c] = 0.0;
+        w.pc[PR_T * (int64_t)w.nchunk + c] = q[0];
+    }
 }
 
 // ------------------------------------------------------------------ small eigenproblem
@@ -356,18 +414,34 @@ static __device__ void eig_load(const DavState &S, int n, int ob, EigLds &L) {
 }
 
 // One wavefront: border z = Y^T b and the corner, and the threshold.
-static __device__ void eig_border(int n, const double *bcol, EigLds &L) {
+// The new column of B from the raw sums of the projection y = H t': bcol[k] =
+// V(:, k)^T y (k < m), bcol[m] = t'^T y, where the new basis vector is
+// v = (t' - V s2) / nu (second Gram-Schmidt pass).  By linearity
+//   B(k, m) = (bcol[k] - (B s2)_k) / nu,
+//   B(m, m) = (bcol[m] - 2 s2^T bcol[:m] + s2^T B s2) / nu^2,
+// and in the previous Ritz basis Y (B = Y diag(theta) Y^T up to the threshold)
+// the border is z = (Y^T bcol[:m] - theta o Y^T s2) / nu.
+static __device__ void eig_border(int n, const double *bcol, const double *s2, double nu, EigLds &L) {
     const int lane = threadIdx.x & 63;
     const int m = n - 1;
     wave_sync();
+    double quad = 0.0, cross = 0.0;
     for (int r = lane; r < m; r += 64) {
-        double g = 0.0;
-        for (int k = 0; k < m; ++k) g += L.Vv[k][r] * bcol[k];
-        L.A[r][m] = g;
-        L.A[m][r] = g;
-        L.z[r] = g;
+        double y = 0.0, g = 0.0;
+        for (int k = 0; k < m; ++k) {
+            y += L.Vv[k][r] * bcol[k];
+            g += L.Vv[k][r] * s2[k];
+        }
+        const double z = (y - L.d[r] * g) / nu;
+        L.A[r][m] = z;
+        L.A[m][r] = z;
+        L.z[r] = z;
+        quad += L.d[r] * g * g;
+        cross += s2[r] * bcol[r];
     }
-    if (lane == 0) L.A[m][m] = bcol[m];
+    quad = wave_reduce(quad);
+    cross = wave_reduce(cross);
+    if (lane == 0) L.A[m][m] = (bcol[m] - 2.0 * cross + quad) / (nu * nu);
     wave_sync();
     double fro = 0.0;
     for (int r = 0; r < n; ++r)
@@ -672,15 +746,36 @@ static __device__ void eig_jacobi(int n, EigLds &L) {
 
 // ------------------------------------------------------------------ iteration kernels
 
-// Small eigenproblem of the Rayleigh step for one member in one block (all
-// threads call): B(:, i-1) from the member's tile rows, then the arrowhead
-// solve (Jacobi fallback) by wavefront 0.  Results stay in L.
-static __device__ void rayleigh_solve(DavState &S, const DavArgs &w, const int32_t *__restrict__ slot_begin,
-                                      int member, int i, int par, int jacobi_only, EigLds &L, double *bcol) {
-    if (threadIdx.x < 64) eig_load(S, i, par ^ 1, L);
-    sum_rows(w.ptile, w.tile_ld, slot_begin[member], slot_begin[member + 1], i, i, bcol);
+// The pending basis vector from the summed second-pass rows sums[0..q) = s2 =
+// V^T t' and sums[q + 1] = ||t'||^2: copies s2 and returns nu = ||t' - V s2||
+// (Pythagoras; s2 is the small remainder of the first pass, nothing cancels).
+// All threads call; s2 is valid after the call.
+static __device__ double pending_nu(const double *sums, int q, double *s2) {
+    double ss = 0.0;
+    for (int j = 0; j < q; ++j) ss += sums[j] * sums[j];
+    for (int j = threadIdx.x; j < q; j += TPB) s2[j] = sums[j];
+    __syncthreads();
+    return sqrt(fmax(sums[q + 1] - ss, 0.0));
+}
+
+// A basis vector that vanished after orthogonalization ends the member.
+static __device__ __forceinline__ bool broke_down(DavState &S, const DavArgs &w, int member, bool writer, double nu) {
+    if (nu > 1e-13 * S.tn0) return false;
+    if (writer && threadIdx.x == 0) {
+        S.breakdown = 1;
+        deactivate(w, member);
+    }
+    return true;
+}
+
+// Small eigenproblem of the Rayleigh step for one member (all threads call;
+// wavefront 0 works): the new column of B from the summed tile rows bcol
+// (corrected for the second pass, see eig_border), then the arrowhead solve
+// (Jacobi fallback).  eig_load must have run.  Results stay in L.
+static __device__ void rayleigh_solve(int i, int jacobi_only, const double *s2, double nu, EigLds &L,
+                                      const double *bcol) {
     if (threadIdx.x < 64) {
-        eig_border(i, bcol, L);
+        eig_border(i, bcol, s2, nu, L);
         const int fb = jacobi_only ? 1 : eig_secular(i, L);
         if (fb) eig_jacobi(i, L);
         if (threadIdx.x == 0) L.path = fb;
@@ -693,37 +788,47 @@ static __device__ void rayleigh_solve(DavState &S, const DavArgs &w, const int32
 __global__ __launch_bounds__(TPB) void k_rayleigh(DavArgs w, const int32_t *__restrict__ slot_begin, int i, int par,
                                                   int jacobi_only) {
     __shared__ EigLds L;
-    __shared__ double bcol[KM];
+    __shared__ double bcol[KM], s2[KM], pcs[KM + 2];
     const int member = blockIdx.x;
     if (!w.active[member]) return;
     DavState &S = w.st[member];
+    const int c0 = w.nprob == 1 ? 0 : w.member_chunk[member];
+    const int c1 = w.nprob == 1 ? w.nchunk : w.member_chunk[member + 1];
+    if (threadIdx.x < 64) eig_load(S, i, par ^ 1, L);
+    sum_rows2(w.pc, w.nchunk, c0, c1, i - 1, i + 1, pcs, w.ptile, w.tile_ld, slot_begin[member],
+              slot_begin[member + 1], i, i, bcol);
+    const double nu = pending_nu(pcs, i - 1, s2);
+    if (broke_down(S, w, member, true, nu)) return;
     if (threadIdx.x == 0) track_stagnation(S);  // before this step counts itself
-    rayleigh_solve(S, w, slot_begin, member, i, par, jacobi_only, L, bcol);
+    rayleigh_solve(i, jacobi_only, s2, nu, L, bcol);
     eig_store(S, i, par, L);
 }
 
-// Ritz vector, residual and correction: x = V y, r = W y - lambda x,
+// The newest basis vector and its projection are finished here, element by
+// element: V(:, q) = (t' - V s2) / nu, W(:, q) = (H t' - W s2) / nu, q = i - 1.
+// Then the Ritz vector, residual and correction: x = V y, r = W y - lambda x,
 // t = r / (D - sigma); partial row: V^T t, ||r||^2, ||t||^2.  With SOLVE the
 // Rayleigh step runs here too: every block of a member sums the member's tile
 // rows and solves the small eigenproblem itself (identical inputs and order,
 // hence identical results in every block) while its own rows of V and W are
 // loaded, and the member's first block stores Y and theta (buffer par; the
-// previous iteration's are read from par ^ 1).  Without SOLVE, y, lambda and
-// sigma come from k_rayleigh.
+// previous iteration's are read from par ^ 1).  Without SOLVE, y and lambda
+// come from k_rayleigh.
 template <int KB, bool SOLVE>
 __global__ __launch_bounds__(TPB) void k_ritz(DavArgs w, const int32_t *__restrict__ slot_begin, int i, int restart,
                                               int par, int jacobi_only) {
     __shared__ EigLds L;
-    __shared__ double bcol[KM];
+    __shared__ double bcol[KM], s2[KM];
     __shared__ double y0[KM];
     __shared__ double lds[4 * (KB + 2)];
-    constexpr bool PRE = SOLVE && KB <= 16;  // keep the rows in registers across the solve
+    constexpr bool PRE = KB <= 16;  // keep the rows in registers across the sums and the solve
     const int c = blockIdx.x;
     const Chunk ck = chunk_of(w, c);
     const int member = ck.member;
     if (!w.active[member]) return;
     DavState &S = w.st[member];
     const bool writer = c == ck.c0;
+    const int q = i - 1;  // the pending column
     const int64_t n = w.n, e = ck.e0 + threadIdx.x;
     const bool has = e < ck.e1;
     double v[KB], wv[KB], dv = 0.0;
@@ -734,16 +839,27 @@ __global__ __launch_bounds__(TPB) void k_ritz(DavArgs w, const int32_t *__restri
             dv = w.D[e];
 #pragma unroll
             for (int j = 0; j < KB; ++j) {
-                v[j] = w.V[(int64_t)min(j, i - 1) * n + e];
-                wv[j] = w.W[(int64_t)min(j, i - 1) * n + e];
+                const int jj = min(j, q);
+                v[j] = (jj < q ? w.V + (int64_t)jj * n : w.T)[e];  // column q: t'
+                wv[j] = w.W[(int64_t)jj * n + e];                  // column q: H t'
             }
         }
     };
     if (PRE) load_rows();
+    __shared__ double pcs[KM + 2];
+    if (SOLVE) {
+        if (threadIdx.x < 64) eig_load(S, i, par ^ 1, L);
+        sum_rows2(w.pc, w.nchunk, ck.c0, ck.c1, q, q + 2, pcs, w.ptile, w.tile_ld, slot_begin[member],
+                  slot_begin[member + 1], i, i, bcol);
+    } else {
+        sum_rows(w.pc, w.nchunk, ck.c0, ck.c1, q, q + 2, pcs);
+    }
+    const double nu = pending_nu(pcs, q, s2);
+    if (broke_down(S, w, member, writer, nu)) return;
     double lam;
     if (SOLVE) {
         if (writer && threadIdx.x == 0) track_stagnation(S);  // before this step counts itself
-        rayleigh_solve(S, w, slot_begin, member, i, par, jacobi_only, L, bcol);
+        rayleigh_solve(i, jacobi_only, s2, nu, L, bcol);
         for (int r = threadIdx.x; r < i; r += TPB) y0[r] = eig_y(L, i, r, 0);
         if (writer) eig_store(S, i, par, L);
         lam = L.val[L.inv[0]];
@@ -753,6 +869,31 @@ __global__ __launch_bounds__(TPB) void k_ritz(DavArgs w, const int32_t *__restri
     }
     if (!PRE) load_rows();
     __syncthreads();
+    // finish column q of V and W
+    double dvq = 0.0, dwq = 0.0, vq = 0.0, wq = 0.0;
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+        if (j < q) {
+            dvq += v[j] * s2[j];
+            dwq += wv[j] * s2[j];
+        }
+        if (j == q) {
+            vq = v[j];
+            wq = wv[j];
+        }
+    }
+    vq = (vq - dvq) / nu;
+    wq = (wq - dwq) / nu;
+#pragma unroll
+    for (int j = 0; j < KB; ++j)
+        if (j == q) {
+            v[j] = vq;
+            wv[j] = wq;
+        }
+    if (has) {
+        w.V[(int64_t)q * n + e] = vq;
+        w.W[(int64_t)q * n + e] = wq;
+    }
     const double sig = fmin(lam, S.dmin), fl = S.floor_;
     double x = 0.0, wy = 0.0;
 #pragma unroll
@@ -849,10 +990,9 @@ __global__ __launch_bounds__(TPB) void k_restart(DavArgs w, int i, int kmin, int
     }
 }
 
-// Stop test, then t <- t - V s.  When ||t - V s||^2 = ||t||^2 - ||s||^2 does not
-// cancel below half of ||t||^2, V(:, i) = (t - V s) / sqrt(||t||^2 - ||s||^2)
-// directly; otherwise t is kept and its partial row (V^T t, ||t||^2) feeds the
-// second pass.  pin: the rows of k_ritz, or of k_restart after a restart.
+// Stop test, then the first Gram-Schmidt pass t' = t - V s (kept in T; the
+// projection takes it as is) and the partial rows of the second pass: V^T t'
+// and ||t'||^2.  pin: the rows of k_ritz, or of k_restart after a restart.
 template <int KB>
 __global__ __launch_bounds__(TPB) void k_orth(DavArgs w, int i, const double *__restrict__ pin, int after_restart,
                                               int par) {
@@ -876,11 +1016,8 @@ __global__ __launch_bounds__(TPB) void k_orth(DavArgs w, int i, const double *__
     }
     sum_rows(pin, w.nchunk, ck.c0, ck.c1, i, i + 2, sums);
     const double rr = sums[i], tt = sums[i + 1];
-    double ss = 0.0;
-    for (int j = 0; j < i; ++j) ss += sums[j] * sums[j];
     const int code = stop_code(S, rr);
     const bool brk = !code && !(tt > 0.0);
-    const bool dg = (tt - ss) < 0.5 * tt;
     if (c == ck.c0 && threadIdx.x == 0) {
         S.rnorm = sqrt(rr);
         if (S.iters == 1) S.rnorm1 = S.rnorm;
@@ -890,30 +1027,20 @@ __global__ __launch_bounds__(TPB) void k_orth(DavArgs w, int i, const double *__
         if (brk) S.breakdown = 1;
         if (code || brk) {
             deactivate(w, member);
-        } else {
-            S.dgks = dg;
-            if (after_restart) {  // the kept Ritz vectors are the new basis: B = diag(theta), Y = I
-                S.restarts += 1;
-                for (int r = 0; r < i; ++r)
-                    for (int q = 0; q < i; ++q) S.Y[par][r * KM + q] = (r == q) ? 1.0 : 0.0;
-            }
+        } else if (after_restart) {  // the kept Ritz vectors are the new basis: B = diag(theta), Y = I
+            S.restarts += 1;
+            for (int r = 0; r < i; ++r)
+                for (int q = 0; q < i; ++q) S.Y[par][r * KM + q] = (r == q) ? 1.0 : 0.0;
         }
     }
     if (code || brk) return;
-    const double sc = dg ? 0.0 : 1.0 / sqrt(tt - ss);
-    double acc[KB + 1];
-#pragma unroll
-    for (int j = 0; j < KB + 1; ++j) acc[j] = 0.0;
 #pragma unroll
     for (int j = 0; j < KB; ++j) {
         v[j] = (j < i) ? v[j] : 0.0;
         t -= v[j] * ((j < i) ? sums[j] : 0.0);
     }
-    if (!dg) {
-        if (has) w.V[(int64_t)i * n + e] = t * sc;
-        return;
-    }
     if (has) w.T[e] = t;
+    double acc[KB + 1];
 #pragma unroll
     for (int j = 0; j < KB; ++j) acc[j] = v[j] * t;
     acc[KB] = t * t;
@@ -926,43 +1053,6 @@ __global__ __launch_bounds__(TPB) void k_orth(DavArgs w, int i, const double *__
         w.pc[PR_R * ld + c] = 0.0;
         w.pc[PR_T * ld + c] = acc[KB];
     }
-}
-
-// Second Gram-Schmidt pass: V(:, i) = (t - V s2) / ||t - V s2||; no-op unless
-// k_orth asked for it.
-template <int KB>
-__global__ __launch_bounds__(TPB) void k_append(DavArgs w, int i) {
-    __shared__ double sums[KM + 2];
-    const int c = blockIdx.x;
-    const Chunk ck = chunk_of(w, c);
-    const int member = ck.member;
-    if (!w.active[member]) return;
-    DavState &S = w.st[member];
-    if (!S.dgks) return;
-    const int64_t n = w.n, e = ck.e0 + threadIdx.x;
-    const bool has = e < ck.e1;
-    double t = 0.0, v[KB];
-#pragma unroll
-    for (int j = 0; j < KB; ++j) v[j] = 0.0;
-    if (has) {  // overlaps the sums
-        t = w.T[e];
-#pragma unroll
-        for (int j = 0; j < KB; ++j) v[j] = w.V[(int64_t)min(j, i - 1) * n + e];
-    }
-    sum_rows(w.pc, w.nchunk, ck.c0, ck.c1, i, i + 2, sums);
-    double ss = 0.0;
-    for (int j = 0; j < i; ++j) ss += sums[j] * sums[j];
-    const double nrm = sqrt(fmax(sums[i + 1] - ss, 0.0));
-    if (!(nrm > 1e-13 * S.tn0)) {
-        if (c == ck.c0 && threadIdx.x == 0) {
-            S.breakdown = 1;
-            deactivate(w, member);
-        }
-        return;
-    }
-#pragma unroll
-    for (int j = 0; j < KB; ++j) t -= v[j] * ((j < i) ? sums[j] : 0.0);
-    if (has) w.V[(int64_t)i * n + e] = t * (1.0 / nrm);
 }
 
 // psi = V(:, :nvec) y (normalized Ritz vector of each member)
@@ -1159,12 +1249,10 @@ static dmrg_status enqueue_iters(dmrg_plan *plan, int slot, int i, int t, int co
         set_kb(ie, [&](auto kb) {
             constexpr int KB = decltype(kb)::value;
             hipLaunchKernelGGL(k_orth<KB>, grid, block, 0, s, A, ie, pin, restart ? 1 : 0, par);
-            hipLaunchKernelGGL(k_append<KB>, grid, block, 0, s, A, ie);
         });
         DMRG_HIP(hipGetLastError());
         const RayArgs ray = ray_args(A, ie + 1);
-        DMRG_TRY(launch_project(plan, slot, A.coef, A.V + (int64_t)ie * A.n, A.W + (int64_t)ie * A.n, s, A.active,
-                                A.dfold, &ray));
+        DMRG_TRY(launch_project(plan, slot, A.coef, A.T, A.W + (int64_t)ie * A.n, s, A.active, A.dfold, &ray));
         i = ie + 1;
     }
     *i_next = i;
@@ -1188,7 +1276,7 @@ static dmrg_status enqueue_setup(dmrg_plan *plan, int slot, double tol, double f
     DMRG_HIP(hipGetLastError());
     DMRG_HIP(hipStreamWaitEvent(s, w->join, 0));
     const RayArgs ray = ray_args(A, 1);
-    return launch_project(plan, slot, A.coef, A.V, A.W, s, A.active, A.dfold, &ray);
+    return launch_project(plan, slot, A.coef, A.T, A.W, s, A.active, A.dfold, &ray);
 }
 
 static uint64_t bits_of(double x) {

@@ -141,15 +141,15 @@ struct DavidsonWork;
 
 constexpr int KM = 48;  // largest Davidson subspace (kmax)
 
-// Davidson context for a projection that feeds an iteration: besides
-// W(:, i-1), every output tile writes its share of B(:, i-1) = V(:, :i)^T
-// W(:, i-1) as one partial row (columns 0..i-1, row = the tile's rslot).  The
+// Davidson context for a projection y = H x that feeds an iteration: every
+// output tile writes its share of the dot products of y with V(:, 0..i-2) and
+// with x itself (column i-1) as one partial row (row = the tile's rslot).  The
 // rows are summed by the next kernel in the stream, so no tile waits on
 // another and no device-scope fence is needed.
 struct RayArgs {
-    const double *V = nullptr;  // column j at V + j * n; nullptr = plain projection
+    const double *V = nullptr;  // column j at V + j * n (j < i - 1); nullptr = plain projection
     int64_t n = 0;
-    int i = 0;
+    int i = 0;                  // columns of the partial rows; the last one is x^T y
     double *part = nullptr;     // partial rows, column-major: (row r, column j) at part[j * ld + r]
     int64_t ld = 0;
 };

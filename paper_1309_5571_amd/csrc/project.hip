@@ -500,7 +500,7 @@ __global__ __launch_bounds__(64 * PW) void k_tasks(const Task *__restrict__ task
         }
         if (MODE == 1 && ray.V) {
             // Rayleigh partials of the iteration this projection feeds: the
-            // tile's share of V(:, :i)^T w.  Wave w takes columns w, w + PW, ...;
+            // tile's share of [V(:, :i-1), x]^T y.  Wave w takes columns w, w + PW, ...;
             // its lanes run over the tile's elements (coalesced along tile rows)
             // and combine by shuffles in a fixed order.
             __syncthreads();  // wtile complete
@@ -529,7 +529,7 @@ __global__ __launch_bounds__(64 * PW) void k_tasks(const Task *__restrict__ task
 #pragma unroll
                         for (int jj = jg; jj < jg + 4; ++jj) {
                             const int j = min(wave + PW * jj, ii - 1);
-                            const double *Vj = ray.V + (int64_t)j * ray.n;
+                            const double *Vj = (j == ii - 1) ? in : ray.V + (int64_t)j * ray.n;
 #pragma unroll
                             for (int k = 0; k < 4; ++k) acc[jj] += Vj[off[k]] * wv[k];
                         }
