@@ -201,8 +201,9 @@ void dmrg_davidson_default_opts(dmrg_davidson_opts *opts);
  *  psi:  device FP64 [n]; in: start vectors (any norm, non-zero per member),
  *        out: normalized ground states.
  *  energy: host [nprob] (may be NULL); info: host [nprob] (may be NULL).
- * Iterations run in launches of at most graph_chunk (4 first, then as many as
- * the residual decay predicts); the host waits for each launch's summary.
+ * Iterations run in launches of at most graph_chunk: the first as long as the
+ * plan's previous phase of the same kind took (4 without history), then as
+ * many as the residual decay predicts; the host waits for each launch's summary.
  * energy and info are final on return; psi is completed in stream order
  * (work enqueued on stream afterwards sees it; synchronize stream before
  * reading it from the host).  Returns DMRG_W_NOT_CONVERGED if any member did not

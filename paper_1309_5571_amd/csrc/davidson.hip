@@ -92,6 +92,9 @@ struct DavidsonWork {
     int kmax = 0, kmin = 0;
     int eig_solver = 0;
     DavSummary *h_sum = nullptr;  // pinned, mapped [nprob]
+    // iterations the last phase of each kind needed (first launch size of the next one);
+    // kind = 4 * slot + 2 * (ends in X0) + (starts from X0)
+    std::map<int, int> last_iters;
     hipStream_t side = nullptr;   // second branch of the phase set-up
     hipEvent_t fork = nullptr, join = nullptr;
     // graphs by (slot, 4 * first i (0: with the phase set-up) + 2 * finalize-into-X0 + parity of the
@@ -1317,7 +1320,11 @@ static dmrg_status run_phase(dmrg_plan *plan, int slot, const double *psi_in, do
     if (psi_in) DMRG_HIP(hipMemcpyAsync((void *)A.X0, psi_in, (size_t)A.n * 8, hipMemcpyDeviceToDevice, s));
     int i = 0;  // 0: the launch starts with the phase set-up
     int done = 0;
-    int cnt = std::min({chunk_max, max_iter, FIRST_CHUNK});
+    // first launch: as many iterations as the last phase of this kind needed (a
+    // repeated solve of a plan, e.g. along a sweep, converges alike), else FIRST_CHUNK
+    const int kind = 4 * slot + (fin_x0 ? 2 : 0) + (psi_in ? 0 : 1);
+    const auto hint = w->last_iters.find(kind);
+    int cnt = std::min({chunk_max, max_iter, hint == w->last_iters.end() ? FIRST_CHUNK : hint->second});
     std::vector<DavSummary> sm(A.nprob);
     for (;;) {
         const int i0 = (i == 0) ? 1 : i;
@@ -1375,6 +1382,9 @@ static dmrg_status run_phase(dmrg_plan *plan, int slot, const double *psi_in, do
     }
     out = sm;
     *iters_out = done;
+    int need = 1;
+    for (const DavSummary &r : sm) need = std::max(need, (int)r.iters);
+    w->last_iters[kind] = need;
     return DMRG_OK;
 }
 
