@@ -52,7 +52,7 @@ constexpr int PR_T = KM + 1;  // partial-row column of ||t||^2
 struct DavState {
     double Y[2][KM * KM];  // eigenvectors of B (column c = Y[b][r * KM + c]), ascending
     double theta[2][KM];   // Ritz values, ascending
-    double lambda, sigma, dmin, rnorm, rnorm1, tn0, scale, tol, floor_;
+    double lambda, dmin, rnorm, rnorm1, tn0, tol, floor_;
     double rbest;  // smallest residual of the phase that halved the one before it
     int32_t converged, breakdown, iters, nproj, restarts, nvec, max_iter, bad_start;
     int32_t stag_window, rbest_it, stagnated;  // stagnation exit of a reduced-precision phase
@@ -320,7 +320,6 @@ __global__ __launch_bounds__(TPB) void k_init_vec(const double *__restrict__ psi
     if (c == ck.c0 && threadIdx.x == 0) {
         DavState &S = w.st[ck.member];
         S.dmin = mn;
-        S.scale = bad ? 0.0 : 1.0 / sqrt(s);
         S.tn0 = 1.0;
         if (bad) {
             S.bad_start = 1;
@@ -464,17 +463,29 @@ static __device__ __forceinline__ double rcp_nr(double x) {
 }
 
 // f(o + t) and its derivative, with the pole differences taken relative to o
+// (four poles at a time with separate partial sums, so their loads and
+// reciprocals are in flight together; the partial sums combine in a fixed order)
 static __device__ __forceinline__ double secular_f(const EigLds &L, int k, double beta, double o, double t,
                                                    double &fp) {
-    double fv = (beta - o) - t;
-    fp = -1.0;
-    for (int j = 0; j < k; ++j) {
-        const double dl = (L.dk[j] - o) - t;
-        const double q = L.zk[j] * rcp_nr(dl);
-        fv -= L.zk[j] * q;
-        fp -= q * q;
+    double f[4] = {0.0, 0.0, 0.0, 0.0}, p[4] = {0.0, 0.0, 0.0, 0.0};
+    int j = 0;
+    for (; j + 3 < k; j += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const double z = L.zk[j + u];
+            const double q = z * rcp_nr((L.dk[j + u] - o) - t);
+            f[u] += z * q;
+            p[u] += q * q;
+        }
     }
-    return fv;
+    for (int u = 0; j < k; ++j, ++u) {
+        const double z = L.zk[j];
+        const double q = z * rcp_nr((L.dk[j] - o) - t);
+        f[u] += z * q;
+        p[u] += q * q;
+    }
+    fp = -1.0 - ((p[0] + p[1]) + (p[2] + p[3]));
+    return ((beta - o) - t) - ((f[0] + f[1]) + (f[2] + f[3]));
 }
 
 // One wavefront.  Returns 1 when the fallback is needed (then L.A, L.Vv are
@@ -546,7 +557,7 @@ static __device__ int eig_secular(int n, EigLds &L) {
                 else
                     b = t;
                 const double den = fv + t * fp;  // Newton on t f(t), smooth at the pole o
-                double tn = (den != 0.0) ? t - t * fv / den : 0.5 * (a + b);
+                double tn = (den != 0.0) ? t - t * fv * rcp_nr(den) : 0.5 * (a + b);
                 if (fabs(tn - t) <= 2.0 * EPS * fabs(t)) {
                     t = tn;
                     done = true;
@@ -579,7 +590,9 @@ static __device__ int eig_secular(int n, EigLds &L) {
         const int j = lane;
         const double dj = L.dk[j];
         double prod = -((dj - L.org[j]) - L.tau[j]) * ((dj - L.org[j + 1]) - L.tau[j + 1]);
+#pragma unroll 4
         for (int l = 0; l < j; ++l) prod *= ((dj - L.org[l]) - L.tau[l]) * rcp_nr(dj - L.dk[l]);
+#pragma unroll 4
         for (int l = j + 1; l < k; ++l) prod *= ((dj - L.org[l + 1]) - L.tau[l + 1]) * rcp_nr(dj - L.dk[l]);
         L.zh[j] = copysign(sqrt(fmax(prod, 0.0)), L.zk[j]);
     }
@@ -604,12 +617,14 @@ static __device__ int eig_secular(int n, EigLds &L) {
         if (e <= k) {
             const double o = L.org[e], t = L.tau[e];
             double nrm = 1.0;
+#pragma unroll 4
             for (int j = 0; j < k; ++j) {
                 const double u = L.zh[j] * rcp_nr((L.dk[j] - o) - t);
                 L.A[L.kidx[j]][c] = u;
                 nrm += u * u;
             }
             const double sc = 1.0 / sqrt(nrm);
+#pragma unroll 4
             for (int j = 0; j < k; ++j) L.A[L.kidx[j]][c] *= sc;
             L.A[m][c] = -sc;
         } else {
@@ -639,7 +654,6 @@ static __device__ void eig_store(DavState &S, int n, int nb, const EigLds &L) {
     for (int c = threadIdx.x; c < n; c += TPB) S.theta[nb][c] = L.val[L.inv[c]];
     if (threadIdx.x == 0) {
         S.lambda = L.val[L.inv[0]];
-        S.sigma = fmin(S.lambda, S.dmin);
         S.iters += 1;
         S.nproj += 1;
         S.nvec = n;

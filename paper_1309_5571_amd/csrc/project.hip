@@ -163,10 +163,17 @@ __device__ __forceinline__ void load_q(typename Tr<PREC>::val_t (&v)[Tr<PREC>::K
 constexpr int PW = 4;            // wavefronts per workgroup
 // dynamic LDS of the task kernel: PW partial tiles + one tile of output values
 constexpr size_t TASK_LDS = (size_t)(PW * 32 * 33 + 1024) * sizeof(double);
-constexpr int KC = 32;           // contraction length of one work item
+// contraction length of one work item: 32 (8 MFMA k-blocks for FP64/FP32, one
+// 16x16x32 block for BF16); DMRG_KC_WIDE=16 trades fewer operands in flight
+// for more items (measured: faster on the large batch, slower on small blocks)
+#ifndef DMRG_KC_WIDE
+#define DMRG_KC_WIDE 32
+#endif
+template <int PREC>
+__host__ __device__ constexpr int kc_of() { return PREC == DMRG_BF16 ? 32 : DMRG_KC_WIDE; }
 constexpr int TASK_GRID_MAX = 4096;  // persistent grid cap (blocks loop over tasks)
 
-// One work item: acc[sr][sc] += op(P)[tile rows, k0:k0+KC] op(Q)[k0:k0+KC, tile cols].
+// One work item: acc[sr][sc] += op(P)[tile rows, k0:k0+KC] op(Q)[k0:k0+KC, tile cols], KC = kc_of<PREC>().
 // All operand loads of the item are issued before its MFMAs.
 template <int PREC, int NS, bool PIN, bool PT, bool QIN, bool QT>
 __device__ __forceinline__ void item_gemm(typename Tr<PREC>::acc_t (&acc)[2][2], const Seg &s, const Task &tk,
@@ -174,7 +181,7 @@ __device__ __forceinline__ void item_gemm(typename Tr<PREC>::acc_t (&acc)[2][2],
                                           int nsc, int k0) {
     typedef Tr<PREC> T;
     constexpr int KB = 4 * T::KPL;  // k per MFMA block
-    constexpr int NKB = KC / KB;    // blocks per item
+    constexpr int NKB = kc_of<PREC>() / KB;  // blocks per item
     const int lane = threadIdx.x & 63;
     const int r16 = lane & 15, g = lane >> 4;
     int prow[NS], qcol[NS];
@@ -294,7 +301,7 @@ __device__ __forceinline__ void seg_items(typename Tr<PREC>::acc_t (&acc)[2][2],
                                        const double *__restrict__ in, const void *__restrict__ tmp, int nsr, int nsc,
                                        int first, int nit) {
     for (int it = first; it < nit; it += PW)
-        item_gemm<PREC, NS, PIN, PT, QIN, QT>(acc, s, tk, in, tmp, nsr, nsc, it * KC);
+        item_gemm<PREC, NS, PIN, PT, QIN, QT>(acc, s, tk, in, tmp, nsr, nsc, it * kc_of<PREC>());
 }
 
 // One switch per segment on the operand layout (the task lists use 7 of the 16).
@@ -358,7 +365,7 @@ __device__ __forceinline__ double diag_sum(const DiagTerm *__restrict__ diags, i
 //         and per diagonal term (stage B task list of the FP64 pass).
 // A workgroup of PW wavefronts owns one output tile at a time (a persistent
 // grid walks the cost-sorted task list).  In modes 0/1 the work items of a
-// tile -- (segment, KC-long slice of its contraction) in list order -- are
+// tile -- (segment, kc_of<PREC>()-long slice of its contraction) in list order -- are
 // dealt round-robin to the wavefronts; the PW partial tiles are summed in a
 // fixed order through LDS, so results do not depend on scheduling.
 template <int PREC, int MODE, int NS>
@@ -391,7 +398,7 @@ __global__ __launch_bounds__(64 * PW) void k_tasks(const Task *__restrict__ task
                 } else {
                     // one wavefront runs every work item of the segment (PW-strided item loop, 4 passes)
                     for (int f = 0; f < PW; ++f)
-                        seg_dispatch<PREC, NS>(acc, s, tk, in, tmp, nsr, nsc, f, (s.K + KC - 1) / KC);
+                        seg_dispatch<PREC, NS>(acc, s, tk, in, tmp, nsr, nsc, f, (s.K + kc_of<PREC>() - 1) / kc_of<PREC>());
                 }
                 double part = 0.0;
 #pragma unroll
@@ -448,7 +455,7 @@ __global__ __launch_bounds__(64 * PW) void k_tasks(const Task *__restrict__ task
         for (int si = tk.seg_begin; si < tk.seg_end; ++si) {
             const int K = segs[si].K;
             const bool fused = segs[si].fused != 0;
-            const int nit = fused ? 1 : (K + KC - 1) / KC;  // a fused segment is one item
+            const int nit = fused ? 1 : (K + kc_of<PREC>() - 1) / kc_of<PREC>();  // a fused segment is one item
             const int first = (wave - q % PW + PW) % PW;  // first item of this segment owned by this wave
             if (first < nit) {
                 const Seg s = segs[si];
