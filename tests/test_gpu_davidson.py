@@ -120,6 +120,22 @@ def test_mixed_precision_refinement(prec):
     assert info[0]["iterations_low"] > 0
 
 
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_reduced_precision_phase_exits_on_stagnation(prec):
+    """A phase-1 tolerance below what the reduced-precision projection can reach:
+    the phase ends when its residual stops halving (5 iterations), long before
+    max_iter, and the FP64 phase still converges to the oracle energy."""
+    p = gen.config(3)
+    pl = _plan(p, prec=prec)
+    x0 = gen.start_vector(pl.n, 7)
+    psi, E, info, st = pl.davidson(_dev(x0), tol=1e-10, prec=prec, tol_lowprec=1e-10, max_iter=200)
+    assert st == 0, info
+    assert 0 < info[0]["iterations_low"] < 60
+    assert info[0]["converged"] == 1
+    ref = odav.ground_state_davidson(p, x0, tol=1e-10)
+    assert abs(E[0] - ref.energy) <= 1e-8
+
+
 def test_batched_members_converge_independently():
     probs = [gen.heisenberg_synthetic(m, seed=s) for m, s in ((128, 1), (256, 2), (64, 3))] + [gen.config(1)]
     pl = _plan(probs)
