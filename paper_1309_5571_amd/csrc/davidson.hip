@@ -172,7 +172,7 @@ static __device__ void sum_rows(const double *__restrict__ part, int64_t ld, int
         }
         v = (a0 + a1) + (a2 + a3);
     }
-    for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    v = group_sum(v, G);
     if (q < nq && l == 0) out[q] = v;
     __syncthreads();
 }
@@ -210,7 +210,7 @@ static __device__ void sum_rows2(const double *__restrict__ pa, int64_t lda, int
         }
         v = (s0 + s1) + (s2 + s3);
     }
-    for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    v = group_sum(v, G);
     if (q < nq && l == 0) {
         if (q < nqa)
             outa[q] = v;
@@ -221,8 +221,7 @@ static __device__ void sum_rows2(const double *__restrict__ pa, int64_t lda, int
 }
 
 static __device__ double block_min(double v, double *lds) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+    v = wave_min(v);
     if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
     __syncthreads();
     double m = lds[0];
@@ -353,17 +352,24 @@ __global__ __launch_bounds__(TPB) void k_init_vec(const double *__restrict__ psi
 // leading block is diagonal up to the previous step's threshold
 // tol = 1e-15 ||A||_F, which is dropped.
 //
-// Main path (one wavefront): the arrowhead is solved directly.  Border entries
-// |z_j| <= tol are dropped as well, which makes (d_j, e_j) an eigenpair
-// (deflation).  The other eigenvalues are the roots of the secular equation
+// Main path (all threads of the block): the arrowhead is solved directly.
+// Border entries |z_j| <= tol are dropped as well, which makes (d_j, e_j) an
+// eigenpair (deflation).  The other eigenvalues are the roots of the secular
+// equation
 //     f(x) = beta - x - sum_j z_j^2 / (d_j - x) = 0,
-// exactly one in each gap of the remaining poles and one beyond each end; lane
-// i finds root i as pole + offset (so that differences from the poles keep
-// full relative accuracy) by Newton steps on x f(x) relative to the nearer
-// pole (smooth there), kept inside a shrinking bracket with geometric
-// bisection.  Eigenvectors are (z'_j / (d_j - x))_j extended by -1, normalized,
-// with the border z' recomputed from the roots and poles (Loewner's formula
-// for an arrowhead matrix: z'_j^2 = -prod_i (d_j - x_i) / prod_{l != j} (d_j - d_l)),
+// exactly one in each gap of the remaining poles and one beyond each end.
+// Quad r (four lanes, each summing every fourth pole) finds root r as pole +
+// offset t, the pole being the nearer end of its gap (so that differences from
+// the poles keep full relative accuracy).  A step goes to the root of a model
+// of f that keeps the two poles bounding the gap, with weights matching the
+// derivative of the terms below and above the gap (the -x term joins the far
+// side), written for the correction so that it vanishes with f; the start is
+// the root of f ~ C + z_o^2 / t near the origin pole when that lies inside the
+// bracket.  Iterates stay in a shrinking bracket (geometric bisection as the
+// safeguard) and stop once |f| is at the level of its rounding error.
+// Eigenvectors are (z'_j / (d_j - x))_j extended by -1, normalized, with the
+// border z' recomputed from the roots and poles (Loewner's formula for an
+// arrowhead matrix: z'_j^2 = -prod_i (d_j - x_i) / prod_{l != j} (d_j - d_l)),
 // which keeps them orthogonal to working precision (Gu and Eisenstat).
 //
 // Fallback (two remaining poles closer than 1e3 tol, or a root not found in
@@ -427,29 +433,32 @@ static __device__ void eig_border(int n, const double *bcol, const double *s2, d
     const int lane = threadIdx.x & 63;
     const int m = n - 1;
     wave_sync();
-    double quad = 0.0, cross = 0.0;
-    for (int r = lane; r < m; r += 64) {
+    double quad = 0.0, cross = 0.0, fro = 0.0;
+    if (lane < m) {  // m < 64
+        const int r = lane;
         double y = 0.0, g = 0.0;
+#pragma unroll 4
         for (int k = 0; k < m; ++k) {
             y += L.Vv[k][r] * bcol[k];
             g += L.Vv[k][r] * s2[k];
         }
-        const double z = (y - L.d[r] * g) / nu;
+        const double dr = L.d[r];
+        const double z = (y - dr * g) / nu;
         L.A[r][m] = z;
         L.A[m][r] = z;
         L.z[r] = z;
-        quad += L.d[r] * g * g;
-        cross += s2[r] * bcol[r];
+        quad = dr * g * g;
+        cross = s2[r] * bcol[r];
+        fro = dr * dr + 2.0 * z * z;  // ||A||_F^2 without the corner
     }
     quad = wave_reduce(quad);
     cross = wave_reduce(cross);
-    if (lane == 0) L.A[m][m] = (bcol[m] - 2.0 * cross + quad) / (nu * nu);
-    wave_sync();
-    double fro = 0.0;
-    for (int r = 0; r < n; ++r)
-        for (int c = lane; c < n; c += 64) fro += L.A[r][c] * L.A[r][c];
     fro = wave_reduce(fro);
-    if (lane == 0) L.tol = 1e-15 * sqrt(fro);
+    const double beta = (bcol[m] - 2.0 * cross + quad) / (nu * nu);
+    if (lane == 0) {
+        L.A[m][m] = beta;
+        L.tol = 1e-15 * sqrt(fro + beta * beta);
+    }
     wave_sync();
 }
 
@@ -462,93 +471,137 @@ static __device__ __forceinline__ double rcp_nr(double x) {
     return fma(r, e, r);
 }
 
-// f(o + t) and its derivative, with the pole differences taken relative to o
-// (four poles at a time with separate partial sums, so their loads and
-// reciprocals are in flight together; the partial sums combine in a fixed order)
-static __device__ __forceinline__ double secular_f(const EigLds &L, int k, double beta, double o, double t,
-                                                   double &fp) {
-    double f[4] = {0.0, 0.0, 0.0, 0.0}, p[4] = {0.0, 0.0, 0.0, 0.0};
-    int j = 0;
-    for (; j + 3 < k; j += 4) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const double z = L.zk[j + u];
-            const double q = z * rcp_nr((L.dk[j + u] - o) - t);
-            f[u] += z * q;
-            p[u] += q * q;
-        }
-    }
-    for (int u = 0; j < k; ++j, ++u) {
-        const double z = L.zk[j];
-        const double q = z * rcp_nr((L.dk[j] - o) - t);
-        f[u] += z * q;
-        p[u] += q * q;
-    }
-    fp = -1.0 - ((p[0] + p[1]) + (p[2] + p[3]));
-    return ((beta - o) - t) - ((f[0] + f[1]) + (f[2] + f[3]));
+// Sums and products over the four lanes of a quad (lanes 4r .. 4r+3); all
+// four lanes get the same bits.
+static __device__ __forceinline__ double quad_sum(double v) { return group_sum<4>(v); }
+static __device__ __forceinline__ double quad_prod(double v) {
+    v *= dpp_f64<DPP_XOR1>(v);
+    return v * dpp_f64<DPP_XOR2>(v);
+}
+static __device__ __forceinline__ int quad_isum(int v) {
+    v += __builtin_amdgcn_mov_dpp(v, DPP_XOR1, 0xF, 0xF, false);
+    return v + __builtin_amdgcn_mov_dpp(v, DPP_XOR2, 0xF, 0xF, false);
 }
 
-// One wavefront.  Returns 1 when the fallback is needed (then L.A, L.Vv are
-// untouched); else leaves U in L.A and the entries' values and order in L.val,
-// L.col, L.inv.
+// All threads.  Returns 1 (the same in every thread) when the fallback is
+// needed (then L.A, L.Vv are untouched); else leaves U in L.A and the entries'
+// values and order in L.val, L.col, L.inv.
 static __device__ int eig_secular(int n, EigLds &L) {
-    const int lane = threadIdx.x & 63;
+    const int tid = threadIdx.x, lane = tid & 63;
     const int m = n - 1;
     const double tol = L.tol, beta = L.A[m][m];
     constexpr double EPS = 1.1102230246251565e-16;  // 2^-53
-    // deflation: poles with |z_j| <= tol leave the secular equation
-    const bool live = lane < m && fabs(L.z[lane]) > tol;
-    const bool dead = lane < m && !live;
-    const uint64_t lm = __ballot(live), dm = __ballot(dead);
-    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const int k = __popcll(lm);
-    if (live) {
-        const int r = __popcll(lm & below);
-        L.dk[r] = L.d[lane];
-        L.zk[r] = L.z[lane];
-        L.kidx[r] = lane;
+    // deflation (wavefront 0; m < 64): poles with |z_j| <= tol leave the secular equation
+    if (tid < 64) {
+        const bool live = lane < m && fabs(L.z[lane]) > tol;
+        const bool dead = lane < m && !live;
+        const uint64_t lm = __ballot(live), dm = __ballot(dead);
+        const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+        if (live) {
+            const int r = __popcll(lm & below);
+            L.dk[r] = L.d[lane];
+            L.zk[r] = L.z[lane];
+            L.kidx[r] = lane;
+        }
+        if (dead) L.didx[__popcll(dm & below)] = lane;
+        if (lane == 0) L.k = __popcll(lm);
     }
-    if (dead) L.didx[__popcll(dm & below)] = lane;
-    wave_sync();
+    __syncthreads();
+    const int k = __builtin_amdgcn_readfirstlane(L.k);  // uniform: scalar loop bounds
     bool close = false;
-    if (lane + 1 < k) close = L.dk[lane + 1] - L.dk[lane] <= 1e3 * tol;
-    if (__any(close)) return 1;
-    // roots: lane i <= k
-    double zn = (lane < k) ? L.zk[lane] * L.zk[lane] : 0.0;
-    zn = sqrt(wave_reduce(zn));
+    for (int j = tid; j + 1 < k; j += TPB) close = close || L.dk[j + 1] - L.dk[j] <= 1e3 * tol;
+    if (__syncthreads_or(close)) return 1;
+    const int r = tid >> 2, p = tid & 3;  // quad r; its lane p takes the poles j = p + 4u
+    constexpr int RP = KM / 4;
+    // this lane's poles and border entries; slots beyond k hold a zero term
+    // (z = 0 at a far pole), so the sums below need no per-lane guards
+    double pd[RP], pz[RP];
+#pragma unroll
+    for (int u = 0; u < RP; ++u) {
+        const int j = 4 * u + p;
+        pd[u] = (j < k) ? L.dk[j] : 1e300;
+        pz[u] = (j < k) ? L.zk[j] : 0.0;
+    }
     bool fail = false;
-    if (lane <= k) {
-        const int i = lane;
+    if (r <= k) {
+        const int i = r;  // root i
         double o = beta, t = 0.0;
         if (k > 0) {
+            const double dL = (i > 0) ? L.dk[i - 1] : 0.0, dR = (i < k) ? L.dk[i] : 0.0;  // the gap
+            const double mid = 0.5 * (dL + dR);
+            // one pass: ||z||^2, f(mid) (inner gaps), and for each candidate origin the
+            // rest of f at the origin with the origin's own pole left out
+            double zz = 0.0, fm = 0.0, cl = 0.0, cr = 0.0;
+#pragma unroll
+            for (int u = 0; u < RP; ++u) {
+                if (4 * u >= k) break;
+                const int j = 4 * u + p;
+                const double z2 = pz[u] * pz[u];
+                const double tm = z2 * rcp_nr(pd[u] - mid), tl = z2 * rcp_nr(pd[u] - dL),
+                             tr = z2 * rcp_nr(pd[u] - dR);
+                zz += z2;
+                fm += (i > 0 && i < k) ? tm : 0.0;
+                cl += (i > 0 && j != i - 1) ? tl : 0.0;  // (the excluded terms may be infinite)
+                cr += (i < k && j != i) ? tr : 0.0;
+            }
+            const double zn = sqrt(quad_sum(zz));
+            fm = quad_sum(fm);
+            cl = quad_sum(cl);
+            cr = quad_sum(cr);
             double a, b;
+            bool left;  // origin at the lower end of the gap
             if (i == 0) {
-                o = L.dk[0];
-                a = (fmin(L.dk[0], beta) - zn - tol) - o;
+                left = false;
+                o = dR;
+                a = (fmin(dR, beta) - zn - tol) - o;
                 b = 0.0;
             } else if (i == k) {
-                o = L.dk[k - 1];
+                left = true;
+                o = dL;
                 a = 0.0;
-                b = (fmax(L.dk[k - 1], beta) + zn + tol) - o;
+                b = (fmax(dL, beta) + zn + tol) - o;
+            } else if ((beta - mid) - fm >= 0.0) {  // root between mid and the upper pole
+                left = false;
+                o = dR;
+                a = mid - o;
+                b = 0.0;
             } else {
-                const double mid = 0.5 * (L.dk[i - 1] + L.dk[i]);
-                double fp;
-                if (secular_f(L, k, beta, 0.0, mid, fp) >= 0.0) {  // root between mid and the upper pole
-                    o = L.dk[i];
-                    a = mid - o;
-                    b = 0.0;
-                } else {
-                    o = L.dk[i - 1];
-                    a = 0.0;
-                    b = mid - o;
-                }
+                left = true;
+                o = dL;
+                a = 0.0;
+                b = mid - o;
             }
             t = 0.5 * (a + b);
+            {
+                const double c0 = (beta - o) - (left ? cl : cr), zo = left ? L.zk[i - 1] : L.zk[i];
+                const double t0 = (c0 != 0.0) ? -(zo * zo) / c0 : 0.0;
+                if (t0 > a && t0 < b) t = t0;
+            }
+            // weights of the model's two poles: q^2 sums below / above the gap, the
+            // far side taking the -x term (inner gaps)
+            const double wl = (i < k && !left) ? 1.0 : 0.0, wr = (i > 0 && left) ? 1.0 : 0.0;
             bool done = false;
             for (int it = 0; it < 100 && !done; ++it) {
-                double fp;
-                const double fv = secular_f(L, k, beta, o, t, fp);
-                if (fv == 0.0) {
+                // f(o + t); sums of q_j^2 over the poles below the gap (j < i) and above;
+                // sum |z_j q_j| for the rounding error of f
+                double fs = 0.0, pl = 0.0, pr = 0.0, er = 0.0;
+#pragma unroll
+                for (int u = 0; u < RP; ++u) {
+                    if (4 * u >= k) break;
+                    const int j = 4 * u + p;
+                    const double q = pz[u] * rcp_nr((pd[u] - o) - t);
+                    const double zq = pz[u] * q, qq = q * q;
+                    fs += zq;
+                    er += fabs(zq);
+                    pl += (j < i) ? qq : 0.0;
+                    pr += (j < i) ? 0.0 : qq;
+                }
+                fs = quad_sum(fs);
+                pl = quad_sum(pl);
+                pr = quad_sum(pr);
+                er = quad_sum(er);
+                const double fv = ((beta - o) - t) - fs;
+                if (fabs(fv) <= 8.0 * EPS * (er + fabs(beta - o) + fabs(t))) {
                     done = true;
                     break;
                 }
@@ -556,8 +609,25 @@ static __device__ int eig_secular(int n, EigLds &L) {
                     a = t;
                 else
                     b = t;
-                const double den = fv + t * fp;  // Newton on t f(t), smooth at the pole o
-                double tn = (den != 0.0) ? t - t * fv * rcp_nr(den) : 0.5 * (a + b);
+                // model f(t + eta) ~ c - SL / (DL - eta) - SR / (DR - eta) through f(t), f'(t)
+                // with SL = wL DL^2, SR = wR DR^2; its root solves qa eta^2 - qb eta + qc = 0
+                double qa, qb, qc;
+                if (i == 0 || i == k) {
+                    const double dd = -t;  // to the origin pole; every pole on one side, -x exact
+                    const double wd = (i == 0) ? pr : pl;
+                    qa = 1.0;
+                    qb = dd + fv + wd * dd;
+                    qc = fv * dd;
+                } else {
+                    const double DL = (dL - o) - t, DR = (dR - o) - t;
+                    const double wL = pl + wl, wR = pr + wr;
+                    qa = fv + wL * DL + wR * DR;
+                    qb = qa * (DL + DR) - wL * DL * DL - wR * DR * DR;
+                    qc = DL * DR * fv;
+                }
+                const double disc = sqrt(fabs(qb * qb - 4.0 * qa * qc));
+                const double den = (qb >= 0.0) ? qb + disc : qb - disc;  // the root that vanishes with f
+                double tn = (den != 0.0) ? t + 2.0 * qc * rcp_nr(den) : 0.5 * (a + b);
                 if (fabs(tn - t) <= 2.0 * EPS * fabs(t)) {
                     t = tn;
                     done = true;
@@ -580,58 +650,75 @@ static __device__ int eig_secular(int n, EigLds &L) {
             }
             fail = !done || !isfinite(t);
         }
-        L.org[i] = o;
-        L.tau[i] = t;
+        if (p == 0) {
+            L.org[i] = o;
+            L.tau[i] = t;
+        }
     }
-    if (__any(fail)) return 1;
-    wave_sync();
-    // recomputed border (pairs each pole difference with a root difference)
-    if (lane < k) {
-        const int j = lane;
+    if (__syncthreads_or(fail)) return 1;
+    // recomputed border (pairs each pole difference with a root difference); quad j takes pole j
+    if (r < k) {
+        const int j = r;
         const double dj = L.dk[j];
-        double prod = -((dj - L.org[j]) - L.tau[j]) * ((dj - L.org[j + 1]) - L.tau[j + 1]);
-#pragma unroll 4
-        for (int l = 0; l < j; ++l) prod *= ((dj - L.org[l]) - L.tau[l]) * rcp_nr(dj - L.dk[l]);
-#pragma unroll 4
-        for (int l = j + 1; l < k; ++l) prod *= ((dj - L.org[l + 1]) - L.tau[l + 1]) * rcp_nr(dj - L.dk[l]);
-        L.zh[j] = copysign(sqrt(fmax(prod, 0.0)), L.zk[j]);
+        double prod = 1.0;
+#pragma unroll
+        for (int u = 0; u < RP; ++u) {
+            if (4 * u >= k) break;
+            const int l = 4 * u + p;
+            const int x = (l < j) ? l : min(l + 1, k);
+            const double fct = ((dj - L.org[x]) - L.tau[x]) * rcp_nr(dj - pd[u]);
+            prod *= (l < k && l != j) ? fct : 1.0;
+        }
+        prod = quad_prod(prod) * (-((dj - L.org[j]) - L.tau[j]) * ((dj - L.org[j + 1]) - L.tau[j + 1]));
+        if (p == 0) L.zh[j] = copysign(sqrt(fmax(prod, 0.0)), L.zk[j]);
     }
     // entries: roots 0..k, then the deflated poles; ascending order, ties by entry
-    for (int e = lane; e < n; e += 64) L.val[e] = (e <= k) ? L.org[e] + L.tau[e] : L.d[L.didx[e - k - 1]];
-    wave_sync();
-    for (int e = lane; e < n; e += 64) {
+    for (int e = tid; e < n; e += TPB) L.val[e] = (e <= k) ? L.org[e] + L.tau[e] : L.d[L.didx[e - k - 1]];
+    __syncthreads();
+    if (r < n) {
+        const int e = r;
         const double v = L.val[e];
         int rank = 0;
-        for (int f = 0; f < n; ++f) {
+        for (int f = p; f < n; f += 4) {
             const double w = L.val[f];
             rank += (w < v) || (w == v && f < e);
         }
-        L.col[e] = rank;
-        L.inv[rank] = e;
+        rank = quad_isum(rank);
+        if (p == 0) {
+            L.col[e] = rank;
+            L.inv[rank] = e;
+        }
     }
-    for (int e = lane; e < n * n; e += 64) L.A[e / n][e % n] = 0.0;
-    wave_sync();
-    // eigenvector columns of the arrowhead
-    for (int e = lane; e < n; e += 64) {
-        const int c = L.col[e];
+    for (int e = tid; e < n * n; e += TPB) L.A[e / n][e % n] = 0.0;
+    __syncthreads();
+    // eigenvector columns of the arrowhead; quad e takes entry e
+    if (r < n) {
+        const int e = r, c = L.col[e];
         if (e <= k) {
             const double o = L.org[e], t = L.tau[e];
-            double nrm = 1.0;
-#pragma unroll 4
-            for (int j = 0; j < k; ++j) {
-                const double u = L.zh[j] * rcp_nr((L.dk[j] - o) - t);
-                L.A[L.kidx[j]][c] = u;
-                nrm += u * u;
+            double uv[RP], nrm = 0.0;
+#pragma unroll
+            for (int u = 0; u < RP; ++u) {
+                uv[u] = 0.0;
+                if (4 * u >= k) break;
+                const int j = 4 * u + p;
+                const double x = L.zh[min(j, k - 1)] * rcp_nr((pd[u] - o) - t);
+                uv[u] = (j < k) ? x : 0.0;
+                nrm += uv[u] * uv[u];
             }
-            const double sc = 1.0 / sqrt(nrm);
-#pragma unroll 4
-            for (int j = 0; j < k; ++j) L.A[L.kidx[j]][c] *= sc;
-            L.A[m][c] = -sc;
-        } else {
+            const double sc = 1.0 / sqrt(1.0 + quad_sum(nrm));
+#pragma unroll
+            for (int u = 0; u < RP; ++u) {
+                if (4 * u >= k) break;
+                const int j = 4 * u + p;
+                if (j < k) L.A[L.kidx[j]][c] = uv[u] * sc;
+            }
+            if (p == 0) L.A[m][c] = -sc;
+        } else if (p == 0) {
             L.A[L.didx[e - k - 1]][c] = 1.0;
         }
     }
-    if (lane == 0) L.k = k;
+    __syncthreads();
     return 0;
 }
 
@@ -785,18 +872,18 @@ static __device__ __forceinline__ bool broke_down(DavState &S, const DavArgs &w,
     return true;
 }
 
-// Small eigenproblem of the Rayleigh step for one member (all threads call;
-// wavefront 0 works): the new column of B from the summed tile rows bcol
-// (corrected for the second pass, see eig_border), then the arrowhead solve
-// (Jacobi fallback).  eig_load must have run.  Results stay in L.
-static __device__ void rayleigh_solve(int i, int jacobi_only, const double *s2, double nu, EigLds &L,
+// Small eigenproblem of the Rayleigh step for one member (all threads call):
+// wavefront 0 forms the new column of B from the summed tile rows bcol
+// (corrected for the second pass, see eig_border), the block solves the
+// arrowhead, wavefront 0 runs the Jacobi fallback when needed.  eig_load must
+// have run.  Results stay in L.
+static __device__ __forceinline__ void rayleigh_solve(int i, int jacobi_only, const double *s2, double nu, EigLds &L,
                                       const double *bcol) {
-    if (threadIdx.x < 64) {
-        eig_border(i, bcol, s2, nu, L);
-        const int fb = jacobi_only ? 1 : eig_secular(i, L);
-        if (fb) eig_jacobi(i, L);
-        if (threadIdx.x == 0) L.path = fb;
-    }
+    if (threadIdx.x < 64) eig_border(i, bcol, s2, nu, L);
+    __syncthreads();
+    const int fb = jacobi_only ? 1 : eig_secular(i, L);
+    if (fb && threadIdx.x < 64) eig_jacobi(i, L);
+    if (threadIdx.x == 0) L.path = fb;
     __syncthreads();
 }
 

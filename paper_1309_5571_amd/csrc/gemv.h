@@ -6,22 +6,20 @@
 // narrow V, walks the rows with a grid-stride loop so reads stay coalesced,
 // and finishes with a shared-memory reduction.  On CDNA4 the same idea maps to
 // one wave64 per 64 consecutive rows, up to KMAX FP64 accumulators per lane,
-// a DPP/shuffle wave reduction and a cross-wave reduction in LDS; blocks
+// a DPP wave reduction and a cross-wave reduction in LDS; blocks
 // write per-block partials that a second, fixed-order stage sums, so the
 // result does not depend on scheduling.
 #pragma once
 
 #include <hip/hip_runtime.h>
 
+#include "lanes.h"
+
 namespace dmrg {
 
 constexpr int GEMV_THREADS = 256;
 
-__device__ __forceinline__ double wave_reduce(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
+__device__ __forceinline__ double wave_reduce(double v) { return group_sum<64>(v); }
 
 // Block-wide sum of KB values per thread into red[0..KB) (valid in all threads
 // after the call).  lds must hold (GEMV_THREADS / 64) * KB doubles.

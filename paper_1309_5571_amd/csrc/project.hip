@@ -25,6 +25,7 @@
 #include <cstdio>
 
 #include "internal.h"
+#include "lanes.h"
 
 namespace dmrg {
 
@@ -331,11 +332,7 @@ __device__ __forceinline__ void seg_dispatch(typename Tr<PREC>::acc_t (&acc)[2][
     }
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
+__device__ __forceinline__ double wave_sum(double v) { return group_sum<64>(v); }
 
 template <int PREC>
 __device__ __forceinline__ void zero_acc(typename Tr<PREC>::acc_t (&acc)[2][2]) {
