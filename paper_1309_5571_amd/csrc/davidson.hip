@@ -141,6 +141,26 @@ static __device__ __forceinline__ int lanes_per_column(int ncols) {
     return G;
 }
 
+// One lane's share of a column sum: rows r, r + G, ... below r1, fetched in
+// guarded batches of UMAX (UMAX / 2 for a short tail), every load of a batch
+// in flight together, added into four running sums combined in a fixed order.
+// Kernels that stream long vectors keep UMAX small (registers, occupancy).
+template <int U>
+static __device__ __forceinline__ void lane_rows(const double *__restrict__ col, int r, int r1, int G, double (&a)[4]) {
+    double x[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) x[u] = (r + u * G < r1) ? col[r + u * G] : 0.0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) a[u & 3] += x[u];
+}
+template <int UMAX>
+static __device__ __forceinline__ double lane_col_sum(const double *__restrict__ col, int r, int r1, int G) {
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    for (; r + (UMAX / 2) * G < r1; r += UMAX * G) lane_rows<UMAX>(col, r, r1, G, a);
+    if (r < r1) lane_rows<UMAX / 2>(col, r, r1, G, a);
+    return (a[0] + a[1]) + (a[2] + a[3]);
+}
+
 // out[q] = sum of partial rows [r0, r1) in column col(q), q < nq, where
 // col(q) = q for q < i and KM + (q - i) beyond (the norm columns); element
 // (r, col) at part[col * ld + r].  Each lane keeps 4 running sums (rows
@@ -151,27 +171,7 @@ static __device__ void sum_rows(const double *__restrict__ part, int64_t ld, int
     const int G = lanes_per_column<NT>(nq);
     const int q = threadIdx.x / G, l = threadIdx.x % G;
     double v = 0.0;
-    if (q < nq) {
-        const double *col = part + (int64_t)(q < i ? q : KM + (q - i)) * ld;
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-        int r = r0 + l;
-        for (; r + 7 * G < r1; r += 8 * G) {
-            const double x0 = col[r], x1 = col[r + G], x2 = col[r + 2 * G], x3 = col[r + 3 * G];
-            const double x4 = col[r + 4 * G], x5 = col[r + 5 * G], x6 = col[r + 6 * G], x7 = col[r + 7 * G];
-            a0 += x0 + x4;
-            a1 += x1 + x5;
-            a2 += x2 + x6;
-            a3 += x3 + x7;
-        }
-        for (int k = 0; r < r1; r += G, ++k) {
-            const double x = col[r];
-            if (k == 0) a0 += x;
-            else if (k == 1) a1 += x;
-            else if (k == 2) a2 += x;
-            else a3 += x;
-        }
-        v = (a0 + a1) + (a2 + a3);
-    }
+    if (q < nq) v = lane_col_sum<8>(part + (int64_t)(q < i ? q : KM + (q - i)) * ld, r0 + l, r1, G);
     v = group_sum(v, G);
     if (q < nq && l == 0) out[q] = v;
     __syncthreads();
@@ -191,24 +191,7 @@ static __device__ void sum_rows2(const double *__restrict__ pa, int64_t lda, int
         const int qq = A ? q : q - nqa, ii = A ? ia : ib;
         const double *col = (A ? pa : pb) + (int64_t)(qq < ii ? qq : KM + (qq - ii)) * (A ? lda : ldb);
         const int r0 = A ? a0 : b0, r1 = A ? a1 : b1;
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-        int r = r0 + l;
-        for (; r + 7 * G < r1; r += 8 * G) {
-            const double x0 = col[r], x1 = col[r + G], x2 = col[r + 2 * G], x3 = col[r + 3 * G];
-            const double x4 = col[r + 4 * G], x5 = col[r + 5 * G], x6 = col[r + 6 * G], x7 = col[r + 7 * G];
-            s0 += x0 + x4;
-            s1 += x1 + x5;
-            s2 += x2 + x6;
-            s3 += x3 + x7;
-        }
-        for (int k = 0; r < r1; r += G, ++k) {
-            const double x = col[r];
-            if (k == 0) s0 += x;
-            else if (k == 1) s1 += x;
-            else if (k == 2) s2 += x;
-            else s3 += x;
-        }
-        v = (s0 + s1) + (s2 + s3);
+        v = lane_col_sum<32>(col, r0 + l, r1, G);
     }
     v = group_sum(v, G);
     if (q < nq && l == 0) {
@@ -504,13 +487,16 @@ static __device__ int eig_secular(int n, EigLds &L) {
             L.kidx[r] = lane;
         }
         if (dead) L.didx[__popcll(dm & below)] = lane;
-        if (lane == 0) L.k = __popcll(lm);
+        const int kl = __popcll(lm);
+        wave_sync();
+        // two remaining poles too close for the secular equation: the fallback (k = -1)
+        const bool close = lane + 1 < kl && L.dk[lane + 1] - L.dk[lane] <= 1e3 * tol;
+        const uint64_t cm = __ballot(close);
+        if (lane == 0) L.k = cm ? -1 : kl;
     }
     __syncthreads();
     const int k = __builtin_amdgcn_readfirstlane(L.k);  // uniform: scalar loop bounds
-    bool close = false;
-    for (int j = tid; j + 1 < k; j += TPB) close = close || L.dk[j + 1] - L.dk[j] <= 1e3 * tol;
-    if (__syncthreads_or(close)) return 1;
+    if (k < 0) return 1;
     const int r = tid >> 2, p = tid & 3;  // quad r; its lane p takes the poles j = p + 4u
     constexpr int RP = KM / 4;
     // this lane's poles and border entries; slots beyond k hold a zero term
