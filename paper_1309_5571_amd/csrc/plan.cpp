@@ -733,20 +733,24 @@ dmrg_status build_plan(dmrg_plan *plan, int32_t nprob, const dmrg_problem *probs
                 if (!src(pb.right, B, pr.sr, &dt.vr, &dt.sr)) continue;
                 terms.push_back(dt);
             }
-            // one task per block of up to 64 rows
-            for (int64_t r0 = 0; r0 < pr.dl; r0 += 64) {
-                Task t{};
-                t.diag_begin = d_b;
-                t.diag_end = (int)terms.size();
-                t.c_off = pr.off;
-                t.x_off = pr.off;
-                t.ldc = (int32_t)pr.dr;
-                t.row0 = (int32_t)r0;
-                t.m = (int32_t)std::min<int64_t>(64, pr.dl - r0);
-                t.n = (int32_t)pr.dr;
-                t.member = member;
-                tasks.push_back(t);
-            }
+            // tiles of at most 1024 elements (whole rows when they fit)
+            if (pr.dl <= 0 || pr.dr <= 0) continue;
+            const int64_t tn = std::min<int64_t>(pr.dr, 1024), tm = std::max<int64_t>(1, 1024 / tn);
+            for (int64_t r0 = 0; r0 < pr.dl; r0 += tm)
+                for (int64_t c0 = 0; c0 < pr.dr; c0 += tn) {
+                    Task t{};
+                    t.diag_begin = d_b;
+                    t.diag_end = (int)terms.size();
+                    t.c_off = pr.off;
+                    t.x_off = pr.off;
+                    t.ldc = (int32_t)pr.dr;
+                    t.row0 = (int32_t)r0;
+                    t.col0 = (int32_t)c0;
+                    t.m = (int32_t)std::min<int64_t>(tm, pr.dl - r0);
+                    t.n = (int32_t)std::min<int64_t>(tn, pr.dr - c0);
+                    t.member = member;
+                    tasks.push_back(t);
+                }
         }
         DMRG_TRY(upload(plan, terms, &plan->d_diag_terms, stream));
         DMRG_TRY(upload(plan, tasks, &plan->d_diag_tasks, stream));

@@ -565,38 +565,66 @@ __global__ __launch_bounds__(64) void k_reduce_terms(const int32_t *__restrict__
     if (threadIdx.x == 0) gcoef[k] = s;
 }
 
-// Elementwise diagonal of H (preconditioner): out = sum_d c_d vl[r sl] vr[c sr].
-__global__ __launch_bounds__(256) void k_hdiag(const Task *__restrict__ tasks, int ntask,
-                                               const DiagTerm *__restrict__ diags, const double *__restrict__ coef,
-                                               double *__restrict__ out) {
-    const int t = blockIdx.x;
-    if (t >= ntask) return;
-    const Task tk = tasks[t];
-    const int64_t cnt = (int64_t)tk.m * tk.n;
-    for (int64_t e = threadIdx.x; e < cnt; e += 256) {
-        const int64_t r = tk.row0 + e / tk.n, c = e % tk.n;
-        double v = 0.0;
-        for (int d = tk.diag_begin; d < tk.diag_end; ++d) {
-            const DiagTerm dt = diags[d];
-            double w = coef[dt.coef];
-            if (dt.vl) w *= ((const double *)(uintptr_t)dt.vl)[r * dt.sl];
-            if (dt.vr) w *= ((const double *)(uintptr_t)dt.vr)[c * dt.sr];
-            v += w;
-        }
-        out[tk.c_off + r * tk.ldc + c] = v;
-    }
-}
+// A tile's diagonal terms staged in LDS, DIAG_LDS at a time: slice addresses
+// (null = ones), strides and coefficients.
+constexpr int DIAG_LDS = 64;
+struct DiagLds {
+    const double *vl[DIAG_LDS], *vr[DIAG_LDS];
+    double c[DIAG_LDS];
+    int sl[DIAG_LDS], sr[DIAG_LDS];
+};
 
-// Folded diagonal terms of a pass: out[o] = sum_d c_d vl[r] vr[c] over each
-// stage-B tile's diagonal terms (tiles partition the output, one writer each).
-__global__ __launch_bounds__(256) void k_diag_fold(const Task *__restrict__ tasks, int ntask,
-                                                   const DiagTerm *__restrict__ diags,
-                                                   const double *__restrict__ coef, double *__restrict__ out) {
+// out = sum_d c_d vl[r sl] vr[c sr] over each task's diagonal terms, for
+// every element of the task's tile (at most 1024 elements: 4 per thread).
+// The terms are staged in LDS first, so the slice loads of several terms are
+// in flight together; each element sums its terms in list order.
+__global__ __launch_bounds__(256) void k_diag_terms(const Task *__restrict__ tasks, int ntask,
+                                                    const DiagTerm *__restrict__ diags,
+                                                    const double *__restrict__ coef, double *__restrict__ out) {
+    __shared__ DiagLds D;
     for (int t = blockIdx.x; t < ntask; t += gridDim.x) {
         const Task tk = tasks[t];
-        for (int e = threadIdx.x; e < tk.m * tk.n; e += 256) {
-            const int64_t rr = tk.row0 + e / tk.n, cc = tk.col0 + e % tk.n;
-            out[tk.c_off + rr * tk.ldc + cc] = diag_sum(diags, tk.diag_begin, tk.diag_end, coef, 1.0, rr, cc);
+        const int cnt = tk.m * tk.n;
+        if (cnt <= 0) continue;
+        int64_t rr[4], cc[4];
+        double acc[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = min((int)threadIdx.x + 256 * q, cnt - 1);
+            rr[q] = tk.row0 + e / tk.n;
+            cc[q] = tk.col0 + e % tk.n;
+            acc[q] = 0.0;
+        }
+        for (int d0 = tk.diag_begin; d0 < tk.diag_end; d0 += DIAG_LDS) {
+            const int nt = min(DIAG_LDS, tk.diag_end - d0);
+            __syncthreads();  // the previous terms are no longer read
+            if ((int)threadIdx.x < nt) {
+                const DiagTerm dt = diags[d0 + threadIdx.x];
+                D.vl[threadIdx.x] = (const double *)(uintptr_t)dt.vl;
+                D.vr[threadIdx.x] = (const double *)(uintptr_t)dt.vr;
+                D.c[threadIdx.x] = coef[dt.coef];
+                D.sl[threadIdx.x] = dt.sl;
+                D.sr[threadIdx.x] = dt.sr;
+            }
+            __syncthreads();
+#pragma unroll 4
+            for (int d = 0; d < nt; ++d) {
+                const double *vl = D.vl[d], *vr = D.vr[d];
+                const double c = D.c[d];
+                const int sl = D.sl[d], sr = D.sr[d];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    double w = c;
+                    if (vl) w *= vl[rr[q] * sl];
+                    if (vr) w *= vr[cc[q] * sr];
+                    acc[q] += w;
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = threadIdx.x + 256 * q;
+            if (e < cnt) out[tk.c_off + rr[q] * tk.ldc + cc[q]] = acc[q];
         }
     }
 }
@@ -677,8 +705,8 @@ dmrg_status launch_adjoint(dmrg_plan *plan, const double *coef, const double *in
 dmrg_status launch_diag_fold(dmrg_plan *plan, int slot, const double *coef, double *out, hipStream_t s) {
     const PassSet &ps = plan->fwd[slot];
     if (ps.stageB.ntask)
-        hipLaunchKernelGGL(k_diag_fold, task_grid(ps.stageB.ntask), dim3(256), 0, s, ps.stageB.tasks,
-                           ps.stageB.ntask, ps.diags, coef, out);
+        hipLaunchKernelGGL(k_diag_terms, task_grid(ps.stageB.ntask), dim3(256), 0, s, ps.stageB.tasks,
+                           ps.stageB.ntask, (const DiagTerm *)ps.diags, coef, out);
     DMRG_HIP(hipGetLastError());
     return DMRG_OK;
 }
@@ -703,8 +731,8 @@ dmrg_status launch_gcoef(dmrg_plan *plan, const double *psi, const double *gbar,
 
 dmrg_status launch_diagonal(dmrg_plan *plan, const double *coef, double *diag, hipStream_t s) {
     if (plan->n_diag_tasks)
-        hipLaunchKernelGGL(k_hdiag, dim3(plan->n_diag_tasks), dim3(256), 0, s, plan->d_diag_tasks,
-                           plan->n_diag_tasks, plan->d_diag_terms, coef, diag);
+        hipLaunchKernelGGL(k_diag_terms, task_grid(plan->n_diag_tasks), dim3(256), 0, s, plan->d_diag_tasks,
+                           plan->n_diag_tasks, (const DiagTerm *)plan->d_diag_terms, coef, diag);
     DMRG_HIP(hipGetLastError());
     return DMRG_OK;
 }
