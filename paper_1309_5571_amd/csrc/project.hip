@@ -50,15 +50,26 @@ struct Tr<DMRG_F64> {
     typedef double store_t;  // operator copies / intermediates
     typedef double val_t;    // operand value in registers
     typedef v4d acc_t;
-    static constexpr int KPL = 4;  // consecutive k per lane per k-block
+    // A k-block of 16 is four MFMA steps.  Consecutive layout: lane group g
+    // holds k = kb + 4 g + j (step j), so a lane's operands are contiguous.
+    // Strided layout: step j takes k = kb + 4 j + g, so the steps of a block
+    // that lie beyond the contraction length can be skipped (short blocks).
+    static constexpr int KPL = 4;
+    template <bool STRIDED>
+    __device__ static int kbase(int kb, int g) { return STRIDED ? kb + g : kb + KPL * g; }
+    template <bool STRIDED>
+    __device__ static constexpr int kstep() { return STRIDED ? 4 : 1; }
+    template <bool STRIDED>
+    __device__ static int nsteps(int rem) { return STRIDED ? min(KPL, (rem + 3) >> 2) : (rem > 0 ? KPL : 0); }
     // accumulator value v of lane (g = lane / 16, c = lane % 16) holds D[4 v + g][c]
     __device__ static int row(int g, int v) { return 4 * v + g; }
     __device__ static val_t from_in(double x) { return x; }
     __device__ static val_t from_store(store_t x) { return x; }
     __device__ static store_t to_store(double x) { return x; }
-    __device__ static void mma(acc_t &c, const val_t (&a)[KPL], const val_t (&b)[KPL]) {
+    __device__ static void mma(acc_t &c, const val_t (&a)[KPL], const val_t (&b)[KPL], int ns) {
 #pragma unroll
-        for (int j = 0; j < KPL; ++j) c = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j], b[j], c, 0, 0, 0);
+        for (int j = 0; j < KPL; ++j)
+            if (j < ns) c = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j], b[j], c, 0, 0, 0);
     }
 };
 
@@ -67,15 +78,22 @@ struct Tr<DMRG_F32> {
     typedef float store_t;
     typedef float val_t;
     typedef v4f acc_t;
-    static constexpr int KPL = 4;
+    static constexpr int KPL = 4;  // k layouts as for FP64
+    template <bool STRIDED>
+    __device__ static int kbase(int kb, int g) { return STRIDED ? kb + g : kb + KPL * g; }
+    template <bool STRIDED>
+    __device__ static constexpr int kstep() { return STRIDED ? 4 : 1; }
+    template <bool STRIDED>
+    __device__ static int nsteps(int rem) { return STRIDED ? min(KPL, (rem + 3) >> 2) : (rem > 0 ? KPL : 0); }
     // accumulator value v of lane (g, c) holds D[4 g + v][c]
     __device__ static int row(int g, int v) { return 4 * g + v; }
     __device__ static val_t from_in(double x) { return (float)x; }
     __device__ static val_t from_store(store_t x) { return x; }
     __device__ static store_t to_store(double x) { return (float)x; }
-    __device__ static void mma(acc_t &c, const val_t (&a)[KPL], const val_t (&b)[KPL]) {
+    __device__ static void mma(acc_t &c, const val_t (&a)[KPL], const val_t (&b)[KPL], int ns) {
 #pragma unroll
-        for (int j = 0; j < KPL; ++j) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], b[j], c, 0, 0, 0);
+        for (int j = 0; j < KPL; ++j)
+            if (j < ns) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], b[j], c, 0, 0, 0);
     }
 };
 
@@ -84,13 +102,22 @@ struct Tr<DMRG_BF16> {
     typedef uint16_t store_t;  // bf16 bit pattern
     typedef uint16_t val_t;
     typedef v4f acc_t;
+    // one 16x16x32 MFMA per k-block of 32: lane group g holds k = kb + 8 g + j
+    // (one layout)
     static constexpr int KPL = 8;
+    template <bool STRIDED>
+    __device__ static int kbase(int kb, int g) { return kb + KPL * g; }
+    template <bool STRIDED>
+    __device__ static constexpr int kstep() { return 1; }
+    template <bool STRIDED>
+    __device__ static int nsteps(int rem) { return rem > 0 ? 1 : 0; }
     // accumulator value v of lane (g, c) holds D[4 g + v][c]
     __device__ static int row(int g, int v) { return 4 * g + v; }
     __device__ static val_t from_in(double x) { return f32_to_bf16_bits((float)x); }
     __device__ static val_t from_store(store_t x) { return x; }
     __device__ static store_t to_store(double x) { return f32_to_bf16_bits((float)x); }
-    __device__ static void mma(acc_t &c, const val_t (&a)[KPL], const val_t (&b)[KPL]) {
+    __device__ static void mma(acc_t &c, const val_t (&a)[KPL], const val_t (&b)[KPL], int ns) {
+        if (ns <= 0) return;
         v8bf va, vb;
 #pragma unroll
         for (int j = 0; j < KPL; ++j) {
@@ -103,8 +130,8 @@ struct Tr<DMRG_BF16> {
 
 // ------------------------------------------------------------------ operand fetch
 
-// P fragment: rows row (tile-local r), k = kb + KPL*g + j
-template <int PREC, bool PIN, bool PT>
+// P fragment: rows row (tile-local r), k = k0 + kstep j (k0: the lane's kbase)
+template <int PREC, bool PIN, bool PT, bool ST = false>
 __device__ __forceinline__ void load_p(typename Tr<PREC>::val_t (&v)[Tr<PREC>::KPL], const Seg &s,
                                        const double *__restrict__ in, const void *__restrict__ tmp, int row,
                                        bool row_ok, int k0, int K, double scale) {
@@ -113,7 +140,7 @@ __device__ __forceinline__ void load_p(typename Tr<PREC>::val_t (&v)[Tr<PREC>::K
         const double *P = in + s.p;
 #pragma unroll
         for (int j = 0; j < T::KPL; ++j) {
-            int k = k0 + j;
+            int k = k0 + j * T::template kstep<ST>();
             double x = 0.0;
             if (row_ok && k < K) x = PT ? P[(int64_t)k * s.ldp + row] : P[(int64_t)row * s.ldp + k];
             v[j] = T::from_in(x * scale);
@@ -124,7 +151,7 @@ __device__ __forceinline__ void load_p(typename Tr<PREC>::val_t (&v)[Tr<PREC>::K
                                            : (const typename T::store_t *)tmp + s.p;
 #pragma unroll
         for (int j = 0; j < T::KPL; ++j) {
-            int k = k0 + j;
+            int k = k0 + j * T::template kstep<ST>();
             typename T::store_t x = 0;
             if (row_ok && k < K) x = PT ? P[(int64_t)k * s.ldp + row] : P[(int64_t)row * s.ldp + k];
             v[j] = T::from_store(x);
@@ -132,8 +159,8 @@ __device__ __forceinline__ void load_p(typename Tr<PREC>::val_t (&v)[Tr<PREC>::K
     }
 }
 
-// Q fragment: column col, k = kb + KPL*g + j
-template <int PREC, bool QIN, bool QT>
+// Q fragment: column col, k = k0 + kstep j (k0: the lane's kbase)
+template <int PREC, bool QIN, bool QT, bool ST = false>
 __device__ __forceinline__ void load_q(typename Tr<PREC>::val_t (&v)[Tr<PREC>::KPL], const Seg &s,
                                        const double *__restrict__ in, const void *__restrict__ tmp, int col,
                                        bool col_ok, int k0, int K, double scale) {
@@ -142,7 +169,7 @@ __device__ __forceinline__ void load_q(typename Tr<PREC>::val_t (&v)[Tr<PREC>::K
         const double *Q = in + s.q;
 #pragma unroll
         for (int j = 0; j < T::KPL; ++j) {
-            int k = k0 + j;
+            int k = k0 + j * T::template kstep<ST>();
             double x = 0.0;
             if (col_ok && k < K) x = QT ? Q[(int64_t)col * s.ldq + k] : Q[(int64_t)k * s.ldq + col];
             v[j] = T::from_in(x * scale);
@@ -153,7 +180,7 @@ __device__ __forceinline__ void load_q(typename Tr<PREC>::val_t (&v)[Tr<PREC>::K
                                            : (const typename T::store_t *)tmp + s.q;
 #pragma unroll
         for (int j = 0; j < T::KPL; ++j) {
-            int k = k0 + j;
+            int k = k0 + j * T::template kstep<ST>();
             typename T::store_t x = 0;
             if (col_ok && k < K) x = QT ? Q[(int64_t)col * s.ldq + k] : Q[(int64_t)k * s.ldq + col];
             v[j] = T::from_store(x);
@@ -203,7 +230,7 @@ __device__ __forceinline__ void item_gemm(typename Tr<PREC>::acc_t (&acc)[2][2],
     typename T::val_t pv[NS][NKB][T::KPL], qv[NS][NKB][T::KPL];
 #pragma unroll
     for (int b = 0; b < NKB; ++b) {
-        const int kk = k0 + b * KB + T::KPL * g;
+        const int kk = T::template kbase<false>(k0 + b * KB, g);
 #pragma unroll
         for (int t = 0; t < NS; ++t) {
             if (t < nsr) load_p<PREC, PIN, PT>(pv[t][b], s, in, tmp, prow[t], pok[t], kk, s.K, ps[t]);
@@ -216,7 +243,7 @@ __device__ __forceinline__ void item_gemm(typename Tr<PREC>::acc_t (&acc)[2][2],
         for (int x = 0; x < NS; ++x)
 #pragma unroll
             for (int y = 0; y < NS; ++y)
-                if (x < nsr && y < nsc) T::mma(acc[x][y], pv[x][b], qv[y][b]);
+                if (x < nsr && y < nsc) T::mma(acc[x][y], pv[x][b], qv[y][b], T::KPL);
 }
 
 // Wave-local ordering of LDS accesses (lanes of one wavefront exchange data
@@ -247,16 +274,18 @@ __device__ __forceinline__ void fused_item(typename Tr<PREC>::acc_t (&acc)[2][2]
     for (int cs = 0; cs < 4; ++cs) a1[cs] = typename T::acc_t{0, 0, 0, 0};
     for (int k0 = 0; k0 < s.K; k0 += KB) {
         typename T::val_t pv[T::KPL], qv[4][T::KPL];
-        const int kk = k0 + T::KPL * g;
-        load_p<PREC, false, false>(pv, s, in, nullptr, prow, pok, kk, s.K, 1.0);
+        const int kk = T::template kbase<true>(k0, g);
+        load_p<PREC, false, false, true>(pv, s, in, nullptr, prow, pok, kk, s.K, 1.0);
 #pragma unroll
         for (int cs = 0; cs < 4; ++cs) {
             const int col = cs * 16 + r16;
-            if (cs < ncs) load_q<PREC, true, false>(qv[cs], s, in, nullptr, col < s.K2 ? col : 0, col < s.K2, kk, s.K, 1.0);
+            if (cs < ncs)
+                load_q<PREC, true, false, true>(qv[cs], s, in, nullptr, col < s.K2 ? col : 0, col < s.K2, kk, s.K,
+                                                1.0);
         }
 #pragma unroll
         for (int cs = 0; cs < 4; ++cs)
-            if (cs < ncs) T::mma(a1[cs], pv, qv[cs]);
+            if (cs < ncs) T::mma(a1[cs], pv, qv[cs], T::template nsteps<true>(s.K - k0));
     }
 #pragma unroll
     for (int cs = 0; cs < 4; ++cs)
@@ -268,10 +297,10 @@ __device__ __forceinline__ void fused_item(typename Tr<PREC>::acc_t (&acc)[2][2]
     const typename T::store_t *R = (const typename T::store_t *)(uintptr_t)s.r;
     for (int k0 = 0; k0 < s.K2; k0 += KB) {
         typename T::val_t pv[T::KPL], qv[NS][T::KPL];
-        const int kk = k0 + T::KPL * g;
+        const int kk = T::template kbase<true>(k0, g);
 #pragma unroll
         for (int j = 0; j < T::KPL; ++j) {
-            const int k = kk + j;
+            const int k = kk + j * T::template kstep<true>();
             pv[j] = T::from_in((k < s.K2) ? tl[r16 * 64 + k] : 0.0);
         }
 #pragma unroll
@@ -282,7 +311,7 @@ __device__ __forceinline__ void fused_item(typename Tr<PREC>::acc_t (&acc)[2][2]
             if (b < nsc) {
 #pragma unroll
                 for (int j = 0; j < T::KPL; ++j) {
-                    const int k = kk + j;
+                    const int k = kk + j * T::template kstep<true>();
                     typename T::store_t x = 0;
                     if (ok && k < s.K2) x = R[(int64_t)col * s.ldr + k];
                     qv[b][j] = T::from_store(x);
@@ -291,7 +320,7 @@ __device__ __forceinline__ void fused_item(typename Tr<PREC>::acc_t (&acc)[2][2]
         }
 #pragma unroll
         for (int b = 0; b < NS; ++b)
-            if (b < nsc) T::mma(acc[0][b], pv, qv[b]);
+            if (b < nsc) T::mma(acc[0][b], pv, qv[b], T::template nsteps<true>(s.K2 - k0));
     }
     wave_lds_sync();  // the slice is rewritten by this wavefront's next fused item
 }
@@ -366,15 +395,13 @@ __device__ __forceinline__ double diag_sum(const DiagTerm *__restrict__ diags, i
 // dealt round-robin to the wavefronts; the PW partial tiles are summed in a
 // fixed order through LDS, so results do not depend on scheduling.
 template <int PREC, int MODE, int NS>
-__global__ __launch_bounds__(64 * PW) void k_tasks(const Task *__restrict__ tasks, int ntask,
-                                                  const Seg *__restrict__ segs, const DiagTerm *__restrict__ diags,
-                                                  const double *__restrict__ in, const void *__restrict__ tmp,
-                                                  void *__restrict__ out, const double *__restrict__ coef,
-                                                  const double *__restrict__ gbar, double *__restrict__ partials,
-                                                  const int32_t *__restrict__ mask,
-                                                  const double *__restrict__ dfold, RayArgs ray) {
+__device__ __forceinline__ void tasks_run(const Task *__restrict__ tasks, int ntask, const Seg *__restrict__ segs,
+                                          const DiagTerm *__restrict__ diags, const double *__restrict__ in,
+                                          const void *__restrict__ tmp, void *__restrict__ out,
+                                          const double *__restrict__ coef, const double *__restrict__ gbar,
+                                          double *__restrict__ partials, const int32_t *__restrict__ mask,
+                                          const double *__restrict__ dfold, RayArgs ray, double *smem_tasks) {
     typedef Tr<PREC> T;
-    extern __shared__ __align__(16) double smem_tasks[];
     double(*red)[32][33] = reinterpret_cast<double(*)[32][33]>(smem_tasks);
     double *wtile = smem_tasks + PW * 32 * 33;  // output values of the tile (Rayleigh step)
     const int wave = threadIdx.x >> 6;
@@ -553,6 +580,29 @@ __global__ __launch_bounds__(64 * PW) void k_tasks(const Task *__restrict__ task
     }
 }
 
+#define DMRG_TASK_ARGS                                                                                          \
+    const Task *__restrict__ tasks, int ntask, const Seg *__restrict__ segs, const DiagTerm *__restrict__ diags, \
+        const double *__restrict__ in, const void *__restrict__ tmp, void *__restrict__ out,                     \
+        const double *__restrict__ coef, const double *__restrict__ gbar, double *__restrict__ partials,          \
+        const int32_t *__restrict__ mask, const double *__restrict__ dfold, RayArgs ray
+#define DMRG_TASK_PASS tasks, ntask, segs, diags, in, tmp, out, coef, gbar, partials, mask, dfold, ray, smem_tasks
+
+// The task kernel.  The 16x16-tile forward variants are held to two
+// workgroups per CU (at most 256 registers per lane): a pass has a few hundred
+// tiles, and with one workgroup per CU the second half would wait a round.
+template <int PREC, int MODE, int NS>
+__global__ __launch_bounds__(64 * PW) void k_tasks(DMRG_TASK_ARGS) {
+    extern __shared__ __align__(16) double smem_tasks[];
+    tasks_run<PREC, MODE, NS>(DMRG_TASK_PASS);
+}
+template <int PREC, int MODE>
+__global__ __launch_bounds__(64 * PW) __attribute__((amdgpu_waves_per_eu(2))) void k_tasks_w2(DMRG_TASK_ARGS) {
+    extern __shared__ __align__(16) double smem_tasks[];
+    tasks_run<PREC, MODE, 1>(DMRG_TASK_PASS);
+}
+#undef DMRG_TASK_ARGS
+#undef DMRG_TASK_PASS
+
 // gcoef[k] = sum of the partial slots listed for term k, in list order.
 __global__ __launch_bounds__(64) void k_reduce_terms(const int32_t *__restrict__ ptr, const int32_t *__restrict__ ent,
                                                      const double *__restrict__ partials, double *__restrict__ gcoef,
@@ -665,12 +715,21 @@ static dim3 task_grid(int ntask) { return dim3(std::min(ntask, TASK_GRID_MAX)); 
 // k_tasks<PREC, MODE, NS> launch with the pass list's sub-tile count
 template <int PREC, int MODE, class... Args>
 static void launch_tasks(const Lists &l, size_t lds, hipStream_t s, Args... args) {
-    if (l.ns == 1)
-        hipLaunchKernelGGL((k_tasks<PREC, MODE, 1>), task_grid(l.ntask), dim3(64 * PW), lds, s, l.tasks, l.ntask,
-                           args...);
-    else
-        hipLaunchKernelGGL((k_tasks<PREC, MODE, 2>), task_grid(l.ntask), dim3(64 * PW), lds, s, l.tasks, l.ntask,
-                           args...);
+    if constexpr (MODE != 2) {
+        if (l.ns == 1)
+            hipLaunchKernelGGL((k_tasks_w2<PREC, MODE>), task_grid(l.ntask), dim3(64 * PW), lds, s, l.tasks,
+                               l.ntask, args...);
+        else
+            hipLaunchKernelGGL((k_tasks<PREC, MODE, 2>), task_grid(l.ntask), dim3(64 * PW), lds, s, l.tasks,
+                               l.ntask, args...);
+    } else {
+        if (l.ns == 1)
+            hipLaunchKernelGGL((k_tasks<PREC, MODE, 1>), task_grid(l.ntask), dim3(64 * PW), lds, s, l.tasks,
+                               l.ntask, args...);
+        else
+            hipLaunchKernelGGL((k_tasks<PREC, MODE, 2>), task_grid(l.ntask), dim3(64 * PW), lds, s, l.tasks,
+                               l.ntask, args...);
+    }
 }
 
 template <int PREC>
