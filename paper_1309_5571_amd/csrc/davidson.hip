@@ -85,21 +85,26 @@ struct DavArgs {
     DavState *st = nullptr;           // [nprob]
     const double *X0 = nullptr;       // [n] start vectors of the phase (private copy)
     DavSummary *sum = nullptr;        // [nprob] device view of pinned host memory
+    // set-up gate of a phase queued behind another one: 1 when every member
+    // finished the previous phase, else 0 and the phase idles (null: no gate)
+    int32_t *gate = nullptr;
 };
 
 struct DavidsonWork {
-    DavArgs a;
+    // arguments of the reduced-precision phase (a) and of the FP64 phase (a2):
+    // the same basis and work buffers, each with its own activity flags,
+    // folded diagonal and summary, so that the FP64 phase can be queued behind
+    // the other before its outcome is known
+    DavArgs a, a2;
     int kmax = 0, kmin = 0;
     int eig_solver = 0;
-    DavSummary *h_sum = nullptr;  // pinned, mapped [nprob]
+    DavSummary *h_sum = nullptr, *h_sum2 = nullptr;  // pinned, mapped [nprob]
     // iterations the last phase of each kind needed (first launch size of the next one);
     // kind = 4 * slot + 2 * (ends in X0) + (starts from X0)
     std::map<int, int> last_iters;
-    hipStream_t side = nullptr;   // second branch of the phase set-up
-    hipEvent_t fork = nullptr, join = nullptr;
-    // graphs by (slot, 4 * first i (0: with the phase set-up) + 2 * finalize-into-X0 + parity of the
-    // first iteration, iterations, kmax, eig_solver,
-    // max_iter, tol bits, floor bits)
+    // graphs by (slot + 2 * gated + 4 * with the preconditioner diagonal, 4 * first i (0: with the
+    // phase set-up) + 2 * finalize-into-X0 +
+    // parity of the first iteration, iterations, kmax, eig_solver, max_iter, tol bits, floor bits)
     std::map<std::tuple<int, int, int, int, int, int, uint64_t, uint64_t>, hipGraphExec_t> graphs;
     std::vector<void *> owned;
 };
@@ -266,11 +271,24 @@ static __device__ void set_state(const DavArgs &w, int m, double tol, double flo
     S.Y[0][0] = S.Y[1][0] = 1.0;
 }
 
+// Gate of a phase queued behind another (one block): open when no member of
+// the previous phase (flags prev) still iterates; closed, this phase's members
+// are marked idle and its set-up leaves every shared buffer untouched.
+__global__ __launch_bounds__(TPB) void k_gate(const int32_t *__restrict__ prev, DavArgs w) {
+    int any = 0;
+    for (int m = threadIdx.x; m < w.nprob; m += TPB) any |= prev[m];
+    any = __syncthreads_or(any);
+    if (threadIdx.x == 0) *w.gate = any ? 0 : 1;
+    if (any)
+        for (int m = threadIdx.x; m < w.nprob; m += TPB) w.active[m] = 0;
+}
+
 // Phase start (the first block of each member resets its state); partial
 // rows: ||psi||^2 (column 0) and min D (column 1) of each chunk.
 __global__ __launch_bounds__(TPB) void k_init_norm(const double *__restrict__ psi, DavArgs w, double tol,
                                                    double floor_, int max_iter, int stag) {
     __shared__ double lds[4];
+    if (w.gate && !*w.gate) return;  // the previous phase is still running: idle
     const Chunk ck = chunk_of(w, blockIdx.x);
     if ((int)blockIdx.x == ck.c0 && threadIdx.x == 0) set_state(w, ck.member, tol, floor_, max_iter, stag);
     double ss = 0.0, mn = INFINITY;
@@ -291,6 +309,7 @@ __global__ __launch_bounds__(TPB) void k_init_norm(const double *__restrict__ ps
 __global__ __launch_bounds__(TPB) void k_init_vec(const double *__restrict__ psi, DavArgs w) {
     __shared__ double lds[4];
     __shared__ double sums[1];
+    if (w.gate && !*w.gate) return;
     const int c = blockIdx.x;
     const Chunk ck = chunk_of(w, c);
     sum_rows(w.pa, w.nchunk, ck.c0, ck.c1, 1, 1, sums);
@@ -1264,13 +1283,20 @@ static dmrg_status work_alloc(dmrg_plan *plan, int kmax, int kmin, hipStream_t s
     DMRG_HIP(hipHostMalloc((void **)&w->h_sum, plan->nprob * sizeof(DavSummary),
                            hipHostMallocMapped | hipHostMallocCoherent));
     DMRG_HIP(hipHostGetDevicePointer((void **)&A.sum, w->h_sum, 0));
-    DMRG_HIP(hipStreamCreateWithFlags(&w->side, hipStreamNonBlocking));
-    DMRG_HIP(hipEventCreateWithFlags(&w->fork, hipEventDisableTiming));
-    DMRG_HIP(hipEventCreateWithFlags(&w->join, hipEventDisableTiming));
+    DavArgs &B = w->a2;  // FP64 phase: own flags, folded diagonal, gate and summary
+    B = A;
+    DMRG_TRY(alloc((void **)&B.active, plan->nprob * 4));
+    DMRG_TRY(alloc((void **)&B.dfold, n * 8));
+    DMRG_TRY(alloc((void **)&B.gate, 8));
+    DMRG_HIP(hipHostMalloc((void **)&w->h_sum2, plan->nprob * sizeof(DavSummary),
+                           hipHostMallocMapped | hipHostMallocCoherent));
+    DMRG_HIP(hipHostGetDevicePointer((void **)&B.sum, w->h_sum2, 0));
     DMRG_HIP(hipMemcpyAsync(A.chunk_member, cm.data(), cm.size() * 4, hipMemcpyHostToDevice, s));
     DMRG_HIP(hipMemcpyAsync(A.chunk_begin, cb.data(), cb.size() * 8, hipMemcpyHostToDevice, s));
     DMRG_HIP(hipMemcpyAsync(A.member_chunk, mc.data(), mc.size() * 4, hipMemcpyHostToDevice, s));
     DMRG_HIP(hipMemsetAsync(A.st, 0, plan->nprob * sizeof(DavState), s));
+    DMRG_HIP(hipMemsetAsync(A.active, 0, plan->nprob * 4, s));
+    DMRG_HIP(hipMemsetAsync(B.active, 0, plan->nprob * 4, s));
     DMRG_HIP(hipStreamSynchronize(s));
     return DMRG_OK;
 }
@@ -1281,9 +1307,7 @@ dmrg_status davidson_free(dmrg_plan *plan) {
     for (auto &kv : w->graphs) (void)hipGraphExecDestroy(kv.second);
     for (void *p : w->owned) (void)hipFree(p);
     if (w->h_sum) (void)hipHostFree(w->h_sum);
-    if (w->fork) (void)hipEventDestroy(w->fork);
-    if (w->join) (void)hipEventDestroy(w->join);
-    if (w->side) (void)hipStreamDestroy(w->side);
+    if (w->h_sum2) (void)hipHostFree(w->h_sum2);
     delete w;
     plan->dav = nullptr;
     return DMRG_OK;
@@ -1302,9 +1326,9 @@ static RayArgs ray_args(const DavArgs &A, int i) {
 
 // Enqueue `count` iterations starting at subspace size i and iteration number
 // t (1 = the phase's first; its parity selects the Y/theta buffer); returns the next i.
-static dmrg_status enqueue_iters(dmrg_plan *plan, int slot, int i, int t, int count, int *i_next, hipStream_t s) {
+static dmrg_status enqueue_iters(dmrg_plan *plan, const DavArgs &A, int slot, int i, int t, int count, int *i_next,
+                                 hipStream_t s) {
     DavidsonWork *w = plan->dav;
-    const DavArgs &A = w->a;
     const int kmax = w->kmax, kmin = w->kmin;
     const dim3 grid(A.nchunk), block(TPB);
     const int32_t *slot_begin = plan->fwd[slot].slot_begin;
@@ -1349,22 +1373,23 @@ static dmrg_status enqueue_iters(dmrg_plan *plan, int slot, int i, int t, int co
     return DMRG_OK;
 }
 
-// Phase set-up: state, start vector, diagonal folding (on a parallel branch),
-// and W(:, 0) with the rows of B(0, 0).  Reads the private copy X0 of the
-// start vectors.
-static dmrg_status enqueue_setup(dmrg_plan *plan, int slot, double tol, double floor_, int max_iter, hipStream_t s) {
-    DavidsonWork *w = plan->dav;
-    const DavArgs &A = w->a;
+// Phase set-up: state, start vector, diagonal folding (with the preconditioner
+// diagonal for the first phase of a solve), and W(:, 0) with the rows of
+// B(0, 0).  Reads the private copy X0 of the start vectors.  With A.gate the
+// set-up first tests the previous phase (flags prev) and idles unless it has
+// finished.
+static dmrg_status enqueue_setup(dmrg_plan *plan, const DavArgs &A, const int32_t *prev, int slot, bool with_diag,
+                                 double tol, double floor_, int max_iter, hipStream_t s) {
     const dim3 grid(A.nchunk), block(TPB);
-    DMRG_HIP(hipEventRecord(w->fork, s));
-    DMRG_HIP(hipStreamWaitEvent(w->side, w->fork, 0));
-    DMRG_TRY(launch_diag_fold(plan, slot, A.coef, A.dfold, w->side));  // coefficients are fixed for the phase
-    DMRG_HIP(hipEventRecord(w->join, w->side));
+    if (A.gate) hipLaunchKernelGGL(k_gate, dim3(1), block, 0, s, prev, A);
+    // one queue, no branches: a cross-queue join inside a graph costs more than
+    // the few microseconds the diagonal kernels take
+    if (with_diag) DMRG_TRY(launch_diagonal(plan, A.coef, A.D, s));  // preconditioner diagonal of the solve
+    DMRG_TRY(launch_diag_fold(plan, slot, A.coef, A.dfold, s));       // coefficients are fixed for the phase
     // a reduced-precision phase ends early when its residual stops halving (5 iterations)
     hipLaunchKernelGGL(k_init_norm, grid, block, 0, s, A.X0, A, tol, floor_, max_iter, slot == 0 ? 0 : 5);
     hipLaunchKernelGGL(k_init_vec, grid, block, 0, s, A.X0, A);
     DMRG_HIP(hipGetLastError());
-    DMRG_HIP(hipStreamWaitEvent(s, w->join, 0));
     const RayArgs ray = ray_args(A, 1);
     return launch_project(plan, slot, A.coef, A.T, A.W, s, A.active, A.dfold, &ray);
 }
@@ -1397,81 +1422,129 @@ static int predict_iters(const std::vector<DavSummary> &sm, double tol, int cap)
 // One phase (fixed projection precision) to tolerance tol, in launches of
 // iterations (captured hipGraphs when use_graph); after each launch the
 // per-member summary comes back to the host and decides about the next one.
-// psi_in: start vectors (nullptr: X0 already holds them).  fin_x0: every
-// launch ends with X0 = the current Ritz vectors (start of a following phase).
-static dmrg_status run_phase(dmrg_plan *plan, int slot, const double *psi_in, double tol, double floor_,
-                             int max_iter, bool use_graph, int chunk_max, bool fin_x0, hipStream_t s,
-                             int *iters_out, std::vector<DavSummary> &out) {
+struct Phase {
+    int slot = 0;                    // 1: reduced-precision projection, 0: FP64
+    bool psi_in = false;             // starts from the caller's vectors (staged in X0), else from X0 as left
+    bool with_diag = false;          // the set-up also computes the preconditioner diagonal
+    double tol = 0.0, floor_ = 0.0;
+    int max_iter = 1, chunk_max = 1;
+    bool use_graph = true;
+    bool fin_x0 = false;        // every launch ends with X0 = the current Ritz vectors
+    bool gated = false;         // the first launch idles unless the other phase has finished
+    double *fin_psi = nullptr;  // every launch ends with fin_psi = the current Ritz vectors
+    int i = 0, done = 0, cnt = 0;
+};
+
+static const DavArgs &phase_args(const DavidsonWork *w, int slot) { return slot == 0 ? w->a2 : w->a; }
+static int phase_kind(const Phase &P) { return 4 * P.slot + (P.fin_x0 ? 2 : 0) + (P.psi_in ? 0 : 1); }
+
+// The caller's coefficients and start vectors into the private copies that
+// the captured graphs read (one launch for both).
+__global__ __launch_bounds__(TPB) void k_stage(const double *__restrict__ coef, int ncoef, double *__restrict__ cdst,
+                                               const double *__restrict__ psi, int64_t n, double *__restrict__ x0) {
+    const int64_t t = (int64_t)blockIdx.x * TPB + threadIdx.x, stride = (int64_t)gridDim.x * TPB;
+    for (int64_t e = t; e < ncoef; e += stride) cdst[e] = coef[e];
+    for (int64_t e = t; e < n; e += stride) x0[e] = psi[e];
+}
+
+// First launch: as many iterations as the last phase of this kind needed (a
+// repeated solve of a plan, e.g. along a sweep, converges alike), else FIRST_CHUNK.
+static void phase_begin(const DavidsonWork *w, Phase &P) {
+    const auto hint = w->last_iters.find(phase_kind(P));
+    P.i = 0;
+    P.done = 0;
+    P.cnt = std::min({P.chunk_max, P.max_iter, hint == w->last_iters.end() ? FIRST_CHUNK : hint->second});
+}
+
+// Queue the next launch of P.cnt iterations (with the set-up when P.i == 0).
+static dmrg_status phase_launch(dmrg_plan *plan, Phase &P, hipStream_t s) {
     DavidsonWork *w = plan->dav;
-    const DavArgs &A = w->a;
-    if (psi_in) DMRG_HIP(hipMemcpyAsync((void *)A.X0, psi_in, (size_t)A.n * 8, hipMemcpyDeviceToDevice, s));
-    int i = 0;  // 0: the launch starts with the phase set-up
-    int done = 0;
-    // first launch: as many iterations as the last phase of this kind needed (a
-    // repeated solve of a plan, e.g. along a sweep, converges alike), else FIRST_CHUNK
-    const int kind = 4 * slot + (fin_x0 ? 2 : 0) + (psi_in ? 0 : 1);
-    const auto hint = w->last_iters.find(kind);
-    int cnt = std::min({chunk_max, max_iter, hint == w->last_iters.end() ? FIRST_CHUNK : hint->second});
-    std::vector<DavSummary> sm(A.nprob);
-    for (;;) {
-        const int i0 = (i == 0) ? 1 : i;
-        int inext = i0;
-        auto enqueue = [&](hipStream_t q) -> dmrg_status {
-            if (i == 0) DMRG_TRY(enqueue_setup(plan, slot, tol, floor_, max_iter, q));
-            DMRG_TRY(enqueue_iters(plan, slot, i0, done + 1, cnt, &inext, q));
-            hipLaunchKernelGGL(k_summary, dim3((A.nprob + 63) / 64), dim3(64), 0, q, A);
-            if (fin_x0)
-                set_kb(w->kmax, [&](auto kb) {  // nvec <= kmax
-                    constexpr int KB = decltype(kb)::value;
-                    hipLaunchKernelGGL(k_finalize<KB>, dim3(A.nchunk), dim3(TPB), 0, q, A, (double *)A.X0);
-                });
-            DMRG_HIP(hipGetLastError());
-            return DMRG_OK;
-        };
-        if (use_graph) {
-            auto key = std::make_tuple(slot, i * 4 + (fin_x0 ? 2 : 0) + ((done + 1) & 1), cnt, w->kmax,
-                                       w->eig_solver, max_iter, bits_of(tol), bits_of(floor_));
-            auto it = w->graphs.find(key);
-            if (it == w->graphs.end()) {
-                hipStream_t cs;
-                DMRG_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-                hipGraph_t g;
-                DMRG_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-                dmrg_status st = enqueue(cs);
-                hipError_t ce = hipStreamEndCapture(cs, &g);
-                (void)hipStreamDestroy(cs);
-                if (st < 0) return st;
-                if (ce != hipSuccess) return set_error(DMRG_E_HIP, "graph capture failed: %s", hipGetErrorString(ce));
-                hipGraphExec_t ge;
-                hipError_t ie = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-                (void)hipGraphDestroy(g);
-                if (ie != hipSuccess)
-                    return set_error(DMRG_E_HIP, "graph instantiate failed: %s", hipGetErrorString(ie));
-                it = w->graphs.emplace(key, ge).first;
-            } else {
-                // the subspace sequence is deterministic: recompute the next i
-                int ii = i0;
-                for (int q = 0; q < cnt; ++q) ii = (ii == w->kmax ? w->kmin : ii) + 1;
-                inext = ii;
-            }
-            DMRG_HIP(hipGraphLaunch(it->second, s));
+    DavArgs A = phase_args(w, P.slot);
+    const bool gated = P.gated && P.i == 0;
+    if (!gated) A.gate = nullptr;
+    const int32_t *prev = phase_args(w, 1 - P.slot).active;
+    const bool with_diag = P.with_diag && P.i == 0;
+    const int i = P.i;
+    const int i0 = (i == 0) ? 1 : i;
+    int inext = i0;
+    auto enqueue = [&](hipStream_t q) -> dmrg_status {
+        if (i == 0) DMRG_TRY(enqueue_setup(plan, A, prev, P.slot, with_diag, P.tol, P.floor_, P.max_iter, q));
+        DMRG_TRY(enqueue_iters(plan, A, P.slot, i0, P.done + 1, P.cnt, &inext, q));
+        hipLaunchKernelGGL(k_summary, dim3((A.nprob + 63) / 64), dim3(64), 0, q, A);
+        if (P.fin_x0)
+            set_kb(w->kmax, [&](auto kb) {  // nvec <= kmax
+                constexpr int KB = decltype(kb)::value;
+                hipLaunchKernelGGL(k_finalize<KB>, dim3(A.nchunk), dim3(TPB), 0, q, A, (double *)A.X0);
+            });
+        DMRG_HIP(hipGetLastError());
+        return DMRG_OK;
+    };
+    if (P.use_graph) {
+        auto key = std::make_tuple(P.slot + (gated ? 2 : 0) + (with_diag ? 4 : 0),
+                                   i * 4 + (P.fin_x0 ? 2 : 0) + ((P.done + 1) & 1), P.cnt,
+                                   w->kmax, w->eig_solver, P.max_iter, bits_of(P.tol), bits_of(P.floor_));
+        auto it = w->graphs.find(key);
+        if (it == w->graphs.end()) {
+            hipStream_t cs;
+            DMRG_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+            hipGraph_t g;
+            DMRG_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+            dmrg_status st = enqueue(cs);
+            hipError_t ce = hipStreamEndCapture(cs, &g);
+            (void)hipStreamDestroy(cs);
+            if (st < 0) return st;
+            if (ce != hipSuccess) return set_error(DMRG_E_HIP, "graph capture failed: %s", hipGetErrorString(ce));
+            hipGraphExec_t ge;
+            hipError_t ie = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (ie != hipSuccess) return set_error(DMRG_E_HIP, "graph instantiate failed: %s", hipGetErrorString(ie));
+            it = w->graphs.emplace(key, ge).first;
         } else {
-            DMRG_TRY(enqueue(s));
+            // the subspace sequence is deterministic: recompute the next i
+            int ii = i0;
+            for (int q = 0; q < P.cnt; ++q) ii = (ii == w->kmax ? w->kmin : ii) + 1;
+            inext = ii;
         }
-        i = inext;
-        done += cnt;
-        DMRG_HIP(hipStreamSynchronize(s));  // k_summary wrote h_sum
-        sm.assign(w->h_sum, w->h_sum + A.nprob);
-        bool any = false;
-        for (const DavSummary &r : sm) any = any || r.active;
-        if (!any || done >= max_iter) break;
-        cnt = std::min(predict_iters(sm, tol, chunk_max), max_iter - done);
+        DMRG_HIP(hipGraphLaunch(it->second, s));
+    } else {
+        DMRG_TRY(enqueue(s));
     }
-    out = sm;
-    *iters_out = done;
+    if (P.fin_psi)  // outside the graphs: the caller's buffer changes from call to call
+        set_kb(w->kmax, [&](auto kb) {
+            constexpr int KB = decltype(kb)::value;
+            hipLaunchKernelGGL(k_finalize<KB>, dim3(A.nchunk), dim3(TPB), 0, s, A, P.fin_psi);
+        });
+    DMRG_HIP(hipGetLastError());
+    P.i = inext;
+    P.done += P.cnt;
+    return DMRG_OK;
+}
+
+// After the stream has synchronized: the phase's summary into sm; true when
+// the phase needs another launch (then P.cnt is its size).
+static bool phase_more(DavidsonWork *w, Phase &P, std::vector<DavSummary> &sm) {
+    const DavSummary *h = P.slot == 0 ? w->h_sum2 : w->h_sum;
+    const int nprob = w->a.nprob;
+    sm.assign(h, h + nprob);
+    bool any = false;
+    for (const DavSummary &r : sm) any = any || r.active;
+    if (any && P.done < P.max_iter) {
+        P.cnt = std::min(predict_iters(sm, P.tol, P.chunk_max), P.max_iter - P.done);
+        return true;
+    }
     int need = 1;
     for (const DavSummary &r : sm) need = std::max(need, (int)r.iters);
-    w->last_iters[kind] = need;
+    w->last_iters[phase_kind(P)] = need;
+    return false;
+}
+
+// A whole phase, one synchronization per launch.
+static dmrg_status phase_run(dmrg_plan *plan, Phase &P, hipStream_t s, std::vector<DavSummary> &sm) {
+    phase_begin(plan->dav, P);
+    do {
+        DMRG_TRY(phase_launch(plan, P, s));
+        DMRG_HIP(hipStreamSynchronize(s));  // k_summary wrote the mapped summary
+    } while (phase_more(plan->dav, P, sm));
     return DMRG_OK;
 }
 
@@ -1590,36 +1663,66 @@ dmrg_status dmrg_davidson(dmrg_plan *plan, const double *coef, const dmrg_davids
     DavidsonWork *w = plan->dav;
     w->eig_solver = o.eig_solver;
     const DavArgs &A = w->a;
-    if (plan->nterm_total)
-        DMRG_HIP(hipMemcpyAsync(A.coef, coef, plan->nterm_total * 8, hipMemcpyDeviceToDevice, s));
-    DMRG_TRY(launch_diagonal(plan, A.coef, A.D, s));
+    hipLaunchKernelGGL(k_stage, dim3((unsigned)std::min<int64_t>((A.n + TPB - 1) / TPB, 2048)), dim3(TPB), 0, s, coef,
+                       plan->nterm_total, A.coef, psi, A.n, (double *)A.X0);
+    DMRG_HIP(hipGetLastError());
 
-    auto finalize = [&]() -> dmrg_status {  // psi = V y, ordered on the stream
-        set_kb(kmax, [&](auto kb) {  // nvec <= kmax
-            constexpr int KB = decltype(kb)::value;
-            hipLaunchKernelGGL(k_finalize<KB>, dim3(A.nchunk), dim3(TPB), 0, s, A, psi);
-        });
-        DMRG_HIP(hipGetLastError());
-        return DMRG_OK;
-    };
     std::vector<DavSummary> hs, low;
-    int done = 0;
     const bool two_phase = o.prec != DMRG_F64;
-    if (two_phase) {
-        double tl = o.tol_lowprec > 0 ? o.tol_lowprec : (o.prec == DMRG_F32 ? 1e-5 : 1e-3);
-        tl = std::max(tl, o.tol);
-        // with refinement the phase-1 Ritz vectors stay in X0 as the start of phase 2
-        DMRG_TRY(run_phase(plan, 1, psi, tl, o.precond_floor, o.max_iter, o.use_graph != 0, o.graph_chunk,
-                           o.refine != 0, s, &done, low));
-        if (!o.refine) DMRG_TRY(finalize());
-        for (int p = 0; p < plan->nprob; ++p)
-            if (low[p].bad_start == 1) return set_error(DMRG_E_NONFINITE, "member %d: zero or non-finite start", p);
-        hs = low;
+    Phase P1, P2;  // reduced precision, FP64
+    P1.slot = 1;
+    P2.slot = 0;
+    for (Phase *P : {&P1, &P2}) {
+        P->floor_ = o.precond_floor;
+        P->max_iter = o.max_iter;
+        P->chunk_max = o.graph_chunk;
+        P->use_graph = o.use_graph != 0;
     }
-    if (!two_phase || o.refine) {
-        DMRG_TRY(run_phase(plan, 0, two_phase ? nullptr : psi, o.tol, o.precond_floor, o.max_iter,
-                           o.use_graph != 0, o.graph_chunk, false, s, &done, hs));
-        DMRG_TRY(finalize());
+    P1.tol = std::max(o.tol, o.tol_lowprec > 0 ? o.tol_lowprec : (o.prec == DMRG_F32 ? 1e-5 : 1e-3));
+    P2.tol = o.tol;
+    P2.fin_psi = psi;  // psi = V y, ordered on the stream
+    if (!two_phase) {
+        P2.psi_in = P2.with_diag = true;
+        DMRG_TRY(phase_run(plan, P2, s, hs));
+    } else if (!o.refine) {
+        P1.psi_in = P1.with_diag = true;
+        P1.fin_psi = psi;
+        DMRG_TRY(phase_run(plan, P1, s, low));
+        hs = low;
+    } else {
+        // the phase-1 Ritz vectors stay in X0 as the start of phase 2
+        P1.psi_in = P1.with_diag = true;
+        P1.fin_x0 = true;
+        phase_begin(w, P1);
+        // a repeated solve (both phases seen before) queues phase 2 right behind
+        // the first launch of phase 1, gated on device: one synchronization fewer
+        const bool chain = P1.use_graph && w->last_iters.count(phase_kind(P1)) && w->last_iters.count(phase_kind(P2));
+        DMRG_TRY(phase_launch(plan, P1, s));
+        if (chain) {
+            P2.gated = true;
+            phase_begin(w, P2);
+            DMRG_TRY(phase_launch(plan, P2, s));
+        }
+        DMRG_HIP(hipStreamSynchronize(s));
+        bool more1 = phase_more(w, P1, low);
+        bool open = chain;  // phase 2 has run its first launch
+        for (const DavSummary &r : low) open = open && !r.active;
+        if (open) {
+            while (phase_more(w, P2, hs)) {
+                DMRG_TRY(phase_launch(plan, P2, s));
+                DMRG_HIP(hipStreamSynchronize(s));
+            }
+        } else {  // finish phase 1, then phase 2 from its start (a gated launch idled)
+            while (more1) {
+                DMRG_TRY(phase_launch(plan, P1, s));
+                DMRG_HIP(hipStreamSynchronize(s));
+                more1 = phase_more(w, P1, low);
+            }
+            for (int p = 0; p < plan->nprob; ++p)
+                if (low[p].bad_start == 1) return set_error(DMRG_E_NONFINITE, "member %d: zero or non-finite start", p);
+            P2.gated = false;
+            DMRG_TRY(phase_run(plan, P2, s, hs));
+        }
     }
     const bool both = two_phase && o.refine;
     dmrg_status ret = DMRG_OK;

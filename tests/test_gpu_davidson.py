@@ -120,6 +120,33 @@ def test_mixed_precision_refinement(prec):
     assert info[0]["iterations_low"] > 0
 
 
+def test_queued_fp64_phase_matches_sequential():
+    """A repeated mixed-precision solve queues the FP64 phase right behind the
+    first launch of the reduced-precision phase, gated on device.  Whether the
+    gate opens (phase 1 finished in that launch) or stays shut (phase 1 needs
+    more iterations than last time, so it continues and phase 2 restarts), the
+    outcome is bit-identical to the sequential run of a fresh plan."""
+    p = gen.config(3)
+    x0 = gen.start_vector(_plan(p, "f32").n, 7)
+
+    def solve(pl, x):
+        psi, E, info, st = pl.davidson(_dev(x), tol=1e-10, prec="f32")
+        assert st == 0, info
+        return psi.cpu().numpy(), E[0], info[0]
+
+    ref = solve(_plan(p, "f32"), x0)  # first solve of a plan: no queued phase
+    pl = _plan(p, "f32")
+    solve(pl, x0)
+    opened = solve(pl, x0)  # same start: phase 1 ends within its first launch
+    solve(pl, ref[0])  # converged start: both phases record one-iteration launch sizes
+    shut = solve(pl, x0)  # phase 1 outlasts its first launch: the queued phase idles
+    for got in (opened, shut):
+        assert np.array_equal(got[0], ref[0])
+        assert got[1] == ref[1]
+        for key in ("iterations", "iterations_low", "projections", "restarts", "converged"):
+            assert got[2][key] == ref[2][key], key
+
+
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
 def test_reduced_precision_phase_exits_on_stagnation(prec):
     """A phase-1 tolerance below what the reduced-precision projection can reach:
