@@ -33,6 +33,7 @@
 #include <cstring>
 #include <map>
 #include <tuple>
+#include <vector>
 
 #include "gemv.h"
 #include "internal.h"
@@ -102,10 +103,11 @@ struct DavidsonWork {
     // iterations the last phase of each kind needed (first launch size of the next one);
     // kind = 4 * slot + 2 * (ends in X0) + (starts from X0)
     std::map<int, int> last_iters;
-    // graphs by (slot + 2 * gated + 4 * with the preconditioner diagonal, 4 * first i (0: with the
-    // phase set-up) + 2 * finalize-into-X0 +
-    // parity of the first iteration, iterations, kmax, eig_solver, max_iter, tol bits, floor bits)
-    std::map<std::tuple<int, int, int, int, int, int, uint64_t, uint64_t>, hipGraphExec_t> graphs;
+    // graphs by the key fields of each phase launch they hold, in order: slot + 2 * gated + 4 *
+    // with the preconditioner diagonal, 4 * first i (0: with the phase set-up) + 2 *
+    // finalize-into-X0 + parity of the first iteration, iterations, kmax, eig_solver,
+    // max_iter, tol bits, floor bits
+    std::map<std::vector<uint64_t>, hipGraphExec_t> graphs;
     std::vector<void *> owned;
 };
 
@@ -1456,40 +1458,51 @@ static void phase_begin(const DavidsonWork *w, Phase &P) {
     P.cnt = std::min({P.chunk_max, P.max_iter, hint == w->last_iters.end() ? FIRST_CHUNK : hint->second});
 }
 
-// Queue the next launch of P.cnt iterations (with the set-up when P.i == 0).
-static dmrg_status phase_launch(dmrg_plan *plan, Phase &P, hipStream_t s) {
+// Graph key fields of a phase's next launch.
+static void phase_key(const DavidsonWork *w, const Phase &P, std::vector<uint64_t> &k) {
+    const bool gated = P.gated && P.i == 0, with_diag = P.with_diag && P.i == 0;
+    k.insert(k.end(), {(uint64_t)(P.slot + (gated ? 2 : 0) + (with_diag ? 4 : 0)),
+                       (uint64_t)(P.i * 4 + (P.fin_x0 ? 2 : 0) + ((P.done + 1) & 1)), (uint64_t)P.cnt,
+                       (uint64_t)w->kmax, (uint64_t)w->eig_solver, (uint64_t)P.max_iter, bits_of(P.tol),
+                       bits_of(P.floor_)});
+}
+
+// Record the next launch of P.cnt iterations of a phase (with the set-up when P.i == 0).
+static dmrg_status phase_enqueue(dmrg_plan *plan, const Phase &P, hipStream_t q) {
     DavidsonWork *w = plan->dav;
     DavArgs A = phase_args(w, P.slot);
     const bool gated = P.gated && P.i == 0;
     if (!gated) A.gate = nullptr;
     const int32_t *prev = phase_args(w, 1 - P.slot).active;
-    const bool with_diag = P.with_diag && P.i == 0;
-    const int i = P.i;
-    const int i0 = (i == 0) ? 1 : i;
+    const int i0 = (P.i == 0) ? 1 : P.i;
     int inext = i0;
-    auto enqueue = [&](hipStream_t q) -> dmrg_status {
-        if (i == 0) DMRG_TRY(enqueue_setup(plan, A, prev, P.slot, with_diag, P.tol, P.floor_, P.max_iter, q));
-        DMRG_TRY(enqueue_iters(plan, A, P.slot, i0, P.done + 1, P.cnt, &inext, q));
-        hipLaunchKernelGGL(k_summary, dim3((A.nprob + 63) / 64), dim3(64), 0, q, A);
-        if (P.fin_x0)
-            set_kb(w->kmax, [&](auto kb) {  // nvec <= kmax
-                constexpr int KB = decltype(kb)::value;
-                hipLaunchKernelGGL(k_finalize<KB>, dim3(A.nchunk), dim3(TPB), 0, q, A, (double *)A.X0);
-            });
-        DMRG_HIP(hipGetLastError());
-        return DMRG_OK;
-    };
-    if (P.use_graph) {
-        auto key = std::make_tuple(P.slot + (gated ? 2 : 0) + (with_diag ? 4 : 0),
-                                   i * 4 + (P.fin_x0 ? 2 : 0) + ((P.done + 1) & 1), P.cnt,
-                                   w->kmax, w->eig_solver, P.max_iter, bits_of(P.tol), bits_of(P.floor_));
+    if (P.i == 0) DMRG_TRY(enqueue_setup(plan, A, prev, P.slot, P.with_diag, P.tol, P.floor_, P.max_iter, q));
+    DMRG_TRY(enqueue_iters(plan, A, P.slot, i0, P.done + 1, P.cnt, &inext, q));
+    hipLaunchKernelGGL(k_summary, dim3((A.nprob + 63) / 64), dim3(64), 0, q, A);
+    if (P.fin_x0)
+        set_kb(w->kmax, [&](auto kb) {  // nvec <= kmax
+            constexpr int KB = decltype(kb)::value;
+            hipLaunchKernelGGL(k_finalize<KB>, dim3(A.nchunk), dim3(TPB), 0, q, A, (double *)A.X0);
+        });
+    DMRG_HIP(hipGetLastError());
+    return DMRG_OK;
+}
+
+// Queue the next launch of each of np phases, in order, as one captured graph
+// (use_graph) or directly; the caller's output (fin_psi) is written after it.
+static dmrg_status launch_phases(dmrg_plan *plan, Phase *const *ph, int np, hipStream_t s) {
+    DavidsonWork *w = plan->dav;
+    if (ph[0]->use_graph) {
+        std::vector<uint64_t> key;
+        for (int j = 0; j < np; ++j) phase_key(w, *ph[j], key);
         auto it = w->graphs.find(key);
         if (it == w->graphs.end()) {
             hipStream_t cs;
             DMRG_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
             hipGraph_t g;
             DMRG_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-            dmrg_status st = enqueue(cs);
+            dmrg_status st = DMRG_OK;
+            for (int j = 0; j < np && st >= 0; ++j) st = phase_enqueue(plan, *ph[j], cs);
             hipError_t ce = hipStreamEndCapture(cs, &g);
             (void)hipStreamDestroy(cs);
             if (st < 0) return st;
@@ -1499,25 +1512,32 @@ static dmrg_status phase_launch(dmrg_plan *plan, Phase &P, hipStream_t s) {
             (void)hipGraphDestroy(g);
             if (ie != hipSuccess) return set_error(DMRG_E_HIP, "graph instantiate failed: %s", hipGetErrorString(ie));
             it = w->graphs.emplace(key, ge).first;
-        } else {
-            // the subspace sequence is deterministic: recompute the next i
-            int ii = i0;
-            for (int q = 0; q < P.cnt; ++q) ii = (ii == w->kmax ? w->kmin : ii) + 1;
-            inext = ii;
         }
         DMRG_HIP(hipGraphLaunch(it->second, s));
     } else {
-        DMRG_TRY(enqueue(s));
+        for (int j = 0; j < np; ++j) DMRG_TRY(phase_enqueue(plan, *ph[j], s));
     }
-    if (P.fin_psi)  // outside the graphs: the caller's buffer changes from call to call
-        set_kb(w->kmax, [&](auto kb) {
-            constexpr int KB = decltype(kb)::value;
-            hipLaunchKernelGGL(k_finalize<KB>, dim3(A.nchunk), dim3(TPB), 0, s, A, P.fin_psi);
-        });
+    for (int j = 0; j < np; ++j) {
+        Phase &P = *ph[j];
+        if (P.fin_psi)  // outside the graphs: the caller's buffer changes from call to call
+            set_kb(w->kmax, [&](auto kb) {
+                constexpr int KB = decltype(kb)::value;
+                hipLaunchKernelGGL(k_finalize<KB>, dim3(w->a.nchunk), dim3(TPB), 0, s, phase_args(w, P.slot),
+                                   P.fin_psi);
+            });
+        // the subspace sequence is deterministic: i after P.cnt iterations
+        int ii = (P.i == 0) ? 1 : P.i;
+        for (int q = 0; q < P.cnt; ++q) ii = (ii == w->kmax ? w->kmin : ii) + 1;
+        P.i = ii;
+        P.done += P.cnt;
+    }
     DMRG_HIP(hipGetLastError());
-    P.i = inext;
-    P.done += P.cnt;
     return DMRG_OK;
+}
+
+static dmrg_status phase_launch(dmrg_plan *plan, Phase &P, hipStream_t s) {
+    Phase *one[1] = {&P};
+    return launch_phases(plan, one, 1, s);
 }
 
 // After the stream has synchronized: the phase's summary into sm; true when
@@ -1697,11 +1717,13 @@ dmrg_status dmrg_davidson(dmrg_plan *plan, const double *coef, const dmrg_davids
         // a repeated solve (both phases seen before) queues phase 2 right behind
         // the first launch of phase 1, gated on device: one synchronization fewer
         const bool chain = P1.use_graph && w->last_iters.count(phase_kind(P1)) && w->last_iters.count(phase_kind(P2));
-        DMRG_TRY(phase_launch(plan, P1, s));
         if (chain) {
             P2.gated = true;
             phase_begin(w, P2);
-            DMRG_TRY(phase_launch(plan, P2, s));
+            Phase *both[2] = {&P1, &P2};  // one graph
+            DMRG_TRY(launch_phases(plan, both, 2, s));
+        } else {
+            DMRG_TRY(phase_launch(plan, P1, s));
         }
         DMRG_HIP(hipStreamSynchronize(s));
         bool more1 = phase_more(w, P1, low);
