@@ -204,7 +204,11 @@ void dmrg_davidson_default_opts(dmrg_davidson_opts *opts);
  * Iterations run in launches of at most graph_chunk: the first as long as the
  * plan's previous phase of the same kind took (4 without history), then as
  * many as the residual decay predicts; the host waits for each launch's summary.
- * energy and info are final on return; psi is completed in stream order
+ * When the plan has solved with refinement before, the first launch of the
+ * FP64 phase is queued right behind the first launch of phase 1 (one graph) and
+ * starts on device only if every member has finished phase 1; otherwise it
+ * idles, phase 1 continues and phase 2 starts afterwards (same results either
+ * way).  energy and info are final on return; psi is completed in stream order
  * (work enqueued on stream afterwards sees it; synchronize stream before
  * reading it from the host).  Returns DMRG_W_NOT_CONVERGED if any member did not
  * converge, DMRG_E_BREAKDOWN if any broke down, DMRG_E_NONFINITE for a
