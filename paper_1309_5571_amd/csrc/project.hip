@@ -188,6 +188,56 @@ __device__ __forceinline__ void load_q(typename Tr<PREC>::val_t (&v)[Tr<PREC>::K
     }
 }
 
+// Raw fragments for the reduced-precision paths: FP64 from the input vector,
+// the stored type from operator blocks and intermediates, converted to the
+// MFMA type only where consumed.  A conversion next to a guarded load makes the
+// wavefront wait for that load before it issues the next one (the FP64 path
+// needs no conversion and loads through load_p / load_q).
+template <int PREC, bool IN>
+struct RawT {
+    typedef typename Tr<PREC>::store_t type;
+};
+template <int PREC>
+struct RawT<PREC, true> {
+    typedef double type;
+};
+template <int PREC, bool IN>
+__device__ __forceinline__ void cvt_frag(typename Tr<PREC>::val_t (&v)[Tr<PREC>::KPL],
+                                         const typename RawT<PREC, IN>::type (&x)[Tr<PREC>::KPL], double scale) {
+#pragma unroll
+    for (int j = 0; j < Tr<PREC>::KPL; ++j) {
+        if constexpr (IN)
+            v[j] = Tr<PREC>::from_in(x[j] * scale);
+        else
+            v[j] = Tr<PREC>::from_store(x[j]);
+    }
+}
+// op(P)[row, k] (Q: op(Q)[k, col]) for k = k0 + kstep j, zero outside; the block
+// at base + off, leading dimension ld, transposed when TR.
+template <int PREC, bool IN, bool TR, bool ST>
+__device__ __forceinline__ void load_raw(typename RawT<PREC, IN>::type (&v)[Tr<PREC>::KPL],
+                                         const typename RawT<PREC, IN>::type *__restrict__ B, int ld, int rc,
+                                         bool rc_ok, int k0, int K) {
+    typedef typename RawT<PREC, IN>::type R;
+#pragma unroll
+    for (int j = 0; j < Tr<PREC>::KPL; ++j) {
+        const int k = k0 + j * Tr<PREC>::template kstep<ST>();
+        R x = 0;
+        if (rc_ok && k < K) x = TR ? B[(int64_t)k * ld + rc] : B[(int64_t)rc * ld + k];
+        v[j] = x;
+    }
+}
+template <int PREC, bool IN>
+__device__ __forceinline__ const typename RawT<PREC, IN>::type *raw_base(const double *__restrict__ in,
+                                                                         const void *__restrict__ tmp, uint64_t a,
+                                                                         int16_t kind) {
+    typedef typename RawT<PREC, IN>::type R;
+    if constexpr (IN)
+        return in + a;
+    else
+        return (kind == OPD_ABS) ? (const R *)(uintptr_t)a : (const R *)tmp + a;
+}
+
 constexpr int PW = 4;            // wavefronts per workgroup
 // dynamic LDS of the task kernel: PW partial tiles + one tile of output values
 constexpr size_t TASK_LDS = (size_t)(PW * 32 * 33 + 1024) * sizeof(double);
@@ -227,23 +277,53 @@ __device__ __forceinline__ void item_gemm(typename Tr<PREC>::acc_t (&acc)[2][2],
         if (PIN && s.pscale && pok[t]) ps[t] = ((const double *)(uintptr_t)s.pscale)[prow[t]];
         if (QIN && s.qscale && qok[t]) qs[t] = ((const double *)(uintptr_t)s.qscale)[qcol[t]];
     }
-    typename T::val_t pv[NS][NKB][T::KPL], qv[NS][NKB][T::KPL];
+    if constexpr (PREC == DMRG_F64) {
+        typename T::val_t pv[NS][NKB][T::KPL], qv[NS][NKB][T::KPL];
 #pragma unroll
-    for (int b = 0; b < NKB; ++b) {
-        const int kk = T::template kbase<false>(k0 + b * KB, g);
+        for (int b = 0; b < NKB; ++b) {
+            const int kk = T::template kbase<false>(k0 + b * KB, g);
 #pragma unroll
-        for (int t = 0; t < NS; ++t) {
-            if (t < nsr) load_p<PREC, PIN, PT>(pv[t][b], s, in, tmp, prow[t], pok[t], kk, s.K, ps[t]);
-            if (t < nsc) load_q<PREC, QIN, QT>(qv[t][b], s, in, tmp, qcol[t], qok[t], kk, s.K, qs[t]);
+            for (int t = 0; t < NS; ++t) {
+                if (t < nsr) load_p<PREC, PIN, PT>(pv[t][b], s, in, tmp, prow[t], pok[t], kk, s.K, ps[t]);
+                if (t < nsc) load_q<PREC, QIN, QT>(qv[t][b], s, in, tmp, qcol[t], qok[t], kk, s.K, qs[t]);
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < NKB; ++b)
+#pragma unroll
+            for (int x = 0; x < NS; ++x)
+#pragma unroll
+                for (int y = 0; y < NS; ++y)
+                    if (x < nsr && y < nsc) T::mma(acc[x][y], pv[x][b], qv[y][b], T::KPL);
+    } else {
+        typename RawT<PREC, PIN>::type pr[NS][NKB][T::KPL];
+        typename RawT<PREC, QIN>::type qr[NS][NKB][T::KPL];
+        const auto *P = raw_base<PREC, PIN>(in, tmp, s.p, s.pkind);
+        const auto *Q = raw_base<PREC, QIN>(in, tmp, s.q, s.qkind);
+#pragma unroll
+        for (int b = 0; b < NKB; ++b) {
+            const int kk = T::template kbase<false>(k0 + b * KB, g);
+#pragma unroll
+            for (int t = 0; t < NS; ++t) {
+                if (t < nsr) load_raw<PREC, PIN, PT, false>(pr[t][b], P, s.ldp, prow[t], pok[t], kk, s.K);
+                if (t < nsc) load_raw<PREC, QIN, !QT, false>(qr[t][b], Q, s.ldq, qcol[t], qok[t], kk, s.K);
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < NKB; ++b) {
+            typename T::val_t pv[NS][T::KPL], qv[NS][T::KPL];
+#pragma unroll
+            for (int t = 0; t < NS; ++t) {
+                cvt_frag<PREC, PIN>(pv[t], pr[t][b], ps[t]);
+                cvt_frag<PREC, QIN>(qv[t], qr[t][b], qs[t]);
+            }
+#pragma unroll
+            for (int x = 0; x < NS; ++x)
+#pragma unroll
+                for (int y = 0; y < NS; ++y)
+                    if (x < nsr && y < nsc) T::mma(acc[x][y], pv[x], qv[y], T::KPL);
         }
     }
-#pragma unroll
-    for (int b = 0; b < NKB; ++b)
-#pragma unroll
-        for (int x = 0; x < NS; ++x)
-#pragma unroll
-            for (int y = 0; y < NS; ++y)
-                if (x < nsr && y < nsc) T::mma(acc[x][y], pv[x][b], qv[y][b], T::KPL);
 }
 
 // Wave-local ordering of LDS accesses (lanes of one wavefront exchange data
@@ -275,13 +355,28 @@ __device__ __forceinline__ void fused_item(typename Tr<PREC>::acc_t (&acc)[2][2]
     for (int k0 = 0; k0 < s.K; k0 += KB) {
         typename T::val_t pv[T::KPL], qv[4][T::KPL];
         const int kk = T::template kbase<true>(k0, g);
-        load_p<PREC, false, false, true>(pv, s, in, nullptr, prow, pok, kk, s.K, 1.0);
+        if constexpr (T::KPL == 4 && PREC != DMRG_F64) {  // FP32: raw FP64 input, converted at the MFMA
+            double qr[4][T::KPL];
+            load_p<PREC, false, false, true>(pv, s, in, nullptr, prow, pok, kk, s.K, 1.0);
 #pragma unroll
-        for (int cs = 0; cs < 4; ++cs) {
-            const int col = cs * 16 + r16;
-            if (cs < ncs)
-                load_q<PREC, true, false, true>(qv[cs], s, in, nullptr, col < s.K2 ? col : 0, col < s.K2, kk, s.K,
-                                                1.0);
+            for (int cs = 0; cs < 4; ++cs) {
+                const int col = cs * 16 + r16;
+                if (cs < ncs)
+                    load_raw<PREC, true, true, true>(qr[cs], in + s.q, s.ldq, col < s.K2 ? col : 0, col < s.K2, kk,
+                                                     s.K);
+            }
+#pragma unroll
+            for (int cs = 0; cs < 4; ++cs)
+                if (cs < ncs) cvt_frag<PREC, true>(qv[cs], qr[cs], 1.0);
+        } else {
+            load_p<PREC, false, false, true>(pv, s, in, nullptr, prow, pok, kk, s.K, 1.0);
+#pragma unroll
+            for (int cs = 0; cs < 4; ++cs) {
+                const int col = cs * 16 + r16;
+                if (cs < ncs)
+                    load_q<PREC, true, false, true>(qv[cs], s, in, nullptr, col < s.K2 ? col : 0, col < s.K2, kk,
+                                                    s.K, 1.0);
+            }
         }
 #pragma unroll
         for (int cs = 0; cs < 4; ++cs)
