@@ -279,15 +279,27 @@ __device__ __forceinline__ void item_gemm(typename Tr<PREC>::acc_t (&acc)[2][2],
     }
     if constexpr (PREC == DMRG_F64) {
         typename T::val_t pv[NS][NKB][T::KPL], qv[NS][NKB][T::KPL];
+        const double *P = raw_base<PREC, PIN>(in, tmp, s.p, s.pkind);
+        const double *Q = raw_base<PREC, QIN>(in, tmp, s.q, s.qkind);
 #pragma unroll
         for (int b = 0; b < NKB; ++b) {
             const int kk = T::template kbase<false>(k0 + b * KB, g);
 #pragma unroll
             for (int t = 0; t < NS; ++t) {
-                if (t < nsr) load_p<PREC, PIN, PT>(pv[t][b], s, in, tmp, prow[t], pok[t], kk, s.K, ps[t]);
-                if (t < nsc) load_q<PREC, QIN, QT>(qv[t][b], s, in, tmp, qcol[t], qok[t], kk, s.K, qs[t]);
+                if (t < nsr) load_raw<PREC, PIN, PT, false>(pv[t][b], P, s.ldp, prow[t], pok[t], kk, s.K);
+                if (t < nsc) load_raw<PREC, QIN, !QT, false>(qv[t][b], Q, s.ldq, qcol[t], qok[t], kk, s.K);
             }
         }
+        // row / column scales after all loads are issued
+#pragma unroll
+        for (int b = 0; b < NKB; ++b)
+#pragma unroll
+            for (int t = 0; t < NS; ++t)
+#pragma unroll
+                for (int j = 0; j < T::KPL; ++j) {
+                    if (PIN) pv[t][b][j] *= ps[t];
+                    if (QIN) qv[t][b][j] *= qs[t];
+                }
 #pragma unroll
         for (int b = 0; b < NKB; ++b)
 #pragma unroll
