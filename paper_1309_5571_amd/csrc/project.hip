@@ -227,6 +227,26 @@ __device__ __forceinline__ void load_raw(typename RawT<PREC, IN>::type (&v)[Tr<P
         v[j] = x;
     }
 }
+// As load_raw without a branch per load: indices outside the block are clamped
+// to its element (0, 0) and the values zeroed after every load has been issued.
+template <int PREC, bool IN, bool TR, bool ST>
+__device__ __forceinline__ void load_raw_u(typename RawT<PREC, IN>::type (&v)[Tr<PREC>::KPL],
+                                           const typename RawT<PREC, IN>::type *__restrict__ B, int ld, int rc,
+                                           bool rc_ok, int k0, int K) {
+    typedef typename RawT<PREC, IN>::type R;
+#pragma unroll
+    for (int j = 0; j < Tr<PREC>::KPL; ++j) {
+        const int k = k0 + j * Tr<PREC>::template kstep<ST>();
+        const bool ok = rc_ok && k < K;
+        const int64_t kk = ok ? k : 0, r = ok ? rc : 0;
+        v[j] = TR ? B[kk * ld + r] : B[r * ld + kk];
+    }
+#pragma unroll
+    for (int j = 0; j < Tr<PREC>::KPL; ++j) {
+        const int k = k0 + j * Tr<PREC>::template kstep<ST>();
+        v[j] = (rc_ok && k < K) ? v[j] : (R)0;
+    }
+}
 template <int PREC, bool IN>
 __device__ __forceinline__ const typename RawT<PREC, IN>::type *raw_base(const double *__restrict__ in,
                                                                          const void *__restrict__ tmp, uint64_t a,
@@ -380,6 +400,18 @@ __device__ __forceinline__ void fused_item(typename Tr<PREC>::acc_t (&acc)[2][2]
 #pragma unroll
             for (int cs = 0; cs < 4; ++cs)
                 if (cs < ncs) cvt_frag<PREC, true>(qv[cs], qr[cs], 1.0);
+        } else if constexpr (PREC != DMRG_F64) {  // BF16: unconditional loads, one sub-tile at a time
+            load_p<PREC, false, false, true>(pv, s, in, nullptr, prow, pok, kk, s.K, 1.0);
+#pragma unroll
+            for (int cs = 0; cs < 4; ++cs) {
+                const int col = cs * 16 + r16;
+                if (cs < ncs) {
+                    double qr[T::KPL];
+                    load_raw_u<PREC, true, true, true>(qr, in + s.q, s.ldq, col < s.K2 ? col : 0, col < s.K2, kk,
+                                                       s.K);
+                    cvt_frag<PREC, true>(qv[cs], qr, 1.0);
+                }
+            }
         } else {
             load_p<PREC, false, false, true>(pv, s, in, nullptr, prow, pok, kk, s.K, 1.0);
 #pragma unroll
@@ -405,10 +437,21 @@ __device__ __forceinline__ void fused_item(typename Tr<PREC>::acc_t (&acc)[2][2]
     for (int k0 = 0; k0 < s.K2; k0 += KB) {
         typename T::val_t pv[T::KPL], qv[NS][T::KPL];
         const int kk = T::template kbase<true>(k0, g);
+        if constexpr (PREC == DMRG_BF16) {  // every read first (k < 64: inside the slice), then the conversions
+            double tv[T::KPL];
 #pragma unroll
-        for (int j = 0; j < T::KPL; ++j) {
-            const int k = kk + j * T::template kstep<true>();
-            pv[j] = T::from_in((k < s.K2) ? tl[r16 * 64 + k] : 0.0);
+            for (int j = 0; j < T::KPL; ++j) tv[j] = tl[r16 * 64 + kk + j * T::template kstep<true>()];
+#pragma unroll
+            for (int j = 0; j < T::KPL; ++j) {
+                const int k = kk + j * T::template kstep<true>();
+                pv[j] = T::from_in((k < s.K2) ? tv[j] : 0.0);
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < T::KPL; ++j) {
+                const int k = kk + j * T::template kstep<true>();
+                pv[j] = T::from_in((k < s.K2) ? tl[r16 * 64 + k] : 0.0);
+            }
         }
 #pragma unroll
         for (int b = 0; b < NS; ++b) {
