@@ -15,9 +15,11 @@ projection  y = P_Q (sum_k c_k A_k (x) B_k) P_Q^T psi, by Kronecker products
 davidson    the Davidson iteration of Alg. 3 with the readings listed in the
             design notes; LAPACK/ARPACK ground states for pinning
 precision   emulated FP32/BF16 operator rounding with the FP64 diagonal split
+density     reduced density matrices of both blocks (Alg. 1, step 5), by pair
+            blocks and by the dense partial trace
 
 Every function states the passage of the paper it follows.  Nothing here is
 "parity unpinned": each function has at least one independent pin in
 ``tests/test_oracle_*.py`` (closed forms, brute force, library routines).
 """
-from . import models, sectors, projection, davidson, precision  # noqa: F401
+from . import models, sectors, projection, davidson, precision, density  # noqa: F401

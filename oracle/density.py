@@ -1,0 +1,52 @@
+"""Reduced density matrices of the two blocks, in FP64 (Alg. 1, step 5).
+
+Test infrastructure (see the package docstring).
+
+After the lowest eigenstate psi of the superblock is found, each block's
+density matrix is the partial trace of |psi><psi| over the other block
+(Sec. "The DMRG algorithm").  Two independent evaluations are given:
+
+* :func:`density_dense` scatters psi into the full m_L m_R space through the
+  brute-force index map and forms rho_L = Psi Psi^T and rho_R = Psi^T Psi
+  from the dense [m_L, m_R] coefficient matrix (tiny blocks only);
+* :func:`density_sectors` works pair by pair: a left (right) sector meets
+  exactly one right (left) sector inside the target Q, so its block of rho_L
+  (rho_R) is Psi_p Psi_p^T (Psi_p^T Psi_p) of that pair's row-major block.
+"""
+from __future__ import annotations
+
+from typing import List, Tuple
+
+import numpy as np
+
+from . import sectors
+
+
+def density_dense(prob, psi) -> Tuple[np.ndarray, np.ndarray]:
+    """Dense rho_L [m_L, m_L] and rho_R [m_R, m_R] of the state psi (psi layout)."""
+    lay = sectors.layout(prob.left, prob.right, prob.target)
+    mL, mR = prob.left.m, prob.right.m
+    full = np.zeros(mL * mR)
+    full[lay.index_map] = np.asarray(psi, dtype=np.float64)
+    Psi = full.reshape(mL, mR)
+    return Psi @ Psi.T, Psi.T @ Psi
+
+
+def density_sectors(prob, psi) -> Tuple[List[np.ndarray], List[np.ndarray]]:
+    """Per pair p of the psi layout: (rho_L block [d_L, d_L], rho_R block [d_R, d_R])."""
+    psi = np.asarray(psi, dtype=np.float64)
+    table, _ = sectors.pair_table(prob.left, prob.right, prob.target)
+    left, right = [], []
+    for off, dL, dR in table.values():
+        X = psi[off:off + dL * dR].reshape(dL, dR)
+        left.append(X @ X.T)
+        right.append(X.T @ X)
+    return left, right
+
+
+def density_flat(prob, psi) -> Tuple[np.ndarray, np.ndarray]:
+    """The blocks of :func:`density_sectors` concatenated in pair order, each
+    row-major: the layout of the library's output."""
+    left, right = density_sectors(prob, psi)
+    cat = lambda bl: np.concatenate([b.reshape(-1) for b in bl]) if bl else np.zeros(0)
+    return cat(left), cat(right)

@@ -1,0 +1,139 @@
+"""Pins of the oracle's reduced density matrices (Alg. 1, step 5).
+
+Each pin reaches the result by a route that shares nothing with the oracle's
+pair-by-pair products: a closed form (the singlet), the free-fermion
+correlation-matrix spectrum of the XX chain, the Schmidt decomposition, and the
+dense partial trace through the brute-force index map.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import gen
+from oracle import davidson, density, sectors
+
+RANDOM_CASES = [(s, r) for s in range(6) for r in (1, 2)]
+
+
+def _blocks_by_sector(prob):
+    """(left sector, right sector, d_L, d_R) of every pair, in psi order."""
+    table, _ = sectors.pair_table(prob.left, prob.right, prob.target)
+    return [(sl, sr, dl, dr) for (sl, sr), (_, dl, dr) in table.items()]
+
+
+def test_singlet_gives_maximally_mixed_spin():
+    """Two spins in their singlet ground state: each spin's density matrix is
+    1/2 times the identity (one state in each of the S^z = +-1/2 sectors)."""
+    p = gen.heisenberg_exact(1, 1)
+    E, psi, _ = davidson.ground_state_dense(p)
+    assert E == pytest.approx(-0.75, abs=1e-14)
+    left, right = density.density_sectors(p, psi)
+    assert len(left) == 2
+    for b in left + right:
+        assert b.shape == (1, 1)
+        assert b[0, 0] == pytest.approx(0.5, abs=1e-15)
+
+
+def _xx_block_spectrum(nsites, nleft):
+    """Peschel's free-fermion result for the open XX chain (Jordan-Wigner):
+    the half-filled ground state's left-block density matrix has eigenvalues
+    prod_j (n_j nu_j + (1 - n_j)(1 - nu_j)) over occupations n_j of the
+    eigenmodes of the block's correlation matrix C_ij = <c_i^+ c_j> (nu_j its
+    eigenvalues), with sum_j n_j = the block's particle number."""
+    i = np.arange(1, nsites + 1)
+    modes = [np.sqrt(2.0 / (nsites + 1)) * np.sin(k * np.pi * i / (nsites + 1)) for k in range(1, nsites + 1)]
+    occ = modes[: nsites // 2]  # half filling; the other half differs by a sign pattern only
+    C = sum(np.outer(f, f) for f in occ)[:nleft, :nleft]
+    nu = np.linalg.eigvalsh(C)
+    out = {}
+    for n in itertools.product((0, 1), repeat=nleft):
+        val = np.prod([nu[j] if n[j] else 1.0 - nu[j] for j in range(nleft)])
+        out.setdefault(sum(n), []).append(val)
+    return {k: np.sort(v) for k, v in out.items()}
+
+
+@pytest.mark.parametrize("nl,nr", [(4, 4), (3, 5)])
+def test_xx_chain_block_spectrum_matches_free_fermions(nl, nr):
+    p = gen.heisenberg_exact(nl, nr, delta=0.0)
+    _, psi, w = davidson.ground_state_dense(p)
+    assert w[1] - w[0] > 1e-3  # non-degenerate ground state
+    left, _ = density.density_sectors(p, psi)
+    want = _xx_block_spectrum(nl + nr, nl)
+    seen = set()
+    for (sl, _, dl, _), blk in zip(_blocks_by_sector(p), left):
+        lab = int(p.left.labels[sl, 0])  # 2 S^z = (#up - #down)
+        nup = (lab + nl) // 2
+        got = np.sort(np.linalg.eigvalsh(blk))
+        ref = want[nup]
+        # the spin-down-as-particle reading gives the same spectra (half filling)
+        assert got.shape == ref.shape
+        np.testing.assert_allclose(got, ref, atol=1e-12)
+        seen.add(nup)
+    assert seen == set(want.keys())
+
+
+@pytest.mark.parametrize("seed,rank", RANDOM_CASES)
+def test_schmidt_spectra_agree_and_trace_is_norm(seed, rank):
+    """Schmidt decomposition: the non-zero eigenvalues of rho_L and rho_R are
+    the same squared singular values, and both traces equal |psi|^2."""
+    p = gen.random_problem(seed, rank=rank)
+    psi = gen.start_vector(sectors.pair_table(p.left, p.right, p.target)[1], seed + 3)
+    psi *= 1.7
+    left, right = density.density_sectors(p, psi)
+    nrm2 = float(psi @ psi)
+    assert sum(np.trace(b) for b in left) == pytest.approx(nrm2, rel=1e-13)
+    assert sum(np.trace(b) for b in right) == pytest.approx(nrm2, rel=1e-13)
+    for bl, br, (_, _, dl, dr) in zip(left, right, _blocks_by_sector(p)):
+        el, er = np.sort(np.linalg.eigvalsh(bl))[::-1], np.sort(np.linalg.eigvalsh(br))[::-1]
+        r = min(dl, dr)
+        np.testing.assert_allclose(el[:r], er[:r], atol=1e-12 * nrm2)
+        assert np.all(np.abs(el[r:]) < 1e-12 * nrm2) and np.all(np.abs(er[r:]) < 1e-12 * nrm2)
+        assert np.all(el[:r] > -1e-12 * nrm2)
+
+
+@pytest.mark.parametrize("seed,rank", RANDOM_CASES)
+def test_sector_blocks_match_dense_partial_trace(seed, rank):
+    """The dense partial trace is block diagonal over sectors (charge
+    conservation); its diagonal blocks are the pair blocks, zero for sectors
+    that no pair of the target uses."""
+    p = gen.random_problem(seed, rank=rank)
+    psi = gen.start_vector(sectors.pair_table(p.left, p.right, p.target)[1], seed + 5)
+    rL, rR = density.density_dense(p, psi)
+    left, right = density.density_sectors(p, psi)
+    offL, offR = p.left.offsets(), p.right.offsets()
+    mask_l = np.zeros_like(rL, dtype=bool)
+    mask_r = np.zeros_like(rR, dtype=bool)
+    for (sl, sr, dl, dr), bl, br in zip(_blocks_by_sector(p), left, right):
+        np.testing.assert_allclose(rL[offL[sl]:offL[sl + 1], offL[sl]:offL[sl + 1]], bl, atol=1e-14, rtol=1e-13)
+        np.testing.assert_allclose(rR[offR[sr]:offR[sr + 1], offR[sr]:offR[sr + 1]], br, atol=1e-14, rtol=1e-13)
+        mask_l[offL[sl]:offL[sl + 1], offL[sl]:offL[sl + 1]] = True
+        mask_r[offR[sr]:offR[sr + 1], offR[sr]:offR[sr + 1]] = True
+    assert np.all(rL[~mask_l] == 0.0) and np.all(rR[~mask_r] == 0.0)
+
+
+def test_product_state_has_rank_one_density():
+    """psi = u (x) v inside one pair: rank one, rho_L = |v|^2 u u^T and rho_R = |u|^2 v v^T."""
+    p = gen.random_problem(2, rank=1)
+    table, n = sectors.pair_table(p.left, p.right, p.target)
+    (off, dl, dr) = max(table.values(), key=lambda t: t[1] * t[2])
+    rng = np.random.default_rng(9)
+    u, v = rng.standard_normal(dl), rng.standard_normal(dr)
+    psi = np.zeros(n)
+    psi[off:off + dl * dr] = np.outer(u, v).reshape(-1)
+    left, right = density.density_sectors(p, psi)
+    k = list(table.values()).index((off, dl, dr))
+    np.testing.assert_allclose(left[k], (v @ v) * np.outer(u, u), rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(right[k], (u @ u) * np.outer(v, v), rtol=1e-13, atol=1e-15)
+    for j, b in enumerate(left):
+        if j != k:
+            assert np.all(b == 0.0)
+
+
+def test_flat_layout_concatenates_pairs():
+    p = gen.random_problem(4, rank=2)
+    psi = gen.start_vector(sectors.pair_table(p.left, p.right, p.target)[1], 1)
+    fl, fr = density.density_flat(p, psi)
+    left, right = density.density_sectors(p, psi)
+    assert fl.size == sum(b.size for b in left) and fr.size == sum(b.size for b in right)
+    np.testing.assert_array_equal(fl[: left[0].size], left[0].reshape(-1))
