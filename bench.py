@@ -81,6 +81,35 @@ def projection_stats(plan, psi, y, prec, torch, reps=200, flush=None):
             "p90_us": float(np.percentile(d, 90))}
 
 
+def density_stats(plan, psi, reps, torch):
+    """Both blocks' reduced density matrices (Alg. 1, step 5) from psi: average
+    duration of one call (HIP events on the launch stream) and its algorithmic
+    work, a symmetric rank-K update per pair and side (d (d + 1) K FLOP, psi
+    read once and both outputs written once)."""
+    import numpy as np
+
+    lo, ro = plan.density_layout()
+    out = (torch.empty(int(lo[-1]), dtype=torch.float64, device=psi.device),
+           torch.empty(int(ro[-1]), dtype=torch.float64, device=psi.device))
+    lay = plan.layout()
+    dl = np.sqrt(np.diff(lo)).round().astype(np.int64)
+    dr = np.sqrt(np.diff(ro)).round().astype(np.int64)
+    assert np.array_equal(dl * dr, np.diff(lay["pair_off"]))
+    flop = int(np.sum(dl * (dl + 1) * dr + dr * (dr + 1) * dl))
+    nbytes = 8 * int(plan.n + lo[-1] + ro[-1])
+    s = torch.cuda.current_stream()
+    for _ in range(5):
+        plan.density(psi, out=out)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        plan.density(psi, out=out)
+    e1.record(s)
+    e1.synchronize()
+    t = e0.elapsed_time(e1) * 1e-3 / reps
+    return {"us": t * 1e6, "flop": flop, "bytes": nbytes, "tflops": flop / t * 1e-12, "GBs": nbytes / t * 1e-9}
+
+
 def cpu_baseline(p, x0):
     """The FP64 oracle (NumPy + OpenBLAS) on the host: one full Davidson solve
     of the same workload from the same start vector, plus projection timing."""
@@ -285,6 +314,8 @@ def main():
         del flush
         extra["projection_percall"] = stats
         log(f"projection per call: {stats}")
+        extra["density"] = density_stats(plan, psi, args.proj_reps, torch)
+        log(f"density matrices: {extra['density']}")
         extra["mixed_vs_fp64_time_ratio"] = (dt / args.steps * 1e3) / extra["fp64_solve"]["ms_per_solve"]
 
     # roofline of the dominant kernel: the FP64 projection, bound by HBM bytes at

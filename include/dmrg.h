@@ -231,6 +231,27 @@ dmrg_status dmrg_gemv_t(int64_t n, int32_t k, const double *V, int64_t ldv, cons
 dmrg_status dmrg_gemv_n(int64_t n, int32_t k, const double *V, int64_t ldv, const double *s,
                         double beta, double *y, void *stream);
 
+/* Reduced density matrices of the left and right blocks from a state psi
+ * (Alg. 1, step 5: each block's density matrix, built from the superblock's
+ * lowest eigenstate; it is the partial trace of |psi><psi| over the other
+ * block).  A left sector meets exactly one right sector inside the target,
+ * so for every pair p of the psi layout, with Psi_p the row-major
+ * [d_L, d_R] block of psi at pair_off[p]:
+ *   rho_left  + left_off[p]:  Psi_p Psi_p^T, row-major [d_L][d_L]
+ *   rho_right + right_off[p]: Psi_p^T Psi_p, row-major [d_R][d_R]
+ * which is that sector's whole block of the block's density matrix (sectors
+ * that no pair uses have a zero block and no storage).  psi is used as given
+ * (the traces equal |psi|^2).  Outputs are exactly symmetric.
+ *  dmrg_density_layout: host outputs [npair + 1] each (either may be NULL);
+ *    left_off[npair] and right_off[npair] are the output lengths.
+ *  dmrg_density: psi device FP64 [n]; rho_left, rho_right device FP64 of
+ *    those lengths, owned by the caller; either may be NULL (not computed);
+ *    must not overlap psi or each other.  FP64 throughout.  Batched plans:
+ *    the members' pairs in order.  Asynchronous on stream. */
+dmrg_status dmrg_density_layout(const dmrg_plan *plan, int64_t *left_off, int64_t *right_off);
+dmrg_status dmrg_density(dmrg_plan *plan, const double *psi, double *rho_left, double *rho_right,
+                         void *stream);
+
 /* Set the tile table used by later dmrg_plan_create calls: for output
  * blocks with max(rows, cols) <= bound[c] (ascending, ncls <= 8), tiles of
  * tile[c] rows and columns (16 or 32).  ncls = 0 restores the built-in table.

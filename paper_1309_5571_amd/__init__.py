@@ -251,6 +251,33 @@ class Plan:
             _stream(self.device)))
         return gpsi, gcoef
 
+    def density_layout(self) -> tuple:
+        """Element offsets [npair + 1] of each pair's block in rho_left and rho_right."""
+        lo = np.zeros(self.npair + 1, dtype=np.int64)
+        ro = np.zeros(self.npair + 1, dtype=np.int64)
+        N.check(self._lib.dmrg_density_layout(self._h, _ptr(lo, ctypes.c_int64), _ptr(ro, ctypes.c_int64)))
+        return lo, ro
+
+    def density(self, psi, left: bool = True, right: bool = True, out=None):
+        """Reduced density matrices of both blocks (Alg. 1, step 5): per pair,
+        Psi_p Psi_p^T and Psi_p^T Psi_p, row-major, concatenated in pair order
+        (offsets from density_layout).  Either output may be skipped (None).
+        out: optional (rho_left, rho_right) tensors to write into."""
+        import torch
+
+        if out is None:
+            lo, ro = self.density_layout()
+            rl = torch.empty(int(lo[-1]), dtype=torch.float64, device=self.device) if left else None
+            rr = torch.empty(int(ro[-1]), dtype=torch.float64, device=self.device) if right else None
+        else:
+            rl, rr = out
+            left, right = rl is not None, rr is not None
+        N.check(self._lib.dmrg_density(self._h, self._vec(psi, "psi"),
+                                       self._vec(rl, "rho_left") if left and rl.numel() else None,
+                                       self._vec(rr, "rho_right") if right and rr.numel() else None,
+                                       _stream(self.device)))
+        return rl, rr
+
     def diagonal(self, coef=None):
         import torch
 

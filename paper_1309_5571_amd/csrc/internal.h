@@ -183,6 +183,10 @@ struct dmrg_plan {
     dmrg::Task *d_diag_tasks = nullptr;
     dmrg::DiagTerm *d_diag_terms = nullptr;
     int32_t n_diag_tasks = 0;
+    // reduced density matrices: output offsets per pair [npair + 1] (0 left, 1 right) and tile tasks
+    std::vector<int64_t> rho_off[2];
+    void *d_rho_tasks = nullptr;
+    int32_t n_rho_tasks = 0;
     dmrg::DavidsonWork *dav = nullptr;
 };
 
@@ -209,4 +213,6 @@ dmrg_status launch_convert_jobs(const ConvJob *jobs, int njob, int prec, hipStre
 dmrg_status launch_diagonal(dmrg_plan *plan, const double *coef, double *diag, hipStream_t s);
 // davidson.hip
 dmrg_status davidson_free(dmrg_plan *plan);
+// density.hip: output offsets and tile tasks of the reduced density matrices
+dmrg_status build_density(dmrg_plan *plan, hipStream_t s);
 }  // namespace dmrg

@@ -756,6 +756,7 @@ dmrg_status build_plan(dmrg_plan *plan, int32_t nprob, const dmrg_problem *probs
         DMRG_TRY(upload(plan, tasks, &plan->d_diag_tasks, stream));
         plan->n_diag_tasks = (int32_t)tasks.size();
     }
+    DMRG_TRY(build_density(plan, stream));
     DMRG_HIP(hipStreamSynchronize(stream));
     return DMRG_OK;
 }
