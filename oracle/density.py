@@ -44,6 +44,24 @@ def density_sectors(prob, psi) -> Tuple[List[np.ndarray], List[np.ndarray]]:
     return left, right
 
 
+def eigh_blocks(blocks) -> Tuple[List[np.ndarray], List[np.ndarray]]:
+    """Alg. 1, step 6: the eigenvalues (and eigenvectors) of each density-matrix
+    block, by LAPACK, in descending order; each eigenvector's first entry of
+    largest magnitude is made positive.  Returns (values, vectors) with
+    vectors[b][:, j] the eigenvector of values[b][j]."""
+    vals, vecs = [], []
+    for B in blocks:
+        w, U = np.linalg.eigh(np.asarray(B, dtype=np.float64))
+        w, U = w[::-1].copy(), U[:, ::-1].copy()
+        for j in range(U.shape[1]):
+            k = int(np.argmax(np.abs(U[:, j])))
+            if U[k, j] < 0:
+                U[:, j] = -U[:, j]
+        vals.append(w)
+        vecs.append(U)
+    return vals, vecs
+
+
 def density_flat(prob, psi) -> Tuple[np.ndarray, np.ndarray]:
     """The blocks of :func:`density_sectors` concatenated in pair order, each
     row-major: the layout of the library's output."""

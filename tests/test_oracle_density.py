@@ -137,3 +137,37 @@ def test_flat_layout_concatenates_pairs():
     left, right = density.density_sectors(p, psi)
     assert fl.size == sum(b.size for b in left) and fr.size == sum(b.size for b in right)
     np.testing.assert_array_equal(fl[: left[0].size], left[0].reshape(-1))
+
+
+# --------------------------------------------------------------------------- step 6
+
+
+@pytest.mark.parametrize("seed,rank", RANDOM_CASES[:6])
+def test_eigh_blocks_reconstructs_and_orders(seed, rank):
+    """U diag(w) U^T = rho, U^T U = I, w descending, sign convention held."""
+    p = gen.random_problem(seed, rank=rank, dmax=30)
+    psi = gen.start_vector(sectors.pair_table(p.left, p.right, p.target)[1], seed)
+    left, right = density.density_sectors(p, psi)
+    vals, vecs = density.eigh_blocks(left + right)
+    for B, w, U in zip(left + right, vals, vecs):
+        d = B.shape[0]
+        scale = max(np.abs(B).max(), 1e-300)
+        np.testing.assert_allclose(U @ np.diag(w) @ U.T, B, atol=1e-13 * scale * d)
+        np.testing.assert_allclose(U.T @ U, np.eye(d), atol=1e-13 * d)
+        assert np.all(np.diff(w) <= 0)
+        for j in range(d):
+            k = int(np.argmax(np.abs(U[:, j])))
+            assert U[k, j] > 0
+
+
+def test_eigh_blocks_xx_chain_spectrum():
+    """The free-fermion spectra of the XX chain's left block, through the
+    oracle's step-6 routine."""
+    p = gen.heisenberg_exact(4, 4, delta=0.0)
+    _, psi, _ = davidson.ground_state_dense(p)
+    left, _ = density.density_sectors(p, psi)
+    vals, _ = density.eigh_blocks(left)
+    want = _xx_block_spectrum(8, 4)
+    for (sl, _, _, _), w in zip(_blocks_by_sector(p), vals):
+        nup = (int(p.left.labels[sl, 0]) + 4) // 2
+        np.testing.assert_allclose(w, want[nup][::-1], atol=1e-12)
