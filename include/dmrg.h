@@ -252,6 +252,24 @@ dmrg_status dmrg_density_layout(const dmrg_plan *plan, int64_t *left_off, int64_
 dmrg_status dmrg_density(dmrg_plan *plan, const double *psi, double *rho_left, double *rho_right,
                          void *stream);
 
+/* Eigen-decomposition of symmetric blocks, e.g. the density-matrix blocks of
+ * dmrg_density (Alg. 1, step 6: the eigenvalues of each block's density
+ * matrix select the states the block keeps).  Cyclic Jacobi method in FP64,
+ * one workgroup per block.
+ *  off, dim, woff: device arrays [nblk].  Block b is the row-major symmetric
+ *    [dim[b]][dim[b]] matrix at a + off[b] (every entry is read).
+ *  w + woff[b]: its eigenvalues in descending order (ties by index).
+ *  u + off[b]: row-major [dim[b]][dim[b]]; column j is the unit eigenvector
+ *    of w[woff[b] + j], with its first entry of largest magnitude positive.
+ *  a is overwritten (contents unspecified on return).  a, w and u are
+ *    device FP64, owned by the caller, and must not overlap.
+ *  info: optional device [nblk]: sweeps used, -1 if dim[b] is outside
+ *    1..2048 (the block is then not touched), -2 if 40 sweeps did not converge.
+ *  The sizes are read on the device: the caller guarantees that every
+ *  block lies inside a, w and u.  Asynchronous on stream. */
+dmrg_status dmrg_eigh_blocks(int32_t nblk, const int64_t *off, const int32_t *dim, const int64_t *woff,
+                             double *a, double *w, double *u, int32_t *info, void *stream);
+
 /* Set the tile table used by later dmrg_plan_create calls: for output
  * blocks with max(rows, cols) <= bound[c] (ascending, ncls <= 8), tiles of
  * tile[c] rows and columns (16 or 32).  ncls = 0 restores the built-in table.

@@ -386,3 +386,37 @@ def gemv_n(V, s, y, beta: float = 0.0, k: Optional[int] = None):
                                 ctypes.c_void_p(s.data_ptr()), beta, ctypes.c_void_p(y.data_ptr()),
                                 _stream(V.device)))
     return y
+
+
+def eigh_blocks(a, dims, return_info: bool = False):
+    """Eigen-decomposition of the row-major symmetric blocks concatenated in
+    `a` (orders `dims`), e.g. the output of Plan.density (Alg. 1, step 6).
+    Returns (w, u): per block, eigenvalues in descending order and the
+    row-major eigenvector matrix (column j for w[j]), concatenated like `a`.
+    `a` is not modified (the library works on a copy)."""
+    import torch
+
+    dims = np.asarray(dims, dtype=np.int64)
+    if dims.size and (dims.min() < 1 or dims.max() > 2048):
+        raise ValueError("block orders must lie in 1..2048")
+    off = np.zeros(dims.size, dtype=np.int64)
+    woff = np.zeros(dims.size, dtype=np.int64)
+    if dims.size:
+        off[1:] = np.cumsum(dims * dims)[:-1]
+        woff[1:] = np.cumsum(dims)[:-1]
+    if a.numel() != int((dims * dims).sum()):
+        raise ValueError("a does not hold the blocks")
+    dev = a.device
+    work = a.clone()
+    w = torch.empty(int(dims.sum()), dtype=torch.float64, device=dev)
+    u = torch.empty_like(a)
+    t_off = torch.from_numpy(off).to(dev)
+    t_dim = torch.from_numpy(dims.astype(np.int32)).to(dev)
+    t_woff = torch.from_numpy(woff).to(dev)
+    info = torch.zeros(max(dims.size, 1), dtype=torch.int32, device=dev)
+    p = lambda t: ctypes.c_void_p(t.data_ptr())
+    N.check(N.lib().dmrg_eigh_blocks(int(dims.size), p(t_off), p(t_dim), p(t_woff), p(work), p(w), p(u), p(info),
+                                     _stream(dev)))
+    if return_info:
+        return w, u, info[: dims.size]
+    return w, u

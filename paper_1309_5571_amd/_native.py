@@ -91,6 +91,8 @@ SIGNATURES = {
     "dmrg_gemv_n": (c_int32, [c_int64, c_int32, c_void_p, c_int64, c_void_p, c_double, c_void_p, c_void_p]),
     "dmrg_density_layout": (c_int32, [c_void_p, POINTER(c_int64), POINTER(c_int64)]),
     "dmrg_density": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "dmrg_eigh_blocks": (c_int32, [c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                   c_void_p, c_void_p]),
     "dmrg_set_tile_table": (c_int32, [c_int32, POINTER(c_int32), POINTER(c_int32)]),
     "dmrg_plan_destroy": (None, [c_void_p]),
     "dmrg_last_error": (c_char_p, []),

@@ -1,0 +1,175 @@
+"""GPU parity of the blockwise eigen-decomposition (Alg. 1, step 6) against
+the oracle (LAPACK through NumPy), called through the C ABI.
+
+Tolerances follow the Jacobi method's backward error, a small multiple of
+d u |A|_F per block (u = 2^-53, d the block order): eigenvalues and the
+reconstruction U diag(w) U^T within 16 d u |A|_F, U^T U within 16 d u of
+the identity, and each eigenvector within 16 d u |A|_F / gap of the oracle's
+(up to sign) where its eigenvalue is separated by `gap` from the others.
+"""
+import numpy as np
+import pytest
+
+import gen
+from oracle import davidson, density
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+U64 = 2.0 ** -53
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _dm():
+    import paper_1309_5571_amd as dm
+
+    return dm
+
+
+def _run(blocks):
+    dims = [b.shape[0] for b in blocks]
+    flat = np.concatenate([b.reshape(-1) for b in blocks])
+    w, u, info = _dm().eigh_blocks(torch.from_numpy(flat).cuda(), dims, return_info=True)
+    w, u, info = w.cpu().numpy(), u.cpu().numpy(), info.cpu().numpy()
+    out, o, ow = [], 0, 0
+    for d in dims:
+        out.append((w[ow:ow + d], u[o:o + d * d].reshape(d, d)))
+        o += d * d
+        ow += d
+    return out, info
+
+
+def _check(blocks, res):
+    vals, vecs = density.eigh_blocks(blocks)
+    for B, (w, U), wr, Ur in zip(blocks, res, vals, vecs):
+        d = B.shape[0]
+        fro = max(float(np.linalg.norm(B)), 1e-300)
+        tol = 16 * d * U64 * fro
+        assert np.all(np.diff(w) <= 0)
+        assert np.max(np.abs(w - wr)) <= tol
+        assert np.max(np.abs(U @ np.diag(w) @ U.T - B)) <= tol
+        assert np.max(np.abs(U.T @ U - np.eye(d))) <= 16 * d * U64
+        for j in range(d):
+            k = int(np.argmax(np.abs(U[:, j])))
+            assert U[k, j] > 0
+            others = np.delete(wr, j)
+            gap = float(np.min(np.abs(others - wr[j]))) if d > 1 else np.inf
+            if gap > 1e-8 * fro:
+                sgn = 1.0 if U[:, j] @ Ur[:, j] >= 0 else -1.0
+                assert np.max(np.abs(sgn * U[:, j] - Ur[:, j])) <= tol / gap + 1e-14
+
+
+def _sym(rng, d):
+    G = rng.standard_normal((d, d))
+    return (G + G.T) / 2
+
+
+def _psd(rng, d, r):
+    X = rng.standard_normal((d, r))
+    return X @ X.T
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_eigh_random_blocks_small_and_large(seed):
+    rng = np.random.default_rng(seed)
+    dims = [1, 2, 3, 17, 47, 48, 49, 64, 100, 181]
+    blocks = []
+    for d in dims:
+        blocks.append(_sym(rng, d))
+        blocks.append(_psd(rng, d, max(1, d // 2)))  # rank-deficient, like rho_L when d_L > d_R
+    res, info = _run(blocks)
+    assert np.all(info >= 1)
+    _check(blocks, res)
+
+
+def test_eigh_degenerate_and_special_blocks():
+    rng = np.random.default_rng(5)
+    D = np.diag(rng.standard_normal(20))
+    blocks = [np.zeros((3, 3)), np.eye(7), 2.5 * np.eye(60), D, np.array([[0.0, 1.0], [1.0, 0.0]])]
+    res, info = _run(blocks)
+    assert np.all(info >= 1)
+    # already diagonal: no rotation, eigenvalues are the diagonal sorted, exactly
+    w, U = res[3]
+    assert np.array_equal(w, np.sort(np.diag(D))[::-1])
+    assert np.array_equal(np.abs(U), np.abs(U).round())
+    for (w, U), B in zip(res[:3], blocks[:3]):
+        assert np.array_equal(w, np.diag(B)) and np.array_equal(U, np.eye(B.shape[0]))
+    w, U = res[4]
+    np.testing.assert_allclose(w, [1.0, -1.0], atol=1e-15)
+    _check(blocks, res)
+
+
+@pytest.mark.parametrize("cfg", [2, 3])
+def test_eigh_of_density_blocks(cfg):
+    """Alg. 1, steps 5 and 6 on the device: density matrices of both blocks of
+    a full-size workload, then their eigen-decomposition."""
+    p = gen.config(cfg)
+    pl = _dm().Plan(p)
+    psi = gen.start_vector(pl.n, 13)
+    psi /= np.linalg.norm(psi)
+    rl, rr = pl.density(torch.from_numpy(psi).cuda())
+    lo, ro = pl.density_layout()
+    dl = np.sqrt(np.diff(lo)).round().astype(int)
+    dr = np.sqrt(np.diff(ro)).round().astype(int)
+    for rho, dims in ((rl, dl), (rr, dr)):
+        # the device's density blocks are the input of both sides (step 5 has its own parity tests)
+        host = rho.cpu().numpy()
+        ref, o = [], 0
+        for d in dims:
+            ref.append(host[o:o + d * d].reshape(d, d))
+            o += d * d
+        w, u, info = _dm().eigh_blocks(rho, dims, return_info=True)
+        assert np.all(info.cpu().numpy() >= 1)
+        w, u = w.cpu().numpy(), u.cpu().numpy()
+        res, o, ow = [], 0, 0
+        for d in dims:
+            res.append((w[ow:ow + d], u[o:o + d * d].reshape(d, d)))
+            o += d * d
+            ow += d
+        _check(ref, res)
+        # eigenvalues of a density matrix of a unit state: non-negative, sum 1
+        assert w.min() > -1e-12 and abs(w.sum() - 1.0) < 1e-12
+
+
+def test_xx_chain_step_5_and_6_on_gpu():
+    """Davidson ground state, density matrix and its spectrum, all on the
+    device, against the free-fermion-pinned oracle spectrum."""
+    p = gen.heisenberg_exact(4, 4, delta=0.0)
+    pl = _dm().Plan(p)
+    psi, _, infos, st = pl.davidson(torch.from_numpy(gen.start_vector(pl.n, 2)).cuda(), tol=1e-12)
+    assert st == 0
+    rl, _ = pl.density(psi)
+    lo, _ = pl.density_layout()
+    dims = np.sqrt(np.diff(lo)).round().astype(int)
+    w, _ = _dm().eigh_blocks(rl, dims)
+    _, psi_ref, _ = davidson.ground_state_dense(p)
+    vals, _ = density.eigh_blocks(density.density_sectors(p, psi_ref)[0])
+    np.testing.assert_allclose(w.cpu().numpy(), np.concatenate(vals), atol=1e-10)
+
+
+def test_eigh_rejects_unsupported_order_on_device():
+    """A block order beyond 2048 is reported in info and the block untouched."""
+    from paper_1309_5571_amd import _native as N
+
+    a = torch.arange(4, dtype=torch.float64).cuda()
+    w = torch.full((2,), 7.0, dtype=torch.float64).cuda()
+    u = torch.full((4,), 7.0, dtype=torch.float64).cuda()
+    off = torch.tensor([0], dtype=torch.int64).cuda()
+    dim = torch.tensor([4096], dtype=torch.int32).cuda()
+    woff = torch.tensor([0], dtype=torch.int64).cuda()
+    info = torch.zeros(1, dtype=torch.int32).cuda()
+    st = N.lib().dmrg_eigh_blocks(1, off.data_ptr(), dim.data_ptr(), woff.data_ptr(), a.data_ptr(), w.data_ptr(),
+                                  u.data_ptr(), info.data_ptr(), None)
+    torch.cuda.synchronize()
+    assert st == N.OK and int(info[0]) == -1
+    assert torch.all(u == 7.0) and torch.all(w == 7.0)
+    assert N.lib().dmrg_eigh_blocks(1, off.data_ptr(), dim.data_ptr(), woff.data_ptr(), a.data_ptr(), w.data_ptr(),
+                                    a.data_ptr(), None, None) == N.E_INVALID_ARG
+    with pytest.raises(ValueError):
+        _dm().eigh_blocks(a, [3000])
