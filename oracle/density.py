@@ -62,6 +62,21 @@ def eigh_blocks(blocks) -> Tuple[List[np.ndarray], List[np.ndarray]]:
     return vals, vecs
 
 
+def truncate(values, m: int) -> Tuple[np.ndarray, float]:
+    """Alg. 1, step 7: keep the m states of largest density-matrix eigenvalue
+    over all sector blocks of one block.  values: per block, the eigenvalues in
+    descending order.  Equal values are taken in block order, then in index
+    order.  Returns (kept count per block, discarded weight = sum of the
+    eigenvalues not kept)."""
+    flat = np.concatenate([np.asarray(v, dtype=np.float64) for v in values]) if values else np.zeros(0)
+    owner = np.concatenate([np.full(len(v), b) for b, v in enumerate(values)]) if values else np.zeros(0, int)
+    order = np.argsort(-flat, kind="stable")
+    kept = np.zeros(flat.size, dtype=bool)
+    kept[order[:max(0, min(m, flat.size))]] = True
+    counts = np.array([int(kept[owner == b].sum()) for b in range(len(values))], dtype=np.int64)
+    return counts, float(flat[~kept].sum())
+
+
 def density_flat(prob, psi) -> Tuple[np.ndarray, np.ndarray]:
     """The blocks of :func:`density_sectors` concatenated in pair order, each
     row-major: the layout of the library's output."""

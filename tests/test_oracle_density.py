@@ -171,3 +171,51 @@ def test_eigh_blocks_xx_chain_spectrum():
     for (sl, _, _, _), w in zip(_blocks_by_sector(p), vals):
         nup = (int(p.left.labels[sl, 0]) + 4) // 2
         np.testing.assert_allclose(w, want[nup][::-1], atol=1e-12)
+
+
+# --------------------------------------------------------------------------- step 7 (selection)
+
+
+def test_truncation_weight_is_the_projection_error():
+    """Keeping the left block's states of largest weight: the discarded weight
+    equals |psi - P psi|^2 with P the projector on the kept eigenvectors, and it
+    is the smallest such error over the same number of states (here checked
+    against keeping the states of smallest weight instead)."""
+    p = gen.random_problem(7, rank=1, dmax=14)
+    psi = gen.start_vector(sectors.pair_table(p.left, p.right, p.target)[1], 4)
+    psi /= np.linalg.norm(psi)
+    table, _ = sectors.pair_table(p.left, p.right, p.target)
+    left, _ = density.density_sectors(p, psi)
+    vals, vecs = density.eigh_blocks(left)
+    total = sum(len(v) for v in vals)
+    for m in (1, 3, total // 2, total - 1, total, total + 5):
+        counts, disc = density.truncate(vals, m)
+        assert counts.sum() == min(m, total)
+        err = alt = 0.0
+        for (off, dl, dr), U, k in zip(table.values(), vecs, counts):
+            X = psi[off:off + dl * dr].reshape(dl, dr)
+            P = U[:, :k] @ U[:, :k].T
+            err += float(np.sum((X - P @ X) ** 2))
+            Q = U[:, dl - k:] @ U[:, dl - k:].T  # the same counts, states of smallest weight
+            alt += float(np.sum((X - Q @ X) ** 2))
+        assert disc == pytest.approx(err, abs=1e-13)
+        assert alt >= err - 1e-13
+
+
+def test_truncation_of_xx_chain_matches_free_fermion_weights():
+    p = gen.heisenberg_exact(4, 4, delta=0.0)
+    _, psi, _ = davidson.ground_state_dense(p)
+    vals, _ = density.eigh_blocks(density.density_sectors(p, psi)[0])
+    spec = np.sort(np.concatenate(list(_xx_block_spectrum(8, 4).values())))[::-1]
+    for m in (2, 5, 9):
+        counts, disc = density.truncate(vals, m)
+        assert counts.sum() == m
+        assert disc == pytest.approx(float(spec[m:].sum()), abs=1e-12)
+
+
+def test_truncation_ties_follow_block_order():
+    vals = [np.array([0.4, 0.1]), np.array([0.4, 0.1]), np.array([0.0])]
+    assert density.truncate(vals, 1)[0].tolist() == [1, 0, 0]
+    assert density.truncate(vals, 3)[0].tolist() == [2, 1, 0]
+    c, d = density.truncate(vals, 0)
+    assert c.tolist() == [0, 0, 0] and d == pytest.approx(1.0)
