@@ -77,6 +77,16 @@ def truncate(values, m: int) -> Tuple[np.ndarray, float]:
     return counts, float(flat[~kept].sum())
 
 
+def renormalize_block(O, U_dst, U_src, k_dst: int, k_src: int) -> np.ndarray:
+    """Alg. 1, step 7: one operator block in the kept basis,
+    U_dst[:, :k_dst]^T O U_src[:, :k_src].  O is a dense [rows, cols] block,
+    or a 1-D diagonal (then rows = cols and O stands for diag(O))."""
+    O = np.asarray(O, dtype=np.float64)
+    if O.ndim == 1:
+        O = np.diag(O)
+    return U_dst[:, :k_dst].T @ O @ U_src[:, :k_src]
+
+
 def density_flat(prob, psi) -> Tuple[np.ndarray, np.ndarray]:
     """The blocks of :func:`density_sectors` concatenated in pair order, each
     row-major: the layout of the library's output."""

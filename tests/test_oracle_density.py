@@ -219,3 +219,66 @@ def test_truncation_ties_follow_block_order():
     assert density.truncate(vals, 3)[0].tolist() == [2, 1, 0]
     c, d = density.truncate(vals, 0)
     assert c.tolist() == [0, 0, 0] and d == pytest.approx(1.0)
+
+
+# --------------------------------------------------------------------------- step 7 (operators)
+
+
+def test_renormalized_identity_and_own_eigenbasis():
+    """The identity stays the identity on the kept states (U has orthonormal
+    columns); a symmetric block taken to its own eigenbasis is diagonal with
+    its eigenvalues."""
+    rng = np.random.default_rng(2)
+    G = rng.standard_normal((9, 9))
+    H = (G + G.T) / 2
+    vals, vecs = density.eigh_blocks([H])
+    U = vecs[0]
+    np.testing.assert_allclose(density.renormalize_block(np.ones(9), U, U, 4, 4), np.eye(4), atol=1e-14)
+    np.testing.assert_allclose(density.renormalize_block(H, U, U, 9, 6), np.diag(vals[0])[:, :6], atol=1e-13)
+
+
+def test_renormalized_superblock_is_the_projected_superblock():
+    """The basis change of one block: with V = blockdiag over sectors of the
+    kept eigenvectors of rho_L, every left operator renormalized block by block
+    gives the superblock Hamiltonian V^T H V (V acting on the left block only,
+    dense Kronecker products), and the truncated state V^T psi keeps the
+    weight 1 - discarded."""
+    p = gen.heisenberg_exact(3, 3)
+    _, psi, _ = davidson.ground_state_dense(p)
+    left, _ = density.density_sectors(p, psi)
+    vals, vecs = density.eigh_blocks(left)
+    counts, disc = density.truncate(vals, 4)
+    table, _ = sectors.pair_table(p.left, p.right, p.target)
+    kept = {sl: (vecs[i], int(counts[i])) for i, ((sl, _), _) in enumerate(table.items())}
+    off = p.left.offsets()
+    mL = p.left.m
+    # V: full left space -> kept states, sector by sector in sector order
+    cols = []
+    for s in range(p.left.nsec):
+        if s in kept:
+            U, k = kept[s]
+            for j in range(k):
+                c = np.zeros(mL)
+                c[off[s]:off[s + 1]] = U[:, j]
+                cols.append(c)
+    V = np.array(cols).T
+    for op in p.ops_left:
+        A = sectors.dense_operator(p.left, op)
+        want = V.T @ A @ V
+        got = np.zeros_like(want)
+        new_off = {}
+        pos = 0
+        for s in range(p.left.nsec):
+            if s in kept:
+                new_off[s] = pos
+                pos += kept[s][1]
+        for s in kept:
+            for t in kept:
+                blk = A[off[t]:off[t + 1], off[s]:off[s + 1]]
+                got[new_off[t]:new_off[t] + kept[t][1], new_off[s]:new_off[s] + kept[s][1]] = \
+                    density.renormalize_block(blk, kept[t][0], kept[s][0], kept[t][1], kept[s][1])
+        np.testing.assert_allclose(got, want, atol=1e-13)
+    full = np.zeros(mL * p.right.m)
+    full[sectors.layout(p.left, p.right, p.target).index_map] = psi
+    red = V.T @ full.reshape(mL, p.right.m)
+    assert float(np.sum(red ** 2)) == pytest.approx(1.0 - disc, abs=1e-13)
