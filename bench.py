@@ -110,6 +110,57 @@ def density_stats(plan, psi, reps, torch):
     return {"us": t * 1e6, "flop": flop, "bytes": nbytes, "tflops": flop / t * 1e-12, "GBs": nbytes / t * 1e-9}
 
 
+def renorm_stats(plan, psi, torch, reps=10):
+    """The rest of the renormalization step on the device (Alg. 1, steps 6-7)
+    for the left block: eigen-decomposition of every density-matrix block
+    (dmrg_eigh_blocks) and the state selection (dmrg_truncate).  Per-call
+    durations from HIP event pairs on the launch stream (the work copy of rho
+    that each eigen-decomposition overwrites is refreshed outside the pair)."""
+    import ctypes
+
+    import numpy as np
+
+    from paper_1309_5571_amd import _native as N
+
+    lo, _ = plan.density_layout()
+    rl, _ = plan.density(psi, right=False)
+    dims = np.sqrt(np.diff(lo)).round().astype(np.int64)
+    dev = psi.device
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    off, woff = t(lo[:-1].astype(np.int64)), t(np.concatenate([[0], np.cumsum(dims)[:-1]]).astype(np.int64))
+    tdim = t(dims.astype(np.int32))
+    work, u = torch.empty_like(rl), torch.empty_like(rl)
+    w = torch.empty(int(dims.sum()), dtype=torch.float64, device=dev)
+    # one group per member, each keeping a quarter of its states
+    groups = np.bincount(plan.layout()["member"], minlength=len(plan.problems))
+    gb = np.concatenate([[0], np.cumsum(groups)]).astype(np.int32)
+    ms = np.array([max(1, int(dims[gb[g]:gb[g + 1]].sum()) // 4) for g in range(groups.size)], dtype=np.int32)
+    gblk, tm = t(gb), t(ms)
+    keep = torch.empty(dims.size, dtype=torch.int32, device=dev)
+    disc = torch.empty(groups.size, dtype=torch.float64, device=dev)
+    P = lambda x: ctypes.c_void_p(x.data_ptr())
+    lib, s = N.lib(), torch.cuda.current_stream()
+    te, tt = [], []
+    for i in range(reps + 1):
+        work.copy_(rl)
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record(s)
+        N.check(lib.dmrg_eigh_blocks(int(dims.size), P(off), P(tdim), P(woff), P(work), P(w), P(u), None,
+                                     ctypes.c_void_p(s.cuda_stream)))
+        e[1].record(s)
+        N.check(lib.dmrg_truncate(int(groups.size), P(gblk), P(tdim), P(woff), P(w), P(tm), P(keep), P(disc),
+                                  ctypes.c_void_p(s.cuda_stream)))
+        e[2].record(s)
+        e[2].synchronize()
+        if i:  # the first call is a warm-up
+            te.append(e[0].elapsed_time(e[1]) * 1e3)
+            tt.append(e[1].elapsed_time(e[2]) * 1e3)
+    return {"blocks": int(dims.size), "max_block": int(dims.max()), "states": int(dims.sum()),
+            "groups": int(groups.size), "m_keep": int(ms.sum()),
+            "eigh_us": float(np.median(te)), "truncate_us": float(np.median(tt)),
+            "discarded": float(disc.sum().cpu())}
+
+
 def cpu_baseline(p, x0):
     """The FP64 oracle (NumPy + OpenBLAS) on the host: one full Davidson solve
     of the same workload from the same start vector, plus projection timing."""
@@ -316,6 +367,8 @@ def main():
         log(f"projection per call: {stats}")
         extra["density"] = density_stats(plan, psi, args.proj_reps, torch)
         log(f"density matrices: {extra['density']}")
+        extra["renormalization"] = renorm_stats(plan, psi, torch)
+        log(f"eigen-decomposition and selection: {extra['renormalization']}")
         extra["mixed_vs_fp64_time_ratio"] = (dt / args.steps * 1e3) / extra["fp64_solve"]["ms_per_solve"]
 
     # roofline of the dominant kernel: the FP64 projection, bound by HBM bytes at

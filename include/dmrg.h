@@ -270,6 +270,50 @@ dmrg_status dmrg_density(dmrg_plan *plan, const double *psi, double *rho_left, d
 dmrg_status dmrg_eigh_blocks(int32_t nblk, const int64_t *off, const int32_t *dim, const int64_t *woff,
                              double *a, double *w, double *u, int32_t *info, void *stream);
 
+/* State selection of the renormalization step (Alg. 1, step 7: a block keeps
+ * its states of largest density-matrix eigenvalue).  The sector blocks are
+ * grouped (e.g. the left block of one superblock, or of one batch member):
+ * group g is blocks gblk[g] .. gblk[g + 1] - 1, whose eigenvalues, each
+ * block's in descending order as dmrg_eigh_blocks writes them, lie contiguous
+ * in w from w + woff[gblk[g]].  The m_keep[g] largest values of each group
+ * are kept; equal values are taken in block order, then in index order.
+ *  gblk device [ngroup + 1]; dim, woff device [nblk]; m_keep device [ngroup].
+ *  keep: device out [nblk], the number of states kept per block (a prefix of
+ *    its eigenvectors); -1 for the blocks of a group of more than 16384 values.
+ *  discarded: device out [ngroup] or NULL: the sum of the values not kept
+ *    (NaN for an oversized group).
+ *  The sizes are read on the device: the caller guarantees that they describe
+ *  w.  Asynchronous on stream. */
+dmrg_status dmrg_truncate(int32_t ngroup, const int32_t *gblk, const int32_t *dim, const int64_t *woff,
+                          const double *w, const int32_t *m_keep, int32_t *keep, double *discarded,
+                          void *stream);
+
+/* One operator block to take to the kept basis (see dmrg_renormalize). */
+typedef struct {
+    int64_t o;            /* element offset in data: the dense block [rows][cols] (row-major),
+                             or its diagonal [rows] when diag = 1 */
+    int64_t u_dst, u_src; /* element offsets in u of U_dst [rows][rows] and U_src [cols][cols]
+                             (row-major, eigenvectors in columns, as dmrg_eigh_blocks writes them) */
+    int64_t out;          /* element offset in out of the result [k_dst][k_src] (row-major) */
+    int32_t rows, cols;   /* dimensions of the destination and source sectors, >= 1 */
+    int32_t k_dst, k_src; /* states kept: 0 <= k_dst <= rows, 0 <= k_src <= cols */
+    int32_t diag;         /* 1: the block is diagonal (rows == cols) */
+} dmrg_renorm_block;
+
+/* Operator blocks in the kept basis (Alg. 1, step 7: the block's basis is
+ * renormalized to its kept states): for every block b,
+ *   out[b] = U_dst[:, :k_dst]^T O U_src[:, :k_src],
+ * the first k columns of each sector's eigenvector block being the kept
+ * states (dmrg_truncate's counts).  FP64, two batched GEMM stages on MFMA.
+ *  blocks: host [nblk], validated on the host (sizes, kinds, offsets >= 0);
+ *    the caller guarantees that the offsets and sizes lie inside data, u and
+ *    out.  data, u: device FP64 inputs; out: device FP64, owned by the
+ *    caller, not overlapping data or u.
+ *  Allocates a device intermediate (sum of rows * k_src doubles) and the
+ *  tile list for the call and synchronizes stream before returning. */
+dmrg_status dmrg_renormalize(int32_t nblk, const dmrg_renorm_block *blocks, const double *data,
+                             const double *u, double *out, void *stream);
+
 /* Set the tile table used by later dmrg_plan_create calls: for output
  * blocks with max(rows, cols) <= bound[c] (ascending, ncls <= 8), tiles of
  * tile[c] rows and columns (16 or 32).  ncls = 0 restores the built-in table.

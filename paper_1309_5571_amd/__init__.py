@@ -420,3 +420,54 @@ def eigh_blocks(a, dims, return_info: bool = False):
     if return_info:
         return w, u, info[: dims.size]
     return w, u
+
+
+def truncate(w, dims, m_keep, groups=None):
+    """Alg. 1, step 7 (state selection): keep the m_keep[g] largest of the
+    eigenvalues `w` (concatenated per block, each block descending, as
+    eigh_blocks returns them) in each group of consecutive blocks
+    (`groups`: block counts per group; default one group).  Returns
+    (kept count per block [host int array], discarded weight per group [host])."""
+    import torch
+
+    dims = np.asarray(dims, dtype=np.int64)
+    groups = np.array([dims.size] if groups is None else groups, dtype=np.int64)
+    if groups.sum() != dims.size or np.any(groups < 0):
+        raise ValueError("groups must partition the blocks")
+    m_keep = np.broadcast_to(np.asarray(m_keep, dtype=np.int32), groups.shape).copy()
+    gblk = np.zeros(groups.size + 1, dtype=np.int32)
+    np.cumsum(groups, out=gblk[1:])
+    for g in range(groups.size):
+        if int(dims[gblk[g]:gblk[g + 1]].sum()) > 16384:
+            raise ValueError("a group holds more than 16384 values")
+    woff = np.zeros(dims.size, dtype=np.int64)
+    if dims.size:
+        woff[1:] = np.cumsum(dims)[:-1]
+    if w.numel() != int(dims.sum()):
+        raise ValueError("w does not hold the blocks' values")
+    dev = w.device
+    t = lambda a: torch.from_numpy(a).to(dev)
+    t_gblk, t_dim, t_woff, t_m = t(gblk), t(dims.astype(np.int32)), t(woff), t(m_keep)
+    keep = torch.empty(max(dims.size, 1), dtype=torch.int32, device=dev)
+    disc = torch.empty(max(groups.size, 1), dtype=torch.float64, device=dev)
+    p = lambda x: ctypes.c_void_p(x.data_ptr())
+    N.check(N.lib().dmrg_truncate(int(groups.size), p(t_gblk), p(t_dim), p(t_woff), p(w), p(t_m), p(keep), p(disc),
+                                  _stream(dev)))
+    return keep.cpu().numpy()[: dims.size], disc.cpu().numpy()[: groups.size]
+
+
+def renormalize(data, u, blocks, out_len: int):
+    """Alg. 1, step 7 (operators): every requested block O of `data` taken to
+    the kept basis, U_dst[:, :k_dst]^T O U_src[:, :k_src], with `u` the
+    eigenvector blocks from eigh_blocks.  blocks: sequence of
+    (o, u_dst, u_src, out, rows, cols, k_dst, k_src, diag) element offsets and
+    sizes (see dmrg_renorm_block).  Returns the output tensor of out_len."""
+    import torch
+
+    arr = (N.RenormBlock * max(len(blocks), 1))()
+    for i, b in enumerate(blocks):
+        arr[i] = N.RenormBlock(*[int(x) for x in b])
+    out = torch.zeros(max(int(out_len), 1), dtype=torch.float64, device=data.device)
+    p = lambda x: ctypes.c_void_p(x.data_ptr())
+    N.check(N.lib().dmrg_renormalize(len(blocks), arr, p(data), p(u), p(out), _stream(data.device)))
+    return out

@@ -64,6 +64,11 @@ class DavidsonInfo(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class RenormBlock(ctypes.Structure):
+    _fields_ = [("o", c_int64), ("u_dst", c_int64), ("u_src", c_int64), ("out", c_int64),
+                ("rows", c_int32), ("cols", c_int32), ("k_dst", c_int32), ("k_src", c_int32), ("diag", c_int32)]
+
+
 class DmrgError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__(f"dmrg status {status}: {message}")
@@ -93,6 +98,9 @@ SIGNATURES = {
     "dmrg_density": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "dmrg_eigh_blocks": (c_int32, [c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                    c_void_p, c_void_p]),
+    "dmrg_truncate": (c_int32, [c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                c_void_p, c_void_p]),
+    "dmrg_renormalize": (c_int32, [c_int32, POINTER(RenormBlock), c_void_p, c_void_p, c_void_p, c_void_p]),
     "dmrg_set_tile_table": (c_int32, [c_int32, POINTER(c_int32), POINTER(c_int32)]),
     "dmrg_plan_destroy": (None, [c_void_p]),
     "dmrg_last_error": (c_char_p, []),

@@ -1,0 +1,172 @@
+// Operator blocks in the kept basis (Alg. 1, step 7: the block's basis is
+// renormalized to the states of largest density-matrix eigenvalue).
+//
+// Every block O (sector src -> dst) of an operator becomes
+// U_dst[:, :k_dst]^T O U_src[:, :k_src], with U the eigenvector blocks of the
+// density matrix.  Two batched GEMM stages: T = O U_src (or diag(o) U_src),
+// then U_dst^T T; each stage runs one workgroup per 32x32 output tile, four
+// waves of FP64 MFMA 16x16x4.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "internal.h"
+
+namespace dmrg {
+
+typedef double v4d_rn __attribute__((ext_vector_type(4)));
+
+// One 32x32 tile of C = op(A) B:  op(A)(i, k) = A[i lda + k], or A[k lda + i]
+// (trans), or (i == k) A[i] (diag, then K == M);  B(k, j) = B[k ldb + j].
+struct GemmTile {
+    const double *A, *B;
+    double *C;
+    int32_t lda, ldb, ldc;
+    int32_t M, N, K;
+    int32_t mode;  // 0 plain, 1 transposed A, 2 diagonal A
+    int32_t ti, tj;
+};
+
+constexpr int RN_TILE = 32;
+
+__global__ __launch_bounds__(256) void k_gemm_tiles(const GemmTile *__restrict__ tiles) {
+    const GemmTile t = tiles[blockIdx.x];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int r16 = lane & 15, g = lane >> 4;
+    const int r0 = t.ti * RN_TILE + 16 * (wave >> 1), c0 = t.tj * RN_TILE + 16 * (wave & 1);
+    if (r0 >= t.M || c0 >= t.N) return;
+    if (t.mode == 2) {  // C = diag(A) B: elementwise over the wave's quarter
+        for (int e = lane; e < 256; e += 64) {
+            const int r = r0 + (e >> 4), c = c0 + (e & 15);
+            if (r < t.M && c < t.N) t.C[(int64_t)r * t.ldc + c] = t.A[r] * t.B[(int64_t)r * t.ldb + c];
+        }
+        return;
+    }
+    const int ra = min(r0 + r16, t.M - 1), cb = min(c0 + r16, t.N - 1);
+    const bool oka = r0 + r16 < t.M, okb = c0 + r16 < t.N;
+    v4d_rn acc = {0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < t.K; k0 += 16) {
+        double a[4], b[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {  // clamped loads, all issued before any use
+            const int k = min(k0 + 4 * j + g, t.K - 1);
+            a[j] = t.mode == 1 ? t.A[(int64_t)k * t.lda + ra] : t.A[(int64_t)ra * t.lda + k];
+            b[j] = t.B[(int64_t)k * t.ldb + cb];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const bool kin = k0 + 4 * j + g < t.K;
+            a[j] = (oka && kin) ? a[j] : 0.0;
+            b[j] = (okb && kin) ? b[j] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (k0 + 4 * j < t.K) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j], b[j], acc, 0, 0, 0);
+    }
+    // accumulator value v of lane (g, c) holds D[4 v + g][c]
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int r = r0 + 4 * v + g, c = c0 + r16;
+        if (r < t.M && c < t.N) t.C[(int64_t)r * t.ldc + c] = acc[v];
+    }
+}
+
+static void add_tiles(std::vector<GemmTile> &out, const GemmTile &base) {
+    if (base.M <= 0 || base.N <= 0) return;
+    for (int ti = 0; ti * RN_TILE < base.M; ++ti)
+        for (int tj = 0; tj * RN_TILE < base.N; ++tj) {
+            GemmTile t = base;
+            t.ti = ti;
+            t.tj = tj;
+            out.push_back(t);
+        }
+}
+
+}  // namespace dmrg
+
+// ================================================================== ABI
+
+using namespace dmrg;
+
+extern "C" {
+
+dmrg_status dmrg_renormalize(int32_t nblk, const dmrg_renorm_block *blocks, const double *data, const double *u,
+                             double *out, void *stream) {
+    clear_error();
+    if (nblk < 0) return set_error(DMRG_E_INVALID_ARG, "negative block count");
+    if (nblk == 0) return DMRG_OK;
+    if (!blocks || !data || !u || !out) return set_error(DMRG_E_INVALID_ARG, "null argument");
+    if ((const double *)out == data || (const double *)out == u)
+        return set_error(DMRG_E_INVALID_ARG, "out must not overlap data or u");
+    int64_t tmp_len = 0;
+    for (int32_t b = 0; b < nblk; ++b) {
+        const dmrg_renorm_block &B = blocks[b];
+        if (B.rows < 1 || B.cols < 1 || B.k_dst < 0 || B.k_dst > B.rows || B.k_src < 0 || B.k_src > B.cols ||
+            B.o < 0 || B.u_dst < 0 || B.u_src < 0 || B.out < 0 || (B.diag != 0 && B.diag != 1) ||
+            (B.diag && B.rows != B.cols))
+            return set_error(DMRG_E_INVALID_ARG, "block %d: bad sizes, offsets or kind", b);
+        tmp_len += (int64_t)B.rows * B.k_src;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    double *tmp = nullptr;
+    DMRG_HIP(hipMalloc(&tmp, std::max<int64_t>(tmp_len, 1) * sizeof(double)));
+    std::vector<GemmTile> st1, st2;
+    int64_t toff = 0;
+    for (int32_t b = 0; b < nblk; ++b) {
+        const dmrg_renorm_block &B = blocks[b];
+        double *T = tmp + toff;
+        toff += (int64_t)B.rows * B.k_src;
+        GemmTile a{};  // T [rows][k_src] = O U_src[:, :k_src]
+        a.A = data + B.o;
+        a.B = u + B.u_src;
+        a.C = T;
+        a.lda = B.cols;
+        a.ldb = B.cols;
+        a.ldc = B.k_src;
+        a.M = B.rows;
+        a.N = B.k_src;
+        a.K = B.cols;
+        a.mode = B.diag ? 2 : 0;
+        add_tiles(st1, a);
+        GemmTile c{};  // out [k_dst][k_src] = U_dst[:, :k_dst]^T T
+        c.A = u + B.u_dst;
+        c.B = T;
+        c.C = out + B.out;
+        c.lda = B.rows;
+        c.ldb = B.k_src;
+        c.ldc = B.k_src;
+        c.M = B.k_dst;
+        c.N = B.k_src;
+        c.K = B.rows;
+        c.mode = 1;
+        add_tiles(st2, c);
+    }
+    GemmTile *d_tiles = nullptr;
+    const size_t n1 = st1.size(), n2 = st2.size();
+    hipError_t e = hipMalloc(&d_tiles, std::max<size_t>(n1 + n2, 1) * sizeof(GemmTile));
+    if (e != hipSuccess) {
+        (void)hipFree(tmp);
+        return set_error(DMRG_E_NOMEM, "hipMalloc failed: %s", hipGetErrorString(e));
+    }
+    std::vector<GemmTile> all(st1);
+    all.insert(all.end(), st2.begin(), st2.end());
+    if (!all.empty()) e = hipMemcpyAsync(d_tiles, all.data(), all.size() * sizeof(GemmTile), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && n1) {
+        hipLaunchKernelGGL(k_gemm_tiles, dim3((unsigned)n1), dim3(256), 0, s, d_tiles);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess && n2) {
+        hipLaunchKernelGGL(k_gemm_tiles, dim3((unsigned)n2), dim3(256), 0, s, d_tiles + n1);
+        e = hipGetLastError();
+    }
+    // the tile list and the intermediate are freed once the stream has used them
+    const hipError_t e2 = hipStreamSynchronize(s);
+    (void)hipFree(d_tiles);
+    (void)hipFree(tmp);
+    if (e != hipSuccess) return set_error(DMRG_E_HIP, "renormalize: %s", hipGetErrorString(e));
+    if (e2 != hipSuccess) return set_error(DMRG_E_HIP, "renormalize: %s", hipGetErrorString(e2));
+    return DMRG_OK;
+}
+
+}  // extern "C"

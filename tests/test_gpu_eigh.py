@@ -173,3 +173,121 @@ def test_eigh_rejects_unsupported_order_on_device():
                                     a.data_ptr(), None, None) == N.E_INVALID_ARG
     with pytest.raises(ValueError):
         _dm().eigh_blocks(a, [3000])
+
+
+# ------------------------------------------------------------------ step 7: state selection
+
+
+def _desc_blocks(rng, dims, ties=True):
+    vals = []
+    for d in dims:
+        v = rng.choice([0.5, 0.25, 0.125, 0.0], size=d) if ties else rng.random(d)
+        vals.append(np.sort(v)[::-1].copy())
+    return vals
+
+
+@pytest.mark.parametrize("ties", [True, False])
+def test_truncate_matches_oracle_exactly(ties):
+    rng = np.random.default_rng(11 if ties else 12)
+    dims = [3, 1, 7, 40, 2, 33]
+    vals = _desc_blocks(rng, dims, ties)
+    w = torch.from_numpy(np.concatenate(vals)).cuda()
+    total = sum(dims)
+    for m in (0, 1, 5, total // 2, total - 1, total, total + 9):
+        keep, disc = _dm().truncate(w, dims, m)
+        counts, ref = density.truncate(vals, m)
+        assert keep.tolist() == counts.tolist()
+        assert abs(disc[0] - ref) <= 1e-14 * total
+
+
+def test_truncate_groups_are_independent():
+    rng = np.random.default_rng(3)
+    dims = [4, 9, 2, 6, 6, 1, 30]
+    groups = [3, 0, 2, 2]
+    ms = [5, 2, 3, 10]
+    vals = _desc_blocks(rng, dims)
+    keep, disc = _dm().truncate(torch.from_numpy(np.concatenate(vals)).cuda(), dims, ms, groups=groups)
+    b = 0
+    for g, (cnt, m) in enumerate(zip(groups, ms)):
+        counts, ref = density.truncate(vals[b:b + cnt], m)
+        assert keep[b:b + cnt].tolist() == counts.tolist()
+        assert abs(disc[g] - ref) <= 1e-13
+        b += cnt
+
+
+@pytest.mark.parametrize("cfg,m", [(3, 256), (2, 128)])
+def test_steps_5_to_7_on_full_size_workloads(cfg, m):
+    """Density matrices, their eigenvalues and the kept states, all on the
+    device; the selection matches the oracle's on the device's eigenvalues and
+    the kept weight is within rounding of the oracle's full FP64 chain."""
+    p = gen.config(cfg)
+    pl = _dm().Plan(p)
+    psi = gen.start_vector(pl.n, 21)
+    psi /= np.linalg.norm(psi)
+    rl, _ = pl.density(torch.from_numpy(psi).cuda())
+    lo, _ = pl.density_layout()
+    dims = np.sqrt(np.diff(lo)).round().astype(int)
+    w, _ = _dm().eigh_blocks(rl, dims)
+    keep, disc = _dm().truncate(w, dims, m)
+    wh, o, vals = w.cpu().numpy(), 0, []
+    for d in dims:
+        vals.append(wh[o:o + d])
+        o += d
+    counts, ref = density.truncate(vals, m)
+    assert keep.tolist() == counts.tolist() and keep.sum() == min(m, dims.sum())
+    assert abs(disc[0] - ref) <= 1e-13
+    ovals, _ = density.eigh_blocks(density.density_sectors(p, psi)[0])
+    _, ref64 = density.truncate(ovals, m)
+    assert abs(disc[0] - ref64) <= 1e-12
+
+
+def test_truncate_batched_members():
+    probs = gen.config(4)
+    pl = _dm().Plan(probs)
+    psi = gen.start_vector(pl.n, 5)
+    rl, _ = pl.density(torch.from_numpy(psi).cuda())
+    lo, _ = pl.density_layout()
+    dims = np.sqrt(np.diff(lo)).round().astype(int)
+    lay = pl.layout()
+    groups = np.bincount(lay["member"], minlength=len(probs))
+    w, _ = _dm().eigh_blocks(rl, dims)
+    keep, disc = _dm().truncate(w, dims, 100, groups=groups)
+    wh, o, vals = w.cpu().numpy(), 0, []
+    for d in dims:
+        vals.append(wh[o:o + d])
+        o += d
+    b = 0
+    for g, cnt in enumerate(groups):
+        counts, ref = density.truncate(vals[b:b + cnt], 100)
+        assert keep[b:b + cnt].tolist() == counts.tolist()
+        assert abs(disc[g] - ref) <= 1e-12 * max(1.0, abs(ref))
+        b += cnt
+
+
+def test_truncate_reports_oversized_group():
+    from paper_1309_5571_amd import _native as N
+
+    w = torch.zeros(4, dtype=torch.float64).cuda()
+    gblk = torch.tensor([0, 1], dtype=torch.int32).cuda()
+    dim = torch.tensor([20000], dtype=torch.int32).cuda()
+    woff = torch.tensor([0], dtype=torch.int64).cuda()
+    m = torch.tensor([5], dtype=torch.int32).cuda()
+    keep = torch.zeros(1, dtype=torch.int32).cuda()
+    disc = torch.zeros(1, dtype=torch.float64).cuda()
+    st = N.lib().dmrg_truncate(1, gblk.data_ptr(), dim.data_ptr(), woff.data_ptr(), w.data_ptr(), m.data_ptr(),
+                               keep.data_ptr(), disc.data_ptr(), None)
+    torch.cuda.synchronize()
+    assert st == N.OK and int(keep[0]) == -1 and torch.isnan(disc[0])
+    with pytest.raises(ValueError):
+        _dm().truncate(w, [20000], 5)
+
+
+def test_truncate_signed_zero_ties_like_equal_values():
+    """-0 and +0 are equal values: their order is the storage order."""
+    vals = [np.array([0.5, 0.0, -0.0]), np.array([0.0, -0.0]), np.array([-0.0, -1.0])]
+    dims = [3, 2, 2]
+    w = torch.from_numpy(np.concatenate(vals)).cuda()
+    for m in range(0, 8):
+        keep, disc = _dm().truncate(w, dims, m)
+        counts, ref = density.truncate(vals, m)
+        assert keep.tolist() == counts.tolist() and disc[0] == ref
