@@ -1299,6 +1299,17 @@ static dmrg_status work_alloc(dmrg_plan *plan, int kmax, int kmin, hipStream_t s
     DMRG_HIP(hipMemsetAsync(A.st, 0, plan->nprob * sizeof(DavState), s));
     DMRG_HIP(hipMemsetAsync(A.active, 0, plan->nprob * 4, s));
     DMRG_HIP(hipMemsetAsync(B.active, 0, plan->nprob * 4, s));
+    // subspace, work vectors and partial rows start at zero (once per plan,
+    // outside any captured graph): a subspace that fills the whole space
+    // (n <= kmax) reaches columns and rows no iteration has written yet
+    DMRG_HIP(hipMemsetAsync(A.V, 0, (kmax + 1) * n * 8, s));
+    DMRG_HIP(hipMemsetAsync(A.W, 0, (kmax + 1) * n * 8, s));
+    DMRG_HIP(hipMemsetAsync(A.T, 0, n * 8, s));
+    DMRG_HIP(hipMemsetAsync((void *)A.X0, 0, n * 8, s));
+    DMRG_HIP(hipMemsetAsync(A.pa, 0, (size_t)A.nchunk * rowb, s));
+    DMRG_HIP(hipMemsetAsync(A.pb, 0, (size_t)A.nchunk * rowb, s));
+    DMRG_HIP(hipMemsetAsync(A.pc, 0, (size_t)A.nchunk * rowb, s));
+    DMRG_HIP(hipMemsetAsync(A.ptile, 0, (size_t)tiles * rowb, s));
     DMRG_HIP(hipStreamSynchronize(s));
     return DMRG_OK;
 }

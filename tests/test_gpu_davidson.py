@@ -222,3 +222,26 @@ def test_energy_gradient_hellmann_feynman_j1j2():
     dc = projection.coef_gradient(p, ref.x, ref.x)
     gref = p.meta["coef_basis"].T @ dc
     assert np.all(np.abs(g[1:] - gref[1:]) <= 1e-7 * np.abs(gref[1:]))
+
+
+def test_subspace_filling_the_space_is_reproducible_across_plans():
+    """A superblock of dimension n <= kmax: the subspace fills the whole space.
+    Plans created one after another (device memory reused) must reach the same
+    converged result from the same start vector (the workspace starts at zero;
+    stale memory once made the second plan break down)."""
+    import paper_1309_5571_amd as dm
+
+    p = gen.heisenberg_exact(2, 2)  # n = 6
+    x0 = gen.start_vector(6, 3)
+    out = []
+    for _ in range(3):
+        pl = dm.Plan(p)
+        big = torch.full((1 << 20,), 1e300, dtype=torch.float64, device="cuda")  # dirty memory between plans
+        del big
+        psi, E, infos, st = pl.davidson(torch.from_numpy(x0).cuda(), tol=1e-11, kmax=6, kmin=5)
+        assert st == 0 and infos[0]["converged"]
+        out.append(float(E[0]))
+        pl.close()
+        del pl
+    assert out[0] == pytest.approx(-1.6160254037844386, abs=1e-12)
+    assert out[0] == out[1] == out[2]
