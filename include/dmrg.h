@@ -314,6 +314,28 @@ typedef struct {
 dmrg_status dmrg_renormalize(int32_t nblk, const dmrg_renorm_block *blocks, const double *data,
                              const double *u, double *out, void *stream);
 
+/* One block placement (see dmrg_place_blocks). */
+typedef struct {
+    int64_t src;      /* element offset in src of a row-major [rows][ld_src] block (ignored if identity) */
+    int64_t dst;      /* element offset in dst of the target [rows][ld_dst] region */
+    int32_t rows, cols, ld_src, ld_dst;
+    double coef;
+    int32_t identity; /* 1: place coef times the identity (i == j) instead of src */
+} dmrg_place;
+
+/* Block placement, the assembly step of enlarging a block by one site
+ * (Alg. 1, step 2: the enlarged block's operators are Kronecker products of
+ * block and site operators, so every sector block of them is made of scaled
+ * copies of the block operator's blocks, or of identities):
+ *   dst[dst + i ld_dst + j] += coef * src[src + i ld_src + j]   (i < rows, j < cols)
+ * for every item.  items: host [n], validated on the host; the items of one
+ * call must not overlap in dst (they run in parallel; overlapping sums go in
+ * separate calls, which run in call order).  src, dst: device FP64, owned by
+ * the caller; the caller guarantees the offsets lie inside them.  Allocates
+ * the item list for the call and synchronizes stream before returning. */
+dmrg_status dmrg_place_blocks(int32_t n, const dmrg_place *items, const double *src, double *dst,
+                              void *stream);
+
 /* Set the tile table used by later dmrg_plan_create calls: for output
  * blocks with max(rows, cols) <= bound[c] (ascending, ncls <= 8), tiles of
  * tile[c] rows and columns (16 or 32).  ncls = 0 restores the built-in table.

@@ -118,6 +118,20 @@ def hubbard_dimer_energy(t: float, U: float) -> float:
     return 0.5 * (U - np.sqrt(U * U + 16 * t * t))
 
 
+def chain_ground_energy(n: int, delta: float = 1.0) -> float:
+    """Lowest energy of the open Heisenberg chain of Eq. 1 in the S^z = 0 sector,
+    by LAPACK on the dense sector block (n <= 14)."""
+    H = heisenberg_chain(n, delta)
+    idx = np.flatnonzero(spin_labels(n) == 0)
+    return float(np.linalg.eigvalsh(H[np.ix_(idx, idx)])[0])
+
+
+def hulthen_energy_per_site() -> float:
+    """Ground-state energy per site of the infinite spin-1/2 Heisenberg chain
+    (J = 1, Delta = 1), Hulthen's Bethe-ansatz result 1/4 - ln 2."""
+    return 0.25 - float(np.log(2.0))
+
+
 def majumdar_ghosh_energy(n: int, J1: float = 1.0) -> float:
     """J2 = J1/2 open chain with halved end bonds: sum of triangle projectors,
     ground energy -3 J1 (n - 2) / 8 (dimer states)."""

@@ -82,6 +82,11 @@ class _Marshal:
         kind = N.OP_KIND[op.kind]
         if kind == N.OP_IDENTITY:
             return N.Op(kind, 0, None, None, None, None)
+        if getattr(op, "device_data", None) is not None:  # dense blocks already on the device
+            src, dst, off = _i32(op.src), _i32(op.dst), _i64(op.off)
+            self.keep += [src, dst, off, op.device_data]
+            return N.Op(kind, len(src), _ptr(src, ctypes.c_int32), _ptr(dst, ctypes.c_int32),
+                        _ptr(off, ctypes.c_int64), op.device_data.data_ptr())
         if kind == N.OP_DIAG:
             return N.Op(kind, 0, None, None, None, self._data(op.diag, device))
         blocks = [np.ascontiguousarray(b, dtype=np.float64) for b in op.blocks]

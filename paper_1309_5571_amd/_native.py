@@ -69,6 +69,11 @@ class RenormBlock(ctypes.Structure):
                 ("rows", c_int32), ("cols", c_int32), ("k_dst", c_int32), ("k_src", c_int32), ("diag", c_int32)]
 
 
+class Place(ctypes.Structure):
+    _fields_ = [("src", c_int64), ("dst", c_int64), ("rows", c_int32), ("cols", c_int32), ("ld_src", c_int32),
+                ("ld_dst", c_int32), ("coef", c_double), ("identity", c_int32)]
+
+
 class DmrgError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__(f"dmrg status {status}: {message}")
@@ -101,6 +106,7 @@ SIGNATURES = {
     "dmrg_truncate": (c_int32, [c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                 c_void_p, c_void_p]),
     "dmrg_renormalize": (c_int32, [c_int32, POINTER(RenormBlock), c_void_p, c_void_p, c_void_p, c_void_p]),
+    "dmrg_place_blocks": (c_int32, [c_int32, POINTER(Place), c_void_p, c_void_p, c_void_p]),
     "dmrg_set_tile_table": (c_int32, [c_int32, POINTER(c_int32), POINTER(c_int32)]),
     "dmrg_plan_destroy": (None, [c_void_p]),
     "dmrg_last_error": (c_char_p, []),

@@ -72,6 +72,28 @@ __global__ __launch_bounds__(256) void k_gemm_tiles(const GemmTile *__restrict__
     }
 }
 
+// Block placement for the enlargement of a block by one site (Alg. 1, step
+// 2: the enlarged block's operators are Kronecker products of block and site
+// operators, so each of their sector blocks is assembled from scaled copies of
+// the block operator's blocks, or of identities): one workgroup per item,
+// dst[i][j] += coef * src[i][j] (or coef * (i == j)).
+struct PlaceItem {
+    const double *src;
+    double *dst;
+    int32_t rows, cols, ld_src, ld_dst;
+    double coef;
+    int32_t identity;
+};
+
+__global__ __launch_bounds__(256) void k_place(const PlaceItem *__restrict__ items) {
+    const PlaceItem it = items[blockIdx.x];
+    for (int e = threadIdx.x; e < it.rows * it.cols; e += 256) {
+        const int i = e / it.cols, j = e - i * it.cols;
+        const double v = it.identity ? (i == j ? 1.0 : 0.0) : it.src[(int64_t)i * it.ld_src + j];
+        it.dst[(int64_t)i * it.ld_dst + j] += it.coef * v;
+    }
+}
+
 static void add_tiles(std::vector<GemmTile> &out, const GemmTile &base) {
     if (base.M <= 0 || base.N <= 0) return;
     for (int ti = 0; ti * RN_TILE < base.M; ++ti)
@@ -166,6 +188,41 @@ dmrg_status dmrg_renormalize(int32_t nblk, const dmrg_renorm_block *blocks, cons
     (void)hipFree(tmp);
     if (e != hipSuccess) return set_error(DMRG_E_HIP, "renormalize: %s", hipGetErrorString(e));
     if (e2 != hipSuccess) return set_error(DMRG_E_HIP, "renormalize: %s", hipGetErrorString(e2));
+    return DMRG_OK;
+}
+
+dmrg_status dmrg_place_blocks(int32_t n, const dmrg_place *items, const double *src, double *dst, void *stream) {
+    clear_error();
+    if (n < 0) return set_error(DMRG_E_INVALID_ARG, "negative item count");
+    if (n == 0) return DMRG_OK;
+    if (!items || !dst) return set_error(DMRG_E_INVALID_ARG, "null argument");
+    std::vector<PlaceItem> it(n);
+    for (int32_t i = 0; i < n; ++i) {
+        const dmrg_place &P = items[i];
+        if (P.rows < 0 || P.cols < 0 || P.dst < 0 || P.ld_dst < P.cols || (P.identity != 0 && P.identity != 1) ||
+            (!P.identity && (!src || P.src < 0 || P.ld_src < P.cols)))
+            return set_error(DMRG_E_INVALID_ARG, "item %d: bad sizes, strides, offsets or kind", i);
+        it[i].src = P.identity ? nullptr : src + P.src;
+        it[i].dst = dst + P.dst;
+        it[i].rows = P.rows;
+        it[i].cols = P.cols;
+        it[i].ld_src = P.ld_src;
+        it[i].ld_dst = P.ld_dst;
+        it[i].coef = P.coef;
+        it[i].identity = P.identity;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    PlaceItem *d_it = nullptr;
+    DMRG_HIP(hipMalloc(&d_it, n * sizeof(PlaceItem)));
+    hipError_t e = hipMemcpyAsync(d_it, it.data(), n * sizeof(PlaceItem), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_place, dim3(n), dim3(256), 0, s, d_it);
+        e = hipGetLastError();
+    }
+    const hipError_t e2 = hipStreamSynchronize(s);
+    (void)hipFree(d_it);
+    if (e != hipSuccess) return set_error(DMRG_E_HIP, "place_blocks: %s", hipGetErrorString(e));
+    if (e2 != hipSuccess) return set_error(DMRG_E_HIP, "place_blocks: %s", hipGetErrorString(e2));
     return DMRG_OK;
 }
 

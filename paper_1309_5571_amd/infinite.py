@@ -1,0 +1,261 @@
+"""Infinite-lattice DMRG for the open spin-1/2 Heisenberg chain (Alg. 1), every
+numerical step on the device through the C ABI.
+
+One iteration: enlarge the block by one site (dmrg_place_blocks), form the
+superblock of two mirror-image enlarged blocks in the S^z = 0 sector, find its
+lowest eigenstate (dmrg_davidson), build the left block's density matrix
+(dmrg_density), diagonalize it sector by sector (dmrg_eigh_blocks), keep the m
+states of largest weight (dmrg_truncate) and take the block's operators to
+the kept basis (dmrg_renormalize).  The chain grows by two sites per
+iteration (Sec. "The DMRG algorithm").
+
+Blocks carry four operators in dense sector form: the block Hamiltonian H and
+the spin operators S+, S-, Sz of the site at the block's inner edge.  Labels
+are 2 S^z.  The right block is the mirror image of the left one, so the same
+operator data serves both sides.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass, field
+from typing import Dict, List, Sequence, Tuple
+
+import numpy as np
+
+from . import _native as N
+
+OPS = ("H", "Sp", "Sm", "Sz")
+
+
+@dataclass
+class DevOp:
+    """Dense sector-form operator whose blocks live in one device tensor."""
+    src: np.ndarray  # int32 [nblk] source sector
+    dst: np.ndarray  # int32 [nblk] destination sector
+    off: np.ndarray  # int64 [nblk] element offset of each row-major block
+    device_data: object  # torch float64 tensor
+    kind: str = "dense"
+
+
+@dataclass
+class Block:
+    labels: np.ndarray  # int32 [nsec], ascending
+    dims: np.ndarray  # int64 [nsec]
+    ops: Dict[str, DevOp]
+    nsites: int
+
+
+@dataclass
+class _Space:
+    labels: np.ndarray
+    dims: np.ndarray
+
+
+@dataclass
+class _Identity:
+    kind: str = "identity"
+
+
+@dataclass
+class _Superblock:
+    left: _Space
+    right: _Space
+    target: np.ndarray
+    ops_left: list
+    ops_right: list
+    terms: np.ndarray
+    coef: np.ndarray
+
+
+@dataclass
+class StepResult:
+    nsites: int  # sites of the superblock
+    energy: float
+    discarded: float
+    kept: int
+    iterations: int
+
+
+def _p(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(dev):
+    import torch
+
+    return ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+
+def site_block(device) -> Block:
+    """One spin: sectors 2S^z = -1 (down), +1 (up)."""
+    import torch
+
+    def op(src, dst, vals):
+        t = torch.tensor(vals, dtype=torch.float64, device=device)
+        return DevOp(np.array(src, np.int32), np.array(dst, np.int32), np.arange(len(vals), dtype=np.int64), t)
+
+    return Block(np.array([-1, 1], np.int32), np.array([1, 1], np.int64),
+                 {"H": op([0, 1], [0, 1], [0.0, 0.0]), "Sp": op([0], [1], [1.0]), "Sm": op([1], [0], [1.0]),
+                  "Sz": op([0, 1], [0, 1], [-0.5, 0.5])}, 1)
+
+
+# site operators as (source site state, destination site state, value); state 0 = down, 1 = up
+_SITE = {"I": [(0, 0, 1.0), (1, 1, 1.0)], "Sp": [(0, 1, 1.0)], "Sm": [(1, 0, 1.0)], "Sz": [(0, 0, -0.5), (1, 1, 0.5)]}
+_SIGMA = (-1, 1)
+
+
+def enlarge(B: Block, J: float = 1.0, delta: float = 1.0) -> Block:
+    """Block + one site (Alg. 1, step 2), in sector form:
+    H' = H (x) I + J/2 (S+ (x) S- + S- (x) S+) + J delta Sz (x) Sz, and the new
+    edge operators I (x) S+, I (x) S-, I (x) Sz.  Enlarged sector mu holds the
+    parts (lambda, sigma) with lambda + sigma = mu, spin down first."""
+    import torch
+
+    dev = B.ops["H"].device_data.device
+    lab = {int(l): i for i, l in enumerate(B.labels)}
+    mus = sorted({int(l) + s for l in B.labels for s in _SIGMA})
+    part_off: Dict[Tuple[int, int], Tuple[int, int]] = {}  # (block sector, site state) -> (E sector, row offset)
+    dims = []
+    for e, mu in enumerate(mus):
+        o = 0
+        for st, s in enumerate(_SIGMA):
+            if mu - s in lab:
+                part_off[(lab[mu - s], st)] = (e, o)
+                o += int(B.dims[lab[mu - s]])
+        dims.append(o)
+    dims = np.array(dims, np.int64)
+
+    def build(pieces):
+        """pieces: list of (block op name or None for identity, site op name, coef).
+        Returns the enlarged DevOp; each piece is one dmrg_place_blocks call."""
+        # destination blocks first
+        keys = {}
+        plans = []
+        for name, sname, coef in pieces:
+            items = []
+            if name is None:
+                blocks = [(s, s, None, int(B.dims[s]), int(B.dims[s])) for s in range(len(B.dims))]
+            else:
+                opb = B.ops[name]
+                blocks = [(int(a), int(b), int(o), int(B.dims[b]), int(B.dims[a]))
+                          for a, b, o in zip(opb.src, opb.dst, opb.off)]
+            for (a, b, o, rows, cols) in blocks:  # block sector a -> b
+                for (ss, sd, v) in _SITE[sname]:
+                    if (a, ss) not in part_off or (b, sd) not in part_off:
+                        continue
+                    es, cs = part_off[(a, ss)]
+                    ed, rd = part_off[(b, sd)]
+                    keys.setdefault((es, ed), None)
+                    items.append(((es, ed), rd, cs, rows, cols, o, coef * v))
+            plans.append((name, items))
+        order = sorted(keys)
+        boff, pos = {}, 0
+        for (es, ed) in order:
+            boff[(es, ed)] = pos
+            pos += int(dims[ed]) * int(dims[es])
+        data = torch.zeros(max(pos, 1), dtype=torch.float64, device=dev)
+        for name, items in plans:
+            if not items:
+                continue
+            arr = (N.Place * len(items))()
+            for i, ((es, ed), rd, cs, rows, cols, o, c) in enumerate(items):
+                ld = int(dims[es])
+                arr[i] = N.Place(0 if o is None else o, boff[(es, ed)] + rd * ld + cs, rows, cols,
+                                 max(cols, 1), ld, c, 1 if o is None else 0)
+            src = B.ops[name].device_data if name is not None else data
+            N.check(N.lib().dmrg_place_blocks(len(items), arr, _p(src), _p(data), _stream(dev)))
+        return DevOp(np.array([k[0] for k in order], np.int32), np.array([k[1] for k in order], np.int32),
+                     np.array([boff[k] for k in order], np.int64), data)
+
+    ops = {
+        # H (x) I, the two spin flips and Sz (x) Sz: the last overlaps the first, so it is its own call
+        "H": build([("H", "I", 1.0), ("Sp", "Sm", 0.5 * J), ("Sm", "Sp", 0.5 * J), ("Sz", "Sz", J * delta)]),
+        "Sp": build([(None, "Sp", 1.0)]),
+        "Sm": build([(None, "Sm", 1.0)]),
+        "Sz": build([(None, "Sz", 1.0)]),
+    }
+    return Block(np.array(mus, np.int32), dims, ops, B.nsites + 1)
+
+
+def superblock(E: Block, J: float = 1.0, delta: float = 1.0) -> _Superblock:
+    """Two mirror-image enlarged blocks coupled through their edge sites, S^z = 0."""
+    sp = _Space(E.labels.copy(), E.dims.copy())
+    ops = [_Identity(), E.ops["H"], E.ops["Sp"], E.ops["Sm"], E.ops["Sz"]]
+    terms = np.array([(1, 0), (0, 1), (2, 3), (3, 2), (4, 4)], np.int32)
+    coef = np.array([1.0, 1.0, 0.5 * J, 0.5 * J, J * delta])
+    return _Superblock(sp, sp, np.array([0], np.int32), ops, ops, terms, coef)
+
+
+def renormalize_block(E: Block, plan, psi, m: int) -> Tuple[Block, float, int]:
+    """Alg. 1, steps 5-7 for the left block: density matrix, its eigenpairs,
+    the m kept states, and the operators in the kept basis."""
+    import torch
+
+    from . import eigh_blocks, renormalize, truncate
+
+    dev = psi.device
+    rl, _ = plan.density(psi, right=False)
+    lo, _ = plan.density_layout()
+    dims = np.sqrt(np.diff(lo)).round().astype(np.int64)
+    w, u = eigh_blocks(rl, dims)
+    keep, disc = truncate(w, dims, m)
+    lay = plan.layout()
+    pair_of = {int(s): k for k, s in enumerate(lay["pair_left"])}
+    kept_secs = [s for s in range(len(E.dims)) if s in pair_of and keep[pair_of[s]] > 0]
+    new_index = {s: i for i, s in enumerate(kept_secs)}
+    new_dims = np.array([int(keep[pair_of[s]]) for s in kept_secs], np.int64)
+    ops = {}
+    for name in OPS:
+        op = E.ops[name]
+        reqs, src, dst, off = [], [], [], []
+        pos = 0
+        for a, b, o in zip(op.src, op.dst, op.off):
+            a, b = int(a), int(b)
+            if a not in new_index or b not in new_index:
+                continue
+            ka, kb = int(keep[pair_of[a]]), int(keep[pair_of[b]])
+            reqs.append((int(o), int(lo[pair_of[b]]), int(lo[pair_of[a]]), pos, int(E.dims[b]), int(E.dims[a]),
+                         kb, ka, 0))
+            src.append(new_index[a])
+            dst.append(new_index[b])
+            off.append(pos)
+            pos += kb * ka
+        data = renormalize(op.device_data, u, reqs, pos) if reqs else torch.zeros(1, dtype=torch.float64,
+                                                                                 device=dev)
+        ops[name] = DevOp(np.array(src, np.int32), np.array(dst, np.int32), np.array(off, np.int64), data)
+    newB = Block(E.labels[kept_secs].copy(), new_dims, ops, E.nsites)
+    return newB, float(disc[0]), int(new_dims.sum())
+
+
+def run(nsites: int, m: int, J: float = 1.0, delta: float = 1.0, tol: float = 1e-10, device=None,
+        seed: int = 0) -> List[StepResult]:
+    """Grow the chain from 4 to `nsites` sites (even), keeping m states per
+    block; returns the ground-state energy of every superblock on the way."""
+    import torch
+
+    from . import Plan
+
+    if nsites < 4 or nsites % 2:
+        raise ValueError("nsites must be even and >= 4")
+    dev = torch.device("cuda", 0) if device is None else torch.device(device)
+    rng = np.random.default_rng(seed)
+    B = site_block(dev)
+    out: List[StepResult] = []
+    while 2 * (B.nsites + 1) <= nsites:
+        E = enlarge(B, J, delta)
+        plan = Plan(superblock(E, J, delta), device=dev, tiles=None)
+        # in a tiny superblock the preconditioned correction can fall inside the
+        # subspace before convergence (breakdown): start again from another vector
+        for attempt in range(4):
+            x0 = torch.from_numpy(rng.standard_normal(plan.n)).to(dev)
+            psi, energy, infos, st = plan.davidson(x0, tol=tol, kmax=min(32, max(2, plan.n)),
+                                                   kmin=min(8, max(1, plan.n - 1)))
+            if infos[0]["converged"]:
+                break
+        else:
+            N.check(st)
+            raise N.DmrgError(N.W_NOT_CONVERGED, "Davidson did not converge")
+        B, disc, kept = renormalize_block(E, plan, psi, m)
+        out.append(StepResult(2 * E.nsites, float(energy[0]), disc, kept, int(infos[0]["iterations"])))
+        plan.close()
+    return out

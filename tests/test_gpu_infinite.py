@@ -1,0 +1,89 @@
+"""The infinite-lattice DMRG iteration (Alg. 1) on the device, every step
+through the C ABI, against exact diagonalization and closed forms.
+
+* Without truncation (m above the block dimension) the enlarged block is the
+  exact chain in a rotated basis: its Hamiltonian has the chain's spectrum
+  (LAPACK on the dense chain of Eq. 1), and the superblock energies equal the
+  exact ground energies.
+* The XX chain (Delta = 0) has the free-fermion ground energy.
+* With truncation the energy per site from the last two growth steps
+  approaches Hulthen's 1/4 - ln 2.
+"""
+import numpy as np
+import pytest
+
+from oracle import models
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _inf():
+    from paper_1309_5571_amd import infinite
+
+    return infinite
+
+
+def _dense_h(E):
+    """The enlarged block's Hamiltonian assembled on the host from its device blocks."""
+    off = np.concatenate([[0], np.cumsum(E.dims)])
+    m = int(off[-1])
+    H = np.zeros((m, m))
+    op = E.ops["H"]
+    data = op.device_data.cpu().numpy()
+    for a, b, o in zip(op.src, op.dst, op.off):
+        r, c = int(E.dims[b]), int(E.dims[a])
+        H[off[b]:off[b] + r, off[a]:off[a] + c] = data[o:o + r * c].reshape(r, c)
+    return H
+
+
+def test_enlarged_block_spectrum_matches_exact_chain():
+    inf = _inf()
+    from paper_1309_5571_amd import Plan
+
+    dev = torch.device("cuda", 0)
+    B = inf.site_block(dev)
+    for _ in range(5):
+        E = inf.enlarge(B)
+        H = _dense_h(E)
+        np.testing.assert_allclose(H, H.T, atol=1e-13)
+        want = np.linalg.eigvalsh(models.heisenberg_chain(E.nsites))
+        np.testing.assert_allclose(np.linalg.eigvalsh(H), want, atol=1e-10)
+        plan = Plan(inf.superblock(E), device=dev, tiles=None)
+        x0 = torch.from_numpy(np.random.default_rng(1).standard_normal(plan.n)).to(dev)
+        psi, _, infos, st = plan.davidson(x0, tol=1e-11, kmax=min(32, plan.n), kmin=min(8, plan.n - 1))
+        assert infos[0]["converged"]
+        B, disc, kept = inf.renormalize_block(E, plan, psi, 1 << 20)  # keep everything
+        assert kept == int(E.dims.sum()) and abs(disc) < 1e-12
+        plan.close()
+
+
+def test_infinite_dmrg_is_exact_without_truncation():
+    res = _inf().run(12, m=64, tol=1e-11)
+    assert [r.nsites for r in res] == [4, 6, 8, 10, 12]
+    for r in res:
+        assert r.energy == pytest.approx(models.chain_ground_energy(r.nsites), abs=1e-9)
+
+
+def test_infinite_dmrg_xx_chain_free_fermions():
+    res = _inf().run(24, m=64, delta=0.0, tol=1e-11)
+    for r in res:
+        assert r.energy == pytest.approx(models.xx_chain_energy(r.nsites), abs=1e-5)
+
+
+def test_infinite_dmrg_approaches_hulthen():
+    res = _inf().run(100, m=32, tol=1e-10)
+    e = [r.energy for r in res]
+    assert res[-1].nsites == 100
+    per_site = (e[-1] - e[-2]) / 2
+    assert abs(per_site - models.hulthen_energy_per_site()) < 2e-3
+    # the discarded weight stays small and every step keeps m states once the block is larger
+    assert max(r.discarded for r in res) < 1e-3
+    assert all(r.kept == 32 for r in res[5:])

@@ -103,3 +103,15 @@ def test_golden_energies_reproduce():
     assert g["hubbard_open_N2_t1_U4_half"] == pytest.approx(models.hubbard_dimer_energy(1, 4), abs=1e-13)
     H = models.heisenberg_chain(10)
     assert sector_min(H, models.spin_labels(10), 0) == pytest.approx(g["heisenberg_open_N10_Sz0"], abs=1e-12)
+
+
+def test_chain_ground_energy_matches_closed_forms():
+    """The S^z = 0 sector ED of the chain: the dimer -3/4, the XX chain's free
+    fermions, and energies per site approaching Hulthen's 1/4 - ln 2 from
+    above as the open chain grows (the boundary costs energy)."""
+    assert models.chain_ground_energy(2) == pytest.approx(-0.75, abs=1e-14)
+    for n in (4, 6, 8):
+        assert models.chain_ground_energy(n, delta=0.0) == pytest.approx(models.xx_chain_energy(n), abs=1e-12)
+    e = [models.chain_ground_energy(n) for n in (8, 10, 12)]
+    d = [(e[1] - e[0]) / 2, (e[2] - e[1]) / 2]
+    assert abs(d[1] - models.hulthen_energy_per_site()) < abs(d[0] - models.hulthen_energy_per_site()) < 0.01
