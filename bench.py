@@ -38,7 +38,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true", help="skip the projection and FP64 comparison timings")
     ap.add_argument("--workload", default="hubbard_m2048",
-                    choices=["hubbard_m2048", "heisenberg_m1024", "j1j2_m1024", "batched_64", "gemv", "pmc"],
+                    choices=["hubbard_m2048", "heisenberg_m1024", "j1j2_m1024", "batched_64", "gemv", "pmc",
+                             "infinite_heisenberg"],
                     help="hubbard_m2048 is the headline line; the others time the projection and the "
                          "mixed-precision solve of the other synthetic workloads")
     return ap.parse_args()
@@ -159,6 +160,34 @@ def renorm_stats(plan, psi, torch, reps=10):
             "groups": int(groups.size), "m_keep": int(ms.sum()),
             "eigh_us": float(np.median(te)), "truncate_us": float(np.median(tt)),
             "discarded": float(disc.sum().cpu())}
+
+
+def infinite_workload(nsites=100, m=32, reps=3):
+    """The whole infinite-lattice iteration (Alg. 1) grown from 4 to `nsites`
+    sites of the Heisenberg chain keeping m states: wall time per growth step
+    (median of `reps` runs after one warm-up) and the energy per site from the
+    last two steps against Hulthen's 1/4 - ln 2."""
+    import math
+
+    import torch
+
+    from paper_1309_5571_amd import infinite
+
+    infinite.run(12, m=m)  # warm-up (library load, first kernels)
+    times, res = [], None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = infinite.run(nsites, m=m)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    t = sorted(times)[len(times) // 2]
+    e = [r.energy for r in res]
+    per_site = (e[-1] - e[-2]) / 2
+    return {"workload": f"infinite_heisenberg_N{nsites}_m{m}", "steps": len(res), "seconds": t,
+            "ms_per_step": t / len(res) * 1e3, "energy": e[-1], "energy_per_site": per_site,
+            "hulthen": 0.25 - math.log(2.0), "max_discarded": max(r.discarded for r in res),
+            "davidson_iterations": sum(r.iterations for r in res)}
 
 
 def cpu_baseline(p, x0):
@@ -299,6 +328,9 @@ def main():
         return
     if args.workload == "pmc":
         print(json.dumps(pmc_workload()))
+        return
+    if args.workload == "infinite_heisenberg":
+        print(json.dumps(infinite_workload()))
         return
     cfg = {"hubbard_m2048": 3, "heisenberg_m1024": 2, "j1j2_m1024": 5, "batched_64": 4}[args.workload]
     p = gen.config(cfg)
