@@ -42,6 +42,8 @@ def test_struct_sizes_match_c_layout():
     assert ctypes.sizeof(N.Op) == 40
     assert ctypes.sizeof(N.DavidsonOpts) == 64
     assert ctypes.sizeof(N.DavidsonInfo) == 40
+    assert ctypes.sizeof(N.RenormBlock) == 56
+    assert ctypes.sizeof(N.Place) == 48
 
 
 @pytest.mark.parametrize("cfg", [1, 2, 3, 5])
@@ -125,3 +127,46 @@ def test_gemv_argument_errors():
     assert lib.dmrg_gemv_t(0, 1, None, 1, None, None, None) == N.E_INVALID_ARG
     assert lib.dmrg_gemv_n(10, 65, None, 10, None, 0.0, None, None) == N.E_INVALID_ARG
     assert lib.dmrg_set_tile_table(1, (ctypes.c_int32 * 1)(8), (ctypes.c_int32 * 1)(24)) == N.E_INVALID_ARG
+
+
+def test_renormalization_entry_points_validate_on_the_host():
+    """Density, eigen-decomposition, selection, renormalization and placement
+    reject bad arguments before any device work."""
+    lib = N.lib()
+    assert lib.dmrg_density(None, None, None, None, None) == N.E_INVALID_ARG
+    assert lib.dmrg_density_layout(None, None, None) == N.E_INVALID_ARG
+    assert lib.dmrg_eigh_blocks(-1, None, None, None, None, None, None, None, None) == N.E_INVALID_ARG
+    assert lib.dmrg_eigh_blocks(0, None, None, None, None, None, None, None, None) == N.OK
+    assert lib.dmrg_eigh_blocks(1, None, None, None, None, None, None, None, None) == N.E_INVALID_ARG
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.dmrg_eigh_blocks(1, fake, fake, fake, fake, fake, fake, None, None) == N.E_INVALID_ARG  # overlap
+    assert lib.dmrg_truncate(-1, None, None, None, None, None, None, None, None) == N.E_INVALID_ARG
+    assert lib.dmrg_truncate(2, fake, fake, fake, fake, None, fake, None, None) == N.E_INVALID_ARG
+    # renormalize: sizes and kinds are checked block by block
+    a, b = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000)
+    out = ctypes.c_void_p(0x3000)
+    bad = [N.RenormBlock(0, 0, 0, 0, 4, 4, 5, 4, 0),   # k_dst > rows
+           N.RenormBlock(0, 0, 0, 0, 2, 3, 1, 1, 1),   # diagonal but not square
+           N.RenormBlock(-1, 0, 0, 0, 2, 2, 1, 1, 0),  # negative offset
+           N.RenormBlock(0, 0, 0, 0, 0, 2, 0, 1, 0),   # empty sector
+           N.RenormBlock(0, 0, 0, 0, 2, 2, 1, 1, 2)]   # unknown kind
+    for blk in bad:
+        arr = (N.RenormBlock * 1)(blk)
+        assert lib.dmrg_renormalize(1, arr, a, b, out, None) == N.E_INVALID_ARG
+        assert "block 0" in N.last_error()
+    ok = (N.RenormBlock * 1)(N.RenormBlock(0, 0, 0, 0, 2, 2, 1, 1, 0))
+    assert lib.dmrg_renormalize(1, ok, a, b, a, None) == N.E_INVALID_ARG  # out overlaps data
+    assert lib.dmrg_renormalize(-1, ok, a, b, out, None) == N.E_INVALID_ARG
+    assert lib.dmrg_renormalize(0, ok, a, b, out, None) == N.OK
+    # placement
+    badp = [N.Place(0, 0, -1, 2, 2, 2, 1.0, 0),   # negative rows
+            N.Place(0, 0, 2, 3, 3, 2, 1.0, 0),    # ld_dst < cols
+            N.Place(0, 0, 2, 3, 2, 3, 1.0, 0),    # ld_src < cols
+            N.Place(-4, 0, 2, 2, 2, 2, 1.0, 0),   # negative source offset
+            N.Place(0, 0, 2, 2, 2, 2, 1.0, 3)]    # unknown kind
+    for it in badp:
+        arr = (N.Place * 1)(it)
+        assert lib.dmrg_place_blocks(1, arr, a, out, None) == N.E_INVALID_ARG
+    ident = (N.Place * 1)(N.Place(0, 0, 2, 2, 0, 2, 1.0, 1))
+    assert lib.dmrg_place_blocks(1, ident, None, None, None) == N.E_INVALID_ARG  # null dst
+    assert lib.dmrg_place_blocks(0, ident, None, None, None) == N.OK
