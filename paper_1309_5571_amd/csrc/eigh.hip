@@ -19,7 +19,8 @@
 
 namespace dmrg {
 
-constexpr int EIG_TPB = 256;
+constexpr int EIG_TPB = 256;        // selection kernel
+constexpr int EIG_TPB_SMALL = 512;  // Jacobi, blocks in LDS (a round has ~d^2/2 independent items)
 constexpr int EIG_LDS_DIM = 48;  // A (padded rows) and V in LDS: 37 KB
 constexpr int EIG_MAX_DIM = 2048;
 constexpr int EIG_MAX_SWEEPS = 40;
@@ -37,12 +38,12 @@ __device__ __forceinline__ void circle_pair(int r, int k, int m, int &p, int &q)
 }
 
 template <bool SMALL>
-__global__ __launch_bounds__(SMALL ? EIG_TPB : 1024) void k_eigh(int nblk, const int64_t *__restrict__ off,
+__global__ __launch_bounds__(SMALL ? EIG_TPB_SMALL : 1024) void k_eigh(int nblk, const int64_t *__restrict__ off,
                                                   const int32_t *__restrict__ dim, const int64_t *__restrict__ woff,
                                                   double *__restrict__ a, double *__restrict__ w,
                                                   double *__restrict__ u, int32_t *__restrict__ info) {
     constexpr int NP = SMALL ? EIG_LDS_DIM / 2 : EIG_MAX_DIM / 2;  // pairs per round
-    constexpr int NT = SMALL ? EIG_TPB : 1024;                      // threads
+    constexpr int NT = SMALL ? EIG_TPB_SMALL : 1024;                // threads
     __shared__ double sA[SMALL ? EIG_LDS_DIM * (EIG_LDS_DIM + 1) : 1];
     __shared__ double sV[SMALL ? EIG_LDS_DIM * EIG_LDS_DIM : 1];
     __shared__ double rc[NP], rs[NP];
@@ -330,7 +331,7 @@ dmrg_status dmrg_eigh_blocks(int32_t nblk, const int64_t *off, const int32_t *di
     if (!off || !dim || !woff || !a || !w || !u) return set_error(DMRG_E_INVALID_ARG, "null argument");
     if (a == u || a == w || u == w) return set_error(DMRG_E_INVALID_ARG, "a, w and u must not overlap");
     hipStream_t s = (hipStream_t)stream;
-    hipLaunchKernelGGL(k_eigh<true>, dim3(nblk), dim3(EIG_TPB), 0, s, nblk, off, dim, woff, a, w, u, info);
+    hipLaunchKernelGGL(k_eigh<true>, dim3(nblk), dim3(EIG_TPB_SMALL), 0, s, nblk, off, dim, woff, a, w, u, info);
     hipLaunchKernelGGL(k_eigh<false>, dim3(nblk), dim3(1024), 0, s, nblk, off, dim, woff, a, w, u, info);
     DMRG_HIP(hipGetLastError());
     return DMRG_OK;

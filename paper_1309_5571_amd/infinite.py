@@ -17,8 +17,8 @@ operator data serves both sides.
 from __future__ import annotations
 
 import ctypes
-from dataclasses import dataclass, field
-from typing import Dict, List, Sequence, Tuple
+from dataclasses import dataclass
+from typing import Dict, List, Tuple
 
 import numpy as np
 
@@ -197,7 +197,10 @@ def renormalize_block(E: Block, plan, psi, m: int) -> Tuple[Block, float, int]:
     rl, _ = plan.density(psi, right=False)
     lo, _ = plan.density_layout()
     dims = np.sqrt(np.diff(lo)).round().astype(np.int64)
-    w, u = eigh_blocks(rl, dims)
+    w, u, info = eigh_blocks(rl, dims, return_info=True)
+    bad = info.cpu().numpy() < 0
+    if bad.any():
+        raise N.DmrgError(N.E_UNSUPPORTED, f"eigen-decomposition failed for blocks {np.flatnonzero(bad).tolist()}")
     keep, disc = truncate(w, dims, m)
     lay = plan.layout()
     pair_of = {int(s): k for k, s in enumerate(lay["pair_left"])}
