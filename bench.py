@@ -401,6 +401,9 @@ def main():
         log(f"density matrices: {extra['density']}")
         extra["renormalization"] = renorm_stats(plan, psi, torch)
         log(f"eigen-decomposition and selection: {extra['renormalization']}")
+        if cfg == 3:  # the whole infinite-lattice iteration, Heisenberg chain to 100 sites
+            extra["infinite_heisenberg"] = infinite_workload(reps=1)
+            log(f"infinite-lattice DMRG: {extra['infinite_heisenberg']}")
         extra["mixed_vs_fp64_time_ratio"] = (dt / args.steps * 1e3) / extra["fp64_solve"]["ms_per_solve"]
 
     # roofline of the dominant kernel: the FP64 projection, bound by HBM bytes at
