@@ -231,7 +231,7 @@ def renormalize_block(E: Block, plan, psi, m: int) -> Tuple[Block, float, int]:
 
 
 def run(nsites: int, m: int, J: float = 1.0, delta: float = 1.0, tol: float = 1e-10, device=None,
-        seed: int = 0) -> List[StepResult]:
+        seed: int = 0, kmax: int = 32, kmin: int = 8) -> List[StepResult]:
     """Grow the chain from 4 to `nsites` sites (even), keeping m states per
     block; returns the ground-state energy of every superblock on the way."""
     import torch
@@ -251,8 +251,8 @@ def run(nsites: int, m: int, J: float = 1.0, delta: float = 1.0, tol: float = 1e
         # subspace before convergence (breakdown): start again from another vector
         for attempt in range(4):
             x0 = torch.from_numpy(rng.standard_normal(plan.n)).to(dev)
-            psi, energy, infos, st = plan.davidson(x0, tol=tol, kmax=min(32, max(2, plan.n)),
-                                                   kmin=min(8, max(1, plan.n - 1)))
+            psi, energy, infos, st = plan.davidson(x0, tol=tol, kmax=min(kmax, max(2, plan.n)),
+                                                   kmin=min(kmin, max(1, min(kmax, plan.n) - 1)))
             if infos[0]["converged"]:
                 break
         else:
