@@ -247,7 +247,10 @@ dmrg_status dmrg_gemv_n(int64_t n, int32_t k, const double *V, int64_t ldv, cons
  *  dmrg_density: psi device FP64 [n]; rho_left, rho_right device FP64 of
  *    those lengths, owned by the caller; either may be NULL (not computed);
  *    must not overlap psi or each other.  FP64 throughout.  Batched plans:
- *    the members' pairs in order.  Asynchronous on stream. */
+ *    the members' pairs in order.  Asynchronous on stream.
+ *  Errors: DMRG_E_INVALID_ARG for a null plan or psi, outputs that alias psi
+ *  or each other, or a device other than the plan's; DMRG_E_HIP if the
+ *  launch fails. */
 dmrg_status dmrg_density_layout(const dmrg_plan *plan, int64_t *left_off, int64_t *right_off);
 dmrg_status dmrg_density(dmrg_plan *plan, const double *psi, double *rho_left, double *rho_right,
                          void *stream);
@@ -266,7 +269,9 @@ dmrg_status dmrg_density(dmrg_plan *plan, const double *psi, double *rho_left, d
  *  info: optional device [nblk]: sweeps used, -1 if dim[b] is outside
  *    1..2048 (the block is then not touched), -2 if 40 sweeps did not converge.
  *  The sizes are read on the device: the caller guarantees that every
- *  block lies inside a, w and u.  Asynchronous on stream. */
+ *  block lies inside a, w and u.  Asynchronous on stream.
+ *  Errors: DMRG_E_INVALID_ARG for nblk < 0, a null array, or a, w, u that
+ *  alias; DMRG_E_HIP if a launch fails.  nblk = 0 does nothing. */
 dmrg_status dmrg_eigh_blocks(int32_t nblk, const int64_t *off, const int32_t *dim, const int64_t *woff,
                              double *a, double *w, double *u, int32_t *info, void *stream);
 
@@ -283,7 +288,9 @@ dmrg_status dmrg_eigh_blocks(int32_t nblk, const int64_t *off, const int32_t *di
  *  discarded: device out [ngroup] or NULL: the sum of the values not kept
  *    (NaN for an oversized group).
  *  The sizes are read on the device: the caller guarantees that they describe
- *  w.  Asynchronous on stream. */
+ *  w.  Asynchronous on stream.
+ *  Errors: DMRG_E_INVALID_ARG for ngroup < 0 or a null array (discarded may
+ *  be NULL); DMRG_E_HIP if the launch fails.  ngroup = 0 does nothing. */
 dmrg_status dmrg_truncate(int32_t ngroup, const int32_t *gblk, const int32_t *dim, const int64_t *woff,
                           const double *w, const int32_t *m_keep, int32_t *keep, double *discarded,
                           void *stream);
@@ -310,7 +317,11 @@ typedef struct {
  *    out.  data, u: device FP64 inputs; out: device FP64, owned by the
  *    caller, not overlapping data or u.
  *  Allocates a device intermediate (sum of rows * k_src doubles) and the
- *  tile list for the call and synchronizes stream before returning. */
+ *  tile list for the call and synchronizes stream before returning.
+ *  Errors: DMRG_E_INVALID_ARG for nblk < 0, a null pointer, out aliasing
+ *  data or u, or a block with bad sizes, kind or offsets (the message names
+ *  the block); DMRG_E_NOMEM / DMRG_E_HIP from the allocation, copy or
+ *  launches.  nblk = 0 does nothing. */
 dmrg_status dmrg_renormalize(int32_t nblk, const dmrg_renorm_block *blocks, const double *data,
                              const double *u, double *out, void *stream);
 
@@ -332,7 +343,11 @@ typedef struct {
  * call must not overlap in dst (they run in parallel; overlapping sums go in
  * separate calls, which run in call order).  src, dst: device FP64, owned by
  * the caller; the caller guarantees the offsets lie inside them.  Allocates
- * the item list for the call and synchronizes stream before returning. */
+ * the item list for the call and synchronizes stream before returning.
+ * Errors: DMRG_E_INVALID_ARG for n < 0, a null dst (or src with a copy
+ * item), or an item with negative sizes or offsets, strides below cols or
+ * an unknown kind (the message names the item); DMRG_E_NOMEM / DMRG_E_HIP
+ * from the allocation, copy or launch.  n = 0 does nothing. */
 dmrg_status dmrg_place_blocks(int32_t n, const dmrg_place *items, const double *src, double *dst,
                               void *stream);
 
