@@ -87,3 +87,21 @@ def test_infinite_dmrg_approaches_hulthen():
     # the discarded weight stays small and every step keeps m states once the block is larger
     assert max(r.discarded for r in res) < 1e-3
     assert all(r.kept == 32 for r in res[5:])
+
+
+@pytest.mark.parametrize("delta", [0.5, 2.0])
+def test_infinite_dmrg_anisotropic_chain_is_exact(delta):
+    """The Sz Sz coupling enters through its own placement call: XXZ chains
+    without truncation equal their exact ground energies."""
+    res = _inf().run(10, m=64, delta=delta, tol=1e-11)
+    for r in res:
+        assert r.energy == pytest.approx(models.chain_ground_energy(r.nsites, delta), abs=1e-9)
+
+
+def test_infinite_dmrg_energy_scales_with_coupling():
+    """H is linear in J: the same growth with J = 2 doubles every energy."""
+    a = _inf().run(16, m=16, tol=1e-11)
+    b = _inf().run(16, m=16, J=2.0, tol=1e-11)
+    for x, y in zip(a, b):
+        assert y.energy == pytest.approx(2.0 * x.energy, abs=1e-8)
+        assert y.discarded == pytest.approx(x.discarded, abs=1e-9)
