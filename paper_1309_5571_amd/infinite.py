@@ -177,25 +177,33 @@ def enlarge(B: Block, J: float = 1.0, delta: float = 1.0) -> Block:
     return Block(np.array(mus, np.int32), dims, ops, B.nsites + 1)
 
 
-def superblock(E: Block, J: float = 1.0, delta: float = 1.0) -> _Superblock:
-    """Two mirror-image enlarged blocks coupled through their edge sites, S^z = 0."""
-    sp = _Space(E.labels.copy(), E.dims.copy())
-    ops = [_Identity(), E.ops["H"], E.ops["Sp"], E.ops["Sm"], E.ops["Sz"]]
+def superblock(E: Block, J: float = 1.0, delta: float = 1.0, ER: Block = None) -> _Superblock:
+    """A left and a right enlarged block (the right one mirrored: its edge site
+    faces the centre; ER None: the mirror image of E) coupled through their
+    edge sites, S^z = 0."""
+    ER = E if ER is None else ER
+    sides = []
+    for B in (E, ER):
+        sides.append((_Space(B.labels.copy(), B.dims.copy()),
+                      [_Identity(), B.ops["H"], B.ops["Sp"], B.ops["Sm"], B.ops["Sz"]]))
     terms = np.array([(1, 0), (0, 1), (2, 3), (3, 2), (4, 4)], np.int32)
     coef = np.array([1.0, 1.0, 0.5 * J, 0.5 * J, J * delta])
-    return _Superblock(sp, sp, np.array([0], np.int32), ops, ops, terms, coef)
+    return _Superblock(sides[0][0], sides[1][0], np.array([0], np.int32), sides[0][1], sides[1][1], terms, coef)
 
 
-def renormalize_block(E: Block, plan, psi, m: int) -> Tuple[Block, float, int]:
-    """Alg. 1, steps 5-7 for the left block: density matrix, its eigenpairs,
-    the m kept states, and the operators in the kept basis."""
+def renormalize_block(E: Block, plan, psi, m: int, side: str = "left") -> Tuple[Block, float, int]:
+    """Alg. 1, steps 5-7 for one block (the enlarged block E on `side` of the
+    plan's superblock): density matrix, its eigenpairs, the m kept states, and
+    the operators in the kept basis."""
     import torch
 
     from . import eigh_blocks, renormalize, truncate
 
     dev = psi.device
-    rl, _ = plan.density(psi, right=False)
-    lo, _ = plan.density_layout()
+    left = side == "left"
+    rl, rr = plan.density(psi, left=left, right=not left)
+    lo_l, lo_r = plan.density_layout()
+    rl, lo = (rl, lo_l) if left else (rr, lo_r)
     dims = np.sqrt(np.diff(lo)).round().astype(np.int64)
     w, u, info = eigh_blocks(rl, dims, return_info=True)
     bad = info.cpu().numpy() < 0
@@ -203,7 +211,7 @@ def renormalize_block(E: Block, plan, psi, m: int) -> Tuple[Block, float, int]:
         raise N.DmrgError(N.E_UNSUPPORTED, f"eigen-decomposition failed for blocks {np.flatnonzero(bad).tolist()}")
     keep, disc = truncate(w, dims, m)
     lay = plan.layout()
-    pair_of = {int(s): k for k, s in enumerate(lay["pair_left"])}
+    pair_of = {int(s): k for k, s in enumerate(lay["pair_left" if left else "pair_right"])}
     kept_secs = [s for s in range(len(E.dims)) if s in pair_of and keep[pair_of[s]] > 0]
     new_index = {s: i for i, s in enumerate(kept_secs)}
     new_dims = np.array([int(keep[pair_of[s]]) for s in kept_secs], np.int64)
@@ -230,6 +238,77 @@ def renormalize_block(E: Block, plan, psi, m: int) -> Tuple[Block, float, int]:
     return newB, float(disc[0]), int(new_dims.sum())
 
 
+def _solve(plan, rng, tol, kmax, kmin):
+    """Lowest eigenstate of the superblock (Alg. 1, step 3).  In a tiny
+    superblock the preconditioned correction can fall inside the subspace
+    before convergence (breakdown): then start again from another vector."""
+    import torch
+
+    for attempt in range(4):
+        x0 = torch.from_numpy(rng.standard_normal(plan.n)).to(plan.device)
+        psi, energy, infos, st = plan.davidson(x0, tol=tol, kmax=min(kmax, max(2, plan.n)),
+                                               kmin=min(kmin, max(1, min(kmax, plan.n) - 1)))
+        if infos[0]["converged"]:
+            return psi, float(energy[0]), int(infos[0]["iterations"])
+    N.check(st)
+    raise N.DmrgError(N.W_NOT_CONVERGED, "Davidson did not converge")
+
+
+def run_finite(nsites: int, m: int, sweeps: int = 2, J: float = 1.0, delta: float = 1.0, tol: float = 1e-10,
+               device=None, seed: int = 0, kmax: int = 32, kmin: int = 8) -> Tuple[List[StepResult], List[float]]:
+    """The infinite-lattice growth to `nsites`, then `sweeps` finite-lattice
+    sweeps at fixed size (the optional second phase of Sec. "The DMRG
+    algorithm"): the centre moves to the right end (left blocks renormalized
+    from rho_L), back to the left end (right blocks from rho_R) and to the
+    middle.  Returns the growth steps and the energy at the middle after each
+    sweep."""
+    from . import Plan
+
+    import torch
+
+    if nsites < 6 or nsites % 2:
+        raise ValueError("nsites must be even and >= 6")
+    dev = torch.device("cuda", 0) if device is None else torch.device(device)
+    rng = np.random.default_rng(seed)
+    L: Dict[int, Block] = {1: site_block(dev)}
+    R: Dict[int, Block] = {1: L[1]}
+    grow: List[StepResult] = []
+    B = L[1]
+    while 2 * (B.nsites + 1) <= nsites:
+        E = enlarge(B, J, delta)
+        plan = Plan(superblock(E, J, delta), device=dev, tiles=None)
+        psi, energy, its = _solve(plan, rng, tol, kmax, kmin)
+        B, disc, kept = renormalize_block(E, plan, psi, m)
+        L[B.nsites] = R[B.nsites] = B  # mirror images of each other
+        grow.append(StepResult(2 * E.nsites, energy, disc, kept, its))
+        plan.close()
+
+    def step(l, side):
+        r = nsites - 2 - l
+        EL, ER = enlarge(L[l], J, delta), enlarge(R[r], J, delta)
+        plan = Plan(superblock(EL, J, delta, ER), device=dev, tiles=None)
+        psi, energy, _ = _solve(plan, rng, tol, kmax, kmin)
+        if side == "left":
+            L[l + 1], _, _ = renormalize_block(EL, plan, psi, m, "left")
+        else:
+            R[r + 1], _, _ = renormalize_block(ER, plan, psi, m, "right")
+        plan.close()
+        return energy
+
+    mid = []
+    half = nsites // 2 - 1
+    for _ in range(sweeps):
+        for l in range(half, nsites - 3):  # centre to the right end
+            step(l, "left")
+        for r in range(1, nsites - 3):  # to the left end
+            step(nsites - 2 - r, "right")
+        e = None
+        for l in range(1, half + 1):  # back to the middle (energy at l = r)
+            e = step(l, "left")
+        mid.append(e)
+    return grow, mid
+
+
 def run(nsites: int, m: int, J: float = 1.0, delta: float = 1.0, tol: float = 1e-10, device=None,
         seed: int = 0, kmax: int = 32, kmin: int = 8) -> List[StepResult]:
     """Grow the chain from 4 to `nsites` sites (even), keeping m states per
@@ -247,18 +326,8 @@ def run(nsites: int, m: int, J: float = 1.0, delta: float = 1.0, tol: float = 1e
     while 2 * (B.nsites + 1) <= nsites:
         E = enlarge(B, J, delta)
         plan = Plan(superblock(E, J, delta), device=dev, tiles=None)
-        # in a tiny superblock the preconditioned correction can fall inside the
-        # subspace before convergence (breakdown): start again from another vector
-        for attempt in range(4):
-            x0 = torch.from_numpy(rng.standard_normal(plan.n)).to(dev)
-            psi, energy, infos, st = plan.davidson(x0, tol=tol, kmax=min(kmax, max(2, plan.n)),
-                                                   kmin=min(kmin, max(1, min(kmax, plan.n) - 1)))
-            if infos[0]["converged"]:
-                break
-        else:
-            N.check(st)
-            raise N.DmrgError(N.W_NOT_CONVERGED, "Davidson did not converge")
+        psi, energy, its = _solve(plan, rng, tol, kmax, kmin)
         B, disc, kept = renormalize_block(E, plan, psi, m)
-        out.append(StepResult(2 * E.nsites, float(energy[0]), disc, kept, int(infos[0]["iterations"])))
+        out.append(StepResult(2 * E.nsites, energy, disc, kept, its))
         plan.close()
     return out

@@ -105,3 +105,26 @@ def test_infinite_dmrg_energy_scales_with_coupling():
     for x, y in zip(a, b):
         assert y.energy == pytest.approx(2.0 * x.energy, abs=1e-8)
         assert y.discarded == pytest.approx(x.discarded, abs=1e-9)
+
+
+def test_finite_sweeps_exact_without_truncation():
+    """Finite-lattice sweeps (right blocks renormalized from rho_R) keep the
+    exact ground energy when nothing is truncated."""
+    grow, mid = _inf().run_finite(10, m=64, sweeps=1, tol=1e-11)
+    assert grow[-1].nsites == 10
+    exact = models.chain_ground_energy(10)
+    assert grow[-1].energy == pytest.approx(exact, abs=1e-9)
+    assert mid[-1] == pytest.approx(exact, abs=1e-9)
+
+
+def test_finite_sweeps_improve_the_truncated_xx_chain():
+    """With truncation the sweeps lower the energy towards the exact
+    free-fermion value and never below it (variational); consecutive sweeps
+    agree to the truncation level (with m fixed they need not decrease)."""
+    grow, mid = _inf().run_finite(20, m=10, sweeps=2, delta=0.0, tol=1e-11)
+    exact = models.xx_chain_energy(20)
+    e_inf = grow[-1].energy
+    assert grow[-1].nsites == 20
+    assert all(e >= exact - 1e-9 for e in [e_inf] + mid)
+    assert abs(mid[-1] - exact) < abs(e_inf - exact)
+    assert abs(mid[-1] - mid[0]) < 1e-5
