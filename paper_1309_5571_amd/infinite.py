@@ -1,5 +1,6 @@
-"""Infinite-lattice DMRG for the open spin-1/2 Heisenberg chain (Alg. 1), every
-numerical step on the device through the C ABI.
+"""Infinite-lattice DMRG (Alg. 1) and finite-lattice sweeps for the open
+spin-1/2 XXZ (Heisenberg) chain, every numerical step on the device through
+the C ABI.
 
 One iteration: enlarge the block by one site (dmrg_place_blocks), form the
 superblock of two mirror-image enlarged blocks in the S^z = 0 sector, find its
@@ -7,7 +8,9 @@ lowest eigenstate (dmrg_davidson), build the left block's density matrix
 (dmrg_density), diagonalize it sector by sector (dmrg_eigh_blocks), keep the m
 states of largest weight (dmrg_truncate) and take the block's operators to
 the kept basis (dmrg_renormalize).  The chain grows by two sites per
-iteration (Sec. "The DMRG algorithm").
+iteration (Sec. "The DMRG algorithm").  `run_finite` continues at fixed size
+with sweeps of the centre, renormalizing the right block from the right-side
+density matrix on the way back.
 
 Blocks carry four operators in dense sector form: the block Hamiltonian H and
 the spin operators S+, S-, Sz of the site at the block's inner edge.  Labels
