@@ -39,7 +39,7 @@ def parse():
     ap.add_argument("--quick", action="store_true", help="skip the projection and FP64 comparison timings")
     ap.add_argument("--workload", default="hubbard_m2048",
                     choices=["hubbard_m2048", "heisenberg_m1024", "j1j2_m1024", "batched_64", "gemv", "pmc",
-                             "infinite_heisenberg"],
+                             "infinite_heisenberg", "block_projection"],
                     help="hubbard_m2048 is the headline line; the others time the projection and the "
                          "mixed-precision solve of the other synthetic workloads")
     return ap.parse_args()
@@ -160,6 +160,28 @@ def renorm_stats(plan, psi, torch, reps=10):
             "groups": int(groups.size), "m_keep": int(ms.sum()),
             "eigh_us": float(np.median(te)), "truncate_us": float(np.median(tt)),
             "discarded": float(disc.sum().cpu())}
+
+
+def block_projection(p, reps, sizes=(1, 2, 4, 8, 16, 32)):
+    """b vectors projected in one launch (a plan of b copies of the superblock,
+    whose output tiles share one persistent grid): the throughput a block
+    Davidson would see on a latency-bound workload.  FP64, HIP events on the
+    launch stream, average over `reps` back-to-back calls."""
+    import numpy as np
+    import torch
+
+    import paper_1309_5571_amd as dm
+
+    rows = []
+    for b in sizes:
+        plan = dm.Plan([p] * b)
+        x = torch.from_numpy(np.random.default_rng(b).standard_normal(plan.n)).cuda()
+        y = torch.empty_like(x)
+        t = timed_projection(plan, x, y, "f64", reps, torch)
+        rows.append({"vectors": b, "us_per_call": t * 1e6, "us_per_vector": t * 1e6 / b,
+                     "tflops": plan.flop / t * 1e-12, "GBs_algorithmic": plan.bytes / t * 1e-9})
+        plan.close()
+    return {"workload": "block_projection_hubbard_m2048", "rows": rows}
 
 
 def infinite_workload(nsites=100, m=32, reps=3):
@@ -331,6 +353,9 @@ def main():
         return
     if args.workload == "infinite_heisenberg":
         print(json.dumps(infinite_workload()))
+        return
+    if args.workload == "block_projection":
+        print(json.dumps(block_projection(gen.config(3), args.proj_reps)))
         return
     cfg = {"hubbard_m2048": 3, "heisenberg_m1024": 2, "j1j2_m1024": 5, "batched_64": 4}[args.workload]
     p = gen.config(cfg)
