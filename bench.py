@@ -36,6 +36,9 @@ def parse():
     ap.add_argument("--prec", default="f32", choices=["f32", "bf16"], help="reduced precision of phase 1")
     ap.add_argument("--proj-reps", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-renorm", action="store_true",
+                    help="skip the eigen-decomposition / selection timing and the infinite-lattice run "
+                         "reported beside the solve")
     ap.add_argument("--quick", action="store_true", help="skip the projection and FP64 comparison timings")
     ap.add_argument("--workload", default="hubbard_m2048",
                     choices=["hubbard_m2048", "heisenberg_m1024", "j1j2_m1024", "batched_64", "gemv", "pmc",
@@ -424,9 +427,10 @@ def main():
         log(f"projection per call: {stats}")
         extra["density"] = density_stats(plan, psi, args.proj_reps, torch)
         log(f"density matrices: {extra['density']}")
-        extra["renormalization"] = renorm_stats(plan, psi, torch)
-        log(f"eigen-decomposition and selection: {extra['renormalization']}")
-        if cfg == 3:  # the whole infinite-lattice iteration, Heisenberg chain to 100 sites
+        if not args.no_renorm:
+            extra["renormalization"] = renorm_stats(plan, psi, torch)
+            log(f"eigen-decomposition and selection: {extra['renormalization']}")
+        if cfg == 3 and not args.no_renorm:  # the whole infinite-lattice iteration, Heisenberg chain to 100 sites
             extra["infinite_heisenberg"] = infinite_workload(reps=1)
             log(f"infinite-lattice DMRG: {extra['infinite_heisenberg']}")
         extra["mixed_vs_fp64_time_ratio"] = (dt / args.steps * 1e3) / extra["fp64_solve"]["ms_per_solve"]
