@@ -337,7 +337,7 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: there is no multi-GPU path "
               "(the path is not sharded across GPUs); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import numpy as np
