@@ -2,11 +2,13 @@
 
 Test infrastructure (see the package docstring).
 
-Alg. 3 fixes the steps of one iteration: W(:,i) = H V(:,i); B(:,i) = V^T
-W(:,i); the smallest eigenpair (lambda, y) of B; x = V y; r = W y - lambda x;
-stop when ||r|| ~ 0; otherwise correct r, orthogonalize it against V
-(s = V^T r, r = r - V s), normalize and append it.  The paper leaves several
-points open; this oracle takes these readings (the HIP solver takes the same):
+Davidson's method as the paper states it (Alg. 3): the basis V grows by one
+vector per iteration; its projections W = H V and the Rayleigh matrix
+B = V^T W give the smallest Ritz pair (lambda, y), the Ritz vector x = V y and
+the residual r = W y - lambda x; the run stops once r is small, otherwise the
+corrected residual is orthogonalized against V, normalized and appended.  The
+paper leaves several points open; this oracle takes these readings (the HIP
+solver takes the same):
 
 * "correct r": shifted diagonal (Davidson) preconditioner
   t_i = r_i / (D_ii - sigma) with D = diag(H_Q) and sigma = min(lambda, min_i D_ii),
@@ -26,8 +28,9 @@ points open; this oracle takes these readings (the HIP solver takes the same):
   B <- diag(theta), before the correction vector is appended;
 * the small eigenproblem is solved by LAPACK (``numpy.linalg.eigh``).
 
-An "iteration" is one pass through lines 3-7 (one Ritz evaluation); the number
-of projections is one more than the number of appended vectors.
+An "iteration" is one Ritz evaluation (Rayleigh matrix column, small
+eigenproblem, Ritz vector, residual, stop test); the number of projections is
+one more than the number of appended vectors.
 """
 from __future__ import annotations
 
@@ -70,19 +73,19 @@ def davidson(matvec: Callable[[np.ndarray], np.ndarray], D: np.ndarray, x0: np.n
     restarts = 0
     dmin = float(D.min())
     for it in range(1, max_iter + 1):
-        # line 4: smallest eigenpair of the Rayleigh matrix
+        # Rayleigh-Ritz: smallest eigenpair of B restricted to the current basis
         theta, Y = np.linalg.eigh(Bm[:i, :i])
         lam, y = theta[0], Y[:, 0]
-        # lines 5-6: Ritz vector and residual
+        # Ritz vector and its residual
         x = V[:, :i] @ y
         r = W[:, :i] @ y - lam * x
         rn = float(np.linalg.norm(r))
         hist.append(rn)
-        if rn <= tol:  # line 7
+        if rn <= tol:  # converged
             return DavidsonResult(lam, x, it, nproj, rn, True, restarts=restarts, history=hist)
         if i == n:
             return DavidsonResult(lam, x, it, nproj, rn, False, restarts=restarts, history=hist)
-        # line 10: correction
+        # preconditioned correction of the residual
         den = D - min(lam, dmin)
         small = np.abs(den) < floor
         den[small] = np.where(den[small] < 0, -floor, floor)
@@ -96,7 +99,7 @@ def davidson(matvec: Callable[[np.ndarray], np.ndarray], D: np.ndarray, x0: np.n
             Bm[:keep, :keep] = np.diag(theta[:keep])
             i = keep
             restarts += 1
-        # lines 12-14: orthonormalize against V and append
+        # orthonormalize the correction against V (CGS, DGKS repeat) and append it
         n0 = np.linalg.norm(t)
         s = V[:, :i].T @ t
         t = t - V[:, :i] @ s
@@ -109,7 +112,7 @@ def davidson(matvec: Callable[[np.ndarray], np.ndarray], D: np.ndarray, x0: np.n
             return DavidsonResult(lam, x, it, nproj, rn, False, breakdown=True,
                                   restarts=restarts, history=hist)
         V[:, i] = t / n1
-        # line 2 of the next iteration: project the new vector, extend B (line 3)
+        # project the new basis vector and extend B by its column
         W[:, i] = matvec(V[:, i])
         nproj += 1
         col = V[:, :i + 1].T @ W[:, i]

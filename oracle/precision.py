@@ -104,6 +104,55 @@ def project_magnitude(prob, psi, coef=None) -> np.ndarray:
     return y
 
 
+UNIT = {"fp32": 2.0 ** -24, "bf16": 2.0 ** -8}
+
+
+def project_envelope(prob, psi, prec: str, coef=None) -> np.ndarray:
+    """Elementwise bound on |device - project_emulated| for one output entry.
+
+    The emulation rounds exactly the operands the device rounds, so what is
+    left are the device's FP32 sums and, for a record with two dense factors,
+    the rounding of its intermediate.  Per record, with mag_rec = |c| |A| |X| |B|^T
+    (this record's share of :func:`project_magnitude`):
+
+    * every FP32 sum of length K (FP32/BF16 MFMA accumulate in FP32) is off by
+      at most (K + 2) 2^-24 of the sum of its absolute terms (standard
+      floating-point summation bound, two guard terms for the product rounding
+      inside the matrix instruction);
+    * the intermediate of a two-sided record is rounded to the operand format
+      (unit u_T); the device may form it as (A X) or as (X B^T), whichever is
+      cheaper, while the emulation always forms (A X): both are within
+      u_T mag_rec of the product of the rounded operands, hence 2 u_T;
+    * the per-record sums, coefficients and diagonal terms are FP64 (their
+      errors are ~1e-16 relative and covered by the safety factor).
+
+    The bound is sum_rec gamma_rec mag_rec with gamma = (K_A + K_B + 4) 2^-24
+    + 2 u_T [two-sided], times 1.25 for the (1 + u)^3 growth of the rounded
+    operands' magnitudes over the unrounded ones used in mag_rec.
+    """
+    coef = prob.coef if coef is None else np.asarray(coef, dtype=np.float64)
+    recs, table, n = projection.records(prob)
+    psi = np.abs(np.asarray(psi, dtype=np.float64))
+    u32, uT = 2.0 ** -24, UNIT[prec]
+    env = np.zeros(n)
+    for k, pin, pout, pa, pb in recs:
+        o, dL, dR = table[pin]
+        X = psi[o:o + dL * dR].reshape(dL, dR)
+        o2, dL2, dR2 = table[pout]
+        da = pa is not None and pa.ndim == 2
+        db = pb is not None and pb.ndim == 2
+        if not da and not db:
+            continue  # FP64 diagonal term
+        pa_ = None if pa is None else np.abs(pa)
+        pb_ = None if pb is None else np.abs(pb)
+        mag = abs(coef[k]) * projection._right_t(pb_, projection._left(pa_, X))
+        gamma = ((dL if da else 0) + (dR if db else 0) + (4 if da and db else 2)) * u32
+        if da and db:
+            gamma += 2.0 * uT
+        env[o2:o2 + dL2 * dR2] += gamma * mag.reshape(-1)
+    return 1.25 * env
+
+
 def max_contraction(prob) -> int:
     """Longest inner dimension any output entry accumulates over (sum over its
     records of the contraction lengths), for envelope sizing."""
@@ -116,5 +165,5 @@ def max_contraction(prob) -> int:
     return max(acc.values()) if acc else 0
 
 
-__all__ = ["round_fp32", "round_bf16", "project_emulated", "project_magnitude",
+__all__ = ["round_fp32", "round_bf16", "project_emulated", "project_magnitude", "project_envelope",
            "max_contraction", "sectors"]

@@ -1,9 +1,13 @@
 """Writes the stored expected values under tests/golden/ using only ``oracle``.
 
 Run from the repository root:  python tests/golden/make_golden.py
-Each value is a full-chain exact diagonalization (LAPACK) of a Hamiltonian
-built straight from the paper's Eq. 1-8 by ``oracle.models``; none comes from
-the HIP library.
+exact_energies.json: each value is a full-chain exact diagonalization
+(LAPACK) of a Hamiltonian built straight from the paper's Eq. 1-8 by
+``oracle.models``.  arpack_energies.json: the ground energies of the
+synthetic superblock workloads (Heisenberg m=1024, Hubbard m=2048, J1-J2
+m=1024) by ARPACK's implicitly restarted Lanczos (scipy ``eigsh``) with the
+oracle's sector-form projection (Eq. 11) as the only access to H.  None comes
+from the HIP library.
 """
 import json
 import os
@@ -14,7 +18,8 @@ import numpy as np
 ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 sys.path.insert(0, ROOT)
 
-from oracle import models  # noqa: E402
+import gen  # noqa: E402
+from oracle import davidson, models  # noqa: E402
 
 
 def sector_min(H, labels, want):
@@ -42,6 +47,14 @@ def main():
         json.dump({"source": "oracle.models + numpy.linalg.eigvalsh (LAPACK), FP64",
                    "energies": out}, f, indent=1, sort_keys=True)
     print(json.dumps(out, indent=1))
+    arp = {}
+    for cfg in (2, 3, 5):
+        arp[gen.CONFIG_NAMES[cfg]] = davidson.ground_state_arpack(gen.config(cfg), tol=1e-15)[0]
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "arpack_energies.json")
+    with open(path, "w") as f:
+        json.dump({"source": "gen.config + oracle.projection.project_sectors + scipy eigsh (ARPACK, "
+                             "which='SA', tol=1e-15, ncv=40), FP64", "energies": arp}, f, indent=1, sort_keys=True)
+    print(json.dumps(arp, indent=1))
 
 
 if __name__ == "__main__":

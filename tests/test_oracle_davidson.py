@@ -9,6 +9,7 @@ import gen
 from oracle import davidson, models, projection, sectors
 
 GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "exact_energies.json")))["energies"]
+ARPACK = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "arpack_energies.json")))["energies"]
 
 
 def _n(p):
@@ -97,6 +98,21 @@ def test_hubbard_m2048_matches_arpack():
     E, _ = davidson.ground_state_arpack(p, tol=1e-15)
     assert r.converged
     assert abs(r.energy - E) <= 1e-10
+    assert abs(ARPACK[gen.CONFIG_NAMES[3]] - E) <= 1e-10
+
+
+@pytest.mark.parametrize("cfg", [2, 5])
+def test_synthetic_m1024_matches_arpack(cfg):
+    """Heisenberg m=1024 and J1-J2 m=1024: the oracle's Davidson vs ARPACK
+    Lanczos run live on the oracle projection (no shared solver code), and
+    both vs the stored ARPACK energy the GPU tests compare with."""
+    p = gen.config(cfg)
+    r = davidson.ground_state_davidson(p, gen.start_vector(_n(p), 7), tol=1e-10)
+    E, x = davidson.ground_state_arpack(p, tol=1e-15)
+    assert r.converged
+    assert abs(r.energy - E) <= 1e-10
+    assert abs(abs(r.x @ x) - 1.0) <= 1e-10
+    assert abs(ARPACK[gen.CONFIG_NAMES[cfg]] - E) <= 1e-10
 
 
 def test_hellmann_feynman_two_site():

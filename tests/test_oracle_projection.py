@@ -237,3 +237,100 @@ def test_magnitude_bounds_result():
     n = sectors.pair_table(p.left, p.right, p.target)[1]
     psi = np.random.default_rng(3).standard_normal(n)
     assert np.all(np.abs(projection.project_sectors(p, psi)) <= precision.project_magnitude(p, psi) * (1 + 1e-12))
+
+
+def _float32_projection(p, psi, prec, order_flip):
+    """Eq. 11 evaluated with FP32 sums (NumPy float32 matmul), the operands
+    rounded like the device's (FP64 diagonal split, rounded input, rounded
+    intermediate), and the intermediate formed as X B^T instead of A X for
+    every record where order_flip(i) is true: a second, independent reduced-
+    precision evaluation for pinning the elementwise envelope."""
+    rnd = precision.ROUND[prec]
+    f32 = lambda a: rnd(a).astype(np.float32)
+    recs, table, n = projection.records(p)
+    y = np.zeros(n)
+    for i, (k, pin, pout, pa, pb) in enumerate(recs):
+        o, dL, dR = table[pin]
+        X = np.asarray(psi[o:o + dL * dR], dtype=np.float64).reshape(dL, dR)
+        o2, dL2, dR2 = table[pout]
+        da = pa is not None and pa.ndim == 2
+        db = pb is not None and pb.ndim == 2
+        if not da and not db:
+            Z = projection._right_t(pb, projection._left(pa, X))
+        elif da and not db:
+            Xs = projection._right_t(pb, X)
+            R, dpart = pa, 0.0
+            if pin[0] == pout[0]:
+                R = pa - np.diag(np.diag(pa))
+                dpart = np.diag(pa)[:, None] * Xs
+            Z = dpart + (f32(R) @ f32(Xs)).astype(np.float64)
+        elif db and not da:
+            Xs = projection._left(pa, X)
+            R, dpart = pb, 0.0
+            if pin[1] == pout[1]:
+                R = pb - np.diag(np.diag(pb))
+                dpart = Xs * np.diag(pb)[None, :]
+            Z = dpart + (f32(Xs) @ f32(R).T).astype(np.float64)
+        elif order_flip(i):
+            T = f32((f32(X) @ f32(pb).T).astype(np.float64))
+            Z = (f32(pa) @ T).astype(np.float64)
+        else:
+            T = f32((f32(pa) @ f32(X)).astype(np.float64))
+            Z = (T @ f32(pb).T).astype(np.float64)
+        y[o2:o2 + dL2 * dR2] += (p.coef[k] * Z).reshape(-1)
+    return y
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("seed", range(6))
+def test_envelope_holds_for_an_independent_fp32_evaluation(prec, seed):
+    """The elementwise envelope contains an FP32-accumulated evaluation with
+    either order of the two-sided products (what the device may do)."""
+    p = gen.random_problem(40 + seed, rank=1 + seed % 2, dmax=40)
+    n = sectors.pair_table(p.left, p.right, p.target)[1]
+    psi = np.random.default_rng(seed).standard_normal(n)
+    emul = precision.project_emulated(p, psi, prec)
+    env = precision.project_envelope(p, psi, prec)
+    for flip in (lambda i: False, lambda i: True, lambda i: i % 2 == 1):
+        y = _float32_projection(p, psi, prec, flip)
+        assert np.all(np.abs(y - emul) <= env), prec
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_envelope_catches_a_missing_or_transposed_contribution(prec):
+    """Tight enough to fail on a plausible device bug.  The envelope is an
+    elementwise fraction of the magnitude (about 1e-5 for FP32, 1 % for BF16:
+    the operand rounding itself), so in FP32 any single record left out, or
+    one block applied transposed, breaks the bound somewhere; in BF16 every
+    record that carries more than 1.2 % of an entry's magnitude does."""
+    p = gen.random_problem(7, rank=1, dmax=9, square=True)
+    n = sectors.pair_table(p.left, p.right, p.target)[1]
+    psi = np.random.default_rng(1).standard_normal(n)
+    emul = precision.project_emulated(p, psi, prec)
+    env = precision.project_envelope(p, psi, prec)
+    mag = precision.project_magnitude(p, psi)
+    K = precision.max_contraction(p)
+    width = 1.25 * (K * 2.0 ** -24 + 2 * precision.UNIT[prec])
+    assert np.all(env <= width * mag)
+    recs, table, _ = projection.records(p)
+    checked = 0
+    for k, pin, pout, pa, pb in recs:
+        o, dL, dR = table[pin]
+        X = psi[o:o + dL * dR].reshape(dL, dR)
+        o2, dL2, dR2 = table[pout]
+        Z = p.coef[k] * projection._right_t(pb, projection._left(pa, X))
+        if prec == "fp32" and np.abs(Z).max() < 1e-6:
+            continue
+        if prec == "bf16" and not np.any(np.abs(Z).reshape(-1) > 1.2 * width * mag[o2:o2 + dL2 * dR2]):
+            continue
+        bad = emul.copy()
+        bad[o2:o2 + dL2 * dR2] -= Z.reshape(-1)  # the record is missing
+        assert np.any(np.abs(bad - emul) > env)
+        if pa is not None and pa.ndim == 2 and pa.shape[0] == pa.shape[1] and not np.allclose(pa, pa.T):
+            Zt = p.coef[k] * projection._right_t(pb, pa.T @ X)
+            bad = emul.copy()
+            bad[o2:o2 + dL2 * dR2] += (Zt - Z).reshape(-1)  # A applied transposed
+            if prec == "fp32":
+                assert np.any(np.abs(bad - emul) > env)
+        checked += 1
+    assert checked >= 5
