@@ -212,7 +212,8 @@ def infinite_workload(nsites=100, m=32, reps=3):
     return {"workload": f"infinite_heisenberg_N{nsites}_m{m}", "steps": len(res), "seconds": t,
             "ms_per_step": t / len(res) * 1e3, "energy": e[-1], "energy_per_site": per_site,
             "hulthen": 0.25 - math.log(2.0), "max_discarded": max(r.discarded for r in res),
-            "davidson_iterations": sum(r.iterations for r in res)}
+            "davidson_iterations": sum(r.iterations for r in res),
+            "davidson_retries": sum(r.retries for r in res)}
 
 
 def cpu_baseline(p, x0):

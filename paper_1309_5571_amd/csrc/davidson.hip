@@ -32,6 +32,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <tuple>
 #include <vector>
 
@@ -109,6 +110,11 @@ struct DavidsonWork {
     // max_iter, tol bits, floor bits
     std::map<std::vector<uint64_t>, hipGraphExec_t> graphs;
     std::vector<void *> owned;
+    // set while a solve runs and cleared when every member ended with finite
+    // data: a solve that stopped early, broke down or met a non-finite iterate
+    // leaves the workspace dirty, and the next solve clears it first
+    bool dirty = false;
+    size_t rowb = 0;  // bytes of one partial-row column set per chunk / tile row
 };
 
 // ------------------------------------------------------------------ helpers
@@ -1225,9 +1231,29 @@ static void set_kb(int ncols, K &&f) {
         f(std::integral_constant<int, KM>{});
 }
 
+// Subspace, work vectors and partial rows to zero (outside any captured
+// graph): a subspace that fills the whole space (n <= kmax) reaches columns
+// and rows no iteration has written yet, where a stale value (a NaN left by a
+// failed solve) would survive a zero weight.
+static dmrg_status work_zero(const dmrg_plan *plan, DavidsonWork *w, hipStream_t s) {
+    const DavArgs &A = w->a;
+    const size_t n = (size_t)plan->n, kp = (size_t)w->kmax + 1;
+    DMRG_HIP(hipMemsetAsync(A.V, 0, kp * n * 8, s));
+    DMRG_HIP(hipMemsetAsync(A.W, 0, kp * n * 8, s));
+    DMRG_HIP(hipMemsetAsync(A.T, 0, n * 8, s));
+    DMRG_HIP(hipMemsetAsync((void *)A.X0, 0, n * 8, s));
+    DMRG_HIP(hipMemsetAsync(A.pa, 0, (size_t)A.nchunk * w->rowb, s));
+    DMRG_HIP(hipMemsetAsync(A.pb, 0, (size_t)A.nchunk * w->rowb, s));
+    DMRG_HIP(hipMemsetAsync(A.pc, 0, (size_t)A.nchunk * w->rowb, s));
+    DMRG_HIP(hipMemsetAsync(A.ptile, 0, (size_t)A.tile_ld * w->rowb, s));
+    DMRG_HIP(hipStreamSynchronize(s));
+    w->dirty = false;
+    return DMRG_OK;
+}
+
 static dmrg_status work_alloc(dmrg_plan *plan, int kmax, int kmin, hipStream_t s) {
     DavidsonWork *w = plan->dav;
-    if (w && w->kmax == kmax && w->kmin == kmin) return DMRG_OK;
+    if (w && w->kmax == kmax && w->kmin == kmin) return w->dirty ? work_zero(plan, w, s) : DMRG_OK;
     davidson_free(plan);
     w = new DavidsonWork();
     plan->dav = w;
@@ -1269,6 +1295,7 @@ static dmrg_status work_alloc(dmrg_plan *plan, int kmax, int kmin, hipStream_t s
     DMRG_TRY(alloc((void **)&A.coef, std::max(plan->nterm_total, 1) * 8));
     // partial rows: one per chunk (three sets), one per output tile (Rayleigh rows)
     const size_t rowb = (KM + 2) * 8;
+    w->rowb = rowb;
     const int tiles = std::max({1, plan->fwd[0].stageB.ntask, plan->fwd[1].stageB.ntask});
     A.tile_ld = tiles;
     DMRG_TRY(alloc((void **)&A.pa, (size_t)A.nchunk * rowb));
@@ -1299,19 +1326,7 @@ static dmrg_status work_alloc(dmrg_plan *plan, int kmax, int kmin, hipStream_t s
     DMRG_HIP(hipMemsetAsync(A.st, 0, plan->nprob * sizeof(DavState), s));
     DMRG_HIP(hipMemsetAsync(A.active, 0, plan->nprob * 4, s));
     DMRG_HIP(hipMemsetAsync(B.active, 0, plan->nprob * 4, s));
-    // subspace, work vectors and partial rows start at zero (once per plan,
-    // outside any captured graph): a subspace that fills the whole space
-    // (n <= kmax) reaches columns and rows no iteration has written yet
-    DMRG_HIP(hipMemsetAsync(A.V, 0, (kmax + 1) * n * 8, s));
-    DMRG_HIP(hipMemsetAsync(A.W, 0, (kmax + 1) * n * 8, s));
-    DMRG_HIP(hipMemsetAsync(A.T, 0, n * 8, s));
-    DMRG_HIP(hipMemsetAsync((void *)A.X0, 0, n * 8, s));
-    DMRG_HIP(hipMemsetAsync(A.pa, 0, (size_t)A.nchunk * rowb, s));
-    DMRG_HIP(hipMemsetAsync(A.pb, 0, (size_t)A.nchunk * rowb, s));
-    DMRG_HIP(hipMemsetAsync(A.pc, 0, (size_t)A.nchunk * rowb, s));
-    DMRG_HIP(hipMemsetAsync(A.ptile, 0, (size_t)tiles * rowb, s));
-    DMRG_HIP(hipStreamSynchronize(s));
-    return DMRG_OK;
+    return work_zero(plan, w, s);
 }
 
 dmrg_status davidson_free(dmrg_plan *plan) {
@@ -1586,48 +1601,6 @@ static dmrg_status phase_run(dmrg_plan *plan, Phase &P, hipStream_t s, std::vect
 using namespace dmrg;
 
 template <int KB>
-__global__ __launch_bounds__(TPB) void k_gemv_t_part(int64_t n, int k, const double *__restrict__ V, int64_t ldv,
-                                                     const double *__restrict__ x, double *__restrict__ part) {
-    __shared__ double lds[4 * KB];
-    double acc[KB];
-#pragma unroll
-    for (int j = 0; j < KB; ++j) acc[j] = 0.0;
-    for (int64_t e = (int64_t)blockIdx.x * TPB + threadIdx.x; e < n; e += (int64_t)gridDim.x * TPB) {
-        const double xv = x[e];
-#pragma unroll
-        for (int j = 0; j < KB; ++j)
-            if (j < k) acc[j] += V[(int64_t)j * ldv + e] * xv;
-    }
-    block_reduce<KB>(acc, k, lds);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int j = 0; j < KB; ++j)
-            if (j < k) part[(size_t)blockIdx.x * KB + j] = acc[j];
-    }
-}
-
-// second stage: all k columns at once, thread t owns column t % k and every
-// (TPB / k)-th block from t / k; slots are then added in order (deterministic)
-template <int KB>
-__global__ __launch_bounds__(TPB) void k_gemv_t_final(int nblk, int k, const double *__restrict__ part,
-                                                      double *__restrict__ s) {
-    __shared__ double scratch[TPB];
-    const int t = threadIdx.x, per = TPB / k, j = t % k, slot = t / k;
-    double v = 0.0;
-    if (slot < per) {
-#pragma unroll 4
-        for (int b = slot; b < nblk; b += per) v += part[(size_t)b * KB + j];
-    }
-    scratch[t] = v;
-    __syncthreads();
-    if (t < k) {
-        double acc = 0.0;
-        for (int q = 0; q < per; ++q) acc += scratch[t + q * k];
-        s[t] = acc;
-    }
-}
-
-template <int KB>
 __global__ __launch_bounds__(TPB) void k_gemv_n(int64_t n, int k, const double *__restrict__ V, int64_t ldv,
                                                 const double *__restrict__ s, double beta, double *__restrict__ y) {
     double sv[KB];
@@ -1642,12 +1615,33 @@ __global__ __launch_bounds__(TPB) void k_gemv_n(int64_t n, int k, const double *
     }
 }
 
-// per-device partials of dmrg_gemv_t (kept until the process ends)
+// Partials of dmrg_gemv_t: one buffer per (device, stream), kept until the
+// process ends, so calls on different streams never share one.  The map is
+// guarded; a buffer only grows, after its own stream has drained.
 struct GemvScratch {
     double *p = nullptr;
     size_t bytes = 0;
 };
-static std::map<int, GemvScratch> g_gemv_scratch;
+static std::map<std::pair<int, hipStream_t>, GemvScratch> g_gemv_scratch;
+static std::mutex g_gemv_mutex;
+
+// Both stages of s = V^T x with the partials in part (>= nblk * 64 doubles).
+dmrg_status gemv_t_launch(int64_t n, int32_t k, const double *V, int64_t ldv, const double *x, double *s,
+                                 int nblk, double *part, hipStream_t st) {
+    auto go = [&](auto kb) {
+        constexpr int KB = decltype(kb)::value;
+        hipLaunchKernelGGL(k_gemv_t_part<KB>, dim3(nblk), dim3(TPB), 0, st, n, k, V, ldv, x, part);
+        hipLaunchKernelGGL(k_gemv_t_final<KB>, dim3(1), dim3(TPB), 0, st, nblk, k, (const double *)part, s);
+    };
+    if (k <= 16)
+        go(std::integral_constant<int, 16>{});
+    else if (k <= 32)
+        go(std::integral_constant<int, 32>{});
+    else
+        go(std::integral_constant<int, 64>{});
+    DMRG_HIP(hipGetLastError());
+    return DMRG_OK;
+}
 
 extern "C" {
 
@@ -1692,6 +1686,7 @@ dmrg_status dmrg_davidson(dmrg_plan *plan, const double *coef, const dmrg_davids
     int kmin = std::min(o.kmin, kmax - 1);
     DMRG_TRY(work_alloc(plan, kmax, kmin, s));
     DavidsonWork *w = plan->dav;
+    w->dirty = true;  // until every member is seen to end with finite data
     w->eig_solver = o.eig_solver;
     const DavArgs &A = w->a;
     hipLaunchKernelGGL(k_stage, dim3((unsigned)std::min<int64_t>((A.n + TPB - 1) / TPB, 2048)), dim3(TPB), 0, s, coef,
@@ -1758,6 +1753,11 @@ dmrg_status dmrg_davidson(dmrg_plan *plan, const double *coef, const dmrg_davids
         }
     }
     const bool both = two_phase && o.refine;
+    bool clean = true;
+    for (int p = 0; p < plan->nprob; ++p)
+        clean = clean && !hs[p].bad_start && !hs[p].breakdown && std::isfinite(hs[p].energy) &&
+                (!both || (!low[p].bad_start && !low[p].breakdown));
+    w->dirty = !clean;
     dmrg_status ret = DMRG_OK;
     for (int p = 0; p < plan->nprob; ++p) {
         const DavSummary &S = hs[p];
@@ -1788,35 +1788,27 @@ dmrg_status dmrg_gemv_t(int64_t n, int32_t k, const double *V, int64_t ldv, cons
     clear_error();
     if (n < 1 || k < 1 || k > 64 || ldv < n || !V || !x || !s)
         return set_error(DMRG_E_INVALID_ARG, "need n >= 1, 1 <= k <= 64, ldv >= n and non-null pointers");
-    int nblk = (int)std::min<int64_t>((n + TPB - 1) / TPB, 1024);
-    size_t need = (size_t)nblk * 64 * 8;
+    const int nblk = (int)std::min<int64_t>((n + TPB - 1) / TPB, GEMV_PART_BLOCKS);
+    const size_t need = (size_t)nblk * GEMV_PART_COLS * 8;
     int dev = 0;
     DMRG_HIP(hipGetDevice(&dev));
-    GemvScratch &gs = g_gemv_scratch[dev];
-    if (need > gs.bytes) {
-        // the stream may still use the old buffer: let it finish before freeing
-        DMRG_HIP(hipStreamSynchronize((hipStream_t)stream));
-        if (gs.p) (void)hipFree(gs.p);
-        gs.p = nullptr;
-        gs.bytes = 0;
-        DMRG_HIP(hipMalloc((void **)&gs.p, need));
-        gs.bytes = need;
-    }
-    double *part = gs.p;
     hipStream_t st = (hipStream_t)stream;
-    auto go = [&](auto kb) {
-        constexpr int KB = decltype(kb)::value;
-        hipLaunchKernelGGL(k_gemv_t_part<KB>, dim3(nblk), dim3(TPB), 0, st, n, k, V, ldv, x, part);
-        hipLaunchKernelGGL(k_gemv_t_final<KB>, dim3(1), dim3(TPB), 0, st, nblk, k, (const double *)part, s);
-    };
-    if (k <= 16)
-        go(std::integral_constant<int, 16>{});
-    else if (k <= 32)
-        go(std::integral_constant<int, 32>{});
-    else
-        go(std::integral_constant<int, 64>{});
-    DMRG_HIP(hipGetLastError());
-    return DMRG_OK;
+    double *part = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_gemv_mutex);
+        GemvScratch &gs = g_gemv_scratch[{dev, st}];
+        if (need > gs.bytes) {
+            // this stream may still read the old buffer: let it finish before freeing
+            DMRG_HIP(hipStreamSynchronize(st));
+            if (gs.p) (void)hipFree(gs.p);
+            gs.p = nullptr;
+            gs.bytes = 0;
+            DMRG_HIP(hipMalloc((void **)&gs.p, need));
+            gs.bytes = need;
+        }
+        part = gs.p;
+    }
+    return gemv_t_launch(n, k, V, ldv, x, s, nblk, part, st);
 }
 
 dmrg_status dmrg_gemv_n(int64_t n, int32_t k, const double *V, int64_t ldv, const double *s, double beta,

@@ -77,6 +77,7 @@ class StepResult:
     discarded: float
     kept: int
     iterations: int
+    retries: int = 0  # Davidson runs restarted from a new random vector after a breakdown
 
 
 def _p(t):
@@ -244,7 +245,8 @@ def renormalize_block(E: Block, plan, psi, m: int, side: str = "left") -> Tuple[
 def _solve(plan, rng, tol, kmax, kmin, use_graph=False):
     """Lowest eigenstate of the superblock (Alg. 1, step 3).  In a tiny
     superblock the preconditioned correction can fall inside the subspace
-    before convergence (breakdown): then start again from another vector.
+    before convergence (breakdown): then start again from another vector (at
+    most three times; the count is returned and reported per step).
     Every step builds a new plan that is solved once, so by default the
     iterations are launched directly rather than captured into graphs (the
     capture would not be replayed; measured 16 % faster over a 100-site run)."""
@@ -256,7 +258,7 @@ def _solve(plan, rng, tol, kmax, kmin, use_graph=False):
                                                kmin=min(kmin, max(1, min(kmax, plan.n) - 1)),
                                                use_graph=use_graph)
         if infos[0]["converged"]:
-            return psi, float(energy[0]), int(infos[0]["iterations"])
+            return psi, float(energy[0]), int(infos[0]["iterations"]), attempt
     N.check(st)
     raise N.DmrgError(N.W_NOT_CONVERGED, "Davidson did not converge")
 
@@ -284,17 +286,17 @@ def run_finite(nsites: int, m: int, sweeps: int = 2, J: float = 1.0, delta: floa
     while 2 * (B.nsites + 1) <= nsites:
         E = enlarge(B, J, delta)
         plan = Plan(superblock(E, J, delta), device=dev, tiles=None)
-        psi, energy, its = _solve(plan, rng, tol, kmax, kmin)
+        psi, energy, its, retries = _solve(plan, rng, tol, kmax, kmin)
         B, disc, kept = renormalize_block(E, plan, psi, m)
         L[B.nsites] = R[B.nsites] = B  # mirror images of each other
-        grow.append(StepResult(2 * E.nsites, energy, disc, kept, its))
+        grow.append(StepResult(2 * E.nsites, energy, disc, kept, its, retries))
         plan.close()
 
     def step(l, side):
         r = nsites - 2 - l
         EL, ER = enlarge(L[l], J, delta), enlarge(R[r], J, delta)
         plan = Plan(superblock(EL, J, delta, ER), device=dev, tiles=None)
-        psi, energy, _ = _solve(plan, rng, tol, kmax, kmin)
+        psi, energy, _, _ = _solve(plan, rng, tol, kmax, kmin)
         if side == "left":
             L[l + 1], _, _ = renormalize_block(EL, plan, psi, m, "left")
         else:
@@ -333,8 +335,8 @@ def run(nsites: int, m: int, J: float = 1.0, delta: float = 1.0, tol: float = 1e
     while 2 * (B.nsites + 1) <= nsites:
         E = enlarge(B, J, delta)
         plan = Plan(superblock(E, J, delta), device=dev, tiles=None)
-        psi, energy, its = _solve(plan, rng, tol, kmax, kmin)
+        psi, energy, its, retries = _solve(plan, rng, tol, kmax, kmin)
         B, disc, kept = renormalize_block(E, plan, psi, m)
-        out.append(StepResult(2 * E.nsites, energy, disc, kept, its))
+        out.append(StepResult(2 * E.nsites, energy, disc, kept, its, retries))
         plan.close()
     return out

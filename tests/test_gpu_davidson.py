@@ -15,6 +15,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "exact_energies.json")))["energies"]
+ARPACK = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "arpack_energies.json")))["energies"]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -245,3 +246,91 @@ def test_subspace_filling_the_space_is_reproducible_across_plans():
         del pl
     assert out[0] == pytest.approx(-1.6160254037844386, abs=1e-12)
     assert out[0] == out[1] == out[2]
+
+
+@pytest.mark.parametrize("cfg", [2, 3, 5])
+def test_synthetic_configs_match_arpack(cfg):
+    """GPU ground energies of the m=1024 / m=2048 workloads against ARPACK
+    Lanczos on the oracle projection (stored by tests/golden/make_golden.py),
+    FP64 and mixed precision with refinement."""
+    p = gen.config(cfg)
+    E_ref = ARPACK[gen.CONFIG_NAMES[cfg]]
+    x0 = gen.start_vector(_plan(p).n, 7)
+    for prec, tol in (("f64", 1e-10), ("f32", 1e-8)):
+        pl = _plan(p, prec=prec)
+        _, E, info, st = pl.davidson(_dev(x0), tol=1e-10, prec=prec)
+        assert st == 0 and info[0]["converged"] == 1, info
+        assert abs(E[0] - E_ref) <= tol, (prec, E[0], E_ref)
+        pl.close()
+
+
+def test_forced_restart_heisenberg_m1024_matches_oracle():
+    """kmax = 4, kmin = 2 on the Heisenberg m=1024 workload (it converges in 7
+    iterations, so only a small subspace forces restarts): the thick restart
+    runs twice at full size; the device and the oracle (same subspace
+    bounds, same start) agree on the energy and the vector, and both on ARPACK."""
+    p = gen.config(2)
+    pl = _plan(p)
+    x0 = gen.start_vector(pl.n, 7)
+    psi, E, info, st = pl.davidson(_dev(x0), tol=1e-10, kmax=4, kmin=2)
+    assert st == 0, info
+    assert info[0]["restarts"] >= 2, info
+    ref = odav.ground_state_davidson(p, x0, tol=1e-10, kmax=4, kmin=2)
+    assert ref.converged and ref.restarts >= 2
+    assert abs(E[0] - ref.energy) <= 1e-10
+    assert abs(E[0] - ARPACK[gen.CONFIG_NAMES[2]]) <= 1e-10
+    x = psi.cpu().numpy()
+    assert abs(abs(x @ ref.x) - 1.0) <= 1e-10
+    assert abs(info[0]["iterations"] - ref.iterations) <= 2
+
+
+def test_energy_gradient_j1j2_m1024():
+    """The J1-J2 m=1024 workload: dE/dJ1 and dE/dJ2 through the adjoint kernel
+    against central finite differences (h = 1e-5) of the GPU ground energy and
+    against Hellmann-Feynman <psi|dH/dJ|psi> from the oracle's ground state,
+    relative error <= 1e-7 each."""
+    import paper_1309_5571_amd as dm
+
+    p = gen.config(5)
+    pl = _plan(p)
+    basis = torch.from_numpy(p.meta["coef_basis"]).cuda()
+    J0 = np.array([1.0, 1.0, 0.5])
+    J = torch.tensor(J0, dtype=torch.float64, device="cuda", requires_grad=True)
+    x0 = _dev(gen.start_vector(pl.n, 2))
+    E = dm.ground_energy(pl, basis @ J, x0, tol=1e-11)
+    E.sum().backward()
+    g = J.grad.cpu().numpy()
+    h = 1e-5
+    for j in (1, 2):
+        e = np.zeros(3)
+        e[j] = h
+        Ep = pl.davidson(x0, coef=basis @ torch.from_numpy(J0 + e).cuda(), tol=1e-11)[1][0]
+        Em = pl.davidson(x0, coef=basis @ torch.from_numpy(J0 - e).cuda(), tol=1e-11)[1][0]
+        fd = (Ep - Em) / (2 * h)
+        assert abs(g[j] - fd) <= 1e-7 * abs(fd), (j, g[j], fd)
+    ref = odav.ground_state_davidson(p, gen.start_vector(pl.n, 2), tol=1e-11)
+    assert abs(ref.energy - ARPACK[gen.CONFIG_NAMES[5]]) <= 1e-10
+    dc = projection.coef_gradient(p, ref.x, ref.x)
+    gref = p.meta["coef_basis"].T @ dc
+    assert np.all(np.abs(g[1:] - gref[1:]) <= 1e-7 * np.abs(gref[1:])), (g, gref)
+
+
+def test_same_plan_recovers_after_a_non_finite_solve():
+    """A solve whose iterate turns non-finite (NaN coefficients) leaves its
+    NaNs in the plan's workspace; the next solve on the same plan clears it and
+    reaches the exact result (also with a subspace that fills the space)."""
+    import paper_1309_5571_amd as dm
+
+    for p, kw, E_ref in ((gen.heisenberg_exact(2, 2), dict(kmax=6, kmin=5), -1.6160254037844386),
+                         (gen.config(1), dict(kmax=32, kmin=8), GOLDEN["heisenberg_open_N10_Sz0"])):
+        pl = _plan(p)
+        x0 = _dev(gen.start_vector(pl.n, 3))
+        bad = torch.full((len(p.coef),), float("nan"), dtype=torch.float64, device="cuda")
+        with pytest.raises(dm.DmrgError) as e:
+            pl.davidson(x0, coef=bad, tol=1e-11, **kw)
+        assert e.value.status == -6  # non-finite iterate
+        psi, E, info, st = pl.davidson(x0, tol=1e-11, **kw)
+        assert st == 0 and info[0]["converged"] == 1
+        assert abs(E[0] - E_ref) <= 1e-10
+        assert np.all(np.isfinite(psi.cpu().numpy()))
+        pl.close()

@@ -229,3 +229,43 @@ def test_lowprec_random_structures(tiles):
             u = 2.0 ** -24 if prec == "f32" else 2.0 ** -8
             env = (K * 2.0 ** -24 + (4 * u if prec == "bf16" else 0.0)) * np.linalg.norm(mag)
             assert np.linalg.norm(y - emul) <= env + 1e-300, (seed, prec)
+
+
+def _elementwise_ok(y, p, psi, prec):
+    """|device - emulation| <= the per-entry envelope of oracle.precision (the
+    FP32 sums and the rounded intermediate of that entry's own records), plus
+    the FP64 rounding of the per-record and diagonal-term sums (a few units of
+    2^-53 of the entry's magnitude, which the envelope leaves out)."""
+    key = "fp32" if prec == "f32" else "bf16"
+    emul = precision.project_emulated(p, psi, key)
+    env = precision.project_envelope(p, psi, key) + 8 * 2.0 ** -53 * precision.project_magnitude(p, psi)
+    bad = np.abs(y - emul) > env
+    return int(bad.sum()), float(np.max(np.abs(y - emul) / np.maximum(env, 1e-300)))
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+@pytest.mark.parametrize("cfg", [2, 3, 5])
+def test_lowprec_projection_elementwise(cfg, prec):
+    """Every output entry of the FP32/BF16 projection lies inside its own
+    rounding envelope around the emulated oracle (no global norm)."""
+    p = gen.config(cfg)
+    pl = _plan(p, prec=prec)
+    psi = gen.start_vector(pl.n, 4)
+    y = pl.project_raw(_dev(psi), prec=prec).cpu().numpy()
+    nbad, worst = _elementwise_ok(y, p, psi, prec)
+    assert nbad == 0, (nbad, worst)
+
+
+@pytest.mark.parametrize("tiles", ["t16", "t32"])
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_lowprec_random_structures_elementwise(tiles, prec):
+    import paper_1309_5571_amd as dm
+
+    for seed in range(6):
+        p = gen.random_problem(seed, rank=1 + seed % 2, dmax=30)
+        pl = dm.Plan(p, prec=prec, tiles=TILES[tiles])
+        psi = np.random.default_rng(seed).standard_normal(pl.n)
+        y = pl.project_raw(_dev(psi), prec=prec).cpu().numpy()
+        nbad, worst = _elementwise_ok(y, p, psi, prec)
+        assert nbad == 0, (seed, nbad, worst)
+        pl.close()
