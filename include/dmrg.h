@@ -231,6 +231,18 @@ dmrg_status dmrg_gemv_t(int64_t n, int32_t k, const double *V, int64_t ldv, cons
 dmrg_status dmrg_gemv_n(int64_t n, int32_t k, const double *V, int64_t ldv, const double *s,
                         double beta, double *y, void *stream);
 
+/* dmrg_gemv_t without any allocation, for callers that cannot allocate
+ * device memory (code under hipGraph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, kernels and results (bit for bit)
+ * as dmrg_gemv_t, but the per-block partial sums live in a fixed 512 KiB
+ * array of device memory inside the library, one copy per device, held until
+ * the process ends.  Limits: 1 <= k <= 64 (larger k returns
+ * DMRG_E_INVALID_ARG naming the limit); any n >= 1.  Calls on one device
+ * share that array: calls that overlap in time on one device (different
+ * streams or threads) race and must not be issued.  Asynchronous on stream. */
+dmrg_status dmrg_gemv_t_noalloc(int64_t n, int32_t k, const double *V, int64_t ldv, const double *x,
+                                double *s, void *stream);
+
 /* Reduced density matrices of the left and right blocks from a state psi
  * (Alg. 1, step 5: each block's density matrix, built from the superblock's
  * lowest eigenstate; it is the partial trace of |psi><psi| over the other

@@ -99,6 +99,7 @@ SIGNATURES = {
     "dmrg_diagonal": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "dmrg_gemv_t": (c_int32, [c_int64, c_int32, c_void_p, c_int64, c_void_p, c_void_p, c_void_p]),
     "dmrg_gemv_n": (c_int32, [c_int64, c_int32, c_void_p, c_int64, c_void_p, c_double, c_void_p, c_void_p]),
+    "dmrg_gemv_t_noalloc": (c_int32, [c_int64, c_int32, c_void_p, c_int64, c_void_p, c_void_p, c_void_p]),
     "dmrg_density_layout": (c_int32, [c_void_p, POINTER(c_int64), POINTER(c_int64)]),
     "dmrg_density": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "dmrg_eigh_blocks": (c_int32, [c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
