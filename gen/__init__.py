@@ -20,11 +20,15 @@ Conventions (the paper's LR strategy, Eq. 9-11):
 
 * A *term* ``(c, a, b)`` stands for ``c * A_a (x) B_b`` with ``A_a`` from the
   left operator list and ``B_b`` from the right one (Eq. 9).
+* A four-subsystem superblock (Sec. "l-1-1-r strategy", :class:`Problem4`)
+  has one space and operator list per subsystem (block l, site 1, site 2,
+  block r) and terms ``(c, a, b, c', d)`` for c * A_a (x) a_b (x) b_c' (x) B_d.
 """
 from .workloads import (  # noqa: F401
     Space,
     Operator,
     Problem,
+    Problem4,
     largest_remainder,
     heisenberg_exact,
     hubbard_exact,
@@ -33,6 +37,12 @@ from .workloads import (  # noqa: F401
     j1j2_synthetic,
     batched_heisenberg,
     random_problem,
+    random_problem4,
+    spin_site,
+    hubbard_site,
+    heisenberg_l11r,
+    hubbard_l11r_exact,
+    hubbard_l11r_synthetic,
     start_vector,
     config,
     CONFIG_NAMES,

@@ -579,3 +579,208 @@ def config(i: int, seed: Optional[int] = None):
     if i == 5:
         return j1j2_synthetic(1024, seed=2468 if seed is None else seed)
     raise ValueError(i)
+
+
+# ---------------------------------------------------------------------------
+# four subsystems: block l, site 1, site 2, block r (the l-1-1-r strategy)
+# ---------------------------------------------------------------------------
+
+
+@dataclass
+class Problem4:
+    """One superblock written over its four subsystems (Sec. "l-1-1-r strategy"):
+    ``spaces`` = [l, s1, s2, r], ``ops`` = one operator list per subsystem,
+    ``terms`` int32 [nterm, 4] with ``coef`` [nterm]: term k is
+    coef[k] * ops[0][a] (x) ops[1][b] (x) ops[2][c] (x) ops[3][d]."""
+
+    spaces: List[Space]
+    target: np.ndarray
+    ops: List[List[Operator]]
+    terms: np.ndarray
+    coef: np.ndarray
+    name: str = ""
+    seed: int = 0
+    meta: dict = field(default_factory=dict)
+
+    def __post_init__(self):
+        self.target = np.asarray(self.target, dtype=np.int32).reshape(-1)
+        self.terms = np.ascontiguousarray(np.asarray(self.terms, dtype=np.int32).reshape(-1, 4))
+        self.coef = np.ascontiguousarray(np.asarray(self.coef, dtype=np.float64).reshape(-1))
+
+
+def spin_site():
+    """One spin-1/2 site in sector form: labels 2 S^z = -1 (down), +1 (up);
+    operators I, Sz, S+, S- (Eq. 3)."""
+    space = Space(np.array([[-1], [1]], dtype=np.int32), np.array([1, 1]))
+    ops = [Operator("identity", name="I"),
+           Operator("diag", diag=np.array([-0.5, 0.5]), name="Sz"),
+           Operator("dense", src=[0], dst=[1], blocks=[np.ones((1, 1))], name="S+"),
+           Operator("dense", src=[1], dst=[0], blocks=[np.ones((1, 1))], name="S-")]
+    return space, ops
+
+
+def heisenberg_l11r(n_left: int = 4, n_right: int = 4, J: float = 1.0, delta: float = 1.0) -> Problem4:
+    """Open spin-1/2 Heisenberg chain (Eq. 1-3) of n_left + 2 + n_right sites
+    as exact block l, two single sites and exact block r; target S^z = 0.
+
+    Operator lists: l and r as in :func:`heisenberg_exact` (I, H, S+, S-, Sz,
+    coupling operators on the site next to the middle), sites I, Sz, S+, S-.
+    Eleven terms: H_l, H_r, and the three bonds l-1, 1-2, 2-r.
+    """
+    L, opsL = _spin_block(n_left, n_left, J, delta)
+    R, opsR = _spin_block(n_right, 1, J, delta)
+    S, opsS = spin_site()
+    S2, opsS2 = spin_site()
+    h = 0.5 * J
+    z = J * delta
+    # (l, s1, s2, r): l ops I0 H1 S+2 S-3 Sz4; site ops I0 Sz1 S+2 S-3
+    terms = [(1, 0, 0, 0), (0, 0, 0, 1),
+             (2, 3, 0, 0), (3, 2, 0, 0), (4, 1, 0, 0),
+             (0, 2, 3, 0), (0, 3, 2, 0), (0, 1, 1, 0),
+             (0, 0, 2, 3), (0, 0, 3, 2), (0, 0, 1, 4)]
+    coef = [1.0, 1.0, h, h, z, h, h, z, h, h, z]
+    return Problem4([L, S, S2, R], [0], [opsL, opsS, opsS2, opsR], terms, coef,
+                    name=f"heisenberg_l11r_{n_left}+1+1+{n_right}",
+                    meta={"nsites": n_left + n_right + 2, "J": J, "delta": delta})
+
+
+def hubbard_site(t: float = 1.0, U: float = 4.0):
+    """One spin-1/2 Hubbard site (Eq. 4-8) in sector form, labels (N_up, N_dn):
+    operators I, H = U n_up n_dn, n_up n_dn, n_up, n_dn, the parity P = (-1)^N,
+    and c_sigma, c_sigma^dagger with their products with P (the single-site
+    block of :func:`hubbard_exact`: modes ordered down, up)."""
+    space, o = _hubbard_block(1, 1, t, U)
+    nn = Operator("diag", diag=_sector_values(space, space.labels[:, 0] * space.labels[:, 1]), name="nn")
+    nu = Operator("diag", diag=_sector_values(space, space.labels[:, 0]), name="nu")
+    nd = Operator("diag", diag=_sector_values(space, space.labels[:, 1]), name="nd")
+    par = Operator("diag", diag=_sector_values(space, (-1.0) ** (space.labels[:, 0] + space.labels[:, 1])),
+                   name="P")
+    names = ["cdag_up", "c_up", "cdag_dn", "c_dn", "cdagP_up", "Pc_up", "cdagP_dn", "Pc_dn"]
+    ops = [o["I"], o["H"], nn, nu, nd, par] + [o[k] for k in names]
+    return space, ops
+
+
+def _hubbard_l11r_terms(t: float, with_site_u: bool, U: float):
+    """Terms over (l, s1, s2, r) for a Hubbard chain; site op indices as in
+    :func:`hubbard_site` (I0 H1 nn2 nu3 nd4 P5 cdag_up6 c_up7 cdag_dn8 c_dn9
+    cdagP_up10 Pc_up11 cdagP_dn12 Pc_dn13); block op order
+    I0 H1 cdagP_up2 Pc_up3 cdagP_dn4 Pc_dn5 (left) and I0 H1 c_up2 cdag_up3
+    c_dn4 cdag_dn5 (right).  Hopping across a cut: the creation operator of the
+    earlier subsystem times its parity, then the annihilator of the later
+    one, and the Hermitian conjugate (Jordan-Wigner, Eq. 5-8)."""
+    terms = [(1, 0, 0, 0), (0, 0, 0, 1)]
+    coef = [1.0, 1.0]
+    if with_site_u:
+        terms += [(0, 1, 0, 0), (0, 0, 1, 0)]  # U n_up n_dn on each site
+        coef += [1.0, 1.0]
+    # l - s1: cdagP_l c_1 and P c_l cdag_1 per spin
+    terms += [(2, 7, 0, 0), (3, 6, 0, 0), (4, 9, 0, 0), (5, 8, 0, 0)]
+    # s1 - s2
+    terms += [(0, 10, 7, 0), (0, 11, 6, 0), (0, 12, 9, 0), (0, 13, 8, 0)]
+    # s2 - r
+    terms += [(0, 0, 10, 2), (0, 0, 11, 3), (0, 0, 12, 4), (0, 0, 13, 5)]
+    coef += [-t] * 12
+    return terms, coef
+
+
+def hubbard_l11r_exact(n_left: int = 1, n_right: int = 1, t: float = 1.0, U: float = 4.0) -> Problem4:
+    """Spin-1/2 Hubbard chain of n_left + 2 + n_right sites (Eq. 4-8) as exact
+    block l, two sites and exact block r, at half filling."""
+    L, oL = _hubbard_block(n_left, n_left, t, U)
+    R, oR = _hubbard_block(n_right, 1, t, U)
+    S, opsS = hubbard_site(t, U)
+    S2, opsS2 = hubbard_site(t, U)
+    opsL = [oL[k] for k in ["I", "H", "cdagP_up", "Pc_up", "cdagP_dn", "Pc_dn"]]
+    opsR = [oR[k] for k in ["I", "H", "c_up", "cdag_up", "c_dn", "cdag_dn"]]
+    terms, coef = _hubbard_l11r_terms(t, True, U)
+    N = n_left + n_right + 2
+    return Problem4([L, S, S2, R], [N // 2, N // 2], [opsL, opsS, opsS2, opsR], terms, coef,
+                    name=f"hubbard_l11r_{n_left}+1+1+{n_right}", meta={"nsites": N, "t": t, "U": U})
+
+
+def hubbard_l11r_synthetic(m: int = 512, seed: int = 8642, t: float = 1.0, U: float = 4.0) -> Problem4:
+    """Hubbard superblock of four subsystems: random blocks l and r of m states
+    with the Gaussian (N_up, N_dn) sectors of :func:`hubbard_space` (H block,
+    cdag maps with the block parity, as in :func:`hubbard_synthetic`; l from
+    ``seed``, r from ``seed + 1``) and two exact Hubbard sites (U n_up n_dn).
+    Sixteen terms: H_l, H_r, U on each site, four hoppings across each of the
+    three cuts.  Target: the block reference fillings plus one particle of
+    each spin on the two sites (labels measured from the blocks' reference)."""
+    space = hubbard_space(m)
+    opsL_all = _hub_side(space, m, seed, True)
+    opsR_all = _hub_side(space, m, seed + 1, False)
+    opsL = [opsL_all[k] for k in (0, 1, 5, 6, 7, 8)]
+    opsR = [opsR_all[k] for k in (0, 1, 5, 6, 7, 8)]
+    S, opsS = hubbard_site(t, U)
+    S2, opsS2 = hubbard_site(t, U)
+    terms, coef = _hubbard_l11r_terms(t, True, U)
+    return Problem4([space, S, S2, Space(space.labels, space.dims)], [1, 1], [opsL, opsS, opsS2, opsR],
+                    terms, coef, name=f"hubbard_l11r_m{m}", seed=seed, meta={"m": m, "t": t, "U": U})
+
+
+def random_problem4(seed: int, rank: int = 1, nsec: int = 4, dmax: int = 7, site_dmax: int = 2,
+                    nops: int = 3, nterm: int = 6, p_zero: float = 0.15, p_drop: float = 0.2) -> Problem4:
+    """Random four-subsystem structure: ragged block spaces (zero and unit
+    dimensions), small site spaces with sectors of dimension up to site_dmax,
+    every operator kind, missing blocks; every term conserves the target."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    if rank == 1:
+        pool = [(a,) for a in range(-3, 4)]
+    else:
+        pool = [(a, b) for a in range(-2, 3) for b in range(-2, 3)]
+    unit = [np.zeros(rank, dtype=np.int32)]
+    for a in range(rank):
+        e = np.zeros(rank, dtype=np.int32)
+        e[a] = 1
+        unit += [e, -e]
+
+    def make_space(k, dmax_):
+        k = min(k, len(pool))
+        pick = sorted(rng.choice(len(pool), size=k, replace=False))
+        labels = np.array([pool[i] for i in pick], dtype=np.int32)
+        dims = rng.integers(1, dmax_ + 1, size=k)
+        dims[rng.random(k) < p_zero] = 0
+        return Space(labels, dims)
+
+    spaces = [make_space(nsec, dmax), make_space(3, site_dmax), make_space(3, site_dmax), make_space(nsec, dmax)]
+    for sp in spaces[1:3]:  # sites keep every sector non-empty
+        sp.dims[sp.dims == 0] = 1
+
+    def make_op(space, sh):
+        if sh is None:
+            return Operator("diag", diag=rng.standard_normal(space.m), name="D")
+        src, dst, blocks = [], [], []
+        for s in range(space.nsec):
+            d = space.index(space.labels[s] + sh)
+            if d < 0 or rng.random() < p_drop:
+                continue
+            src.append(s)
+            dst.append(d)
+            blocks.append(rng.standard_normal((int(space.dims[d]), int(space.dims[s]))))
+        return Operator("dense", src=src, dst=dst, blocks=blocks, name="M")
+
+    # operator j of every subsystem has shift shifts[j]; shift None = diagonal
+    shifts = [[None] + [unit[int(rng.integers(len(unit)))] for _ in range(nops - 1)] for _ in range(4)]
+    ops = [[Operator("identity", name="I")] + [make_op(spaces[s], sh) for sh in shifts[s]] for s in range(4)]
+
+    def shift(s, j):
+        if j == 0 or shifts[s][j - 1] is None:
+            return np.zeros(rank, dtype=np.int32)
+        return shifts[s][j - 1]
+
+    terms = []
+    while len(terms) < nterm:
+        pick = [int(rng.integers(len(ops[s]))) for s in range(3)]
+        tot = sum(shift(s, pick[s]) for s in range(3))
+        ok = [d for d in range(len(ops[3])) if np.array_equal(shift(3, d), -tot)]
+        if not ok:
+            continue
+        terms.append(tuple(pick) + (ok[int(rng.integers(len(ok)))],))
+    # a target reachable by some non-empty quadruple
+    cand = [(i, j, k, l) for i in range(spaces[0].nsec) for j in range(spaces[1].nsec)
+            for k in range(spaces[2].nsec) for l in range(spaces[3].nsec)
+            if spaces[0].dims[i] and spaces[1].dims[j] and spaces[2].dims[k] and spaces[3].dims[l]]
+    q = cand[int(rng.integers(len(cand)))]
+    target = sum(spaces[s].labels[q[s]] for s in range(4))
+    coef = rng.standard_normal(len(terms))
+    return Problem4(spaces, target, ops, terms, coef, name=f"random4_{seed}_r{rank}", seed=seed)

@@ -17,9 +17,11 @@ davidson    the Davidson iteration of Alg. 3 with the readings listed in the
 precision   emulated FP32/BF16 operator rounding with the FP64 diagonal split
 density     reduced density matrices of both blocks (Alg. 1, step 5), by pair
             blocks and by the dense partial trace
+l11r        the l-1-1-r strategy (Eq. 12-13, Alg. 2): enlarged-basis order,
+            four-fold Kronecker definition, sector-wise evaluation, LR form
 
 Every function states the passage of the paper it follows.  Nothing here is
 "parity unpinned": each function has at least one independent pin in
 ``tests/test_oracle_*.py`` (closed forms, brute force, library routines).
 """
-from . import models, sectors, projection, davidson, precision, density  # noqa: F401
+from . import models, sectors, projection, davidson, precision, density, l11r  # noqa: F401
