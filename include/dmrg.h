@@ -363,6 +363,92 @@ typedef struct {
 dmrg_status dmrg_place_blocks(int32_t n, const dmrg_place *items, const double *src, double *dst,
                               void *stream);
 
+/* ------------------------------------------------------------------------
+ * Enlarged blocks and the l-1-1-r strategy
+ * ------------------------------------------------------------------------
+ * Basis of an enlarged block slow (x) fast (Alg. 1, steps 1-2: a block and
+ * its neighbouring site, L = l (x) s1 or R = s2 (x) r; the paper leaves the
+ * order open, this is the library's reading): one sector per label sum
+ * q = q_slow + q_fast that holds states, in ascending lexicographic order;
+ * inside sector q the combinations (s_slow, s_fast) with that sum follow in
+ * ascending order of s_slow, each a row-major [d(s_slow)][d(s_fast)]
+ * sub-block (slow index first, as in the Kronecker product slow (x) fast). */
+
+/* Term of an enlarged operator: op_out += coef * slow_op[a] (x) fast_op[b]. */
+typedef struct {
+    int32_t out, a, b;
+    double coef;
+} dmrg_kron_term;
+
+typedef struct {
+    int32_t nsec;        /* sectors of the enlarged block */
+    int32_t nblk_total;  /* dense blocks over all output operators */
+    int64_t m;           /* dimension of the enlarged block */
+    int64_t data_len;    /* FP64 elements of all output operators */
+} dmrg_enlarge_sizes;
+
+/* Operators of an enlarged block (Alg. 1, steps 1-2): for every output o,
+ *   op_out[o] = sum over its terms of coef * slow_op[a] (x) fast_op[b]
+ * in the enlarged basis above.  Host only (no GPU): every data pointer of
+ * ops_slow / ops_fast is HOST FP64 here (the dmrg_op layouts as usual).
+ * Two calls: with label == NULL only *sizes is filled; then call again with
+ * arrays of those sizes:
+ *  label [nsec * rank], dim [nsec]: the enlarged space;
+ *  op_kind [nout]: IDENTITY (a single term I (x) I with coef 1), DIAG (every
+ *    term's two factors are identity or diagonal) or DENSE;
+ *  op_nblk [nout], op_off [nout]: blocks and first data element of output o;
+ *  src, dst, off [nblk_total]: the blocks of output 0, then of output 1, ...,
+ *    each output's in ascending (src, dst); off relative to op_off[o];
+ *  data [data_len]: DIAG outputs hold their diagonal [m], DENSE outputs their
+ *    row-major blocks [dim(dst)][dim(src)].
+ * A dmrg_op for output o is {op_kind[o], op_nblk[o], src + b0, dst + b0,
+ * off + b0, data + op_off[o]} with b0 = the blocks of the outputs before it.
+ * Errors: DMRG_E_INVALID_ARG (null or out-of-range arguments, output arrays
+ * missing in the second call), DMRG_E_LAYOUT (labels not ascending, duplicate
+ * blocks), DMRG_E_UNSUPPORTED (a sector above 2^20 states). */
+dmrg_status dmrg_enlarge(const dmrg_space *slow, int32_t nop_slow, const dmrg_op *ops_slow,
+                         const dmrg_space *fast, int32_t nop_fast, const dmrg_op *ops_fast,
+                         int32_t nterm, const dmrg_kron_term *terms, int32_t nout,
+                         dmrg_enlarge_sizes *sizes, int32_t *label, int64_t *dim, int32_t *op_kind,
+                         int32_t *op_nblk, int64_t *op_off, int32_t *src, int32_t *dst, int64_t *off,
+                         double *data);
+
+/* Term k of a four-subsystem superblock (Sec. "l-1-1-r strategy", Eq. 12):
+ * coef[k] * ops[0][a] (x) ops[1][b] (x) ops[2][c] (x) ops[3][d]. */
+typedef struct {
+    int32_t a, b, c, d;
+} dmrg_term4;
+
+/* A superblock written over its four subsystems: block l, site 1, site 2,
+ * block r.  Operator data: blocks l and r device FP64 (kept by reference, as
+ * in dmrg_problem); the two sites HOST FP64, read once at plan creation
+ * (their matrix elements become constant factors of the records). */
+typedef struct {
+    dmrg_space space[4];
+    const int32_t *target; /* host [rank] */
+    int32_t nop[4];
+    const dmrg_op *ops[4]; /* host arrays of descriptors */
+    int32_t nterm;
+    const dmrg_term4 *terms; /* host [nterm] */
+} dmrg_problem4;
+
+/* Plan of the l-1-1-r strategy (Eq. 13, Alg. 2): the projection is formed
+ * from the four subsystems' operators, so no operator of an enlarged block
+ * (largest matrix O((m q)^2)) is ever built, only blocks of l and r
+ * (O(m^2)).  psi has the LR layout of the enlarged blocks (l (x) s1,
+ * s2 (x) r) in the basis above (dmrg_enlarge with no terms returns their
+ * spaces); a sector quadruple (s_l, s_1, s_2, s_r) is the sub-block of rows
+ * of its combination (s_l, s_1) and columns of (s_2, s_r), a [d_l d_1] x
+ * [d_2 d_r] sub-matrix that reshapes to Alg. 2's X[i_l][i_1][i_2][i_r].
+ * Every record applies A_l X B_r^T to the [d_l x d_r] slice of fixed site
+ * indices (i_1, i_2), scaled by the site matrix elements, on the same
+ * grouped-GEMM kernels as the LR plans.  The resulting plan serves
+ * dmrg_project, dmrg_project_backward, dmrg_davidson, dmrg_diagonal and the
+ * density calls exactly like an LR plan (FP64 only).  Synchronizes stream.
+ * Errors: as dmrg_plan_create; DMRG_E_SECTOR for a term that leaves the
+ * target sector. */
+dmrg_status dmrg_plan_create_l11r(dmrg_plan **out, int32_t nprob, const dmrg_problem4 *probs, void *stream);
+
 /* Set the tile table used by later dmrg_plan_create calls: for output
  * blocks with max(rows, cols) <= bound[c] (ascending, ncls <= 8), tiles of
  * tile[c] rows and columns (16 or 32).  ncls = 0 restores the built-in table.

@@ -10,7 +10,9 @@ Problem descriptions are duck-typed: any object with the attributes
 ``left``/``right`` (``labels`` int [nsec, rank], ``dims`` int [nsec]),
 ``target``, ``ops_left``/``ops_right`` (each with ``kind`` in
 {"identity", "diag", "dense"}, and ``src``/``dst``/``blocks`` or ``diag``),
-``terms`` ([nterm, 2]) and ``coef`` ([nterm]).
+``terms`` ([nterm, 2]) and ``coef`` ([nterm]).  A four-subsystem superblock
+(the l-1-1-r strategy) has ``spaces`` and ``ops`` (four each: block l, site 1,
+site 2, block r) and ``terms`` [nterm, 4] instead of the left/right fields.
 """
 from __future__ import annotations
 
@@ -23,7 +25,12 @@ from . import _native as N
 from ._native import DmrgError  # noqa: F401
 
 __all__ = ["Plan", "project", "ground_energy", "problem_check", "DmrgError", "gemv_t", "gemv_n",
-           "set_tile_table", "version"]
+           "set_tile_table", "version", "enlarge", "is_four_subsystem"]
+
+
+def is_four_subsystem(p) -> bool:
+    """True for a superblock given over its four subsystems (l-1-1-r)."""
+    return hasattr(p, "spaces") and not hasattr(p, "left")
 
 
 def version() -> str:
@@ -53,9 +60,33 @@ class _Marshal:
     def __init__(self, problems: Sequence, device=None):
         self.keep: list = []
         self.dev_tensors: list = []
-        self.structs = (N.Problem * len(problems))()
-        for i, p in enumerate(problems):
-            self.structs[i] = self._problem(p, device)
+        self.four = bool(problems) and is_four_subsystem(problems[0])
+        if self.four:
+            self.structs = (N.Problem4 * len(problems))()
+            for i, p in enumerate(problems):
+                self.structs[i] = self._problem4(p, device)
+        else:
+            self.structs = (N.Problem * len(problems))()
+            for i, p in enumerate(problems):
+                self.structs[i] = self._problem(p, device)
+
+    def _problem4(self, p, device) -> N.Problem4:
+        """Blocks l and r: data on the device (host when device is None); the
+        two sites: host data, read by the library at plan creation."""
+        spaces = (N.Space * 4)(*[self._space(sp) for sp in p.spaces])
+        ops = (ctypes.POINTER(N.Op) * 4)()
+        nop = (ctypes.c_int32 * 4)()
+        for s in range(4):
+            dev = device if s in (0, 3) else None
+            arr = (N.Op * max(1, len(p.ops[s])))(*[self._op(o, dev) for o in p.ops[s]])
+            self.keep.append(arr)
+            ops[s] = ctypes.cast(arr, ctypes.POINTER(N.Op))
+            nop[s] = len(p.ops[s])
+        tgt = _i32(np.asarray(p.target).reshape(-1))
+        t4 = _i32(np.asarray(p.terms).reshape(-1, 4))
+        terms = (N.Term4 * max(1, t4.shape[0]))(*[N.Term4(*[int(x) for x in row]) for row in t4])
+        self.keep += [tgt, terms, spaces, ops, nop]
+        return N.Problem4(spaces, _ptr(tgt, ctypes.c_int32), nop, ops, int(t4.shape[0]), terms)
 
     def _space(self, sp) -> N.Space:
         lab = _i32(sp.labels)
@@ -130,8 +161,92 @@ def _stream(device):
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
 
+class EnlargedSpace:
+    """Sector table of an enlarged block as dmrg_enlarge returns it."""
+
+    def __init__(self, labels, dims):
+        self.labels = np.ascontiguousarray(labels, dtype=np.int32)
+        self.dims = np.ascontiguousarray(dims, dtype=np.int64)
+
+    @property
+    def nsec(self) -> int:
+        return int(self.dims.shape[0])
+
+    @property
+    def rank(self) -> int:
+        return int(self.labels.shape[1])
+
+    @property
+    def m(self) -> int:
+        return int(self.dims.sum())
+
+    def offsets(self) -> np.ndarray:
+        return np.concatenate([[0], np.cumsum(self.dims)]).astype(np.int64)
+
+
+class EnlargedOp:
+    """One operator of an enlarged block as dmrg_enlarge returns it (kind,
+    and src/dst/blocks or diag, the layout every problem description uses)."""
+
+    def __init__(self, kind, src=None, dst=None, blocks=None, diag=None):
+        self.kind, self.src, self.dst, self.blocks, self.diag = kind, src, dst, blocks, diag
+
+    @property
+    def nblk(self) -> int:
+        return len(self.blocks) if self.kind == "dense" else 0
+
+
+def enlarge(slow, slow_ops, fast, fast_ops, terms, nout: int):
+    """Operators of the enlarged block slow (x) fast (dmrg_enlarge, host only):
+    ``terms`` = [(out, a, b, coef), ...] meaning op_out += coef *
+    slow_ops[a] (x) fast_ops[b].  Returns (EnlargedSpace, [EnlargedOp] * nout)."""
+    m = _Marshal([], device=None)
+    S, F = m._space(slow), m._space(fast)
+    os_ = (N.Op * max(1, len(slow_ops)))(*[m._op(o, None) for o in slow_ops])
+    of_ = (N.Op * max(1, len(fast_ops)))(*[m._op(o, None) for o in fast_ops])
+    kt = (N.KronTerm * max(1, len(terms)))(*[N.KronTerm(int(o), int(a), int(b), float(c)) for o, a, b, c in terms])
+    sz = N.EnlargeSizes()
+    lib = N.lib()
+    args = (ctypes.byref(S), len(slow_ops), os_, ctypes.byref(F), len(fast_ops), of_, len(terms), kt, nout,
+            ctypes.byref(sz))
+    N.check(lib.dmrg_enlarge(*args, None, None, None, None, None, None, None, None, None))
+    rank = int(np.asarray(slow.labels).reshape(slow.dims.shape[0], -1).shape[1])
+    label = np.zeros(max(1, sz.nsec * rank), dtype=np.int32)
+    dim = np.zeros(max(1, sz.nsec), dtype=np.int64)
+    kind = np.zeros(max(1, nout), dtype=np.int32)
+    nblk = np.zeros(max(1, nout), dtype=np.int32)
+    ooff = np.zeros(max(1, nout), dtype=np.int64)
+    src = np.zeros(max(1, sz.nblk_total), dtype=np.int32)
+    dst = np.zeros(max(1, sz.nblk_total), dtype=np.int32)
+    off = np.zeros(max(1, sz.nblk_total), dtype=np.int64)
+    data = np.zeros(max(1, sz.data_len), dtype=np.float64)
+    N.check(lib.dmrg_enlarge(*args, label.ctypes.data, dim.ctypes.data, kind.ctypes.data, nblk.ctypes.data,
+                             ooff.ctypes.data, src.ctypes.data, dst.ctypes.data, off.ctypes.data,
+                             data.ctypes.data))
+    space = EnlargedSpace(label[:sz.nsec * rank].reshape(sz.nsec, rank), dim[:sz.nsec])
+    names = {N.OP_IDENTITY: "identity", N.OP_DIAG: "diag", N.OP_DENSE: "dense"}
+    ops, b = [], 0
+    for o in range(nout):
+        k = names[int(kind[o])]
+        if k == "identity":
+            ops.append(EnlargedOp("identity"))
+        elif k == "diag":
+            ops.append(EnlargedOp("diag", diag=data[ooff[o]:ooff[o] + sz.m].copy()))
+        else:
+            blocks = []
+            for j in range(b, b + int(nblk[o])):
+                r, c = int(dim[dst[j]]), int(dim[src[j]])
+                st = int(ooff[o] + off[j])
+                blocks.append(data[st:st + r * c].reshape(r, c).copy())
+            ops.append(EnlargedOp("dense", src=src[b:b + nblk[o]].copy(), dst=dst[b:b + nblk[o]].copy(),
+                                  blocks=blocks))
+            b += int(nblk[o])
+    return space, ops
+
+
 class Plan:
-    """A device plan for one or many superblocks (dmrg_plan_create).
+    """A device plan for one or many superblocks (dmrg_plan_create, or
+    dmrg_plan_create_l11r for superblocks given over four subsystems).
 
     ``prec``: "f64", "f32" or "bf16" -- the reduced precision the plan
     prepares in addition to FP64.
@@ -151,8 +266,13 @@ class Plan:
                                    torch.device(device).index or 0)
         self.prec = N.PREC[prec]
         self._lib = N.lib()
+        self.four = is_four_subsystem(self.problems[0])
+        if self.four and self.prec != N.F64:
+            raise ValueError("four-subsystem (l-1-1-r) plans compute in FP64 only")
         table = None
-        if tiles == "auto":
+        if tiles == "auto" and self.four:
+            table = None
+        elif tiles == "auto":
             from . import autotune
 
             table = autotune.load_table(autotune.key_of(self.problems, prec))
@@ -165,8 +285,12 @@ class Plan:
             if table is not None:
                 set_tile_table(*table)
             try:
-                st = self._lib.dmrg_plan_create(ctypes.byref(h), len(self.problems), self._m.structs, self.prec,
-                                                _stream(self.device))
+                if self.four:
+                    st = self._lib.dmrg_plan_create_l11r(ctypes.byref(h), len(self.problems), self._m.structs,
+                                                         _stream(self.device))
+                else:
+                    st = self._lib.dmrg_plan_create(ctypes.byref(h), len(self.problems), self._m.structs,
+                                                    self.prec, _stream(self.device))
             finally:
                 if table is not None:
                     set_tile_table((), ())
@@ -178,7 +302,7 @@ class Plan:
                                           ctypes.byref(flop), ctypes.byref(nbytes)))
         self.n, self.npair, self.nrec, self.flop, self.bytes = n.value, npair.value, nrec.value, flop.value, \
             nbytes.value
-        self.nterm = [int(np.asarray(p.terms).reshape(-1, 2).shape[0]) for p in self.problems]
+        self.nterm = [int(np.asarray(p.terms).reshape(-1, 4 if self.four else 2).shape[0]) for p in self.problems]
         coef = np.concatenate([np.asarray(p.coef, dtype=np.float64).reshape(-1) for p in self.problems]) \
             if sum(self.nterm) else np.zeros(1)
         self.coef = torch.from_numpy(coef).to(self.device)

@@ -74,6 +74,23 @@ class Place(ctypes.Structure):
                 ("ld_dst", c_int32), ("coef", c_double), ("identity", c_int32)]
 
 
+class KronTerm(ctypes.Structure):
+    _fields_ = [("out", c_int32), ("a", c_int32), ("b", c_int32), ("coef", c_double)]
+
+
+class EnlargeSizes(ctypes.Structure):
+    _fields_ = [("nsec", c_int32), ("nblk_total", c_int32), ("m", c_int64), ("data_len", c_int64)]
+
+
+class Term4(ctypes.Structure):
+    _fields_ = [("a", c_int32), ("b", c_int32), ("c", c_int32), ("d", c_int32)]
+
+
+class Problem4(ctypes.Structure):
+    _fields_ = [("space", Space * 4), ("target", POINTER(c_int32)), ("nop", c_int32 * 4),
+                ("ops", POINTER(Op) * 4), ("nterm", c_int32), ("terms", POINTER(Term4))]
+
+
 class DmrgError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__(f"dmrg status {status}: {message}")
@@ -109,6 +126,10 @@ SIGNATURES = {
     "dmrg_renormalize": (c_int32, [c_int32, POINTER(RenormBlock), c_void_p, c_void_p, c_void_p, c_void_p]),
     "dmrg_place_blocks": (c_int32, [c_int32, POINTER(Place), c_void_p, c_void_p, c_void_p]),
     "dmrg_set_tile_table": (c_int32, [c_int32, POINTER(c_int32), POINTER(c_int32)]),
+    "dmrg_enlarge": (c_int32, [POINTER(Space), c_int32, POINTER(Op), POINTER(Space), c_int32, POINTER(Op), c_int32,
+                               POINTER(KronTerm), c_int32, POINTER(EnlargeSizes), c_void_p, c_void_p, c_void_p,
+                               c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "dmrg_plan_create_l11r": (c_int32, [POINTER(c_void_p), c_int32, POINTER(Problem4), c_void_p]),
     "dmrg_plan_destroy": (None, [c_void_p]),
     "dmrg_last_error": (c_char_p, []),
     "dmrg_version": (c_char_p, []),

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libdmrg.so")
-SOURCES = ["plan.cpp", "project.hip", "davidson.hip", "density.hip", "eigh.hip", "renorm.hip",
+SOURCES = ["plan.cpp", "enlarge.cpp", "project.hip", "davidson.hip", "density.hip", "eigh.hip", "renorm.hip",
            "gemv_noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

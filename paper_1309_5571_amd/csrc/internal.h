@@ -48,6 +48,12 @@ enum : int16_t {
 // intermediate slice T = P[rows, :K] Q[:K, :K2] (P = A block, Q = the input
 // block, both as above) in LDS and then C += coef * T R^T with R the
 // row-major B block read as R[c * ldr + k], k < K2.
+// A copy segment (fused = 2) adds coef * pscale[r] qscale[c] X(r, c), X the
+// input sub-matrix at element offset q with rows of ldq (a term whose block
+// factors are identities or diagonals but whose input lies elsewhere in psi:
+// the site factors of the l-1-1-r strategy move it).
+// Every contribution is also multiplied by the constant w (the site matrix
+// elements of an l-1-1-r record; 1 otherwise).
 struct Seg {
     uint64_t p, q;            // address (OPD_ABS) or element offset
     uint64_t pscale, qscale;  // absolute FP64 addresses, 0 = none
@@ -61,6 +67,7 @@ struct Seg {
     int16_t fused, pad16;
     int32_t coef;  // global coefficient index, -1 = 1.0
     int32_t term;  // global term index (for coefficient gradients), -1 = none
+    double w = 1.0;  // constant factor of the contribution
 };
 
 // A purely diagonal contribution at an output pair:
@@ -72,6 +79,7 @@ struct DiagTerm {
     int32_t coef;
     int32_t term;
     int32_t sl, sr;
+    double w = 1.0;  // constant factor (1 for the LR strategy)
 };
 
 // One output tile.
@@ -104,12 +112,24 @@ struct OpBlock {  // resolved block of one operator (identity/diag/dense)
     int32_t blk;        // block index within the operator (dense), -1 otherwise
 };
 
+// A row-major sub-matrix of psi: rows x cols, consecutive rows ld elements apart.
+struct Geo {
+    int64_t off;
+    int64_t rows, cols, ld;
+};
+
 struct Record {
     int32_t term;   // term index within the member
     int32_t gterm;  // global term index
     int32_t pin, pout;  // global pair indices
     OpBlock a, b;
     int32_t order;  // 0: (A X) B^T, 1: A (X B^T), 2: one-sided / diagonal
+    // Y[gout] += c w A X[gin] B^T.  LR strategy: the pair blocks, w = 1;
+    // l-1-1-r strategy: the [d_l x d_r] slices of fixed site indices, w the
+    // product of the two site matrix elements.
+    Geo gin, gout;
+    int32_t oin, oout;  // indices of gin / gout in the plan's output sub-matrices
+    double w;
 };
 
 struct Lists {  // device task lists of one pass
@@ -169,6 +189,11 @@ struct dmrg_plan {
     std::vector<dmrg::Pair> pairs;
     std::vector<int32_t> pair_member;
     std::vector<dmrg::Record> records;
+    // the sub-matrices of psi that output tiles cover, in psi order (LR: the
+    // pair blocks; l-1-1-r: every [d_l x d_r] slice of fixed site indices);
+    // together they cover psi exactly once
+    std::vector<dmrg::Geo> out_geo;
+    std::vector<int32_t> out_member;
     // device pass sets: [prec slot][direction]  slot 0 = F64, slot 1 = plan precision
     dmrg::PassSet fwd[2], adj[2];
     // coefficient-gradient reduction (forward F64 pass): CSR over global terms

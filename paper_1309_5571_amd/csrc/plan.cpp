@@ -19,6 +19,7 @@
 #include <set>
 #include <tuple>
 
+#include "enlarge.h"
 #include "internal.h"
 
 namespace dmrg {
@@ -218,6 +219,11 @@ static dmrg_status analyse(const dmrg_problem *p, MemberPairs *mp_out, std::vect
                     r.pout = po;
                     r.a = a;
                     r.b = b;
+                    r.gin = Geo{in.off, in.dl, in.dr, in.dr};
+                    r.gout = Geo{mp.pairs[po].off, mp.pairs[po].dl, mp.pairs[po].dr, mp.pairs[po].dr};
+                    r.oin = pi;
+                    r.oout = po;
+                    r.w = 1.0;
                     bool da = a.kind == DMRG_OP_DENSE, db = b.kind == DMRG_OP_DENSE;
                     if (da && db) {
                         int64_t di = in.dl, dk = in.dr, dj = mp.pairs[po].dl, dl = mp.pairs[po].dr;
@@ -250,7 +256,7 @@ static uint64_t U(const void *p) { return (uint64_t)(uintptr_t)p; }
 // Largest intermediate width a fused two-sided segment keeps in LDS (16 rows x 64).
 constexpr int64_t FUSE_MAX_K2 = 64;
 
-static void add_tiles(std::vector<Task> &out, int64_t rows, int64_t cols, int64_t c_off, int64_t x_off,
+static void add_tiles(std::vector<Task> &out, int64_t rows, int64_t cols, int64_t c_off, int64_t x_off, int64_t ld,
                       int32_t seg_b, int32_t seg_e, int32_t d_b, int32_t d_e, int member) {
     int ts = tile_for(rows, cols);
     for (int64_t r0 = 0; r0 < rows; r0 += ts)
@@ -262,7 +268,7 @@ static void add_tiles(std::vector<Task> &out, int64_t rows, int64_t cols, int64_
             t.diag_end = d_e;
             t.c_off = c_off;
             t.x_off = x_off;
-            t.ldc = (int32_t)cols;
+            t.ldc = (int32_t)ld;
             t.row0 = (int32_t)r0;
             t.col0 = (int32_t)c0;
             t.m = (int32_t)std::min<int64_t>(ts, rows - r0);
@@ -324,12 +330,11 @@ struct LowStore {
 // With `low` set, dense operator blocks are taken from low-precision copies and
 // the diagonals of square blocks in one-sided records are split off in FP64.
 static void build_pass(const dmrg_plan *plan, bool adjoint, LowStore *low, uint64_t low_base, HostPass &hp) {
-    const auto &pairs = plan->pairs;
-    int npair = (int)pairs.size();
-    std::vector<std::vector<int>> by_out(npair);
+    const int nout = (int)plan->out_geo.size();
+    std::vector<std::vector<int>> by_out(nout);
     for (int r = 0; r < (int)plan->records.size(); ++r) {
         const Record &rc = plan->records[r];
-        by_out[adjoint ? rc.pin : rc.pout].push_back(r);
+        by_out[adjoint ? rc.oin : rc.oout].push_back(r);
     }
     auto blk_addr = [&](const OpBlock &b, int variant) -> uint64_t {
         if (!low) return U(b.data);
@@ -344,44 +349,64 @@ static void build_pass(const dmrg_plan *plan, bool adjoint, LowStore *low, uint6
         int member;
     };
     std::vector<TMat> tmats;
-    std::vector<Seg> segsA;  // stage-A (intermediate) segments, appended after the pairs' lists
-    for (int q = 0; q < npair; ++q) {
-        const Pair &po = pairs[q];
-        int member = plan->pair_member[q];
+    std::vector<Seg> segsA;  // stage-A (intermediate) segments, appended after the output lists
+    for (int q = 0; q < nout; ++q) {
+        const Geo &go = plan->out_geo[q];
+        int member = plan->out_member[q];
         int seg_b = (int)hp.segs.size(), d_b = (int)hp.diags.size();
         for (int ri : by_out[q]) {
             const Record &rc = plan->records[ri];
-            const Pair &pin = pairs[adjoint ? rc.pout : rc.pin];  // where the input block lives
+            const Geo &gi = adjoint ? rc.gout : rc.gin;  // where the input sub-matrix lives
             bool da = rc.a.kind == DMRG_OP_DENSE, db = rc.b.kind == DMRG_OP_DENSE;
             int gt = rc.gterm;
             if (!da && !db) {
-                hp.diags.push_back(DiagTerm{diag_addr(rc.a), diag_addr(rc.b), gt, gt, 1, 1});
+                if (gi.off == go.off && gi.ld == go.ld) {  // same place: an epilogue term
+                    DiagTerm dt{diag_addr(rc.a), diag_addr(rc.b), gt, gt, 1, 1};
+                    dt.w = rc.w;
+                    hp.diags.push_back(dt);
+                } else {  // the input lies elsewhere: a copy segment
+                    Seg c{};
+                    c.fused = 2;
+                    c.q = (uint64_t)gi.off;
+                    c.qkind = OPD_IN;
+                    c.ldq = (int32_t)gi.ld;
+                    c.pscale = diag_addr(rc.a);
+                    c.qscale = diag_addr(rc.b);
+                    c.coef = gt;
+                    c.term = gt;
+                    c.w = rc.w;
+                    hp.segs.push_back(c);
+                }
                 continue;
             }
             Seg s{};
             s.coef = gt;
             s.term = gt;
+            s.w = rc.w;
             if (!adjoint) {
-                // X = input block [di x dk] at pin; output [dj x dl] at q
-                int64_t di = pin.dl, dk = pin.dr;
+                // X = input [di x dk] (rows gi.ld apart); output [dj x dl]; A [dj x di], B [dl x dk]
+                int64_t di = gi.rows, dk = gi.cols;
                 if (da && !db) {
                     bool split = low && rc.a.src == rc.a.dst;
                     s.p = blk_addr(rc.a, split ? 1 : 0);
                     s.pkind = OPD_ABS;
                     s.ldp = (int32_t)di;
-                    s.q = (uint64_t)pin.off;
+                    s.q = (uint64_t)gi.off;
                     s.qkind = OPD_IN;
-                    s.ldq = (int32_t)dk;
+                    s.ldq = (int32_t)gi.ld;
                     s.qscale = diag_addr(rc.b);
                     s.K = (int32_t)di;
                     hp.segs.push_back(s);
-                    if (split)
-                        hp.diags.push_back(DiagTerm{blk_addr(rc.a, 2), diag_addr(rc.b), gt, -1, 1, 1});
+                    if (split) {
+                        DiagTerm dt{blk_addr(rc.a, 2), diag_addr(rc.b), gt, -1, 1, 1};
+                        dt.w = rc.w;
+                        hp.diags.push_back(dt);
+                    }
                 } else if (!da && db) {
                     bool split = low && rc.b.src == rc.b.dst;
-                    s.p = (uint64_t)pin.off;
+                    s.p = (uint64_t)gi.off;
                     s.pkind = OPD_IN;
-                    s.ldp = (int32_t)dk;
+                    s.ldp = (int32_t)gi.ld;
                     s.pscale = diag_addr(rc.a);
                     s.q = blk_addr(rc.b, split ? 1 : 0);
                     s.qkind = OPD_ABS;
@@ -389,24 +414,27 @@ static void build_pass(const dmrg_plan *plan, bool adjoint, LowStore *low, uint6
                     s.ldq = (int32_t)dk;
                     s.K = (int32_t)dk;
                     hp.segs.push_back(s);
-                    if (split)
-                        hp.diags.push_back(DiagTerm{diag_addr(rc.a), blk_addr(rc.b, 2), gt, -1, 1, 1});
-                } else if (tile_for(po.dl, po.dr) == 16 && dk <= FUSE_MAX_K2) {
+                    if (split) {
+                        DiagTerm dt{diag_addr(rc.a), blk_addr(rc.b, 2), gt, -1, 1, 1};
+                        dt.w = rc.w;
+                        hp.diags.push_back(dt);
+                    }
+                } else if (tile_for(go.rows, go.cols) == 16 && dk <= FUSE_MAX_K2) {
                     // small intermediate: fused in the output tile (no stage-A task)
                     s.fused = 1;
                     s.p = blk_addr(rc.a, 0);
                     s.pkind = OPD_ABS;
                     s.ldp = (int32_t)di;
-                    s.q = (uint64_t)pin.off;
+                    s.q = (uint64_t)gi.off;
                     s.qkind = OPD_IN;
-                    s.ldq = (int32_t)dk;
+                    s.ldq = (int32_t)gi.ld;
                     s.K = (int32_t)di;
                     s.r = blk_addr(rc.b, 0);
                     s.ldr = (int32_t)dk;
                     s.K2 = (int32_t)dk;
                     hp.segs.push_back(s);
                 } else {
-                    int64_t dj = po.dl, dl = po.dr;
+                    int64_t dj = go.rows, dl = go.cols;
                     Seg a{};
                     a.coef = -1;
                     a.term = -1;
@@ -415,9 +443,9 @@ static void build_pass(const dmrg_plan *plan, bool adjoint, LowStore *low, uint6
                         a.p = blk_addr(rc.a, 0);
                         a.pkind = OPD_ABS;
                         a.ldp = (int32_t)di;
-                        a.q = (uint64_t)pin.off;
+                        a.q = (uint64_t)gi.off;
                         a.qkind = OPD_IN;
-                        a.ldq = (int32_t)dk;
+                        a.ldq = (int32_t)gi.ld;
                         a.K = (int32_t)di;
                         tm = TMat{dj, dk, hp.tmp, 0, member};
                         s.p = (uint64_t)hp.tmp;
@@ -429,9 +457,9 @@ static void build_pass(const dmrg_plan *plan, bool adjoint, LowStore *low, uint6
                         s.ldq = (int32_t)dk;
                         s.K = (int32_t)dk;
                     } else {  // T = X B^T  [di x dl];  Y += c A T
-                        a.p = (uint64_t)pin.off;
+                        a.p = (uint64_t)gi.off;
                         a.pkind = OPD_IN;
-                        a.ldp = (int32_t)dk;
+                        a.ldp = (int32_t)gi.ld;
                         a.q = blk_addr(rc.b, 0);
                         a.qkind = OPD_ABS;
                         a.qtrans = 1;
@@ -453,24 +481,24 @@ static void build_pass(const dmrg_plan *plan, bool adjoint, LowStore *low, uint6
                     hp.segs.push_back(s);
                 }
             } else {
-                // adjoint: output = gpsi block [di x dk] at q (the record's input pair),
-                // input G = gbar block [dj x dl] at pin (the record's output pair)
-                int64_t di = po.dl, dk = po.dr, dj = pin.dl, dl = pin.dr;
+                // adjoint: output = gpsi [di x dk] at the record's input sub-matrix,
+                // input G = gbar [dj x dl] at its output sub-matrix (rows gi.ld apart)
+                int64_t di = go.rows, dk = go.cols, dj = gi.rows, dl = gi.cols;
                 if (da && !db) {  // gpsi += c A^T (G * v)
                     s.p = U(rc.a.data);
                     s.pkind = OPD_ABS;
                     s.ptrans = 1;
                     s.ldp = (int32_t)di;
-                    s.q = (uint64_t)pin.off;
+                    s.q = (uint64_t)gi.off;
                     s.qkind = OPD_IN;
-                    s.ldq = (int32_t)dl;
+                    s.ldq = (int32_t)gi.ld;
                     s.qscale = diag_addr(rc.b);
                     s.K = (int32_t)dj;
                     hp.segs.push_back(s);
                 } else if (!da && db) {  // gpsi += c (v * G) B
-                    s.p = (uint64_t)pin.off;
+                    s.p = (uint64_t)gi.off;
                     s.pkind = OPD_IN;
-                    s.ldp = (int32_t)dl;
+                    s.ldp = (int32_t)gi.ld;
                     s.pscale = diag_addr(rc.a);
                     s.q = U(rc.b.data);
                     s.qkind = OPD_ABS;
@@ -489,9 +517,9 @@ static void build_pass(const dmrg_plan *plan, bool adjoint, LowStore *low, uint6
                         a.pkind = OPD_ABS;
                         a.ptrans = 1;
                         a.ldp = (int32_t)di;
-                        a.q = (uint64_t)pin.off;
+                        a.q = (uint64_t)gi.off;
                         a.qkind = OPD_IN;
-                        a.ldq = (int32_t)dl;
+                        a.ldq = (int32_t)gi.ld;
                         a.K = (int32_t)dj;
                         tm = TMat{di, dl, hp.tmp, 0, member};
                         s.p = (uint64_t)hp.tmp;
@@ -502,9 +530,9 @@ static void build_pass(const dmrg_plan *plan, bool adjoint, LowStore *low, uint6
                         s.ldq = (int32_t)dk;
                         s.K = (int32_t)dl;
                     } else {  // T = G B [dj x dk];  gpsi += c A^T T
-                        a.p = (uint64_t)pin.off;
+                        a.p = (uint64_t)gi.off;
                         a.pkind = OPD_IN;
-                        a.ldp = (int32_t)dl;
+                        a.ldp = (int32_t)gi.ld;
                         a.q = U(rc.b.data);
                         a.qkind = OPD_ABS;
                         a.ldq = (int32_t)dk;
@@ -528,12 +556,12 @@ static void build_pass(const dmrg_plan *plan, bool adjoint, LowStore *low, uint6
             }
         }
         int seg_e = (int)hp.segs.size();
-        add_tiles(hp.B, po.dl, po.dr, po.off, po.off, seg_b, seg_e, d_b, (int)hp.diags.size(), member);
+        add_tiles(hp.B, go.rows, go.cols, go.off, go.off, go.ld, seg_b, seg_e, d_b, (int)hp.diags.size(), member);
     }
     int baseA = (int)hp.segs.size();
     hp.segs.insert(hp.segs.end(), segsA.begin(), segsA.end());
     for (const TMat &tm : tmats)
-        add_tiles(hp.A, tm.rows, tm.cols, tm.off, 0, baseA + tm.seg, baseA + tm.seg + 1, 0, 0, tm.member);
+        add_tiles(hp.A, tm.rows, tm.cols, tm.off, 0, tm.cols, baseA + tm.seg, baseA + tm.seg + 1, 0, 0, tm.member);
     sort_tasks(hp.A, hp.segs);
     sort_tasks(hp.B, hp.segs);
 }
@@ -574,6 +602,66 @@ static dmrg_status upload_pass(dmrg_plan *plan, HostPass &hp, PassSet &ps, hipSt
     return DMRG_OK;
 }
 
+static dmrg_status finish_plan(dmrg_plan *plan, int32_t prec, hipStream_t stream, const dmrg_problem *probs);
+
+// Preconditioner diagonal of a plan without LR problems: every record whose
+// input and output sub-matrices coincide has only square blocks, and adds
+// c w diag(A)[r] diag(B)[c] there.
+static dmrg_status diag_from_records(dmrg_plan *plan, hipStream_t stream) {
+    const int nout = (int)plan->out_geo.size();
+    std::vector<std::vector<DiagTerm>> per(nout);
+    auto slice = [](const OpBlock &b, uint64_t *addr, int32_t *stride) {
+        if (b.kind == DMRG_OP_IDENTITY) {
+            *addr = 0;
+            *stride = 0;
+        } else if (b.kind == DMRG_OP_DIAG) {
+            *addr = U(b.data);
+            *stride = 1;
+        } else {
+            *addr = U(b.data);
+            *stride = (int32_t)(b.rows + 1);
+        }
+    };
+    for (const Record &rc : plan->records) {
+        if (rc.oin != rc.oout) continue;
+        DiagTerm dt{};
+        dt.coef = rc.gterm;
+        dt.term = rc.gterm;
+        dt.w = rc.w;
+        slice(rc.a, &dt.vl, &dt.sl);
+        slice(rc.b, &dt.vr, &dt.sr);
+        per[rc.oout].push_back(dt);
+    }
+    std::vector<Task> tasks;
+    std::vector<DiagTerm> terms;
+    for (int q = 0; q < nout; ++q) {
+        const Geo &g = plan->out_geo[q];
+        const int d_b = (int)terms.size();
+        terms.insert(terms.end(), per[q].begin(), per[q].end());
+        if (g.rows <= 0 || g.cols <= 0) continue;
+        const int64_t tn = std::min<int64_t>(g.cols, 1024), tm = std::max<int64_t>(1, 1024 / tn);
+        for (int64_t r0 = 0; r0 < g.rows; r0 += tm)
+            for (int64_t c0 = 0; c0 < g.cols; c0 += tn) {
+                Task t{};
+                t.diag_begin = d_b;
+                t.diag_end = (int)terms.size();
+                t.c_off = g.off;
+                t.x_off = g.off;
+                t.ldc = (int32_t)g.ld;
+                t.row0 = (int32_t)r0;
+                t.col0 = (int32_t)c0;
+                t.m = (int32_t)std::min<int64_t>(tm, g.rows - r0);
+                t.n = (int32_t)std::min<int64_t>(tn, g.cols - c0);
+                t.member = plan->out_member[q];
+                tasks.push_back(t);
+            }
+    }
+    DMRG_TRY(upload(plan, terms, &plan->d_diag_terms, stream));
+    DMRG_TRY(upload(plan, tasks, &plan->d_diag_tasks, stream));
+    plan->n_diag_tasks = (int32_t)tasks.size();
+    return DMRG_OK;
+}
+
 dmrg_status build_plan(dmrg_plan *plan, int32_t nprob, const dmrg_problem *probs, int32_t prec,
                        hipStream_t stream) {
     plan->nprob = nprob;
@@ -595,9 +683,17 @@ dmrg_status build_plan(dmrg_plan *plan, int32_t nprob, const dmrg_problem *probs
             plan->pairs.push_back(q);
             plan->pair_member.push_back(p);
         }
+        for (const Pair &q : mp.pairs) {
+            plan->out_geo.push_back(Geo{base + q.off, q.dl, q.dr, q.dr});
+            plan->out_member.push_back(p);
+        }
         for (Record r : recs) {
             r.pin += pair_base;
             r.pout += pair_base;
+            r.oin += pair_base;
+            r.oout += pair_base;
+            r.gin.off += base;
+            r.gout.off += base;
             const Pair &in = plan->pairs[r.pin], &out = plan->pairs[r.pout];
             int64_t di = in.dl, dk = in.dr, dj = out.dl, dl = out.dr;
             bool da = r.a.kind == DMRG_OP_DENSE, db = r.b.kind == DMRG_OP_DENSE;
@@ -626,7 +722,14 @@ dmrg_status build_plan(dmrg_plan *plan, int32_t nprob, const dmrg_problem *probs
     plan->nterm_total = plan->term_off.back();
     plan->flop = flop;
     plan->bytes = opbytes + 16 * plan->n;
+    return finish_plan(plan, prec, stream, probs);
+}
 
+// Everything after the analysis: task lists of both directions, reduced-
+// precision copies, intermediate buffer, preconditioner-diagonal tasks (from
+// the LR problems when given, else from the records whose input and output
+// coincide) and the density tiles.
+static dmrg_status finish_plan(dmrg_plan *plan, int32_t prec, hipStream_t stream, const dmrg_problem *probs) {
     // ---- forward and adjoint passes in FP64
     HostPass f64, a64;
     build_pass(plan, false, nullptr, 0, f64);
@@ -694,7 +797,9 @@ dmrg_status build_plan(dmrg_plan *plan, int32_t nprob, const dmrg_problem *probs
     plan->owned.push_back(plan->d_tmp);
 
     // ---- preconditioner diagonal: per pair, sum_k c_k diag(A_k)(sl) (x) diag(B_k)(sr)
-    {
+    if (!probs) {
+        DMRG_TRY(diag_from_records(plan, stream));
+    } else {
         std::vector<Task> tasks;
         std::vector<DiagTerm> terms;
         for (int q = 0; q < (int)plan->pairs.size(); ++q) {
@@ -761,6 +866,204 @@ dmrg_status build_plan(dmrg_plan *plan, int32_t nprob, const dmrg_problem *probs
     return DMRG_OK;
 }
 
+// ------------------------------------------------------------------ l-1-1-r plans
+
+// One member of an l-1-1-r plan: pairs of the enlarged blocks, output
+// sub-matrices and records (offsets member-local).
+struct Member4 {
+    std::vector<Pair> pairs;
+    std::vector<Geo> outs;
+    std::vector<Record> recs;
+    int64_t n = 0, flop = 0;
+};
+
+static const char *SUB_NAME[4] = {"block l", "site 1", "site 2", "block r"};
+
+// Validation, records and sub-matrices of one four-subsystem problem (Eq. 13):
+// for every term, every sector quadruple of psi and every combination of the
+// four operators' blocks leaving it, one record per pair of non-zero site
+// matrix elements, acting on the [d_l x d_r] slice of fixed site indices.
+static dmrg_status analyse4(const dmrg_problem4 *p, Member4 *out, int gop_base, int gterm_base) {
+    if (!p) return set_error(DMRG_E_INVALID_ARG, "null problem");
+    for (int s = 0; s < 4; ++s) DMRG_TRY(check_space(p->space[s], SUB_NAME[s]));
+    const int rank = p->space[0].rank;
+    for (int s = 1; s < 4; ++s)
+        if (p->space[s].rank != rank) return set_error(DMRG_E_INVALID_ARG, "label ranks differ");
+    if (!p->target) return set_error(DMRG_E_INVALID_ARG, "null target label");
+    if (p->nterm < 0 || (p->nterm && !p->terms)) return set_error(DMRG_E_INVALID_ARG, "missing term array");
+    for (int s = 0; s < 4; ++s) {
+        if (p->nop[s] < 0 || (p->nop[s] && !p->ops[s]))
+            return set_error(DMRG_E_INVALID_ARG, "%s: missing operator array", SUB_NAME[s]);
+        for (int i = 0; i < p->nop[s]; ++i) DMRG_TRY(check_op(p->space[s], p->ops[s][i], SUB_NAME[s], i));
+    }
+    for (int s = 1; s <= 2; ++s)
+        for (int i = 0; i < p->space[s].nsec; ++i)
+            if (p->space[s].dim[i] > 64)
+                return set_error(DMRG_E_UNSUPPORTED, "%s: sector %d has more than 64 states", SUB_NAME[s], i);
+    for (int k = 0; k < p->nterm; ++k) {
+        const dmrg_term4 &t = p->terms[k];
+        const int idx[4] = {t.a, t.b, t.c, t.d};
+        for (int s = 0; s < 4; ++s)
+            if (idx[s] < 0 || idx[s] >= p->nop[s])
+                return set_error(DMRG_E_INVALID_ARG, "term %d: operator index out of range", k);
+    }
+    const Enlarged EL = enlarged_space(p->space[0], p->space[1]);
+    const Enlarged ER = enlarged_space(p->space[2], p->space[3]);
+    // pairs of the enlarged blocks (LR layout)
+    std::vector<int> by_left(EL.nsec(), -1);
+    std::vector<int32_t> want(rank);
+    int64_t off = 0;
+    for (int i = 0; i < EL.nsec(); ++i) {
+        for (int c = 0; c < rank; ++c) want[c] = p->target[c] - EL.label[(size_t)i * rank + c];
+        const int j = ER.find(want.data());
+        if (j < 0) continue;
+        by_left[i] = (int)out->pairs.size();
+        out->pairs.push_back(Pair{i, j, EL.dim[i], ER.dim[j], off});
+        off += EL.dim[i] * ER.dim[j];
+    }
+    out->n = off;
+    const dmrg_space &sl = p->space[0], &s1 = p->space[1], &s2 = p->space[2], &sr = p->space[3];
+    // output sub-matrices: (pair, left combination, right combination, i1, i2)
+    std::map<std::tuple<int, int, int, int, int, int>, int> geo_of;  // (s_l, s_1, s_2, s_r, i1, i2)
+    std::vector<std::tuple<int, int, int, int>> quads;               // every quadruple of psi, in order
+    std::vector<int> quad_pair;
+    for (int pi = 0; pi < (int)out->pairs.size(); ++pi) {
+        const Pair &pr = out->pairs[pi];
+        for (const Combo &cl : EL.combos[pr.sl])
+            for (const Combo &cr : ER.combos[pr.sr]) {
+                quads.emplace_back(cl.s, cl.f, cr.s, cr.f);
+                quad_pair.push_back(pi);
+                const int64_t d1 = s1.dim[cl.f], d2 = s2.dim[cr.s], dl = sl.dim[cl.s], dr = sr.dim[cr.f];
+                for (int64_t i1 = 0; i1 < d1; ++i1)
+                    for (int64_t i2 = 0; i2 < d2; ++i2) {
+                        geo_of[{cl.s, cl.f, cr.s, cr.f, (int)i1, (int)i2}] = (int)out->outs.size();
+                        out->outs.push_back(Geo{pr.off + (cl.off + i1) * pr.dr + cr.off + i2 * dr, dl, dr, d1 * pr.dr});
+                    }
+            }
+    }
+    // operators: blocks l and r resolved on the device data, sites read on the host
+    std::vector<BySrc> L(p->nop[0]), R(p->nop[3]);
+    for (int i = 0; i < p->nop[0]; ++i) L[i] = resolve(sl, p->ops[0][i], gop_base + i);
+    for (int i = 0; i < p->nop[3]; ++i) R[i] = resolve(sr, p->ops[3][i], gop_base + p->nop[0] + i);
+    std::vector<std::vector<HostBlock>> S1(p->nop[1]), S2(p->nop[2]);
+    for (int i = 0; i < p->nop[1]; ++i) S1[i] = host_blocks(s1, p->ops[1][i]);
+    for (int i = 0; i < p->nop[2]; ++i) S2[i] = host_blocks(s2, p->ops[2][i]);
+    auto lab = [&](const dmrg_space &sp, int s, int c) { return sp.label[(size_t)s * rank + c]; };
+    for (int k = 0; k < p->nterm; ++k) {
+        const dmrg_term4 &t = p->terms[k];
+        for (size_t qi = 0; qi < quads.size(); ++qi) {
+            const int ql = std::get<0>(quads[qi]), q1 = std::get<1>(quads[qi]), q2 = std::get<2>(quads[qi]),
+                      qr = std::get<3>(quads[qi]);
+            for (const OpBlock &a : L[t.a][ql])
+                for (const HostBlock &b1 : S1[t.b]) {
+                    if (b1.src != q1) continue;
+                    for (const HostBlock &b2 : S2[t.c]) {
+                        if (b2.src != q2) continue;
+                        for (const OpBlock &b : R[t.d][qr]) {
+                            bool ok = true;
+                            for (int c = 0; c < rank; ++c)
+                                ok &= lab(sl, a.dst, c) + lab(s1, b1.dst, c) + lab(s2, b2.dst, c) + lab(sr, b.dst, c) ==
+                                      p->target[c];
+                            if (!ok)
+                                return set_error(DMRG_E_SECTOR, "term %d leaves the target sector", k);
+                            const int eL = EL.where[a.dst][b1.dst], eR = ER.where[b2.dst][b.dst];
+                            if (eL < 0 || eR < 0) continue;  // an empty output block
+                            const int po = by_left[eL];
+                            if (po < 0 || out->pairs[po].sr != eR) continue;
+                            for (int64_t o1 = 0; o1 < b1.rows; ++o1)
+                                for (int64_t i1 = 0; i1 < b1.cols; ++i1) {
+                                    const double w1 = b1.m[(size_t)(o1 * b1.cols + i1)];
+                                    if (w1 == 0.0) continue;
+                                    for (int64_t o2 = 0; o2 < b2.rows; ++o2)
+                                        for (int64_t i2 = 0; i2 < b2.cols; ++i2) {
+                                            const double w2 = b2.m[(size_t)(o2 * b2.cols + i2)];
+                                            if (w2 == 0.0) continue;
+                                            Record r{};
+                                            r.term = k;
+                                            r.gterm = gterm_base + k;
+                                            r.pin = quad_pair[qi];
+                                            r.pout = po;
+                                            r.a = a;
+                                            r.b = b;
+                                            r.oin = geo_of.at({ql, q1, q2, qr, (int)i1, (int)i2});
+                                            r.oout = geo_of.at({a.dst, b1.dst, b2.dst, b.dst, (int)o1, (int)o2});
+                                            r.gin = out->outs[r.oin];
+                                            r.gout = out->outs[r.oout];
+                                            r.w = w1 * w2;
+                                            const bool da = a.kind == DMRG_OP_DENSE, db = b.kind == DMRG_OP_DENSE;
+                                            const int64_t di = r.gin.rows, dk = r.gin.cols, dj = r.gout.rows,
+                                                          dl = r.gout.cols;
+                                            if (da && db) {
+                                                const int64_t cl = dj * di * dk + dj * dk * dl,
+                                                              cr = di * dk * dl + dj * di * dl;
+                                                r.order = cr < cl ? 1 : 0;
+                                                out->flop += 2 * std::min(cl, cr);
+                                            } else {
+                                                r.order = 2;
+                                                out->flop += da ? 2 * dj * di * dk : (db ? 2 * di * dk * dl : 2 * dj * dl);
+                                            }
+                                            out->recs.push_back(r);
+                                        }
+                                }
+                        }
+                    }
+                }
+        }
+    }
+    return DMRG_OK;
+}
+
+static dmrg_status build_plan_l11r(dmrg_plan *plan, int32_t nprob, const dmrg_problem4 *probs, hipStream_t stream) {
+    plan->nprob = nprob;
+    plan->prec = DMRG_F64;
+    plan->member_off.assign(1, 0);
+    plan->term_off.assign(1, 0);
+    int gop = 0;
+    std::set<std::pair<int, int>> used_blocks, used_slices;
+    int64_t flop = 0, opbytes = 0;
+    for (int p = 0; p < nprob; ++p) {
+        Member4 m4;
+        DMRG_TRY(analyse4(&probs[p], &m4, gop, plan->term_off.back()));
+        const int pair_base = (int)plan->pairs.size(), out_base = (int)plan->out_geo.size();
+        const int64_t base = plan->member_off.back();
+        for (Pair q : m4.pairs) {
+            q.off += base;
+            plan->pairs.push_back(q);
+            plan->pair_member.push_back(p);
+        }
+        for (Geo g : m4.outs) {
+            g.off += base;
+            plan->out_geo.push_back(g);
+            plan->out_member.push_back(p);
+        }
+        for (Record r : m4.recs) {
+            r.pin += pair_base;
+            r.pout += pair_base;
+            r.oin += out_base;
+            r.oout += out_base;
+            r.gin.off += base;
+            r.gout.off += base;
+            for (const OpBlock *b : {&r.a, &r.b}) {
+                if (b->kind == DMRG_OP_DENSE) {
+                    if (used_blocks.insert({b->op, b->blk}).second) opbytes += 8 * b->rows * b->cols;
+                } else if (b->kind == DMRG_OP_DIAG) {
+                    if (used_slices.insert({b->op, b->src}).second) opbytes += 8 * b->rows;
+                }
+            }
+            plan->records.push_back(r);
+        }
+        flop += m4.flop;
+        plan->member_off.push_back(base + m4.n);
+        plan->term_off.push_back(plan->term_off.back() + probs[p].nterm);
+        gop += probs[p].nop[0] + probs[p].nop[3];
+    }
+    plan->n = plan->member_off.back();
+    plan->nterm_total = plan->term_off.back();
+    plan->flop = flop;
+    plan->bytes = opbytes + 16 * plan->n;
+    return finish_plan(plan, DMRG_F64, stream, nullptr);
+}
+
 dmrg_status plan_free(dmrg_plan *plan) {
     davidson_free(plan);
     for (void *p : plan->owned) (void)hipFree(p);
@@ -825,6 +1128,36 @@ dmrg_status dmrg_plan_create(dmrg_plan **out, int32_t nprob, const dmrg_problem 
         return set_error(DMRG_E_HIP, "hipGetDevice failed: %s", hipGetErrorString(e));
     }
     dmrg_status st = build_plan(plan, nprob, probs, prec, (hipStream_t)stream);
+    if (st < 0) {
+        plan_free(plan);
+        delete plan;
+        return st;
+    }
+    *out = plan;
+    return DMRG_OK;
+}
+
+dmrg_status dmrg_plan_create_l11r(dmrg_plan **out, int32_t nprob, const dmrg_problem4 *probs, void *stream) {
+    clear_error();
+    if (!out) return set_error(DMRG_E_INVALID_ARG, "null output pointer");
+    *out = nullptr;
+    if (nprob < 1 || !probs) return set_error(DMRG_E_INVALID_ARG, "need nprob >= 1 problems");
+    for (int p = 0; p < nprob; ++p) {  // host validation first: no GPU is touched for invalid input
+        Member4 m4;
+        dmrg_status st = analyse4(&probs[p], &m4, 0, 0);
+        if (st < 0) {
+            std::string m = g_last_error;
+            return set_error(st, "problem %d: %s", p, m.c_str());
+        }
+    }
+    dmrg_plan *plan = new (std::nothrow) dmrg_plan();
+    if (!plan) return set_error(DMRG_E_NOMEM, "host allocation failed");
+    hipError_t e = hipGetDevice(&plan->device);
+    if (e != hipSuccess) {
+        delete plan;
+        return set_error(DMRG_E_HIP, "hipGetDevice failed: %s", hipGetErrorString(e));
+    }
+    dmrg_status st = build_plan_l11r(plan, nprob, probs, (hipStream_t)stream);
     if (st < 0) {
         plan_free(plan);
         delete plan;

@@ -527,12 +527,40 @@ __device__ __forceinline__ double diag_sum(const DiagTerm *__restrict__ diags, i
     double val = 0.0;
     for (int d = d0; d < d1; ++d) {
         const DiagTerm dt = diags[d];
-        double w = (coef ? coef[dt.coef] : 1.0) * x;
+        double w = (coef ? coef[dt.coef] : 1.0) * dt.w * x;
         if (dt.vl) w *= ((const double *)(uintptr_t)dt.vl)[rr * dt.sl];
         if (dt.vr) w *= ((const double *)(uintptr_t)dt.vr)[cc * dt.sr];
         val += w;
     }
     return val;
+}
+
+// Copy segment (fused = 2) on a tile: v = pscale[r] qscale[c] X(r, c) for the
+// tile's elements in the accumulator layout (zero outside the tile), X the
+// input sub-matrix at s.q with rows s.ldq apart.  FP64 in every precision.
+template <int PREC, int NS>
+__device__ __forceinline__ void copy_item(double (&v)[NS][NS][4], const Seg &s, const Task &tk,
+                                          const double *__restrict__ in) {
+    const int lane = threadIdx.x & 63;
+    const int r16 = lane & 15, g = lane >> 4;
+    const double *X = in + s.q;
+    const double *vl = (const double *)(uintptr_t)s.pscale, *vr = (const double *)(uintptr_t)s.qscale;
+#pragma unroll
+    for (int a = 0; a < NS; ++a)
+#pragma unroll
+        for (int b = 0; b < NS; ++b)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int r = a * 16 + Tr<PREC>::row(g, e), c = b * 16 + r16;
+                double x = 0.0;
+                if (r < tk.m && c < tk.n) {
+                    const int64_t rr = tk.row0 + r, cc = tk.col0 + c;
+                    x = X[rr * s.ldq + cc];
+                    if (vl) x *= vl[rr];
+                    if (vr) x *= vr[cc];
+                }
+                v[a][b][e] = x;
+            }
 }
 
 // MODE 0: write the intermediate (store_t) of stage A.
@@ -566,8 +594,11 @@ __device__ __forceinline__ void tasks_run(const Task *__restrict__ tasks, int nt
             for (int si = tk.seg_begin + wave; si < tk.seg_end; si += PW) {
                 const Seg s = segs[si];
                 typename T::acc_t acc[2][2];
+                double cv[NS][NS][4];
                 zero_acc<PREC>(acc);
-                if (s.fused) {
+                if (s.fused == 2) {
+                    copy_item<PREC, NS>(cv, s, tk, in);
+                } else if (s.fused) {
                     fused_item<PREC, NS>(acc, s, tk, in, &red[wave][0][0], nsc);
                 } else {
                     // one wavefront runs every work item of the segment (PW-strided item loop, 4 passes)
@@ -583,10 +614,10 @@ __device__ __forceinline__ void tasks_run(const Task *__restrict__ tasks, int nt
                         for (int v = 0; v < 4; ++v) {
                             const int r = a * 16 + T::row(g, v), c = b * 16 + r16;
                             if (a < nsr && b < nsc && r < tk.m && c < tk.n)
-                                part += (double)acc[a][b][v] *
+                                part += (s.fused == 2 ? cv[a][b][v] : (double)acc[a][b][v]) *
                                         gbar[tk.c_off + (int64_t)(tk.row0 + r) * tk.ldc + tk.col0 + c];
                         }
-                part = wave_sum(part);
+                part = wave_sum(part) * s.w;
                 if (lane == 0) partials[tk.part0 + (si - tk.seg_begin)] = part;
             }
             const int nseg = tk.seg_end - tk.seg_begin;
@@ -633,19 +664,30 @@ __device__ __forceinline__ void tasks_run(const Task *__restrict__ tasks, int nt
             const int first = (wave - q % PW + PW) % PW;  // first item of this segment owned by this wave
             if (first < nit) {
                 const Seg s = segs[si];
-                typename T::acc_t acc[2][2];
-                zero_acc<PREC>(acc);
-                if (fused)
-                    fused_item<PREC, NS>(acc, s, tk, in, &red[wave][0][0], nsc);
-                else
-                    seg_dispatch<PREC, NS>(acc, s, tk, in, tmp, nsr, nsc, first, nit);
-                const double c = s.coef >= 0 ? coef[s.coef] : 1.0;
+                const double c = (s.coef >= 0 ? coef[s.coef] : 1.0) * s.w;
+                if (s.fused == 2) {  // copy segment, summed in FP64
+                    double cv[NS][NS][4];
+                    copy_item<PREC, NS>(cv, s, tk, in);
 #pragma unroll
-                for (int a = 0; a < NS; ++a)
+                    for (int a = 0; a < NS; ++a)
 #pragma unroll
-                    for (int b = 0; b < NS; ++b)
+                        for (int b = 0; b < NS; ++b)
 #pragma unroll
-                        for (int v = 0; v < 4; ++v) tot[a][b][v] += c * (double)acc[a][b][v];
+                            for (int v = 0; v < 4; ++v) tot[a][b][v] += c * cv[a][b][v];
+                } else {
+                    typename T::acc_t acc[2][2];
+                    zero_acc<PREC>(acc);
+                    if (fused)
+                        fused_item<PREC, NS>(acc, s, tk, in, &red[wave][0][0], nsc);
+                    else
+                        seg_dispatch<PREC, NS>(acc, s, tk, in, tmp, nsr, nsc, first, nit);
+#pragma unroll
+                    for (int a = 0; a < NS; ++a)
+#pragma unroll
+                        for (int b = 0; b < NS; ++b)
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) tot[a][b][v] += c * (double)acc[a][b][v];
+                }
             }
             q += nit;
         }
@@ -802,7 +844,7 @@ __global__ __launch_bounds__(256) void k_diag_terms(const Task *__restrict__ tas
                 const DiagTerm dt = diags[d0 + threadIdx.x];
                 D.vl[threadIdx.x] = (const double *)(uintptr_t)dt.vl;
                 D.vr[threadIdx.x] = (const double *)(uintptr_t)dt.vr;
-                D.c[threadIdx.x] = coef[dt.coef];
+                D.c[threadIdx.x] = coef[dt.coef] * dt.w;
                 D.sl[threadIdx.x] = dt.sl;
                 D.sr[threadIdx.x] = dt.sr;
             }
