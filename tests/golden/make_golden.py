@@ -6,7 +6,8 @@ exact_energies.json: each value is a full-chain exact diagonalization
 ``oracle.models``.  arpack_energies.json: the ground energies of the
 synthetic superblock workloads (Heisenberg m=1024, Hubbard m=2048, J1-J2
 m=1024) by ARPACK's implicitly restarted Lanczos (scipy ``eigsh``) with the
-oracle's sector-form projection (Eq. 11) as the only access to H.  None comes
+oracle's sector-form projection (Eq. 11) as the only access to H, and the
+four lowest energies of the Heisenberg and Hubbard workloads the same way.  None comes
 from the HIP library.
 """
 import json
@@ -50,6 +51,9 @@ def main():
     arp = {}
     for cfg in (2, 3, 5):
         arp[gen.CONFIG_NAMES[cfg]] = davidson.ground_state_arpack(gen.config(cfg), tol=1e-15)[0]
+    for cfg in (2, 3):  # the four lowest, for the block Davidson-Liu solver
+        arp[gen.CONFIG_NAMES[cfg] + "_lowest4"] = [float(x) for x in davidson.lowest_arpack(gen.config(cfg), 4,
+                                                                                             tol=1e-15)]
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "arpack_energies.json")
     with open(path, "w") as f:
         json.dump({"source": "gen.config + oracle.projection.project_sectors + scipy eigsh (ARPACK, "

@@ -138,3 +138,53 @@ def test_hellmann_feynman_matches_finite_differences_j1j2():
         Ep = davidson.ground_state_dense(p, basis @ (np.array([1.0, 1.0, 0.5]) + e))[0]
         Em = davidson.ground_state_dense(p, basis @ (np.array([1.0, 1.0, 0.5]) - e))[0]
         assert g[j] == pytest.approx((Ep - Em) / (2 * h), rel=1e-7, abs=1e-9)
+
+
+# ------------------------------------------------------------------ block Davidson-Liu
+
+
+@pytest.mark.parametrize("b", [1, 2, 4])
+def test_block_davidson_ten_site_chain_lapack(b):
+    """The b lowest eigenpairs of the exact 10-site chain: LAPACK's eigenvalues,
+    orthonormal Ritz vectors, residuals measured by the projection."""
+    p = gen.config(1)
+    n = _n(p)
+    X0 = np.random.default_rng(b).standard_normal((n, b))
+    r = davidson.lowest_block_davidson(p, X0, tol=1e-10)
+    assert r.converged
+    w = np.linalg.eigvalsh(projection.projected_hamiltonian(p))[:b]
+    assert np.max(np.abs(r.energies - w)) <= 1e-10
+    assert np.allclose(r.X.T @ r.X, np.eye(b), atol=1e-12)
+    for j in range(b):
+        res = projection.project_sectors(p, r.X[:, j]) - r.energies[j] * r.X[:, j]
+        assert np.linalg.norm(res) <= 2e-10
+
+
+def test_block_davidson_small_synthetic_lapack():
+    p = gen.heisenberg_synthetic(96, seed=3)
+    n = _n(p)
+    r = davidson.lowest_block_davidson(p, np.random.default_rng(0).standard_normal((n, 3)), tol=1e-10, kmax=18)
+    assert r.converged and r.restarts >= 1
+    w = np.linalg.eigvalsh(projection.projected_hamiltonian(p))[:3]
+    assert np.max(np.abs(r.energies - w)) <= 1e-10
+
+
+def test_block_of_one_is_the_single_vector_method():
+    p = gen.config(1)
+    x0 = gen.start_vector(_n(p), 3)
+    a = davidson.ground_state_davidson(p, x0, tol=1e-11)
+    b = davidson.lowest_block_davidson(p, x0[:, None], tol=1e-11)
+    assert a.converged and b.converged
+    assert abs(a.energy - b.energies[0]) <= 1e-12
+
+
+@pytest.mark.slow
+def test_block_davidson_hubbard_m2048_arpack():
+    """The four lowest energies of the Hubbard m=2048 workload: block
+    Davidson-Liu vs the stored ARPACK values (tests/golden/make_golden.py)."""
+    p = gen.config(3)
+    n = _n(p)
+    r = davidson.lowest_block_davidson(p, np.random.default_rng(1).standard_normal((n, 4)), tol=1e-10)
+    assert r.converged
+    ref = np.array(ARPACK["hubbard_m2048_lowest4"])
+    assert np.max(np.abs(r.energies - ref)) <= 1e-10
