@@ -216,6 +216,42 @@ void dmrg_davidson_default_opts(dmrg_davidson_opts *opts);
 dmrg_status dmrg_davidson(dmrg_plan *plan, const double *coef, const dmrg_davidson_opts *opts,
                           double *psi, double *energy, dmrg_davidson_info *info, void *stream);
 
+/* Block Davidson-Liu options (the block version of Davidson's method named
+ * in Sec. "Runtime & Parallelism"; readings in the design notes). */
+typedef struct {
+    double tol;           /* stop when every ||r_j||_2 <= tol, default 1e-10 */
+    int32_t nroots;       /* b: the lowest b eigenpairs, 1..8, default 4 */
+    int32_t kmax;         /* basis limit, 3 b..48 (and <= n), default 32 */
+    int32_t kmin;         /* Ritz vectors kept at a restart (at least 2 b), default 0 = 2 b */
+    int32_t max_iter;     /* default 500 */
+    double precond_floor; /* |D - sigma| floor, default 1e-3 */
+    int32_t chunk;        /* iterations enqueued between host checks, default 4 */
+} dmrg_block_opts;
+
+typedef struct {
+    int32_t iterations, projections, restarts, converged;
+} dmrg_block_info;
+
+void dmrg_block_default_opts(dmrg_block_opts *opts);
+
+/* The nroots lowest eigenpairs of a single-superblock plan by block
+ * Davidson-Liu on the device (FP64): per iteration one corrected residual
+ * r_j / (D - sigma_j) per unconverged root (sigma_0 = min(theta_0, min D),
+ * sigma_j = theta_j otherwise), orthogonalized against the basis by two
+ * classical passes and among themselves by Cholesky QR twice (a vector that
+ * keeps less than 1e-8 of its norm is dropped), projected as a block, the
+ * Rayleigh matrix extended by FP64 MFMA tall-skinny products and diagonalized
+ * by cyclic Jacobi; thick restart to max(kmin, 2 nroots) Ritz vectors.
+ *  X: device FP64 [nroots][n] (vector j at X + j n): in, the start block (any
+ *     linearly independent columns); out, the Ritz vectors (orthonormal).
+ *  energies, residuals: host [nroots] (may be NULL), ascending.
+ * Sizes that change with the iterations stay on the device; the host waits
+ * once per `chunk` iterations.  Returns DMRG_W_NOT_CONVERGED after max_iter,
+ * DMRG_E_NONFINITE for a non-finite Ritz value, DMRG_E_UNSUPPORTED for a
+ * batched plan. */
+dmrg_status dmrg_block_davidson(dmrg_plan *plan, const double *coef, const dmrg_block_opts *opts, double *X,
+                                double *energies, double *residuals, dmrg_block_info *info, void *stream);
+
 /* Diagonal of H_SB in the target sector (the Davidson preconditioner),
  * device FP64 [n].  Asynchronous. */
 dmrg_status dmrg_diagonal(dmrg_plan *plan, const double *coef, double *diag, void *stream);

@@ -437,6 +437,30 @@ class Plan:
         return psi, np.array(E[:]), [infos[i].as_dict() for i in range(nprob)], int(st)
 
 
+    def block_davidson(self, X0, nroots: Optional[int] = None, coef=None, tol: float = 1e-10, kmax: int = 32,
+                       kmin: int = 0, max_iter: int = 500, precond_floor: float = 1e-3, chunk: int = 4):
+        """The nroots lowest eigenpairs (dmrg_block_davidson).  X0: a [nroots, n]
+        float64 CUDA tensor (row j = start vector j).  Returns (X [nroots, n]
+        Ritz vectors, energies, residuals, info dict, status)."""
+        import torch
+
+        b = X0.shape[0] if nroots is None else nroots
+        if X0.dim() != 2 or X0.shape[0] != b or X0.shape[1] != self.n:
+            raise ValueError("X0 must be [nroots, n]")
+        c = self._coef(coef)
+        X = X0.clone().contiguous()
+        o = N.BlockOpts(tol, b, kmax, kmin, max_iter, precond_floor, chunk)
+        E = (ctypes.c_double * b)()
+        R = (ctypes.c_double * b)()
+        info = N.BlockInfo()
+        st = self._lib.dmrg_block_davidson(self._h, self._vec(c, "coef"), ctypes.byref(o), self._vec(X, "X"), E, R,
+                                           ctypes.byref(info), _stream(self.device))
+        if st < 0:
+            N.check(st)
+        torch.cuda.current_stream(self.device).synchronize()
+        return X, np.array(E[:]), np.array(R[:]), info.as_dict(), int(st)
+
+
 # ---------------------------------------------------------------- autograd
 
 

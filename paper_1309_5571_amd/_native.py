@@ -74,6 +74,18 @@ class Place(ctypes.Structure):
                 ("ld_dst", c_int32), ("coef", c_double), ("identity", c_int32)]
 
 
+class BlockOpts(ctypes.Structure):
+    _fields_ = [("tol", c_double), ("nroots", c_int32), ("kmax", c_int32), ("kmin", c_int32), ("max_iter", c_int32),
+                ("precond_floor", c_double), ("chunk", c_int32)]
+
+
+class BlockInfo(ctypes.Structure):
+    _fields_ = [("iterations", c_int32), ("projections", c_int32), ("restarts", c_int32), ("converged", c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class KronTerm(ctypes.Structure):
     _fields_ = [("out", c_int32), ("a", c_int32), ("b", c_int32), ("coef", c_double)]
 
@@ -130,6 +142,9 @@ SIGNATURES = {
                                POINTER(KronTerm), c_int32, POINTER(EnlargeSizes), c_void_p, c_void_p, c_void_p,
                                c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "dmrg_plan_create_l11r": (c_int32, [POINTER(c_void_p), c_int32, POINTER(Problem4), c_void_p]),
+    "dmrg_block_default_opts": (None, [POINTER(BlockOpts)]),
+    "dmrg_block_davidson": (c_int32, [c_void_p, c_void_p, POINTER(BlockOpts), c_void_p, POINTER(c_double),
+                                      POINTER(c_double), POINTER(BlockInfo), c_void_p]),
     "dmrg_plan_destroy": (None, [c_void_p]),
     "dmrg_last_error": (c_char_p, []),
     "dmrg_version": (c_char_p, []),

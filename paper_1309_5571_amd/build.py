@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libdmrg.so")
 SOURCES = ["plan.cpp", "enlarge.cpp", "project.hip", "davidson.hip", "density.hip", "eigh.hip", "renorm.hip",
-           "gemv_noalloc.hip"]
+           "block.hip", "gemv_noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

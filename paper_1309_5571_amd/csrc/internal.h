@@ -158,6 +158,7 @@ struct ConvJob {
 };
 
 struct DavidsonWork;
+struct BlockWork;
 
 constexpr int KM = 48;  // largest Davidson subspace (kmax)
 
@@ -213,6 +214,7 @@ struct dmrg_plan {
     void *d_rho_tasks = nullptr;
     int32_t n_rho_tasks = 0;
     dmrg::DavidsonWork *dav = nullptr;
+    dmrg::BlockWork *blk = nullptr;  // block Davidson-Liu workspace
 };
 
 namespace dmrg {
@@ -238,6 +240,8 @@ dmrg_status launch_convert_jobs(const ConvJob *jobs, int njob, int prec, hipStre
 dmrg_status launch_diagonal(dmrg_plan *plan, const double *coef, double *diag, hipStream_t s);
 // davidson.hip
 dmrg_status davidson_free(dmrg_plan *plan);
+// block.hip
+dmrg_status block_free(dmrg_plan *plan);
 // density.hip: output offsets and tile tasks of the reduced density matrices
 dmrg_status build_density(dmrg_plan *plan, hipStream_t s);
 }  // namespace dmrg

@@ -1066,6 +1066,7 @@ static dmrg_status build_plan_l11r(dmrg_plan *plan, int32_t nprob, const dmrg_pr
 
 dmrg_status plan_free(dmrg_plan *plan) {
     davidson_free(plan);
+    block_free(plan);
     for (void *p : plan->owned) (void)hipFree(p);
     plan->owned.clear();
     return DMRG_OK;
