@@ -157,6 +157,16 @@ dmrg_status dmrg_plan_records(const dmrg_plan *plan, int32_t *term, int32_t *pai
 dmrg_status dmrg_project(dmrg_plan *plan, int32_t prec, const double *coef, const double *psi,
                          double *y, void *stream);
 
+/* y_v = H_SB psi_v for nvec vectors in FP64 (the block projection of block
+ * Davidson-Liu, Sec. "Runtime & Parallelism"): vector v at psi + v ldpsi,
+ * result at y + v ldy (ldpsi, ldy >= n).  Groups of four vectors run as one
+ * launch in which every output tile loads each operator fragment once for
+ * all four (plans whose tiles fit 16 x 16; other plans take one launch per
+ * vector).  Same results as dmrg_project up to the order of the FP64 sums.
+ * psi and y must not overlap.  Asynchronous on stream. */
+dmrg_status dmrg_project_block(dmrg_plan *plan, int32_t nvec, const double *coef, const double *psi,
+                               int64_t ldpsi, double *y, int64_t ldy, void *stream);
+
 /* Adjoint of dmrg_project with respect to psi and coef, in FP64:
  *  gpsi  = sum_k c_k (A_k^T (x) B_k^T) gbar     (device [n]; may be NULL)
  *  gcoef[k] = <gbar, (A_k (x) B_k) psi>          (device [total terms]; may be NULL)

@@ -368,6 +368,18 @@ class Plan:
                                        self._vec(y, "y"), _stream(self.device)))
         return y
 
+    def project_block(self, X, coef=None, out=None):
+        """Y[v] = H X[v] for a [nvec, n] float64 CUDA tensor (dmrg_project_block)."""
+        import torch
+
+        c = self._coef(coef)
+        if X.dim() != 2 or X.shape[1] != self.n:
+            raise ValueError("X must be [nvec, n]")
+        Y = torch.empty_like(X) if out is None else out
+        N.check(self._lib.dmrg_project_block(self._h, X.shape[0], self._vec(c, "coef"), self._vec(X, "X"),
+                                             X.stride(0), self._vec(Y, "Y"), Y.stride(0), _stream(self.device)))
+        return Y
+
     def backward_raw(self, psi, gbar, coef=None, want_psi: bool = True, want_coef: bool = True):
         import torch
 

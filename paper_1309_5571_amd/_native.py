@@ -122,6 +122,7 @@ SIGNATURES = {
                                     POINTER(c_int32)]),
     "dmrg_project": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]),
     "dmrg_project_backward": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "dmrg_project_block": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_int64, c_void_p, c_int64, c_void_p]),
     "dmrg_davidson_default_opts": (None, [POINTER(DavidsonOpts)]),
     "dmrg_davidson": (c_int32, [c_void_p, c_void_p, POINTER(DavidsonOpts), c_void_p, POINTER(c_double),
                                 POINTER(DavidsonInfo), c_void_p]),

@@ -152,17 +152,51 @@ __global__ __launch_bounds__(256) void k_blk_tn(const BlkState *__restrict__ st,
     }
 }
 
+// out[e] = sum over q < nblk of part[q * stride + idx(e)] for e < nent, by all
+// threads of the block: each entry gets an aligned group of G lanes (the
+// largest power of two with G nent <= blockDim), every lane sums every G-th
+// block with four loads in flight, and the group combines its lanes by DPP.
+// The order of the sums is fixed, so every call gives the same bits.
+template <class Idx, class Out>
+__device__ __forceinline__ void sum_partials(const double *__restrict__ part, int64_t stride, int nblk, int nent,
+                                             Idx idx, Out out) {
+    const int nt = blockDim.x;
+    int G = 64;
+    while (G > 1 && G * nent > nt) G >>= 1;
+    const int per = nt / G;  // entries per pass
+    const int lane_g = threadIdx.x % G, slot = threadIdx.x / G;
+    for (int e0 = 0; e0 < nent; e0 += per) {
+        const int e = e0 + slot;
+        const bool ok = e < nent;
+        const int64_t base = ok ? idx(e) : 0;
+        double a[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int q = lane_g; q < nblk; q += 4 * G) {
+            double v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int qq = q + u * G;
+                v[u] = (ok && qq < nblk) ? part[(int64_t)qq * stride + base] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) a[u] += v[u];
+        }
+        const double sum = group_sum((a[0] + a[1]) + (a[2] + a[3]), G);
+        if (ok && lane_g == 0) out(e, sum);
+    }
+}
+
 // Sum of the partial products over the blocks, in block order, into S.S
 // (row j, column c); one workgroup.
+template <int MODE>
 __global__ __launch_bounds__(256) void k_blk_reduce(BlkState *__restrict__ st, const double *__restrict__ part,
-                                                    int nblk) {
+                                                    int nblk, int b) {
     BlkState &S = *st;
     if (!S.active) return;
-    for (int i = threadIdx.x; i < BK * BB; i += 256) {
-        double s = 0.0;
-        for (int q = 0; q < nblk; ++q) s += part[(size_t)q * BK * BB + i];
-        S.S[i] = s;
-    }
+    const int ka = MODE == TN_ORTH ? S.k : b;
+    for (int i = threadIdx.x; i < BK * BB; i += 256) S.S[i] = 0.0;
+    __syncthreads();
+    sum_partials(part, BK * BB, nblk, ka * b, [&](int e) { return (int64_t)(e / b) * BB + e % b; },
+                 [&](int e, double v) { S.S[(e / b) * BB + e % b] = v; });
 }
 
 // ------------------------------------------------------------------ row kernels
@@ -300,30 +334,43 @@ __global__ __launch_bounds__(BTPB) void k_blk_restart(const BlkState *__restrict
 
 // ------------------------------------------------------------------ small dense steps (one workgroup)
 
-// Cyclic Jacobi on the symmetric k x k matrix A (LDS, leading dimension BK)
-// with eigenvectors U: round-robin pairs, all disjoint rotations of a round
-// applied together (rows, then columns); rotations below tol skipped; at most
-// 40 sweeps.  Then eigenvalues ascending with their columns.
+// Ordering of LDS accesses between the lanes of one wavefront.
+__device__ __forceinline__ void wsync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Cyclic Jacobi on the symmetric k x k matrix A (LDS, leading dimension
+// BK + 1) with eigenvectors U, by the whole workgroup: round-robin pairs, all
+// disjoint rotations of a step applied together (rows, then columns); a step
+// without a rotation costs one barrier (its flag alternates with the next
+// step's); rotations with |a_pq| <= 1e-15 ||A||_F are skipped; at most 40
+// sweeps.  Then eigenvalues ascending (ties by index): w[r] and the column
+// perm[r] of U.
 __device__ void blk_jacobi(int k, double (*A)[BK + 1], double (*U)[BK + 1], double *cs, double *sn, int *perm,
                            double *w) {
-    const int tid = threadIdx.x;
-    for (int i = tid; i < BK * BK; i += blockDim.x) U[i / BK][i % BK] = (i / BK == i % BK) ? 1.0 : 0.0;
+    const int tid = threadIdx.x, nth = blockDim.x;
     __shared__ double fro;
-    __shared__ int any;
-    if (tid == 0) {
+    __shared__ int fl[2], swept;
+    for (int i = tid; i < BK * BK; i += nth) U[i / BK][i % BK] = (i / BK == i % BK) ? 1.0 : 0.0;
+    if (tid < 64) {
         double f = 0.0;
-        for (int i = 0; i < k; ++i)
-            for (int j = 0; j < k; ++j) f += A[i][j] * A[i][j];
-        fro = sqrt(f);
+        for (int i = tid; i < k * k; i += 64) f += A[i / k][i % k] * A[i / k][i % k];
+        f = group_sum<64>(f);
+        if (tid == 0) {
+            fro = sqrt(f);
+            fl[0] = fl[1] = 0;
+            swept = 0;
+        }
     }
     __syncthreads();
     const double tol = 1e-15 * fro;
     const int k2 = (k + 1) & ~1, np = k2 / 2;
+    int gstep = 0;
     for (int sweep = 0; sweep < 40; ++sweep) {
-        if (tid == 0) any = 0;
-        __syncthreads();
-        for (int step = 0; step < k2 - 1; ++step) {
-            // pair q of this step: (0, ...) round robin over k2 indices (index k is a dummy for odd k)
+        for (int step = 0; step < k2 - 1; ++step, ++gstep) {
+            const int f = gstep & 1;
+            if (tid == 0) fl[f ^ 1] = 0;  // the next step's flag
             if (tid < np) {
                 int p, q;
                 if (tid == 0) {
@@ -345,7 +392,8 @@ __device__ void blk_jacobi(int k, double (*A)[BK + 1], double (*U)[BK + 1], doub
                     const double r = 1.0 / sqrt(u * u + e2 * e2);
                     c = u * r;
                     s = (d >= 0.0 ? e2 : -e2) * r;
-                    any = 1;
+                    fl[f] = 1;
+                    swept = 1;
                 }
                 perm[2 * tid] = p;
                 perm[2 * tid + 1] = q;
@@ -353,8 +401,8 @@ __device__ void blk_jacobi(int k, double (*A)[BK + 1], double (*U)[BK + 1], doub
                 sn[tid] = s;
             }
             __syncthreads();
-            // rows p, q of A for every column j
-            for (int i = tid; i < np * k; i += blockDim.x) {
+            if (!fl[f]) continue;
+            for (int i = tid; i < np * k; i += nth) {  // rows p, q
                 const int pr = i / k, j = i % k, p = perm[2 * pr], q = perm[2 * pr + 1];
                 if (q < k) {
                     const double c = cs[pr], s = sn[pr];
@@ -364,8 +412,7 @@ __device__ void blk_jacobi(int k, double (*A)[BK + 1], double (*U)[BK + 1], doub
                 }
             }
             __syncthreads();
-            // columns p, q of A and of U for every row j
-            for (int i = tid; i < np * k; i += blockDim.x) {
+            for (int i = tid; i < np * k; i += nth) {  // columns p, q of A and of U
                 const int pr = i / k, j = i % k, p = perm[2 * pr], q = perm[2 * pr + 1];
                 if (q < k) {
                     const double c = cs[pr], s = sn[pr];
@@ -379,10 +426,12 @@ __device__ void blk_jacobi(int k, double (*A)[BK + 1], double (*U)[BK + 1], doub
             }
             __syncthreads();
         }
-        if (!any) break;
+        __syncthreads();
+        if (!swept) break;
+        __syncthreads();
+        if (tid == 0) swept = 0;  // after every thread has read it, before the next sweep sets it
         __syncthreads();
     }
-    // ascending order (ties by index)
     if (tid < k) {
         const double x = A[tid][tid];
         int r = 0;
@@ -400,19 +449,15 @@ __device__ void blk_jacobi(int k, double (*A)[BK + 1], double (*U)[BK + 1], doub
 // eigen-decomposition of G; restart decision for this iteration.
 __global__ __launch_bounds__(256) void k_blk_eig(BlkState *__restrict__ st, const double *__restrict__ part,
                                                  int nblk) {
-    __shared__ double A[BK][BK + 1], U[BK][BK + 1];
+    __shared__ double A[BK][BK + 1], U[BK][BK + 1], Ye[BK][BK + 1];
     __shared__ double cs[BK / 2], sn[BK / 2], w[BK];
     __shared__ int perm[BK];
     BlkState &S = *st;
     if (!S.active) return;
     const int k0 = S.k, nn = S.nnew, k = k0 + nn;
     // the products V(:, :k)^T W(:, k0:k) from the partial sums
-    for (int i = threadIdx.x; i < k * nn; i += 256) {
-        const int j = i / nn, c = i % nn;
-        double s = 0.0;
-        for (int q = 0; q < nblk; ++q) s += part[(size_t)q * BK * BB + j * BB + c];
-        A[j][c] = s;  // staging
-    }
+    sum_partials(part, BK * BB, nblk, k * nn, [&](int e) { return (int64_t)(e / nn) * BB + e % nn; },
+                 [&](int e, double v) { A[e / nn][e % nn] = v; });  // staging
     __syncthreads();
     for (int i = threadIdx.x; i < k * nn; i += 256) {
         const int j = i / nn, c = i % nn;
@@ -422,12 +467,45 @@ __global__ __launch_bounds__(256) void k_blk_eig(BlkState *__restrict__ st, cons
         S.G[(k0 + c) * BK + j] = v;
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < k * k; i += 256) A[i / k][i % k] = S.G[(i / k) * BK + (i % k)];
-    __syncthreads();
-    blk_jacobi(k, A, U, cs, sn, perm, w);
+    // warm start: G in the basis of the previous Ritz vectors extended by the
+    // new vectors, Ye = blockdiag(Y(:k0, :k0), I), is diagonal up to its new
+    // rows and columns, so the Jacobi sweeps converge in a few passes
     for (int i = threadIdx.x; i < k * k; i += 256) {
         const int r = i / k, c = i % k;
-        S.Y[r * BK + c] = U[r][perm[c]];
+        Ye[r][c] = (r < k0 && c < k0) ? S.Y[r * BK + c] : (r == c ? 1.0 : 0.0);
+        A[r][c] = S.G[r * BK + c];
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < k * k; i += 256) {  // U = G Ye (staging)
+        const int r = i / k, c = i % k;
+        double acc = 0.0;
+        for (int l = 0; l < k; ++l) acc += A[r][l] * Ye[l][c];
+        U[r][c] = acc;
+    }
+    __syncthreads();
+    __syncthreads();
+    for (int i = threadIdx.x; i < k * k; i += 256) {  // A = Ye^T G Ye
+        const int r = i / k, c = i % k;
+        double acc = 0.0;
+        for (int l = 0; l < k; ++l) acc += Ye[l][r] * U[l][c];
+        A[r][c] = acc;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < k * k; i += 256) {  // exactly symmetric
+        const int r = i / k, c = i % k;
+        if (r < c) {
+            const double v = 0.5 * (A[r][c] + A[c][r]);
+            A[r][c] = v;
+            A[c][r] = v;
+        }
+    }
+    __syncthreads();
+    blk_jacobi(k, A, U, cs, sn, perm, w);
+    for (int i = threadIdx.x; i < k * k; i += 256) {  // Y = Ye U, columns in ascending order
+        const int r = i / k, c = i % k;
+        double acc = 0.0;
+        for (int l = 0; l < k; ++l) acc += Ye[r][l] * U[l][perm[c]];
+        S.Y[r * BK + c] = acc;
     }
     for (int i = threadIdx.x; i < k; i += 256) S.theta[i] = w[i];
     if (threadIdx.x == 0) {
@@ -440,17 +518,14 @@ __global__ __launch_bounds__(256) void k_blk_eig(BlkState *__restrict__ st, cons
 
 // Residual norms and convergence; the restart decision: the basis is thick-
 // restarted when the corrections of the unconverged roots would not fit.
-__global__ __launch_bounds__(64) void k_blk_conv(BlkState *__restrict__ st, const double *__restrict__ part,
+__global__ __launch_bounds__(256) void k_blk_conv(BlkState *__restrict__ st, const double *__restrict__ part,
                                                  int nblk) {
     BlkState &S = *st;
     if (!S.active) return;
-    if (threadIdx.x < S.b) {
-        const int j = threadIdx.x;
-        double s = 0.0;
-        for (int q = 0; q < nblk; ++q) s += part[(size_t)q * BK * BB + j];
-        S.rnorm[j] = sqrt(s);
-        S.conv[j] = (S.rnorm[j] <= S.tol) ? 1 : 0;
-    }
+    sum_partials(part, BK * BB, nblk, S.b, [](int e) { return (int64_t)e; }, [&](int e, double v) {
+        S.rnorm[e] = sqrt(v);
+        S.conv[e] = (S.rnorm[e] <= S.tol) ? 1 : 0;
+    });
     __syncthreads();
     if (threadIdx.x == 0) {
         int c = 1, open = 0;
@@ -501,50 +576,65 @@ __global__ __launch_bounds__(256) void k_blk_finish(BlkState *__restrict__ st, B
     }
 }
 
-// Cholesky factor of the block's Gram matrix T^T T (in S.S rows/columns < b)
-// with dropping: a column whose remaining norm^2 is below drop^2 of its own
-// norm^2 is dropped; the kept columns are compacted to the front.  Leaves in
-// S.S the coefficients C with T_new(:, c) = sum_j T(:, j) C[j][c], sets nnew
-// and the projection masks.  Thread 0 (b <= 8).
+// Orthonormalization of the new block from its Gram matrix T^T T (in S.S,
+// rows and columns < b), column by column in order (modified Gram-Schmidt
+// through the Cholesky factor R, R^T R = T^T T): the pivot of column c is its
+// norm^2 left after the kept columns before it; below drop^2 = 1e-16 of its
+// own norm^2 the column is dropped.  Leaves in S.S the coefficients C,
+// T_new(:, m) = sum_j T(:, j) C[j][m], with the m-th kept column at m, and
+// (last pass) nnew and the projection masks.  One wavefront, lane j owns
+// row j of the small matrices.
 __global__ __launch_bounds__(64) void k_blk_chol(BlkState *__restrict__ st, int b, int last) {
     BlkState &S = *st;
-    if (!S.active || threadIdx.x != 0) return;
-    double Gm[BB][BB], L[BB][BB], C[BB][BB];
-    for (int i = 0; i < BB; ++i)
-        for (int j = 0; j < BB; ++j) {
-            Gm[i][j] = (i < b && j < b) ? S.S[i * BB + j] : 0.0;
-            L[i][j] = C[i][j] = 0.0;
-        }
-    // modified Gram-Schmidt on the Gram matrix: R = Q^T T, keep columns with enough norm
-    int kept[BB], nk = 0;
-    for (int c = 0; c < b; ++c) {
-        // coefficients of column c along the kept orthonormal columns: (L^-1)^T ...
-        // work in the basis of the original columns: q_i = sum_j C[j][i] t_j
-        double v[BB];
-        for (int j = 0; j < BB; ++j) v[j] = (j == c) ? 1.0 : 0.0;  // t_c in column coordinates
-        const double n0 = sqrt(fmax(Gm[c][c], 0.0));
-        for (int pass = 0; pass < 2; ++pass)
-            for (int i = 0; i < nk; ++i) {
-                // <q_i, v> = sum_{j,l} C[j][i] Gm[j][l] v[l]
-                double dot = 0.0;
-                for (int j = 0; j < b; ++j)
-                    for (int l = 0; l < b; ++l) dot += C[j][i] * Gm[j][l] * v[l];
-                for (int j = 0; j < b; ++j) v[j] -= dot * C[j][i];
-            }
-        double nn = 0.0;
-        for (int j = 0; j < b; ++j)
-            for (int l = 0; l < b; ++l) nn += v[j] * Gm[j][l] * v[l];
-        nn = sqrt(fmax(nn, 0.0));
-        if (n0 > 0.0 && nn > 1e-8 * n0 && nn > 0.0) {
-            for (int j = 0; j < b; ++j) C[j][nk] = v[j] / nn;
-            kept[nk++] = c;
-        }
+    if (!S.active) return;
+    __shared__ double Gm[BB][BB], R[BB][BB], C[BB][BB];
+    __shared__ double piv;
+    __shared__ int keep_c[BB];
+    const int lane = threadIdx.x;
+    if (lane < BB * BB) {
+        const int i = lane / BB, j = lane % BB;
+        Gm[i][j] = (i < b && j < b) ? S.S[i * BB + j] : 0.0;
+        R[i][j] = C[i][j] = 0.0;
     }
-    (void)kept;
-    (void)L;
-    for (int j = 0; j < BB; ++j)
-        for (int c = 0; c < BB; ++c) S.S[j * BB + c] = (j < b && c < nk) ? C[j][c] : 0.0;
-    if (last) {
+    wsync();
+    for (int c = 0; c < b; ++c) {
+        if (lane == 0) {
+            double d = Gm[c][c];
+            for (int i = 0; i < c; ++i) d -= R[i][c] * R[i][c];
+            piv = (Gm[c][c] > 0.0 && d > 1e-16 * Gm[c][c]) ? sqrt(d) : 0.0;
+            keep_c[c] = piv > 0.0;
+        }
+        wsync();
+        const double rc = piv;
+        if (rc > 0.0 && lane < b) {
+            // row c of R (columns j > c) and column c of C = R^{-1} in column coordinates
+            const int j = lane;
+            if (j > c) {
+                double x = Gm[c][j];
+                for (int i = 0; i < c; ++i) x -= R[i][c] * R[i][j];
+                R[c][j] = x / rc;
+            }
+            double y = (j == c) ? 1.0 : 0.0;
+            for (int i = 0; i < c; ++i) y -= R[i][c] * C[j][i];
+            C[j][c] = y / rc;
+        }
+        if (lane == 0 && rc > 0.0) R[c][c] = rc;
+        wsync();
+    }
+    // compaction: the m-th kept column goes to position m
+    if (lane < BB * BB) {
+        const int j = lane / BB, m = lane % BB;
+        int col = -1, cnt = 0;
+        for (int c = 0; c < b; ++c)
+            if (keep_c[c]) {
+                if (cnt == m) col = c;
+                ++cnt;
+            }
+        S.S[j * BB + m] = (j < b && col >= 0) ? C[j][col] : 0.0;
+    }
+    if (last && lane == 0) {
+        int nk = 0;
+        for (int c = 0; c < b; ++c) nk += keep_c[c];
         S.nnew = nk;
         for (int j = 0; j < BB; ++j) S.slot_on[j] = j < nk ? 1 : 0;
         if (nk == 0) S.active = 0;  // nothing new: the subspace stopped growing
@@ -651,12 +741,12 @@ static void enqueue_orth(const BlockWork &w, dim3 rg, hipStream_t s) {
     const int b = w.b;
     for (int pass = 0; pass < 2; ++pass) {
         hipLaunchKernelGGL(k_blk_tn<TN_ORTH>, dim3(w.nblk), dim3(256), 0, s, w.st, w.V, w.W, w.T, w.n, b, w.part);
-        hipLaunchKernelGGL(k_blk_reduce, dim3(1), dim3(256), 0, s, w.st, w.part, w.nblk);
+        hipLaunchKernelGGL(k_blk_reduce<TN_ORTH>, dim3(1), dim3(256), 0, s, w.st, w.part, w.nblk, b);
         hipLaunchKernelGGL(k_blk_nn<0>, rg, dim3(BTPB), 0, s, w.st, w.V, w.T, w.n, b);
     }
     for (int pass = 0; pass < 2; ++pass) {
         hipLaunchKernelGGL(k_blk_tn<TN_GRAM>, dim3(w.nblk), dim3(256), 0, s, w.st, w.V, w.W, w.T, w.n, b, w.part);
-        hipLaunchKernelGGL(k_blk_reduce, dim3(1), dim3(256), 0, s, w.st, w.part, w.nblk);
+        hipLaunchKernelGGL(k_blk_reduce<TN_GRAM>, dim3(1), dim3(256), 0, s, w.st, w.part, w.nblk, b);
         hipLaunchKernelGGL(k_blk_chol, dim3(1), dim3(64), 0, s, w.st, b, pass);
         hipLaunchKernelGGL(k_blk_nn<1>, rg, dim3(BTPB), 0, s, w.st, w.V, w.T, w.n, b);
     }
@@ -714,16 +804,18 @@ dmrg_status dmrg_block_davidson(dmrg_plan *plan, const double *coef, const dmrg_
     bool more = true;
     while (more) {
         for (int it = 0; it < o.chunk; ++it) {
-            for (int j = 0; j < b; ++j)
-                DMRG_TRY(launch_project(plan, 0, w.coef, w.T + (int64_t)j * n, w.WT + (int64_t)j * n, s,
-                                        &w.st->slot_on[j]));
+            // the new block in groups of PROJ_NVEC vectors per launch (slots past the
+            // block's size are masked off on the device)
+            for (int j = 0; j < b; j += PROJ_NVEC)
+                DMRG_TRY(launch_project_multi(plan, w.coef, w.T + (int64_t)j * n, n, w.WT + (int64_t)j * n, n,
+                                              &w.st->slot_on[j], s));
             hipLaunchKernelGGL(k_blk_append, rg, dim3(BTPB), 0, s, w.st, w.V, w.W, (const double *)w.T,
                                (const double *)w.WT, n);
             hipLaunchKernelGGL(k_blk_tn<TN_RR>, dim3(w.nblk), dim3(256), 0, s, w.st, w.V, w.W, w.T, n, b, w.part);
             hipLaunchKernelGGL(k_blk_eig, dim3(1), dim3(256), 0, s, w.st, (const double *)w.part, w.nblk);
             hipLaunchKernelGGL(k_blk_ritz, rg, dim3(BTPB), 0, s, w.st, (const double *)w.V, (const double *)w.W,
                                (const double *)w.D, X, w.T, n, b, w.part);
-            hipLaunchKernelGGL(k_blk_conv, dim3(1), dim3(64), 0, s, w.st, (const double *)w.part, (int)rg.x);
+            hipLaunchKernelGGL(k_blk_conv, dim3(1), dim3(256), 0, s, w.st, (const double *)w.part, (int)rg.x);
             hipLaunchKernelGGL(k_blk_restart, rg, dim3(BTPB), 0, s, w.st, w.V, w.W, n);
             hipLaunchKernelGGL(k_blk_finish, dim3(1), dim3(256), 0, s, w.st, w.d_sum);
             enqueue_orth(w, rg, s);

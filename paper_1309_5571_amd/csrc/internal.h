@@ -205,6 +205,8 @@ struct dmrg_plan {
     std::vector<void *> owned;
     void *d_tmp = nullptr;  // intermediate buffer (max over passes, 8-byte elements)
     int64_t tmp_bytes = 0;
+    void *d_multi_tmp = nullptr;  // intermediates of several vectors per launch (grown on demand)
+    size_t multi_tmp_bytes = 0;
     // preconditioner diagonal tasks (elementwise): one DiagTerm list per pair
     dmrg::Task *d_diag_tasks = nullptr;
     dmrg::DiagTerm *d_diag_terms = nullptr;
@@ -238,6 +240,11 @@ dmrg_status launch_gcoef(dmrg_plan *plan, const double *psi, const double *gbar,
                          hipStream_t s);
 dmrg_status launch_convert_jobs(const ConvJob *jobs, int njob, int prec, hipStream_t s);
 dmrg_status launch_diagonal(dmrg_plan *plan, const double *coef, double *diag, hipStream_t s);
+// four vectors in one launch where the plan's tiles allow it (else one launch each);
+// vmask: optional device [4], a vector whose flag is 0 is not written
+constexpr int PROJ_NVEC = 4;
+dmrg_status launch_project_multi(dmrg_plan *plan, const double *coef, const double *in, int64_t in_stride,
+                                 double *out, int64_t out_stride, const int32_t *vmask, hipStream_t s);
 // davidson.hip
 dmrg_status davidson_free(dmrg_plan *plan);
 // block.hip

@@ -1069,6 +1069,8 @@ dmrg_status plan_free(dmrg_plan *plan) {
     block_free(plan);
     for (void *p : plan->owned) (void)hipFree(p);
     plan->owned.clear();
+    if (plan->d_multi_tmp) (void)hipFree(plan->d_multi_tmp);
+    plan->d_multi_tmp = nullptr;
     return DMRG_OK;
 }
 

@@ -772,6 +772,242 @@ __device__ __forceinline__ void tasks_run(const Task *__restrict__ tasks, int nt
     }
 }
 
+// ------------------------------------------------------------------ several vectors per launch
+
+// NVEC vectors projected by one launch (FP64, plans whose tiles fit 16 x 16):
+// each tile loads every operator fragment once and applies it to all NVEC
+// vectors, so a tile's chain of dependent loads and products is shared.
+constexpr int NVEC = PROJ_NVEC;
+constexpr int NV_KC = 16;  // contraction length of one work item (registers: NVEC copies of one operand)
+
+struct MultiArgs {
+    int64_t in_stride = 0, out_stride = 0, tmp_stride = 0;  // elements between consecutive vectors
+    const int32_t *vmask = nullptr;                         // device [NVEC]; 0 = vector not written
+};
+
+// Fused two-sided segment on a 16-row tile for NVEC vectors, the intermediate
+// kept in registers: the first product is formed transposed,
+//   D1 = X^T A^T  (16 columns of T as rows, the tile's rows as columns),
+// so that value e of lane (g, c) holds T[c][16 cs + row(g, e)], which is what
+// lane (g, c) supplies as the first operand of the second product's step e
+// (rows c, contraction index 16 cs + row(g, e)); the second operand is the B
+// block at the same index.  A and B fragments are loaded once per step and
+// used for every vector.
+__device__ __forceinline__ void fused_item_nv(v4d (&acc)[NVEC], const Seg &s, const Task &tk,
+                                              const double *__restrict__ in, int64_t stride) {
+    typedef Tr<DMRG_F64> T;
+    const int lane = threadIdx.x & 63;
+    const int c = lane & 15, g = lane >> 4;
+    const bool rok = c < tk.m;
+    const int row = tk.row0 + (rok ? c : 0);
+    const bool cok = c < tk.n;
+    const int col = tk.col0 + (cok ? c : 0);
+    const double *A = (const double *)(uintptr_t)s.p;
+    const double *B = (const double *)(uintptr_t)s.r;
+    const double *X = in + s.q;
+    const int ncs = (s.K2 + 15) >> 4;
+    for (int cs = 0; cs < ncs; ++cs) {
+        v4d t1[NVEC];
+#pragma unroll
+        for (int v = 0; v < NVEC; ++v) t1[v] = v4d{0, 0, 0, 0};
+        const int xc = cs * 16 + c;  // column of X (index of T's second dimension)
+        const bool xok = xc < s.K2;
+        for (int kb = 0; kb < s.K; kb += 16) {
+            double a[4], x[NVEC][4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int i = kb + 4 * j + g;  // strided: step j takes i = kb + 4 j + g
+                const bool iok = i < s.K;
+                a[j] = (rok && iok) ? A[(int64_t)row * s.ldp + i] : 0.0;
+#pragma unroll
+                for (int v = 0; v < NVEC; ++v)
+                    x[v][j] = (xok && iok) ? X[v * stride + (int64_t)i * s.ldq + xc] : 0.0;
+            }
+            const int ns = min(4, (s.K - kb + 3) >> 2);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (j < ns) {
+#pragma unroll
+                    for (int v = 0; v < NVEC; ++v)
+                        t1[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[v][j], a[j], t1[v], 0, 0, 0);
+                }
+        }
+        double b[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int k = cs * 16 + T::row(g, e);
+            b[e] = (cok && k < s.K2) ? B[(int64_t)col * s.ldr + k] : 0.0;
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            if (cs * 16 + 4 * e < s.K2) {
+#pragma unroll
+                for (int v = 0; v < NVEC; ++v)
+                    acc[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(t1[v][e], b[e], acc[v], 0, 0, 0);
+            }
+    }
+}
+
+// One work item of a non-fused segment for NVEC vectors: the operand that is
+// the call's input or the intermediate differs per vector (offset v stride),
+// the operator block is loaded once.
+template <bool PIN, bool PT, bool QIN, bool QT>
+__device__ __forceinline__ void item_gemm_nv(v4d (&acc)[NVEC], const Seg &s, const Task &tk,
+                                             const double *__restrict__ in, const double *__restrict__ tmp,
+                                             const MultiArgs &ma, int k0) {
+    typedef Tr<DMRG_F64> T;
+    constexpr int KB = 16, NKB = NV_KC / 16;  // NV_KC of the contraction per item
+    const int lane = threadIdx.x & 63;
+    const int r16 = lane & 15, g = lane >> 4;
+    const bool pok = r16 < tk.m, qok = r16 < tk.n;
+    const int prow = tk.row0 + (pok ? r16 : 0), qcol = tk.col0 + (qok ? r16 : 0);
+    const bool pv = s.pkind != OPD_ABS;  // which operand depends on the vector
+    const double *P = (s.pkind == OPD_ABS) ? (const double *)(uintptr_t)s.p : (PIN ? in : tmp) + s.p;
+    const double *Q = (s.qkind == OPD_ABS) ? (const double *)(uintptr_t)s.q : (QIN ? in : tmp) + s.q;
+    const int64_t pstr = pv ? (PIN ? ma.in_stride : ma.tmp_stride) : 0;
+    const int64_t qstr = pv ? 0 : (QIN ? ma.in_stride : ma.tmp_stride);
+    double ps = 1.0, qs = 1.0;
+    if (PIN && s.pscale && pok) ps = ((const double *)(uintptr_t)s.pscale)[prow];
+    if (QIN && s.qscale && qok) qs = ((const double *)(uintptr_t)s.qscale)[qcol];
+    double sh[NKB][4], pvec[NVEC][NKB][4];  // the shared operand, the per-vector one
+#pragma unroll
+    for (int b = 0; b < NKB; ++b) {
+        const int kk = T::template kbase<false>(k0 + b * KB, g);
+        if (pv) {
+            load_raw<DMRG_F64, QIN, !QT, false>(sh[b], Q, s.ldq, qcol, qok, kk, s.K);
+#pragma unroll
+            for (int v = 0; v < NVEC; ++v)
+                load_raw<DMRG_F64, PIN, PT, false>(pvec[v][b], P + v * pstr, s.ldp, prow, pok, kk, s.K);
+        } else {
+            load_raw<DMRG_F64, PIN, PT, false>(sh[b], P, s.ldp, prow, pok, kk, s.K);
+#pragma unroll
+            for (int v = 0; v < NVEC; ++v)
+                load_raw<DMRG_F64, QIN, !QT, false>(pvec[v][b], Q + v * qstr, s.ldq, qcol, qok, kk, s.K);
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < NKB; ++b)
+#pragma unroll
+        for (int v = 0; v < NVEC; ++v)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const double x = (pv ? pvec[v][b][j] : sh[b][j]) * (PIN ? ps : 1.0);
+                const double y = (pv ? sh[b][j] : pvec[v][b][j]) * (QIN ? qs : 1.0);
+                acc[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, acc[v], 0, 0, 0);
+            }
+}
+
+__device__ __forceinline__ void seg_items_nv(v4d (&acc)[NVEC], const Seg &s, const Task &tk,
+                                             const double *__restrict__ in, const double *__restrict__ tmp,
+                                             const MultiArgs &ma, int first, int nit) {
+    const bool pin = s.pkind == OPD_IN, qin = s.qkind == OPD_IN;
+    const int code = (pin ? 8 : 0) | (s.ptrans ? 4 : 0) | (qin ? 2 : 0) | (s.qtrans ? 1 : 0);
+    for (int it = first; it < nit; it += PW) {
+        const int k0 = it * NV_KC;
+        switch (code) {
+            case 0: item_gemm_nv<false, false, false, false>(acc, s, tk, in, tmp, ma, k0); break;
+            case 1: item_gemm_nv<false, false, false, true>(acc, s, tk, in, tmp, ma, k0); break;
+            case 2: item_gemm_nv<false, false, true, false>(acc, s, tk, in, tmp, ma, k0); break;
+            case 3: item_gemm_nv<false, false, true, true>(acc, s, tk, in, tmp, ma, k0); break;
+            case 4: item_gemm_nv<false, true, false, false>(acc, s, tk, in, tmp, ma, k0); break;
+            case 5: item_gemm_nv<false, true, false, true>(acc, s, tk, in, tmp, ma, k0); break;
+            case 8: item_gemm_nv<true, false, false, false>(acc, s, tk, in, tmp, ma, k0); break;
+            case 9: item_gemm_nv<true, false, false, true>(acc, s, tk, in, tmp, ma, k0); break;
+            case 12: item_gemm_nv<true, true, false, false>(acc, s, tk, in, tmp, ma, k0); break;
+            default: item_gemm_nv<true, true, false, true>(acc, s, tk, in, tmp, ma, k0); break;
+        }
+    }
+}
+
+// The task loop for NVEC vectors (FP64, 16 x 16 tiles): MODE 0 writes the
+// intermediates of stage A, MODE 1 the output tiles with the diagonal terms.
+template <int MODE>
+__global__ __launch_bounds__(64 * PW) __attribute__((amdgpu_waves_per_eu(2))) void k_tasks_nv(
+    const Task *__restrict__ tasks, int ntask, const Seg *__restrict__ segs, const DiagTerm *__restrict__ diags,
+    const double *__restrict__ in, const double *__restrict__ tmp_in, double *__restrict__ out,
+    const double *__restrict__ coef, MultiArgs ma) {
+    extern __shared__ __align__(16) double smem_tasks[];
+    typedef Tr<DMRG_F64> T;
+    double(*red)[32][33] = reinterpret_cast<double(*)[32][33]>(smem_tasks);
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int r16 = lane & 15, g = lane >> 4;
+    bool on[NVEC];
+    bool any = false;
+#pragma unroll
+    for (int v = 0; v < NVEC; ++v) {
+        on[v] = ma.vmask ? ma.vmask[v] != 0 : true;
+        any = any || on[v];
+    }
+    if (!any) return;
+    for (int t = blockIdx.x; t < ntask; t += gridDim.x) {
+        const Task tk = tasks[t];
+        double tot[NVEC][4];
+#pragma unroll
+        for (int v = 0; v < NVEC; ++v)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) tot[v][e] = 0.0;
+        int q = 0;
+        for (int si = tk.seg_begin; si < tk.seg_end; ++si) {
+            const int K = segs[si].K;
+            const int fz = segs[si].fused;
+            const int nit = fz ? 1 : (K + NV_KC - 1) / NV_KC;
+            const int first = (wave - q % PW + PW) % PW;
+            if (first < nit) {
+                const Seg s = segs[si];
+                const double cf = (s.coef >= 0 ? coef[s.coef] : 1.0) * s.w;
+                if (fz == 2) {
+#pragma unroll
+                    for (int v = 0; v < NVEC; ++v) {
+                        double cv[1][1][4];
+                        copy_item<DMRG_F64, 1>(cv, s, tk, in + v * ma.in_stride);
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) tot[v][e] += cf * cv[0][0][e];
+                    }
+                } else {
+                    v4d acc[NVEC];
+#pragma unroll
+                    for (int v = 0; v < NVEC; ++v) acc[v] = v4d{0, 0, 0, 0};
+                    if (fz)
+                        fused_item_nv(acc, s, tk, in, ma.in_stride);
+                    else
+                        seg_items_nv(acc, s, tk, in, tmp_in, ma, first, nit);
+#pragma unroll
+                    for (int v = 0; v < NVEC; ++v)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) tot[v][e] += cf * acc[v][e];
+                }
+            }
+            q += nit;
+        }
+        // per vector: partial tiles summed in a fixed order through LDS, then the epilogue
+#pragma unroll
+        for (int v = 0; v < NVEC; ++v) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) red[wave][T::row(g, e)][r16] = tot[v][e];
+            __syncthreads();
+            const int el = threadIdx.x;  // one element per thread (16 x 16 tiles)
+            if (el < tk.m * tk.n && on[v]) {
+                const int r = el / tk.n, c = el % tk.n;
+                double val = 0.0;
+#pragma unroll
+                for (int w = 0; w < PW; ++w) val += red[w][r][c];
+                const int64_t rr = tk.row0 + r, cc = tk.col0 + c;
+                const int64_t o = tk.c_off + rr * tk.ldc + cc;
+                if (MODE == 0) {
+                    out[v * ma.tmp_stride + o] = val;
+                } else {
+                    if (tk.diag_end > tk.diag_begin)
+                        val += diag_sum(diags, tk.diag_begin, tk.diag_end, coef,
+                                        in[v * ma.in_stride + tk.x_off + rr * tk.ldc + cc], rr, cc);
+                    out[v * ma.out_stride + o] = val;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
 #define DMRG_TASK_ARGS                                                                                          \
     const Task *__restrict__ tasks, int ntask, const Seg *__restrict__ segs, const DiagTerm *__restrict__ diags, \
         const double *__restrict__ in, const void *__restrict__ tmp, void *__restrict__ out,                     \
@@ -988,6 +1224,44 @@ dmrg_status launch_diagonal(dmrg_plan *plan, const double *coef, double *diag, h
     return DMRG_OK;
 }
 
+// NVEC vectors per launch where every tile of the FP64 forward pass fits
+// 16 x 16; otherwise one launch per vector.  vmask: device [NVEC] or null.
+dmrg_status launch_project_multi(dmrg_plan *plan, const double *coef, const double *in, int64_t in_stride,
+                                 double *out, int64_t out_stride, const int32_t *vmask, hipStream_t s) {
+    const PassSet &ps = plan->fwd[0];
+    if (ps.stageA.ns != 1 || ps.stageB.ns != 1) {
+        for (int v = 0; v < NVEC; ++v)
+            DMRG_TRY(launch_project(plan, 0, coef, in + v * in_stride, out + v * out_stride, s,
+                                    vmask ? vmask + v : nullptr));
+        return DMRG_OK;
+    }
+    MultiArgs ma;
+    ma.in_stride = in_stride;
+    ma.out_stride = out_stride;
+    ma.tmp_stride = (ps.tmp_elems + 63) & ~(int64_t)63;
+    ma.vmask = vmask;
+    if (ps.stageA.ntask) {
+        const size_t need = (size_t)NVEC * ma.tmp_stride * 8;
+        if (need > plan->multi_tmp_bytes) {
+            DMRG_HIP(hipStreamSynchronize(s));
+            if (plan->d_multi_tmp) (void)hipFree(plan->d_multi_tmp);
+            plan->d_multi_tmp = nullptr;
+            plan->multi_tmp_bytes = 0;
+            DMRG_HIP(hipMalloc(&plan->d_multi_tmp, need));
+            plan->multi_tmp_bytes = need;
+        }
+        hipLaunchKernelGGL(k_tasks_nv<0>, task_grid(ps.stageA.ntask), dim3(64 * PW), TASK_LDS, s, ps.stageA.tasks,
+                           ps.stageA.ntask, (const Seg *)ps.segs, (const DiagTerm *)ps.diags, in,
+                           (const double *)plan->d_multi_tmp, (double *)plan->d_multi_tmp, coef, ma);
+    }
+    if (ps.stageB.ntask)
+        hipLaunchKernelGGL(k_tasks_nv<1>, task_grid(ps.stageB.ntask), dim3(64 * PW), TASK_LDS, s, ps.stageB.tasks,
+                           ps.stageB.ntask, (const Seg *)ps.segs, (const DiagTerm *)ps.diags, in,
+                           (const double *)plan->d_multi_tmp, out, coef, ma);
+    DMRG_HIP(hipGetLastError());
+    return DMRG_OK;
+}
+
 }  // namespace dmrg
 
 // ================================================================== ABI
@@ -1029,6 +1303,24 @@ dmrg_status dmrg_project_backward(dmrg_plan *plan, const double *coef, const dou
     hipStream_t s = (hipStream_t)stream;
     if (gcoef) DMRG_TRY(launch_gcoef(plan, psi, gbar, gcoef, s));
     if (gpsi) DMRG_TRY(launch_adjoint(plan, coef, gbar, gpsi, s));
+    return DMRG_OK;
+}
+
+dmrg_status dmrg_project_block(dmrg_plan *plan, int32_t nvec, const double *coef, const double *psi,
+                               int64_t ldpsi, double *y, int64_t ldy, void *stream) {
+    clear_error();
+    if (!plan || !psi || !y || (!coef && plan->nterm_total) || nvec < 0)
+        return set_error(DMRG_E_INVALID_ARG, "null plan, coef, psi or y, or nvec < 0");
+    if (ldpsi < plan->n || ldy < plan->n) return set_error(DMRG_E_INVALID_ARG, "ldpsi and ldy must be >= n");
+    const double *pe = psi + (int64_t)std::max(nvec - 1, 0) * ldpsi + plan->n, *ye = y + (int64_t)std::max(nvec - 1, 0) * ldy + plan->n;
+    if (nvec && psi < ye && y < pe) return set_error(DMRG_E_INVALID_ARG, "psi and y must not overlap");
+    DMRG_TRY(check_device(plan));
+    hipStream_t s = (hipStream_t)stream;
+    int v = 0;
+    for (; v + NVEC <= nvec; v += NVEC)
+        DMRG_TRY(launch_project_multi(plan, coef, psi + (int64_t)v * ldpsi, ldpsi, y + (int64_t)v * ldy, ldy, nullptr,
+                                      s));
+    for (; v < nvec; ++v) DMRG_TRY(launch_project(plan, 0, coef, psi + (int64_t)v * ldpsi, y + (int64_t)v * ldy, s));
     return DMRG_OK;
 }
 
