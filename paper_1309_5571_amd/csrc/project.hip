@@ -793,7 +793,8 @@ struct MultiArgs {
 // (rows c, contraction index 16 cs + row(g, e)); the second operand is the B
 // block at the same index.  A and B fragments are loaded once per step and
 // used for every vector.
-__device__ __forceinline__ void fused_item_nv(v4d (&acc)[NVEC], const Seg &s, const Task &tk,
+template <int NV>
+__device__ __forceinline__ void fused_item_nv(v4d (&acc)[NV], const Seg &s, const Task &tk,
                                               const double *__restrict__ in, int64_t stride) {
     typedef Tr<DMRG_F64> T;
     const int lane = threadIdx.x & 63;
@@ -807,20 +808,20 @@ __device__ __forceinline__ void fused_item_nv(v4d (&acc)[NVEC], const Seg &s, co
     const double *X = in + s.q;
     const int ncs = (s.K2 + 15) >> 4;
     for (int cs = 0; cs < ncs; ++cs) {
-        v4d t1[NVEC];
+        v4d t1[NV];
 #pragma unroll
-        for (int v = 0; v < NVEC; ++v) t1[v] = v4d{0, 0, 0, 0};
+        for (int v = 0; v < NV; ++v) t1[v] = v4d{0, 0, 0, 0};
         const int xc = cs * 16 + c;  // column of X (index of T's second dimension)
         const bool xok = xc < s.K2;
         for (int kb = 0; kb < s.K; kb += 16) {
-            double a[4], x[NVEC][4];
+            double a[4], x[NV][4];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int i = kb + 4 * j + g;  // strided: step j takes i = kb + 4 j + g
                 const bool iok = i < s.K;
                 a[j] = (rok && iok) ? A[(int64_t)row * s.ldp + i] : 0.0;
 #pragma unroll
-                for (int v = 0; v < NVEC; ++v)
+                for (int v = 0; v < NV; ++v)
                     x[v][j] = (xok && iok) ? X[v * stride + (int64_t)i * s.ldq + xc] : 0.0;
             }
             const int ns = min(4, (s.K - kb + 3) >> 2);
@@ -828,7 +829,7 @@ __device__ __forceinline__ void fused_item_nv(v4d (&acc)[NVEC], const Seg &s, co
             for (int j = 0; j < 4; ++j)
                 if (j < ns) {
 #pragma unroll
-                    for (int v = 0; v < NVEC; ++v)
+                    for (int v = 0; v < NV; ++v)
                         t1[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[v][j], a[j], t1[v], 0, 0, 0);
                 }
         }
@@ -842,7 +843,7 @@ __device__ __forceinline__ void fused_item_nv(v4d (&acc)[NVEC], const Seg &s, co
         for (int e = 0; e < 4; ++e)
             if (cs * 16 + 4 * e < s.K2) {
 #pragma unroll
-                for (int v = 0; v < NVEC; ++v)
+                for (int v = 0; v < NV; ++v)
                     acc[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(t1[v][e], b[e], acc[v], 0, 0, 0);
             }
     }
@@ -969,7 +970,7 @@ __global__ __launch_bounds__(64 * PW) __attribute__((amdgpu_waves_per_eu(2))) vo
 #pragma unroll
                     for (int v = 0; v < NVEC; ++v) acc[v] = v4d{0, 0, 0, 0};
                     if (fz)
-                        fused_item_nv(acc, s, tk, in, ma.in_stride);
+                        fused_item_nv<NVEC>(acc, s, tk, in, ma.in_stride);
                     else
                         seg_items_nv(acc, s, tk, in, tmp_in, ma, first, nit);
 #pragma unroll
