@@ -1,21 +1,29 @@
 // Eigen-decomposition of symmetric blocks (Alg. 1, step 6: the eigenvalues of
 // each block's density matrix decide which states the block keeps).
+// One workgroup per block, two methods by order d:
 //
-// One workgroup per block runs the cyclic two-sided Jacobi method with the
-// round-robin ("circle") ordering: each round pairs every index with one
-// other, the d/2 plane rotations J of a round are independent, so all of them
-// are found together and then applied at once, A <- J^T A J and V <- V J.
-// With the indices grouped by pair, A splits into 2x2 sub-blocks A_kl (rows of
-// pair k, columns of pair l) that transform on their own, J_k^T A_kl J_l, so
-// each thread takes whole sub-blocks: A is read and written once per round,
-// and along a row the threads of consecutive l touch consecutive columns (the
-// circle ordering puts pair l at columns r + l and r - l).  A sweep is d - 1
-// rounds (every pair once); the method stops after a sweep with no rotation.
-// Blocks of order <= 48 are held in LDS, larger ones (up to 2048) are worked
-// on in global memory.
+// d <= 48: cyclic two-sided Jacobi in LDS with the round-robin ("circle")
+// ordering: each round pairs every index with one other, the d/2 plane
+// rotations J of a round are independent, so all of them are found together
+// and then applied at once, A <- J^T A J and V <- V J.  With the indices
+// grouped by pair, A splits into 2x2 sub-blocks A_kl (rows of pair k, columns
+// of pair l) that transform on their own, J_k^T A_kl J_l, so each thread takes
+// whole sub-blocks.  A sweep is d - 1 rounds (every pair once); the method
+// stops after a sweep with no rotation.
+//
+// 48 < d <= 2048: Householder reduction to tridiagonal form T = Q^T A Q, the
+// matrix Q formed explicitly, then the implicit QL iteration with Wilkinson's
+// shift on T (the tql2 procedure of Bowdler, Martin, Reinsch and Wilkinson),
+// whose plane rotations are applied to the columns of Q.  The reduction and
+// the formation of Q are whole-workgroup passes over the block (in global
+// memory, where it stays cache-resident); the QL recurrence is sequential and
+// runs on one lane, writing each sweep's rotations to LDS, which the whole
+// workgroup then applies to the rows of Q (Q is stored column-major, so a
+// rotation of columns i, i+1 is a coalesced read of two columns).
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
+#include "lanes.h"
 
 namespace dmrg {
 
@@ -24,6 +32,9 @@ constexpr int EIG_TPB_SMALL = 512;  // Jacobi, blocks in LDS (a round has ~d^2/2
 constexpr int EIG_LDS_DIM = 48;  // A (padded rows) and V in LDS: 37 KB
 constexpr int EIG_MAX_DIM = 2048;
 constexpr int EIG_MAX_SWEEPS = 40;
+constexpr int TRI_TPB = 1024;  // tridiagonal path
+constexpr int TRI_WAVES = TRI_TPB / 64;
+constexpr int QL_MAXIT = 60;  // QL iterations per eigenvalue before the block is reported unconverged
 
 // Pair k of round r of the circle ordering on n' = m + 1 (even) indices:
 // k = 0 pairs r with the fixed index m, k > 0 pairs r + k with r - k (mod m).
@@ -37,33 +48,31 @@ __device__ __forceinline__ void circle_pair(int r, int k, int m, int &p, int &q)
     }
 }
 
-template <bool SMALL>
-__global__ __launch_bounds__(SMALL ? EIG_TPB_SMALL : 1024) void k_eigh(int nblk, const int64_t *__restrict__ off,
-                                                  const int32_t *__restrict__ dim, const int64_t *__restrict__ woff,
-                                                  double *__restrict__ a, double *__restrict__ w,
-                                                  double *__restrict__ u, int32_t *__restrict__ info) {
-    constexpr int NP = SMALL ? EIG_LDS_DIM / 2 : EIG_MAX_DIM / 2;  // pairs per round
-    constexpr int NT = SMALL ? EIG_TPB_SMALL : 1024;                // threads
-    __shared__ double sA[SMALL ? EIG_LDS_DIM * (EIG_LDS_DIM + 1) : 1];
-    __shared__ double sV[SMALL ? EIG_LDS_DIM * EIG_LDS_DIM : 1];
+__global__ __launch_bounds__(EIG_TPB_SMALL) void k_eigh_jacobi(int nblk, const int64_t *__restrict__ off,
+                                                               const int32_t *__restrict__ dim,
+                                                               const int64_t *__restrict__ woff, double *__restrict__ a,
+                                                               double *__restrict__ w, double *__restrict__ u,
+                                                               int32_t *__restrict__ info) {
+    constexpr int NP = EIG_LDS_DIM / 2;  // pairs per round
+    constexpr int NT = EIG_TPB_SMALL;
+    __shared__ double A[EIG_LDS_DIM * (EIG_LDS_DIM + 1)];
+    __shared__ double V[EIG_LDS_DIM * EIG_LDS_DIM];
     __shared__ double rc[NP], rs[NP];
     __shared__ int rp[NP], rq[NP], rf[NP];
     __shared__ double part[NT];
-    __shared__ double diag[SMALL ? EIG_LDS_DIM : EIG_MAX_DIM];
+    __shared__ double diag[EIG_LDS_DIM];
     const int b = blockIdx.x;
     if (b >= nblk) return;
     const int d = dim[b];
     const int tid = threadIdx.x;
     if (d < 1 || d > EIG_MAX_DIM) {
-        if (!SMALL && tid == 0 && info) info[b] = -1;  // unsupported order
+        if (tid == 0 && info) info[b] = -1;  // unsupported order
         return;
     }
-    if (SMALL != (d <= EIG_LDS_DIM)) return;  // the other kernel's block
-    double *in = a + off[b], *out = u + off[b];
-    // working matrices: LDS, or (large blocks) A in u and V in a
-    const int lda = SMALL ? d + 1 : d;
-    double *A = SMALL ? sA : out;
-    double *V = SMALL ? sV : in;
+    if (d > EIG_LDS_DIM) return;  // the tridiagonal kernel's block
+    const double *in = a + off[b];
+    double *out = u + off[b];
+    const int lda = d + 1;
     double fro = 0.0;
     for (int e = tid; e < d * d; e += NT) fro += in[e] * in[e];
     part[tid] = fro;
@@ -79,12 +88,7 @@ __global__ __launch_bounds__(SMALL ? EIG_TPB_SMALL : 1024) void k_eigh(int nblk,
     const double thr = part[0] * 0x1p-53 / d;
     for (int e = tid; e < d * d; e += NT) {
         const int r = e / d, c = e % d;
-        const double x = in[e];
-        A[r * lda + c] = x;  // (large blocks: A = u written before V = a overwrites the input)
-    }
-    __syncthreads();
-    for (int e = tid; e < d * d; e += NT) {
-        const int r = e / d, c = e % d;
+        A[r * lda + c] = in[e];
         V[r * d + c] = (r == c) ? 1.0 : 0.0;
     }
     __syncthreads();
@@ -165,8 +169,7 @@ __global__ __launch_bounds__(SMALL ? EIG_TPB_SMALL : 1024) void k_eigh(int nblk,
         done = !rotated;
     }
     // eigenvalues in descending order (ties by index), eigenvectors with the
-    // first entry of largest magnitude positive (the diagonal is read before
-    // u, which holds A for large blocks, is overwritten)
+    // first entry of largest magnitude positive
     for (int i = tid; i < d; i += NT) diag[i] = A[i * lda + i];
     __syncthreads();
     double *wb = w + woff[b];
@@ -191,6 +194,404 @@ __global__ __launch_bounds__(SMALL ? EIG_TPB_SMALL : 1024) void k_eigh(int nblk,
         for (int r = 0; r < d; ++r) out[r * d + rank] = sg * V[r * d + i];
     }
     if (tid == 0 && info) info[b] = done ? sweep : -2;
+}
+
+// Sum over the workgroup of one value per thread, and the value `lead` of
+// thread 0, both returned to every thread (the same total in every thread).
+// Two barriers: after it, every thread may overwrite what the block read before.
+__device__ __forceinline__ double block_sum_lead(double x, double lead, double *red, double *lead_out) {
+    x = group_sum<64>(x);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) red[wv] = x;
+    if (threadIdx.x == 0) red[TRI_WAVES] = lead;
+    __syncthreads();
+    double t = 0.0;
+    for (int i = 0; i < TRI_WAVES; ++i) t += red[i];
+    *lead_out = red[TRI_WAVES];
+    __syncthreads();
+    return t;
+}
+
+// sqrt(x^2 + y^2) without overflow or harmful underflow
+__device__ __forceinline__ double hyp(double x, double y) {
+    const double ax = fabs(x), ay = fabs(y);
+    const double mx = fmax(ax, ay), mn = fmin(ax, ay);
+    if (mx == 0.0) return 0.0;
+    if (mx > 0x1p-500 && mx < 0x1p+500) return sqrt(x * x + y * y);
+    const double q = mn / mx;
+    return mx * sqrt(1.0 + q * q);
+}
+
+constexpr int TRI_UB = 16;  // rows of a column read per batch of loads (Householder step)
+constexpr int QL_B = 8;     // rotations applied per batch of loads (QL; the next batch is fetched ahead)
+constexpr int Q_REG = 8;    // column entries per lane kept in registers (Q formation, L <= 512)
+
+__global__ __launch_bounds__(TRI_TPB) void k_eigh_tri(int nblk, const int64_t *__restrict__ off,
+                                                      const int32_t *__restrict__ dim, const int64_t *__restrict__ woff,
+                                                      double *__restrict__ a, double *__restrict__ w,
+                                                      double *__restrict__ u, int32_t *__restrict__ info) {
+    __shared__ double sd[EIG_MAX_DIM];  // diagonal of T, then the eigenvalues
+    __shared__ double se[EIG_MAX_DIM];  // se[i] couples i and i + 1
+    __shared__ double sq[EIG_MAX_DIM];  // Householder factors; QL: cosines (second buffer)
+    __shared__ double sx[EIG_MAX_DIM];  // Householder vector; QL: cosines (first buffer)
+    __shared__ double sy[EIG_MAX_DIM];  // p, then w = p - K v; QL: sines (first buffer)
+    __shared__ double sz[EIG_MAX_DIM];  // QL: sines (second buffer)
+    __shared__ int srank[EIG_MAX_DIM];
+    __shared__ double spart[EIG_MAX_DIM];  // row-group partial sums of p
+    __shared__ double red[TRI_WAVES + 1];
+    __shared__ int ctl[4];
+    const int b = blockIdx.x;
+    if (b >= nblk) return;
+    const int d = dim[b];
+    if (d <= EIG_LDS_DIM || d > EIG_MAX_DIM) return;  // the Jacobi kernel's block (or rejected there)
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const size_t D = (size_t)d;
+    double *A = u + off[b];  // working matrix (row-major, both triangles), then Householder vectors
+    double *Z = a + off[b];  // Q, then the eigenvectors; column-major: Z[c * d + r] = Q(r, c)
+    for (int r = wv; r < d; r += TRI_WAVES)
+        for (int c = lane; c < d; c += 64) A[r * D + c] = Z[r * D + c];
+    __syncthreads();
+
+    // ---- Householder reduction: step k zeroes A(k, k+2..) and A(k+2.., k) with
+    // H = I - t v v^T acting on indices k+1.., v(0) = 1 (stored in row k beyond it).
+    // A stays exactly symmetric, so column i of the trailing block is its row i:
+    // each thread owns columns (coalesced across the threads of a row).
+    for (int k = 0; k + 2 < d; ++k) {
+        const int L = d - k - 1;
+        const double *rowk = A + k * D + k + 1;  // x = A(k, k+1..) = A(k+1.., k)
+        double part = 0.0;
+        for (int j = tid; j < L; j += TRI_TPB) {
+            const double x = rowk[j];
+            sx[j] = x;
+            if (j) part += x * x;
+        }
+        double alpha;
+        const double sigma = block_sum_lead(part, tid == 0 ? rowk[0] : 0.0, red, &alpha);
+        if (tid == 0) sd[k] = A[k * D + k];
+        if (sigma == 0.0) {  // the column is already reduced
+            if (tid == 0) {
+                se[k] = alpha;
+                sq[k] = 0.0;
+            }
+            continue;
+        }
+        const double beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
+        const double t = (beta - alpha) / beta;
+        const double scale = 1.0 / (alpha - beta);
+        for (int j = tid; j < L; j += TRI_TPB) sx[j] = j ? sx[j] * scale : 1.0;
+        if (tid == 0) {
+            se[k] = beta;
+            sq[k] = t;
+        }
+        __syncthreads();
+        // p = t A22 v: p_i = t sum_j A(k+1+j, k+1+i) v_j.  Thread (i, g) sums the
+        // rows of group g of column i (G groups, so that every thread works and
+        // each issues its loads in batches); the groups' partials meet in LDS.
+        const int G = max(1, min(TRI_TPB / L, 32)), R = (L + G - 1) / G;
+        for (int q = tid; q < G * L; q += TRI_TPB) {
+            const int i = q % L, g = q / L;
+            const int j0 = g * R, j1 = min(L, j0 + R);
+            const double *col = A + (k + 1) * D + k + 1 + i;
+            double acc = 0.0;
+            for (int jb = j0; jb < j1; jb += TRI_UB) {
+                double av[TRI_UB];
+#pragma unroll
+                for (int u = 0; u < TRI_UB; ++u) av[u] = col[min(jb + u, j1 - 1) * D];
+#pragma unroll
+                for (int u = 0; u < TRI_UB; ++u)
+                    if (jb + u < j1) acc += av[u] * sx[jb + u];
+            }
+            spart[q] = acc;
+        }
+        __syncthreads();
+        double pv = 0.0;
+        for (int i = tid; i < L; i += TRI_TPB) {
+            double acc = 0.0;
+            for (int g = 0; g < G; ++g) acc += spart[g * L + i];
+            const double pi = t * acc;
+            sy[i] = pi;
+            pv += pi * sx[i];
+        }
+        double unused;
+        const double K = 0.5 * t * block_sum_lead(pv, 0.0, red, &unused);
+        for (int j = tid; j < L; j += TRI_TPB) sy[j] -= K * sx[j];  // w
+        __syncthreads();
+        // A22 -= v w^T + w v^T, thread (i, g) on the rows of group g of column i;
+        // both products rounded before the sum, so A(i, j) and A(j, i) stay
+        // bit-identical; loads in batches (the stores of a column may alias its
+        // next loads as far as the compiler knows)
+        for (int q = tid; q < G * L; q += TRI_TPB) {
+            const int i = q % L, g = q / L;
+            const int j0 = g * R, j1 = min(L, j0 + R);
+            double *col = A + (k + 1) * D + k + 1 + i;
+            const double vi = sx[i], wi = sy[i];
+            for (int jb = j0; jb < j1; jb += TRI_UB) {
+                double av[TRI_UB];
+#pragma unroll
+                for (int u = 0; u < TRI_UB; ++u) av[u] = col[min(jb + u, j1 - 1) * D];
+#pragma unroll
+                for (int u = 0; u < TRI_UB; ++u) {
+                    const int j = jb + u;
+                    if (j < j1) col[j * D] = av[u] - __dadd_rn(__dmul_rn(sx[j], wi), __dmul_rn(sy[j], vi));
+                }
+            }
+        }
+        for (int j = 1 + tid; j < L; j += TRI_TPB) A[k * D + k + 1 + j] = sx[j];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        sd[d - 2] = A[(d - 2) * D + d - 2];
+        sd[d - 1] = A[(d - 1) * D + d - 1];
+        se[d - 2] = A[(d - 1) * D + d - 2];
+        se[d - 1] = 0.0;
+    }
+    // ---- Q = H_0 H_1 ... H_{d-3}, accumulated from the last factor; H_k Q only
+    // changes the trailing block from index k + 1.  One wave per column: y_c =
+    // v^T Q(:, c), then Q(:, c) -= t y_c v, the column kept in registers between.
+    for (int c = wv; c < d; c += TRI_WAVES)
+        for (int r = lane; r < d; r += 64) Z[c * D + r] = r == c ? 1.0 : 0.0;
+    __syncthreads();
+    for (int k = d - 3; k >= 0; --k) {
+        const double t = sq[k];
+        if (t == 0.0) continue;
+        const int L = d - k - 1;
+        for (int j = tid; j < L; j += TRI_TPB) sx[j] = j ? A[k * D + k + 1 + j] : 1.0;
+        __syncthreads();
+        if (L <= 64 * Q_REG) {
+            // four columns per wave at a time: all their loads in flight together
+            for (int c0 = 4 * wv; c0 < L; c0 += 4 * TRI_WAVES) {
+                double cv[4][Q_REG];
+                double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const double *col = Z + (k + 1 + min(c0 + e, L - 1)) * D + k + 1;
+#pragma unroll
+                    for (int q = 0; q < Q_REG; ++q) cv[e][q] = col[min(lane + 64 * q, L - 1)];
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+#pragma unroll
+                    for (int q = 0; q < Q_REG; ++q) {
+                        const int r = lane + 64 * q;
+                        if (r < L) acc[e] += sx[r] * cv[e][q];
+                    }
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const double ty = t * group_sum<64>(acc[e]);
+                    if (c0 + e < L) {
+                        double *col = Z + (k + 1 + c0 + e) * D + k + 1;
+#pragma unroll
+                        for (int q = 0; q < Q_REG; ++q) {
+                            const int r = lane + 64 * q;
+                            if (r < L) col[r] = cv[e][q] - ty * sx[r];
+                        }
+                    }
+                }
+            }
+        } else {
+            for (int c = wv; c < L; c += TRI_WAVES) {
+                double *col = Z + (k + 1 + c) * D + k + 1;
+                double acc = 0.0;
+                for (int r = lane; r < L; r += 64) acc += sx[r] * col[r];
+                const double ty = t * group_sum<64>(acc);
+                for (int r = lane; r < L; r += 64) col[r] -= ty * sx[r];
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---- implicit QL on T (sd, se).  Lane 0 of wave 0 runs the recurrence and
+    // leaves each iteration's rotations (indices lo..hi) in one of two LDS
+    // buffers; in the same interval the other waves apply the previous
+    // iteration's rotations to the rows of Z.
+    int l = 0, it_l = 0, its = 0, bad = 0;
+    double tol = 0.0;
+    // one QL iteration into buffer `buf` (lane 0 of wave 0 only); ctl[2 buf] = lo,
+    // ctl[2 buf + 1] = hi, lo = -1 when every eigenvalue has converged
+    auto ql_next = [&](int buf) {
+        int lo = -1, hi = -1;
+        double *rc = buf ? sq : sx, *rs = buf ? sz : sy;
+        while (l < d) {
+            // m: the first index >= l whose coupling counts as zero (se[d - 1] = 0);
+            // eight couplings tested per round of LDS loads
+            int m = l;
+            for (;;) {
+                double ev[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) ev[u] = se[min(m + u, d - 1)];
+                int found = -1;
+#pragma unroll
+                for (int u = 7; u >= 0; --u)
+                    if (fabs(ev[u]) <= tol || m + u >= d - 1) found = min(m + u, d - 1);
+                if (found >= 0) {
+                    m = found;
+                    break;
+                }
+                m += 8;
+            }
+            if (m == l) {  // sd[l] is an eigenvalue
+                ++l;
+                it_l = 0;
+                continue;
+            }
+            if (++it_l > QL_MAXIT) {
+                bad = 1;
+                l = d;
+                break;
+            }
+            ++its;
+            // shift: the eigenvalue of the leading 2 x 2 of the segment nearer sd[l]
+            const double dl = sd[l];
+            double g = (sd[l + 1] - dl) / (2.0 * se[l]);
+            double r = hyp(g, 1.0);
+            g = sd[m] - dl + se[l] / (g + copysign(r, g));
+            double s = 1.0, c = 1.0, p = 0.0;
+            // every value read below is still the one from before this iteration
+            // (iteration i writes index i + 1), so the next ones are fetched ahead
+            double dip1 = sd[m], di = sd[m - 1], ei = se[m - 1];
+            int i = m - 1;
+            bool early = false;
+            for (; i >= l; --i) {
+                const int in = i > l ? i - 1 : i;
+                const double dn = sd[in], en = se[in];
+                const double f = s * ei, bb = c * ei;
+                // T is scaled to a norm in [1, 2), so f and g cannot overflow; a
+                // rotation norm below 2^-500 (135 orders of magnitude below the
+                // deflation threshold) counts as zero: the chase splits there and
+                // the iteration is repeated on the shorter segment
+                const double r2 = f * f + g * g;
+                if (__builtin_expect(r2 <= 0x1p-1000, 0)) {
+                    se[i + 1] = 0.0;
+                    sd[i + 1] = dip1 - p;
+                    se[m] = 0.0;
+                    early = true;
+                    break;
+                }
+                const double ir = rsqrt(r2);
+                r = r2 * ir;
+                se[i + 1] = r;
+                s = f * ir;
+                c = g * ir;
+                g = dip1 - p;
+                r = (di - g) * s + 2.0 * c * bb;
+                p = s * r;
+                sd[i + 1] = g + p;
+                g = c * r - bb;
+                rc[i] = c;
+                rs[i] = s;
+                dip1 = di;
+                di = dn;
+                ei = en;
+            }
+            if (!early) {
+                sd[l] -= p;
+                se[l] = g;
+                se[m] = 0.0;
+            }
+            lo = early ? i + 1 : l;
+            hi = m - 1;
+            break;
+        }
+        ctl[2 * buf] = lo;
+        ctl[2 * buf + 1] = hi;
+    };
+    double scale = 1.0;  // power of two: T * scale has a norm in [1, 2) (exact)
+    if (tid == 0) {
+        double anorm = 0.0;
+        for (int i = 0; i < d; ++i)
+            anorm = fmax(anorm, fabs(sd[i]) + fabs(se[i]) + (i ? fabs(se[i - 1]) : 0.0));
+        if (anorm > 0.0 && isfinite(anorm)) {
+            scale = ldexp(1.0, -ilogb(anorm));
+            for (int i = 0; i < d; ++i) {
+                sd[i] *= scale;
+                se[i] *= scale;
+            }
+            anorm *= scale;
+        }
+        tol = anorm * 0x1p-53;
+        ql_next(0);
+    }
+    __syncthreads();
+    for (int step = 0;; ++step) {
+        const int cur = step & 1;
+        const int lo = ctl[2 * cur], hi = ctl[2 * cur + 1];
+        if (lo < 0) break;
+        if (wv == 0) {
+            if (lane == 0) ql_next(cur ^ 1);
+        } else if (hi >= lo) {
+            // rotation i acts on columns i, i + 1, from hi down to lo: the column
+            // i + 1 entering rotation i is the one rotation i + 1 left (carried),
+            // column i is still the old one (fetched ahead in batches)
+            const double *rc = cur ? sq : sx, *rs = cur ? sz : sy;
+            for (int r = tid - 64; r < d; r += TRI_TPB - 64) {
+                double carry = Z[(hi + 1) * D + r];
+                double zv[QL_B], zn[QL_B];
+#pragma unroll
+                for (int q = 0; q < QL_B; ++q) zv[q] = Z[max(hi - q, lo) * D + r];
+                for (int i0 = hi; i0 >= lo; i0 -= QL_B) {
+                    // the next batch's columns lie below every column this batch writes
+#pragma unroll
+                    for (int q = 0; q < QL_B; ++q) zn[q] = Z[max(i0 - QL_B - q, lo) * D + r];
+#pragma unroll
+                    for (int q = 0; q < QL_B; ++q) {
+                        const int i = i0 - q;
+                        if (i >= lo) {
+                            const double c = rc[i], s = rs[i];
+                            Z[(i + 1) * D + r] = s * zv[q] + c * carry;
+                            carry = c * zv[q] - s * carry;
+                        }
+                    }
+#pragma unroll
+                    for (int q = 0; q < QL_B; ++q) zv[q] = zn[q];
+                }
+                Z[lo * D + r] = carry;
+            }
+        }
+        __syncthreads();
+    }
+
+    if (tid == 0 && scale != 1.0) {
+        const double inv = 1.0 / scale;  // a power of two: exact
+        for (int i = 0; i < d; ++i) sd[i] *= inv;
+    }
+    __syncthreads();
+    // ---- descending order (ties by index), first entry of largest magnitude positive
+    for (int i = tid; i < d; i += TRI_TPB) {
+        const double wi = sd[i];
+        int rank = 0;
+        for (int j = 0; j < d; ++j) {
+            const double wj = sd[j];
+            rank += (wj > wi) || (wj == wi && j < i);
+        }
+        srank[i] = rank;
+    }
+    __syncthreads();
+    double *wb = w + woff[b];
+    for (int i = wv; i < d; i += TRI_WAVES) {
+        const double *col = Z + i * D;
+        double best = -1.0;
+        int bi = 0;
+        for (int r = lane; r < d; r += 64) {
+            const double av = fabs(col[r]);
+            if (av > best) {
+                best = av;
+                bi = r;
+            }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            const double ob = __shfl_xor(best, o, 64);
+            const int oi = __shfl_xor(bi, o, 64);
+            if (ob > best || (ob == best && oi < bi)) {
+                best = ob;
+                bi = oi;
+            }
+        }
+        const double sg = col[bi] < 0.0 ? -1.0 : 1.0;
+        const int rk = srank[i];
+        for (int r = lane; r < d; r += 64) A[r * D + rk] = sg * col[r];
+        if (lane == 0) wb[rk] = sd[i];
+    }
+    if (tid == 0 && info) info[b] = bad ? -2 : 1 + its;
 }
 
 // State selection (Alg. 1, step 7: a block keeps its states of largest
@@ -331,8 +732,8 @@ dmrg_status dmrg_eigh_blocks(int32_t nblk, const int64_t *off, const int32_t *di
     if (!off || !dim || !woff || !a || !w || !u) return set_error(DMRG_E_INVALID_ARG, "null argument");
     if (a == u || a == w || u == w) return set_error(DMRG_E_INVALID_ARG, "a, w and u must not overlap");
     hipStream_t s = (hipStream_t)stream;
-    hipLaunchKernelGGL(k_eigh<true>, dim3(nblk), dim3(EIG_TPB_SMALL), 0, s, nblk, off, dim, woff, a, w, u, info);
-    hipLaunchKernelGGL(k_eigh<false>, dim3(nblk), dim3(1024), 0, s, nblk, off, dim, woff, a, w, u, info);
+    hipLaunchKernelGGL(k_eigh_jacobi, dim3(nblk), dim3(EIG_TPB_SMALL), 0, s, nblk, off, dim, woff, a, w, u, info);
+    hipLaunchKernelGGL(k_eigh_tri, dim3(nblk), dim3(TRI_TPB), 0, s, nblk, off, dim, woff, a, w, u, info);
     DMRG_HIP(hipGetLastError());
     return DMRG_OK;
 }

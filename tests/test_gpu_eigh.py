@@ -1,8 +1,9 @@
 """GPU parity of the blockwise eigen-decomposition (Alg. 1, step 6) against
 the oracle (LAPACK through NumPy), called through the C ABI.
 
-Tolerances follow the Jacobi method's backward error, a small multiple of
-d u |A|_F per block (u = 2^-53, d the block order): eigenvalues and the
+Tolerances follow the backward error of both device methods (Jacobi up to
+order 48, Householder tridiagonalization + implicit QL above), a small
+multiple of d u |A|_F per block (u = 2^-53, d the block order): eigenvalues and the
 reconstruction U diag(w) U^T within 16 d u |A|_F, U^T U within 16 d u of
 the identity, and each eigenvector within 16 d u |A|_F / gap of the oracle's
 (up to sign) where its eigenvalue is separated by `gap` from the others.
@@ -88,17 +89,36 @@ def test_eigh_random_blocks_small_and_large(seed):
     _check(blocks, res)
 
 
+def test_eigh_large_orders():
+    """The tridiagonal path at the orders of the 64-member batch (361) and up
+    to the largest supported one, random and density-like (rank-deficient,
+    exponentially decaying spectrum) blocks."""
+    rng = np.random.default_rng(21)
+    blocks = [_sym(rng, 361), _psd(rng, 700, 350), _sym(rng, 2048)]
+    X = rng.standard_normal((400, 1200)) * np.exp(-np.arange(400) / 6.0)[:, None]
+    rho = X @ X.T
+    blocks.append(rho / np.trace(rho))
+    res, info = _run(blocks)
+    assert np.all(info >= 1)
+    _check(blocks, res)
+
+
 def test_eigh_degenerate_and_special_blocks():
     rng = np.random.default_rng(5)
     D = np.diag(rng.standard_normal(20))
-    blocks = [np.zeros((3, 3)), np.eye(7), 2.5 * np.eye(60), D, np.array([[0.0, 1.0], [1.0, 0.0]])]
+    D2 = np.diag(rng.standard_normal(80))
+    blocks = [np.zeros((3, 3)), np.eye(7), 2.5 * np.eye(60), D, np.array([[0.0, 1.0], [1.0, 0.0]]), D2,
+              np.zeros((50, 50))]
     res, info = _run(blocks)
     assert np.all(info >= 1)
     # already diagonal: no rotation, eigenvalues are the diagonal sorted, exactly
     w, U = res[3]
     assert np.array_equal(w, np.sort(np.diag(D))[::-1])
     assert np.array_equal(np.abs(U), np.abs(U).round())
-    for (w, U), B in zip(res[:3], blocks[:3]):
+    w, U = res[5]  # the same above order 48 (tridiagonal path: no reflection, no QL step)
+    assert np.array_equal(w, np.sort(np.diag(D2))[::-1])
+    assert np.array_equal(np.abs(U), np.abs(U).round())
+    for (w, U), B in zip(res[:3] + res[6:], blocks[:3] + blocks[6:]):
         assert np.array_equal(w, np.diag(B)) and np.array_equal(U, np.eye(B.shape[0]))
     w, U = res[4]
     np.testing.assert_allclose(w, [1.0, -1.0], atol=1e-15)
