@@ -121,9 +121,33 @@ dmrg_status dmrg_problem_check(const dmrg_problem *prob);
  * convert the dense operator blocks once (FP64 -> FP32 [-> BF16], round to
  * nearest even) with the diagonals of square blocks kept in FP64.
  * A plan of precision F32/BF16 can also project in F64.  Synchronizes stream.
- * out: receives the plan (NULL on failure). */
+ * out: receives the plan (NULL on failure).
+ * workspace: NULL, or caller-owned device memory (256-byte aligned) of at
+ *   least dmrg_plan_workspace_size(.., ws_kmax, ..) bytes that the plan uses
+ *   for all of its per-call scratch: the projection intermediate, the
+ *   coefficient-gradient partials and the Davidson arrays (basis, products,
+ *   partial rows) of a subspace of up to ws_kmax vectors.  It must outlive
+ *   the plan and must not be shared with another plan used concurrently.
+ *   With NULL the plan allocates that scratch itself (the Davidson arrays at
+ *   the first solve).  The plan still owns its metadata, task lists and
+ *   reduced-precision operator copies; the block solver, dmrg_project_block
+ *   and the density-matrix calls keep allocating their own scratch.
+ * ws_kmax: 2..48, read only with a workspace; a later dmrg_davidson with a
+ *   larger kmax fails with DMRG_E_NOMEM.
+ * Errors: as dmrg_problem_check; DMRG_E_NOMEM when ws_bytes is below the
+ * size needed (found on the host, before any device call). */
 dmrg_status dmrg_plan_create(dmrg_plan **out, int32_t nprob, const dmrg_problem *probs,
-                             int32_t prec, void *stream);
+                             int32_t prec, int32_t ws_kmax, void *workspace, size_t ws_bytes,
+                             void *stream);
+
+/* Bytes of the caller workspace that dmrg_plan_create needs for these problems,
+ * this precision and Davidson subspaces of up to kmax vectors (2..48), found
+ * by the same host analysis that plan creation runs (records built once, Sec.
+ * "Accelerating projection operation"); no device call.  bytes: host.
+ * The size depends on the tile table in force (dmrg_set_tile_table): query it
+ * under the table the plan will be created with. */
+dmrg_status dmrg_plan_workspace_size(int32_t nprob, const dmrg_problem *probs, int32_t prec,
+                                     int32_t kmax, size_t *bytes);
 
 /* Sizes of a plan.  Any output pointer may be NULL.
  *  n:       total length of psi (sum over members)
@@ -202,6 +226,8 @@ typedef struct {
     int32_t restarts;
     int32_t converged;      /* 1 if ||r|| <= tol */
     int32_t breakdown;      /* 1 if the correction vanished */
+    int32_t host_waits;     /* host waits for the launches of iterations of the whole call
+                               (all members share them) */
 } dmrg_davidson_info;
 
 void dmrg_davidson_default_opts(dmrg_davidson_opts *opts);
@@ -222,7 +248,10 @@ void dmrg_davidson_default_opts(dmrg_davidson_opts *opts);
  * (work enqueued on stream afterwards sees it; synchronize stream before
  * reading it from the host).  Returns DMRG_W_NOT_CONVERGED if any member did not
  * converge, DMRG_E_BREAKDOWN if any broke down, DMRG_E_NONFINITE for a
- * zero or non-finite start vector. */
+ * zero or non-finite start vector, DMRG_E_NOMEM when the plan runs on a caller
+ * workspace sized for fewer than kmax vectors.  The arrays of the subspace
+ * come from the plan's workspace, or are allocated at the first solve (and
+ * again when kmax or kmin changes). */
 dmrg_status dmrg_davidson(dmrg_plan *plan, const double *coef, const dmrg_davidson_opts *opts,
                           double *psi, double *energy, dmrg_davidson_info *info, void *stream);
 
@@ -315,8 +344,9 @@ dmrg_status dmrg_density(dmrg_plan *plan, const double *psi, double *rho_left, d
 
 /* Eigen-decomposition of symmetric blocks, e.g. the density-matrix blocks of
  * dmrg_density (Alg. 1, step 6: the eigenvalues of each block's density
- * matrix select the states the block keeps).  Cyclic Jacobi method in FP64,
- * one workgroup per block.
+ * matrix select the states the block keeps).  FP64, one workgroup per block:
+ * cyclic Jacobi for orders up to 48 (in LDS), Householder reduction to
+ * tridiagonal form and the implicit QL iteration for larger orders.
  *  off, dim, woff: device arrays [nblk].  Block b is the row-major symmetric
  *    [dim[b]][dim[b]] matrix at a + off[b] (every entry is read).
  *  w + woff[b]: its eigenvalues in descending order (ties by index).
@@ -324,8 +354,10 @@ dmrg_status dmrg_density(dmrg_plan *plan, const double *psi, double *rho_left, d
  *    of w[woff[b] + j], with its first entry of largest magnitude positive.
  *  a is overwritten (contents unspecified on return).  a, w and u are
  *    device FP64, owned by the caller, and must not overlap.
- *  info: optional device [nblk]: sweeps used, -1 if dim[b] is outside
- *    1..2048 (the block is then not touched), -2 if 40 sweeps did not converge.
+ *  info: optional device [nblk]: Jacobi sweeps (order <= 48) or 1 + the QL
+ *    iterations (larger orders), -1 if dim[b] is outside 1..2048 (the block is
+ *    then not touched), -2 if the method did not converge (40 sweeps; 60 QL
+ *    iterations for one eigenvalue).
  *  The sizes are read on the device: the caller guarantees that every
  *  block lies inside a, w and u.  Asynchronous on stream.
  *  Errors: DMRG_E_INVALID_ARG for nblk < 0, a null array, or a, w, u that

@@ -254,9 +254,58 @@ class Plan:
     workload class and precision (built-in table if none is stored), None
     keeps the process-wide table as set by :func:`set_tile_table`, or a pair
     ``(bounds, tiles)`` is used for this plan only.
+    ``workspace``: None (the plan allocates its scratch), a CUDA uint8 tensor
+    of at least :meth:`workspace_size` bytes that the caller owns, or True (a
+    tensor of that size is allocated here and kept by the plan); the scratch
+    of Davidson solves with kmax <= ``ws_kmax`` then comes from it (LR plans).
     """
 
-    def __init__(self, problems, prec: str = "f64", device=None, tiles="auto"):
+    @staticmethod
+    def _table(problems, prec: str, tiles):
+        """The tile table a plan of these problems is built with (None: the
+        process-wide one)."""
+        if tiles == "auto":
+            if is_four_subsystem(problems[0]):
+                return None
+            from . import autotune
+
+            return autotune.load_table(autotune.key_of(problems, prec))
+        return tiles
+
+    @staticmethod
+    def _with_table(table, call):
+        """Run call() with `table` in force (the process-wide table is restored
+        after); the library's error message is read before the restore."""
+        if table is None:
+            st = call()
+            return st, N.last_error() if st else ""
+        set_tile_table(*table)
+        try:
+            st = call()
+            msg = N.last_error() if st else ""
+        finally:
+            set_tile_table((), ())
+        return st, msg
+
+    @staticmethod
+    def workspace_size(problems, prec: str = "f64", kmax: int = 32, tiles="auto") -> int:
+        """Bytes of the caller workspace of an LR plan (dmrg_plan_workspace_size;
+        host analysis only, no device call), under the tile table the plan
+        will be built with (``tiles`` as in the constructor)."""
+        if not isinstance(problems, (list, tuple)):
+            problems = [problems]
+        problems = list(problems)
+        m = _Marshal(problems, device=None)
+        if m.four:
+            raise ValueError("plans of four subsystems (l-1-1-r) take no caller workspace")
+        b = ctypes.c_size_t()
+        st, msg = Plan._with_table(Plan._table(problems, prec, tiles), lambda: N.lib().dmrg_plan_workspace_size(
+            len(problems), m.structs, N.PREC[prec], int(kmax), ctypes.byref(b)))
+        if st:
+            raise N.DmrgError(st, msg)
+        return int(b.value)
+
+    def __init__(self, problems, prec: str = "f64", device=None, tiles="auto", workspace=None, ws_kmax: int = 32):
         import torch
 
         if not isinstance(problems, (list, tuple)):
@@ -269,32 +318,33 @@ class Plan:
         self.four = is_four_subsystem(self.problems[0])
         if self.four and self.prec != N.F64:
             raise ValueError("four-subsystem (l-1-1-r) plans compute in FP64 only")
-        table = None
-        if tiles == "auto" and self.four:
-            table = None
-        elif tiles == "auto":
-            from . import autotune
-
-            table = autotune.load_table(autotune.key_of(self.problems, prec))
-        elif tiles is not None:
-            table = tiles
+        table = Plan._table(self.problems, prec, tiles)
         self.tiles = table
+        self.workspace = None
+        if workspace is not None:
+            if self.four:
+                raise ValueError("plans of four subsystems (l-1-1-r) take no caller workspace")
+            if workspace is True:
+                nb = Plan.workspace_size(self.problems, prec, ws_kmax, tiles=table)
+                workspace = torch.empty(nb, dtype=torch.uint8, device=self.device)
+            if not (workspace.is_cuda and workspace.dtype == torch.uint8 and workspace.is_contiguous()):
+                raise ValueError("workspace must be a contiguous CUDA uint8 tensor")
+            self.workspace = workspace  # the caller's memory must outlive the plan
         with torch.cuda.device(self.device):
             self._m = _Marshal(self.problems, device=self.device)
             h = ctypes.c_void_p()
-            if table is not None:
-                set_tile_table(*table)
-            try:
-                if self.four:
-                    st = self._lib.dmrg_plan_create_l11r(ctypes.byref(h), len(self.problems), self._m.structs,
-                                                         _stream(self.device))
-                else:
-                    st = self._lib.dmrg_plan_create(ctypes.byref(h), len(self.problems), self._m.structs,
-                                                    self.prec, _stream(self.device))
-            finally:
-                if table is not None:
-                    set_tile_table((), ())
-            N.check(st)
+            ws = self.workspace
+            if self.four:
+                create = lambda: self._lib.dmrg_plan_create_l11r(ctypes.byref(h), len(self.problems),
+                                                                 self._m.structs, _stream(self.device))
+            else:
+                create = lambda: self._lib.dmrg_plan_create(
+                    ctypes.byref(h), len(self.problems), self._m.structs, self.prec, int(ws_kmax),
+                    ws.data_ptr() if ws is not None else None, ws.numel() if ws is not None else 0,
+                    _stream(self.device))
+            st, msg = Plan._with_table(table, create)
+            if st < 0 or st > 0:
+                raise N.DmrgError(st, msg)
         self._h = h
         n, npair, nrec, flop, nbytes = (ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64(),
                                         ctypes.c_int64())

@@ -7,7 +7,7 @@ from __future__ import annotations
 
 import ctypes
 import os
-from ctypes import POINTER, c_char_p, c_double, c_int32, c_int64, c_void_p
+from ctypes import POINTER, c_char_p, c_double, c_int32, c_int64, c_size_t, c_void_p
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdmrg.so")
 
@@ -58,7 +58,7 @@ class DavidsonOpts(ctypes.Structure):
 class DavidsonInfo(ctypes.Structure):
     _fields_ = [("energy", c_double), ("residual", c_double), ("iterations", c_int32),
                 ("iterations_low", c_int32), ("projections", c_int32), ("restarts", c_int32),
-                ("converged", c_int32), ("breakdown", c_int32)]
+                ("converged", c_int32), ("breakdown", c_int32), ("host_waits", c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -113,7 +113,9 @@ _lib = None
 
 SIGNATURES = {
     "dmrg_problem_check": (c_int32, [POINTER(Problem)]),
-    "dmrg_plan_create": (c_int32, [POINTER(c_void_p), c_int32, POINTER(Problem), c_int32, c_void_p]),
+    "dmrg_plan_create": (c_int32, [POINTER(c_void_p), c_int32, POINTER(Problem), c_int32, c_int32, c_void_p,
+                                   c_size_t, c_void_p]),
+    "dmrg_plan_workspace_size": (c_int32, [c_int32, POINTER(Problem), c_int32, c_int32, POINTER(c_size_t)]),
     "dmrg_plan_sizes": (c_int32, [c_void_p, POINTER(c_int64), POINTER(c_int32), POINTER(c_int32),
                                   POINTER(c_int64), POINTER(c_int64)]),
     "dmrg_plan_layout": (c_int32, [c_void_p, POINTER(c_int32), POINTER(c_int32), POINTER(c_int32),

@@ -114,6 +114,7 @@ struct DavidsonWork {
     // data: a solve that stopped early, broke down or met a non-finite iterate
     // leaves the workspace dirty, and the next solve clears it first
     bool dirty = false;
+    int32_t waits = 0;  // host synchronizations of the current dmrg_davidson call
     size_t rowb = 0;  // bytes of one partial-row column set per chunk / tile row
 };
 
@@ -1251,9 +1252,67 @@ static dmrg_status work_zero(const dmrg_plan *plan, DavidsonWork *w, hipStream_t
     return DMRG_OK;
 }
 
+// Chunks of the vector kernels: at most TPB elements, never crossing a member
+// boundary (an empty member gets one empty chunk, which keeps the bookkeeping
+// uniform).  Returns the chunk count; the lists are filled when given.
+static int dav_chunks(const dmrg_plan *plan, std::vector<int32_t> *cm, std::vector<int64_t> *cb,
+                      std::vector<int32_t> *mc) {
+    const int64_t CH = TPB;  // one element per thread: many blocks, every column load in flight
+    int count = 0;
+    if (mc) mc->assign(1, 0);
+    for (int p = 0; p < plan->nprob; ++p) {
+        int64_t b = plan->member_off[p], e = plan->member_off[p + 1];
+        if (e == b) {
+            if (cm) cm->push_back(p);
+            if (cb) cb->push_back(b);
+            ++count;
+        }
+        for (int64_t x = b; x < e; x += CH) {
+            if (cm) cm->push_back(p);
+            if (cb) cb->push_back(x);
+            ++count;
+        }
+        if (mc) mc->push_back(count);
+    }
+    if (cb) cb->push_back(plan->n);
+    return count;
+}
+
+// The Davidson arrays, in allocation order.
+enum {
+    DB_V, DB_W, DB_T, DB_D, DB_DFOLD, DB_COEF, DB_PA, DB_PB, DB_PC, DB_PTILE, DB_CMEM, DB_CBEG, DB_MCH, DB_ST,
+    DB_ACT, DB_X0, DB_ACT2, DB_DFOLD2, DB_GATE, DB_COUNT
+};
+
+static void dav_sizes(const dmrg_plan *plan, int kmax, int nchunk, int tiles, size_t sz[DB_COUNT]) {
+    const size_t n = (size_t)plan->n, rowb = (KM + 2) * 8, np = (size_t)plan->nprob;
+    sz[DB_V] = sz[DB_W] = (kmax + 1) * n * 8;
+    sz[DB_T] = sz[DB_D] = sz[DB_DFOLD] = sz[DB_X0] = sz[DB_DFOLD2] = n * 8;
+    sz[DB_COEF] = (size_t)std::max(plan->nterm_total, 1) * 8;
+    sz[DB_PA] = sz[DB_PB] = sz[DB_PC] = (size_t)nchunk * rowb;  // partial rows, one per chunk (three sets)
+    sz[DB_PTILE] = (size_t)tiles * rowb;                         // one per output tile (Rayleigh rows)
+    sz[DB_CMEM] = (size_t)nchunk * 4;
+    sz[DB_CBEG] = (size_t)(nchunk + 1) * 8;
+    sz[DB_MCH] = (np + 1) * 4;
+    sz[DB_ST] = np * sizeof(DavState);
+    sz[DB_ACT] = sz[DB_ACT2] = np * 4;
+    sz[DB_GATE] = 8;
+    for (int i = 0; i < DB_COUNT; ++i) sz[i] = std::max<size_t>(sz[i], 8);
+}
+
+size_t dav_workspace_bytes(const dmrg_plan *plan, int kmax, int tiles) {
+    size_t sz[DB_COUNT], total = 0;
+    dav_sizes(plan, kmax, dav_chunks(plan, nullptr, nullptr, nullptr), tiles, sz);
+    for (int i = 0; i < DB_COUNT; ++i) total += ws_align(sz[i]);
+    return total;
+}
+
 static dmrg_status work_alloc(dmrg_plan *plan, int kmax, int kmin, hipStream_t s) {
     DavidsonWork *w = plan->dav;
     if (w && w->kmax == kmax && w->kmin == kmin) return w->dirty ? work_zero(plan, w, s) : DMRG_OK;
+    if (plan->ws && kmax > plan->ws_kmax)
+        return set_error(DMRG_E_NOMEM, "the plan's workspace holds a subspace of at most %d vectors (kmax %d asked)",
+                         plan->ws_kmax, kmax);
     davidson_free(plan);
     w = new DavidsonWork();
     plan->dav = w;
@@ -1262,61 +1321,53 @@ static dmrg_status work_alloc(dmrg_plan *plan, int kmax, int kmin, hipStream_t s
     DavArgs &A = w->a;
     A.n = plan->n;
     A.nprob = plan->nprob;
-    // chunks: at most 2048 elements, never crossing a member boundary
-    std::vector<int32_t> cm;
+    std::vector<int32_t> cm, mc;
     std::vector<int64_t> cb;
-    std::vector<int32_t> mc(1, 0);
-    const int64_t CH = TPB;  // one element per thread: many blocks, every column load in flight
-    for (int p = 0; p < plan->nprob; ++p) {
-        int64_t b = plan->member_off[p], e = plan->member_off[p + 1];
-        if (e == b) {  // empty member: one empty chunk keeps the bookkeeping uniform
-            cm.push_back(p);
-            cb.push_back(b);
-        }
-        for (int64_t x = b; x < e; x += CH) {
-            cm.push_back(p);
-            cb.push_back(x);
-        }
-        mc.push_back((int32_t)cm.size());
-    }
-    cb.push_back(plan->n);
-    A.nchunk = (int)cm.size();
-    auto alloc = [&](void **p, size_t bytes) -> dmrg_status {
-        DMRG_HIP(hipMalloc(p, std::max<size_t>(bytes, 8)));
-        w->owned.push_back(*p);
-        return DMRG_OK;
-    };
-    const size_t n = (size_t)plan->n;
-    DMRG_TRY(alloc((void **)&A.V, (kmax + 1) * n * 8));
-    DMRG_TRY(alloc((void **)&A.W, (kmax + 1) * n * 8));
-    DMRG_TRY(alloc((void **)&A.T, n * 8));
-    DMRG_TRY(alloc((void **)&A.D, n * 8));
-    DMRG_TRY(alloc((void **)&A.dfold, n * 8));
-    DMRG_TRY(alloc((void **)&A.coef, std::max(plan->nterm_total, 1) * 8));
-    // partial rows: one per chunk (three sets), one per output tile (Rayleigh rows)
-    const size_t rowb = (KM + 2) * 8;
-    w->rowb = rowb;
+    A.nchunk = dav_chunks(plan, &cm, &cb, &mc);
     const int tiles = std::max({1, plan->fwd[0].stageB.ntask, plan->fwd[1].stageB.ntask});
     A.tile_ld = tiles;
-    DMRG_TRY(alloc((void **)&A.pa, (size_t)A.nchunk * rowb));
-    DMRG_TRY(alloc((void **)&A.pb, (size_t)A.nchunk * rowb));
-    DMRG_TRY(alloc((void **)&A.pc, (size_t)A.nchunk * rowb));
-    DMRG_TRY(alloc((void **)&A.ptile, (size_t)tiles * rowb));
-    DMRG_TRY(alloc((void **)&A.chunk_member, cm.size() * 4));
-    DMRG_TRY(alloc((void **)&A.chunk_begin, cb.size() * 8));
-    DMRG_TRY(alloc((void **)&A.member_chunk, mc.size() * 4));
-    DMRG_TRY(alloc((void **)&A.st, plan->nprob * sizeof(DavState)));
-    DMRG_TRY(alloc((void **)&A.active, plan->nprob * 4));
-    DMRG_TRY(alloc((void **)&A.X0, n * 8));
+    w->rowb = (KM + 2) * 8;
+    size_t sz[DB_COUNT];
+    dav_sizes(plan, kmax, A.nchunk, tiles, sz);
+    void *buf[DB_COUNT];
+    if (plan->ws) {  // carved from the caller's workspace, in order
+        char *q = plan->ws + plan->ws_dav;
+        for (int i = 0; i < DB_COUNT; ++i) {
+            buf[i] = q;
+            q += ws_align(sz[i]);
+        }
+        if (q > plan->ws + plan->ws_bytes) return set_error(DMRG_E_NOMEM, "workspace too small for the Davidson arrays");
+    } else {
+        for (int i = 0; i < DB_COUNT; ++i) {
+            DMRG_HIP(hipMalloc(&buf[i], sz[i]));
+            w->owned.push_back(buf[i]);
+        }
+    }
+    A.V = (double *)buf[DB_V];
+    A.W = (double *)buf[DB_W];
+    A.T = (double *)buf[DB_T];
+    A.D = (double *)buf[DB_D];
+    A.dfold = (double *)buf[DB_DFOLD];
+    A.coef = (double *)buf[DB_COEF];
+    A.pa = (double *)buf[DB_PA];
+    A.pb = (double *)buf[DB_PB];
+    A.pc = (double *)buf[DB_PC];
+    A.ptile = (double *)buf[DB_PTILE];
+    A.chunk_member = (int32_t *)buf[DB_CMEM];
+    A.chunk_begin = (int64_t *)buf[DB_CBEG];
+    A.member_chunk = (int32_t *)buf[DB_MCH];
+    A.st = (DavState *)buf[DB_ST];
+    A.active = (int32_t *)buf[DB_ACT];
+    A.X0 = (double *)buf[DB_X0];
     // the summary goes straight to pinned, mapped, coherent host memory (no copy step)
     DMRG_HIP(hipHostMalloc((void **)&w->h_sum, plan->nprob * sizeof(DavSummary),
                            hipHostMallocMapped | hipHostMallocCoherent));
     DMRG_HIP(hipHostGetDevicePointer((void **)&A.sum, w->h_sum, 0));
     DavArgs &B = w->a2;  // FP64 phase: own flags, folded diagonal, gate and summary
     B = A;
-    DMRG_TRY(alloc((void **)&B.active, plan->nprob * 4));
-    DMRG_TRY(alloc((void **)&B.dfold, n * 8));
-    DMRG_TRY(alloc((void **)&B.gate, 8));
+    B.active = (int32_t *)buf[DB_ACT2];
+    B.dfold = (double *)buf[DB_DFOLD2];
+    B.gate = (int32_t *)buf[DB_GATE];
     DMRG_HIP(hipHostMalloc((void **)&w->h_sum2, plan->nprob * sizeof(DavSummary),
                            hipHostMallocMapped | hipHostMallocCoherent));
     DMRG_HIP(hipHostGetDevicePointer((void **)&B.sum, w->h_sum2, 0));
@@ -1584,12 +1635,19 @@ static bool phase_more(DavidsonWork *w, Phase &P, std::vector<DavSummary> &sm) {
     return false;
 }
 
+// The host waits for the stream (a launch's mapped summary is then readable).
+static dmrg_status host_wait(DavidsonWork *w, hipStream_t s) {
+    ++w->waits;
+    DMRG_HIP(hipStreamSynchronize(s));
+    return DMRG_OK;
+}
+
 // A whole phase, one synchronization per launch.
 static dmrg_status phase_run(dmrg_plan *plan, Phase &P, hipStream_t s, std::vector<DavSummary> &sm) {
     phase_begin(plan->dav, P);
     do {
         DMRG_TRY(phase_launch(plan, P, s));
-        DMRG_HIP(hipStreamSynchronize(s));  // k_summary wrote the mapped summary
+        DMRG_TRY(host_wait(plan->dav, s));  // k_summary wrote the mapped summary
     } while (phase_more(plan->dav, P, sm));
     return DMRG_OK;
 }
@@ -1687,6 +1745,7 @@ dmrg_status dmrg_davidson(dmrg_plan *plan, const double *coef, const dmrg_davids
     DMRG_TRY(work_alloc(plan, kmax, kmin, s));
     DavidsonWork *w = plan->dav;
     w->dirty = true;  // until every member is seen to end with finite data
+    w->waits = 0;
     w->eig_solver = o.eig_solver;
     const DavArgs &A = w->a;
     hipLaunchKernelGGL(k_stage, dim3((unsigned)std::min<int64_t>((A.n + TPB - 1) / TPB, 2048)), dim3(TPB), 0, s, coef,
@@ -1731,19 +1790,19 @@ dmrg_status dmrg_davidson(dmrg_plan *plan, const double *coef, const dmrg_davids
         } else {
             DMRG_TRY(phase_launch(plan, P1, s));
         }
-        DMRG_HIP(hipStreamSynchronize(s));
+        DMRG_TRY(host_wait(w, s));
         bool more1 = phase_more(w, P1, low);
         bool open = chain;  // phase 2 has run its first launch
         for (const DavSummary &r : low) open = open && !r.active;
         if (open) {
             while (phase_more(w, P2, hs)) {
                 DMRG_TRY(phase_launch(plan, P2, s));
-                DMRG_HIP(hipStreamSynchronize(s));
+                DMRG_TRY(host_wait(w, s));
             }
         } else {  // finish phase 1, then phase 2 from its start (a gated launch idled)
             while (more1) {
                 DMRG_TRY(phase_launch(plan, P1, s));
-                DMRG_HIP(hipStreamSynchronize(s));
+                DMRG_TRY(host_wait(w, s));
                 more1 = phase_more(w, P1, low);
             }
             for (int p = 0; p < plan->nprob; ++p)
@@ -1774,6 +1833,7 @@ dmrg_status dmrg_davidson(dmrg_plan *plan, const double *coef, const dmrg_davids
             I.restarts = S.restarts + (both ? low[p].restarts : 0);
             I.converged = S.converged;
             I.breakdown = S.breakdown;
+            I.host_waits = w->waits;
         }
         if (S.breakdown && ret == DMRG_OK)
             ret = set_error(DMRG_E_BREAKDOWN, "member %d: correction vanished after orthogonalization", p);

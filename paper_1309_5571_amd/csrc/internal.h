@@ -217,6 +217,13 @@ struct dmrg_plan {
     int32_t n_rho_tasks = 0;
     dmrg::DavidsonWork *dav = nullptr;
     dmrg::BlockWork *blk = nullptr;  // block Davidson-Liu workspace
+    // caller workspace (null: the plan allocates its scratch itself): the
+    // projection intermediate at offset 0, the coefficient-gradient partials
+    // after it, the Davidson arrays for up to ws_kmax vectors at ws_dav
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    int32_t ws_kmax = 0;
+    size_t ws_part = 0, ws_dav = 0;
 };
 
 namespace dmrg {
@@ -247,6 +254,12 @@ dmrg_status launch_project_multi(dmrg_plan *plan, const double *coef, const doub
                                  double *out, int64_t out_stride, const int32_t *vmask, hipStream_t s);
 // davidson.hip
 dmrg_status davidson_free(dmrg_plan *plan);
+// bytes of the Davidson arrays of a subspace of kmax vectors (the pieces
+// 256-byte aligned), for a plan whose analysis is done; tiles = the largest
+// stage-B task count of its forward passes
+size_t dav_workspace_bytes(const dmrg_plan *plan, int kmax, int tiles);
+constexpr size_t WS_ALIGN = 256;
+inline size_t ws_align(size_t b) { return (b + WS_ALIGN - 1) / WS_ALIGN * WS_ALIGN; }
 // block.hip
 dmrg_status block_free(dmrg_plan *plan);
 // density.hip: output offsets and tile tasks of the reduced density matrices

@@ -662,8 +662,8 @@ static dmrg_status diag_from_records(dmrg_plan *plan, hipStream_t stream) {
     return DMRG_OK;
 }
 
-dmrg_status build_plan(dmrg_plan *plan, int32_t nprob, const dmrg_problem *probs, int32_t prec,
-                       hipStream_t stream) {
+// Host analysis of LR problems: pairs, psi layout, records, FLOP and byte counts.
+static dmrg_status analyse_plan(dmrg_plan *plan, int32_t nprob, const dmrg_problem *probs, int32_t prec) {
     plan->nprob = nprob;
     plan->prec = prec;
     plan->member_off.assign(1, 0);
@@ -722,7 +722,54 @@ dmrg_status build_plan(dmrg_plan *plan, int32_t nprob, const dmrg_problem *probs
     plan->nterm_total = plan->term_off.back();
     plan->flop = flop;
     plan->bytes = opbytes + 16 * plan->n;
+    return DMRG_OK;
+}
+
+dmrg_status build_plan(dmrg_plan *plan, int32_t nprob, const dmrg_problem *probs, int32_t prec,
+                       hipStream_t stream) {
+    DMRG_TRY(analyse_plan(plan, nprob, probs, prec));
     return finish_plan(plan, prec, stream, probs);
+}
+
+// Scratch of an analysed plan: intermediate-buffer elements (largest over the
+// passes), coefficient-gradient partial slots (one per segment and diagonal
+// term of every forward FP64 stage-B task) and the largest stage-B task count.
+static void scratch_sizes(const dmrg_plan *plan, int32_t prec, int64_t *tmp, int32_t *npart, int32_t *tiles) {
+    HostPass f64, a64;
+    build_pass(plan, false, nullptr, 0, f64);
+    build_pass(plan, true, nullptr, 0, a64);
+    int64_t t = std::max(f64.tmp, a64.tmp);
+    int32_t part = 0;
+    for (const Task &k : f64.B) part += (k.seg_end - k.seg_begin) + (k.diag_end - k.diag_begin);
+    int32_t tl = std::max<int32_t>(1, (int32_t)f64.B.size());
+    if (prec != DMRG_F64) {
+        LowStore ls;
+        ls.esize = prec == DMRG_F32 ? 4 : 2;
+        HostPass lo;
+        build_pass(plan, false, &ls, 0, lo);
+        t = std::max(t, lo.tmp);
+        tl = std::max(tl, (int32_t)lo.B.size());
+    }
+    *tmp = std::max<int64_t>(t, 1);
+    *npart = part;
+    *tiles = tl;
+}
+
+// Bytes of the caller workspace of LR problems (host only), and the offsets of
+// its partial-slot and Davidson regions.
+static dmrg_status workspace_need(int32_t nprob, const dmrg_problem *probs, int32_t prec, int32_t kmax,
+                                  size_t *bytes, size_t *part_off, size_t *dav_off) {
+    dmrg_plan tmp;
+    DMRG_TRY(analyse_plan(&tmp, nprob, probs, prec));
+    int64_t te;
+    int32_t npart, tiles;
+    scratch_sizes(&tmp, prec, &te, &npart, &tiles);
+    const size_t po = ws_align((size_t)te * 8);
+    const size_t dav = po + ws_align((size_t)std::max(npart, 1) * 8);
+    if (part_off) *part_off = po;
+    if (dav_off) *dav_off = dav;
+    *bytes = dav + dav_workspace_bytes(&tmp, kmax, tiles);
+    return DMRG_OK;
 }
 
 // Everything after the analysis: task lists of both directions, reduced-
@@ -757,7 +804,11 @@ static dmrg_status finish_plan(dmrg_plan *plan, int32_t prec, hipStream_t stream
         }
         DMRG_TRY(upload(plan, ptr, &plan->d_term_ptr, stream));
         DMRG_TRY(upload(plan, ent, &plan->d_term_ent, stream));
-        if (part > 0) {
+        if (part > 0 && plan->ws) {
+            if (plan->ws_part + (size_t)part * 8 > plan->ws_dav)
+                return set_error(DMRG_E_NOMEM, "workspace layout does not hold the gradient partials");
+            plan->d_partials = (double *)(plan->ws + plan->ws_part);
+        } else if (part > 0) {
             void *q = nullptr;
             DMRG_HIP(hipMalloc(&q, (size_t)part * sizeof(double)));
             plan->owned.push_back(q);
@@ -793,8 +844,14 @@ static dmrg_status finish_plan(dmrg_plan *plan, int32_t prec, hipStream_t stream
         tmp = std::max(tmp, lo2.tmp);
     }
     plan->tmp_bytes = std::max<int64_t>(tmp, 1) * 8;
-    DMRG_HIP(hipMalloc(&plan->d_tmp, plan->tmp_bytes));
-    plan->owned.push_back(plan->d_tmp);
+    if (plan->ws) {
+        if ((size_t)plan->tmp_bytes > plan->ws_part)
+            return set_error(DMRG_E_NOMEM, "workspace layout does not hold the intermediate buffer");
+        plan->d_tmp = plan->ws;
+    } else {
+        DMRG_HIP(hipMalloc(&plan->d_tmp, plan->tmp_bytes));
+        plan->owned.push_back(plan->d_tmp);
+    }
 
     // ---- preconditioner diagonal: per pair, sum_k c_k diag(A_k)(sl) (x) diag(B_k)(sr)
     if (!probs) {
@@ -1107,15 +1164,10 @@ dmrg_status dmrg_set_tile_table(int32_t ncls, const int32_t *bound, const int32_
     return DMRG_OK;
 }
 
-dmrg_status dmrg_plan_create(dmrg_plan **out, int32_t nprob, const dmrg_problem *probs, int32_t prec,
-                             void *stream) {
-    clear_error();
-    if (!out) return set_error(DMRG_E_INVALID_ARG, "null output pointer");
-    *out = nullptr;
+static dmrg_status validate_problems(int32_t nprob, const dmrg_problem *probs, int32_t prec) {
     if (nprob < 1 || !probs) return set_error(DMRG_E_INVALID_ARG, "need nprob >= 1 problems");
     if (prec != DMRG_F64 && prec != DMRG_F32 && prec != DMRG_BF16)
         return set_error(DMRG_E_INVALID_ARG, "unknown precision %d", prec);
-    // host validation first: no GPU is touched for invalid input
     for (int p = 0; p < nprob; ++p) {
         dmrg_status st = analyse(&probs[p], nullptr, nullptr, 0, 0);
         if (st < 0) {
@@ -1123,8 +1175,45 @@ dmrg_status dmrg_plan_create(dmrg_plan **out, int32_t nprob, const dmrg_problem 
             return set_error(st, "problem %d: %s", p, m.c_str());
         }
     }
+    return DMRG_OK;
+}
+
+dmrg_status dmrg_plan_workspace_size(int32_t nprob, const dmrg_problem *probs, int32_t prec, int32_t kmax,
+                                     size_t *bytes) {
+    clear_error();
+    if (!bytes) return set_error(DMRG_E_INVALID_ARG, "null output pointer");
+    *bytes = 0;
+    if (kmax < 2 || kmax > KM) return set_error(DMRG_E_INVALID_ARG, "need 2 <= kmax <= %d", KM);
+    DMRG_TRY(validate_problems(nprob, probs, prec));
+    return workspace_need(nprob, probs, prec, kmax, bytes, nullptr, nullptr);
+}
+
+dmrg_status dmrg_plan_create(dmrg_plan **out, int32_t nprob, const dmrg_problem *probs, int32_t prec,
+                             int32_t ws_kmax, void *workspace, size_t ws_bytes, void *stream) {
+    clear_error();
+    if (!out) return set_error(DMRG_E_INVALID_ARG, "null output pointer");
+    *out = nullptr;
+    // host validation first: no GPU is touched for invalid input or a short workspace
+    DMRG_TRY(validate_problems(nprob, probs, prec));
+    size_t need = 0, part_off = 0, dav_off = 0;
+    if (workspace) {
+        if (ws_kmax < 2 || ws_kmax > KM) return set_error(DMRG_E_INVALID_ARG, "need 2 <= ws_kmax <= %d", KM);
+        if ((uintptr_t)workspace % WS_ALIGN)
+            return set_error(DMRG_E_INVALID_ARG, "workspace must be %d-byte aligned", (int)WS_ALIGN);
+        DMRG_TRY(workspace_need(nprob, probs, prec, ws_kmax, &need, &part_off, &dav_off));
+        if (ws_bytes < need)
+            return set_error(DMRG_E_NOMEM, "workspace of %zu bytes is smaller than the %zu this plan needs", ws_bytes,
+                             need);
+    }
     dmrg_plan *plan = new (std::nothrow) dmrg_plan();
     if (!plan) return set_error(DMRG_E_NOMEM, "host allocation failed");
+    if (workspace) {
+        plan->ws = (char *)workspace;
+        plan->ws_bytes = ws_bytes;
+        plan->ws_kmax = ws_kmax;
+        plan->ws_part = part_off;
+        plan->ws_dav = dav_off;
+    }
     hipError_t e = hipGetDevice(&plan->device);
     if (e != hipSuccess) {
         delete plan;

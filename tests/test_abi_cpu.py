@@ -41,7 +41,7 @@ def test_struct_sizes_match_c_layout():
     assert ctypes.sizeof(N.Space) == 24
     assert ctypes.sizeof(N.Op) == 40
     assert ctypes.sizeof(N.DavidsonOpts) == 64
-    assert ctypes.sizeof(N.DavidsonInfo) == 40
+    assert ctypes.sizeof(N.DavidsonInfo) == 48  # two doubles, seven int32, tail padding
     assert ctypes.sizeof(N.RenormBlock) == 56
     assert ctypes.sizeof(N.Place) == 48
 
@@ -115,11 +115,64 @@ def test_plan_create_rejects_invalid_input_without_gpu():
     p.coef = np.array([1.0])
     m = _Marshal([p], device=None)
     h = ctypes.c_void_p()
-    st = N.lib().dmrg_plan_create(ctypes.byref(h), 1, m.structs, N.F64, None)
+    st = N.lib().dmrg_plan_create(ctypes.byref(h), 1, m.structs, N.F64, 0, None, 0, None)
     assert st == N.E_SECTOR and not h.value
     assert "target sector" in N.last_error()
-    st = N.lib().dmrg_plan_create(ctypes.byref(h), 1, m.structs, 7, None)
+    st = N.lib().dmrg_plan_create(ctypes.byref(h), 1, m.structs, 7, 0, None, 0, None)
     assert st == N.E_INVALID_ARG
+
+
+def test_workspace_size_host_only():
+    """dmrg_plan_workspace_size runs the host analysis only: it works without a
+    GPU, and each extra Davidson vector adds the two basis columns (V and W,
+    n doubles each) up to the 256-byte alignment of the two arrays."""
+    from paper_1309_5571_amd import Plan
+
+    p = gen.config(2)
+    n = int(sum(int(p.left.dims[i]) * int(p.right.dims[j]) for i, j in _target_pairs(p)))
+    sizes = {k: Plan.workspace_size(p, "f64", k) for k in (8, 9, 32, 48)}
+    assert sizes[8] < sizes[9] < sizes[32] < sizes[48]
+    assert abs((sizes[9] - sizes[8]) - 16 * n) <= 512
+    assert abs((sizes[48] - sizes[32]) - 16 * 16 * n) <= 512
+    # the reduced-precision plan may need a larger intermediate, never a smaller one
+    assert Plan.workspace_size(p, "f32", 32) >= sizes[32]
+    lib, m = N.lib(), _Marshal_of(p)
+    b = ctypes.c_size_t()
+    assert lib.dmrg_plan_workspace_size(1, m.structs, N.F64, 1, ctypes.byref(b)) == N.E_INVALID_ARG
+    assert lib.dmrg_plan_workspace_size(1, m.structs, N.F64, 49, ctypes.byref(b)) == N.E_INVALID_ARG
+
+
+def test_plan_create_short_workspace_is_nomem_without_gpu():
+    """A workspace below the size is refused on the host (DMRG_E_NOMEM), as is
+    a misaligned one (DMRG_E_INVALID_ARG); neither pointer is dereferenced."""
+    from paper_1309_5571_amd import Plan
+
+    p = gen.heisenberg_synthetic(64, seed=1)
+    need = Plan.workspace_size(p, "f64", 16)
+    m = _Marshal_of(p)
+    h = ctypes.c_void_p()
+    fake = ctypes.c_void_p(1 << 20)
+    st = N.lib().dmrg_plan_create(ctypes.byref(h), 1, m.structs, N.F64, 16, fake, need - 1, None)
+    assert st == N.E_NOMEM and not h.value
+    assert "workspace" in N.last_error()
+    st = N.lib().dmrg_plan_create(ctypes.byref(h), 1, m.structs, N.F64, 16, ctypes.c_void_p((1 << 20) + 8), need, None)
+    assert st == N.E_INVALID_ARG and not h.value
+    st = N.lib().dmrg_plan_create(ctypes.byref(h), 1, m.structs, N.F64, 60, fake, need, None)
+    assert st == N.E_INVALID_ARG
+
+
+def _Marshal_of(p):
+    from paper_1309_5571_amd import _Marshal
+
+    return _Marshal([p], device=None)
+
+
+def _target_pairs(p):
+    """(left sector, right sector) index pairs whose labels add to the target."""
+    tgt = np.asarray(p.target).reshape(-1)
+    L = np.asarray(p.left.labels).reshape(len(p.left.dims), -1)
+    R = np.asarray(p.right.labels).reshape(len(p.right.dims), -1)
+    return [(i, j) for i in range(len(L)) for j in range(len(R)) if np.array_equal(L[i] + R[j], tgt)]
 
 
 def test_gemv_argument_errors():
