@@ -14,6 +14,14 @@ adjoint kernel.  `value` = Davidson iterations per second over the timed
 steps.  The projection alone is also timed (HIP events, FP64/FP32/BF16) and
 reported in TFLOP/s, and the FP64-only solve is timed for comparison.
 
+Beside the headline line (unless --no-extras): time to solution in mixed
+precision and in FP64 from the same start vector at two residual tolerances,
+with the energy error against an FP64 solve at 1e-12; plan creation plus the
+first solve on a fresh plan; compact projection and solve figures of the
+Heisenberg m=1024 superblock and the 64-member batch; block Davidson-Liu for
+the four lowest states; and the l-1-1-r strategy on a Hubbard superblock of two
+512-state blocks and two sites.
+
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
 import argparse
@@ -40,9 +48,12 @@ def parse():
                     help="skip the eigen-decomposition / selection timing and the infinite-lattice run "
                          "reported beside the solve")
     ap.add_argument("--quick", action="store_true", help="skip the projection and FP64 comparison timings")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the time-to-solution table, the fresh-plan solve and the other workloads "
+                         "(block Davidson-Liu, l-1-1-r, Heisenberg m=1024, the 64-member batch)")
     ap.add_argument("--workload", default="hubbard_m2048",
                     choices=["hubbard_m2048", "heisenberg_m1024", "j1j2_m1024", "batched_64", "gemv", "pmc",
-                             "infinite_heisenberg", "block_projection"],
+                             "pmc_heisenberg", "infinite_heisenberg", "block_projection"],
                     help="hubbard_m2048 is the headline line; the others time the projection and the "
                          "mixed-precision solve of the other synthetic workloads")
     return ap.parse_args()
@@ -116,7 +127,8 @@ def density_stats(plan, psi, reps, torch):
 
 def renorm_stats(plan, psi, torch, reps=10):
     """The rest of the renormalization step on the device (Alg. 1, steps 6-7)
-    for the left block: eigen-decomposition of every density-matrix block
+    for the left block of the state psi (the ground state in the bench line):
+    eigen-decomposition of every density-matrix block
     (dmrg_eigh_blocks) and the state selection (dmrg_truncate).  Per-call
     durations from HIP event pairs on the launch stream (the work copy of rho
     that each eigen-decomposition overwrites is refreshed outside the pair)."""
@@ -187,6 +199,182 @@ def block_projection(p, reps, sizes=(1, 2, 4, 8, 16, 32)):
     return {"workload": "block_projection_hubbard_m2048", "rows": rows}
 
 
+def _median(xs):
+    xs = sorted(xs)
+    return xs[len(xs) // 2]
+
+
+def _solve_ms(plan, x0, prec, tol, reps, torch):
+    """Warm solves of one plan from the same start vector: median wall time of
+    dmrg_davidson (host clock around the call, stream drained on both sides),
+    with the last call's energies and infos."""
+    out = None
+    for _ in range(2):
+        plan.davidson(x0, tol=tol, prec=prec)
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = plan.davidson(x0, tol=tol, prec=prec)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    _, E, info, st = out
+    if st != 0:
+        raise RuntimeError(f"Davidson status {st}: {info}")
+    return _median(ts) * 1e3, E, info
+
+
+def solve_comparison(plan, x0, prec, torch, tols=(1e-5, 1e-10), reps=5):
+    """Time to solution, mixed precision against FP64, from the same start
+    vector: for each residual tolerance, the warm solve time, the iterations, the
+    host waits and the largest energy error against an FP64 solve at 1e-12.
+    `time_to_1e-8` is, per precision, the fastest solve whose energies are all
+    within 1e-8 of that reference."""
+    import numpy as np
+
+    _, Eref, _ = _solve_ms(plan, x0, "f64", 1e-12, 1, torch)
+    rows = []
+    best = {}
+    for pr in (prec, "f64"):
+        for tol in tols:
+            ms, E, info = _solve_ms(plan, x0, pr, tol, reps, torch)
+            dE = float(np.max(np.abs(np.asarray(E) - Eref)))
+            rows.append({"prec": pr, "tol": tol, "ms": ms, "dE": dE,
+                         "iterations": max(i["iterations"] for i in info),
+                         "iterations_lowprec": max(i["iterations_low"] for i in info),
+                         "host_waits": info[0]["host_waits"]})
+            if dE <= 1e-8:
+                best[pr] = min(best.get(pr, float("inf")), ms)
+    return {"rows": rows, "time_to_1e-8_ms": best,
+            "mixed_over_fp64": best[prec] / best["f64"] if prec in best and "f64" in best else None}
+
+
+def fresh_plan_solve(p, x0_np, prec, torch, reps=3):
+    """What every DMRG step pays: plan creation (operator upload, records, task
+    lists, low-precision copies) and the first solve on that plan (workspace
+    allocation and graph capture included), FP64 and mixed, to 1e-10.  Median of
+    `reps` fresh plans, host clock with the stream drained."""
+    import paper_1309_5571_amd as dm
+
+    res = {}
+    for pr in ("f64", prec):
+        tp, ts = [], []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan = dm.Plan(p, prec=pr)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            x0 = torch.from_numpy(x0_np).cuda()
+            _, _, info, st = plan.davidson(x0, tol=1e-10, prec=pr)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            if st != 0:
+                raise RuntimeError(f"Davidson status {st}: {info}")
+            plan.close()
+            tp.append(t1 - t0)
+            ts.append(t2 - t1)
+        res[pr] = {"plan_ms": _median(tp) * 1e3, "first_solve_ms": _median(ts) * 1e3,
+                   "total_ms": (_median(tp) + _median(ts)) * 1e3}
+    return res
+
+
+def config_summary(cfg, prec, torch, proj_reps=100, reps=3):
+    """Compact figures of another workload: the projection per precision (µs,
+    TFLOP/s and the fraction of that precision's dense MFMA peak) and the solve to
+    1e-10 in mixed precision against FP64 (ms, iterations, host waits)."""
+    import gen
+    import paper_1309_5571_amd as dm
+
+    p = gen.config(cfg)
+    plan = dm.Plan(p, prec=prec)
+    planb = dm.Plan(p, prec="bf16") if prec != "bf16" else plan
+    x0 = torch.from_numpy(gen.start_vector(plan.n, 7)).cuda()
+    psi = x0 / x0.norm()
+    y = torch.empty_like(psi)
+    peak = {"f64": PEAK["f64_TFs"], "f32": PEAK["f32_TFs"], "bf16": PEAK["bf16_TFs"]}
+    proj = {}
+    for pr, pl in (("f64", plan), (prec, plan), ("bf16", planb)):
+        t = timed_projection(pl, psi, y, pr, proj_reps, torch)
+        tf = plan.flop / t * 1e-12
+        proj[pr] = {"us": t * 1e6, "tflops": tf, "frac_mfma_peak": tf / peak[pr]}
+    solve = {}
+    for pr in (prec, "f64"):
+        ms, E, info = _solve_ms(plan, x0, pr, 1e-10, reps, torch)
+        solve[pr] = {"ms": ms, "iterations": max(i["iterations"] for i in info),
+                     "host_waits": info[0]["host_waits"], "energy0": float(E[0])}
+    res = {"workload": gen.CONFIG_NAMES[cfg], "members": len(plan.problems), "n": plan.n, "flop": plan.flop,
+           "projection": proj, "solve": solve,
+           "mixed_over_fp64_solve": solve[prec]["ms"] / solve["f64"]["ms"]}
+    if planb is not plan:
+        planb.close()
+    plan.close()
+    return res
+
+
+def block_summary(p, torch, b=4, reps=3, proj_reps=100):
+    """Block Davidson-Liu on one superblock: the b lowest eigenpairs to 1e-10
+    (median wall time, iterations, restarts) and the b-vector projection per
+    vector against b single projections (HIP events on the launch stream)."""
+    import numpy as np
+
+    import gen
+    import paper_1309_5571_amd as dm
+
+    plan = dm.Plan(p)
+    X0 = torch.from_numpy(np.stack([gen.start_vector(plan.n, 7 + j) for j in range(b)])).cuda()
+    Y = torch.empty_like(X0)
+    s = torch.cuda.current_stream()
+    for _ in range(5):
+        plan.project_block(X0, out=Y)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(proj_reps):
+        plan.project_block(X0, out=Y)
+    e1.record(s)
+    e1.synchronize()
+    t_blk = e0.elapsed_time(e1) * 1e-3 / proj_reps
+    t_one = timed_projection(plan, X0[0].contiguous(), Y[0], "f64", proj_reps, torch)
+    out = None
+    plan.block_davidson(X0, tol=1e-10)
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = plan.block_davidson(X0, tol=1e-10)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    _, E, R, info, st = out
+    _, E1, _, _ = plan.davidson(X0[0], tol=1e-10)
+    plan.close()
+    return {"nroots": b, "solve_ms": _median(ts) * 1e3, "status": st, "energies": [float(e) for e in E],
+            "max_residual": float(np.max(R)), "iterations": info["iterations"], "restarts": info["restarts"],
+            "projections": info["projections"], "E0_minus_single_vector": float(E[0] - E1[0]),
+            "projection_us_per_vector": t_blk * 1e6 / b, "projection_us_single": t_one * 1e6}
+
+
+def l11r_summary(torch, m=512, reps=3, proj_reps=100):
+    """The l-1-1-r strategy (Eq. 12-13, Alg. 2) on the Hubbard superblock of
+    two m-state blocks and two sites (the enlarged blocks have 4 m states, as
+    the LR workload at m = 4 m): FP64 projection time and FLOP rate, and the
+    FP64 ground-state solve to 1e-10."""
+    import gen
+    import paper_1309_5571_amd as dm
+
+    p = gen.hubbard_l11r_synthetic(m)
+    plan = dm.Plan(p)
+    x0 = torch.from_numpy(gen.start_vector(plan.n, 7)).cuda()
+    psi = x0 / x0.norm()
+    y = torch.empty_like(psi)
+    t = timed_projection(plan, psi, y, "f64", proj_reps, torch)
+    ms, E, info = _solve_ms(plan, x0, "f64", 1e-10, reps, torch)
+    res = {"workload": f"hubbard_l11r_m{m}", "n": plan.n, "records": plan.nrec, "flop": plan.flop,
+           "algorithmic_bytes": plan.bytes, "projection_us": t * 1e6, "tflops": plan.flop / t * 1e-12,
+           "solve_ms": ms, "iterations": info[0]["iterations"], "energy": float(E[0])}
+    plan.close()
+    return res
+
+
 def infinite_workload(nsites=100, m=32, reps=3):
     """The whole infinite-lattice iteration (Alg. 1) grown from 4 to `nsites`
     sites of the Heisenberg chain keeping m states: wall time per growth step
@@ -255,10 +443,11 @@ def log(msg):
 COPY_BYTES = 256 << 20  # calibration copy: reads and writes this many bytes
 
 
-def pmc_workload():
-    """Dispatches for the HBM-traffic counters (run under rocprofv3 --pmc): a plain
-    device copy of COPY_BYTES (calibrates FETCH_SIZE / WRITE_SIZE), then 20 FP64
-    projections of the Hubbard m=2048 superblock."""
+def pmc_workload(cfg=3):
+    """Dispatches for the hardware counters (run under rocprofv3 --pmc): a plain
+    device copy of COPY_BYTES (calibrates FETCH_SIZE / WRITE_SIZE), then 20
+    projections of the workload in each precision, FP64 first, then FP32 and BF16
+    (distinct kernel instantiations, so the counters separate by kernel name)."""
     import torch
 
     import gen
@@ -270,15 +459,19 @@ def pmc_workload():
         y.copy_(x)
     torch.cuda.synchronize()
     del x, y
-    p = gen.config(3)
-    plan = dm.Plan(p)
+    p = gen.config(cfg)
+    plans = {"f32": dm.Plan(p, prec="f32"), "bf16": dm.Plan(p, prec="bf16")}
+    plan = plans["f32"]
     psi = torch.from_numpy(gen.start_vector(plan.n, 7)).cuda()
+    psi /= psi.norm()
     out = torch.empty_like(psi)
-    for _ in range(20):
-        plan.project_raw(psi, out=out)
-    torch.cuda.synchronize()
-    return {"workload": "pmc", "copy_bytes": COPY_BYTES, "projections": 20,
-            "projection_algorithmic_bytes": plan.bytes}
+    for prec, pl in (("f64", plan), ("f32", plan), ("bf16", plans["bf16"])):
+        for _ in range(20):
+            pl.project_raw(psi, prec=prec, out=out)
+        torch.cuda.synchronize()
+    return {"workload": "pmc", "config": gen.CONFIG_NAMES[cfg], "copy_bytes": COPY_BYTES,
+            "projections_per_precision": 20, "projection_algorithmic_bytes": plan.bytes,
+            "projection_algorithmic_flop": plan.flop}
 
 
 def traffic_from_profile(plan_bytes):
@@ -352,8 +545,8 @@ def main():
     if args.workload == "gemv":
         print(json.dumps({"workload": "gemv_sweep", "unit": "GB/s", "rows": gemv_sweep()}))
         return
-    if args.workload == "pmc":
-        print(json.dumps(pmc_workload()))
+    if args.workload in ("pmc", "pmc_heisenberg"):
+        print(json.dumps(pmc_workload(3 if args.workload == "pmc" else 2)))
         return
     if args.workload == "infinite_heisenberg":
         print(json.dumps(infinite_workload()))
@@ -429,12 +622,28 @@ def main():
         extra["density"] = density_stats(plan, psi, args.proj_reps, torch)
         log(f"density matrices: {extra['density']}")
         if not args.no_renorm:
-            extra["renormalization"] = renorm_stats(plan, psi, torch)
+            # the density matrix of the ground state, as the renormalization step takes it
+            psi_gs, _, _, st_gs = plan.davidson(x0, coef, tol=1e-10)
+            if st_gs != 0:
+                raise RuntimeError(f"Davidson status {st_gs}")
+            extra["renormalization"] = renorm_stats(plan, psi_gs, torch)
             log(f"eigen-decomposition and selection: {extra['renormalization']}")
         if cfg == 3 and not args.no_renorm:  # the whole infinite-lattice iteration, Heisenberg chain to 100 sites
             extra["infinite_heisenberg"] = infinite_workload(reps=1)
             log(f"infinite-lattice DMRG: {extra['infinite_heisenberg']}")
         extra["mixed_vs_fp64_time_ratio"] = (dt / args.steps * 1e3) / extra["fp64_solve"]["ms_per_solve"]
+    if not args.quick and not args.no_extras:
+        extra["solve"] = solve_comparison(plan, x0, args.prec, torch)
+        log(f"time to solution, mixed vs FP64: {extra['solve']}")
+        extra["fresh_plan"] = fresh_plan_solve(p, x0_np, args.prec, torch)
+        log(f"fresh plan + first solve: {extra['fresh_plan']}")
+        if cfg == 3:
+            extra["other_configs"] = [config_summary(c, args.prec, torch) for c in (2, 4)]
+            log(f"other workloads: {extra['other_configs']}")
+            extra["block_davidson"] = block_summary(p, torch)
+            log(f"block Davidson-Liu: {extra['block_davidson']}")
+            extra["l11r"] = l11r_summary(torch)
+            log(f"l-1-1-r: {extra['l11r']}")
 
     # roofline of the dominant kernel: the FP64 projection, bound by HBM bytes at
     # this workload's arithmetic intensity (algorithmic FLOP / algorithmic bytes = 5)
