@@ -406,8 +406,11 @@ typedef struct {
  *    the caller guarantees that the offsets and sizes lie inside data, u and
  *    out.  data, u: device FP64 inputs; out: device FP64, owned by the
  *    caller, not overlapping data or u.
- *  Allocates a device intermediate (sum of rows * k_src doubles) and the
- *  tile list for the call and synchronizes stream before returning.
+ *  The device intermediate (sum of rows * k_src doubles) and the tile list
+ *  live in a scratch buffer kept per (device, stream) and grown only when a
+ *  call needs more, so repeated calls allocate nothing; the call
+ *  synchronizes stream before returning.  Calls on one stream from several
+ *  host threads at once are not supported (they share that buffer).
  *  Errors: DMRG_E_INVALID_ARG for nblk < 0, a null pointer, out aliasing
  *  data or u, or a block with bad sizes, kind or offsets (the message names
  *  the block); DMRG_E_NOMEM / DMRG_E_HIP from the allocation, copy or
@@ -432,8 +435,9 @@ typedef struct {
  * for every item.  items: host [n], validated on the host; the items of one
  * call must not overlap in dst (they run in parallel; overlapping sums go in
  * separate calls, which run in call order).  src, dst: device FP64, owned by
- * the caller; the caller guarantees the offsets lie inside them.  Allocates
- * the item list for the call and synchronizes stream before returning.
+ * the caller; the caller guarantees the offsets lie inside them.  The item
+ * list goes to the per-(device, stream) scratch buffer of dmrg_renormalize
+ * (grown only when needed); the call synchronizes stream before returning.
  * Errors: DMRG_E_INVALID_ARG for n < 0, a null dst (or src with a copy
  * item), or an item with negative sizes or offsets, strides below cols or
  * an unknown kind (the message names the item); DMRG_E_NOMEM / DMRG_E_HIP

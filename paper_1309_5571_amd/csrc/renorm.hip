@@ -9,6 +9,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "internal.h"
@@ -105,6 +107,35 @@ static void add_tiles(std::vector<GemmTile> &out, const GemmTile &base) {
         }
 }
 
+// Device scratch of the host-side entry points below, one buffer per (device,
+// stream), grown on demand and kept: after the first calls of a DMRG run (the
+// largest step's sizes) these entry points allocate nothing.  Every call ends
+// with a stream synchronization, so a buffer is idle whenever a call starts;
+// calls on one stream from several host threads at once are not supported.
+struct StreamScratch {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+static std::mutex g_rn_mutex;
+static std::map<std::pair<int, hipStream_t>, StreamScratch> g_rn_scratch;
+
+static dmrg_status stream_scratch(hipStream_t s, size_t need, void **out) {
+    int dev = 0;
+    DMRG_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(g_rn_mutex);
+    StreamScratch &sc = g_rn_scratch[{dev, s}];
+    if (need > sc.bytes) {
+        if (sc.p) (void)hipFree(sc.p);
+        sc.p = nullptr;
+        sc.bytes = 0;
+        const size_t grow = std::max(need, need + need / 2);
+        DMRG_HIP(hipMalloc(&sc.p, grow));
+        sc.bytes = grow;
+    }
+    *out = sc.p;
+    return DMRG_OK;
+}
+
 }  // namespace dmrg
 
 // ================================================================== ABI
@@ -131,9 +162,18 @@ dmrg_status dmrg_renormalize(int32_t nblk, const dmrg_renorm_block *blocks, cons
         tmp_len += (int64_t)B.rows * B.k_src;
     }
     hipStream_t s = (hipStream_t)stream;
-    double *tmp = nullptr;
-    DMRG_HIP(hipMalloc(&tmp, std::max<int64_t>(tmp_len, 1) * sizeof(double)));
     std::vector<GemmTile> st1, st2;
+    // the tile lists (counted here) and the intermediate share one scratch buffer
+    auto ntiles = [](int64_t M, int64_t N) -> size_t {
+        return M > 0 && N > 0 ? (size_t)((M + RN_TILE - 1) / RN_TILE) * (size_t)((N + RN_TILE - 1) / RN_TILE) : 0;
+    };
+    size_t nt = 0;
+    for (int32_t b = 0; b < nblk; ++b) nt += ntiles(blocks[b].rows, blocks[b].k_src) + ntiles(blocks[b].k_dst, blocks[b].k_src);
+    const size_t tile_bytes = ws_align(std::max<size_t>(nt, 1) * sizeof(GemmTile));
+    void *scratch = nullptr;
+    DMRG_TRY(stream_scratch(s, tile_bytes + (size_t)std::max<int64_t>(tmp_len, 1) * sizeof(double), &scratch));
+    GemmTile *d_tiles = (GemmTile *)scratch;
+    double *tmp = (double *)((char *)scratch + tile_bytes);
     int64_t toff = 0;
     for (int32_t b = 0; b < nblk; ++b) {
         const dmrg_renorm_block &B = blocks[b];
@@ -164,13 +204,9 @@ dmrg_status dmrg_renormalize(int32_t nblk, const dmrg_renorm_block *blocks, cons
         c.mode = 1;
         add_tiles(st2, c);
     }
-    GemmTile *d_tiles = nullptr;
     const size_t n1 = st1.size(), n2 = st2.size();
-    hipError_t e = hipMalloc(&d_tiles, std::max<size_t>(n1 + n2, 1) * sizeof(GemmTile));
-    if (e != hipSuccess) {
-        (void)hipFree(tmp);
-        return set_error(DMRG_E_NOMEM, "hipMalloc failed: %s", hipGetErrorString(e));
-    }
+    if (n1 + n2 > nt) return set_error(DMRG_E_INVALID_ARG, "internal: tile count %zu above %zu", n1 + n2, nt);
+    hipError_t e = hipSuccess;
     std::vector<GemmTile> all(st1);
     all.insert(all.end(), st2.begin(), st2.end());
     if (!all.empty()) e = hipMemcpyAsync(d_tiles, all.data(), all.size() * sizeof(GemmTile), hipMemcpyHostToDevice, s);
@@ -182,10 +218,8 @@ dmrg_status dmrg_renormalize(int32_t nblk, const dmrg_renorm_block *blocks, cons
         hipLaunchKernelGGL(k_gemm_tiles, dim3((unsigned)n2), dim3(256), 0, s, d_tiles + n1);
         e = hipGetLastError();
     }
-    // the tile list and the intermediate are freed once the stream has used them
+    // the host tile list must outlive its copy, and the scratch is idle for the next call
     const hipError_t e2 = hipStreamSynchronize(s);
-    (void)hipFree(d_tiles);
-    (void)hipFree(tmp);
     if (e != hipSuccess) return set_error(DMRG_E_HIP, "renormalize: %s", hipGetErrorString(e));
     if (e2 != hipSuccess) return set_error(DMRG_E_HIP, "renormalize: %s", hipGetErrorString(e2));
     return DMRG_OK;
@@ -212,15 +246,15 @@ dmrg_status dmrg_place_blocks(int32_t n, const dmrg_place *items, const double *
         it[i].identity = P.identity;
     }
     hipStream_t s = (hipStream_t)stream;
-    PlaceItem *d_it = nullptr;
-    DMRG_HIP(hipMalloc(&d_it, n * sizeof(PlaceItem)));
+    void *scratch = nullptr;
+    DMRG_TRY(stream_scratch(s, (size_t)n * sizeof(PlaceItem), &scratch));
+    PlaceItem *d_it = (PlaceItem *)scratch;
     hipError_t e = hipMemcpyAsync(d_it, it.data(), n * sizeof(PlaceItem), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_place, dim3(n), dim3(256), 0, s, d_it);
         e = hipGetLastError();
     }
     const hipError_t e2 = hipStreamSynchronize(s);
-    (void)hipFree(d_it);
     if (e != hipSuccess) return set_error(DMRG_E_HIP, "place_blocks: %s", hipGetErrorString(e));
     if (e2 != hipSuccess) return set_error(DMRG_E_HIP, "place_blocks: %s", hipGetErrorString(e2));
     return DMRG_OK;

@@ -242,6 +242,26 @@ def renormalize_block(E: Block, plan, psi, m: int, side: str = "left") -> Tuple[
     return newB, float(disc[0]), int(new_dims.sum())
 
 
+class _Workspace:
+    """One caller workspace reused by the plans of consecutive steps (grown
+    when a step needs more), so a step's Davidson arrays are not allocated
+    again for every new superblock."""
+
+    def __init__(self, dev, kmax):
+        self.dev, self.kmax, self.buf = dev, kmax, None
+
+    def plan(self, problem):
+        import torch
+
+        from . import Plan
+
+        need = Plan.workspace_size(problem, "f64", self.kmax, tiles=None)
+        if self.buf is None or self.buf.numel() < need:
+            self.buf = None  # the previous plan is closed: its workspace may go
+            self.buf = torch.empty(need + need // 4, dtype=torch.uint8, device=self.dev)
+        return Plan(problem, device=self.dev, tiles=None, workspace=self.buf, ws_kmax=self.kmax)
+
+
 def _solve(plan, rng, tol, kmax, kmin, use_graph=False):
     """Lowest eigenstate of the superblock (Alg. 1, step 3).  In a tiny
     superblock the preconditioned correction can fall inside the subspace
@@ -271,8 +291,6 @@ def run_finite(nsites: int, m: int, sweeps: int = 2, J: float = 1.0, delta: floa
     from rho_L), back to the left end (right blocks from rho_R) and to the
     middle.  Returns the growth steps and the energy at the middle after each
     sweep."""
-    from . import Plan
-
     import torch
 
     if nsites < 6 or nsites % 2:
@@ -283,9 +301,10 @@ def run_finite(nsites: int, m: int, sweeps: int = 2, J: float = 1.0, delta: floa
     R: Dict[int, Block] = {1: L[1]}
     grow: List[StepResult] = []
     B = L[1]
+    ws = _Workspace(dev, max(2, min(kmax, 48)))
     while 2 * (B.nsites + 1) <= nsites:
         E = enlarge(B, J, delta)
-        plan = Plan(superblock(E, J, delta), device=dev, tiles=None)
+        plan = ws.plan(superblock(E, J, delta))
         psi, energy, its, retries = _solve(plan, rng, tol, kmax, kmin)
         B, disc, kept = renormalize_block(E, plan, psi, m)
         L[B.nsites] = R[B.nsites] = B  # mirror images of each other
@@ -295,7 +314,7 @@ def run_finite(nsites: int, m: int, sweeps: int = 2, J: float = 1.0, delta: floa
     def step(l, side):
         r = nsites - 2 - l
         EL, ER = enlarge(L[l], J, delta), enlarge(R[r], J, delta)
-        plan = Plan(superblock(EL, J, delta, ER), device=dev, tiles=None)
+        plan = ws.plan(superblock(EL, J, delta, ER))
         psi, energy, _, _ = _solve(plan, rng, tol, kmax, kmin)
         if side == "left":
             L[l + 1], _, _ = renormalize_block(EL, plan, psi, m, "left")
@@ -324,17 +343,16 @@ def run(nsites: int, m: int, J: float = 1.0, delta: float = 1.0, tol: float = 1e
     block; returns the ground-state energy of every superblock on the way."""
     import torch
 
-    from . import Plan
-
     if nsites < 4 or nsites % 2:
         raise ValueError("nsites must be even and >= 4")
     dev = torch.device("cuda", 0) if device is None else torch.device(device)
     rng = np.random.default_rng(seed)
     B = site_block(dev)
     out: List[StepResult] = []
+    ws = _Workspace(dev, max(2, min(kmax, 48)))
     while 2 * (B.nsites + 1) <= nsites:
         E = enlarge(B, J, delta)
-        plan = Plan(superblock(E, J, delta), device=dev, tiles=None)
+        plan = ws.plan(superblock(E, J, delta))
         psi, energy, its, retries = _solve(plan, rng, tol, kmax, kmin)
         B, disc, kept = renormalize_block(E, plan, psi, m)
         out.append(StepResult(2 * E.nsites, energy, disc, kept, its, retries))
