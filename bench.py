@@ -423,16 +423,37 @@ def cpu_baseline(p, x0):
         projection.project_sectors(p, x0)
         reps += 1
     t_proj = (time.perf_counter() - t0) / reps
+    # the same on one host thread (BLAS limited to one thread for the oracle's products)
+    one = None
+    try:
+        from threadpoolctl import threadpool_limits
+
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            r1 = odav.ground_state_davidson(p, x0, tol=1e-10)
+            t_dav1 = time.perf_counter() - t0
+            reps1 = 0
+            t0 = time.perf_counter()
+            while time.perf_counter() - t0 < 2.0:
+                projection.project_sectors(p, x0)
+                reps1 += 1
+            t_proj1 = (time.perf_counter() - t0) / reps1
+        one = {"value": r1.iterations / t_dav1, "unit": "iter/s", "cores": 1, "solve_s": t_dav1,
+               "projection_ms": t_proj1 * 1e3}
+    except ImportError:
+        pass
     return {
         "value": r.iterations / t_dav,
         "unit": "iter/s",
         "cores": threads,
         "kind": "oracle",
         "sample": f"one FP64 oracle Davidson solve of the m=2048 Hubbard superblock to ||r|| <= 1e-10 "
-                  f"({r.iterations} iterations, {t_dav:.2f} s) and {reps} oracle projections",
+                  f"({r.iterations} iterations, {t_dav:.2f} s) and {reps} oracle projections; the same "
+                  f"solve and 2 s of projections again on one thread (one_thread)",
         "projection_ms": t_proj * 1e3,
         "projection_gflops": flop / t_proj * 1e-9,
         "energy": r.energy,
+        "one_thread": one,
     }, r.energy
 
 
