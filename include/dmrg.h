@@ -346,7 +346,8 @@ dmrg_status dmrg_density(dmrg_plan *plan, const double *psi, double *rho_left, d
  * dmrg_density (Alg. 1, step 6: the eigenvalues of each block's density
  * matrix select the states the block keeps).  FP64, one workgroup per block:
  * cyclic Jacobi for orders up to 48 (in LDS), Householder reduction to
- * tridiagonal form and the implicit QL iteration for larger orders.
+ * tridiagonal form for larger orders, finished by divide and conquer up to
+ * order 512 and by the implicit QL iteration above.
  *  off, dim, woff: device arrays [nblk].  Block b is the row-major symmetric
  *    [dim[b]][dim[b]] matrix at a + off[b] (every entry is read).
  *  w + woff[b]: its eigenvalues in descending order (ties by index).
@@ -354,10 +355,11 @@ dmrg_status dmrg_density(dmrg_plan *plan, const double *psi, double *rho_left, d
  *    of w[woff[b] + j], with its first entry of largest magnitude positive.
  *  a is overwritten (contents unspecified on return).  a, w and u are
  *    device FP64, owned by the caller, and must not overlap.
- *  info: optional device [nblk]: Jacobi sweeps (order <= 48) or 1 + the QL
- *    iterations (larger orders), -1 if dim[b] is outside 1..2048 (the block is
- *    then not touched), -2 if the method did not converge (40 sweeps; 60 QL
- *    iterations for one eigenvalue).
+ *  info: optional device [nblk]: Jacobi sweeps (order <= 48), 1 + the QL
+ *    iterations of the leaves plus the merges (divide and conquer, orders
+ *    49..512), or 1 + the QL iterations (orders above 512); -1 if dim[b] is
+ *    outside 1..2048 (the block is then not touched), -2 if the method did
+ *    not converge (40 sweeps; 60 QL iterations for one eigenvalue).
  *  The sizes are read on the device: the caller guarantees that every
  *  block lies inside a, w and u.  Asynchronous on stream.
  *  Errors: DMRG_E_INVALID_ARG for nblk < 0, a null array, or a, w, u that

@@ -12,14 +12,19 @@
 // stops after a sweep with no rotation.
 //
 // 48 < d <= 2048: Householder reduction to tridiagonal form T = Q^T A Q, the
-// matrix Q formed explicitly, then the implicit QL iteration with Wilkinson's
-// shift on T (the tql2 procedure of Bowdler, Martin, Reinsch and Wilkinson),
-// whose plane rotations are applied to the columns of Q.  The reduction and
-// the formation of Q are whole-workgroup passes over the block (in global
-// memory, where it stays cache-resident); the QL recurrence is sequential and
-// runs on one lane, writing each sweep's rotations to LDS, which the whole
-// workgroup then applies to the rows of Q (Q is stored column-major, so a
-// rotation of columns i, i+1 is a coalesced read of two columns).
+// matrix Q formed explicitly, then T's eigenpairs.  The reduction and the
+// formation of Q are whole-workgroup passes over the block (in global memory,
+// where it stays cache-resident).  Orders up to 512: Cuppen's divide and
+// conquer on T (leaves of at most 16 by implicit QL, one wavefront each;
+// merges by deflation, the secular equation one thread per root and Gu and
+// Eisenstat's recomputed weights), then the eigenvectors of the block as Q
+// times those of T.  Larger orders: the implicit QL iteration with
+// Wilkinson's shift on T (the tql2 procedure of Bowdler, Martin, Reinsch and
+// Wilkinson), whose plane rotations are applied to the columns of Q: the QL
+// recurrence is sequential and runs on one lane, writing each sweep's
+// rotations to LDS, which the whole workgroup then applies to the rows of Q
+// (Q is stored column-major, so a rotation of columns i, i+1 is a coalesced
+// read of two columns).
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -226,18 +231,490 @@ constexpr int TRI_UB = 16;  // rows of a column read per batch of loads (Househo
 constexpr int QL_B = 8;     // rotations applied per batch of loads (QL; the next batch is fetched ahead)
 constexpr int Q_REG = 8;    // column entries per lane kept in registers (Q formation, L <= 512)
 
+// ------------------------------------------------------------------ divide and conquer
+// The symmetric tridiagonal eigenproblem of orders up to DC_MAX by Cuppen's
+// divide and conquer (eigenvectors by Gu and Eisenstat's recomputed weights):
+// T is torn at the boundaries of a bisection tree, T = blockdiag(T_i) + sum
+// |e_b| v_b v_b^T (v_b = e_{b-1} + sign(e_b) e_b, the torn diagonals reduced by
+// |e_b|); the leaves (at most DC_LEAF) are solved by implicit QL, one wavefront
+// each; then the tree is merged bottom-up.  A merge of two solved halves is the
+// rank-one eigenproblem D + rho z z^T (z: the last row of the left half's
+// eigenvectors and the first row of the right half's): deflation of
+// negligible weights and of nearly equal poles (a plane rotation), the roots
+// of the secular equation 1 + rho sum z_i^2 / (d_i - lambda) = 0 from the
+// nearer pole (one thread per root: a two-pole rational model, bracketed), the weights recomputed from the
+// roots, and the rows of the merged block of eigenvectors multiplied by the
+// merge's eigenvector matrix (one wavefront per row, in place).
+constexpr int DC_MAX = 512;
+constexpr int DC_LEAF = 16;
+constexpr int DC_ITMAX = 100;  // root-finder steps per root (they end at the resolution, typically after 3-8)
+
+// LDS writes of a wavefront's lanes are visible to its other lanes after it
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// 1/x: the hardware reciprocal refined by one Newton step
+__device__ __forceinline__ double rcpd(double x) {
+    const double r = __builtin_amdgcn_rcp(x);
+    return fma(fma(-x, r, 1.0), r, r);
+}
+constexpr int DC_NLEAF = 32;    // most leaves: orders <= DC_MAX need at most 2^5 of at most DC_LEAF
+constexpr int DC_STAGE = 224;   // LDS staging of a row per wavefront (the pool's last 16 x 224)
+static_assert((DC_MAX + DC_NLEAF - 1) / DC_NLEAF <= DC_LEAF, "leaf count");
+// the pool (5 EIG_MAX_DIM doubles) holds the leaves, then the scratch of a merge
+static_assert(DC_NLEAF * DC_LEAF * (DC_LEAF + 1) <= 5 * EIG_MAX_DIM, "leaf scratch");
+static_assert(13 * DC_MAX + 16 * DC_STAGE <= 5 * EIG_MAX_DIM, "merge scratch");
+
+// Implicit QL (as the large-order path) on a leaf of order m <= DC_LEAF on one
+// lane: d (LDS, length m) becomes its eigenvalues, e (length m, e[m-1] = 0) is
+// destroyed, Zl (row-major m x m, LDS) its eigenvectors.  Returns the
+// iteration count, or -1 if an eigenvalue needed more than QL_MAXIT.
+__device__ int ql_leaf(int m, double *d, double *e, double *Zl) {
+    for (int r = 0; r < m; ++r)
+        for (int c = 0; c < m; ++c) Zl[r * DC_LEAF + c] = r == c ? 1.0 : 0.0;
+    double anorm = 0.0;
+    for (int i = 0; i < m; ++i) anorm = fmax(anorm, fabs(d[i]) + fabs(e[i]) + (i ? fabs(e[i - 1]) : 0.0));
+    const double tol = anorm * 0x1p-53;
+    int its = 0;
+    for (int l = 0; l < m; ++l) {
+        for (int it = 0;; ++it) {
+            int mm = l;
+            while (mm < m - 1 && fabs(e[mm]) > tol) ++mm;
+            if (mm == l) break;
+            if (it >= QL_MAXIT) return -1;
+            ++its;
+            double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+            double r = hyp(g, 1.0);
+            g = d[mm] - d[l] + e[l] / (g + copysign(r, g));
+            double s = 1.0, c = 1.0, p = 0.0;
+            bool early = false;
+            for (int i = mm - 1; i >= l; --i) {
+                const double f = s * e[i], bb = c * e[i];
+                r = hyp(f, g);
+                e[i + 1] = r;
+                if (r == 0.0) {
+                    d[i + 1] -= p;
+                    e[mm] = 0.0;
+                    early = true;
+                    break;
+                }
+                s = f / r;
+                c = g / r;
+                g = d[i + 1] - p;
+                r = (d[i] - g) * s + 2.0 * c * bb;
+                p = s * r;
+                d[i + 1] = g + p;
+                g = c * r - bb;
+                for (int row = 0; row < m; ++row) {
+                    double *zr = Zl + row * DC_LEAF;
+                    const double h = zr[i + 1];
+                    zr[i + 1] = s * zr[i] + c * h;
+                    zr[i] = c * zr[i] - s * h;
+                }
+            }
+            if (!early) {
+                d[l] -= p;
+                e[l] = g;
+                e[mm] = 0.0;
+            }
+        }
+    }
+    return its;
+}
+
+// Scratch of one merge (LDS, carved from the pool): doubles of length DC_MAX
+struct DcScratch {
+    double *zz, *ds, *rc, *rs, *delta, *zeta, *tau, *zhat, *invn, *lamn;
+    double *stage;  // [TRI_WAVES][DC_STAGE]: one row's weighted entries per wavefront
+    int *perm, *defl, *rj, *ri, *nd, *tmp, *org;
+};
+
+// Merge of the solved halves [lo, mid) and [mid, hi) coupled by rho.  Zt:
+// column-major n x n eigenvectors of T (rows and columns of the block only).
+__device__ void dc_merge(int n, int lo, int mid, int hi, double rho, double *sd, double *Zt, const DcScratch &S,
+                         double *red, int *ctl) {
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const size_t N = (size_t)n;
+    const int m = hi - lo;
+    // z: row mid - 1 of the left half's eigenvectors, row mid of the right half's
+    double part = 0.0;
+    for (int c = tid; c < m; c += TRI_TPB) {
+        const int col = lo + c;
+        double v = col < mid ? Zt[col * N + (mid - 1)] : Zt[col * N + mid];
+        if (col >= mid && rho < 0.0) v = -v;
+        S.zz[c] = v;
+        part += v * v;
+    }
+    double unused;
+    const double nz2 = block_sum_lead(part, 0.0, red, &unused);
+    const double rh = fabs(rho) * nz2;  // rho of the normalized z
+    if (!(rh > 0.0)) return;            // no coupling: the halves are already solved
+    const double inz = 1.0 / sqrt(nz2);
+    // ascending order of the poles (ties by index)
+    for (int c = tid; c < m; c += TRI_TPB) {
+        const double x = sd[lo + c];
+        int rk = 0;
+        for (int j = 0; j < m; ++j) {
+            const double y = sd[lo + j];
+            rk += (y < x) || (y == x && j < c);
+        }
+        S.perm[rk] = c;
+    }
+    __syncthreads();
+    for (int t = tid; t < m; t += TRI_TPB) {
+        S.ds[t] = sd[lo + S.perm[t]];
+        S.zeta[t] = S.zz[S.perm[t]] * inz;  // (zeta used as the sorted z during deflation)
+    }
+    __syncthreads();
+    // deflation (one thread, in pole order): a negligible weight leaves its pole;
+    // two poles closer than the resolution are rotated so that one weight vanishes
+    if (tid == 0) {
+        double *zs = S.zeta, *ds = S.ds;
+        const double tol = 8.0 * 0x1p-53 * fmax(fmax(fabs(ds[0]), fabs(ds[m - 1])), rh);
+        int nrot = 0, prev = -1, k = 0;
+        for (int t = 0; t < m; ++t) {
+            S.defl[t] = 0;
+            if (rh * fabs(zs[t]) <= tol) {
+                S.defl[t] = 1;
+                continue;
+            }
+            if (prev >= 0) {
+                const double tt = hyp(zs[prev], zs[t]);
+                const double c = zs[t] / tt, sn = -zs[prev] / tt;
+                if (fabs((ds[t] - ds[prev]) * c * sn) <= tol) {
+                    zs[t] = tt;
+                    zs[prev] = 0.0;
+                    const double dp = ds[prev] * c * c + ds[t] * sn * sn;
+                    const double dt = ds[prev] * sn * sn + ds[t] * c * c;
+                    ds[prev] = dp;
+                    ds[t] = dt;
+                    S.rj[nrot] = prev;
+                    S.ri[nrot] = t;
+                    S.rc[nrot] = c;
+                    S.rs[nrot] = sn;
+                    ++nrot;
+                    S.defl[prev] = 1;
+                }
+            }
+            prev = t;
+        }
+        for (int t = 0; t < m; ++t)
+            if (!S.defl[t]) S.tmp[k++] = t;
+        ctl[0] = k;
+        ctl[1] = nrot;
+    }
+    __syncthreads();
+    const int k = ctl[0], nrot = ctl[1];
+    // the non-deflated poles in ascending order (a rotation may move one by a rounding)
+    for (int j = tid; j < k; j += TRI_TPB) {
+        const double x = S.ds[S.tmp[j]];
+        int rk = 0;
+        for (int i = 0; i < k; ++i) {
+            const double y = S.ds[S.tmp[i]];
+            rk += (y < x) || (y == x && i < j);
+        }
+        S.nd[rk] = S.tmp[j];
+    }
+    __syncthreads();
+    for (int j = tid; j < k; j += TRI_TPB) {
+        S.delta[j] = S.ds[S.nd[j]];
+        S.zz[j] = S.zeta[S.nd[j]];  // zz: the weights of the non-deflated poles
+    }
+    __syncthreads();
+    // roots of the secular equation: root j lies between delta[j] and delta[j+1]
+    // (the last one below delta[k-1] + rh sum z^2), in coordinates centred on
+    // the nearer pole.  Each step fits the sums over the poles below and above
+    // the gap with one pole each (value and slope at the iterate) and moves to
+    // the root of that model; a step that leaves the bracket bisects instead.
+    const double *dl = S.delta, *zw = S.zz;
+    for (int j = tid; j < k; j += TRI_TPB) {
+        double zsum = 0.0;
+        for (int i = 0; i < k; ++i) zsum += zw[i] * zw[i];
+        const bool last = j + 1 == k;
+        const double lo_d = dl[j], hi_d = last ? dl[j] + rh * zsum : dl[j + 1];
+        const double half = 0.5 * (hi_d - lo_d);
+        double f = 0.0;
+        for (int i = 0; i < k; ++i) f += zw[i] * zw[i] * rcpd(dl[i] - (lo_d + half));
+        f = 1.0 + rh * f;
+        int o;
+        double a, bnd;
+        if (last || f >= 0.0) {
+            o = j;
+            a = 0.0;
+            bnd = last ? hi_d - lo_d : half;
+        } else {
+            o = j + 1;
+            a = -half;
+            bnd = 0.0;
+        }
+        const double dorg = dl[o];
+        const double dj = dl[j] - dorg, dj1 = last ? 0.0 : dl[j + 1] - dorg;
+        double x = 0.5 * (a + bnd);
+        for (int it = 0; it < DC_ITMAX; ++it) {
+            double psi = 0.0, dpsi = 0.0, phi = 0.0, dphi = 0.0;
+            for (int i = 0; i < k; ++i) {
+                const double r = rcpd((dl[i] - dorg) - x);
+                const double t = zw[i] * zw[i] * r;
+                const bool below = i <= j;
+                psi += below ? t : 0.0;
+                dpsi += below ? t * r : 0.0;
+                phi += below ? 0.0 : t;
+                dphi += below ? 0.0 : t * r;
+            }
+            const double fx = 1.0 + rh * (psi + phi);
+            if (fx > 0.0)
+                bnd = x;
+            else
+                a = x;
+            const double err = 8.0 * 0x1p-53 * (1.0 + rh * (fabs(psi) + fabs(phi)) + fabs(x) * rh * (dpsi + dphi));
+            if (fabs(fx) <= err || bnd - a <= 2.0 * 0x1p-53 * fmax(fabs(a), fabs(bnd))) break;
+            const double u = dj - x, qq = dpsi * u * u, pp = psi - dpsi * u;
+            double xn;
+            if (!last) {
+                const double v = dj1 - x, ss = dphi * v * v, rr = phi - dphi * v;
+                const double C = 1.0 + rh * (pp + rr), A1 = rh * qq, A2 = rh * ss;
+                // C (u - eta)(v - eta) + A1 (v - eta) + A2 (u - eta) = 0, root inside the gap
+                const double qb = -(C * (u + v) + A1 + A2), qc = C * u * v + A1 * v + A2 * u;
+                double eta;
+                if (C == 0.0) {
+                    eta = -qc / qb;
+                } else {
+                    const double sq = sqrt(fmax(qb * qb - 4.0 * C * qc, 0.0));
+                    const double q1 = -0.5 * (qb + copysign(sq, qb));
+                    const double e1 = q1 / C, e2 = q1 != 0.0 ? qc / q1 : e1;
+                    eta = (dj < x + e1 && x + e1 < dj1) ? e1 : e2;
+                }
+                xn = x + eta;
+            } else {
+                const double C = 1.0 + rh * (pp + phi);
+                xn = C != 0.0 ? dj + rh * qq / C : bnd;
+            }
+            x = (a < xn && xn < bnd) ? xn : 0.5 * (a + bnd);
+        }
+        S.org[j] = o;
+        S.tau[j] = x;
+    }
+    __syncthreads();
+    // weights recomputed from the roots (their signs kept), then the norms of
+    // the eigenvectors zhat_i / (delta_i - lambda_j)
+    for (int i = tid; i < k; i += TRI_TPB) {
+        double prod = ((dl[S.org[i]] - dl[i]) + S.tau[i]) / rh;
+        for (int j = 0; j < k; ++j)
+            if (j != i) prod *= ((dl[S.org[j]] - dl[i]) + S.tau[j]) * rcpd(dl[j] - dl[i]);
+        S.zhat[i] = copysign(sqrt(fmax(prod, 0.0)), zw[i]);
+    }
+    __syncthreads();
+    for (int j = tid; j < k; j += TRI_TPB) {
+        const double dj = dl[S.org[j]], tj = S.tau[j];
+        double q = 0.0;
+        for (int i = 0; i < k; ++i) {
+            const double x = S.zhat[i] * rcpd((dl[i] - dj) - tj);
+            q += x * x;
+        }
+        S.invn[j] = 1.0 / sqrt(q);
+        S.lamn[j] = dj + tj;
+    }
+    __syncthreads();
+    // the deflation rotations on the columns of the block (in pole order)
+    for (int q = 0; q < nrot; ++q) {
+        const size_t cj = (size_t)(lo + S.perm[S.rj[q]]) * N, ci = (size_t)(lo + S.perm[S.ri[q]]) * N;
+        const double c = S.rc[q], sn = S.rs[q];
+        for (int r = lo + tid; r < hi; r += TRI_TPB) {
+            const double yj = Zt[cj + r], yi = Zt[ci + r];
+            Zt[cj + r] = c * yj + sn * yi;
+            Zt[ci + r] = c * yi - sn * yj;
+        }
+        __syncthreads();
+    }
+    // rows of the block times the merge's eigenvectors: slot t of the block takes
+    // pole t (in pole order); a deflated slot keeps its column, the slot of the
+    // non-deflated pole nd[j] gets root j's eigenvector.  One wavefront per row:
+    // the row's weighted entries y_i zhat_i are staged in LDS and read by every
+    // lane, each lane accumulating the outputs of its roots j = lane + 64 q.
+    constexpr int NQ = DC_MAX / 64;
+    double djr[NQ], tjr[NQ];  // origin pole and offset of this lane's roots
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int j = lane + 64 * q;
+        djr[q] = j < k ? dl[S.org[j]] : 0.0;
+        tjr[q] = j < k ? S.tau[j] : -1.0;  // (past k: a finite, unused difference)
+    }
+    double *st = S.stage + wv * DC_STAGE;
+    for (int r = lo + wv; r < hi; r += TRI_WAVES) {
+        double yd[NQ], acc[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int t = lane + 64 * q;
+            acc[q] = 0.0;
+            yd[q] = (64 * q < m && t < m) ? Zt[(size_t)(lo + S.perm[t]) * N + r] : 0.0;
+        }
+        for (int c0 = 0; c0 < k; c0 += DC_STAGE) {
+            const int cnt = min(DC_STAGE, k - c0);
+            for (int e = lane; e < cnt; e += 64) {
+                const int i = c0 + e;
+                st[e] = Zt[(size_t)(lo + S.perm[S.nd[i]]) * N + r] * S.zhat[i];
+            }
+            wave_sync_lds();
+            for (int e = 0; e < cnt; ++e) {
+                const double yv = st[e], di = dl[c0 + e];
+#pragma unroll
+                for (int q = 0; q < NQ; ++q)
+                    if (64 * q < k) acc[q] += yv * rcpd((di - djr[q]) - tjr[q]);  // uniform skip
+            }
+            wave_sync_lds();  // the next chunk rewrites the staging slice
+        }
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int i = lane + 64 * q;
+            if (64 * q < m) {
+                if (i < k) Zt[(size_t)(lo + S.nd[i]) * N + r] = acc[q] * S.invn[i];
+                if (i < m && S.defl[i]) Zt[(size_t)(lo + i) * N + r] = yd[q];
+            }
+        }
+    }
+    __syncthreads();
+    for (int t = tid; t < m; t += TRI_TPB)
+        if (S.defl[t]) sd[lo + t] = S.ds[t];
+    for (int j = tid; j < k; j += TRI_TPB) sd[lo + S.nd[j]] = S.lamn[j];
+    __syncthreads();
+}
+
+// The whole tridiagonal solve and the back-transformation.  Zt: n x n global
+// scratch (u); Q: the Householder product (a, column-major), replaced by the
+// eigenvectors of the block.  ctl[2]: set to 1 if a leaf did not converge;
+// ctl[3]: leaf QL iterations + merges.
+__device__ void dc_solve(int n, double *sd, double *se, double *pool, int *ipool, double *Zt, double *Q,
+                         double *red, int *ctl) {
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const size_t N = (size_t)n;
+    int T = 0;
+    while (((n + (1 << T) - 1) >> T) > DC_LEAF) ++T;
+    const int nleaf = 1 << T;
+    auto bnd = [&](int t, int i) { return (n * i) >> t; };
+    for (int c = wv; c < n; c += TRI_WAVES)
+        for (int r = lane; r < n; r += 64) Zt[c * N + r] = 0.0;
+    // tear at the leaf boundaries (leaves hold at least 8 rows: no index is shared)
+    if (tid >= 1 && tid < nleaf) {
+        const int b0 = bnd(T, tid);
+        const double r = fabs(se[b0 - 1]);
+        sd[b0 - 1] -= r;
+        sd[b0] -= r;
+    }
+    if (tid == 0) ctl[3] = 0;
+    __syncthreads();
+    // leaves: one wavefront each (its lane 0), eigenvectors in LDS, then into Zt
+    double *leafZ = pool;                              // [nleaf][DC_LEAF][DC_LEAF]
+    double *leafE = pool + DC_NLEAF * DC_LEAF * DC_LEAF;  // [nleaf][DC_LEAF]
+    for (int lf = wv; lf < nleaf; lf += TRI_WAVES) {
+        if (lane == 0) {
+            const int lo = bnd(T, lf), m = bnd(T, lf + 1) - lo;
+            double *el = leafE + lf * DC_LEAF;
+            for (int i = 0; i < m; ++i) el[i] = i + 1 < m ? se[lo + i] : 0.0;
+            const int it = ql_leaf(m, sd + lo, el, leafZ + lf * DC_LEAF * DC_LEAF);
+            if (it < 0) ctl[2] = 1;
+            else atomicAdd(&ctl[3], it);
+        }
+    }
+    __syncthreads();
+    for (int lf = wv; lf < nleaf; lf += TRI_WAVES) {
+        const int lo = bnd(T, lf), m = bnd(T, lf + 1) - lo;
+        const double *Zl = leafZ + lf * DC_LEAF * DC_LEAF;
+        for (int e = lane; e < m * m; e += 64) {
+            const int r = e / m, c = e % m;
+            Zt[(size_t)(lo + c) * N + lo + r] = Zl[r * DC_LEAF + c];
+        }
+    }
+    __syncthreads();
+    // merges, deepest level first
+    DcScratch S;
+    S.zz = pool;
+    S.ds = pool + DC_MAX;
+    S.rc = pool + 2 * DC_MAX;
+    S.rs = pool + 3 * DC_MAX;
+    S.delta = pool + 4 * DC_MAX;
+    S.zeta = pool + 5 * DC_MAX;
+    S.tau = pool + 6 * DC_MAX;
+    S.zhat = pool + 7 * DC_MAX;
+    S.invn = pool + 8 * DC_MAX;
+    S.lamn = pool + 9 * DC_MAX;
+    int *ip = (int *)(pool + 10 * DC_MAX);
+    S.perm = ip;
+    S.defl = ip + DC_MAX;
+    S.rj = ip + 2 * DC_MAX;
+    S.ri = ip + 3 * DC_MAX;
+    S.nd = ip + 4 * DC_MAX;
+    S.tmp = ip + 5 * DC_MAX;
+    S.org = ipool;
+    S.stage = pool + 13 * DC_MAX;
+    for (int t = T - 1; t >= 0; --t)
+        for (int i = 0; i < (1 << t); ++i) {
+            const int lo = bnd(t, i), mid = bnd(t + 1, 2 * i + 1), hi = bnd(t, i + 1);
+            if (lo < mid && mid < hi) dc_merge(n, lo, mid, hi, se[mid - 1], sd, Zt, S, red, ctl);
+            if (tid == 0) ++ctl[3];
+        }
+    __syncthreads();
+    // eigenvectors of the block: E = Q Zt, column j of E over column j of Zt (it
+    // is read into registers first), two columns per wavefront at a time
+    constexpr int NQ = DC_MAX / 64;
+    for (int j0 = 2 * wv; j0 < n; j0 += 2 * TRI_WAVES) {
+        double zt[2][NQ], acc[2][NQ];
+#pragma unroll
+        for (int e = 0; e < 2; ++e)
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const int r = lane + 64 * q;
+                zt[e][q] = r < n ? Zt[(size_t)min(j0 + e, n - 1) * N + r] : 0.0;
+                acc[e][q] = 0.0;
+            }
+#pragma unroll
+        for (int cq = 0; cq < NQ; ++cq) {
+            if (64 * cq >= n) break;
+            const int cn = min(64, n - 64 * cq);
+            for (int cl = 0; cl < cn; ++cl) {
+                const int c = 64 * cq + cl;
+                const double z0 = readlane_f64(zt[0][cq], cl), z1 = readlane_f64(zt[1][cq], cl);
+                const double *qc = Q + (size_t)c * N;
+#pragma unroll
+                for (int q = 0; q < NQ; ++q)
+                    if (64 * q < n) {  // uniform
+                        const int r = lane + 64 * q;
+                        const double x = r < n ? qc[r] : 0.0;
+                        acc[0][q] += x * z0;
+                        acc[1][q] += x * z1;
+                    }
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < 2; ++e)
+            if (j0 + e < n)
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    const int r = lane + 64 * q;
+                    if (r < n) Zt[(size_t)(j0 + e) * N + r] = acc[e][q];
+                }
+    }
+    __syncthreads();
+    for (int c = wv; c < n; c += TRI_WAVES)
+        for (int r = lane; r < n; r += 64) Q[c * N + r] = Zt[c * N + r];
+    __syncthreads();
+}
+
 __global__ __launch_bounds__(TRI_TPB) void k_eigh_tri(int nblk, const int64_t *__restrict__ off,
                                                       const int32_t *__restrict__ dim, const int64_t *__restrict__ woff,
                                                       double *__restrict__ a, double *__restrict__ w,
                                                       double *__restrict__ u, int32_t *__restrict__ info) {
     __shared__ double sd[EIG_MAX_DIM];  // diagonal of T, then the eigenvalues
     __shared__ double se[EIG_MAX_DIM];  // se[i] couples i and i + 1
-    __shared__ double sq[EIG_MAX_DIM];  // Householder factors; QL: cosines (second buffer)
-    __shared__ double sx[EIG_MAX_DIM];  // Householder vector; QL: cosines (first buffer)
-    __shared__ double sy[EIG_MAX_DIM];  // p, then w = p - K v; QL: sines (first buffer)
-    __shared__ double sz[EIG_MAX_DIM];  // QL: sines (second buffer)
+    __shared__ double pool[5 * EIG_MAX_DIM];
+    double *sq = pool;                     // Householder factors; QL: cosines (second buffer)
+    double *sx = pool + EIG_MAX_DIM;       // Householder vector; QL: cosines (first buffer)
+    double *sy = pool + 2 * EIG_MAX_DIM;   // p, then w = p - K v; QL: sines (first buffer)
+    double *sz = pool + 3 * EIG_MAX_DIM;   // QL: sines (second buffer)
+    double *spart = pool + 4 * EIG_MAX_DIM;  // row-group partial sums of p
+    // (after Q is formed, the divide-and-conquer path uses the whole pool)
     __shared__ int srank[EIG_MAX_DIM];
-    __shared__ double spart[EIG_MAX_DIM];  // row-group partial sums of p
     __shared__ double red[TRI_WAVES + 1];
     __shared__ int ctl[4];
     const int b = blockIdx.x;
@@ -400,11 +877,20 @@ __global__ __launch_bounds__(TRI_TPB) void k_eigh_tri(int nblk, const int64_t *_
         __syncthreads();
     }
 
+    int its = 0, bad = 0;
+    if (d <= DC_MAX) {
+        // divide and conquer on T; its eigenvectors go to u (free now that Q is
+        // formed), then the eigenvectors of the block, Q times them, back to a
+        if (tid == 0) ctl[2] = 0;
+        dc_solve(d, sd, se, pool, (int *)srank, A, Z, red, ctl);
+        its = ctl[3];
+        bad = ctl[2];
+    } else {
     // ---- implicit QL on T (sd, se).  Lane 0 of wave 0 runs the recurrence and
     // leaves each iteration's rotations (indices lo..hi) in one of two LDS
     // buffers; in the same interval the other waves apply the previous
     // iteration's rotations to the rows of Z.
-    int l = 0, it_l = 0, its = 0, bad = 0;
+    int l = 0, it_l = 0;
     double tol = 0.0;
     // one QL iteration into buffer `buf` (lane 0 of wave 0 only); ctl[2 buf] = lo,
     // ctl[2 buf + 1] = hi, lo = -1 when every eigenvalue has converged
@@ -554,6 +1040,7 @@ __global__ __launch_bounds__(TRI_TPB) void k_eigh_tri(int nblk, const int64_t *_
         const double inv = 1.0 / scale;  // a power of two: exact
         for (int i = 0; i < d; ++i) sd[i] *= inv;
     }
+    }  // QL
     __syncthreads();
     // ---- descending order (ties by index), first entry of largest magnitude positive
     for (int i = tid; i < d; i += TRI_TPB) {
