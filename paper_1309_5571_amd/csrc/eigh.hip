@@ -230,6 +230,7 @@ __device__ __forceinline__ double hyp(double x, double y) {
 constexpr int TRI_UB = 16;  // rows of a column read per batch of loads (Householder step)
 constexpr int QL_B = 8;     // rotations applied per batch of loads (QL; the next batch is fetched ahead)
 constexpr int Q_REG = 8;    // column entries per lane kept in registers (Q formation, L <= 512)
+constexpr int QB = 16;      // factors per block of the Q formation (their vectors: QB x 512 doubles of LDS)
 
 // ------------------------------------------------------------------ divide and conquer
 // The symmetric tridiagonal eigenproblem of orders up to DC_MAX by Cuppen's
@@ -266,6 +267,7 @@ static_assert((DC_MAX + DC_NLEAF - 1) / DC_NLEAF <= DC_LEAF, "leaf count");
 // the pool (5 EIG_MAX_DIM doubles) holds the leaves, then the scratch of a merge
 static_assert(DC_NLEAF * DC_LEAF * (DC_LEAF + 1) <= 5 * EIG_MAX_DIM, "leaf scratch");
 static_assert(13 * DC_MAX + 16 * DC_STAGE <= 5 * EIG_MAX_DIM, "merge scratch");
+static_assert(QB * 64 * Q_REG <= 4 * EIG_MAX_DIM, "Q formation: factor vectors in the pool past the factors' t");
 
 // Implicit QL (as the large-order path) on a leaf of order m <= DC_LEAF on one
 // lane: d (LDS, length m) becomes its eigenvalues, e (length m, e[m-1] = 0) is
@@ -823,58 +825,119 @@ __global__ __launch_bounds__(TRI_TPB) void k_eigh_tri(int nblk, const int64_t *_
         se[d - 1] = 0.0;
     }
     // ---- Q = H_0 H_1 ... H_{d-3}, accumulated from the last factor; H_k Q only
-    // changes the trailing block from index k + 1.  One wave per column: y_c =
-    // v^T Q(:, c), then Q(:, c) -= t y_c v, the column kept in registers between.
+    // changes the trailing block from index k + 1: y_c = v^T Q(:, c), then
+    // Q(:, c) -= t y_c v.
     for (int c = wv; c < d; c += TRI_WAVES)
         for (int r = lane; r < d; r += 64) Z[c * D + r] = r == c ? 1.0 : 0.0;
     __syncthreads();
-    for (int k = d - 3; k >= 0; --k) {
-        const double t = sq[k];
-        if (t == 0.0) continue;
-        const int L = d - k - 1;
-        for (int j = tid; j < L; j += TRI_TPB) sx[j] = j ? A[k * D + k + 1 + j] : 1.0;
-        __syncthreads();
-        if (L <= 64 * Q_REG) {
-            // four columns per wave at a time: all their loads in flight together
-            for (int c0 = 4 * wv; c0 < L; c0 += 4 * TRI_WAVES) {
+    if (d - 1 <= 64 * Q_REG) {
+        // QB factors at a time: their vectors staged in LDS (rows from the
+        // block's first touched index r0 = klo + 1, zero above each factor's
+        // own start), then every wave applies all of them, last first, to four
+        // columns at a time held in registers: one load and one store of each
+        // column per block instead of per factor.  A factor meets zeros in the
+        // rows and columns it does not reach, which leaves them unchanged.
+        double *sv = sx;  // [QB][L0] (the pool past the factors' t)
+        for (int khi = d - 3; khi >= 0; khi -= QB) {
+            const int klo = max(0, khi - QB + 1), r0 = klo + 1, L0 = d - r0;
+            for (int i = tid; i < (khi - klo + 1) * L0; i += TRI_TPB) {
+                const int kk = i / L0, j = i - kk * L0, k = klo + kk, r = r0 + j;
+                sv[i] = r == k + 1 ? 1.0 : (r > k + 1 ? A[k * D + r] : 0.0);
+            }
+            __syncthreads();
+            for (int c0 = 4 * wv; c0 < L0; c0 += 4 * TRI_WAVES) {
                 double cv[4][Q_REG];
-                double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    const double *col = Z + (k + 1 + min(c0 + e, L - 1)) * D + k + 1;
+                    const double *col = Z + (r0 + min(c0 + e, L0 - 1)) * D + r0;
 #pragma unroll
-                    for (int q = 0; q < Q_REG; ++q) cv[e][q] = col[min(lane + 64 * q, L - 1)];
+                    for (int q = 0; q < Q_REG; ++q) cv[e][q] = col[min(lane + 64 * q, L0 - 1)];
                 }
+                for (int k = khi; k >= klo; --k) {
+                    const double t = sq[k];
+                    if (t == 0.0) continue;
+                    const double *v = sv + (k - klo) * L0;
+                    double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int e = 0; e < 4; ++e)
-#pragma unroll
-                    for (int q = 0; q < Q_REG; ++q) {
-                        const int r = lane + 64 * q;
-                        if (r < L) acc[e] += sx[r] * cv[e][q];
-                    }
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const double ty = t * group_sum<64>(acc[e]);
-                    if (c0 + e < L) {
-                        double *col = Z + (k + 1 + c0 + e) * D + k + 1;
+                    for (int e = 0; e < 4; ++e)
 #pragma unroll
                         for (int q = 0; q < Q_REG; ++q) {
                             const int r = lane + 64 * q;
-                            if (r < L) col[r] = cv[e][q] - ty * sx[r];
+                            if (r < L0) acc[e] += v[r] * cv[e][q];
+                        }
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const double ty = t * group_sum<64>(acc[e]);
+#pragma unroll
+                        for (int q = 0; q < Q_REG; ++q) {
+                            const int r = lane + 64 * q;
+                            if (r < L0) cv[e][q] -= ty * v[r];
                         }
                     }
                 }
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (c0 + e < L0) {
+                        double *col = Z + (r0 + c0 + e) * D + r0;
+#pragma unroll
+                        for (int q = 0; q < Q_REG; ++q) {
+                            const int r = lane + 64 * q;
+                            if (r < L0) col[r] = cv[e][q];
+                        }
+                    }
             }
-        } else {
-            for (int c = wv; c < L; c += TRI_WAVES) {
-                double *col = Z + (k + 1 + c) * D + k + 1;
-                double acc = 0.0;
-                for (int r = lane; r < L; r += 64) acc += sx[r] * col[r];
-                const double ty = t * group_sum<64>(acc);
-                for (int r = lane; r < L; r += 64) col[r] -= ty * sx[r];
-            }
+            __syncthreads();  // the next block reads these columns and rewrites sv
         }
-        __syncthreads();
+    } else {
+        // one factor at a time, one wave per column (or four columns)
+        for (int k = d - 3; k >= 0; --k) {
+            const double t = sq[k];
+            if (t == 0.0) continue;
+            const int L = d - k - 1;
+            for (int j = tid; j < L; j += TRI_TPB) sx[j] = j ? A[k * D + k + 1 + j] : 1.0;
+            __syncthreads();
+            if (L <= 64 * Q_REG) {
+                // four columns per wave at a time: all their loads in flight together
+                for (int c0 = 4 * wv; c0 < L; c0 += 4 * TRI_WAVES) {
+                    double cv[4][Q_REG];
+                    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const double *col = Z + (k + 1 + min(c0 + e, L - 1)) * D + k + 1;
+#pragma unroll
+                        for (int q = 0; q < Q_REG; ++q) cv[e][q] = col[min(lane + 64 * q, L - 1)];
+                    }
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+#pragma unroll
+                        for (int q = 0; q < Q_REG; ++q) {
+                            const int r = lane + 64 * q;
+                            if (r < L) acc[e] += sx[r] * cv[e][q];
+                        }
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const double ty = t * group_sum<64>(acc[e]);
+                        if (c0 + e < L) {
+                            double *col = Z + (k + 1 + c0 + e) * D + k + 1;
+#pragma unroll
+                            for (int q = 0; q < Q_REG; ++q) {
+                                const int r = lane + 64 * q;
+                                if (r < L) col[r] = cv[e][q] - ty * sx[r];
+                            }
+                        }
+                    }
+                }
+            } else {
+                for (int c = wv; c < L; c += TRI_WAVES) {
+                    double *col = Z + (k + 1 + c) * D + k + 1;
+                    double acc = 0.0;
+                    for (int r = lane; r < L; r += 64) acc += sx[r] * col[r];
+                    const double ty = t * group_sum<64>(acc);
+                    for (int r = lane; r < L; r += 64) col[r] -= ty * sx[r];
+                }
+            }
+            __syncthreads();
+        }
     }
 
     int its = 0, bad = 0;
