@@ -562,8 +562,10 @@ __device__ void dc_merge(int n, int lo, int mid, int hi, double rho, double *sd,
             for (int e = 0; e < cnt; ++e) {
                 const double yv = st[e], di = dl[c0 + e];
 #pragma unroll
-                for (int q = 0; q < NQ; ++q)
-                    if (64 * q < k) acc[q] += yv * rcpd((di - djr[q]) - tjr[q]);  // uniform skip
+                for (int q = 0; q < NQ; ++q) {
+                    if (64 * q >= k) break;  // uniform: the root slots past k are not computed
+                    acc[q] += yv * rcpd((di - djr[q]) - tjr[q]);
+                }
             }
             wave_sync_lds();  // the next chunk rewrites the staging slice
         }
