@@ -430,16 +430,24 @@ __device__ void dc_merge(int n, int lo, int mid, int hi, double rho, double *sd,
     // the nearer pole.  Each step fits the sums over the poles below and above
     // the gap with one pole each (value and slope at the iterate) and moves to
     // the root of that model; a step that leaves the bracket bisects instead.
+    // G lanes per root (aligned groups inside a wavefront) split the sums over
+    // the poles and combine them with group sums, so every lane of a group
+    // holds the same values and takes the same steps; a wavefront iterates
+    // until all of its roots have stopped, finished roots keeping their value.
     const double *dl = S.delta, *zw = S.zz;
-    for (int j = tid; j < k; j += TRI_TPB) {
-        double zsum = 0.0;
-        for (int i = 0; i < k; ++i) zsum += zw[i] * zw[i];
+    int G = 64;
+    while (G > 1 && G * k > TRI_TPB) G >>= 1;
+    if (64 * wv < G * k) {  // wavefronts past the last root's group have nothing to do
+        const int g = lane & (G - 1), jr = tid / G, j = min(jr, k - 1);
+        double part = 0.0;
+        for (int i = g; i < k; i += G) part += zw[i] * zw[i];
+        const double zsum = group_sum(part, G);
         const bool last = j + 1 == k;
         const double lo_d = dl[j], hi_d = last ? dl[j] + rh * zsum : dl[j + 1];
         const double half = 0.5 * (hi_d - lo_d);
-        double f = 0.0;
-        for (int i = 0; i < k; ++i) f += zw[i] * zw[i] * rcpd(dl[i] - (lo_d + half));
-        f = 1.0 + rh * f;
+        part = 0.0;
+        for (int i = g; i < k; i += G) part += zw[i] * zw[i] * rcpd(dl[i] - (lo_d + half));
+        const double f = 1.0 + rh * group_sum(part, G);
         int o;
         double a, bnd;
         if (last || f >= 0.0) {
@@ -454,9 +462,11 @@ __device__ void dc_merge(int n, int lo, int mid, int hi, double rho, double *sd,
         const double dorg = dl[o];
         const double dj = dl[j] - dorg, dj1 = last ? 0.0 : dl[j + 1] - dorg;
         double x = 0.5 * (a + bnd);
+        bool done = false;
         for (int it = 0; it < DC_ITMAX; ++it) {
+            if (__builtin_amdgcn_ballot_w64(!done) == 0) break;  // every root of the wavefront has stopped
             double psi = 0.0, dpsi = 0.0, phi = 0.0, dphi = 0.0;
-            for (int i = 0; i < k; ++i) {
+            for (int i = g; i < k; i += G) {
                 const double r = rcpd((dl[i] - dorg) - x);
                 const double t = zw[i] * zw[i] * r;
                 const bool below = i <= j;
@@ -465,13 +475,21 @@ __device__ void dc_merge(int n, int lo, int mid, int hi, double rho, double *sd,
                 phi += below ? 0.0 : t;
                 dphi += below ? 0.0 : t * r;
             }
+            psi = group_sum(psi, G);
+            dpsi = group_sum(dpsi, G);
+            phi = group_sum(phi, G);
+            dphi = group_sum(dphi, G);
+            if (done) continue;
             const double fx = 1.0 + rh * (psi + phi);
             if (fx > 0.0)
                 bnd = x;
             else
                 a = x;
             const double err = 8.0 * 0x1p-53 * (1.0 + rh * (fabs(psi) + fabs(phi)) + fabs(x) * rh * (dpsi + dphi));
-            if (fabs(fx) <= err || bnd - a <= 2.0 * 0x1p-53 * fmax(fabs(a), fabs(bnd))) break;
+            if (fabs(fx) <= err || bnd - a <= 2.0 * 0x1p-53 * fmax(fabs(a), fabs(bnd))) {
+                done = true;
+                continue;
+            }
             const double u = dj - x, qq = dpsi * u * u, pp = psi - dpsi * u;
             double xn;
             if (!last) {
@@ -495,8 +513,10 @@ __device__ void dc_merge(int n, int lo, int mid, int hi, double rho, double *sd,
             }
             x = (a < xn && xn < bnd) ? xn : 0.5 * (a + bnd);
         }
-        S.org[j] = o;
-        S.tau[j] = x;
+        if (jr < k && g == 0) {
+            S.org[j] = o;
+            S.tau[j] = x;
+        }
     }
     __syncthreads();
     // weights recomputed from the roots (their signs kept), then the norms of
@@ -681,13 +701,13 @@ __device__ void dc_solve(int n, double *sd, double *se, double *pool, int *ipool
                 const double z0 = readlane_f64(zt[0][cq], cl), z1 = readlane_f64(zt[1][cq], cl);
                 const double *qc = Q + (size_t)c * N;
 #pragma unroll
-                for (int q = 0; q < NQ; ++q)
-                    if (64 * q < n) {  // uniform
-                        const int r = lane + 64 * q;
-                        const double x = r < n ? qc[r] : 0.0;
-                        acc[0][q] += x * z0;
-                        acc[1][q] += x * z1;
-                    }
+                for (int q = 0; q < NQ; ++q) {
+                    if (64 * q >= n) break;  // uniform: the row slots past n are not computed
+                    const int r = lane + 64 * q;
+                    const double x = r < n ? qc[r] : 0.0;
+                    acc[0][q] += x * z0;
+                    acc[1][q] += x * z1;
+                }
             }
         }
 #pragma unroll
