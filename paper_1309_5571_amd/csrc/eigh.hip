@@ -265,65 +265,105 @@ constexpr int DC_NLEAF = 32;    // most leaves: orders <= DC_MAX need at most 2^
 constexpr int DC_STAGE = 224;   // LDS staging of a row per wavefront (the pool's last 16 x 224)
 static_assert((DC_MAX + DC_NLEAF - 1) / DC_NLEAF <= DC_LEAF, "leaf count");
 // the pool (5 EIG_MAX_DIM doubles) holds the leaves, then the scratch of a merge
-static_assert(DC_NLEAF * DC_LEAF * (DC_LEAF + 1) <= 5 * EIG_MAX_DIM, "leaf scratch");
+static_assert(DC_NLEAF * DC_LEAF * (DC_LEAF + 1) + TRI_WAVES * (2 * DC_LEAF + 2) <= 5 * EIG_MAX_DIM, "leaf scratch");
 static_assert(13 * DC_MAX + 16 * DC_STAGE <= 5 * EIG_MAX_DIM, "merge scratch");
 static_assert(QB * 64 * Q_REG <= 4 * EIG_MAX_DIM, "Q formation: factor vectors in the pool past the factors' t");
 
-// Implicit QL (as the large-order path) on a leaf of order m <= DC_LEAF on one
-// lane: d (LDS, length m) becomes its eigenvalues, e (length m, e[m-1] = 0) is
-// destroyed, Zl (row-major m x m, LDS) its eigenvectors.  Returns the
-// iteration count, or -1 if an eigenvalue needed more than QL_MAXIT.
-__device__ int ql_leaf(int m, double *d, double *e, double *Zl) {
-    for (int r = 0; r < m; ++r)
-        for (int c = 0; c < m; ++c) Zl[r * DC_LEAF + c] = r == c ? 1.0 : 0.0;
-    double anorm = 0.0;
-    for (int i = 0; i < m; ++i) anorm = fmax(anorm, fabs(d[i]) + fabs(e[i]) + (i ? fabs(e[i - 1]) : 0.0));
-    const double tol = anorm * 0x1p-53;
-    int its = 0;
-    for (int l = 0; l < m; ++l) {
-        for (int it = 0;; ++it) {
-            int mm = l;
-            while (mm < m - 1 && fabs(e[mm]) > tol) ++mm;
-            if (mm == l) break;
-            if (it >= QL_MAXIT) return -1;
-            ++its;
-            double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
-            double r = hyp(g, 1.0);
-            g = d[mm] - d[l] + e[l] / (g + copysign(r, g));
-            double s = 1.0, c = 1.0, p = 0.0;
-            bool early = false;
-            for (int i = mm - 1; i >= l; --i) {
-                const double f = s * e[i], bb = c * e[i];
-                r = hyp(f, g);
-                e[i + 1] = r;
-                if (r == 0.0) {
-                    d[i + 1] -= p;
-                    e[mm] = 0.0;
-                    early = true;
+// Implicit QL (as the large-order path) on a leaf of order m <= DC_LEAF, one
+// wavefront: d (LDS, length m) becomes its eigenvalues, e (length m,
+// e[m-1] = 0) is destroyed, Zl (row-major m x m, LDS, row stride DC_LEAF) its
+// eigenvectors.  Lane 0 runs each iteration's chase and leaves its rotations
+// in rot (cosines, then sines, by index); then lane r applies them, in the
+// chase's order, to row r of Zl.  wctl: four ints of LDS.  Every lane returns
+// the iteration count, or -1 if an eigenvalue needed more than QL_MAXIT.
+__device__ __forceinline__ int ql_leaf(int m, double *d, double *e, double *Zl, double *rot, int *wctl) {
+    const int lane = threadIdx.x & 63;
+    for (int i = lane; i < m * DC_LEAF; i += 64) Zl[i] = i / DC_LEAF == i % DC_LEAF ? 1.0 : 0.0;
+    double *rc = rot, *rs = rot + DC_LEAF;
+    int l = 0, it_l = 0, its = 0;
+    double tol = 0.0;
+    if (lane == 0) {
+        double anorm = 0.0;
+        for (int i = 0; i < m; ++i) anorm = fmax(anorm, fabs(d[i]) + fabs(e[i]) + (i ? fabs(e[i - 1]) : 0.0));
+        tol = anorm * 0x1p-53;
+    }
+    for (;;) {
+        if (lane == 0) {
+            // the next iteration: status 0 and the rotation range [lo, hi], 1 when
+            // every eigenvalue has converged, -1 when one did not
+            int status = 1, lo = 0, hi = -1;
+            while (l < m) {
+                int mm = l;
+                while (mm < m - 1 && fabs(e[mm]) > tol) ++mm;
+                if (mm == l) {
+                    ++l;
+                    it_l = 0;
+                    continue;
+                }
+                if (it_l >= QL_MAXIT) {
+                    status = -1;
                     break;
                 }
-                s = f / r;
-                c = g / r;
-                g = d[i + 1] - p;
-                r = (d[i] - g) * s + 2.0 * c * bb;
-                p = s * r;
-                d[i + 1] = g + p;
-                g = c * r - bb;
-                for (int row = 0; row < m; ++row) {
-                    double *zr = Zl + row * DC_LEAF;
-                    const double h = zr[i + 1];
-                    zr[i + 1] = s * zr[i] + c * h;
-                    zr[i] = c * zr[i] - s * h;
+                ++it_l;
+                ++its;
+                double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+                double r = hyp(g, 1.0);
+                g = d[mm] - d[l] + e[l] / (g + copysign(r, g));
+                double s = 1.0, c = 1.0, p = 0.0;
+                bool early = false;
+                int i = mm - 1;
+                for (; i >= l; --i) {
+                    const double f = s * e[i], bb = c * e[i];
+                    r = hyp(f, g);
+                    e[i + 1] = r;
+                    if (r == 0.0) {
+                        d[i + 1] -= p;
+                        e[mm] = 0.0;
+                        early = true;
+                        break;
+                    }
+                    s = f / r;
+                    c = g / r;
+                    g = d[i + 1] - p;
+                    r = (d[i] - g) * s + 2.0 * c * bb;
+                    p = s * r;
+                    d[i + 1] = g + p;
+                    g = c * r - bb;
+                    rc[i] = c;
+                    rs[i] = s;
                 }
+                if (!early) {
+                    d[l] -= p;
+                    e[l] = g;
+                    e[mm] = 0.0;
+                }
+                status = 0;
+                lo = i + 1;  // (l when the chase ran through)
+                hi = mm - 1;
+                break;
             }
-            if (!early) {
-                d[l] -= p;
-                e[l] = g;
-                e[mm] = 0.0;
+            wctl[0] = status;
+            wctl[1] = lo;
+            wctl[2] = hi;
+            wctl[3] = its;
+        }
+        wave_sync_lds();
+        const int status = wctl[0], lo = wctl[1], hi = wctl[2];
+        if (status != 0) {
+            const int n_its = wctl[3];
+            wave_sync_lds();  // (wctl is rewritten by the next leaf of this wavefront)
+            return status < 0 ? -1 : n_its;
+        }
+        if (lane < m) {
+            double *zr = Zl + lane * DC_LEAF;
+            for (int i = hi; i >= lo; --i) {
+                const double c = rc[i], s = rs[i], h = zr[i + 1];
+                zr[i + 1] = s * zr[i] + c * h;
+                zr[i] = c * zr[i] - s * h;
             }
         }
+        wave_sync_lds();  // the next chase rewrites rc, rs
     }
-    return its;
 }
 
 // Scratch of one merge (LDS, carved from the pool): doubles of length DC_MAX
@@ -631,12 +671,15 @@ __device__ void dc_solve(int n, double *sd, double *se, double *pool, int *ipool
     // leaves: one wavefront each (its lane 0), eigenvectors in LDS, then into Zt
     double *leafZ = pool;                              // [nleaf][DC_LEAF][DC_LEAF]
     double *leafE = pool + DC_NLEAF * DC_LEAF * DC_LEAF;  // [nleaf][DC_LEAF]
+    double *leafR = leafE + DC_NLEAF * DC_LEAF + wv * 2 * DC_LEAF;  // this wavefront's rotations
+    int *leafC = (int *)(leafE + DC_NLEAF * DC_LEAF + TRI_WAVES * 2 * DC_LEAF) + 4 * wv;
     for (int lf = wv; lf < nleaf; lf += TRI_WAVES) {
+        const int lo = bnd(T, lf), m = bnd(T, lf + 1) - lo;
+        double *el = leafE + lf * DC_LEAF;
+        for (int i = lane; i < m; i += 64) el[i] = i + 1 < m ? se[lo + i] : 0.0;
+        wave_sync_lds();
+        const int it = ql_leaf(m, sd + lo, el, leafZ + lf * DC_LEAF * DC_LEAF, leafR, leafC);
         if (lane == 0) {
-            const int lo = bnd(T, lf), m = bnd(T, lf + 1) - lo;
-            double *el = leafE + lf * DC_LEAF;
-            for (int i = 0; i < m; ++i) el[i] = i + 1 < m ? se[lo + i] : 0.0;
-            const int it = ql_leaf(m, sd + lo, el, leafZ + lf * DC_LEAF * DC_LEAF);
             if (it < 0) ctl[2] = 1;
             else atomicAdd(&ctl[3], it);
         }
