@@ -217,6 +217,21 @@ __device__ __forceinline__ double block_sum_lead(double x, double lead, double *
     return t;
 }
 
+// Sum over the workgroup with one barrier, and the value `lead` of the thread
+// where `own` holds, to every thread: the caller alternates two buffers of
+// TRI_WAVES + 1, so that a buffer is rewritten only after another barrier
+__device__ __forceinline__ double block_sum1(double x, bool own, double lead, double *buf, double *lead_out) {
+    x = group_sum<64>(x);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) buf[wv] = x;
+    if (own) buf[TRI_WAVES] = lead;
+    __syncthreads();
+    double t = 0.0;
+    for (int i = 0; i < TRI_WAVES; ++i) t += buf[i];
+    *lead_out = buf[TRI_WAVES];
+    return t;
+}
+
 // sqrt(x^2 + y^2) without overflow or harmful underflow
 __device__ __forceinline__ double hyp(double x, double y) {
     const double ax = fabs(x), ay = fabs(y);
@@ -783,6 +798,7 @@ __global__ __launch_bounds__(TRI_TPB) void k_eigh_tri(int nblk, const int64_t *_
     // (after Q is formed, the divide-and-conquer path uses the whole pool)
     __shared__ int srank[EIG_MAX_DIM];
     __shared__ double red[TRI_WAVES + 1];
+    __shared__ double red2[TRI_WAVES + 1];  // second buffer of the reductions of the Householder steps
     __shared__ int ctl[4];
     const int b = blockIdx.x;
     if (b >= nblk) return;
@@ -799,43 +815,49 @@ __global__ __launch_bounds__(TRI_TPB) void k_eigh_tri(int nblk, const int64_t *_
     // ---- Householder reduction: step k zeroes A(k, k+2..) and A(k+2.., k) with
     // H = I - t v v^T acting on indices k+1.., v(0) = 1 (stored in row k beyond it).
     // A stays exactly symmetric, so column i of the trailing block is its row i:
-    // each thread owns columns (coalesced across the threads of a row).
-    for (int k = 0; k + 2 < d; ++k) {
-        const int L = d - k - 1;
-        const double *rowk = A + k * D + k + 1;  // x = A(k, k+1..) = A(k+1.., k)
+    // each thread owns columns (coalesced across the threads of a row).  Step k
+    // needs p = t A22 v, w = p - K v and A22 -= v w^T + w v^T; the update of
+    // step k and the product of step k + 1 are one pass over the block: row
+    // k + 1 is updated first (it yields the next reflector), then every other
+    // element is updated, stored and multiplied by the next v at once.
+    // sv: v of the current step, sn: v of the next one, sy: p, then w.
+    double *sv = sx, *sn = sz;
+    double t = 0.0;  // the current step's factor
+    {
+        // step 0's reflector from row 0 and its product p = t A22 v
+        const int L = d - 1;
         double part = 0.0;
         for (int j = tid; j < L; j += TRI_TPB) {
-            const double x = rowk[j];
-            sx[j] = x;
+            const double x = A[1 + j];
+            sv[j] = x;
             if (j) part += x * x;
         }
         double alpha;
-        const double sigma = block_sum_lead(part, tid == 0 ? rowk[0] : 0.0, red, &alpha);
-        if (tid == 0) sd[k] = A[k * D + k];
-        if (sigma == 0.0) {  // the column is already reduced
+        const double sigma = block_sum_lead(part, tid == 0 ? A[1] : 0.0, red, &alpha);
+        if (sigma == 0.0) {
             if (tid == 0) {
-                se[k] = alpha;
-                sq[k] = 0.0;
+                sd[0] = A[0];
+                se[0] = alpha;
+                sq[0] = 0.0;
             }
-            continue;
-        }
-        const double beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
-        const double t = (beta - alpha) / beta;
-        const double scale = 1.0 / (alpha - beta);
-        for (int j = tid; j < L; j += TRI_TPB) sx[j] = j ? sx[j] * scale : 1.0;
-        if (tid == 0) {
-            se[k] = beta;
-            sq[k] = t;
+            for (int j = tid; j < L; j += TRI_TPB) sv[j] = j ? 0.0 : 1.0;  // with t = 0: no reflection
+        } else {
+            const double beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
+            t = (beta - alpha) / beta;
+            const double scale = 1.0 / (alpha - beta);
+            for (int j = tid; j < L; j += TRI_TPB) sv[j] = j ? sv[j] * scale : 1.0;
+            if (tid == 0) {
+                sd[0] = A[0];
+                se[0] = beta;
+                sq[0] = t;
+            }
         }
         __syncthreads();
-        // p = t A22 v: p_i = t sum_j A(k+1+j, k+1+i) v_j.  Thread (i, g) sums the
-        // rows of group g of column i (G groups, so that every thread works and
-        // each issues its loads in batches); the groups' partials meet in LDS.
         const int G = max(1, min(TRI_TPB / L, 32)), R = (L + G - 1) / G;
         for (int q = tid; q < G * L; q += TRI_TPB) {
             const int i = q % L, g = q / L;
             const int j0 = g * R, j1 = min(L, j0 + R);
-            const double *col = A + (k + 1) * D + k + 1 + i;
+            const double *col = A + D + 1 + i;
             double acc = 0.0;
             for (int jb = j0; jb < j1; jb += TRI_UB) {
                 double av[TRI_UB];
@@ -843,32 +865,77 @@ __global__ __launch_bounds__(TRI_TPB) void k_eigh_tri(int nblk, const int64_t *_
                 for (int u = 0; u < TRI_UB; ++u) av[u] = col[min(jb + u, j1 - 1) * D];
 #pragma unroll
                 for (int u = 0; u < TRI_UB; ++u)
-                    if (jb + u < j1) acc += av[u] * sx[jb + u];
+                    if (jb + u < j1) acc += av[u] * sv[jb + u];
             }
             spart[q] = acc;
         }
         __syncthreads();
+    }
+    for (int k = 0; k + 2 < d; ++k) {
+        const int L = d - k - 1, G = max(1, min(TRI_TPB / L, 32));
+        // p and w of step k (the groups' partial products meet in LDS)
         double pv = 0.0;
         for (int i = tid; i < L; i += TRI_TPB) {
             double acc = 0.0;
             for (int g = 0; g < G; ++g) acc += spart[g * L + i];
             const double pi = t * acc;
             sy[i] = pi;
-            pv += pi * sx[i];
+            pv += pi * sv[i];
         }
         double unused;
-        const double K = 0.5 * t * block_sum_lead(pv, 0.0, red, &unused);
-        for (int j = tid; j < L; j += TRI_TPB) sy[j] -= K * sx[j];  // w
+        const double K = 0.5 * t * block_sum1(pv, false, 0.0, red, &unused);
+        for (int j = tid; j < L; j += TRI_TPB) sy[j] -= K * sv[j];  // w
         __syncthreads();
-        // A22 -= v w^T + w v^T, thread (i, g) on the rows of group g of column i;
-        // both products rounded before the sum, so A(i, j) and A(j, i) stay
-        // bit-identical; loads in batches (the stores of a column may alias its
-        // next loads as far as the compiler knows)
-        for (int q = tid; q < G * L; q += TRI_TPB) {
-            const int i = q % L, g = q / L;
-            const int j0 = g * R, j1 = min(L, j0 + R);
-            double *col = A + (k + 1) * D + k + 1 + i;
-            const double vi = sx[i], wi = sy[i];
+        for (int j = 1 + tid; j < L; j += TRI_TPB) A[k * D + k + 1 + j] = sv[j];
+        // row k + 1 after step k's update (both products rounded before the sum,
+        // so A(i, j) and A(j, i) stay bit-identical): its diagonal, and the
+        // vector x of step k + 1 into sn
+        const bool next = k + 3 < d;
+        double part = 0.0, diag = 0.0, lead = 0.0;
+        for (int i = tid; i < L; i += TRI_TPB) {
+            const double val = A[(k + 1) * D + k + 1 + i] - __dadd_rn(__dmul_rn(sv[0], sy[i]), __dmul_rn(sy[0], sv[i]));
+            if (i == 0) diag = val;
+            if (i == 1) lead = val;
+            if (i >= 1) sn[i - 1] = val;
+            if (i >= 2) part += val * val;
+        }
+        double alpha;  // x(0), handed over by the thread that formed it (sn[0] is rescaled below)
+        const double sigma = block_sum1(part, tid == 1, lead, red2, &alpha);
+        double tn = 0.0;
+        if (!next) {  // the trailing 2 x 2: no reflector
+            if (tid == 0) {
+                sd[k + 1] = diag;
+                se[k + 1] = alpha;
+            }
+        } else if (sigma == 0.0) {  // the column is already reduced
+            if (tid == 0) {
+                sd[k + 1] = diag;
+                se[k + 1] = alpha;
+                sq[k + 1] = 0.0;
+            }
+            for (int j = tid; j < L - 1; j += TRI_TPB) sn[j] = j ? 0.0 : 1.0;  // with t = 0: no reflection
+        } else {
+            const double beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
+            tn = (beta - alpha) / beta;
+            const double scale = 1.0 / (alpha - beta);
+            for (int j = tid; j < L - 1; j += TRI_TPB) sn[j] = j ? sn[j] * scale : 1.0;
+            if (tid == 0) {
+                sd[k + 1] = diag;
+                se[k + 1] = beta;
+                sq[k + 1] = tn;
+            }
+        }
+        __syncthreads();
+        // the rest of A22 (indices k + 2..): updated, stored, and (with a next
+        // step) summed into that step's p; thread (i, g) on the rows of group g
+        // of column i, loads in batches
+        const int L1 = L - 1, G1 = max(1, min(TRI_TPB / L1, 32)), R1 = (L1 + G1 - 1) / G1;
+        for (int q = tid; q < G1 * L1; q += TRI_TPB) {
+            const int i = q % L1, g = q / L1;
+            const int j0 = g * R1, j1 = min(L1, j0 + R1);
+            double *col = A + (k + 2) * D + k + 2 + i;
+            const double vi = sv[i + 1], wi = sy[i + 1];
+            double acc = 0.0;
             for (int jb = j0; jb < j1; jb += TRI_UB) {
                 double av[TRI_UB];
 #pragma unroll
@@ -876,17 +943,23 @@ __global__ __launch_bounds__(TRI_TPB) void k_eigh_tri(int nblk, const int64_t *_
 #pragma unroll
                 for (int u = 0; u < TRI_UB; ++u) {
                     const int j = jb + u;
-                    if (j < j1) col[j * D] = av[u] - __dadd_rn(__dmul_rn(sx[j], wi), __dmul_rn(sy[j], vi));
+                    if (j < j1) {
+                        const double val = av[u] - __dadd_rn(__dmul_rn(sv[j + 1], wi), __dmul_rn(sy[j + 1], vi));
+                        col[j * D] = val;
+                        acc += val * sn[j];
+                    }
                 }
             }
+            if (next) spart[q] = acc;
         }
-        for (int j = 1 + tid; j < L; j += TRI_TPB) A[k * D + k + 1 + j] = sx[j];
         __syncthreads();
+        double *tmp = sv;  // the next step's v becomes the current one
+        sv = sn;
+        sn = tmp;
+        t = tn;
     }
     if (tid == 0) {
-        sd[d - 2] = A[(d - 2) * D + d - 2];
         sd[d - 1] = A[(d - 1) * D + d - 1];
-        se[d - 2] = A[(d - 1) * D + d - 2];
         se[d - 1] = 0.0;
     }
     // ---- Q = H_0 H_1 ... H_{d-3}, accumulated from the last factor; H_k Q only
