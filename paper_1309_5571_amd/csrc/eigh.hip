@@ -754,17 +754,34 @@ __device__ void dc_solve(int n, double *sd, double *se, double *pool, int *ipool
         for (int cq = 0; cq < NQ; ++cq) {
             if (64 * cq >= n) break;
             const int cn = min(64, n - 64 * cq);
-            for (int cl = 0; cl < cn; ++cl) {
+            // two columns of Q per step, both loaded before their products
+            for (int cl = 0; cl < cn; cl += 2) {
                 const int c = 64 * cq + cl;
-                const double z0 = readlane_f64(zt[0][cq], cl), z1 = readlane_f64(zt[1][cq], cl);
-                const double *qc = Q + (size_t)c * N;
+                const bool two = cl + 1 < cn;  // uniform
+                const double *qa = Q + (size_t)c * N, *qb = Q + (size_t)(two ? c + 1 : c) * N;
+                double xa[NQ], xb[NQ];
 #pragma unroll
                 for (int q = 0; q < NQ; ++q) {
                     if (64 * q >= n) break;  // uniform: the row slots past n are not computed
                     const int r = lane + 64 * q;
-                    const double x = r < n ? qc[r] : 0.0;
-                    acc[0][q] += x * z0;
-                    acc[1][q] += x * z1;
+                    xa[q] = r < n ? qa[r] : 0.0;
+                    xb[q] = r < n ? qb[r] : 0.0;
+                }
+                const double z0 = readlane_f64(zt[0][cq], cl), z1 = readlane_f64(zt[1][cq], cl);
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    if (64 * q >= n) break;
+                    acc[0][q] += xa[q] * z0;
+                    acc[1][q] += xa[q] * z1;
+                }
+                if (two) {
+                    const double y0 = readlane_f64(zt[0][cq], cl + 1), y1 = readlane_f64(zt[1][cq], cl + 1);
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q) {
+                        if (64 * q >= n) break;
+                        acc[0][q] += xb[q] * y0;
+                        acc[1][q] += xb[q] * y1;
+                    }
                 }
             }
         }
