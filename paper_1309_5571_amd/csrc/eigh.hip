@@ -1006,7 +1006,10 @@ __global__ __launch_bounds__(TRI_TPB) void k_eigh_tri(int nblk, const int64_t *_
                 for (int e = 0; e < 4; ++e) {
                     const double *col = Z + (r0 + min(c0 + e, L0 - 1)) * D + r0;
 #pragma unroll
-                    for (int q = 0; q < Q_REG; ++q) cv[e][q] = col[min(lane + 64 * q, L0 - 1)];
+                    for (int q = 0; q < Q_REG; ++q) {
+                        if (64 * q >= L0) break;  // uniform: the row slots past L0 are not used
+                        cv[e][q] = col[min(lane + 64 * q, L0 - 1)];
+                    }
                 }
                 for (int k = khi; k >= klo; --k) {
                     const double t = sq[k];
@@ -1014,17 +1017,19 @@ __global__ __launch_bounds__(TRI_TPB) void k_eigh_tri(int nblk, const int64_t *_
                     const double *v = sv + (k - klo) * L0;
                     double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                    for (int e = 0; e < 4; ++e)
+                    for (int q = 0; q < Q_REG; ++q) {
+                        if (64 * q >= L0) break;
+                        const int r = lane + 64 * q;
+                        const double vr = r < L0 ? v[r] : 0.0;
 #pragma unroll
-                        for (int q = 0; q < Q_REG; ++q) {
-                            const int r = lane + 64 * q;
-                            if (r < L0) acc[e] += v[r] * cv[e][q];
-                        }
+                        for (int e = 0; e < 4; ++e) acc[e] += vr * cv[e][q];
+                    }
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
                         const double ty = t * group_sum<64>(acc[e]);
 #pragma unroll
                         for (int q = 0; q < Q_REG; ++q) {
+                            if (64 * q >= L0) break;
                             const int r = lane + 64 * q;
                             if (r < L0) cv[e][q] -= ty * v[r];
                         }
