@@ -16,9 +16,9 @@
 // formation of Q are whole-workgroup passes over the block (in global memory,
 // where it stays cache-resident).  Orders up to 512: Cuppen's divide and
 // conquer on T (leaves of at most 16 by implicit QL, one wavefront each;
-// merges by deflation, the secular equation one thread per root and Gu and
-// Eisenstat's recomputed weights), then the eigenvectors of the block as Q
-// times those of T.  Larger orders: the implicit QL iteration with
+// merges by deflation, the secular equation on a group of lanes per root and
+// Gu and Eisenstat's recomputed weights), then the eigenvectors of the block
+// as Q times those of T.  Larger orders: the implicit QL iteration with
 // Wilkinson's shift on T (the tql2 procedure of Bowdler, Martin, Reinsch and
 // Wilkinson), whose plane rotations are applied to the columns of Q: the QL
 // recurrence is sequential and runs on one lane, writing each sweep's
@@ -258,9 +258,10 @@ constexpr int QB = 16;      // factors per block of the Q formation (their vecto
 // eigenvectors and the first row of the right half's): deflation of
 // negligible weights and of nearly equal poles (a plane rotation), the roots
 // of the secular equation 1 + rho sum z_i^2 / (d_i - lambda) = 0 from the
-// nearer pole (one thread per root: a two-pole rational model, bracketed), the weights recomputed from the
-// roots, and the rows of the merged block of eigenvectors multiplied by the
-// merge's eigenvector matrix (one wavefront per row, in place).
+// nearer pole (a group of lanes per root: a two-pole rational model,
+// bracketed), the weights recomputed from the roots, and the rows of the
+// merged block of eigenvectors multiplied by the merge's eigenvector matrix
+// (one wavefront per row, in place).
 constexpr int DC_MAX = 512;
 constexpr int DC_LEAF = 16;
 constexpr int DC_ITMAX = 100;  // root-finder steps per root (they end at the resolution, typically after 3-8)
