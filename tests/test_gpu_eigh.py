@@ -1,8 +1,9 @@
 """GPU parity of the blockwise eigen-decomposition (Alg. 1, step 6) against
 the oracle (LAPACK through NumPy), called through the C ABI.
 
-Tolerances follow the backward error of both device methods (Jacobi up to
-order 48, Householder tridiagonalization + implicit QL above), a small
+Tolerances follow the backward error of the device methods (Jacobi up to
+order 16, Householder tridiagonalization + divide and conquer or implicit QL
+above), a small
 multiple of d u |A|_F per block (u = 2^-53, d the block order): eigenvalues and the
 reconstruction U diag(w) U^T within 16 d u |A|_F, U^T U within 16 d u of
 the identity, and each eigenvector within 16 d u |A|_F / gap of the oracle's
@@ -115,7 +116,7 @@ def test_eigh_degenerate_and_special_blocks():
     w, U = res[3]
     assert np.array_equal(w, np.sort(np.diag(D))[::-1])
     assert np.array_equal(np.abs(U), np.abs(U).round())
-    w, U = res[5]  # the same above order 48 (tridiagonal path: no reflection, no QL step)
+    w, U = res[5]  # the same on the tridiagonal path (no reflection, no QL step)
     assert np.array_equal(w, np.sort(np.diag(D2))[::-1])
     assert np.array_equal(np.abs(U), np.abs(U).round())
     for (w, U), B in zip(res[:3] + res[6:], blocks[:3] + blocks[6:]):
