@@ -261,7 +261,7 @@ constexpr int QB = 16;      // factors per block of the Q formation (their vecto
 // nearer pole (a group of lanes per root: a two-pole rational model,
 // bracketed), the weights recomputed from the roots, and the rows of the
 // merged block of eigenvectors multiplied by the merge's eigenvector matrix
-// (one wavefront per row, in place).
+// (two rows per wavefront, in place).
 constexpr int DC_MAX = 512;
 constexpr int DC_LEAF = 16;
 constexpr int DC_ITMAX = 100;  // root-finder steps per root (they end at the resolution, typically after 3-8)
@@ -608,10 +608,12 @@ __device__ void dc_merge(int n, int lo, int mid, int hi, double rho, double *sd,
     }
     // rows of the block times the merge's eigenvectors: slot t of the block takes
     // pole t (in pole order); a deflated slot keeps its column, the slot of the
-    // non-deflated pole nd[j] gets root j's eigenvector.  One wavefront per row:
-    // the row's weighted entries y_i zhat_i are staged in LDS and read by every
-    // lane, each lane accumulating the outputs of its roots j = lane + 64 q.
+    // non-deflated pole nd[j] gets root j's eigenvector.  One wavefront per two
+    // rows: their weighted entries y_i zhat_i are staged in LDS and read by every
+    // lane, each lane accumulating the outputs of its roots j = lane + 64 q, one
+    // reciprocal serving both rows.
     constexpr int NQ = DC_MAX / 64;
+    constexpr int CH = DC_STAGE / 2;  // entries of each row per staging round
     double djr[NQ], tjr[NQ];  // origin pole and offset of this lane's roots
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
@@ -619,38 +621,49 @@ __device__ void dc_merge(int n, int lo, int mid, int hi, double rho, double *sd,
         djr[q] = j < k ? dl[S.org[j]] : 0.0;
         tjr[q] = j < k ? S.tau[j] : -1.0;  // (past k: a finite, unused difference)
     }
-    double *st = S.stage + wv * DC_STAGE;
-    for (int r = lo + wv; r < hi; r += TRI_WAVES) {
-        double yd[NQ], acc[NQ];
+    double *st = S.stage + wv * DC_STAGE;  // [CH][2]
+    for (int r = lo + 2 * wv; r < hi; r += 2 * TRI_WAVES) {
+        const bool two = r + 1 < hi;  // uniform
+        double yd[2][NQ], acc[2][NQ];
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
             const int t = lane + 64 * q;
-            acc[q] = 0.0;
-            yd[q] = (64 * q < m && t < m) ? Zt[(size_t)(lo + S.perm[t]) * N + r] : 0.0;
+            acc[0][q] = acc[1][q] = 0.0;
+            yd[0][q] = (64 * q < m && t < m) ? Zt[(size_t)(lo + S.perm[t]) * N + r] : 0.0;
+            yd[1][q] = (two && 64 * q < m && t < m) ? Zt[(size_t)(lo + S.perm[t]) * N + r + 1] : 0.0;
         }
-        for (int c0 = 0; c0 < k; c0 += DC_STAGE) {
-            const int cnt = min(DC_STAGE, k - c0);
+        for (int c0 = 0; c0 < k; c0 += CH) {
+            const int cnt = min(CH, k - c0);
             for (int e = lane; e < cnt; e += 64) {
                 const int i = c0 + e;
-                st[e] = Zt[(size_t)(lo + S.perm[S.nd[i]]) * N + r] * S.zhat[i];
+                const double *src = Zt + (size_t)(lo + S.perm[S.nd[i]]) * N;
+                const double zh = S.zhat[i];
+                st[2 * e] = src[r] * zh;
+                st[2 * e + 1] = two ? src[r + 1] * zh : 0.0;
             }
             wave_sync_lds();
             for (int e = 0; e < cnt; ++e) {
-                const double yv = st[e], di = dl[c0 + e];
+                const double ya = st[2 * e], yb = st[2 * e + 1], di = dl[c0 + e];
 #pragma unroll
                 for (int q = 0; q < NQ; ++q) {
                     if (64 * q >= k) break;  // uniform: the root slots past k are not computed
-                    acc[q] += yv * rcpd((di - djr[q]) - tjr[q]);
+                    const double rc = rcpd((di - djr[q]) - tjr[q]);
+                    acc[0][q] += ya * rc;
+                    acc[1][q] += yb * rc;
                 }
             }
             wave_sync_lds();  // the next chunk rewrites the staging slice
         }
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            const int i = lane + 64 * q;
-            if (64 * q < m) {
-                if (i < k) Zt[(size_t)(lo + S.nd[i]) * N + r] = acc[q] * S.invn[i];
-                if (i < m && S.defl[i]) Zt[(size_t)(lo + i) * N + r] = yd[q];
+        for (int h = 0; h < 2; ++h) {
+            if (h == 1 && !two) break;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const int i = lane + 64 * q;
+                if (64 * q < m) {
+                    if (i < k) Zt[(size_t)(lo + S.nd[i]) * N + r + h] = acc[h][q] * S.invn[i];
+                    if (i < m && S.defl[i]) Zt[(size_t)(lo + i) * N + r + h] = yd[h][q];
+                }
             }
         }
     }
