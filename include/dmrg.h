@@ -345,7 +345,7 @@ dmrg_status dmrg_density(dmrg_plan *plan, const double *psi, double *rho_left, d
 /* Eigen-decomposition of symmetric blocks, e.g. the density-matrix blocks of
  * dmrg_density (Alg. 1, step 6: the eigenvalues of each block's density
  * matrix select the states the block keeps).  FP64, one workgroup per block:
- * cyclic Jacobi for orders up to 16 (in LDS), Householder reduction to
+ * cyclic Jacobi for orders up to 8 (in LDS), Householder reduction to
  * tridiagonal form for larger orders, finished by divide and conquer up to
  * order 512 and by the implicit QL iteration above.
  *  off, dim, woff: device arrays [nblk].  Block b is the row-major symmetric
@@ -355,9 +355,9 @@ dmrg_status dmrg_density(dmrg_plan *plan, const double *psi, double *rho_left, d
  *    of w[woff[b] + j], with its first entry of largest magnitude positive.
  *  a is overwritten (contents unspecified on return).  a, w and u are
  *    device FP64, owned by the caller, and must not overlap.
- *  info: optional device [nblk]: Jacobi sweeps (order <= 16), 1 + the QL
+ *  info: optional device [nblk]: Jacobi sweeps (order <= 8), 1 + the QL
  *    iterations of the leaves plus the merges (divide and conquer, orders
- *    17..512), or 1 + the QL iterations (orders above 512); -1 if dim[b] is
+ *    9..512), or 1 + the QL iterations (orders above 512); -1 if dim[b] is
  *    outside 1..2048 (the block is then not touched), -2 if the method did
  *    not converge (40 sweeps; 60 QL iterations for one eigenvalue).
  *  The sizes are read on the device: the caller guarantees that every

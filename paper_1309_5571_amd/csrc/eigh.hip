@@ -2,7 +2,7 @@
 // each block's density matrix decide which states the block keeps).
 // One workgroup per block, two methods by order d:
 //
-// d <= 16: cyclic two-sided Jacobi in LDS with the round-robin ("circle")
+// d <= 8: cyclic two-sided Jacobi in LDS with the round-robin ("circle")
 // ordering: each round pairs every index with one other, the d/2 plane
 // rotations J of a round are independent, so all of them are found together
 // and then applied at once, A <- J^T A J and V <- V J.  With the indices
@@ -11,7 +11,7 @@
 // whole sub-blocks.  A sweep is d - 1 rounds (every pair once); the method
 // stops after a sweep with no rotation.
 //
-// 16 < d <= 2048: Householder reduction to tridiagonal form T = Q^T A Q, the
+// 8 < d <= 2048: Householder reduction to tridiagonal form T = Q^T A Q, the
 // matrix Q formed explicitly, then T's eigenpairs.  The reduction and the
 // formation of Q are whole-workgroup passes over the block (in global memory,
 // where it stays cache-resident).  Orders up to 512: Cuppen's divide and
@@ -34,7 +34,7 @@ namespace dmrg {
 
 constexpr int EIG_TPB = 256;        // selection kernel
 constexpr int EIG_TPB_SMALL = 512;  // Jacobi, blocks in LDS (a round has ~d^2/2 independent items)
-constexpr int EIG_LDS_DIM = 16;  // largest order of the Jacobi kernel (larger ones are faster on the tridiagonal path)
+constexpr int EIG_LDS_DIM = 8;  // largest order of the Jacobi kernel (larger ones are faster on the tridiagonal path)
 constexpr int EIG_MAX_DIM = 2048;
 constexpr int EIG_MAX_SWEEPS = 40;
 constexpr int TRI_TPB = 1024;  // tridiagonal path

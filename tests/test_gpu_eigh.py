@@ -2,7 +2,7 @@
 the oracle (LAPACK through NumPy), called through the C ABI.
 
 Tolerances follow the backward error of the device methods (Jacobi up to
-order 16, Householder tridiagonalization + divide and conquer or implicit QL
+order 8, Householder tridiagonalization + divide and conquer or implicit QL
 above), a small
 multiple of d u |A|_F per block (u = 2^-53, d the block order): eigenvalues and the
 reconstruction U diag(w) U^T within 16 d u |A|_F, U^T U within 16 d u of
