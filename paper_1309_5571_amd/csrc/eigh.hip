@@ -427,39 +427,62 @@ __device__ void dc_merge(int n, int lo, int mid, int hi, double rho, double *sd,
     }
     __syncthreads();
     // deflation (one thread, in pole order): a negligible weight leaves its pole;
-    // two poles closer than the resolution are rotated so that one weight vanishes
+    // two poles closer than the resolution are rotated so that one weight vanishes.
+    // The poles and weights are read eight at a time; the pole kept from the last
+    // step (prev) is carried in registers, and the rotation test |(d_t - d_p) c s|
+    // <= tol is taken as |d_t - d_p| |z_t z_p| <= tol (z_p^2 + z_t^2) (no root: the
+    // weights left are above tol / rh >= 8u, so the squares do not underflow).  A
+    // pole joins the list of kept ones once the next one can no longer deflate it.
     if (tid == 0) {
         double *zs = S.zeta, *ds = S.ds;
         const double tol = 8.0 * 0x1p-53 * fmax(fmax(fabs(ds[0]), fabs(ds[m - 1])), rh);
         int nrot = 0, prev = -1, k = 0;
-        for (int t = 0; t < m; ++t) {
-            S.defl[t] = 0;
-            if (rh * fabs(zs[t]) <= tol) {
-                S.defl[t] = 1;
-                continue;
+        double zp = 0.0, dp = 0.0;  // weight and pole of prev
+        for (int t0 = 0; t0 < m; t0 += 8) {
+            double zb[8], db[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int t = min(t0 + u, m - 1);
+                zb[u] = zs[t];
+                db[u] = ds[t];
             }
-            if (prev >= 0) {
-                const double tt = hyp(zs[prev], zs[t]);
-                const double c = zs[t] / tt, sn = -zs[prev] / tt;
-                if (fabs((ds[t] - ds[prev]) * c * sn) <= tol) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int t = t0 + u;
+                if (t >= m) break;
+                double zt = zb[u], dt = db[u];
+                if (rh * fabs(zt) <= tol) {
+                    S.defl[t] = 1;
+                    continue;
+                }
+                S.defl[t] = 0;
+                bool rotated = false;
+                if (prev >= 0 && fabs(dt - dp) * fabs(zt * zp) <= tol * (zp * zp + zt * zt)) {
+                    const double tt = hyp(zp, zt);
+                    const double c = zt / tt, sn = -zp / tt;
+                    const double dpn = dp * c * c + dt * sn * sn;
+                    const double dtn = dp * sn * sn + dt * c * c;
                     zs[t] = tt;
                     zs[prev] = 0.0;
-                    const double dp = ds[prev] * c * c + ds[t] * sn * sn;
-                    const double dt = ds[prev] * sn * sn + ds[t] * c * c;
-                    ds[prev] = dp;
-                    ds[t] = dt;
+                    ds[prev] = dpn;
+                    ds[t] = dtn;
                     S.rj[nrot] = prev;
                     S.ri[nrot] = t;
                     S.rc[nrot] = c;
                     S.rs[nrot] = sn;
                     ++nrot;
                     S.defl[prev] = 1;
+                    zt = tt;
+                    dt = dtn;
+                    rotated = true;
                 }
+                if (prev >= 0 && !rotated) S.tmp[k++] = prev;  // prev is final
+                prev = t;
+                zp = zt;
+                dp = dt;
             }
-            prev = t;
         }
-        for (int t = 0; t < m; ++t)
-            if (!S.defl[t]) S.tmp[k++] = t;
+        if (prev >= 0) S.tmp[k++] = prev;
         ctl[0] = k;
         ctl[1] = nrot;
     }
