@@ -266,6 +266,30 @@ constexpr int DC_MAX = 512;
 constexpr int DC_LEAF = 16;
 constexpr int DC_ITMAX = 100;  // root-finder steps per root (they end at the resolution, typically after 3-8)
 
+// Product over aligned groups of G lanes (G a power of two, 1 <= G <= 64), the
+// same bits on every lane of a group (as group_sum); all lanes active
+template <int G>
+__device__ __forceinline__ double group_prod(double v) {
+    if (G >= 2) v *= dpp_f64<DPP_XOR1>(v);
+    if (G >= 4) v *= dpp_f64<DPP_XOR2>(v);
+    if (G >= 8) v *= dpp_f64<DPP_HALF_MIRROR>(v);
+    if (G >= 16) v *= dpp_f64<DPP_MIRROR>(v);
+    if (G == 32) v *= __shfl_xor(v, 16, 64);
+    if (G == 64) v = (readlane_f64(v, 0) * readlane_f64(v, 16)) * (readlane_f64(v, 32) * readlane_f64(v, 48));
+    return v;
+}
+__device__ __forceinline__ double group_prod(double v, int G) {
+    switch (G) {
+    case 1: return v;
+    case 2: return group_prod<2>(v);
+    case 4: return group_prod<4>(v);
+    case 8: return group_prod<8>(v);
+    case 16: return group_prod<16>(v);
+    case 32: return group_prod<32>(v);
+    default: return group_prod<64>(v);
+    }
+}
+
 // LDS writes of a wavefront's lanes are visible to its other lanes after it
 __device__ __forceinline__ void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -599,23 +623,30 @@ __device__ void dc_merge(int n, int lo, int mid, int hi, double rho, double *sd,
     }
     __syncthreads();
     // weights recomputed from the roots (their signs kept), then the norms of
-    // the eigenvectors zhat_i / (delta_i - lambda_j)
-    for (int i = tid; i < k; i += TRI_TPB) {
-        double prod = ((dl[S.org[i]] - dl[i]) + S.tau[i]) / rh;
-        for (int j = 0; j < k; ++j)
+    // the eigenvectors zhat_i / (delta_i - lambda_j); G lanes per weight (per
+    // norm) split the product (the sum) over the poles, as for the roots
+    if (64 * wv < G * k) {
+        const int g = lane & (G - 1), ir = tid / G, i = min(ir, k - 1);
+        double prod = 1.0;
+        for (int j = g; j < k; j += G)
             if (j != i) prod *= ((dl[S.org[j]] - dl[i]) + S.tau[j]) * rcpd(dl[j] - dl[i]);
-        S.zhat[i] = copysign(sqrt(fmax(prod, 0.0)), zw[i]);
+        prod = group_prod(prod, G) * (((dl[S.org[i]] - dl[i]) + S.tau[i]) / rh);
+        if (ir < k && g == 0) S.zhat[i] = copysign(sqrt(fmax(prod, 0.0)), zw[i]);
     }
     __syncthreads();
-    for (int j = tid; j < k; j += TRI_TPB) {
+    if (64 * wv < G * k) {
+        const int g = lane & (G - 1), jr = tid / G, j = min(jr, k - 1);
         const double dj = dl[S.org[j]], tj = S.tau[j];
         double q = 0.0;
-        for (int i = 0; i < k; ++i) {
+        for (int i = g; i < k; i += G) {
             const double x = S.zhat[i] * rcpd((dl[i] - dj) - tj);
             q += x * x;
         }
-        S.invn[j] = 1.0 / sqrt(q);
-        S.lamn[j] = dj + tj;
+        q = group_sum(q, G);
+        if (jr < k && g == 0) {
+            S.invn[j] = 1.0 / sqrt(q);
+            S.lamn[j] = dj + tj;
+        }
     }
     __syncthreads();
     // the deflation rotations on the columns of the block (in pole order)
