@@ -415,7 +415,7 @@ struct DcScratch {
 
 // Merge of the solved halves [lo, mid) and [mid, hi) coupled by rho.  Zt:
 // column-major n x n eigenvectors of T (rows and columns of the block only).
-__device__ void dc_merge(int n, int lo, int mid, int hi, double rho, double *sd, double *Zt, const DcScratch &S,
+__device__ __forceinline__ void dc_merge(int n, int lo, int mid, int hi, double rho, double *sd, double *Zt, const DcScratch &S,
                          double *red, int *ctl) {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const size_t N = (size_t)n;
@@ -732,7 +732,7 @@ __device__ void dc_merge(int n, int lo, int mid, int hi, double rho, double *sd,
 // scratch (u); Q: the Householder product (a, column-major), replaced by the
 // eigenvectors of the block.  ctl[2]: set to 1 if a leaf did not converge;
 // ctl[3]: leaf QL iterations + merges.
-__device__ void dc_solve(int n, double *sd, double *se, double *pool, int *ipool, double *Zt, double *Q,
+__device__ __forceinline__ void dc_solve(int n, double *sd, double *se, double *pool, int *ipool, double *Zt, double *Q,
                          double *red, int *ctl) {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const size_t N = (size_t)n;
