@@ -246,6 +246,11 @@ constexpr int TRI_UB = 16;  // rows of a column read per batch of loads (Househo
 constexpr int QL_B = 8;     // rotations applied per batch of loads (QL; the next batch is fetched ahead)
 constexpr int Q_REG = 8;    // column entries per lane kept in registers (Q formation, L <= 512)
 constexpr int QB = 16;      // factors per block of the Q formation (their vectors: QB x 512 doubles of LDS)
+constexpr int HH_ROWS = 36;     // rows of the block per thread (Householder reduction in registers, orders 129..)
+constexpr int HH_REG_DIM = 180; // largest order reduced in registers (five groups of HH_ROWS rows)
+constexpr int HH_VEC = 256;     // LDS vectors of that reduction: past the order up to the last group's end
+static_assert(TRI_WAVES == 16 && 5 * HH_ROWS >= HH_REG_DIM && 8 * 16 >= 128 && 16 * 4 >= 64, "register rows");
+static_assert(HH_REG_DIM + HH_ROWS <= HH_VEC && HH_REG_DIM <= 192, "register reduction vectors");
 
 // ------------------------------------------------------------------ divide and conquer
 // The symmetric tridiagonal eigenproblem of orders up to DC_MAX by Cuppen's
@@ -868,6 +873,179 @@ __device__ __forceinline__ void dc_solve(int n, double *sd, double *se, double *
     __syncthreads();
 }
 
+// Householder reduction with the block in registers, R rows per thread: the
+// wavefront wv keeps the entries (j, c) of the rows j0 <= j < j0 + R of its
+// group g = wv / CB and of the column c = 64 (wv % CB) + lane, so that only
+// vectors pass through LDS (zero past the order, so that rows past it add
+// nothing).  Step k: column k (left in scol by the previous step's pass, with
+// step k - 1's update still to apply: v', w' in sv, sy) gives the diagonal
+// and the reflector (v into sn, also stored in row k beyond k + 1 for the Q
+// formation); then rows and columns k + 1.. take step k - 1's update and are
+// multiplied by v in one pass, which also leaves column k + 1 in scol; the
+// groups' partial products meet in LDS (spart) as p = t A v, and w = p - K v
+// is the next step's pending update.  Both products of an update are rounded
+// before their sum (no contraction in this function), so A(i, j) and A(j, i)
+// stay bit-identical.
+template <int R>
+__device__ __forceinline__ void hh_reduce(int d, const double *Z, double *A, double *wb, double *sx, double *sy,
+                                          double *sz, double *scol, double *spart, double *red, double *red2) {
+#pragma clang fp contract(off)
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // (so that the rows, and their tests, are scalar)
+    const size_t D = (size_t)d;
+    const int CB = (d + 63) >> 6, G = (d + R - 1) / R;
+    const int g = wv / CB, cb = wv % CB, c = cb * 64 + lane;
+    const bool act = g < G;  // (uniform: the wavefronts past the groups only join the reductions)
+    const int j0 = g * R;
+    const int jv = ((tid >> 6) / CB) * R;  // j0 in a vector register: LDS rows at immediate offsets from it
+    double a[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) a[q] = (act && j0 + q < d && c < d) ? Z[(size_t)(j0 + q) * D + c] : 0.0;
+    for (int j = tid; j < HH_VEC; j += TRI_TPB) {
+        sx[j] = 0.0;  // no update pending before step 0
+        sy[j] = 0.0;
+        sz[j] = 0.0;
+        scol[j] = j < d ? Z[(size_t)j * D] : 0.0;  // column 0
+    }
+    __syncthreads();
+    double *sv = sx, *sn = sz;
+    for (int k = 0; k + 2 < d; ++k) {
+        // column k after step k - 1's update: the diagonal, and x into sn
+        double part = 0.0, lead = 0.0;
+        bool own = false;
+        {
+            const double vk = sv[k], wk = sy[k];
+            for (int j = k + tid; j < d; j += TRI_TPB) {
+                const double x = scol[j] - (sv[j] * wk + sy[j] * vk);
+                if (j == k) {
+                    wb[k] = x;
+                } else {
+                    sn[j] = x;
+                    if (j == k + 1) {
+                        own = true;
+                        lead = x;
+                    } else {
+                        part += x * x;
+                    }
+                }
+            }
+        }
+        double alpha;  // x(0), handed over by its thread (sn[k + 1] is rewritten below)
+        const double sigma = block_sum1(part, own, lead, red2, &alpha);
+        double t = 0.0;
+        if (sigma == 0.0) {  // the column is already reduced: t = 0
+            for (int j = k + 1 + tid; j < d; j += TRI_TPB) {
+                sn[j] = j == k + 1 ? 1.0 : 0.0;
+                if (j > k + 1) A[k * D + j] = 0.0;
+            }
+            if (tid == 0) {
+                A[(k + 1) * D + k] = alpha;
+                A[(k + 2) * D + k] = 0.0;
+            }
+        } else {
+            const double beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
+            t = (beta - alpha) / beta;
+            const double scale = 1.0 / (alpha - beta);
+            for (int j = k + 1 + tid; j < d; j += TRI_TPB) {
+                const double vj = j == k + 1 ? 1.0 : sn[j] * scale;
+                sn[j] = vj;
+                if (j > k + 1) A[k * D + j] = vj;
+            }
+            if (tid == 0) {
+                A[(k + 1) * D + k] = beta;
+                A[(k + 2) * D + k] = t;
+            }
+        }
+        __syncthreads();
+        // rows and columns k + 1..: step k - 1's update, and the product with v;
+        // column k + 1 into scol
+        double acc = 0.0;
+        if (act && cb * 64 + 63 > k) {  // (uniform: a column block left of k + 1 is finished)
+            const double vc = sv[c], wc = sy[c];
+            const double *pv = sv + jv, *pw = sy + jv, *pn = sn + jv;
+            double *pc = scol + jv;
+            const bool next = c == k + 1;
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                if (j0 + q > k) {  // (uniform)
+                    const double x = a[q] - (pv[q] * wc + pw[q] * vc);
+                    a[q] = x;
+                    acc += x * pn[q];
+                    if (next) pc[q] = x;
+                }
+            }
+        }
+        spart[tid] = acc;
+        __syncthreads();
+        // p = t A v (column tid), K = t p.v / 2, w = p - K v
+        const bool mine = tid > k && tid < d;
+        double pc = 0.0, pv = 0.0;
+        if (mine) {
+            double sum = 0.0;
+            for (int gg = 0; gg < G; ++gg) sum += spart[(gg * CB + (tid >> 6)) * 64 + (tid & 63)];
+            pc = t * sum;
+            pv = pc * sn[tid];
+        }
+        double unused;
+        const double K = 0.5 * t * block_sum1(pv, false, 0.0, red, &unused);
+        if (mine) sy[tid] = pc - K * sn[tid];
+        double *tmp = sv;  // v of this step is the next step's pending one
+        sv = sn;
+        sn = tmp;
+        __syncthreads();
+    }
+    // the trailing 2 x 2 after the last step's update: column d - 2 from scol,
+    // the entry (d - 1, d - 1) from its thread
+    const int k = d - 2;
+    if (tid < 2) {
+        const int j = k + tid;
+        const double x = scol[j] - (sv[j] * sy[k] + sy[j] * sv[k]);
+        if (tid == 0)
+            wb[k] = x;
+        else
+            A[(k + 1) * D + k] = x;
+    }
+    if (act && c == d - 1) {
+        double ad = 0.0;
+        bool has = false;
+#pragma unroll
+        for (int q = 0; q < R; ++q)
+            if (j0 + q == d - 1) {
+                ad = a[q];
+                has = true;
+            }
+        if (has) wb[d - 1] = ad - (sv[d - 1] * sy[d - 1] + sy[d - 1] * sv[d - 1]);
+    }
+}
+
+// Householder reduction of the blocks of orders EIG_LDS_DIM + 1 .. HH_REG_DIM to
+// tridiagonal form T = Q^T A Q (Q = H_0 ... H_{d-3}, H_k = I - t_k v_k v_k^T on
+// indices k + 1.., v_k(k + 1) = 1), one workgroup per block, the block held in
+// registers.  Output for k_eigh_tri: the diagonal of T in w (block b's slice),
+// T(k + 1, k) at u(k + 1, k), t_k at u(k + 2, k), and v_k(j) at u(k, j) for
+// j >= k + 2 (u row-major, block b at off[b]); a is only read.
+__global__ __launch_bounds__(TRI_TPB) void k_eigh_hh(int nblk, const int64_t *__restrict__ off,
+                                                     const int32_t *__restrict__ dim, const int64_t *__restrict__ woff,
+                                                     const double *__restrict__ a, double *__restrict__ w,
+                                                     double *__restrict__ u) {
+    __shared__ double sx[HH_VEC], sy[HH_VEC], sz[HH_VEC], scol[HH_VEC];
+    __shared__ double spart[TRI_TPB];
+    __shared__ double red[TRI_WAVES + 1], red2[TRI_WAVES + 1];
+    const int b = blockIdx.x;
+    if (b >= nblk) return;
+    const int d = dim[b];
+    if (d <= EIG_LDS_DIM || d > HH_REG_DIM) return;
+    const double *Z = a + off[b];
+    double *A = u + off[b], *wb = w + woff[b];
+    // rows per thread: 4, 16 or 36 for one, two or three column blocks of 64
+    if (d <= 64)
+        hh_reduce<4>(d, Z, A, wb, sx, sy, sz, scol, spart, red, red2);
+    else if (d <= 128)
+        hh_reduce<16>(d, Z, A, wb, sx, sy, sz, scol, spart, red, red2);
+    else
+        hh_reduce<HH_ROWS>(d, Z, A, wb, sx, sy, sz, scol, spart, red, red2);
+}
+
 __global__ __launch_bounds__(TRI_TPB) void k_eigh_tri(int nblk, const int64_t *__restrict__ off,
                                                       const int32_t *__restrict__ dim, const int64_t *__restrict__ woff,
                                                       double *__restrict__ a, double *__restrict__ w,
@@ -893,159 +1071,171 @@ __global__ __launch_bounds__(TRI_TPB) void k_eigh_tri(int nblk, const int64_t *_
     const size_t D = (size_t)d;
     double *A = u + off[b];  // working matrix (row-major, both triangles), then Householder vectors
     double *Z = a + off[b];  // Q, then the eigenvectors; column-major: Z[c * d + r] = Q(r, c)
-    for (int r = wv; r < d; r += TRI_WAVES)
-        for (int c = lane; c < d; c += 64) A[r * D + c] = Z[r * D + c];
-    __syncthreads();
+    if (d <= HH_REG_DIM) {
+        // reduced by k_eigh_hh: the diagonal in w, the off-diagonal and the
+        // factors t below the diagonal of u, the reflectors in its rows
+        const double *wb = w + woff[b];
+        for (int j = tid; j < d; j += TRI_TPB) {
+            sd[j] = wb[j];
+            se[j] = j + 1 < d ? A[(j + 1) * D + j] : 0.0;
+            if (j + 2 < d) sq[j] = A[(j + 2) * D + j];
+        }
+        __syncthreads();
+    } else {
+        for (int r = wv; r < d; r += TRI_WAVES)
+            for (int c = lane; c < d; c += 64) A[r * D + c] = Z[r * D + c];
+        __syncthreads();
 
-    // ---- Householder reduction: step k zeroes A(k, k+2..) and A(k+2.., k) with
-    // H = I - t v v^T acting on indices k+1.., v(0) = 1 (stored in row k beyond it).
-    // A stays exactly symmetric, so column i of the trailing block is its row i:
-    // each thread owns columns (coalesced across the threads of a row).  Step k
-    // needs p = t A22 v, w = p - K v and A22 -= v w^T + w v^T; the update of
-    // step k and the product of step k + 1 are one pass over the block: row
-    // k + 1 is updated first (it yields the next reflector), then every other
-    // element is updated, stored and multiplied by the next v at once.
-    // sv: v of the current step, sn: v of the next one, sy: p, then w.
-    double *sv = sx, *sn = sz;
-    double t = 0.0;  // the current step's factor
-    {
-        // step 0's reflector from row 0 and its product p = t A22 v
-        const int L = d - 1;
-        double part = 0.0;
-        for (int j = tid; j < L; j += TRI_TPB) {
-            const double x = A[1 + j];
-            sv[j] = x;
-            if (j) part += x * x;
-        }
-        double alpha;
-        const double sigma = block_sum_lead(part, tid == 0 ? A[1] : 0.0, red, &alpha);
-        if (sigma == 0.0) {
-            if (tid == 0) {
-                sd[0] = A[0];
-                se[0] = alpha;
-                sq[0] = 0.0;
+        // ---- Householder reduction: step k zeroes A(k, k+2..) and A(k+2.., k) with
+        // H = I - t v v^T acting on indices k+1.., v(0) = 1 (stored in row k beyond it).
+        // A stays exactly symmetric, so column i of the trailing block is its row i:
+        // each thread owns columns (coalesced across the threads of a row).  Step k
+        // needs p = t A22 v, w = p - K v and A22 -= v w^T + w v^T; the update of
+        // step k and the product of step k + 1 are one pass over the block: row
+        // k + 1 is updated first (it yields the next reflector), then every other
+        // element is updated, stored and multiplied by the next v at once.
+        // sv: v of the current step, sn: v of the next one, sy: p, then w.
+        double *sv = sx, *sn = sz;
+        double t = 0.0;  // the current step's factor
+        {
+            // step 0's reflector from row 0 and its product p = t A22 v
+            const int L = d - 1;
+            double part = 0.0;
+            for (int j = tid; j < L; j += TRI_TPB) {
+                const double x = A[1 + j];
+                sv[j] = x;
+                if (j) part += x * x;
             }
-            for (int j = tid; j < L; j += TRI_TPB) sv[j] = j ? 0.0 : 1.0;  // with t = 0: no reflection
-        } else {
-            const double beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
-            t = (beta - alpha) / beta;
-            const double scale = 1.0 / (alpha - beta);
-            for (int j = tid; j < L; j += TRI_TPB) sv[j] = j ? sv[j] * scale : 1.0;
-            if (tid == 0) {
-                sd[0] = A[0];
-                se[0] = beta;
-                sq[0] = t;
-            }
-        }
-        __syncthreads();
-        const int G = max(1, min(TRI_TPB / L, 32)), R = (L + G - 1) / G;
-        for (int q = tid; q < G * L; q += TRI_TPB) {
-            const int i = q % L, g = q / L;
-            const int j0 = g * R, j1 = min(L, j0 + R);
-            const double *col = A + D + 1 + i;
-            double acc = 0.0;
-            for (int jb = j0; jb < j1; jb += TRI_UB) {
-                double av[TRI_UB];
-#pragma unroll
-                for (int u = 0; u < TRI_UB; ++u) av[u] = col[min(jb + u, j1 - 1) * D];
-#pragma unroll
-                for (int u = 0; u < TRI_UB; ++u)
-                    if (jb + u < j1) acc += av[u] * sv[jb + u];
-            }
-            spart[q] = acc;
-        }
-        __syncthreads();
-    }
-    for (int k = 0; k + 2 < d; ++k) {
-        const int L = d - k - 1, G = max(1, min(TRI_TPB / L, 32));
-        // p and w of step k (the groups' partial products meet in LDS)
-        double pv = 0.0;
-        for (int i = tid; i < L; i += TRI_TPB) {
-            double acc = 0.0;
-            for (int g = 0; g < G; ++g) acc += spart[g * L + i];
-            const double pi = t * acc;
-            sy[i] = pi;
-            pv += pi * sv[i];
-        }
-        double unused;
-        const double K = 0.5 * t * block_sum1(pv, false, 0.0, red, &unused);
-        for (int j = tid; j < L; j += TRI_TPB) sy[j] -= K * sv[j];  // w
-        __syncthreads();
-        for (int j = 1 + tid; j < L; j += TRI_TPB) A[k * D + k + 1 + j] = sv[j];
-        // row k + 1 after step k's update (both products rounded before the sum,
-        // so A(i, j) and A(j, i) stay bit-identical): its diagonal, and the
-        // vector x of step k + 1 into sn
-        const bool next = k + 3 < d;
-        double part = 0.0, diag = 0.0, lead = 0.0;
-        for (int i = tid; i < L; i += TRI_TPB) {
-            const double val = A[(k + 1) * D + k + 1 + i] - __dadd_rn(__dmul_rn(sv[0], sy[i]), __dmul_rn(sy[0], sv[i]));
-            if (i == 0) diag = val;
-            if (i == 1) lead = val;
-            if (i >= 1) sn[i - 1] = val;
-            if (i >= 2) part += val * val;
-        }
-        double alpha;  // x(0), handed over by the thread that formed it (sn[0] is rescaled below)
-        const double sigma = block_sum1(part, tid == 1, lead, red2, &alpha);
-        double tn = 0.0;
-        if (!next) {  // the trailing 2 x 2: no reflector
-            if (tid == 0) {
-                sd[k + 1] = diag;
-                se[k + 1] = alpha;
-            }
-        } else if (sigma == 0.0) {  // the column is already reduced
-            if (tid == 0) {
-                sd[k + 1] = diag;
-                se[k + 1] = alpha;
-                sq[k + 1] = 0.0;
-            }
-            for (int j = tid; j < L - 1; j += TRI_TPB) sn[j] = j ? 0.0 : 1.0;  // with t = 0: no reflection
-        } else {
-            const double beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
-            tn = (beta - alpha) / beta;
-            const double scale = 1.0 / (alpha - beta);
-            for (int j = tid; j < L - 1; j += TRI_TPB) sn[j] = j ? sn[j] * scale : 1.0;
-            if (tid == 0) {
-                sd[k + 1] = diag;
-                se[k + 1] = beta;
-                sq[k + 1] = tn;
-            }
-        }
-        __syncthreads();
-        // the rest of A22 (indices k + 2..): updated, stored, and (with a next
-        // step) summed into that step's p; thread (i, g) on the rows of group g
-        // of column i, loads in batches
-        const int L1 = L - 1, G1 = max(1, min(TRI_TPB / L1, 32)), R1 = (L1 + G1 - 1) / G1;
-        for (int q = tid; q < G1 * L1; q += TRI_TPB) {
-            const int i = q % L1, g = q / L1;
-            const int j0 = g * R1, j1 = min(L1, j0 + R1);
-            double *col = A + (k + 2) * D + k + 2 + i;
-            const double vi = sv[i + 1], wi = sy[i + 1];
-            double acc = 0.0;
-            for (int jb = j0; jb < j1; jb += TRI_UB) {
-                double av[TRI_UB];
-#pragma unroll
-                for (int u = 0; u < TRI_UB; ++u) av[u] = col[min(jb + u, j1 - 1) * D];
-#pragma unroll
-                for (int u = 0; u < TRI_UB; ++u) {
-                    const int j = jb + u;
-                    if (j < j1) {
-                        const double val = av[u] - __dadd_rn(__dmul_rn(sv[j + 1], wi), __dmul_rn(sy[j + 1], vi));
-                        col[j * D] = val;
-                        acc += val * sn[j];
-                    }
+            double alpha;
+            const double sigma = block_sum_lead(part, tid == 0 ? A[1] : 0.0, red, &alpha);
+            if (sigma == 0.0) {
+                if (tid == 0) {
+                    sd[0] = A[0];
+                    se[0] = alpha;
+                    sq[0] = 0.0;
+                }
+                for (int j = tid; j < L; j += TRI_TPB) sv[j] = j ? 0.0 : 1.0;  // with t = 0: no reflection
+            } else {
+                const double beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
+                t = (beta - alpha) / beta;
+                const double scale = 1.0 / (alpha - beta);
+                for (int j = tid; j < L; j += TRI_TPB) sv[j] = j ? sv[j] * scale : 1.0;
+                if (tid == 0) {
+                    sd[0] = A[0];
+                    se[0] = beta;
+                    sq[0] = t;
                 }
             }
-            if (next) spart[q] = acc;
+            __syncthreads();
+            const int G = max(1, min(TRI_TPB / L, 32)), R = (L + G - 1) / G;
+            for (int q = tid; q < G * L; q += TRI_TPB) {
+                const int i = q % L, g = q / L;
+                const int j0 = g * R, j1 = min(L, j0 + R);
+                const double *col = A + D + 1 + i;
+                double acc = 0.0;
+                for (int jb = j0; jb < j1; jb += TRI_UB) {
+                    double av[TRI_UB];
+    #pragma unroll
+                    for (int u = 0; u < TRI_UB; ++u) av[u] = col[min(jb + u, j1 - 1) * D];
+    #pragma unroll
+                    for (int u = 0; u < TRI_UB; ++u)
+                        if (jb + u < j1) acc += av[u] * sv[jb + u];
+                }
+                spart[q] = acc;
+            }
+            __syncthreads();
         }
-        __syncthreads();
-        double *tmp = sv;  // the next step's v becomes the current one
-        sv = sn;
-        sn = tmp;
-        t = tn;
-    }
-    if (tid == 0) {
-        sd[d - 1] = A[(d - 1) * D + d - 1];
-        se[d - 1] = 0.0;
+        for (int k = 0; k + 2 < d; ++k) {
+            const int L = d - k - 1, G = max(1, min(TRI_TPB / L, 32));
+            // p and w of step k (the groups' partial products meet in LDS)
+            double pv = 0.0;
+            for (int i = tid; i < L; i += TRI_TPB) {
+                double acc = 0.0;
+                for (int g = 0; g < G; ++g) acc += spart[g * L + i];
+                const double pi = t * acc;
+                sy[i] = pi;
+                pv += pi * sv[i];
+            }
+            double unused;
+            const double K = 0.5 * t * block_sum1(pv, false, 0.0, red, &unused);
+            for (int j = tid; j < L; j += TRI_TPB) sy[j] -= K * sv[j];  // w
+            __syncthreads();
+            for (int j = 1 + tid; j < L; j += TRI_TPB) A[k * D + k + 1 + j] = sv[j];
+            // row k + 1 after step k's update (both products rounded before the sum,
+            // so A(i, j) and A(j, i) stay bit-identical): its diagonal, and the
+            // vector x of step k + 1 into sn
+            const bool next = k + 3 < d;
+            double part = 0.0, diag = 0.0, lead = 0.0;
+            for (int i = tid; i < L; i += TRI_TPB) {
+                const double val = A[(k + 1) * D + k + 1 + i] - __dadd_rn(__dmul_rn(sv[0], sy[i]), __dmul_rn(sy[0], sv[i]));
+                if (i == 0) diag = val;
+                if (i == 1) lead = val;
+                if (i >= 1) sn[i - 1] = val;
+                if (i >= 2) part += val * val;
+            }
+            double alpha;  // x(0), handed over by the thread that formed it (sn[0] is rescaled below)
+            const double sigma = block_sum1(part, tid == 1, lead, red2, &alpha);
+            double tn = 0.0;
+            if (!next) {  // the trailing 2 x 2: no reflector
+                if (tid == 0) {
+                    sd[k + 1] = diag;
+                    se[k + 1] = alpha;
+                }
+            } else if (sigma == 0.0) {  // the column is already reduced
+                if (tid == 0) {
+                    sd[k + 1] = diag;
+                    se[k + 1] = alpha;
+                    sq[k + 1] = 0.0;
+                }
+                for (int j = tid; j < L - 1; j += TRI_TPB) sn[j] = j ? 0.0 : 1.0;  // with t = 0: no reflection
+            } else {
+                const double beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
+                tn = (beta - alpha) / beta;
+                const double scale = 1.0 / (alpha - beta);
+                for (int j = tid; j < L - 1; j += TRI_TPB) sn[j] = j ? sn[j] * scale : 1.0;
+                if (tid == 0) {
+                    sd[k + 1] = diag;
+                    se[k + 1] = beta;
+                    sq[k + 1] = tn;
+                }
+            }
+            __syncthreads();
+            // the rest of A22 (indices k + 2..): updated, stored, and (with a next
+            // step) summed into that step's p; thread (i, g) on the rows of group g
+            // of column i, loads in batches
+            const int L1 = L - 1, G1 = max(1, min(TRI_TPB / L1, 32)), R1 = (L1 + G1 - 1) / G1;
+            for (int q = tid; q < G1 * L1; q += TRI_TPB) {
+                const int i = q % L1, g = q / L1;
+                const int j0 = g * R1, j1 = min(L1, j0 + R1);
+                double *col = A + (k + 2) * D + k + 2 + i;
+                const double vi = sv[i + 1], wi = sy[i + 1];
+                double acc = 0.0;
+                for (int jb = j0; jb < j1; jb += TRI_UB) {
+                    double av[TRI_UB];
+    #pragma unroll
+                    for (int u = 0; u < TRI_UB; ++u) av[u] = col[min(jb + u, j1 - 1) * D];
+    #pragma unroll
+                    for (int u = 0; u < TRI_UB; ++u) {
+                        const int j = jb + u;
+                        if (j < j1) {
+                            const double val = av[u] - __dadd_rn(__dmul_rn(sv[j + 1], wi), __dmul_rn(sy[j + 1], vi));
+                            col[j * D] = val;
+                            acc += val * sn[j];
+                        }
+                    }
+                }
+                if (next) spart[q] = acc;
+            }
+            __syncthreads();
+            double *tmp = sv;  // the next step's v becomes the current one
+            sv = sn;
+            sn = tmp;
+            t = tn;
+        }
+        if (tid == 0) {
+            sd[d - 1] = A[(d - 1) * D + d - 1];
+            se[d - 1] = 0.0;
+        }
     }
     // ---- Q = H_0 H_1 ... H_{d-3}, accumulated from the last factor; H_k Q only
     // changes the trailing block from index k + 1: y_c = v^T Q(:, c), then
@@ -1511,6 +1701,7 @@ dmrg_status dmrg_eigh_blocks(int32_t nblk, const int64_t *off, const int32_t *di
     if (a == u || a == w || u == w) return set_error(DMRG_E_INVALID_ARG, "a, w and u must not overlap");
     hipStream_t s = (hipStream_t)stream;
     hipLaunchKernelGGL(k_eigh_jacobi, dim3(nblk), dim3(EIG_TPB_SMALL), 0, s, nblk, off, dim, woff, a, w, u, info);
+    hipLaunchKernelGGL(k_eigh_hh, dim3(nblk), dim3(TRI_TPB), 0, s, nblk, off, dim, woff, a, w, u);
     hipLaunchKernelGGL(k_eigh_tri, dim3(nblk), dim3(TRI_TPB), 0, s, nblk, off, dim, woff, a, w, u, info);
     DMRG_HIP(hipGetLastError());
     return DMRG_OK;
