@@ -878,18 +878,17 @@ __device__ __forceinline__ void dc_solve(int n, double *sd, double *se, double *
 // group g = wv / CB and of the column c = 64 (wv % CB) + lane, so that only
 // vectors pass through LDS (zero past the order, so that rows past it add
 // nothing).  Step k: column k (left in scol by the previous step's pass, with
-// step k - 1's update still to apply: v', w' in sv, sy) gives the diagonal
-// and the reflector (v into sn, also stored in row k beyond k + 1 for the Q
-// formation); then rows and columns k + 1.. take step k - 1's update and are
-// multiplied by v in one pass, which also leaves column k + 1 in scol; the
-// groups' partial products meet in LDS (spart) as p = t A v, and w = p - K v
-// is the next step's pending update.  Both products of an update are rounded
-// before their sum (no contraction in this function), so A(i, j) and A(j, i)
-// stay bit-identical.
+// step k - 1's update still to apply: (v', w') pairs in cur) gives the
+// diagonal and the reflector (v into nxt, also stored in row k beyond k + 1
+// for the Q formation); then rows and columns k + 1.. take step k - 1's
+// update and are multiplied by v in one pass, which also leaves column k + 1
+// in scol; the groups' partial products meet in LDS (spart) as p = t A v, and
+// w = p - K v goes next to v in nxt, the next step's pending update.  Each
+// entry is updated by its own thread (A(i, j) and A(j, i) may differ by
+// roundings; every step reads the block by columns).
 template <int R>
-__device__ __forceinline__ void hh_reduce(int d, const double *Z, double *A, double *wb, double *sx, double *sy,
-                                          double *sz, double *scol, double *spart, double *red, double *red2) {
-#pragma clang fp contract(off)
+__device__ __forceinline__ void hh_reduce(int d, const double *Z, double *A, double *wb, double2 *P0, double2 *P1,
+                                          double *scol, double *spart, double *red, double *red2) {
     const int tid = threadIdx.x, lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // (so that the rows, and their tests, are scalar)
     const size_t D = (size_t)d;
@@ -902,25 +901,25 @@ __device__ __forceinline__ void hh_reduce(int d, const double *Z, double *A, dou
 #pragma unroll
     for (int q = 0; q < R; ++q) a[q] = (act && j0 + q < d && c < d) ? Z[(size_t)(j0 + q) * D + c] : 0.0;
     for (int j = tid; j < HH_VEC; j += TRI_TPB) {
-        sx[j] = 0.0;  // no update pending before step 0
-        sy[j] = 0.0;
-        sz[j] = 0.0;
+        P0[j] = make_double2(0.0, 0.0);  // no update pending before step 0
+        P1[j] = make_double2(0.0, 0.0);
         scol[j] = j < d ? Z[(size_t)j * D] : 0.0;  // column 0
     }
     __syncthreads();
-    double *sv = sx, *sn = sz;
+    double2 *cur = P0, *nxt = P1;
     for (int k = 0; k + 2 < d; ++k) {
-        // column k after step k - 1's update: the diagonal, and x into sn
+        // column k after step k - 1's update: the diagonal, and x into nxt
         double part = 0.0, lead = 0.0;
         bool own = false;
         {
-            const double vk = sv[k], wk = sy[k];
+            const double2 pk = cur[k];
             for (int j = k + tid; j < d; j += TRI_TPB) {
-                const double x = scol[j] - (sv[j] * wk + sy[j] * vk);
+                const double2 pj = cur[j];
+                const double x = fma(-pj.x, pk.y, fma(-pj.y, pk.x, scol[j]));
                 if (j == k) {
                     wb[k] = x;
                 } else {
-                    sn[j] = x;
+                    nxt[j].x = x;
                     if (j == k + 1) {
                         own = true;
                         lead = x;
@@ -930,12 +929,12 @@ __device__ __forceinline__ void hh_reduce(int d, const double *Z, double *A, dou
                 }
             }
         }
-        double alpha;  // x(0), handed over by its thread (sn[k + 1] is rewritten below)
+        double alpha;  // x(0), handed over by its thread (nxt[k + 1] is rewritten below)
         const double sigma = block_sum1(part, own, lead, red2, &alpha);
         double t = 0.0;
         if (sigma == 0.0) {  // the column is already reduced: t = 0
             for (int j = k + 1 + tid; j < d; j += TRI_TPB) {
-                sn[j] = j == k + 1 ? 1.0 : 0.0;
+                nxt[j].x = j == k + 1 ? 1.0 : 0.0;
                 if (j > k + 1) A[k * D + j] = 0.0;
             }
             if (tid == 0) {
@@ -947,8 +946,8 @@ __device__ __forceinline__ void hh_reduce(int d, const double *Z, double *A, dou
             t = (beta - alpha) / beta;
             const double scale = 1.0 / (alpha - beta);
             for (int j = k + 1 + tid; j < d; j += TRI_TPB) {
-                const double vj = j == k + 1 ? 1.0 : sn[j] * scale;
-                sn[j] = vj;
+                const double vj = j == k + 1 ? 1.0 : nxt[j].x * scale;
+                nxt[j].x = vj;
                 if (j > k + 1) A[k * D + j] = vj;
             }
             if (tid == 0) {
@@ -961,17 +960,18 @@ __device__ __forceinline__ void hh_reduce(int d, const double *Z, double *A, dou
         // column k + 1 into scol
         double acc = 0.0;
         if (act && cb * 64 + 63 > k) {  // (uniform: a column block left of k + 1 is finished)
-            const double vc = sv[c], wc = sy[c];
-            const double *pv = sv + jv, *pw = sy + jv, *pn = sn + jv;
-            double *pc = scol + jv;
+            const double2 pc = cur[c];
+            const double2 *pr = cur + jv, *pn = nxt + jv;
+            double *sc = scol + jv;
             const bool next = c == k + 1;
 #pragma unroll
             for (int q = 0; q < R; ++q) {
                 if (j0 + q > k) {  // (uniform)
-                    const double x = a[q] - (pv[q] * wc + pw[q] * vc);
+                    const double2 pj = pr[q];
+                    const double x = fma(-pj.x, pc.y, fma(-pj.y, pc.x, a[q]));
                     a[q] = x;
-                    acc += x * pn[q];
-                    if (next) pc[q] = x;
+                    acc = fma(x, pn[q].x, acc);
+                    if (next) sc[q] = x;
                 }
             }
         }
@@ -979,19 +979,20 @@ __device__ __forceinline__ void hh_reduce(int d, const double *Z, double *A, dou
         __syncthreads();
         // p = t A v (column tid), K = t p.v / 2, w = p - K v
         const bool mine = tid > k && tid < d;
-        double pc = 0.0, pv = 0.0;
+        double pc = 0.0, pv = 0.0, vt = 0.0;
         if (mine) {
             double sum = 0.0;
             for (int gg = 0; gg < G; ++gg) sum += spart[(gg * CB + (tid >> 6)) * 64 + (tid & 63)];
             pc = t * sum;
-            pv = pc * sn[tid];
+            vt = nxt[tid].x;
+            pv = pc * vt;
         }
         double unused;
         const double K = 0.5 * t * block_sum1(pv, false, 0.0, red, &unused);
-        if (mine) sy[tid] = pc - K * sn[tid];
-        double *tmp = sv;  // v of this step is the next step's pending one
-        sv = sn;
-        sn = tmp;
+        if (mine) nxt[tid].y = pc - K * vt;
+        double2 *tmp = cur;  // (v, w) of this step is the next step's pending update
+        cur = nxt;
+        nxt = tmp;
         __syncthreads();
     }
     // the trailing 2 x 2 after the last step's update: column d - 2 from scol,
@@ -999,7 +1000,8 @@ __device__ __forceinline__ void hh_reduce(int d, const double *Z, double *A, dou
     const int k = d - 2;
     if (tid < 2) {
         const int j = k + tid;
-        const double x = scol[j] - (sv[j] * sy[k] + sy[j] * sv[k]);
+        const double2 pk = cur[k], pj = cur[j];
+        const double x = fma(-pj.x, pk.y, fma(-pj.y, pk.x, scol[j]));
         if (tid == 0)
             wb[k] = x;
         else
@@ -1014,7 +1016,8 @@ __device__ __forceinline__ void hh_reduce(int d, const double *Z, double *A, dou
                 ad = a[q];
                 has = true;
             }
-        if (has) wb[d - 1] = ad - (sv[d - 1] * sy[d - 1] + sy[d - 1] * sv[d - 1]);
+        const double2 pd = cur[d - 1];
+        if (has) wb[d - 1] = fma(-pd.x, pd.y, fma(-pd.y, pd.x, ad));
     }
 }
 
@@ -1028,7 +1031,8 @@ __global__ __launch_bounds__(TRI_TPB) void k_eigh_hh(int nblk, const int64_t *__
                                                      const int32_t *__restrict__ dim, const int64_t *__restrict__ woff,
                                                      const double *__restrict__ a, double *__restrict__ w,
                                                      double *__restrict__ u) {
-    __shared__ double sx[HH_VEC], sy[HH_VEC], sz[HH_VEC], scol[HH_VEC];
+    __shared__ double2 P0[HH_VEC], P1[HH_VEC];  // (v, w) of two steps
+    __shared__ double scol[HH_VEC];
     __shared__ double spart[TRI_TPB];
     __shared__ double red[TRI_WAVES + 1], red2[TRI_WAVES + 1];
     const int b = blockIdx.x;
@@ -1039,11 +1043,11 @@ __global__ __launch_bounds__(TRI_TPB) void k_eigh_hh(int nblk, const int64_t *__
     double *A = u + off[b], *wb = w + woff[b];
     // rows per thread: 4, 16 or 36 for one, two or three column blocks of 64
     if (d <= 64)
-        hh_reduce<4>(d, Z, A, wb, sx, sy, sz, scol, spart, red, red2);
+        hh_reduce<4>(d, Z, A, wb, P0, P1, scol, spart, red, red2);
     else if (d <= 128)
-        hh_reduce<16>(d, Z, A, wb, sx, sy, sz, scol, spart, red, red2);
+        hh_reduce<16>(d, Z, A, wb, P0, P1, scol, spart, red, red2);
     else
-        hh_reduce<HH_ROWS>(d, Z, A, wb, sx, sy, sz, scol, spart, red, red2);
+        hh_reduce<HH_ROWS>(d, Z, A, wb, P0, P1, scol, spart, red, red2);
 }
 
 __global__ __launch_bounds__(TRI_TPB) void k_eigh_tri(int nblk, const int64_t *__restrict__ off,
