@@ -1092,8 +1092,10 @@ __global__ __launch_bounds__(TRI_TPB) void k_eigh_tri(int nblk, const int64_t *_
 
         // ---- Householder reduction: step k zeroes A(k, k+2..) and A(k+2.., k) with
         // H = I - t v v^T acting on indices k+1.., v(0) = 1 (stored in row k beyond it).
-        // A stays exactly symmetric, so column i of the trailing block is its row i:
-        // each thread owns columns (coalesced across the threads of a row).  Step k
+        // A stays symmetric up to roundings (the two products of an update may be
+        // fused differently for A(i, j) and A(j, i)), so column i of the trailing
+        // block is read as its row i: each thread owns columns (coalesced across
+        // the threads of a row).  Step k
         // needs p = t A22 v, w = p - K v and A22 -= v w^T + w v^T; the update of
         // step k and the product of step k + 1 are one pass over the block: row
         // k + 1 is updated first (it yields the next reflector), then every other
@@ -1165,9 +1167,8 @@ __global__ __launch_bounds__(TRI_TPB) void k_eigh_tri(int nblk, const int64_t *_
             for (int j = tid; j < L; j += TRI_TPB) sy[j] -= K * sv[j];  // w
             __syncthreads();
             for (int j = 1 + tid; j < L; j += TRI_TPB) A[k * D + k + 1 + j] = sv[j];
-            // row k + 1 after step k's update (both products rounded before the sum,
-            // so A(i, j) and A(j, i) stay bit-identical): its diagonal, and the
-            // vector x of step k + 1 into sn
+            // row k + 1 after step k's update (the same expression as for the
+            // rest of the block): its diagonal, and the vector x of step k + 1 into sn
             const bool next = k + 3 < d;
             double part = 0.0, diag = 0.0, lead = 0.0;
             for (int i = tid; i < L; i += TRI_TPB) {
