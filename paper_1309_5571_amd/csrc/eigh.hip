@@ -733,12 +733,11 @@ __device__ __forceinline__ void dc_merge(int n, int lo, int mid, int hi, double 
     __syncthreads();
 }
 
-// The whole tridiagonal solve and the back-transformation.  Zt: n x n global
-// scratch (u); Q: the Householder product (a, column-major), replaced by the
-// eigenvectors of the block.  ctl[2]: set to 1 if a leaf did not converge;
-// ctl[3]: leaf QL iterations + merges.
-__device__ __forceinline__ void dc_solve(int n, double *sd, double *se, double *pool, int *ipool, double *Zt, double *Q,
-                         double *red, int *ctl) {
+// The whole tridiagonal solve: sd becomes the eigenvalues of T (unordered) and
+// Zt (n x n global, column-major: u) its eigenvectors.  ctl[2]: set to 1 if a
+// leaf did not converge; ctl[3]: leaf QL iterations + merges.
+__device__ __forceinline__ void dc_solve(int n, double *sd, double *se, double *pool, int *ipool, double *Zt,
+                                         double *red, int *ctl) {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const size_t N = (size_t)n;
     int T = 0;
@@ -809,67 +808,6 @@ __device__ __forceinline__ void dc_solve(int n, double *sd, double *se, double *
             if (lo < mid && mid < hi) dc_merge(n, lo, mid, hi, se[mid - 1], sd, Zt, S, red, ctl);
             if (tid == 0) ++ctl[3];
         }
-    __syncthreads();
-    // eigenvectors of the block: E = Q Zt, column j of E over column j of Zt (it
-    // is read into registers first), two columns per wavefront at a time
-    constexpr int NQ = DC_MAX / 64;
-    for (int j0 = 2 * wv; j0 < n; j0 += 2 * TRI_WAVES) {
-        double zt[2][NQ], acc[2][NQ];
-#pragma unroll
-        for (int e = 0; e < 2; ++e)
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                const int r = lane + 64 * q;
-                zt[e][q] = r < n ? Zt[(size_t)min(j0 + e, n - 1) * N + r] : 0.0;
-                acc[e][q] = 0.0;
-            }
-#pragma unroll
-        for (int cq = 0; cq < NQ; ++cq) {
-            if (64 * cq >= n) break;
-            const int cn = min(64, n - 64 * cq);
-            // two columns of Q per step, both loaded before their products
-            for (int cl = 0; cl < cn; cl += 2) {
-                const int c = 64 * cq + cl;
-                const bool two = cl + 1 < cn;  // uniform
-                const double *qa = Q + (size_t)c * N, *qb = Q + (size_t)(two ? c + 1 : c) * N;
-                double xa[NQ], xb[NQ];
-#pragma unroll
-                for (int q = 0; q < NQ; ++q) {
-                    if (64 * q >= n) break;  // uniform: the row slots past n are not computed
-                    const int r = lane + 64 * q;
-                    xa[q] = r < n ? qa[r] : 0.0;
-                    xb[q] = r < n ? qb[r] : 0.0;
-                }
-                const double z0 = readlane_f64(zt[0][cq], cl), z1 = readlane_f64(zt[1][cq], cl);
-#pragma unroll
-                for (int q = 0; q < NQ; ++q) {
-                    if (64 * q >= n) break;
-                    acc[0][q] += xa[q] * z0;
-                    acc[1][q] += xa[q] * z1;
-                }
-                if (two) {
-                    const double y0 = readlane_f64(zt[0][cq], cl + 1), y1 = readlane_f64(zt[1][cq], cl + 1);
-#pragma unroll
-                    for (int q = 0; q < NQ; ++q) {
-                        if (64 * q >= n) break;
-                        acc[0][q] += xb[q] * y0;
-                        acc[1][q] += xb[q] * y1;
-                    }
-                }
-            }
-        }
-#pragma unroll
-        for (int e = 0; e < 2; ++e)
-            if (j0 + e < n)
-#pragma unroll
-                for (int q = 0; q < NQ; ++q) {
-                    const int r = lane + 64 * q;
-                    if (r < n) Zt[(size_t)(j0 + e) * N + r] = acc[e][q];
-                }
-    }
-    __syncthreads();
-    for (int c = wv; c < n; c += TRI_WAVES)
-        for (int r = lane; r < n; r += 64) Q[c * N + r] = Zt[c * N + r];
     __syncthreads();
 }
 
@@ -1366,11 +1304,14 @@ __global__ __launch_bounds__(TRI_TPB) void k_eigh_tri(int nblk, const int64_t *_
     int its = 0, bad = 0;
     if (d <= DC_MAX) {
         // divide and conquer on T; its eigenvectors go to u (free now that Q is
-        // formed), then the eigenvectors of the block, Q times them, back to a
+        // formed) and its eigenvalues, unordered, to w: k_eigh_gemm forms the
+        // block's eigenvectors Q Z in a, k_eigh_out orders them into u
         if (tid == 0) ctl[2] = 0;
-        dc_solve(d, sd, se, pool, (int *)srank, A, Z, red, ctl);
-        its = ctl[3];
-        bad = ctl[2];
+        dc_solve(d, sd, se, pool, (int *)srank, A, red, ctl);
+        double *wb = w + woff[b];
+        for (int i = tid; i < d; i += TRI_TPB) wb[i] = sd[i];
+        if (tid == 0 && info) info[b] = ctl[2] ? -2 : 1 + ctl[3];
+        return;
     } else {
     // ---- implicit QL on T (sd, se).  Lane 0 of wave 0 runs the recurrence and
     // leaves each iteration's rotations (indices lo..hi) in one of two LDS
@@ -1567,6 +1508,120 @@ __global__ __launch_bounds__(TRI_TPB) void k_eigh_tri(int nblk, const int64_t *_
     if (tid == 0 && info) info[b] = bad ? -2 : 1 + its;
 }
 
+typedef double v4d_eig __attribute__((ext_vector_type(4)));
+constexpr int GE_ROWS = 16;                  // rows of E per workgroup of k_eigh_gemm
+constexpr int GE_PANELS = DC_MAX / GE_ROWS;  // its grid's second dimension
+constexpr int GE_TPB = 256;
+
+// Eigenvectors of the divide-and-conquer blocks (orders EIG_LDS_DIM + 1 ..
+// DC_MAX): E = Q Z, Q the Householder product (a, column-major), Z the
+// eigenvectors of T (u, column-major).  Workgroup (b, p) forms rows
+// [16 p, 16 p + 16) of block b's E from the same rows of Q, staged in LDS
+// first, so that it writes them over those rows of Q in place; each
+// wavefront takes 16-column tiles on FP64 MFMA (16 x 16 x 4), Z read from
+// global memory (L2).
+__global__ __launch_bounds__(GE_TPB) void k_eigh_gemm(int nblk, const int64_t *__restrict__ off,
+                                                      const int32_t *__restrict__ dim, double *__restrict__ a,
+                                                      const double *__restrict__ u) {
+    __shared__ double qs[DC_MAX * GE_ROWS];  // Q(r0 + r, k) at qs[k * 16 + r]
+    const int b = blockIdx.x;
+    if (b >= nblk) return;
+    const int d = dim[b];
+    if (d <= EIG_LDS_DIM || d > DC_MAX) return;
+    const int r0 = blockIdx.y * GE_ROWS;
+    if (r0 >= d) return;
+    const size_t D = (size_t)d;
+    double *Q = a + off[b];
+    const double *Zt = u + off[b];
+    for (int e = threadIdx.x; e < GE_ROWS * d; e += blockDim.x) {
+        const int k = e >> 4, r = e & 15;
+        qs[e] = r0 + r < d ? Q[k * D + r0 + r] : 0.0;
+    }
+    __syncthreads();
+    const int nw = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int r16 = lane & 15, g = lane >> 4;
+    for (int c0 = 16 * wave; c0 < d; c0 += 16 * nw) {
+        const double *zc = Zt + (size_t)min(c0 + r16, d - 1) * D;  // column of Z of this lane (clamped)
+        v4d_eig acc = {0.0, 0.0, 0.0, 0.0};
+        for (int k0 = 0; k0 < d; k0 += 16) {
+            double av[4], bv[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {  // loads first, all in flight
+                const int k = min(k0 + 4 * j + g, d - 1);
+                av[j] = qs[k * GE_ROWS + r16];
+                bv[j] = zc[k];
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const bool kin = k0 + 4 * j + g < d;
+                if (k0 + 4 * j < d)  // (uniform)
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(kin ? av[j] : 0.0, kin ? bv[j] : 0.0, acc, 0, 0, 0);
+            }
+        }
+        // value v of lane (g, c) holds E(r0 + 4 v + g, c0 + c)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = r0 + 4 * v + g, c = c0 + r16;
+            if (r < d && c < d) Q[c * D + r] = acc[v];
+        }
+    }
+}
+
+// Output of the divide-and-conquer blocks: eigenvalues descending (ties by
+// index) into w, and the columns of E (a) in that order into u (row-major),
+// each with its first entry of largest magnitude positive.
+__global__ __launch_bounds__(TRI_TPB) void k_eigh_out(int nblk, const int64_t *__restrict__ off,
+                                                      const int32_t *__restrict__ dim,
+                                                      const int64_t *__restrict__ woff, const double *__restrict__ a,
+                                                      double *__restrict__ w, double *__restrict__ u) {
+    __shared__ double sv[DC_MAX];
+    __shared__ int srk[DC_MAX];
+    const int b = blockIdx.x;
+    if (b >= nblk) return;
+    const int d = dim[b];
+    if (d <= EIG_LDS_DIM || d > DC_MAX) return;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
+    const size_t D = (size_t)d;
+    const double *E = a + off[b];
+    double *U = u + off[b], *wb = w + woff[b];
+    for (int i = tid; i < d; i += blockDim.x) sv[i] = wb[i];
+    __syncthreads();
+    for (int i = tid; i < d; i += blockDim.x) {
+        const double wi = sv[i];
+        int rank = 0;
+        for (int j = 0; j < d; ++j) {
+            const double wj = sv[j];
+            rank += (wj > wi) || (wj == wi && j < i);
+        }
+        srk[i] = rank;
+    }
+    __syncthreads();
+    for (int i = wv; i < d; i += nw) {
+        const double *col = E + i * D;
+        double best = -1.0;
+        int bi = 0;
+        for (int r = lane; r < d; r += 64) {
+            const double av = fabs(col[r]);
+            if (av > best) {
+                best = av;
+                bi = r;
+            }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            const double ob = __shfl_xor(best, o, 64);
+            const int oi = __shfl_xor(bi, o, 64);
+            if (ob > best || (ob == best && oi < bi)) {
+                best = ob;
+                bi = oi;
+            }
+        }
+        const double sg = col[bi] < 0.0 ? -1.0 : 1.0;
+        const int rk = srk[i];
+        for (int r = lane; r < d; r += 64) U[r * D + rk] = sg * col[r];
+        if (lane == 0) wb[rk] = sv[i];
+    }
+}
+
 // State selection (Alg. 1, step 7: a block keeps its states of largest
 // density-matrix eigenvalue).  One workgroup per group of sector blocks whose
 // eigenvalues lie contiguous in w.  The m-th largest value is found by a radix
@@ -1708,6 +1763,8 @@ dmrg_status dmrg_eigh_blocks(int32_t nblk, const int64_t *off, const int32_t *di
     hipLaunchKernelGGL(k_eigh_jacobi, dim3(nblk), dim3(EIG_TPB_SMALL), 0, s, nblk, off, dim, woff, a, w, u, info);
     hipLaunchKernelGGL(k_eigh_hh, dim3(nblk), dim3(TRI_TPB), 0, s, nblk, off, dim, woff, a, w, u);
     hipLaunchKernelGGL(k_eigh_tri, dim3(nblk), dim3(TRI_TPB), 0, s, nblk, off, dim, woff, a, w, u, info);
+    hipLaunchKernelGGL(k_eigh_gemm, dim3(nblk, GE_PANELS), dim3(GE_TPB), 0, s, nblk, off, dim, a, u);
+    hipLaunchKernelGGL(k_eigh_out, dim3(nblk), dim3(TRI_TPB), 0, s, nblk, off, dim, woff, a, w, u);
     DMRG_HIP(hipGetLastError());
     return DMRG_OK;
 }
