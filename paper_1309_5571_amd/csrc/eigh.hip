@@ -1180,6 +1180,23 @@ __global__ __launch_bounds__(TRI_TPB) void k_eigh_tri(int nblk, const int64_t *_
             se[d - 1] = 0.0;
         }
     }
+    if (d <= DC_MAX) {
+        // the reflectors (rows of u beyond k + 1) and their factors t (at
+        // (k + 2, k)) to a, which the input no longer needs: k_eigh_back applies
+        // them to the eigenvectors of T; divide and conquer on T, its
+        // eigenvectors into u and its eigenvalues, unordered, into w
+        for (int k = wv; k + 2 < d; k += TRI_WAVES) {
+            for (int j = k + 2 + lane; j < d; j += 64) Z[k * D + j] = A[k * D + j];
+            if (lane == 0) Z[(k + 2) * D + k] = sq[k];
+        }
+        __syncthreads();
+        if (tid == 0) ctl[2] = 0;
+        dc_solve(d, sd, se, pool, (int *)srank, A, red, ctl);
+        double *wb = w + woff[b];
+        for (int i = tid; i < d; i += TRI_TPB) wb[i] = sd[i];
+        if (tid == 0 && info) info[b] = ctl[2] ? -2 : 1 + ctl[3];
+        return;
+    }
     // ---- Q = H_0 H_1 ... H_{d-3}, accumulated from the last factor; H_k Q only
     // changes the trailing block from index k + 1: y_c = v^T Q(:, c), then
     // Q(:, c) -= t y_c v.
@@ -1302,17 +1319,7 @@ __global__ __launch_bounds__(TRI_TPB) void k_eigh_tri(int nblk, const int64_t *_
     }
 
     int its = 0, bad = 0;
-    if (d <= DC_MAX) {
-        // divide and conquer on T; its eigenvectors go to u (free now that Q is
-        // formed) and its eigenvalues, unordered, to w: k_eigh_gemm forms the
-        // block's eigenvectors Q Z in a, k_eigh_out orders them into u
-        if (tid == 0) ctl[2] = 0;
-        dc_solve(d, sd, se, pool, (int *)srank, A, red, ctl);
-        double *wb = w + woff[b];
-        for (int i = tid; i < d; i += TRI_TPB) wb[i] = sd[i];
-        if (tid == 0 && info) info[b] = ctl[2] ? -2 : 1 + ctl[3];
-        return;
-    } else {
+    {
     // ---- implicit QL on T (sd, se).  Lane 0 of wave 0 runs the recurrence and
     // leaves each iteration's rotations (indices lo..hi) in one of two LDS
     // buffers; in the same interval the other waves apply the previous
@@ -1508,71 +1515,98 @@ __global__ __launch_bounds__(TRI_TPB) void k_eigh_tri(int nblk, const int64_t *_
     if (tid == 0 && info) info[b] = bad ? -2 : 1 + its;
 }
 
-typedef double v4d_eig __attribute__((ext_vector_type(4)));
-constexpr int GE_ROWS = 16;                  // rows of E per workgroup of k_eigh_gemm
-constexpr int GE_PANELS = DC_MAX / GE_ROWS;  // its grid's second dimension
-constexpr int GE_TPB = 256;
+constexpr int BK_COLS = 16;                 // columns of a block per workgroup of k_eigh_back
+constexpr int BK_PANELS = DC_MAX / BK_COLS;  // its grid's second dimension
+constexpr int BK_TPB = 256;                  // four wavefronts of four columns
 
 // Eigenvectors of the divide-and-conquer blocks (orders EIG_LDS_DIM + 1 ..
-// DC_MAX): E = Q Z, Q the Householder product (a, column-major), Z the
-// eigenvectors of T (u, column-major).  Workgroup (b, p) forms rows
-// [16 p, 16 p + 16) of block b's E from the same rows of Q, staged in LDS
-// first, so that it writes them over those rows of Q in place; each
-// wavefront takes 16-column tiles on FP64 MFMA (16 x 16 x 4), Z read from
-// global memory (L2).
-__global__ __launch_bounds__(GE_TPB) void k_eigh_gemm(int nblk, const int64_t *__restrict__ off,
-                                                      const int32_t *__restrict__ dim, double *__restrict__ a,
-                                                      const double *__restrict__ u) {
-    __shared__ double qs[DC_MAX * GE_ROWS];  // Q(r0 + r, k) at qs[k * 16 + r]
+// DC_MAX): E = H_0 H_1 ... H_{d-3} Z, the reflectors (rows of a beyond k + 1,
+// t_k at a(k + 2, k)) applied to the eigenvectors Z of T (u, column-major),
+// the last one first.  Workgroup (b, p) owns columns [16 p, 16 p + 16) of
+// block b's Z and overwrites them with E: QB reflectors at a time are staged
+// in LDS (zero above each one's first row, 1 there), then each wavefront
+// applies them to four register-resident columns (one load and one store of
+// a column per QB reflectors).
+__global__ __launch_bounds__(BK_TPB) void k_eigh_back(int nblk, const int64_t *__restrict__ off,
+                                                      const int32_t *__restrict__ dim, const double *__restrict__ a,
+                                                      double *__restrict__ u) {
+    __shared__ double sv[QB * DC_MAX];  // [QB][L0]: the staged reflectors, rows r0..d-1
+    __shared__ double st[QB];
     const int b = blockIdx.x;
     if (b >= nblk) return;
     const int d = dim[b];
     if (d <= EIG_LDS_DIM || d > DC_MAX) return;
-    const int r0 = blockIdx.y * GE_ROWS;
-    if (r0 >= d) return;
+    const int cp = blockIdx.y * BK_COLS;
+    if (cp >= d) return;
     const size_t D = (size_t)d;
-    double *Q = a + off[b];
-    const double *Zt = u + off[b];
-    for (int e = threadIdx.x; e < GE_ROWS * d; e += blockDim.x) {
-        const int k = e >> 4, r = e & 15;
-        qs[e] = r0 + r < d ? Q[k * D + r0 + r] : 0.0;
-    }
-    __syncthreads();
-    const int nw = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int r16 = lane & 15, g = lane >> 4;
-    for (int c0 = 16 * wave; c0 < d; c0 += 16 * nw) {
-        const double *zc = Zt + (size_t)min(c0 + r16, d - 1) * D;  // column of Z of this lane (clamped)
-        v4d_eig acc = {0.0, 0.0, 0.0, 0.0};
-        for (int k0 = 0; k0 < d; k0 += 16) {
-            double av[4], bv[4];
+    const double *H = a + off[b];
+    double *Z = u + off[b];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int khi = d - 3; khi >= 0; khi -= QB) {
+        const int klo = max(0, khi - QB + 1), r0 = klo + 1, L0 = d - r0;
+        for (int i = threadIdx.x; i < (khi - klo + 1) * L0; i += blockDim.x) {
+            const int kk = i / L0, j = i - kk * L0, k = klo + kk, r = r0 + j;
+            sv[i] = r == k + 1 ? 1.0 : (r > k + 1 ? H[k * D + r] : 0.0);
+        }
+        for (int i = threadIdx.x; i <= khi - klo; i += blockDim.x) st[i] = H[(klo + i + 2) * D + klo + i];
+        __syncthreads();
+        for (int c0 = cp + 4 * wave; c0 < min(d, cp + BK_COLS); c0 += 4 * nw) {
+            double cv[4][Q_REG];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {  // loads first, all in flight
-                const int k = min(k0 + 4 * j + g, d - 1);
-                av[j] = qs[k * GE_ROWS + r16];
-                bv[j] = zc[k];
+            for (int e = 0; e < 4; ++e) {
+                const double *col = Z + (size_t)min(c0 + e, d - 1) * D + r0;
+#pragma unroll
+                for (int q = 0; q < Q_REG; ++q) {
+                    if (64 * q >= L0) break;  // uniform: the row slots past L0 are not used
+                    cv[e][q] = col[min(lane + 64 * q, L0 - 1)];
+                }
+            }
+            for (int k = khi; k >= klo; --k) {
+                const double t = st[k - klo];
+                if (t == 0.0) continue;
+                const double *v = sv + (k - klo) * L0;
+                double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int q = 0; q < Q_REG; ++q) {
+                    if (64 * q >= L0) break;
+                    const int r = lane + 64 * q;
+                    const double vr = r < L0 ? v[r] : 0.0;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) acc[e] += vr * cv[e][q];
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const double ty = t * group_sum<64>(acc[e]);
+#pragma unroll
+                    for (int q = 0; q < Q_REG; ++q) {
+                        if (64 * q >= L0) break;
+                        const int r = lane + 64 * q;
+                        if (r < L0) cv[e][q] -= ty * v[r];
+                    }
+                }
             }
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const bool kin = k0 + 4 * j + g < d;
-                if (k0 + 4 * j < d)  // (uniform)
-                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(kin ? av[j] : 0.0, kin ? bv[j] : 0.0, acc, 0, 0, 0);
-            }
-        }
-        // value v of lane (g, c) holds E(r0 + 4 v + g, c0 + c)
+            for (int e = 0; e < 4; ++e)
+                if (c0 + e < d) {
+                    double *col = Z + (size_t)(c0 + e) * D + r0;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int r = r0 + 4 * v + g, c = c0 + r16;
-            if (r < d && c < d) Q[c * D + r] = acc[v];
+                    for (int q = 0; q < Q_REG; ++q) {
+                        const int r = lane + 64 * q;
+                        if (r < L0) col[r] = cv[e][q];
+                    }
+                }
         }
+        __syncthreads();  // the next block restages sv
     }
 }
 
 // Output of the divide-and-conquer blocks: eigenvalues descending (ties by
-// index) into w, and the columns of E (a) in that order into u (row-major),
-// each with its first entry of largest magnitude positive.
+// index) into w, and the columns of E (u, column-major) in that order into u
+// (row-major), each with its first entry of largest magnitude positive; a is
+// the staging copy.
 __global__ __launch_bounds__(TRI_TPB) void k_eigh_out(int nblk, const int64_t *__restrict__ off,
                                                       const int32_t *__restrict__ dim,
-                                                      const int64_t *__restrict__ woff, const double *__restrict__ a,
+                                                      const int64_t *__restrict__ woff, double *__restrict__ a,
                                                       double *__restrict__ w, double *__restrict__ u) {
     __shared__ double sv[DC_MAX];
     __shared__ int srk[DC_MAX];
@@ -1582,8 +1616,8 @@ __global__ __launch_bounds__(TRI_TPB) void k_eigh_out(int nblk, const int64_t *_
     if (d <= EIG_LDS_DIM || d > DC_MAX) return;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
     const size_t D = (size_t)d;
-    const double *E = a + off[b];
-    double *U = u + off[b], *wb = w + woff[b];
+    const double *E = u + off[b];
+    double *S = a + off[b], *U = u + off[b], *wb = w + woff[b];
     for (int i = tid; i < d; i += blockDim.x) sv[i] = wb[i];
     __syncthreads();
     for (int i = tid; i < d; i += blockDim.x) {
@@ -1617,9 +1651,11 @@ __global__ __launch_bounds__(TRI_TPB) void k_eigh_out(int nblk, const int64_t *_
         }
         const double sg = col[bi] < 0.0 ? -1.0 : 1.0;
         const int rk = srk[i];
-        for (int r = lane; r < d; r += 64) U[r * D + rk] = sg * col[r];
+        for (int r = lane; r < d; r += 64) S[r * D + rk] = sg * col[r];
         if (lane == 0) wb[rk] = sv[i];
     }
+    __syncthreads();
+    for (size_t e = tid; e < D * D; e += blockDim.x) U[e] = S[e];
 }
 
 // State selection (Alg. 1, step 7: a block keeps its states of largest
@@ -1763,7 +1799,7 @@ dmrg_status dmrg_eigh_blocks(int32_t nblk, const int64_t *off, const int32_t *di
     hipLaunchKernelGGL(k_eigh_jacobi, dim3(nblk), dim3(EIG_TPB_SMALL), 0, s, nblk, off, dim, woff, a, w, u, info);
     hipLaunchKernelGGL(k_eigh_hh, dim3(nblk), dim3(TRI_TPB), 0, s, nblk, off, dim, woff, a, w, u);
     hipLaunchKernelGGL(k_eigh_tri, dim3(nblk), dim3(TRI_TPB), 0, s, nblk, off, dim, woff, a, w, u, info);
-    hipLaunchKernelGGL(k_eigh_gemm, dim3(nblk, GE_PANELS), dim3(GE_TPB), 0, s, nblk, off, dim, a, u);
+    hipLaunchKernelGGL(k_eigh_back, dim3(nblk, BK_PANELS), dim3(BK_TPB), 0, s, nblk, off, dim, a, u);
     hipLaunchKernelGGL(k_eigh_out, dim3(nblk), dim3(TRI_TPB), 0, s, nblk, off, dim, woff, a, w, u);
     DMRG_HIP(hipGetLastError());
     return DMRG_OK;
