@@ -347,9 +347,10 @@ dmrg_status dmrg_density(dmrg_plan *plan, const double *psi, double *rho_left, d
  * matrix select the states the block keeps).  FP64, one workgroup per block:
  * cyclic Jacobi for orders up to 8 (in LDS), Householder reduction to
  * tridiagonal form for larger orders (with the block in registers up to
- * order 180), finished by divide and conquer up to order 512 (its
- * back-transformation on FP64 MFMA, one workgroup per 16 rows of a block)
- * and by the implicit QL iteration above.
+ * order 180), finished by divide and conquer up to order 512 (the
+ * reflectors applied to the eigenvectors of the tridiagonal matrix by one
+ * workgroup per 16 columns of a block) and by the implicit QL iteration
+ * above.
  *  off, dim, woff: device arrays [nblk].  Block b is the row-major symmetric
  *    [dim[b]][dim[b]] matrix at a + off[b] (every entry is read).
  *  w + woff[b]: its eigenvalues in descending order (ties by index).

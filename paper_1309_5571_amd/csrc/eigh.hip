@@ -1525,13 +1525,14 @@ constexpr int BK_TPB = 256;                  // four wavefronts of four columns
 // the last one first.  Workgroup (b, p) owns columns [16 p, 16 p + 16) of
 // block b's Z and overwrites them with E: QB reflectors at a time are staged
 // in LDS (zero above each one's first row, 1 there), then each wavefront
-// applies them to four register-resident columns (one load and one store of
-// a column per QB reflectors).
+// applies them, two at a time, to four register-resident columns (one load
+// and one store of a column per QB reflectors).
 __global__ __launch_bounds__(BK_TPB) void k_eigh_back(int nblk, const int64_t *__restrict__ off,
                                                       const int32_t *__restrict__ dim, const double *__restrict__ a,
                                                       double *__restrict__ u) {
     __shared__ double sv[QB * DC_MAX];  // [QB][L0]: the staged reflectors, rows r0..d-1
     __shared__ double st[QB];
+    __shared__ double ss[QB / 2];  // v_{k-1}.v_k of the pairs
     const int b = blockIdx.x;
     if (b >= nblk) return;
     const int d = dim[b];
@@ -1550,6 +1551,17 @@ __global__ __launch_bounds__(BK_TPB) void k_eigh_back(int nblk, const int64_t *_
         }
         for (int i = threadIdx.x; i <= khi - klo; i += blockDim.x) st[i] = H[(klo + i + 2) * D + klo + i];
         __syncthreads();
+        // the reflectors go in pairs (k, k - 1) from khi down: s = v_{k-1}.v_k lets
+        // both products with a column be formed at once
+        const int npair = (khi - klo + 1) >> 1;
+        for (int pr = wave; pr < npair; pr += nw) {
+            const double *v1 = sv + (khi - 2 * pr - klo) * L0, *v2 = v1 - L0;
+            double part = 0.0;
+            for (int r = lane; r < L0; r += 64) part += v1[r] * v2[r];
+            part = group_sum<64>(part);
+            if (lane == 0) ss[pr] = part;
+        }
+        __syncthreads();
         for (int c0 = cp + 4 * wave; c0 < min(d, cp + BK_COLS); c0 += 4 * nw) {
             double cv[4][Q_REG];
 #pragma unroll
@@ -1561,10 +1573,39 @@ __global__ __launch_bounds__(BK_TPB) void k_eigh_back(int nblk, const int64_t *_
                     cv[e][q] = col[min(lane + 64 * q, L0 - 1)];
                 }
             }
-            for (int k = khi; k >= klo; --k) {
-                const double t = st[k - klo];
-                if (t == 0.0) continue;
-                const double *v = sv + (k - klo) * L0;
+            // H_{k-1} H_k c = c - t_k y1 v_k - t_{k-1} y2 v_{k-1}, y1 = v_k.c,
+            // y2 = v_{k-1}.c - t_k y1 s
+            for (int pr = 0; pr < npair; ++pr) {
+                const int k = khi - 2 * pr;
+                const double t1 = st[k - klo], t2 = st[k - 1 - klo], sp = ss[pr];
+                const double *v1 = sv + (k - klo) * L0, *v2 = v1 - L0;
+                double a1[4] = {0.0, 0.0, 0.0, 0.0}, a2[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int q = 0; q < Q_REG; ++q) {
+                    if (64 * q >= L0) break;
+                    const int r = lane + 64 * q;
+                    const double x1 = r < L0 ? v1[r] : 0.0, x2 = r < L0 ? v2[r] : 0.0;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        a1[e] += x1 * cv[e][q];
+                        a2[e] += x2 * cv[e][q];
+                    }
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const double y1 = group_sum<64>(a1[e]), z = group_sum<64>(a2[e]);
+                    const double f1 = t1 * y1, f2 = t2 * (z - f1 * sp);
+#pragma unroll
+                    for (int q = 0; q < Q_REG; ++q) {
+                        if (64 * q >= L0) break;
+                        const int r = lane + 64 * q;
+                        if (r < L0) cv[e][q] -= f1 * v1[r] + f2 * v2[r];
+                    }
+                }
+            }
+            if (((khi - klo + 1) & 1) && st[0] != 0.0) {  // the block's last reflector, klo, alone
+                const double t = st[0];
+                const double *v = sv;
                 double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
                 for (int q = 0; q < Q_REG; ++q) {
