@@ -1649,8 +1649,9 @@ __global__ __launch_bounds__(TRI_TPB) void k_eigh_out(int nblk, const int64_t *_
                                                       const int32_t *__restrict__ dim,
                                                       const int64_t *__restrict__ woff, double *__restrict__ a,
                                                       double *__restrict__ w, double *__restrict__ u) {
-    __shared__ double sv[DC_MAX];
-    __shared__ int srk[DC_MAX];
+    __shared__ double sv[DC_MAX], ssg[DC_MAX];
+    __shared__ int srk[DC_MAX], sinv[DC_MAX];
+    __shared__ double tile[32][33];
     const int b = blockIdx.x;
     if (b >= nblk) return;
     const int d = dim[b];
@@ -1690,12 +1691,27 @@ __global__ __launch_bounds__(TRI_TPB) void k_eigh_out(int nblk, const int64_t *_
                 bi = oi;
             }
         }
-        const double sg = col[bi] < 0.0 ? -1.0 : 1.0;
-        const int rk = srk[i];
-        for (int r = lane; r < d; r += 64) S[r * D + rk] = sg * col[r];
-        if (lane == 0) wb[rk] = sv[i];
+        if (lane == 0) {
+            const int rk = srk[i];
+            ssg[rk] = col[bi] < 0.0 ? -1.0 : 1.0;
+            sinv[rk] = i;
+            wb[rk] = sv[i];
+        }
     }
     __syncthreads();
+    // U(r, rk) = sign * E(r, i(rk)): 32 x 32 tiles through LDS, read down the
+    // columns of E and written along the rows of the staging copy
+    static_assert(TRI_TPB == 1024, "32 x 32 tile threads");
+    const int tr = tid & 31, tc = tid >> 5;
+    for (int c0 = 0; c0 < d; c0 += 32)
+        for (int rr = 0; rr < d; rr += 32) {
+            const int rk = c0 + tc, r = rr + tr;
+            if (rk < d && r < d) tile[tc][tr] = ssg[rk] * E[(size_t)sinv[rk] * D + r];
+            __syncthreads();
+            const int r2 = rr + tc, rk2 = c0 + tr;
+            if (r2 < d && rk2 < d) S[(size_t)r2 * D + rk2] = tile[tr][tc];
+            __syncthreads();
+        }
     for (size_t e = tid; e < D * D; e += blockDim.x) U[e] = S[e];
 }
 
