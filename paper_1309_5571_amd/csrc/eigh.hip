@@ -988,6 +988,12 @@ __global__ __launch_bounds__(TRI_TPB) void k_eigh_hh(int nblk, const int64_t *__
         hh_reduce<HH_ROWS>(d, Z, A, wb, P0, P1, scol, spart, red, red2);
 }
 
+// Tridiagonal path of the orders EIG_LDS_DIM + 1 .. EIG_MAX_DIM, one workgroup
+// per block: T handed over by k_eigh_hh (orders up to HH_REG_DIM) or reduced
+// here in global memory.  Orders up to DC_MAX: divide and conquer on T, which
+// leaves the eigenvectors of T in u, its eigenvalues (unordered) in w and the
+// reflectors in a, for k_eigh_back and k_eigh_out.  Larger orders: Q formed,
+// implicit QL on T applied to it, and the ordered output written here.
 __global__ __launch_bounds__(TRI_TPB) void k_eigh_tri(int nblk, const int64_t *__restrict__ off,
                                                       const int32_t *__restrict__ dim, const int64_t *__restrict__ woff,
                                                       double *__restrict__ a, double *__restrict__ w,
