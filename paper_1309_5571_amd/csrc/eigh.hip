@@ -740,13 +740,16 @@ __device__ __forceinline__ void dc_solve(int n, double *sd, double *se, double *
                                          double *red, int *ctl) {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const size_t N = (size_t)n;
+    // leaves of at most 8 below order 65 (their QL chases are serial on one
+    // lane; measured faster there), of at most DC_LEAF above (fewer merges)
+    const int lmax = n <= 64 ? 8 : DC_LEAF;
     int T = 0;
-    while (((n + (1 << T) - 1) >> T) > DC_LEAF) ++T;
+    while (((n + (1 << T) - 1) >> T) > lmax) ++T;
     const int nleaf = 1 << T;
     auto bnd = [&](int t, int i) { return (n * i) >> t; };
     for (int c = wv; c < n; c += TRI_WAVES)
         for (int r = lane; r < n; r += 64) Zt[c * N + r] = 0.0;
-    // tear at the leaf boundaries (leaves hold at least 8 rows: no index is shared)
+    // tear at the leaf boundaries (leaves hold at least 4 rows: no index is shared)
     if (tid >= 1 && tid < nleaf) {
         const int b0 = bnd(T, tid);
         const double r = fabs(se[b0 - 1]);
