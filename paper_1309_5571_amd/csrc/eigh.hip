@@ -905,13 +905,23 @@ __device__ __forceinline__ void hh_reduce(int d, const double *Z, double *A, dou
             const double2 *pr = cur + jv, *pn = nxt + jv;
             double *sc = scol + jv;
             const bool next = c == k + 1;
+            // the rows past k form a suffix; each row's LDS reads are issued one
+            // row ahead, so that their latency overlaps the previous row's work
+            const int qs = max(0, min(R, k + 1 - j0));
+            double2 nr = qs < R ? pr[qs] : make_double2(0.0, 0.0);
+            double nv = qs < R ? pn[qs].x : 0.0;
 #pragma unroll
             for (int q = 0; q < R; ++q) {
                 if (j0 + q > k) {  // (uniform)
-                    const double2 pj = pr[q];
+                    const double2 pj = nr;
+                    const double vq = nv;
+                    if (q + 1 < R) {
+                        nr = pr[q + 1];
+                        nv = pn[q + 1].x;
+                    }
                     const double x = fma(-pj.x, pc.y, fma(-pj.y, pc.x, a[q]));
                     a[q] = x;
-                    acc = fma(x, pn[q].x, acc);
+                    acc = fma(x, vq, acc);
                     if (next) sc[q] = x;
                 }
             }
