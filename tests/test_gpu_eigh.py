@@ -90,6 +90,31 @@ def test_eigh_random_blocks_small_and_large(seed):
     _check(blocks, res)
 
 
+def test_eigh_kernel_boundary_orders():
+    """Orders at the edges of each kernel's range: the register reduction's row
+    counts (4, 16, 36 rows per thread up to 64, 128, 180), the global-memory
+    reduction above 180, the last divide-and-conquer order (512: 32 panels of
+    the reflector back-transformation) and the first QL one; random, rank-
+    deficient, already tridiagonal (every reflector the identity) and block
+    diagonal (some columns already reduced) blocks."""
+    rng = np.random.default_rng(9)
+    blocks = []
+    for d in (9, 16, 64, 65, 128, 129, 180, 181, 512, 513):
+        blocks.append(_sym(rng, d))
+        blocks.append(_psd(rng, d, max(1, d // 3)))
+    d = 130
+    T = np.diag(rng.standard_normal(d)) + np.diag(rng.standard_normal(d - 1), 1)
+    blocks.append(T + np.triu(T, 1).T)
+    B = np.zeros((90, 90))
+    X = rng.standard_normal((40, 40))
+    B[:40, :40] = X + X.T
+    B[50:, 50:] = 3.0 * np.eye(40)
+    blocks.append(B)
+    res, info = _run(blocks)
+    assert np.all(info >= 1)
+    _check(blocks, res)
+
+
 def test_eigh_large_orders():
     """The tridiagonal path at the orders of the 64-member batch (361) and up
     to the largest supported one, random and density-like (rank-deficient,
